@@ -1,0 +1,218 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle/oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product library never imports
+this module and this module never imports the product package; both consume
+the same seeded input arrays (numpy) and nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Ray flag bits (see oracle.cpp)
+F_NEAR_TIE = 1
+F_GRAZE = 2
+F_NEAR_ORIGIN = 4
+F_T_ILLCOND = 8
+F_DIAG = 16
+F_SHADE = 32
+ID_FLAGS = F_NEAR_TIE | F_GRAZE | F_NEAR_ORIGIN
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle: plain C++17, -O3, no fast-math, std::thread."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-std=c++17", "-O3", "-march=x86-64-v3", "-fno-fast-math", "-fPIC", "-shared", "-pthread",
+           "-Wall", "-o", tmp, _SRC]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        i32 = ctypes.c_int32
+        L.orc_scene_create.restype = P
+        L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64]
+        L.orc_scene_destroy.argtypes = [P]
+        L.orc_scene_set_albedo.argtypes = [P, P]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
+        L.orc_philox.argtypes = [P, P, P]
+        L.orc_trace.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_trace_d.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_render.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, P, P]
+        L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
+def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox(_p(c), _p(k), _p(out))
+    return out
+
+
+@dataclass
+class Hits:
+    t: np.ndarray
+    inst: np.ndarray
+    prim: np.ndarray
+    half: np.ndarray
+    u: np.ndarray
+    v: np.ndarray
+    flags: np.ndarray
+    cand: np.ndarray
+    ncand: np.ndarray
+
+
+class OracleScene:
+    """FP64 oracle view of a scene given as the generator's arrays."""
+
+    def __init__(self, scene):
+        self._keep = dict(
+            verts=np.ascontiguousarray(scene.verts, dtype=np.float32),
+            quads=np.ascontiguousarray(scene.quads, dtype=np.int32),
+            vo=np.ascontiguousarray(scene.proto_vert_off, dtype=np.int64),
+            qo=np.ascontiguousarray(scene.proto_quad_off, dtype=np.int64),
+            albedo=np.ascontiguousarray(scene.albedo, dtype=np.float32),
+            ip=np.ascontiguousarray(scene.inst_proto, dtype=np.int32),
+            x=np.ascontiguousarray(scene.inst_xform, dtype=np.float32),
+        )
+        k = self._keep
+        self.n_quads = int(k["quads"].shape[0])
+        self.h = lib().orc_scene_create(_p(k["verts"]), k["verts"].shape[0], _p(k["quads"]), k["quads"].shape[0],
+                                        _p(k["vo"]), _p(k["qo"]), k["qo"].shape[0] - 1, _p(k["albedo"]),
+                                        _p(k["ip"]), _p(k["x"]), k["ip"].shape[0])
+        if not self.h:
+            raise ValueError("oracle: singular instance transform")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().orc_scene_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_albedo(self, albedo: np.ndarray) -> None:
+        a = np.ascontiguousarray(albedo, dtype=np.float64)
+        assert a.shape == (self.n_quads,)
+        lib().orc_scene_set_albedo(self.h, _p(a))
+
+    def trace(self, rays: np.ndarray, excl: Optional[np.ndarray] = None, r0: Optional[np.ndarray] = None,
+              brute: bool = False, any_hit: bool = False) -> Hits:
+        """Closest hit (or, with any_hit, the first-hit occlusion flags) of n rays given
+        as [n, 8] (ox oy oz dx dy dz tmin tmax): FP32 rays are read exactly, FP64 rays
+        are used as they are."""
+        f64 = rays.dtype == np.float64
+        rays = np.ascontiguousarray(rays, dtype=np.float64 if f64 else np.float32)
+        n = rays.shape[0]
+        ex = None if excl is None else np.ascontiguousarray(excl, dtype=np.int32)
+        rr = None if r0 is None else np.ascontiguousarray(r0, dtype=np.float64)
+        out = Hits(t=np.zeros(n), inst=np.zeros(n, np.int32), prim=np.zeros(n, np.int32),
+                   half=np.zeros(n, np.int32), u=np.zeros(n), v=np.zeros(n), flags=np.zeros(n, np.uint32),
+                   cand=np.zeros((n, 8), np.int32), ncand=np.zeros(n, np.int32))
+        fn = lib().orc_trace_d if f64 else lib().orc_trace
+        fn(self.h, n, _p(rays), _p(ex), _p(rr), 0 if brute else 1, 1 if any_hit else 0, _p(out.t),
+                        _p(out.inst), _p(out.prim), _p(out.half), _p(out.u), _p(out.v), _p(out.flags),
+                        _p(out.cand), _p(out.ncand))
+        return out
+
+    @staticmethod
+    def _params(settings):
+        pi = np.array([settings.spp, settings.depth], dtype=np.int32)
+        pu = np.array([settings.seed, settings.frame], dtype=np.uint64)
+        pd = np.array(list(settings.light_dir) + [settings.E, settings.L_sky], dtype=np.float64)
+        if not (1 <= settings.depth <= 64):
+            raise ValueError("depth must be in [1, 64]")
+        return pi, pu, pd
+
+    @staticmethod
+    def _cams(cams):
+        cf = np.array([list(c.eye) + list(c.look) + list(c.up) + [c.vfov_deg] for c in cams], dtype=np.float64)
+        off = 0
+        ci = []
+        for c in cams:
+            ci.append([c.w, c.h, off])
+            off += c.w * c.h
+        return np.ascontiguousarray(cf), np.array(ci, dtype=np.int64), off
+
+    def render(self, cams, settings, pixels: Optional[np.ndarray] = None, brute: bool = False):
+        """Returns (image or per-listed-pixel radiance [f64], pixel flags [u8], stats dict)."""
+        cf, ci, total = self._cams(cams)
+        pi, pu, pd = self._params(settings)
+        px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+        n = total if px is None else px.shape[0]
+        img = np.zeros(n)
+        fl = np.zeros(n, np.uint8)
+        st = np.zeros(4)
+        lib().orc_render(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px),
+                         0 if px is None else n, 0 if brute else 1, _p(img), _p(fl), _p(st))
+        stats = dict(closest=st[0], shadow=st[1], incoherent=st[2], flagged_pixels=st[3])
+        return img, fl, stats
+
+    def grad(self, cams, settings, gpix: np.ndarray, pixels: Optional[np.ndarray] = None, brute: bool = False):
+        """Path-replay gradient of sum_p gpix[p] * I_p w.r.t. per-face albedo.
+        Returns (grad [Q] f64, pixel flags, face tainted-by-flagged-path mask)."""
+        cf, ci, total = self._cams(cams)
+        pi, pu, pd = self._params(settings)
+        px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+        n = total if px is None else px.shape[0]
+        g = np.ascontiguousarray(gpix, dtype=np.float64)
+        assert g.shape == (n,)
+        out = np.zeros(self.n_quads)
+        fl = np.zeros(n, np.uint8)
+        taint = np.zeros(self.n_quads, np.uint8)
+        lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,
+                       0 if brute else 1, _p(g), 0, None, _p(out), None, _p(fl), _p(taint))
+        return out, fl, taint
+
+    def tangent(self, cams, settings, tangent: np.ndarray, pixels: Optional[np.ndarray] = None):
+        """Forward-mode (dual number) derivative of each pixel along a per-face tangent."""
+        cf, ci, total = self._cams(cams)
+        pi, pu, pd = self._params(settings)
+        px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+        n = total if px is None else px.shape[0]
+        tg = np.ascontiguousarray(tangent, dtype=np.float64)
+        assert tg.shape == (self.n_quads,)
+        dI = np.zeros(n)
+        fl = np.zeros(n, np.uint8)
+        lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,
+                       1, None, 1, _p(tg), None, _p(dI), _p(fl), None)
+        return dI, fl

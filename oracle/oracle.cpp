@@ -1,0 +1,879 @@
+// FP64 CPU oracle for instanced-quad closest-hit tracing and Lambertian path tracing.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+// baseline leg of the benchmark may load this library.  It shares no code,
+// header, table or helper with the HIP library; the two only read the same
+// seeded input arrays.
+//
+// What it computes, and where each piece comes from:
+//  * Scene: prototype quad meshes instanced by affine transforms (object-level
+//    instancing, Section 5.2), quads rendered directly (Section 5.2 "Quads").
+//  * Closest hit: by definition the smallest key (t, inst, prim, half) over ALL
+//    (instance, quad, half) triangles whose hit satisfies tmin < t <= tmax.  The
+//    quad v0..v3 is split on the diagonal v1-v3 into A = (v0, v1, v3) and
+//    B = (v2, v3, v1); both sides count (no back-face culling).  Hits are
+//    computed on world-space vertices w = A v + t (the oracle transforms the
+//    vertices, never the rays) with a plain plane-then-inside test in FP64.
+//    The BVH mode only culls which triangles get tested; the test itself is the
+//    same function as in brute force, so both modes agree exactly whenever the
+//    culling is conservative.
+//  * Flags: rays whose FP32 answer may legitimately differ from this FP64 answer
+//    (near ties, edge grazes, hits next to the origin, ill-conditioned t).
+//  * Camera, counter-based RNG (Philox4x32-10, Salmon et al. 2011), cosine
+//    sampling in the orthonormal basis of Duff et al. 2017, and the Lambertian
+//    path loop with next-event estimation toward one directional light and a
+//    constant sky.  Progressive 1 spp frames follow Section 5.4; the per-sample
+//    average over spp is taken in sample order.
+//  * Gradient of the image with respect to per-face albedo with every path held
+//    fixed: path-replay form (sum over vertices of S_k / a_k) and, independently,
+//    forward-mode dual numbers.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr double kInf = std::numeric_limits<double>::infinity();
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- vectors
+struct V3 {
+  double x, y, z;
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 normalize(V3 a) { return (1.0 / norm(a)) * a; }
+inline double maxabs(V3 a) { return std::max(std::fabs(a.x), std::max(std::fabs(a.y), std::fabs(a.z))); }
+inline double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+// ---------------------------------------------------------------- flags
+enum : uint32_t {
+  F_NEAR_TIE = 1u,     // another (inst, prim) hit within the tie window
+  F_GRAZE = 2u,        // the ray passes within the graze distance of a boundary edge
+  F_NEAR_ORIGIN = 4u,  // the hit lies within the graze distance of the ray origin
+  F_T_ILLCOND = 8u,    // FP32 t cannot be trusted to 1e-5 (grazing incidence)
+  F_DIAG = 16u,        // the two halves of the hit quad are within the window / graze distance
+  F_SHADE = 32u,       // render only: shading decision within rounding (n.d, n.l, n_z ~ 0)
+};
+
+// ---------------------------------------------------------------- scene
+struct Box {
+  double lo[3] = {kInf, kInf, kInf};
+  double hi[3] = {-kInf, -kInf, -kInf};
+  void grow(V3 p) {
+    lo[0] = std::min(lo[0], p.x); hi[0] = std::max(hi[0], p.x);
+    lo[1] = std::min(lo[1], p.y); hi[1] = std::max(hi[1], p.y);
+    lo[2] = std::min(lo[2], p.z); hi[2] = std::max(hi[2], p.z);
+  }
+  void grow(const Box& b) {
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], b.lo[k]); hi[k] = std::max(hi[k], b.hi[k]); }
+  }
+  double mag() const {
+    double m = 0;
+    for (int k = 0; k < 3; ++k) m = std::max(m, std::max(std::fabs(lo[k]), std::fabs(hi[k])));
+    return m;
+  }
+};
+
+struct Node {
+  Box b;
+  int32_t left = -1, right = -1;  // children (internal)
+  int32_t start = 0, count = 0;   // item range (leaf when count > 0)
+};
+
+// Plain top-down BVH with an object-median split on the longest centroid axis.
+struct Bvh {
+  std::vector<Node> nodes;
+  std::vector<int32_t> items;
+  void build(const std::vector<Box>& boxes) {
+    nodes.clear();
+    items.resize(boxes.size());
+    std::iota(items.begin(), items.end(), 0);
+    if (boxes.empty()) return;
+    std::vector<V3> cen(boxes.size());
+    for (size_t i = 0; i < boxes.size(); ++i)
+      cen[i] = {0.5 * (boxes[i].lo[0] + boxes[i].hi[0]), 0.5 * (boxes[i].lo[1] + boxes[i].hi[1]),
+                0.5 * (boxes[i].lo[2] + boxes[i].hi[2])};
+    nodes.reserve(2 * boxes.size() / 2 + 1);
+    struct Job { int32_t node, start, count; };
+    std::vector<Job> jobs;
+    nodes.push_back(Node{});
+    jobs.push_back({0, 0, (int32_t)boxes.size()});
+    while (!jobs.empty()) {
+      Job j = jobs.back();
+      jobs.pop_back();
+      Box b, cb;
+      for (int32_t i = j.start; i < j.start + j.count; ++i) {
+        b.grow(boxes[items[i]]);
+        cb.grow(cen[items[i]]);
+      }
+      nodes[j.node].b = b;
+      if (j.count <= 4) {
+        nodes[j.node].start = j.start;
+        nodes[j.node].count = j.count;
+        continue;
+      }
+      int axis = 0;
+      double ext = -1;
+      for (int k = 0; k < 3; ++k)
+        if (cb.hi[k] - cb.lo[k] > ext) { ext = cb.hi[k] - cb.lo[k]; axis = k; }
+      int32_t mid = j.start + j.count / 2;
+      std::nth_element(items.begin() + j.start, items.begin() + mid, items.begin() + j.start + j.count,
+                       [&](int32_t a, int32_t c) { return comp(cen[a], axis) < comp(cen[c], axis); });
+      int32_t l = (int32_t)nodes.size();
+      nodes.push_back(Node{});
+      nodes.push_back(Node{});
+      nodes[j.node].left = l;
+      nodes[j.node].right = l + 1;
+      jobs.push_back({l, j.start, mid - j.start});
+      jobs.push_back({l + 1, mid, j.start + j.count - mid});
+    }
+  }
+};
+
+struct Scene {
+  int32_t P = 0;
+  std::vector<V3> verts;           // object space, exact copies of the FP32 input
+  std::vector<int32_t> quads;      // 4 per quad, local vertex index
+  std::vector<int64_t> vo, qo;     // per-prototype offsets
+  std::vector<double> albedo;      // per unique quad
+  int64_t N = 0;
+  std::vector<int32_t> iproto;
+  std::vector<double> X;           // 12 per instance: row-major [A | t] (FP32 values)
+  std::vector<double> Xi;          // 12 per instance: FP64 inverse [A^-1 | -A^-1 t]
+  std::vector<double> ainv_frob;   // Frobenius norm of A^-1 (bounds its spectral norm)
+  std::vector<Box> proto_box;      // object space
+  std::vector<Box> inst_box;       // world space
+  std::vector<Bvh> proto_bvh;
+  Bvh inst_bvh;
+  double scene_mag = 1.0;
+};
+
+inline V3 xform_point(const double* X, V3 v) {
+  return {X[0] * v.x + X[1] * v.y + X[2] * v.z + X[3], X[4] * v.x + X[5] * v.y + X[6] * v.z + X[7],
+          X[8] * v.x + X[9] * v.y + X[10] * v.z + X[11]};
+}
+inline V3 xform_vec(const double* X, V3 v) {
+  return {X[0] * v.x + X[1] * v.y + X[2] * v.z, X[4] * v.x + X[5] * v.y + X[6] * v.z,
+          X[8] * v.x + X[9] * v.y + X[10] * v.z};
+}
+
+// FP64 inverse of the affine map by cofactors.  Returns false when singular.
+bool invert_affine(const double* X, double* Y) {
+  const double a = X[0], b = X[1], c = X[2], d = X[4], e = X[5], f = X[6], g = X[8], h = X[9], i = X[10];
+  const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+  const double det = a * A + b * B + c * C;
+  if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return false;
+  const double r = 1.0 / det;
+  double M[9] = {A * r, -(b * i - c * h) * r, (b * f - c * e) * r,
+                 B * r, (a * i - c * g) * r, -(a * f - c * d) * r,
+                 C * r, -(a * h - b * g) * r, (a * e - b * d) * r};
+  for (int k = 0; k < 3; ++k) {
+    Y[4 * k + 0] = M[3 * k + 0];
+    Y[4 * k + 1] = M[3 * k + 1];
+    Y[4 * k + 2] = M[3 * k + 2];
+    Y[4 * k + 3] = -(M[3 * k + 0] * X[3] + M[3 * k + 1] * X[7] + M[3 * k + 2] * X[11]);
+  }
+  return true;
+}
+
+void quad_world(const Scene& S, int64_t inst, int64_t q_global, V3 w[4]) {
+  const int32_t p = S.iproto[inst];
+  const double* X = &S.X[12 * inst];
+  for (int k = 0; k < 4; ++k) w[k] = xform_point(X, S.verts[S.vo[p] + S.quads[4 * q_global + k]]);
+}
+
+// ---------------------------------------------------------------- ray / triangle
+struct Ray {
+  V3 o, d;
+  double tmin, tmax;
+};
+
+struct TriHit {
+  bool hit = false;
+  double t = kInf, l0 = 0, l1 = 0, l2 = 0;  // barycentric weights of w0, w1, w2
+};
+
+// Plane-then-inside test: t from the supporting plane, then the hit point must
+// lie on the inner side of all three edges (boundary included).  Two-sided.
+TriHit tri_test(const Ray& r, V3 w0, V3 w1, V3 w2, double tmax) {
+  TriHit h;
+  const V3 n = cross(w1 - w0, w2 - w0);
+  const double nn = dot(n, n);
+  if (!(nn > 0.0)) return h;
+  const double den = dot(n, r.d);
+  if (den == 0.0) return h;
+  const double t = dot(n, w0 - r.o) / den;
+  if (!(t > r.tmin && t <= tmax)) return h;
+  const V3 p = r.o + t * r.d;
+  const double c0 = dot(cross(w2 - w1, p - w1), n);
+  const double c1 = dot(cross(w0 - w2, p - w2), n);
+  const double c2 = dot(cross(w1 - w0, p - w0), n);
+  if (c0 < 0 || c1 < 0 || c2 < 0) return h;
+  h.hit = true;
+  h.t = t;
+  h.l0 = c0 / nn;
+  h.l1 = c1 / nn;
+  h.l2 = c2 / nn;
+  return h;
+}
+
+struct Key {
+  double t = kInf;
+  int32_t inst = -1, prim = -1, half = -1;
+  double u = 0, v = 0;
+};
+inline bool key_less(const Key& a, const Key& b) {
+  if (a.t != b.t) return a.t < b.t;
+  if (a.inst != b.inst) return a.inst < b.inst;
+  if (a.prim != b.prim) return a.prim < b.prim;
+  return a.half < b.half;
+}
+
+struct Excl {
+  int32_t inst = -1, prim = -1, half = -1;
+};
+
+// Both halves of one quad.  u, v: v0 -> (0,0), v1 -> (1,0), v2 -> (1,1), v3 -> (0,1).
+inline void quad_hits(const Ray& r, const V3 w[4], double tmax, TriHit hA_hB[2], Key k[2], int32_t inst,
+                      int32_t prim) {
+  hA_hB[0] = tri_test(r, w[0], w[1], w[3], tmax);
+  hA_hB[1] = tri_test(r, w[2], w[3], w[1], tmax);
+  k[0] = Key{hA_hB[0].t, inst, prim, 0, hA_hB[0].l1, hA_hB[0].l2};
+  k[1] = Key{hA_hB[1].t, inst, prim, 1, 1.0 - hA_hB[1].l1, 1.0 - hA_hB[1].l2};
+}
+
+// Closest distance between the ray segment {o + s d, s in [s0, s1]} (s1 may be
+// +inf) and the segment [a, b].  Closest points of two segments after Ericson,
+// "Real-Time Collision Detection", Section 5.1.9.  Also returns the edge point.
+double seg_dist(V3 o, V3 d, double s0, double s1, V3 a, V3 b, V3* q_out) {
+  const V3 d2 = b - a;
+  const V3 rr = o - a;
+  const double A = dot(d, d), E = dot(d2, d2), F = dot(d2, rr);
+  const double C = dot(d, rr), B = dot(d, d2);
+  double s, t;
+  if (E <= 0.0) {  // degenerate edge: point
+    s = std::min(std::max(-C / A, s0), s1);
+    t = 0.0;
+  } else {
+    const double den = A * E - B * B;
+    s = den > 1e-300 * A * E ? std::min(std::max((B * F - C * E) / den, s0), s1) : s0;
+    t = (B * s + F) / E;
+    if (t < 0.0) {
+      t = 0.0;
+      s = std::min(std::max(-C / A, s0), s1);
+    } else if (t > 1.0) {
+      t = 1.0;
+      s = std::min(std::max((B - C) / A, s0), s1);
+    }
+  }
+  const V3 p = o + s * d;
+  const V3 q = a + t * d2;
+  if (q_out) *q_out = q;
+  return norm(p - q);
+}
+
+// ---------------------------------------------------------------- traversal
+inline bool slab(const Ray& r, const Box& b, double pad, double t_hi) {
+  double tn = r.tmin, tf = t_hi;
+  for (int k = 0; k < 3; ++k) {
+    const double o = comp(r.o, k), d = comp(r.d, k);
+    const double lo = b.lo[k] - pad, hi = b.hi[k] + pad;
+    if (d == 0.0) {
+      if (o < lo || o > hi) return false;
+      continue;
+    }
+    double t0 = (lo - o) / d, t1 = (hi - o) / d;
+    if (t0 > t1) std::swap(t0, t1);
+    tn = std::max(tn, t0);
+    tf = std::min(tf, t1);
+  }
+  return tn <= tf;
+}
+
+// Visit every (instance, quad) whose inflated boxes intersect the ray over
+// [tmin, t_hi]; t_hi may shrink as the callback finds hits.  g_world is an
+// extra world-space inflation (graze distance).  mode 0 visits all quads.
+template <class Fn>
+void visit(const Scene& S, const Ray& r, int mode, double g_world, double& t_hi, Fn&& fn) {
+  if (mode == 0) {
+    for (int64_t i = 0; i < S.N; ++i) {
+      const int32_t p = S.iproto[i];
+      for (int64_t q = S.qo[p]; q < S.qo[p + 1]; ++q) fn(i, q);
+    }
+    return;
+  }
+  if (S.inst_bvh.nodes.empty()) return;
+  thread_local std::vector<int32_t> st, st2;
+  st.clear();
+  st.push_back(0);
+  while (!st.empty()) {
+    const Node& nd = S.inst_bvh.nodes[st.back()];
+    st.pop_back();
+    if (!slab(r, nd.b, g_world + 1e-9 * (nd.b.mag() + 1.0), t_hi)) continue;
+    if (nd.count == 0) {
+      st.push_back(nd.left);
+      st.push_back(nd.right);
+      continue;
+    }
+    for (int32_t k = nd.start; k < nd.start + nd.count; ++k) {
+      const int64_t inst = S.inst_bvh.items[k];
+      const Box& wb = S.inst_box[inst];
+      if (!slab(r, wb, g_world + 1e-9 * (wb.mag() + 1.0), t_hi)) continue;
+      const double* Y = &S.Xi[12 * inst];
+      Ray ro{xform_point(Y, r.o), xform_vec(Y, r.d), r.tmin, r.tmax};
+      const double gobj = g_world * S.ainv_frob[inst];
+      const int32_t p = S.iproto[inst];
+      const Bvh& pb = S.proto_bvh[p];
+      if (pb.nodes.empty()) continue;
+      st2.clear();
+      st2.push_back(0);
+      while (!st2.empty()) {
+        const Node& pn = pb.nodes[st2.back()];
+        st2.pop_back();
+        if (!slab(ro, pn.b, gobj + 1e-9 * (pn.b.mag() + 1.0), t_hi)) continue;
+        if (pn.count == 0) {
+          st2.push_back(pn.left);
+          st2.push_back(pn.right);
+          continue;
+        }
+        for (int32_t m = pn.start; m < pn.start + pn.count; ++m) fn(inst, S.qo[p] + pb.items[m]);
+      }
+    }
+  }
+}
+
+struct TraceOut {
+  Key best;
+  uint32_t flags = 0;
+  int32_t ncand = 0;
+  int32_t cand[8];  // up to 4 (inst, prim) pairs hit within the tie window
+  double cos_abs = 0;  // |n.d| / |d| at the best hit
+  double S = 1;
+};
+
+// Closest hit by key, then the flag pass over the same candidate triangles.
+TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int mode, bool any_hit) {
+  TraceOut out;
+  const double dn = norm(r.d);
+  if (!(dn > 0.0) || !std::isfinite(dn) || !std::isfinite(maxabs(r.o))) return out;  // miss
+  // pass 1: the closest hit
+  double t_hi = r.tmax;
+  Key best;
+  visit(S, r, mode, 0.0, t_hi, [&](int64_t inst, int64_t qg) {
+    V3 w[4];
+    quad_world(S, inst, qg, w);
+    TriHit h[2];
+    Key k[2];
+    const int32_t prim = (int32_t)(qg - S.qo[S.iproto[inst]]);
+    quad_hits(r, w, t_hi, h, k, (int32_t)inst, prim);
+    for (int s = 0; s < 2; ++s) {
+      if (!h[s].hit) continue;
+      if (k[s].inst == ex.inst && k[s].prim == ex.prim && k[s].half == ex.half) continue;
+      if (key_less(k[s], best)) best = k[s];
+    }
+    if (best.t < t_hi) t_hi = best.t;
+  });
+  out.best = best;
+  const bool hit = best.inst >= 0;
+  const V3 p = hit ? r.o + best.t * r.d : r.o;
+  const double Sv = std::max(1.0, std::max(maxabs(r.o), maxabs(p)));
+  out.S = Sv;
+  // pass 2: flags
+  double t_end = std::isfinite(r.tmax) ? r.tmax + 1e-5 * r.tmax + 1e-6 * Sv / dn : kInf, win = 0;
+  if (hit) {
+    win = 1e-5 * best.t + 1e-6 * Sv / dn;
+    t_end = best.t + win;
+    if (best.t * dn < 1e-6 * Sv + r0) out.flags |= F_NEAR_ORIGIN;
+    V3 w[4];
+    quad_world(S, best.inst, S.qo[S.iproto[best.inst]] + best.prim, w);
+    const V3 n = best.half == 0 ? cross(w[1] - w[0], w[3] - w[0]) : cross(w[3] - w[2], w[1] - w[2]);
+    out.cos_abs = std::fabs(dot(n, r.d)) / (norm(n) * dn);
+    if (16.0 * std::ldexp(1.0, -24) * Sv > 1e-5 * best.t * dn * out.cos_abs) out.flags |= F_T_ILLCOND;
+  }
+  const double s_hi = hit ? std::max(Sv, maxabs(r.o) + t_end * maxabs(r.d)) : std::max(Sv, S.scene_mag);
+  const double g_cull = 1e-6 * s_hi * 1.01 + r0;
+  double t_lim = t_end;
+  visit(S, r, mode, g_cull, t_lim, [&](int64_t inst, int64_t qg) {
+    V3 w[4];
+    quad_world(S, inst, qg, w);
+    const int32_t prim = (int32_t)(qg - S.qo[S.iproto[inst]]);
+    TriHit h[2];
+    Key k[2];
+    quad_hits(r, w, t_end, h, k, (int32_t)inst, prim);
+    const bool same = hit && inst == best.inst && prim == best.prim;
+    for (int s = 0; s < 2; ++s) {
+      if (!h[s].hit) continue;
+      if (k[s].inst == ex.inst && k[s].prim == ex.prim && k[s].half == ex.half) continue;
+      if (!same) {
+        out.flags |= F_NEAR_TIE;
+        bool dup = false;
+        for (int c = 0; c < out.ncand; ++c)
+          if (out.cand[2 * c] == (int32_t)inst && out.cand[2 * c + 1] == prim) dup = true;
+        if (!dup && out.ncand < 4) {
+          out.cand[2 * out.ncand] = (int32_t)inst;
+          out.cand[2 * out.ncand + 1] = prim;
+          out.ncand++;
+        }
+      } else if (s != best.half) {
+        out.flags |= F_DIAG;
+      }
+    }
+    static const int E[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
+    for (int e = 0; e < 4; ++e) {
+      V3 q;
+      const double dist = seg_dist(r.o, r.d, r.tmin, t_end, w[E[e][0]], w[E[e][1]], &q);
+      const double g = 1e-6 * std::max(Sv, maxabs(q)) + r0;
+      if (dist < g) out.flags |= F_GRAZE;
+    }
+    if (same) {
+      V3 q;
+      const double dist = seg_dist(r.o, r.d, r.tmin, t_end, w[1], w[3], &q);
+      if (dist < 1e-6 * std::max(Sv, maxabs(q)) + r0) out.flags |= F_DIAG;
+    }
+  });
+  if (any_hit) out.flags &= ~(uint32_t)(F_NEAR_TIE | F_DIAG | F_T_ILLCOND);
+  return out;
+}
+
+// ---------------------------------------------------------------- RNG
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011).
+void philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+inline double unit(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+// ---------------------------------------------------------------- rendering
+struct Params {
+  int32_t spp, depth;
+  uint64_t seed;
+  uint32_t frame;
+  double light[3];
+  double E, L_sky;
+};
+
+struct Cam {
+  V3 eye, f, r, u;
+  double tan_half, aspect;
+  int64_t w, h, off;
+};
+
+Cam make_cam(const double* cf, const int64_t* ci) {
+  Cam c;
+  c.eye = {cf[0], cf[1], cf[2]};
+  const V3 look{cf[3], cf[4], cf[5]}, up{cf[6], cf[7], cf[8]};
+  c.f = normalize(look - c.eye);
+  c.r = normalize(cross(c.f, up));
+  c.u = cross(c.r, c.f);
+  c.tan_half = std::tan(0.5 * cf[9] * kPi / 180.0);
+  c.w = ci[0];
+  c.h = ci[1];
+  c.off = ci[2];
+  c.aspect = (double)c.w / (double)c.h;
+  return c;
+}
+
+// One sampled path, recorded vertex by vertex (for the image and both gradient forms).
+struct Vertex {
+  int64_t face;
+  double a;      // albedo at the vertex
+  double c;      // (E / pi) * cos_L * visibility: the NEE factor without beta and albedo
+};
+struct PathRec {
+  int nv = 0;
+  Vertex v[64];
+  bool escaped = false;
+  uint32_t flags = 0;
+  int n_closest = 0, n_shadow = 0, n_incoherent = 0;
+};
+
+void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, int64_t pix, int32_t sample,
+                int mode, PathRec& rec) {
+  const uint32_t key[2] = {(uint32_t)(P.seed & 0xffffffffu), (uint32_t)(P.seed >> 32) ^ P.frame};
+  const V3 L{P.light[0], P.light[1], P.light[2]};
+  uint32_t w[4];
+  uint32_t ctr[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0u};
+  philox(ctr, key, w);
+  const int64_t x = pix % cam.w, y = pix / cam.w;
+  const double sx = (2.0 * ((double)x + unit(w[0])) / (double)cam.w - 1.0) * cam.tan_half * cam.aspect;
+  const double sy = (1.0 - 2.0 * ((double)y + unit(w[1])) / (double)cam.h) * cam.tan_half;
+  Ray ray{cam.eye, normalize(cam.f + sx * cam.r + sy * cam.u), 0.0, kInf};
+  Excl ex;
+  double r0 = 0.0;
+  for (int b = 0; b < P.depth; ++b) {
+    TraceOut h = trace_one(S, ray, ex, r0, mode, false);
+    rec.n_closest++;
+    if (b >= 1) rec.n_incoherent++;
+    rec.flags |= h.flags & ~(uint32_t)F_T_ILLCOND;
+    if (h.best.inst < 0) {
+      rec.escaped = true;
+      return;
+    }
+    V3 wq[4];
+    const int32_t pr = S.iproto[h.best.inst];
+    const int64_t face = S.qo[pr] + h.best.prim;
+    quad_world(S, h.best.inst, face, wq);
+    V3 n = h.best.half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
+    n = normalize(n);
+    const double nd = dot(n, ray.d);
+    if (std::fabs(nd) < 1e-3) rec.flags |= F_SHADE;
+    if (nd > 0) n = -1.0 * n;
+    const V3 p = ray.o + h.best.t * ray.d;
+    const double a = S.albedo[face];
+    Vertex vx{face, a, 0.0};
+    const double cl = dot(n, L);
+    if (std::fabs(cl) < 1e-6) rec.flags |= F_SHADE;
+    // origin uncertainty of rays leaving p: FP32 position error amplified by the incidence angle
+    const double r1 = 16.0 * std::ldexp(1.0, -24) * h.S / std::max(h.cos_abs, 1e-3);
+    const Excl here{h.best.inst, h.best.prim, h.best.half};
+    if (cl > 0) {
+      Ray sr{p, L, 0.0, kInf};
+      TraceOut o = trace_one(S, sr, here, r1, mode, true);
+      rec.n_shadow++;
+      rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
+      if (o.best.inst < 0) vx.c = P.E / kPi * cl;
+    }
+    rec.v[rec.nv++] = vx;
+    if (b == P.depth - 1) return;
+    uint32_t ctr2[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, (uint32_t)b};
+    philox(ctr2, key, w);
+    const double u1 = unit(w[2]), u2 = unit(w[3]);
+    if (std::fabs(n.z) < 1e-6) rec.flags |= F_SHADE;
+    const double sg = n.z >= 0 ? 1.0 : -1.0;
+    const double aa = -1.0 / (sg + n.z);
+    const double bb = n.x * n.y * aa;
+    const V3 t1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
+    const V3 t2{bb, sg + n.y * n.y * aa, -n.y};
+    const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
+    const V3 dnew = (rr * std::cos(phi)) * t1 + (rr * std::sin(phi)) * t2 + std::sqrt(1.0 - u1) * n;
+    ray = Ray{p, dnew, 0.0, kInf};
+    ex = here;
+    r0 = r1;
+  }
+}
+
+// Radiance of a recorded path, in the order the terms arise.
+double path_value(const Params& P, const PathRec& rec) {
+  double L = 0.0, beta = 1.0;
+  for (int k = 0; k < rec.nv; ++k) {
+    L += beta * rec.v[k].a * rec.v[k].c;
+    beta *= rec.v[k].a;
+  }
+  if (rec.escaped) L += beta * P.L_sky;
+  return L;
+}
+
+template <class Fn>
+void parallel_for(int64_t n, int nthreads, Fn&& fn) {
+  if (nthreads <= 1 || n < 2) {
+    for (int64_t i = 0; i < n; ++i) fn(i, 0);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> th;
+  const int64_t chunk = 64;
+  for (int t = 0; t < nthreads; ++t)
+    th.emplace_back([&, t] {
+      for (;;) {
+        const int64_t s = next.fetch_add(chunk);
+        if (s >= n) break;
+        const int64_t e = std::min(n, s + chunk);
+        for (int64_t i = s; i < e; ++i) fn(i, t);
+      }
+    });
+  for (auto& x : th) x.join();
+}
+
+int g_threads = 0;
+int threads() {
+  if (g_threads > 0) return g_threads;
+  const unsigned h = std::thread::hardware_concurrency();
+  return h ? (int)h : 1;
+}
+
+void resolve_pixel(const std::vector<Cam>& cams, int64_t g, int32_t* view, int64_t* pix) {
+  for (size_t c = 0; c < cams.size(); ++c)
+    if (g >= cams[c].off && g < cams[c].off + cams[c].w * cams[c].h) {
+      *view = (int32_t)c;
+      *pix = g - cams[c].off;
+      return;
+    }
+  *view = -1;
+  *pix = -1;
+}
+
+}  // namespace
+
+// =============================================================== C ABI
+extern "C" {
+
+void orc_set_threads(int n) { g_threads = n; }
+int orc_get_threads() { return threads(); }
+
+void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox(ctr, key, out); }
+
+void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads, int64_t n_quads,
+                       const int64_t* proto_vert_off, const int64_t* proto_quad_off, int32_t n_protos,
+                       const float* albedo, const int32_t* inst_proto, const float* inst_xform, int64_t n_inst) {
+  Scene* S = new Scene;
+  S->P = n_protos;
+  S->verts.resize(n_verts);
+  for (int64_t i = 0; i < n_verts; ++i) S->verts[i] = {verts[3 * i], verts[3 * i + 1], verts[3 * i + 2]};
+  S->quads.assign(quads, quads + 4 * n_quads);
+  S->vo.assign(proto_vert_off, proto_vert_off + n_protos + 1);
+  S->qo.assign(proto_quad_off, proto_quad_off + n_protos + 1);
+  S->albedo.resize(n_quads);
+  for (int64_t i = 0; i < n_quads; ++i) S->albedo[i] = albedo ? (double)albedo[i] : 0.5;
+  S->N = n_inst;
+  S->iproto.assign(inst_proto, inst_proto + n_inst);
+  S->X.resize(12 * n_inst);
+  S->Xi.resize(12 * n_inst);
+  S->ainv_frob.resize(n_inst);
+  for (int64_t i = 0; i < 12 * n_inst; ++i) S->X[i] = inst_xform[i];
+  for (int64_t i = 0; i < n_inst; ++i) {
+    if (!invert_affine(&S->X[12 * i], &S->Xi[12 * i])) {
+      delete S;
+      return nullptr;
+    }
+    double f = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) f += S->Xi[12 * i + 4 * r + c] * S->Xi[12 * i + 4 * r + c];
+    S->ainv_frob[i] = std::sqrt(f);
+  }
+  // per-prototype object-space BVHs over quads (built in parallel over prototypes)
+  S->proto_box.resize(n_protos);
+  S->proto_bvh.resize(n_protos);
+  parallel_for(n_protos, threads(), [&](int64_t p, int) {
+    std::vector<Box> qb(S->qo[p + 1] - S->qo[p]);
+    Box all;
+    for (int64_t q = S->qo[p]; q < S->qo[p + 1]; ++q) {
+      Box b;
+      for (int k = 0; k < 4; ++k) b.grow(S->verts[S->vo[p] + S->quads[4 * q + k]]);
+      qb[q - S->qo[p]] = b;
+      all.grow(b);
+    }
+    S->proto_box[p] = all;
+    S->proto_bvh[p].build(qb);
+  });
+  // world boxes of instances: the 8 transformed corners of the prototype box
+  S->inst_box.resize(n_inst);
+  double mag = 1.0;
+  for (int64_t i = 0; i < n_inst; ++i) {
+    const Box& pb = S->proto_box[S->iproto[i]];
+    Box wb;
+    if (pb.lo[0] <= pb.hi[0])
+      for (int c = 0; c < 8; ++c) {
+        V3 v{(c & 1) ? pb.hi[0] : pb.lo[0], (c & 2) ? pb.hi[1] : pb.lo[1], (c & 4) ? pb.hi[2] : pb.lo[2]};
+        wb.grow(xform_point(&S->X[12 * i], v));
+      }
+    S->inst_box[i] = wb;
+    if (pb.lo[0] <= pb.hi[0]) mag = std::max(mag, wb.mag());
+  }
+  S->scene_mag = mag;
+  S->inst_bvh.build(S->inst_box);
+  return S;
+}
+
+void orc_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
+
+int orc_scene_set_albedo(void* s, const double* albedo) {
+  Scene* S = static_cast<Scene*>(s);
+  for (size_t i = 0; i < S->albedo.size(); ++i) S->albedo[i] = albedo[i];
+  return 0;
+}
+
+// rays: n x 8 (ox oy oz dx dy dz tmin tmax), FP32 (read as exact doubles) or FP64.
+// excl: n x 3 (inst, prim, half) or NULL; r0: per-ray origin uncertainty or NULL.
+// cand: n x 8 int32 ((inst, prim) x 4) or NULL.
+}  // extern "C"
+
+template <class T>
+static void trace_many(void* s, int64_t n, const T* rays, const int32_t* excl, const double* r0, int32_t mode,
+                       int32_t any_hit, double* t, int32_t* inst, int32_t* prim, int32_t* half, double* u,
+                       double* v, uint32_t* flags, int32_t* cand, int32_t* ncand) {
+  const Scene& S = *static_cast<Scene*>(s);
+  parallel_for(n, threads(), [&](int64_t i, int) {
+    const T* R = rays + 8 * i;
+    Ray r{{(double)R[0], (double)R[1], (double)R[2]}, {(double)R[3], (double)R[4], (double)R[5]}, (double)R[6],
+          (double)R[7]};
+    Excl ex;
+    if (excl) ex = {excl[3 * i], excl[3 * i + 1], excl[3 * i + 2]};
+    TraceOut o = trace_one(S, r, ex, r0 ? r0[i] : 0.0, mode, any_hit != 0);
+    t[i] = o.best.t;
+    inst[i] = o.best.inst;
+    prim[i] = o.best.prim;
+    half[i] = o.best.half;
+    u[i] = o.best.inst >= 0 ? o.best.u : 0.0;
+    v[i] = o.best.inst >= 0 ? o.best.v : 0.0;
+    flags[i] = o.flags;
+    if (cand) {
+      for (int c = 0; c < 8; ++c) cand[8 * i + c] = c < 2 * o.ncand ? o.cand[c] : -1;
+    }
+    if (ncand) ncand[i] = o.ncand;
+  });
+}
+
+extern "C" {
+
+void orc_trace(void* s, int64_t n, const float* rays, const int32_t* excl, const double* r0, int32_t mode,
+               int32_t any_hit, double* t, int32_t* inst, int32_t* prim, int32_t* half, double* u, double* v,
+               uint32_t* flags, int32_t* cand, int32_t* ncand) {
+  trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand);
+}
+
+void orc_trace_d(void* s, int64_t n, const double* rays, const int32_t* excl, const double* r0, int32_t mode,
+                 int32_t any_hit, double* t, int32_t* inst, int32_t* prim, int32_t* half, double* u, double* v,
+                 uint32_t* flags, int32_t* cand, int32_t* ncand) {
+  trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand);
+}
+
+// Image (or listed pixels) of n_cams pinhole cameras.  cam_f: n x 10 (eye, look,
+// up, vfov); cam_i: n x 3 (w, h, offset of the view in the packed image).
+// pix: global packed pixel indices, or NULL for every pixel.  stats (may be NULL):
+// [closest rays, shadow rays, incoherent (bounce >= 1) rays, flagged pixels].
+void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
+                const uint64_t* pu, const double* pd, const int64_t* pix, int64_t n_pix, int32_t mode,
+                double* image, uint8_t* pflags, double* stats) {
+  const Scene& S = *static_cast<Scene*>(s);
+  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  std::vector<Cam> cams;
+  int64_t total = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
+    total += cams.back().w * cams.back().h;
+  }
+  const int64_t n = pix ? n_pix : total;
+  const int nt = threads();
+  std::vector<double> st(4 * nt, 0.0);
+  parallel_for(n, nt, [&](int64_t i, int tid) {
+    const int64_t g = pix ? pix[i] : i;
+    int32_t view;
+    int64_t p;
+    resolve_pixel(cams, g, &view, &p);
+    double sum = 0.0;
+    uint32_t fl = 0;
+    for (int32_t smp = 0; smp < P.spp; ++smp) {
+      PathRec rec;
+      trace_path(S, P, cams[view], view, p, smp, mode, rec);
+      sum += path_value(P, rec);
+      fl |= rec.flags;
+      st[4 * tid + 0] += rec.n_closest;
+      st[4 * tid + 1] += rec.n_shadow;
+      st[4 * tid + 2] += rec.n_incoherent;
+    }
+    image[i] = sum / P.spp;
+    pflags[i] = (uint8_t)(fl != 0);
+    st[4 * tid + 3] += fl != 0;
+  });
+  if (stats)
+    for (int k = 0; k < 4; ++k) {
+      stats[k] = 0;
+      for (int t2 = 0; t2 < nt; ++t2) stats[k] += st[4 * t2 + k];
+    }
+}
+
+// Gradient of sum_p g_p * I_p with respect to per-face albedo, paths held fixed.
+// mode 0: path replay, dI/da_f = (1/spp) sum_s sum_{k: f_k = f} S_k / a_k with
+//         S_k = sum_{j >= k} D_j + M (contributions from vertex k onward).
+// mode 1: forward-mode dual numbers along `tangent` (per face); writes the
+//         directional derivative of each listed pixel into dI (grad_albedo unused).
+void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
+              const uint64_t* pu, const double* pd, const int64_t* pix, int64_t n_pix, int32_t mode,
+              const double* gpix, int32_t grad_mode, const double* tangent, double* grad_albedo, double* dI,
+              uint8_t* pflags, uint8_t* face_tainted) {
+  const Scene& S = *static_cast<Scene*>(s);
+  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  std::vector<Cam> cams;
+  int64_t total = 0;
+  for (int c = 0; c < n_cams; ++c) {
+    cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
+    total += cams.back().w * cams.back().h;
+  }
+  const int64_t n = pix ? n_pix : total;
+  const int nt = threads();
+  const int64_t Q = (int64_t)S.albedo.size();
+  std::vector<std::vector<double>> gacc(grad_mode == 0 ? nt : 0, std::vector<double>(grad_mode == 0 ? Q : 0, 0.0));
+  std::vector<std::vector<uint8_t>> taint(face_tainted ? nt : 0, std::vector<uint8_t>(face_tainted ? Q : 0, 0));
+  parallel_for(n, nt, [&](int64_t i, int tid) {
+    const int64_t g = pix ? pix[i] : i;
+    int32_t view;
+    int64_t p;
+    resolve_pixel(cams, g, &view, &p);
+    uint32_t fl = 0;
+    double dsum = 0.0;
+    for (int32_t smp = 0; smp < P.spp; ++smp) {
+      PathRec rec;
+      trace_path(S, P, cams[view], view, p, smp, mode, rec);
+      fl |= rec.flags;
+      if (grad_mode == 0) {
+        // D_k = beta_k a_k c_k; S_k = sum_{j>=k} D_j + M.  Accumulate S_k / a_k.
+        std::vector<double> beta(rec.nv + 1, 1.0);
+        for (int k = 0; k < rec.nv; ++k) beta[k + 1] = beta[k] * rec.v[k].a;
+        double tail = rec.escaped ? beta[rec.nv] * P.L_sky : 0.0;
+        for (int k = rec.nv - 1; k >= 0; --k) {
+          tail += beta[k] * rec.v[k].a * rec.v[k].c;  // now tail = S_k
+          gacc[tid][rec.v[k].face] += gpix[i] * tail / rec.v[k].a / P.spp;
+        }
+      } else {
+        // dual numbers (value, derivative) along the tangent direction
+        double L = 0, dL = 0, beta = 1, dbeta = 0;
+        for (int k = 0; k < rec.nv; ++k) {
+          const double a = rec.v[k].a, da = tangent[rec.v[k].face];
+          const double c = rec.v[k].c;
+          L += beta * a * c;
+          dL += (dbeta * a + beta * da) * c;
+          const double nb = beta * a;
+          dbeta = dbeta * a + beta * da;
+          beta = nb;
+        }
+        if (rec.escaped) {
+          L += beta * P.L_sky;
+          dL += dbeta * P.L_sky;
+        }
+        dsum += dL;
+      }
+      if (face_tainted && rec.flags)
+        for (int k = 0; k < rec.nv; ++k) taint[tid][rec.v[k].face] = 1;
+    }
+    if (grad_mode == 1) dI[i] = dsum / P.spp;
+    if (pflags) pflags[i] = (uint8_t)(fl != 0);
+  });
+  if (grad_mode == 0)
+    for (int64_t f = 0; f < Q; ++f) {
+      double acc = 0;
+      for (int t2 = 0; t2 < nt; ++t2) acc += gacc[t2][f];
+      grad_albedo[f] = acc;
+    }
+  if (face_tainted)
+    for (int64_t f = 0; f < Q; ++f) {
+      uint8_t any = 0;
+      for (int t2 = 0; t2 < nt; ++t2) any |= taint[t2][f];
+      face_tainted[f] = any;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test names what fixes the expected value: a published known-answer vector,
+a closed form, brute force, or an invariant of the mathematics.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_02620_amd import scenegen as sg
+from tests import scenes as ts
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------- RNG (P7)
+def _philox_bigint(ctr, key):
+    """Philox4x32-10 written from the published description with Python integers."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    c = list(ctr)
+    k0, k1 = key
+    for r in range(10):
+        if r:
+            k0 = (k0 + W0) & 0xFFFFFFFF
+            k1 = (k1 + W1) & 0xFFFFFFFF
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF, ((p0 >> 32) ^ c[3] ^ k1) & 0xFFFFFFFF,
+             p0 & 0xFFFFFFFF]
+    return c
+
+
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(x, 16) for x in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def test_philox_known_answers(ora):
+    rows = _kat()
+    assert len(rows) == 3
+    for ctr, key, out in rows:
+        assert list(oracle.philox(ctr, key)) == out
+        assert _philox_bigint(ctr, key) == out
+
+
+def test_philox_bigint_agrees_and_is_uniform(ora):
+    rng = np.random.default_rng(7)
+    us = []
+    for _ in range(2000):
+        ctr = [int(x) for x in rng.integers(0, 2 ** 32, size=4, dtype=np.uint64)]
+        key = [int(x) for x in rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)]
+        o = [int(x) for x in oracle.philox(ctr, key)]
+        assert o == _philox_bigint(ctr, key)
+        us.extend([(w >> 8) * 2.0 ** -24 for w in o])
+    us = np.array(us)
+    assert abs(us.mean() - 0.5) < 0.01
+    hist = np.histogram(us, bins=16, range=(0, 1))[0]
+    chi2 = ((hist - us.size / 16) ** 2 / (us.size / 16)).sum()
+    assert chi2 < 45.0  # 15 dof, p ~ 1e-4
+    assert us.min() >= 0.0 and us.max() < 1.0
+
+
+# --------------------------------------------------------------------- analytic quads (P1)
+def _rays(o, d, tmin=0.0, tmax=np.inf):
+    o = np.atleast_2d(o)
+    d = np.atleast_2d(d)
+    r = np.zeros((o.shape[0], 8))
+    r[:, 0:3] = o
+    r[:, 3:6] = d
+    r[:, 6] = tmin
+    r[:, 7] = tmax
+    return r
+
+
+def test_axis_aligned_quad_closed_form(ora):
+    x0, x1, y0, y1, c = -1.5, 2.0, -0.5, 1.25, 0.75
+    scene = ts.multi_mesh_scene([ts.axis_quad(x0, x1, y0, y1, c)])
+    o = oracle.OracleScene(scene)
+    rng = np.random.default_rng(11)
+    n = 4000
+    org = np.stack([rng.uniform(-4, 4, n), rng.uniform(-4, 4, n), rng.choice([-3.0, 4.0], n)], 1)
+    tgt = np.stack([rng.uniform(x0 - 1, x1 + 1, n), rng.uniform(y0 - 1, y1 + 1, n), np.full(n, c)], 1)
+    d = (tgt - org) * rng.uniform(0.5, 2.0, (n, 1))
+    h = o.trace(_rays(org, d))
+    uu = (tgt[:, 0] - x0) / (x1 - x0)
+    vv = (tgt[:, 1] - y0) / (y1 - y0)
+    margin = 1e-6
+    inside = (uu > margin) & (uu < 1 - margin) & (vv > margin) & (vv < 1 - margin)
+    outside = (uu < -margin) | (uu > 1 + margin) | (vv < -margin) | (vv > 1 + margin)
+    t_exp = (c - org[:, 2]) / d[:, 2]
+    assert (h.inst[outside] == -1).all() and np.isinf(h.t[outside]).all()
+    assert (h.inst[inside] == 0).all() and (h.prim[inside] == 0).all()
+    np.testing.assert_allclose(h.t[inside], t_exp[inside], rtol=1e-12)
+    np.testing.assert_allclose(h.u[inside], uu[inside], atol=1e-12)
+    np.testing.assert_allclose(h.v[inside], vv[inside], atol=1e-12)
+    # the diagonal v1-v3 separates half A (u + v < 1) from half B
+    off_diag = inside & (np.abs(uu + vv - 1) > 1e-6)
+    np.testing.assert_array_equal(h.half[off_diag], (uu[off_diag] + vv[off_diag] > 1).astype(np.int32))
+    # both faces count: rays from below and from above both hit
+    assert (h.inst[inside & (org[:, 2] < c)] == 0).all() and (h.inst[inside & (org[:, 2] > c)] == 0).all()
+
+
+def test_interval_and_degenerate_rules(ora):
+    scene = ts.multi_mesh_scene([ts.axis_quad(-1, 1, -1, 1, 0.0)])
+    o = oracle.OracleScene(scene)
+    org = np.array([[0.25, 0.25, 2.0]] * 6)
+    d = np.array([[0, 0, -1.0]] * 6)
+    r = _rays(org, d)
+    r[0, 7] = 2.0      # t == tmax: accepted (tmin < t <= tmax)
+    r[1, 7] = 1.999    # t > tmax: miss
+    r[2, 6] = 2.0      # t == tmin: rejected
+    r[3, 3:6] = 0.0    # zero direction: miss
+    r[4, 3] = np.nan   # NaN direction: miss
+    h = o.trace(r)
+    assert h.inst[0] == 0 and h.t[0] == 2.0
+    assert h.inst[1] == -1 and h.inst[2] == -1 and h.inst[3] == -1 and h.inst[4] == -1
+    assert h.inst[5] == 0 and h.t[5] == 2.0
+    # a degenerate (zero-area) quad is never hit
+    v = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [3, 0, 0]], np.float32)
+    deg = ts.multi_mesh_scene([(v, np.array([[0, 1, 2, 3]], np.int32))])
+    hd = oracle.OracleScene(deg).trace(_rays([[1.0, 0.0, 1.0]], [[0, 0, -1.0]]))
+    assert hd.inst[0] == -1
+
+
+def test_miss_encoding(ora):
+    scene = ts.multi_mesh_scene([ts.axis_quad(-1, 1, -1, 1, 0.0)])
+    h = oracle.OracleScene(scene).trace(_rays([[5.0, 5.0, 1.0]], [[0, 0, -1.0]]))
+    assert np.isinf(h.t[0]) and h.inst[0] == -1 and h.prim[0] == -1 and h.u[0] == 0 and h.v[0] == 0
+
+
+# --------------------------------------------------------------------- brute force (P2)
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_bvh_equals_brute_force(ora, seed):
+    rng = np.random.default_rng(100 + seed)
+    scene = sg.tiny_scene(seed, n_inst=4, n_protos=2, nq=int(rng.integers(2, 9)), spread=1.5)
+    o = oracle.OracleScene(scene)
+    rays = np.concatenate([sg.random_rays(rng, 4000, -5, 5, -2, 2),      # from outside
+                           sg.random_rays(rng, 2000, -1, 1, -3, 3)])     # from inside the cluster
+    excl = np.full((rays.shape[0], 3), -1, np.int32)
+    excl[::7] = [0, 1, 0]
+    hb = o.trace(rays, excl=excl, brute=True)
+    hv = o.trace(rays, excl=excl)
+    for f in ("t", "inst", "prim", "half", "u", "v", "flags", "ncand"):
+        np.testing.assert_array_equal(getattr(hb, f), getattr(hv, f), err_msg=f)
+    assert (hb.inst >= 0).mean() > 0.2
+    # occlusion queries agree too
+    ob = o.trace(rays, excl=excl, brute=True, any_hit=True)
+    ov = o.trace(rays, excl=excl, any_hit=True)
+    np.testing.assert_array_equal(ob.inst >= 0, ov.inst >= 0)
+    np.testing.assert_array_equal(ob.flags, ov.flags)
+
+
+def test_brute_force_closest_is_minimum_over_all_triangles(ora):
+    """Independent check of the closest-hit definition: per-triangle hits computed
+    here with numpy (Moller-Trumbore, a different formulation) on world vertices."""
+    scene = sg.tiny_scene(9, n_inst=3, n_protos=1, nq=3, spread=1.0)
+    rng = np.random.default_rng(5)
+    rays = sg.random_rays(rng, 3000, -4, 4, -1.5, 1.5).astype(np.float64)
+    h = oracle.OracleScene(scene).trace(rays, brute=True)
+    P = scene.inst_proto
+    best_t = np.full(rays.shape[0], np.inf)
+    best_key = np.full((rays.shape[0], 3), -1)
+    for i in range(scene.n_instances):
+        X = scene.inst_xform[i].astype(np.float64).reshape(3, 4)
+        p = P[i]
+        vs = scene.verts[scene.proto_vert_off[p]:scene.proto_vert_off[p + 1]].astype(np.float64)
+        W = vs @ X[:, :3].T + X[:, 3]
+        for q in range(scene.proto_quad_off[p + 1] - scene.proto_quad_off[p]):
+            idx = scene.quads[scene.proto_quad_off[p] + q]
+            for half, tri in ((0, (0, 1, 3)), (1, (2, 3, 1))):
+                a, b, c = W[idx[tri[0]]], W[idx[tri[1]]], W[idx[tri[2]]]
+                e1, e2 = b - a, c - a
+                o_, d_ = rays[:, 0:3], rays[:, 3:6]
+                pv = np.cross(d_, e2)
+                det = pv @ e1
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    inv = 1.0 / det
+                    tv = o_ - a
+                    bu = (tv * pv).sum(1) * inv
+                    qv = np.cross(tv, e1)
+                    bv = (d_ * qv).sum(1) * inv
+                    tt = (qv @ e2) * inv
+                ok = (det != 0) & (bu >= 0) & (bv >= 0) & (bu + bv <= 1) & (tt > 0)
+                better = ok & (tt < best_t)
+                best_t[better] = tt[better]
+                best_key[better] = [i, q, half]
+    clean = (h.flags & oracle.ID_FLAGS) == 0
+    assert clean.mean() > 0.95
+    np.testing.assert_array_equal(h.inst[clean], best_key[clean, 0])
+    np.testing.assert_array_equal(h.prim[clean], best_key[clean, 1])
+    hit = clean & (h.inst >= 0)
+    np.testing.assert_allclose(h.t[hit], best_t[hit], rtol=1e-10)
+
+
+# --------------------------------------------------------------------- instance invariant (P3)
+def test_instance_equals_prototype_under_inverse(ora):
+    rng = np.random.default_rng(21)
+    v, q = sg.grid_proto(rng, 8, 8, 1.0, 1.0, 0.3)
+    R = sg.shoemake_rotations(rng, 1)
+    X = sg.compose_xforms(R, np.array([1.7]), np.array([[3.0, -2.0, 5.0]]))
+    world = sg.single_mesh_scene(v, q, xforms=X)
+    proto = sg.single_mesh_scene(v, q)
+    Xd = X.astype(np.float64).reshape(3, 4)
+    A, t = Xd[:, :3], Xd[:, 3]
+    Ai = np.linalg.inv(A)
+    n = 5000
+    org = rng.uniform(-4, 4, (n, 3)) + t
+    tgt = rng.uniform(-1.2, 1.2, (n, 3)) @ A.T + t
+    rw = _rays(org, tgt - org)
+    ro = _rays((org - t) @ Ai.T, (tgt - org) @ Ai.T)
+    hw = oracle.OracleScene(world).trace(rw)
+    ho = oracle.OracleScene(proto).trace(ro)
+    clean = ((hw.flags | ho.flags) & (oracle.ID_FLAGS | oracle.F_DIAG)) == 0
+    assert clean.mean() > 0.97
+    np.testing.assert_array_equal(hw.prim[clean], ho.prim[clean])
+    np.testing.assert_array_equal(hw.half[clean], ho.half[clean])
+    hit = clean & (hw.inst >= 0)
+    assert hit.mean() > 0.3
+    np.testing.assert_allclose(hw.t[hit], ho.t[hit], rtol=1e-12)
+    np.testing.assert_allclose(hw.u[hit], ho.u[hit], atol=1e-9)
+    np.testing.assert_allclose(hw.v[hit], ho.v[hit], atol=1e-9)
+
+
+# --------------------------------------------------------------------- watertightness (P4)
+def test_closed_shell_rays_from_inside(ora):
+    scene, v, q = ts.shell_scene(seed=3, n=6)
+    o = oracle.OracleScene(scene)
+    centre = np.zeros(3)
+    # every vertex and every edge midpoint
+    targets = [v.astype(np.float64)]
+    for a, b in ((0, 1), (1, 2), (2, 3), (3, 0)):
+        targets.append(0.5 * (v[q[:, a]].astype(np.float64) + v[q[:, b]].astype(np.float64)))
+    tg = np.concatenate(targets)
+    rng = np.random.default_rng(3)
+    rnd = rng.normal(size=(20000, 3))
+    rays = np.concatenate([_rays(np.tile(centre, (tg.shape[0], 1)), tg), _rays(np.zeros((20000, 3)), rnd)])
+    h = o.trace(rays)
+    missed = h.inst < 0
+    # aimed at vertices/edges: any miss must be flagged as a graze
+    assert ((h.flags[missed] & oracle.F_GRAZE) != 0).all()
+    # random interior directions: a closed shell is never missed
+    assert not missed[tg.shape[0]:].any()
+
+
+# --------------------------------------------------------------------- flags
+def test_flags_fire_on_constructed_cases(ora):
+    quad = ts.axis_quad(-1, 1, -1, 1, 0.0)
+    # two identical instances: every hit is an exact tie between instances 0 and 1
+    twin = ts.multi_mesh_scene([quad], xforms=sg.identity_xform(2), protos=[0, 0])
+    h = oracle.OracleScene(twin).trace(_rays([[0.3, 0.2, 1.0]], [[0, 0, -1.0]]))
+    assert h.inst[0] == 0 and (h.flags[0] & oracle.F_NEAR_TIE)
+    assert h.ncand[0] == 1 and list(h.cand[0, :2]) == [1, 0]
+    # a 2x1 strip: aim at the shared edge x = 0
+    v = np.array([[-1, -1, 0], [0, -1, 0], [0, 1, 0], [-1, 1, 0], [1, -1, 0], [1, 1, 0]], np.float32)
+    qd = np.array([[0, 1, 2, 3], [1, 4, 5, 2]], np.int32)
+    strip = ts.multi_mesh_scene([(v, qd)])
+    r = _rays([[0.0, 0.3, 1.0], [-0.5, 0.3, 1.0]], [[0, 0, -1.0], [0, 0, -1.0]])
+    h = oracle.OracleScene(strip).trace(r)
+    assert h.flags[0] & oracle.F_GRAZE
+    assert h.flags[1] == 0 and h.inst[1] == 0 and h.prim[1] == 0
+    # a ray starting on the surface: near-origin
+    h = oracle.OracleScene(strip).trace(_rays([[-0.5, 0.3, 1e-9]], [[0, 0, -1.0]]))
+    assert h.flags[0] & oracle.F_NEAR_ORIGIN
+
+
+# --------------------------------------------------------------------- closed-form images (P6)
+def _down_camera(res=16, eye=(0.0, 0.0, 10.0), vfov=30.0):
+    return [sg.Camera(eye, (eye[0], eye[1], 0.0), (0.0, 1.0, 0.0), vfov, res, res)]
+
+
+def test_empty_view_is_sky(ora):
+    scene = ts.multi_mesh_scene([ts.axis_quad(-1, 1, -1, 1, 0.0)],
+                                xforms=[[1, 0, 0, 0, 0, 1, 0, 500, 0, 0, 1, 0]])
+    cams = [sg.Camera((0.0, 0.0, 10.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 30.0, 16, 12)]
+    st = sg.RenderSettings(spp=2, depth=3, seed=5)
+    img, fl, _ = oracle.OracleScene(scene).render(cams, st)
+    assert (img == st.L_sky).all() and (fl == 0).all()
+
+
+@pytest.mark.parametrize("depth", [1, 2, 5])
+def test_floor_closed_form(ora, depth):
+    a = float(np.float32(0.35))  # albedo is stored in FP32
+    scene = ts.floor_scene(albedo=a)
+    st = sg.RenderSettings(spp=2, depth=depth, seed=9)
+    img, fl, _ = oracle.OracleScene(scene).render(_down_camera(), st)
+    cosl = st.light_dir[2]
+    expect = a * (st.E / math.pi) * cosl + (a * st.L_sky if depth >= 2 else 0.0)
+    np.testing.assert_allclose(img, expect, rtol=1e-12)
+    assert (fl == 0).all()
+
+
+def test_floor_with_occluder_shadow_region(ora):
+    a = float(np.float32(0.6))
+    # occluder 2 x 2 at height 3, outside the camera's view but inside the light's path
+    occ = ts.axis_quad(1.0, 3.0, -3.0, -1.0, 3.0)
+    scene = ts.floor_scene(albedo=a, extra=[(occ, 0.5)])
+    res = 24
+    cams = _down_camera(res=res, eye=(0.0, 0.0, 3.5), vfov=90.0)
+    st = sg.RenderSettings(spp=1, depth=1, seed=13)
+    img, fl, _ = oracle.OracleScene(scene).render(cams, st)
+    L = np.array(st.light_dir)
+    cosl = L[2]
+    # footprint of each pixel on the floor (four corners), projected back along the light
+    cam = cams[0]
+    th = math.tan(math.radians(cam.vfov_deg) / 2)
+
+    def floor_pt(px, py):
+        sx = (2 * px / res - 1) * th
+        sy = (1 - 2 * py / res) * th
+        # camera frame: f = -z, r = f x up = (-z) x y = +x, u = r x f = +y
+        d = np.array([sx, sy, -1.0])
+        return np.array(cam.eye) + (cam.eye[2] / -d[2]) * d
+
+    def shadowed(p):
+        q = p + (3.0 / L[2]) * L
+        return 1.0 <= q[0] <= 3.0 and -3.0 <= q[1] <= -1.0
+
+    img = img.reshape(res, res)
+    fl = fl.reshape(res, res)
+    n_sh = 0
+    for y in range(res):
+        for x in range(res):
+            corners = [shadowed(floor_pt(x + i, y + j)) for i in (0, 1) for j in (0, 1)]
+            if fl[y, x]:
+                continue
+            if all(corners):
+                assert img[y, x] == 0.0
+                n_sh += 1
+            elif not any(corners):
+                assert abs(img[y, x] - a * cosl) < 1e-12
+    assert n_sh > 10
+
+
+def test_camera_conventions(ora):
+    """Row 0 is the top of the image and x grows to the right (pinhole camera reading)."""
+    v = np.array([[x, 0.0, z] for z in (-5, 0, 5) for x in (-5, 0, 5)], np.float32)
+    qd = np.array([[0, 1, 4, 3], [1, 2, 5, 4], [3, 4, 7, 6], [4, 5, 8, 7]], np.int32)
+    alb = np.array([0.1, 0.3, 0.5, 0.7], np.float32)
+    f32 = [float(x) for x in alb]
+    scene = sg.single_mesh_scene(v, qd, albedo=alb)
+    res = 16
+    cams = [sg.Camera((0.0, -10.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 40.0, res, res)]
+    st = sg.RenderSettings(spp=1, depth=1, seed=3)
+    img, fl, _ = oracle.OracleScene(scene).render(cams, st)
+    cosl = abs(st.light_dir[1])
+    img = img.reshape(res, res)
+    ok = fl.reshape(res, res) == 0
+    h = res // 2
+    for (ys, xs), a in (((slice(0, h), slice(0, h)), f32[2]), ((slice(0, h), slice(h, res)), f32[3]),
+                        ((slice(h, res), slice(0, h)), f32[0]), ((slice(h, res), slice(h, res)), f32[1])):
+        blk, m = img[ys, xs], ok[ys, xs]
+        np.testing.assert_allclose(blk[m], a * cosl, rtol=1e-12)
+
+
+# --------------------------------------------------------------------- cosine sampling (P8)
+@pytest.mark.parametrize("rot_seed", [None, 4, 17])
+def test_cosine_sampling_form_factor(ora, rot_seed):
+    """Floor under a parallel square 'ceiling': a cosine-distributed bounce hits the
+    ceiling with probability equal to the view factor of the square, so the mean
+    pixel value is a_f cos_L + a_f L_sky (1 - F).  Rotating the whole setup moves
+    the normal off +z and exercises every branch of the orthonormal basis."""
+    a_f, h, half = 0.5, 1.0, 0.4
+    ceil = ts.axis_quad(-half, half, -half, half, h)
+    scene = ts.floor_scene(albedo=a_f, half=50.0, extra=[(ceil, 0.5)])
+    eye, look, up = np.array([0, 0, 0.5]), np.array([0, 0, 0.0]), np.array([0, 1.0, 0])
+    L = np.array([1.0, -1.0, 2.0]) / math.sqrt(6.0)
+    if rot_seed is not None:
+        R = ts.rotation(rot_seed)
+        scene = ts.rotate_scene(scene, R)
+        eye, look, up, L = R @ eye, R @ look, R @ up, R @ L
+    cams = [sg.Camera(tuple(eye), tuple(look), tuple(up), 0.01, 32, 32)]
+    st = sg.RenderSettings(spp=64, depth=2, seed=77)
+    st.light_dir = tuple(L)
+    img, fl, _ = oracle.OracleScene(scene).render(cams, st)
+    F = 4 * ts.form_factor_corner(half, half, h)
+    cosl = 2 / math.sqrt(6.0)
+    escape = (img - a_f * cosl) / (a_f * st.L_sky)
+    n = img.size * st.spp
+    sigma = math.sqrt(F * (1 - F) / n)
+    assert abs(escape.mean() - (1 - F)) < 5 * sigma, (escape.mean(), 1 - F, sigma)
+
+
+# --------------------------------------------------------------------- gradient (P9)
+def _grad_setup(seed=31, res=12, spp=2, depth=3):
+    scene = sg.tiny_scene(seed, n_inst=4, n_protos=2, nq=4, spread=1.0)
+    cams = [sg.Camera((0.0, -8.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 35.0, res, res)]
+    st = sg.RenderSettings(spp=spp, depth=depth, seed=seed)
+    return scene, cams, st
+
+
+def test_gradient_prb_forward_mode_and_fd_agree(ora):
+    scene, cams, st = _grad_setup()
+    o = oracle.OracleScene(scene)
+    rng = np.random.default_rng(2)
+    alb = scene.albedo.astype(np.float64)
+    target_alb = alb + rng.uniform(-0.1, 0.1, alb.shape)
+    o.set_albedo(target_alb)
+    T, _, _ = o.render(cams, st)
+    o.set_albedo(alb)
+    I, _, _ = o.render(cams, st)
+    N = I.size
+    gpix = 2 * (I - T) / N
+    g, _, _ = o.grad(cams, st, gpix)
+    e = rng.normal(size=alb.shape)
+    dI, _ = o.tangent(cams, st, e)
+    fwd = (gpix * dI).sum()
+    prb = (g * e).sum()
+    assert abs(prb - fwd) <= 1e-10 * abs(fwd)
+
+    def loss(a):
+        o.set_albedo(a)
+        Ia, _, _ = o.render(cams, st)
+        return ((Ia - T) ** 2).sum() / N
+
+    hstep = 1e-5
+    fd = (loss(alb + hstep * e) - loss(alb - hstep * e)) / (2 * hstep)
+    assert abs(fd - prb) <= 1e-6 * abs(prb)
+    # single faces with a clearly non-zero gradient
+    for f in np.argsort(-np.abs(g))[:5]:
+        ef = np.zeros_like(alb)
+        ef[f] = 1.0
+        fdf = (loss(alb + hstep * ef) - loss(alb - hstep * ef)) / (2 * hstep)
+        assert abs(fdf - g[f]) <= 1e-6 * abs(g[f])
+    o.set_albedo(alb)
+
+
+def test_gradient_zero_cases(ora):
+    scene, cams, st = _grad_setup(seed=32)
+    o = oracle.OracleScene(scene)
+    I, _, _ = o.render(cams, st)
+    g, _, _ = o.grad(cams, st, 2 * (I - I) / I.size)
+    assert (g == 0).all()
+    # faces no path touches get exactly zero
+    g1, _, _ = o.grad(cams, st, np.ones(I.size))
+    e = np.zeros(g1.shape)
+    touched = g1 != 0
+    assert touched.any() and (~touched).any()
+    e[~touched] = 1.0
+    dI, _ = o.tangent(cams, st, e)
+    assert (dI == 0).all()
+
+
+def test_gradient_floor_closed_form(ora):
+    a = float(np.float32(0.4))
+    scene = ts.floor_scene(albedo=a)
+    st = sg.RenderSettings(spp=2, depth=2, seed=4)
+    cams = _down_camera()
+    n = cams[0].w * cams[0].h
+    g, _, _ = oracle.OracleScene(scene).grad(cams, st, np.full(n, 1.0 / n))
+    cosl = st.light_dir[2]
+    assert abs(g[0] - ((st.E / math.pi) * cosl + st.L_sky)) < 1e-12
