@@ -1,0 +1,225 @@
+/*
+ * rtq — closest-hit tracing of instanced quad meshes and Lambertian path tracing
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The problem this library solves is the one posed by the Moana Island Scene in
+ * "Digesting the Elephant" (Wald et al., TOG 2020): millions of affinely
+ * transformed instances of prototype quad meshes (object-level instancing and
+ * quads rendered directly, Section 5.2), traced by a path tracer whose time goes
+ * mostly into traversal and intersection (Section 6, Table 1), and whose texture
+ * lookup needs the hit's primitive ID and barycentrics (Section 5.3).
+ *
+ * Conventions shared by every call
+ *  - All functions return 0 (RTQ_OK) or a negative RTQ_E_* code.  No C++
+ *    exception crosses this boundary.  rtq_last_error() returns a message for
+ *    the last failure on the calling thread.
+ *  - "device" pointers are HIP device memory on the scene's device; "host"
+ *    pointers are ordinary process memory.  Inputs are read only during the call
+ *    (build) or by the work enqueued on the stream (trace, render); the caller
+ *    keeps them alive until that work completes.
+ *  - Enqueuing calls (trace, render, backward, set_albedo) are asynchronous on
+ *    the given stream and never synchronize the device.  Argument errors are
+ *    reported synchronously, before anything is enqueued.
+ *  - A quad is (v0, v1, v2, v3), counter-clockwise.  It is traced as the two
+ *    triangles A = (v0, v1, v3) and B = (v2, v3, v1), both sides visible.  The hit
+ *    parameterisation is v0 -> (u, v) = (0, 0), v1 -> (1, 0), v2 -> (1, 1),
+ *    v3 -> (0, 1).
+ *  - An instance transform is a row-major 3x4 FP32 matrix [A | t] mapping object
+ *    to world space, w = A v + t.
+ *  - A hit is accepted when tmin < t <= tmax; among accepted hits the one with
+ *    the smallest key (t, instance id, primitive id, half) wins, so the result
+ *    does not depend on traversal order, node format or node width.
+ */
+#ifndef RTQ_H
+#define RTQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ errors */
+#define RTQ_OK 0
+#define RTQ_E_INVALID_ARG (-1)    /* bad pointer, size, index, NaN vertex, ... */
+#define RTQ_E_SINGULAR_XFORM (-2) /* an instance transform cannot be inverted */
+#define RTQ_E_OOM (-3)            /* device or host allocation failed */
+#define RTQ_E_HIP (-4)            /* a HIP runtime call failed */
+#define RTQ_E_LIMIT (-5)          /* a size exceeds an encoding limit of the node formats */
+
+/* Message describing the last error on this thread (never NULL). */
+const char* rtq_last_error(void);
+/* Library version string. */
+const char* rtq_version(void);
+
+/* ------------------------------------------------------------------ scene */
+typedef struct rtq_scene rtq_scene;
+
+/* One prototype quad mesh (host memory). */
+typedef struct {
+  const float* verts;   /* n_verts x 3 FP32, object space */
+  const int32_t* quads; /* n_quads x 4 vertex indices into verts (CCW) */
+  int32_t n_verts;
+  int32_t n_quads;      /* >= 1 */
+  const float* albedo;  /* n_quads per-face albedo, or NULL for 0.5 */
+} rtq_prototype;
+
+/* Object-level instances (host memory): instance i draws prototype proto[i]
+ * through the transform xform[12 i .. 12 i + 11]. */
+typedef struct {
+  int64_t n;
+  const int32_t* proto; /* n prototype indices */
+  const float* xform;   /* n x 12, row-major [A | t], world <- object */
+} rtq_instances;
+
+/* Node formats (bit mask for building, single value for tracing). */
+#define RTQ_NODE_FP32 1 /* 4-wide nodes with FP32 child boxes, 128 B */
+#define RTQ_NODE_Q8 2   /* 4-wide nodes with 8-bit child boxes in an FP32 parent frame, 64 B */
+
+typedef struct {
+  int32_t formats;       /* RTQ_NODE_* mask to build; 0 = both */
+  int32_t leaf_max;      /* quads per bottom-level leaf, 1..8; 0 = 4 */
+  int32_t sah_bins;      /* binned-SAH bins, 4..64; 0 = 16 */
+  int32_t build_threads; /* host threads for the bottom-level builds; 0 = all */
+  int32_t device;        /* HIP device ordinal; -1 = current */
+} rtq_build_opts;
+
+/*
+ * Build the acceleration structures of a scene (Section 5.2: per-object BVHs
+ * under a top-level BVH over instances, quads as primitives).
+ *   protos[0..n_protos), insts: host memory, read during the call only.
+ *   opts: may be NULL for defaults.
+ *   *out: receives a handle owning all device memory of the scene.
+ * Instance inverses and world boxes are computed on the device in FP64; the
+ * BVHs are built on the host (binned SAH) and uploaded.  The call
+ * synchronizes the device it builds on.
+ * Errors: INVALID_ARG (NULL pointer, n_quads < 1, vertex index out of range,
+ * non-finite vertex or transform, proto index out of range), SINGULAR_XFORM,
+ * LIMIT (more than 2^28 quads in one prototype or 2^31 nodes), OOM, HIP.
+ */
+int rtq_scene_build(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
+                    const rtq_build_opts* opts, rtq_scene** out);
+
+/* Free every device allocation of the scene.  NULL-safe.  Synchronizes. */
+void rtq_scene_destroy(rtq_scene* scene);
+
+typedef struct {
+  int64_t n_instances, n_prototypes, n_unique_quads, n_instanced_quads;
+  int64_t tlas_nodes, blas_nodes;
+  int32_t tlas_depth, blas_depth_max; /* 4-wide node levels */
+  int32_t formats;                    /* RTQ_NODE_* built */
+  int64_t device_bytes;               /* all device memory held by the scene */
+  double build_seconds;               /* wall time of rtq_scene_build */
+} rtq_scene_info;
+
+int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);
+
+/*
+ * Replace the per-face albedo (device memory, n = total unique quads, in
+ * prototype order) without rebuilding.  Enqueued on `stream` (a device copy).
+ */
+int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, hipStream_t stream);
+
+/* ------------------------------------------------------------------ tracing */
+/* Rays and hits are structure-of-arrays in device memory, one element per ray. */
+typedef struct {
+  const float *ox, *oy, *oz; /* origin */
+  const float *dx, *dy, *dz; /* direction, need not be normalised; t is in its units */
+  const float *tmin, *tmax;  /* accepted interval tmin < t <= tmax */
+} rtq_rays;
+
+typedef struct {
+  float *t, *u, *v;      /* miss: t = +inf, u = v = 0 */
+  int32_t *inst, *prim;  /* miss: -1, -1; prim is the quad index within its prototype */
+} rtq_hits;
+
+#define RTQ_SCHED_PLAIN 0      /* one ray per lane for its whole traversal */
+#define RTQ_SCHED_PERSISTENT 1 /* resident waves refill finished lanes from a shared ray counter */
+
+typedef struct {
+  int32_t node_format; /* RTQ_NODE_FP32 or RTQ_NODE_Q8; 0 = Q8 if built, else FP32 */
+  int32_t scheduler;   /* RTQ_SCHED_* */
+  int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 24 */
+  int32_t block;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
+  int32_t waves_per_cu;/* persistent scheduler: resident waves per CU; 0 = 16 */
+  int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 16 */
+  uint32_t* visits;    /* optional device n x 4 counters: top nodes, instances entered,
+                          bottom nodes, quads tested (slower kernel variant) */
+} rtq_trace_opts;
+
+/*
+ * Closest hit of n rays (device SoA in, device SoA out), enqueued on `stream`.
+ * opts may be NULL.  Zero-length or NaN directions miss.  n may be 0.
+ */
+int rtq_trace_closest(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits,
+                      const rtq_trace_opts* opts, hipStream_t stream);
+
+/* Occlusion: occluded[i] = 1 if any hit with tmin < t <= tmax exists, else 0. */
+int rtq_trace_occluded(const rtq_scene* scene, const rtq_rays* rays, int64_t n, uint8_t* occluded,
+                       const rtq_trace_opts* opts, hipStream_t stream);
+
+/*
+ * Reference traversal for tests: every instance and every quad of its
+ * prototype is tested with the same leaf code as rtq_trace_closest (no
+ * acceleration structure).  Meant for tiny scenes only.
+ */
+int rtq_trace_brute(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits, hipStream_t stream);
+
+/* ------------------------------------------------------------------ rendering */
+typedef struct {
+  float eye[3], look[3], up[3];
+  float vfov_deg;
+  int32_t w, h;
+  int64_t img_offset; /* first pixel of this view in the packed image buffer */
+} rtq_camera;
+
+typedef struct {
+  uint64_t seed;       /* RNG key (Philox4x32-10 key = (seed_lo, seed_hi ^ frame)) */
+  uint32_t frame;      /* progressive frame index (Section 5.4: 1 spp per frame) */
+  float light_dir[3];  /* unit direction toward the directional light */
+  float E;             /* light irradiance */
+  float L_sky;         /* constant sky radiance */
+  int32_t node_format; /* as rtq_trace_opts */
+  int32_t scheduler;   /* RTQ_SCHED_PLAIN: one kernel per stage and bounce;
+                          RTQ_SCHED_PERSISTENT: one persistent wavefront kernel */
+  int32_t stack_depth, block, waves_per_cu, refill; /* as rtq_trace_opts */
+  uint64_t* counters;  /* optional device [4]: closest rays, shadow rays, incoherent
+                          (bounce >= 1) rays, paths; accumulated (caller zeroes) */
+  uint64_t* view_done; /* optional device [n_cams]: wall-clock tick at which each
+                          view's last path finished (persistent scheduler only) */
+  uint64_t* start_tick;/* optional device [1]: wall-clock tick at kernel start */
+} rtq_render_opts;
+
+/*
+ * Path-trace n_cams pinhole views (Section 5.4, progressive 1 spp frames; here
+ * spp samples per call) with a Lambertian BSDF, next-event estimation toward
+ * one directional light, and a constant sky.  depth counts closest-hit rays per
+ * path including the camera ray.  `images` is a packed FP32 device buffer; view
+ * c occupies [img_offset, img_offset + w h), row 0 at the top.  Each pixel is
+ * the mean over its spp samples, summed in sample order, so every scheduler
+ * produces bit-identical images.  cams: host memory.  Scratch memory is
+ * allocated on first use and kept in the scene handle.
+ * Errors: INVALID_ARG (spp < 1, depth < 1 or > 16, w or h < 1, NULL images).
+ */
+int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
+               const rtq_render_opts* opts, float* images, hipStream_t stream);
+
+/*
+ * Adjoint of rtq_render with respect to per-face albedo, paths held fixed:
+ * grad_albedo[f] += sum over pixels p of grad_images[p] * dI_p / d albedo[f].
+ * Each path is replayed from its RNG counters (same hits as the forward pass).
+ * grad_albedo: device, n_unique_quads floats, zeroed by the caller, accumulated
+ * with atomics (summation order is not fixed).
+ */
+int rtq_render_backward(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp,
+                        int32_t depth, const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,
+                        hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTQ_H */

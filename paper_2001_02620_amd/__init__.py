@@ -1,0 +1,336 @@
+"""Python binding of librtq (the HIP library behind ``include/rtq.h``).
+
+This module only marshals arguments: torch tensors provide device memory and
+the current HIP stream; every step of tracing, shading and differentiation runs
+in the library's kernels.  There is no CPU fallback: importing the binding
+without the built library, or calling it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtq.so")
+
+RTQ_NODE_FP32 = 1
+RTQ_NODE_Q8 = 2
+SCHED_PLAIN = 0
+SCHED_PERSISTENT = 1
+
+ERRORS = {-1: "INVALID_ARG", -2: "SINGULAR_XFORM", -3: "OOM", -4: "HIP", -5: "LIMIT"}
+
+
+class RtqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rtq error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+# ----------------------------------------------------------------------------- C structs
+class _Proto(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("quads", ctypes.c_void_p), ("n_verts", ctypes.c_int32),
+                ("n_quads", ctypes.c_int32), ("albedo", ctypes.c_void_p)]
+
+
+class _Insts(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("proto", ctypes.c_void_p), ("xform", ctypes.c_void_p)]
+
+
+class _BuildOpts(ctypes.Structure):
+    _fields_ = [("formats", ctypes.c_int32), ("leaf_max", ctypes.c_int32), ("sah_bins", ctypes.c_int32),
+                ("build_threads", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_int64), ("n_prototypes", ctypes.c_int64),
+                ("n_unique_quads", ctypes.c_int64), ("n_instanced_quads", ctypes.c_int64),
+                ("tlas_nodes", ctypes.c_int64), ("blas_nodes", ctypes.c_int64), ("tlas_depth", ctypes.c_int32),
+                ("blas_depth_max", ctypes.c_int32), ("formats", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("build_seconds", ctypes.c_double)]
+
+
+class _Rays(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin", "tmax")]
+
+
+class _Hits(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("t", "u", "v", "inst", "prim")]
+
+
+class _TraceOpts(ctypes.Structure):
+    _fields_ = [("node_format", ctypes.c_int32), ("scheduler", ctypes.c_int32), ("stack_depth", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32),
+                ("visits", ctypes.c_void_p)]
+
+
+class _Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("look", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("vfov_deg", ctypes.c_float), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("img_offset", ctypes.c_int64)]
+
+
+class _RenderOpts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("frame", ctypes.c_uint32), ("light_dir", ctypes.c_float * 3),
+                ("E", ctypes.c_float), ("L_sky", ctypes.c_float), ("node_format", ctypes.c_int32),
+                ("scheduler", ctypes.c_int32), ("stack_depth", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32), ("counters", ctypes.c_void_p),
+                ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p)]
+
+
+# ----------------------------------------------------------------------------- loading
+_lib = None
+
+EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destroy", "rtq_scene_get_info",
+           "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
+           "rtq_render_backward"]
+
+
+def load_library():
+    """Load librtq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"librtq.so is not built ({LIB_PATH}); run paper_2001_02620_amd/build.py")
+    # torch carries its own HIP runtime (same SONAME as ROCm's).  Loading torch
+    # first makes librtq bind to that runtime, so both share one device context,
+    # one allocator view and the same streams.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.rtq_last_error.restype = ctypes.c_char_p
+    L.rtq_version.restype = ctypes.c_char_p
+    L.rtq_scene_build.argtypes = [P, ctypes.c_int32, P, P, P]
+    L.rtq_scene_destroy.argtypes = [P]
+    L.rtq_scene_get_info.argtypes = [P, P]
+    L.rtq_scene_set_albedo.argtypes = [P, P, ctypes.c_int64, P]
+    L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
+    L.rtq_render.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    L.rtq_render_backward.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+    for f in EXPORTS:
+        if f not in ("rtq_last_error", "rtq_version", "rtq_scene_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise RtqError(rc, load_library().rtq_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("rtq needs a HIP GPU (torch.cuda is not available)")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ----------------------------------------------------------------------------- scene
+class Scene:
+    """Built acceleration structures of a generator scene (``scenegen.Scene`` arrays)."""
+
+    def __init__(self, s, formats: int = 0, leaf_max: int = 0, sah_bins: int = 0, build_threads: int = 0,
+                 device: int = -1):
+        L = load_library()
+        _torch()
+        self.n_quads = int(s.quads.shape[0])
+        verts = np.ascontiguousarray(s.verts, dtype=np.float32)
+        quads = np.ascontiguousarray(s.quads, dtype=np.int32)
+        albedo = np.ascontiguousarray(s.albedo, dtype=np.float32)
+        P = s.n_protos
+        protos = (_Proto * P)()
+        vb = verts.ctypes.data
+        qb = quads.ctypes.data
+        ab = albedo.ctypes.data
+        for p in range(P):
+            v0, v1 = int(s.proto_vert_off[p]), int(s.proto_vert_off[p + 1])
+            q0, q1 = int(s.proto_quad_off[p]), int(s.proto_quad_off[p + 1])
+            protos[p].verts = vb + 12 * v0
+            protos[p].quads = qb + 16 * q0
+            protos[p].n_verts = v1 - v0
+            protos[p].n_quads = q1 - q0
+            protos[p].albedo = ab + 4 * q0
+        ip = np.ascontiguousarray(s.inst_proto, dtype=np.int32)
+        ix = np.ascontiguousarray(s.inst_xform, dtype=np.float32)
+        insts = _Insts(ip.shape[0], ip.ctypes.data, ix.ctypes.data)
+        opts = _BuildOpts(formats, leaf_max, sah_bins, build_threads, device)
+        h = ctypes.c_void_p()
+        _check(L.rtq_scene_build(ctypes.cast(protos, ctypes.c_void_p), P, ctypes.byref(insts), ctypes.byref(opts),
+                                 ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("scene is closed")
+        return self._h
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(load_library().rtq_scene_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def set_albedo(self, albedo) -> None:
+        assert albedo.dtype.is_floating_point and albedo.numel() == self.n_quads and albedo.is_cuda
+        a = albedo.contiguous().float()
+        _check(load_library().rtq_scene_set_albedo(self.handle, a.data_ptr(), a.numel(), _stream()))
+        self._albedo_keep = a
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().rtq_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Hits:
+    t: object
+    u: object
+    v: object
+    inst: object
+    prim: object
+
+
+def _rays_struct(rays):
+    """rays: CUDA float32 tensor [n, 8] (ox oy oz dx dy dz tmin tmax) -> SoA copy + struct."""
+    torch = _torch()
+    assert rays.is_cuda and rays.dim() == 2 and rays.shape[1] == 8
+    soa = rays.to(torch.float32).t().contiguous()
+    st = _Rays(*[soa[k].data_ptr() for k in range(8)])
+    return soa, st
+
+
+def _trace_opts(node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
+                visits=None):
+    return _TraceOpts(node_format, scheduler, stack_depth, block, waves_per_cu, refill, _ptr(visits))
+
+
+def trace_closest(scene: Scene, rays, **opts) -> Hits:
+    torch = _torch()
+    n = rays.shape[0]
+    soa, st = _rays_struct(rays)
+    dev = rays.device
+    h = Hits(torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev),
+             torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    hs = _Hits(h.t.data_ptr(), h.u.data_ptr(), h.v.data_ptr(), h.inst.data_ptr(), h.prim.data_ptr())
+    o = _trace_opts(**opts)
+    _check(load_library().rtq_trace_closest(scene.handle, ctypes.byref(st), n, ctypes.byref(hs), ctypes.byref(o),
+                                            _stream()))
+    h._keep = (soa, o)
+    return h
+
+
+def trace_occluded(scene: Scene, rays, **opts):
+    torch = _torch()
+    n = rays.shape[0]
+    soa, st = _rays_struct(rays)
+    occ = torch.empty(n, dtype=torch.uint8, device=rays.device)
+    o = _trace_opts(**opts)
+    _check(load_library().rtq_trace_occluded(scene.handle, ctypes.byref(st), n, occ.data_ptr(), ctypes.byref(o),
+                                             _stream()))
+    occ._keep = soa
+    return occ
+
+
+def trace_brute(scene: Scene, rays) -> Hits:
+    torch = _torch()
+    n = rays.shape[0]
+    soa, st = _rays_struct(rays)
+    dev = rays.device
+    h = Hits(torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev),
+             torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    hs = _Hits(h.t.data_ptr(), h.u.data_ptr(), h.v.data_ptr(), h.inst.data_ptr(), h.prim.data_ptr())
+    _check(load_library().rtq_trace_brute(scene.handle, ctypes.byref(st), n, ctypes.byref(hs), _stream()))
+    h._keep = soa
+    return h
+
+
+# ----------------------------------------------------------------------------- rendering
+def camera_structs(cams) -> tuple:
+    arr = (_Camera * len(cams))()
+    off = 0
+    for k, c in enumerate(cams):
+        arr[k].eye[:] = list(c.eye)
+        arr[k].look[:] = list(c.look)
+        arr[k].up[:] = list(c.up)
+        arr[k].vfov_deg = c.vfov_deg
+        arr[k].w = c.w
+        arr[k].h = c.h
+        arr[k].img_offset = off
+        off += c.w * c.h
+    return arr, off
+
+
+def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
+                counters=None, view_done=None, start_tick=None):
+    o = _RenderOpts()
+    o.seed = int(settings.seed)
+    o.frame = int(settings.frame)
+    o.light_dir[:] = [float(x) for x in settings.light_dir]
+    o.E = float(settings.E)
+    o.L_sky = float(settings.L_sky)
+    o.node_format = node_format
+    o.scheduler = scheduler
+    o.stack_depth = stack_depth
+    o.block = block
+    o.waves_per_cu = waves_per_cu
+    o.refill = refill
+    o.counters = _ptr(counters)
+    o.view_done = _ptr(view_done)
+    o.start_tick = _ptr(start_tick)
+    return o
+
+
+def render(scene: Scene, cams, settings, images=None, **opts):
+    """Packed FP32 image of all views (view c at its offset, row 0 at the top)."""
+    torch = _torch()
+    arr, total = camera_structs(cams)
+    if images is None:
+        images = torch.empty(total, device="cuda", dtype=torch.float32)
+    assert images.is_cuda and images.dtype == torch.float32 and images.numel() >= total and images.is_contiguous()
+    o = render_opts(settings, **opts)
+    _check(load_library().rtq_render(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
+                                     settings.depth, ctypes.byref(o), images.data_ptr(), _stream()))
+    return images
+
+
+def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None, **opts):
+    torch = _torch()
+    arr, total = camera_structs(cams)
+    g = grad_images.contiguous().float()
+    assert g.numel() == total and g.is_cuda
+    if grad_albedo is None:
+        grad_albedo = torch.zeros(scene.n_quads, device=g.device, dtype=torch.float32)
+    o = render_opts(settings, **opts)
+    _check(load_library().rtq_render_backward(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams),
+                                              settings.spp, settings.depth, ctypes.byref(o), g.data_ptr(),
+                                              grad_albedo.data_ptr(), _stream()))
+    return grad_albedo
+
+
+def version() -> str:
+    return load_library().rtq_version().decode()

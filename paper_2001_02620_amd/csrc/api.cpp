@@ -1,0 +1,500 @@
+// C-ABI of the library: argument validation, scene construction and ownership,
+// and the dispatch of every enqueued operation onto the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/rtq.h"
+#include "api_internal.h"
+#include "bvh_build.h"
+#include "kernels.h"
+
+using namespace rtq;
+
+namespace {
+thread_local std::string g_err = "no error";
+}
+
+namespace rtq {
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(e == hipErrorOutOfMemory ? RTQ_E_OOM : RTQ_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void* DeviceBuffers::alloc(size_t bytes, hipError_t* err) {
+  void* p = nullptr;
+  *err = hipMalloc(&p, std::max<size_t>(bytes, 16));
+  if (*err != hipSuccess) return nullptr;
+  ptrs.push_back(p);
+  total += bytes;
+  return p;
+}
+
+void DeviceBuffers::release() {
+  for (void* p : ptrs) (void)hipFree(p);
+  ptrs.clear();
+  total = 0;
+}
+
+SceneView scene_view(const rtq_scene* s, int fmt) {
+  SceneView v;
+  v.tlas = reinterpret_cast<const uint4*>(fmt == RTQ_NODE_Q8 ? s->tlas_q8 : s->tlas_f32);
+  v.blas = reinterpret_cast<const uint4*>(fmt == RTQ_NODE_Q8 ? s->blas_q8 : s->blas_f32);
+  v.quads = s->quads;
+  v.quad_prim = s->quad_prim;
+  v.inst = s->inst;
+  v.proto_qbase = s->proto_qbase;
+  v.proto_nq = s->proto_nq;
+  v.albedo = s->albedo;
+  v.pad_rel = s->pad_rel;
+  v.n_inst = (uint32_t)s->n_inst;
+  return v;
+}
+
+int resolve_format(const rtq_scene* s, int32_t req, int* fmt) {
+  int f = req;
+  if (f == 0) f = (s->formats & RTQ_NODE_Q8) ? RTQ_NODE_Q8 : RTQ_NODE_FP32;
+  if (f != RTQ_NODE_FP32 && f != RTQ_NODE_Q8) return set_error(RTQ_E_INVALID_ARG, "unknown node format %d", req);
+  if (!(s->formats & f)) return set_error(RTQ_E_INVALID_ARG, "node format %d was not built", f);
+  *fmt = f;
+  return RTQ_OK;
+}
+
+int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t block, int32_t waves, int32_t refill,
+                   TraceLaunch* tl) {
+  tl->persistent = sched;
+  tl->stack_depth = depth ? depth : 16;
+  tl->block = block ? block : 256;
+  tl->refill = refill ? refill : 16;
+  const int w = waves ? waves : 16;
+  if (sched != RTQ_SCHED_PLAIN && sched != RTQ_SCHED_PERSISTENT)
+    return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", sched);
+  if (tl->stack_depth < 4 || tl->stack_depth > 64)
+    return set_error(RTQ_E_INVALID_ARG, "stack_depth %d outside [4, 64]", tl->stack_depth);
+  if (tl->block < 64 || tl->block > 1024 || tl->block % 64)
+    return set_error(RTQ_E_INVALID_ARG, "block %d must be a multiple of 64 in [64, 1024]", tl->block);
+  if ((size_t)tl->block * tl->stack_depth * 8 > (size_t)s->max_lds)
+    return set_error(RTQ_E_INVALID_ARG, "block %d x stack_depth %d needs %d B of LDS, the device allows %d",
+                     tl->block, tl->stack_depth, tl->block * tl->stack_depth * 8, s->max_lds);
+  if (tl->refill < 1 || tl->refill > 64) return set_error(RTQ_E_INVALID_ARG, "refill %d outside [1, 64]", tl->refill);
+  if (w < 1 || w > 32) return set_error(RTQ_E_INVALID_ARG, "waves_per_cu %d outside [1, 32]", w);
+  const int waves_per_block = tl->block / 64;
+  tl->grid = std::max(1, (s->n_cu * w + waves_per_block - 1) / waves_per_block);
+  const uint32_t slot = s->counter_next.fetch_add(1) % rtq_scene::kCounterSlots;
+  tl->counter = s->counters + slot;
+  return RTQ_OK;
+}
+
+}  // namespace rtq
+
+// =============================================================================
+extern "C" {
+
+const char* rtq_last_error(void) { return g_err.c_str(); }
+
+const char* rtq_version(void) { return "rtq 0.1 (gfx950)"; }
+
+static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
+                      const rtq_build_opts* opts, rtq_scene** out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!out) return set_error(RTQ_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!protos || n_protos < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one prototype");
+  if (!insts || insts->n < 0 || (insts->n > 0 && (!insts->proto || !insts->xform)))
+    return set_error(RTQ_E_INVALID_ARG, "bad instance arrays");
+  rtq_build_opts o{};
+  if (opts) o = *opts;
+  const int formats = o.formats ? o.formats : (RTQ_NODE_FP32 | RTQ_NODE_Q8);
+  if (formats & ~(RTQ_NODE_FP32 | RTQ_NODE_Q8)) return set_error(RTQ_E_INVALID_ARG, "bad formats mask");
+  BuildParams bp;
+  bp.leaf_max = o.leaf_max ? o.leaf_max : 4;
+  bp.bins = o.sah_bins ? o.sah_bins : 16;
+  bp.want_q8 = true;  // the quantized nodes are cheap to derive; keep both topologies identical
+  if (bp.leaf_max < 1 || bp.leaf_max > 8) return set_error(RTQ_E_INVALID_ARG, "leaf_max %d outside [1, 8]", bp.leaf_max);
+  if (bp.bins < 4 || bp.bins > 64) return set_error(RTQ_E_INVALID_ARG, "sah_bins %d outside [4, 64]", bp.bins);
+  const int64_t N = insts->n;
+  if (N > (int64_t)kMaxLeafFirst) return set_error(RTQ_E_LIMIT, "%lld instances exceed 2^28", (long long)N);
+
+  // ---- validate prototypes
+  int64_t total_quads = 0;
+  for (int32_t p = 0; p < n_protos; ++p) {
+    const rtq_prototype& P = protos[p];
+    if (!P.verts || !P.quads || P.n_quads < 1 || P.n_verts < 1)
+      return set_error(RTQ_E_INVALID_ARG, "prototype %d: empty or NULL arrays", p);
+    for (int64_t i = 0; i < 3 * (int64_t)P.n_verts; ++i)
+      if (!std::isfinite(P.verts[i])) return set_error(RTQ_E_INVALID_ARG, "prototype %d: non-finite vertex", p);
+    for (int64_t i = 0; i < 4 * (int64_t)P.n_quads; ++i)
+      if (P.quads[i] < 0 || P.quads[i] >= P.n_verts)
+        return set_error(RTQ_E_INVALID_ARG, "prototype %d: quad index %d out of range", p, P.quads[i]);
+    total_quads += P.n_quads;
+  }
+  if (total_quads > (int64_t)kMaxLeafFirst)
+    return set_error(RTQ_E_LIMIT, "%lld unique quads exceed 2^28", (long long)total_quads);
+  for (int64_t i = 0; i < N; ++i)
+    if (insts->proto[i] < 0 || insts->proto[i] >= n_protos)
+      return set_error(RTQ_E_INVALID_ARG, "instance %lld: prototype %d out of range", (long long)i, insts->proto[i]);
+  for (int64_t i = 0; i < 12 * N; ++i)
+    if (!std::isfinite(insts->xform[i])) return set_error(RTQ_E_INVALID_ARG, "non-finite instance transform");
+
+  int dev = o.device;
+  hipError_t e;
+  if (dev < 0) {
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  }
+  e = hipSetDevice(dev);
+  if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+
+  // ---- bottom level: one BVH per prototype, built on host threads
+  std::vector<Bvh4> blas(n_protos);
+  std::vector<int32_t> order_p(n_protos);
+  for (int32_t p = 0; p < n_protos; ++p) order_p[p] = p;
+  std::sort(order_p.begin(), order_p.end(), [&](int a, int b) { return protos[a].n_quads > protos[b].n_quads; });
+  int nthreads = o.build_threads > 0 ? o.build_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  nthreads = std::min(nthreads, n_protos);
+  std::atomic<int32_t> next{0};
+  auto worker = [&]() {
+    std::vector<Aabb> boxes;
+    for (;;) {
+      const int32_t k = next.fetch_add(1);
+      if (k >= n_protos) break;
+      const int32_t p = order_p[k];
+      const rtq_prototype& P = protos[p];
+      boxes.resize(P.n_quads);
+      for (int32_t q = 0; q < P.n_quads; ++q) {
+        Aabb b;
+        for (int a = 0; a < 3; ++a) {
+          b.lo[a] = std::numeric_limits<float>::infinity();
+          b.hi[a] = -std::numeric_limits<float>::infinity();
+        }
+        for (int c = 0; c < 4; ++c) {
+          const float* v = P.verts + 3 * (int64_t)P.quads[4 * (int64_t)q + c];
+          for (int a = 0; a < 3; ++a) {
+            b.lo[a] = std::min(b.lo[a], v[a]);
+            b.hi[a] = std::max(b.hi[a], v[a]);
+          }
+        }
+        boxes[q] = b;
+      }
+      build_bvh4(boxes.data(), P.n_quads, bp, blas[p]);
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t) th.emplace_back(worker);
+    for (auto& t : th) t.join();
+  }
+
+  rtq_scene* s = new rtq_scene;
+  s->device = dev;
+  s->formats = formats;
+  s->n_protos = n_protos;
+  s->n_inst = N;
+  s->n_quads = total_quads;
+  (void)hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (s->n_cu <= 0) s->n_cu = 256;
+  (void)hipDeviceGetAttribute(&s->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (s->max_lds <= 0) s->max_lds = 65536;
+
+  // ---- concatenate the bottom levels with absolute references
+  std::vector<uint32_t> proto_root(n_protos), face_base(n_protos);
+  std::vector<int32_t> proto_qbase(n_protos), proto_nq(n_protos);
+  std::vector<float> proto_box(6 * (size_t)n_protos);
+  uint64_t node_base = 0, quad_base = 0;
+  int max_blas_depth = 0;
+  for (int32_t p = 0; p < n_protos; ++p) {
+    if (node_base + blas[p].f32.size() >= (uint64_t)kLeafBit) {
+      delete s;
+      return set_error(RTQ_E_LIMIT, "bottom-level node count exceeds 2^31");
+    }
+    if (!relocate(blas[p], (uint32_t)node_base, (uint32_t)quad_base)) {
+      delete s;
+      return set_error(RTQ_E_LIMIT, "reference overflow while relocating prototype %d", p);
+    }
+    proto_root[p] = (uint32_t)node_base;
+    face_base[p] = (uint32_t)quad_base;  // original-order face offset equals the leaf-order quad offset
+    proto_qbase[p] = (int32_t)quad_base;
+    proto_nq[p] = protos[p].n_quads;
+    for (int a = 0; a < 3; ++a) {
+      proto_box[6 * p + a] = blas[p].root_box.lo[a];
+      proto_box[6 * p + 3 + a] = blas[p].root_box.hi[a];
+    }
+    max_blas_depth = std::max(max_blas_depth, blas[p].depth);
+    node_base += blas[p].f32.size();
+    quad_base += protos[p].n_quads;
+  }
+  const size_t n_blas_nodes = node_base;
+  std::vector<float4> quads(3 * (size_t)total_quads);
+  std::vector<int32_t> quad_prim(total_quads);
+  std::vector<float> albedo(total_quads);
+  for (int32_t p = 0; p < n_protos; ++p) {
+    const rtq_prototype& P = protos[p];
+    const size_t qb = proto_qbase[p];
+    for (int32_t j = 0; j < P.n_quads; ++j) {
+      const uint32_t q = blas[p].order[j];
+      const int32_t* iq = P.quads + 4 * (int64_t)q;
+      float f[12];
+      for (int c = 0; c < 4; ++c)
+        for (int a = 0; a < 3; ++a) f[3 * c + a] = P.verts[3 * (int64_t)iq[c] + a];
+      quads[3 * (qb + j) + 0] = make_float4(f[0], f[1], f[2], f[3]);
+      quads[3 * (qb + j) + 1] = make_float4(f[4], f[5], f[6], f[7]);
+      quads[3 * (qb + j) + 2] = make_float4(f[8], f[9], f[10], f[11]);
+      quad_prim[qb + j] = (int32_t)q;
+    }
+    for (int32_t q = 0; q < P.n_quads; ++q) albedo[qb + q] = P.albedo ? P.albedo[q] : 0.5f;
+  }
+
+  auto fail = [&](int code) {
+    s->bufs.release();
+    delete s;
+    return code;
+  };
+#define UPLOAD(dst, src, bytes)                                                   \
+  do {                                                                            \
+    dst = reinterpret_cast<decltype(dst)>(s->bufs.alloc((bytes), &e));            \
+    if (!dst) return fail(hip_error(e, "hipMalloc"));                             \
+    e = hipMemcpy((void*)dst, (src), (bytes), hipMemcpyHostToDevice);             \
+    if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy"));                  \
+  } while (0)
+
+  {
+    std::vector<NodeF32> nf;
+    std::vector<NodeQ8> nq;
+    if (formats & RTQ_NODE_FP32) nf.reserve(n_blas_nodes);
+    if (formats & RTQ_NODE_Q8) nq.reserve(n_blas_nodes);
+    for (int32_t p = 0; p < n_protos; ++p) {
+      if (formats & RTQ_NODE_FP32) nf.insert(nf.end(), blas[p].f32.begin(), blas[p].f32.end());
+      if (formats & RTQ_NODE_Q8) nq.insert(nq.end(), blas[p].q8.begin(), blas[p].q8.end());
+      blas[p] = Bvh4{};  // release host memory early
+    }
+    if (formats & RTQ_NODE_FP32) UPLOAD(s->blas_f32, nf.data(), nf.size() * sizeof(NodeF32));
+    if (formats & RTQ_NODE_Q8) UPLOAD(s->blas_q8, nq.data(), nq.size() * sizeof(NodeQ8));
+  }
+  UPLOAD(s->quads, quads.data(), quads.size() * sizeof(float4));
+  UPLOAD(s->quad_prim, quad_prim.data(), quad_prim.size() * sizeof(int32_t));
+  UPLOAD(s->albedo, albedo.data(), albedo.size() * sizeof(float));
+  UPLOAD(s->proto_qbase, proto_qbase.data(), proto_qbase.size() * sizeof(int32_t));
+  UPLOAD(s->proto_nq, proto_nq.data(), proto_nq.size() * sizeof(int32_t));
+  s->blas_nodes = (int64_t)n_blas_nodes;
+  s->blas_depth = max_blas_depth;
+  quads = std::vector<float4>();
+  quad_prim = std::vector<int32_t>();
+
+  // ---- instances: FP64 inverses and padded world boxes on the device
+  const int64_t Nn = std::max<int64_t>(N, 1);
+  float* d_x = nullptr;
+  int32_t* d_proto = nullptr;
+  uint32_t *d_root = nullptr, *d_face = nullptr;
+  float *d_pbox = nullptr, *d_cond = nullptr, *d_box = nullptr;
+  int32_t* d_status = nullptr;
+  InstRec* d_rec = nullptr;
+  DeviceBuffers tmp;
+  auto tfail = [&](int code) {
+    tmp.release();
+    return fail(code);
+  };
+#define TALLOC(dst, bytes)                                                         \
+  do {                                                                             \
+    dst = reinterpret_cast<decltype(dst)>(tmp.alloc((bytes), &e));                 \
+    if (!dst) return tfail(hip_error(e, "hipMalloc"));                             \
+  } while (0)
+#define TCHECK(expr, what)                                                         \
+  do {                                                                             \
+    e = (expr);                                                                    \
+    if (e != hipSuccess) return tfail(hip_error(e, what));                         \
+  } while (0)
+  TALLOC(d_x, 12 * Nn * sizeof(float));
+  TALLOC(d_proto, Nn * sizeof(int32_t));
+  TALLOC(d_root, n_protos * sizeof(uint32_t));
+  TALLOC(d_face, n_protos * sizeof(uint32_t));
+  TALLOC(d_pbox, 6 * n_protos * sizeof(float));
+  TALLOC(d_cond, Nn * sizeof(float));
+  TALLOC(d_box, 6 * Nn * sizeof(float));
+  TALLOC(d_status, Nn * sizeof(int32_t));
+  TALLOC(d_rec, Nn * sizeof(InstRec));
+  if (N > 0) {
+    TCHECK(hipMemcpy(d_x, insts->xform, 12 * N * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+    TCHECK(hipMemcpy(d_proto, insts->proto, N * sizeof(int32_t), hipMemcpyHostToDevice), "hipMemcpy");
+  }
+  TCHECK(hipMemcpy(d_root, proto_root.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+  TCHECK(hipMemcpy(d_face, face_base.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+  TCHECK(hipMemcpy(d_pbox, proto_box.data(), 6 * n_protos * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  TCHECK(launch_invert_affine(d_x, d_proto, d_root, d_face, N, d_rec, d_cond, d_status, 0), "invert kernel");
+  TCHECK(launch_instance_aabb(d_x, d_proto, d_pbox, d_cond, N, d_box, 0), "aabb kernel");
+  std::vector<int32_t> status(N);
+  std::vector<float> cond(N);
+  std::vector<Aabb> boxes(N);
+  if (N > 0) {
+    TCHECK(hipMemcpy(status.data(), d_status, N * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+    TCHECK(hipMemcpy(cond.data(), d_cond, N * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+    TCHECK(hipMemcpy(boxes.data(), d_box, 6 * N * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
+  }
+  float cond_max = 1.0f;
+  for (int64_t i = 0; i < N; ++i) {
+    if (status[i]) {
+      const int code = set_error(RTQ_E_SINGULAR_XFORM, "instance %lld has a singular transform", (long long)i);
+      return tfail(code);
+    }
+    cond_max = std::max(cond_max, cond[i]);
+  }
+  s->pad_rel = std::ldexp(1.0f, -17) * cond_max;
+
+  // ---- top level over the padded instance boxes (one instance per leaf)
+  Bvh4 tlas;
+  BuildParams tp = bp;
+  tp.leaf_max = 1;
+  if (N > 0) {
+    build_bvh4(boxes.data(), N, tp, tlas);
+  } else {
+    Aabb none;
+    for (int a = 0; a < 3; ++a) none.lo[a] = none.hi[a] = 0.0f;
+    build_bvh4(&none, 1, tp, tlas);  // placeholder root; n_inst = 0 makes every ray miss first
+  }
+  if (!relocate(tlas, 0u, 0u)) return tfail(set_error(RTQ_E_LIMIT, "top-level reference overflow"));
+  if (3 * (tlas.depth + max_blas_depth) + 8 > kStackTotal)
+    return tfail(set_error(RTQ_E_LIMIT, "BVH depth %d + %d exceeds the traversal stack", tlas.depth, max_blas_depth));
+  s->tlas_depth = tlas.depth;
+  s->tlas_nodes = (int64_t)tlas.f32.size();
+  if (formats & RTQ_NODE_FP32) UPLOAD(s->tlas_f32, tlas.f32.data(), tlas.f32.size() * sizeof(NodeF32));
+  if (formats & RTQ_NODE_Q8) UPLOAD(s->tlas_q8, tlas.q8.data(), tlas.q8.size() * sizeof(NodeQ8));
+  s->inst = reinterpret_cast<InstRec*>(s->bufs.alloc(Nn * sizeof(InstRec), &e));
+  if (!s->inst) return tfail(hip_error(e, "hipMalloc"));
+  if (N > 0) {
+    uint32_t* d_order;
+    TALLOC(d_order, N * sizeof(uint32_t));
+    TCHECK(hipMemcpy(d_order, tlas.order.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+    TCHECK(launch_gather_inst(d_rec, d_order, N, s->inst, 0), "gather kernel");
+  }
+  s->counters = reinterpret_cast<unsigned long long*>(
+      s->bufs.alloc(rtq_scene::kCounterSlots * sizeof(unsigned long long), &e));
+  if (!s->counters) return tfail(hip_error(e, "hipMalloc"));
+  TCHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  tmp.release();
+  for (int64_t i = 0; i < N; ++i) s->n_instanced_quads += protos[insts->proto[i]].n_quads;
+  s->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = s;
+  return RTQ_OK;
+#undef UPLOAD
+#undef TALLOC
+#undef TCHECK
+}
+
+int rtq_scene_build(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
+                    const rtq_build_opts* opts, rtq_scene** out) {
+  try {
+    return build_impl(protos, n_protos, insts, opts, out);
+  } catch (const std::bad_alloc&) {
+    return set_error(RTQ_E_OOM, "host allocation failed during build");
+  } catch (...) {
+    return set_error(RTQ_E_HIP, "unexpected failure during build");
+  }
+}
+
+void rtq_scene_destroy(rtq_scene* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  (void)hipDeviceSynchronize();
+  release_render_scratch(s);
+  s->bufs.release();
+  delete s;
+}
+
+int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
+  if (!s || !info) return set_error(RTQ_E_INVALID_ARG, "NULL argument");
+  info->n_instances = s->n_inst;
+  info->n_prototypes = s->n_protos;
+  info->n_unique_quads = s->n_quads;
+  info->n_instanced_quads = s->n_instanced_quads;
+  info->tlas_nodes = s->tlas_nodes;
+  info->blas_nodes = s->blas_nodes;
+  info->tlas_depth = s->tlas_depth;
+  info->blas_depth_max = s->blas_depth;
+  info->formats = s->formats;
+  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total);
+  info->build_seconds = s->build_seconds;
+  return RTQ_OK;
+}
+
+int rtq_scene_set_albedo(rtq_scene* s, const float* albedo_dev, int64_t n, hipStream_t stream) {
+  if (!s || !albedo_dev) return set_error(RTQ_E_INVALID_ARG, "NULL argument");
+  if (n != s->n_quads)
+    return set_error(RTQ_E_INVALID_ARG, "albedo has %lld entries, scene has %lld faces", (long long)n,
+                     (long long)s->n_quads);
+  const hipError_t e = hipMemcpyAsync(s->albedo, albedo_dev, n * sizeof(float), hipMemcpyDeviceToDevice, stream);
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "hipMemcpyAsync");
+}
+
+static int check_rays(const rtq_scene* s, const rtq_rays* r, int64_t n) {
+  if (!s || !r) return set_error(RTQ_E_INVALID_ARG, "NULL scene or rays");
+  if (n < 0) return set_error(RTQ_E_INVALID_ARG, "negative ray count");
+  if (n > 0 && (!r->ox || !r->oy || !r->oz || !r->dx || !r->dy || !r->dz || !r->tmin || !r->tmax))
+    return set_error(RTQ_E_INVALID_ARG, "NULL ray array");
+  return RTQ_OK;
+}
+
+static RaysSoA soa(const rtq_rays* r) { return RaysSoA{r->ox, r->oy, r->oz, r->dx, r->dy, r->dz, r->tmin, r->tmax}; }
+
+static int trace_common(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hits* hits, uint8_t* occ,
+                        const rtq_trace_opts* opts, hipStream_t stream) {
+  int rc = check_rays(s, rays, n);
+  if (rc) return rc;
+  rtq_trace_opts o{};
+  if (opts) o = *opts;
+  int fmt;
+  if ((rc = resolve_format(s, o.node_format, &fmt))) return rc;
+  TraceLaunch tl;
+  if ((rc = resolve_launch(s, o.scheduler, o.stack_depth, o.block, o.waves_per_cu, o.refill, &tl))) return rc;
+  tl.fmt = fmt;
+  if (n == 0) return RTQ_OK;
+  const SceneView sv = scene_view(s, fmt);
+  HitsSoA h{};
+  if (hits) h = HitsSoA{hits->t, hits->u, hits->v, hits->inst, hits->prim};
+  const hipError_t e = launch_trace(sv, soa(rays), n, hits ? &h : nullptr, occ, o.visits, tl, stream);
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "trace launch");
+}
+
+int rtq_trace_closest(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hits* hits, const rtq_trace_opts* opts,
+                      hipStream_t stream) {
+  if (!hits) return set_error(RTQ_E_INVALID_ARG, "NULL hits");
+  if (n > 0 && (!hits->t || !hits->u || !hits->v || !hits->inst || !hits->prim))
+    return set_error(RTQ_E_INVALID_ARG, "NULL hit array");
+  return trace_common(s, rays, n, hits, nullptr, opts, stream);
+}
+
+int rtq_trace_occluded(const rtq_scene* s, const rtq_rays* rays, int64_t n, uint8_t* occluded,
+                       const rtq_trace_opts* opts, hipStream_t stream) {
+  if (n > 0 && !occluded) return set_error(RTQ_E_INVALID_ARG, "NULL occluded array");
+  return trace_common(s, rays, n, nullptr, occluded, opts, stream);
+}
+
+int rtq_trace_brute(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hits* hits, hipStream_t stream) {
+  int rc = check_rays(s, rays, n);
+  if (rc) return rc;
+  if (!hits || (n > 0 && (!hits->t || !hits->u || !hits->v || !hits->inst || !hits->prim)))
+    return set_error(RTQ_E_INVALID_ARG, "NULL hit array");
+  const SceneView sv = scene_view(s, (s->formats & RTQ_NODE_FP32) ? RTQ_NODE_FP32 : RTQ_NODE_Q8);
+  const HitsSoA h{hits->t, hits->u, hits->v, hits->inst, hits->prim};
+  const hipError_t e = launch_trace_brute(sv, soa(rays), n, h, stream);
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "brute launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Library-internal state behind the opaque rtq_scene handle.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/rtq.h"
+#include "kernels.h"
+#include "rtq_layout.h"
+#include "trace_device.h"
+
+namespace rtq {
+
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  size_t total = 0;
+  void* alloc(size_t bytes, hipError_t* err);
+  void release();
+};
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+
+}  // namespace rtq
+
+struct rtq_scene {
+  static constexpr int kCounterSlots = 256;
+  int device = 0;
+  int formats = 0;
+  int n_cu = 256;
+  int max_lds = 65536;  // bytes of LDS one block may use
+  int32_t n_protos = 0;
+  int64_t n_inst = 0, n_quads = 0, n_instanced_quads = 0;
+  int64_t tlas_nodes = 0, blas_nodes = 0;
+  int tlas_depth = 0, blas_depth = 0;
+  double build_seconds = 0.0;
+  float pad_rel = 0.0f;
+  // device data (owned by bufs)
+  void* tlas_f32 = nullptr;
+  void* tlas_q8 = nullptr;
+  void* blas_f32 = nullptr;
+  void* blas_q8 = nullptr;
+  float4* quads = nullptr;
+  int32_t* quad_prim = nullptr;
+  rtq::InstRec* inst = nullptr;
+  int32_t* proto_qbase = nullptr;
+  int32_t* proto_nq = nullptr;
+  float* albedo = nullptr;
+  unsigned long long* counters = nullptr;  // ring of persistent-kernel work counters
+  mutable std::atomic<uint32_t> counter_next{0};
+  rtq::DeviceBuffers bufs;
+  // render scratch, grown on demand (guarded by scratch_mu)
+  std::mutex scratch_mu;
+  rtq::DeviceBuffers scratch;
+  size_t scratch_paths = 0;
+  void* render_state = nullptr;
+};
+
+namespace rtq {
+SceneView scene_view(const rtq_scene* s, int fmt);
+int resolve_format(const rtq_scene* s, int32_t req, int* fmt);
+int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t block, int32_t waves, int32_t refill,
+                   TraceLaunch* tl);
+void release_render_scratch(rtq_scene* s);
+}  // namespace rtq

@@ -1,0 +1,46 @@
+// Host-side BVH construction: binned SAH binary BVH, collapsed to 4-wide nodes,
+// emitted as FP32 nodes and as 8-bit quantized nodes.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "rtq_layout.h"
+
+namespace rtq {
+
+struct Aabb {
+  float lo[3], hi[3];
+};
+
+struct Bvh4 {
+  std::vector<NodeF32> f32;     // local child refs (node index within this BVH)
+  std::vector<NodeQ8> q8;       // same topology, quantized boxes
+  std::vector<uint32_t> order;  // leaf order -> input primitive index
+  Aabb root_box;
+  int depth = 0;                // 4-wide levels
+};
+
+struct BuildParams {
+  int leaf_max = 4;  // primitives per leaf (1..8)
+  int bins = 16;     // SAH bins per axis
+  bool want_f32 = true;
+  bool want_q8 = true;
+};
+
+// Build over n primitive boxes.  Leaves reference [first, first + count) of
+// `order` with local indices; relocate() turns them into absolute references.
+void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out);
+
+// Add node_base to every internal child reference and prim_base to every leaf's
+// first index.  Returns false when an index overflows its encoding.
+bool relocate(Bvh4& b, uint32_t node_base, uint32_t prim_base);
+
+// Quantize one FP32 node into the 8-bit format; every decoded plane is
+// verified to contain the FP32 plane (lower <=, upper >=).
+NodeQ8 quantize_node(const NodeF32& n);
+
+// Decoded quantized plane exactly as the kernels compute it.
+float q8_decode(uint32_t q, int e, float origin);
+
+}  // namespace rtq

@@ -1,0 +1,42 @@
+// Host-callable launchers of the HIP kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rtq_layout.h"
+#include "trace_device.h"
+
+namespace rtq {
+
+hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint32_t* proto_root,
+                                const uint32_t* face_base, int64_t n, InstRec* out, float* cond, int32_t* status,
+                                hipStream_t s);
+hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const float* proto_box, const float* cond,
+                                int64_t n, float* box, hipStream_t s);
+hipError_t launch_gather_inst(const InstRec* in, const uint32_t* order, int64_t n, InstRec* out, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+
+struct RaysSoA {
+  const float *ox, *oy, *oz, *dx, *dy, *dz, *tmin, *tmax;
+};
+struct HitsSoA {
+  float *t, *u, *v;
+  int32_t *inst, *prim;
+};
+
+struct TraceLaunch {
+  int fmt;          // 1 FP32, 2 Q8
+  int persistent;   // 0 plain, 1 persistent with refill
+  int stack_depth;  // LDS entries per lane
+  int block;        // threads per block
+  int grid;         // persistent: blocks
+  int refill;       // persistent: refill threshold (idle lanes)
+  unsigned long long* counter;  // persistent: device ray counter (zeroed by the launcher)
+};
+
+hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA* hits, uint8_t* occ,
+                        uint32_t* visits, const TraceLaunch& tl, hipStream_t s);
+hipError_t launch_trace_brute(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA& hits,
+                              hipStream_t s);
+
+}  // namespace rtq

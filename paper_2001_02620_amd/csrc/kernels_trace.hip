@@ -1,0 +1,176 @@
+// Ray-query kernels: closest hit and occlusion over the two-level quad BVH, in a
+// plain schedule (one ray per lane for its whole traversal) and a persistent
+// schedule (resident waves pull rays from a shared counter and refill lanes
+// whose ray has finished, so the SIMD stays busy on incoherent rays).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "trace_device.h"
+
+namespace rtq {
+
+template <bool ANY>
+__device__ __forceinline__ void store_result(const Lane& L, const SceneView& sc, int64_t i, const HitsSoA& h,
+                                             uint8_t* occ) {
+  const bool hit = L.b_rec != kEmpty;
+  if (ANY) {
+    occ[i] = hit ? 1 : 0;
+    return;
+  }
+  h.t[i] = hit ? L.t_best : kInfF;
+  h.u[i] = hit ? L.b_u : 0.0f;
+  h.v[i] = hit ? L.b_v : 0.0f;
+  h.inst[i] = hit ? (int32_t)L.b_inst : -1;
+  h.prim[i] = hit ? sc.quad_prim[L.b_quad] : -1;
+}
+
+__device__ __forceinline__ bool load_ray(Lane& L, const SceneView& sc, const RaysSoA& r, int64_t i) {
+  L.ex_rec = kEmpty;
+  L.ex_quad = kEmpty;
+  L.ex_half = 0u;
+  return lane_init(L, sc, r.ox[i], r.oy[i], r.oz[i], r.dx[i], r.dy[i], r.dz[i], r.tmin[i], r.tmax[i]);
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void store_visits(uint32_t* visits, int64_t i, const VisitCounters& vc) {
+  if (COUNT) {
+    uint4* v = reinterpret_cast<uint4*>(visits);
+    v[i] = make_uint4(vc.tlas, vc.inst, vc.blas, vc.quads);
+  }
+}
+
+template <int FMT, bool ANY, bool COUNT>
+__global__ void k_trace_plain(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hits, uint8_t* occ, uint32_t* visits,
+                              int depth) {
+  extern __shared__ uint2 lds[];
+  const int lane = threadIdx.x & 63;
+  const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
+  uint2 spill[kStackTotal];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  if (load_ray(L, sc, rays, i))
+    while (!lane_step<FMT, ANY, COUNT>(L, sc, S, spill, vc)) {
+    }
+  store_result<ANY>(L, sc, i, hits, occ);
+  store_visits<COUNT>(visits, i, vc);
+}
+
+template <int FMT, bool ANY, bool COUNT>
+__global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hits, uint8_t* occ,
+                                   uint32_t* visits, int depth, int refill, unsigned long long* counter) {
+  extern __shared__ uint2 lds[];
+  const int lane = threadIdx.x & 63;
+  const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
+  uint2 spill[kStackTotal];
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  bool has = false;
+  bool exhausted = false;  // wave-uniform
+  int64_t idx = -1;
+  for (;;) {
+    const unsigned long long idle = __ballot(!has);
+    const int nidle = __popcll(idle);
+    if (!exhausted && (nidle >= refill || nidle == 64)) {
+      const int leader = __ffsll((long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(counter, (unsigned long long)nidle);
+      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+      base = ((unsigned long long)hi << 32) | lo;
+      if (!has) {
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+        idx = (int64_t)(base + rank);
+        if (idx < n) {
+          vc = VisitCounters{0, 0, 0, 0};
+          if (load_ray(L, sc, rays, idx)) {
+            has = true;
+          } else {
+            store_result<ANY>(L, sc, idx, hits, occ);
+            store_visits<COUNT>(visits, idx, vc);
+          }
+        }
+      }
+      if ((int64_t)(base + nidle) >= n) exhausted = true;
+    }
+    if (!__any(has)) {
+      if (exhausted) break;
+      continue;
+    }
+    if (has) {
+      for (;;) {
+        if (lane_step<FMT, ANY, COUNT>(L, sc, S, spill, vc)) {
+          store_result<ANY>(L, sc, idx, hits, occ);
+          store_visits<COUNT>(visits, idx, vc);
+          has = false;
+          break;
+        }
+        if (!exhausted && __popcll(__ballot(1)) <= 64 - refill) break;
+      }
+    }
+  }
+}
+
+// Reference: every instance, every quad, the same leaf code.
+__global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Lane L;
+  if (load_ray(L, sc, rays, i)) {
+    for (uint32_t r = 0; r < sc.n_inst; ++r) {
+      uint32_t root;
+      enter_instance(L, sc.inst, r, &root);
+      const uint32_t p = sc.inst[r].proto;
+      leaf_quads<false, false>(L, sc, (uint32_t)sc.proto_qbase[p], (uint32_t)sc.proto_nq[p], nullptr);
+    }
+  }
+  store_result<false>(L, sc, i, hits, nullptr);
+}
+
+template <int FMT, bool ANY, bool COUNT>
+static hipError_t launch3(const SceneView& sc, const RaysSoA& r, int64_t n, const HitsSoA& h, uint8_t* occ,
+                          uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
+  const size_t lds = (size_t)tl.block * tl.stack_depth * sizeof(uint2);
+  if (tl.persistent) {
+    hipError_t e = launch_zero_u64(tl.counter, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_trace_persistent<FMT, ANY, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, r, n, h,
+                       occ, visits, tl.stack_depth, tl.refill, tl.counter);
+  } else {
+    const unsigned g = (unsigned)((n + tl.block - 1) / tl.block);
+    hipLaunchKernelGGL((k_trace_plain<FMT, ANY, COUNT>), dim3(g), dim3(tl.block), lds, s, sc, r, n, h, occ, visits,
+                       tl.stack_depth);
+  }
+  return hipGetLastError();
+}
+
+template <int FMT>
+static hipError_t launch2(const SceneView& sc, const RaysSoA& r, int64_t n, const HitsSoA* h, uint8_t* occ,
+                          uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
+  const HitsSoA hh = h ? *h : HitsSoA{};
+  if (occ) {
+    return visits ? launch3<FMT, true, true>(sc, r, n, hh, occ, visits, tl, s)
+                  : launch3<FMT, true, false>(sc, r, n, hh, occ, visits, tl, s);
+  }
+  return visits ? launch3<FMT, false, true>(sc, r, n, hh, occ, visits, tl, s)
+                : launch3<FMT, false, false>(sc, r, n, hh, occ, visits, tl, s);
+}
+
+hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA* hits, uint8_t* occ,
+                        uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  return tl.fmt == 2 ? launch2<2>(sc, rays, n, hits, occ, visits, tl, s)
+                     : launch2<1>(sc, rays, n, hits, occ, visits, tl, s);
+}
+
+hipError_t launch_trace_brute(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA& hits,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trace_brute, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, sc, rays, n, hits);
+  return hipGetLastError();
+}
+
+}  // namespace rtq

@@ -1,0 +1,77 @@
+// Device memory layout of a built scene, shared by the host builder and the kernels.
+//
+// Acceleration structure (Section 5.2 of the paper: one BVH per prototype object
+// under a top-level BVH over the instances; quads are the primitives):
+//   * top level (TLAS): 4-wide nodes over instance world boxes; a leaf holds one
+//     instance record index.
+//   * bottom level (BLAS): 4-wide nodes per prototype over its quads; a leaf
+//     holds 1..8 consecutive quads of the global leaf-ordered quad array.
+// Child references are 32-bit offsets from one 64-bit array base per level (the
+// GPU analogue of the 32-bit addressing from a uniform base that Section 5.5
+// relies on: no object in these scenes needs 64-bit offsets).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtq {
+
+// ---- child references ------------------------------------------------------
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // unused child slot
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kMaxLeafFirst = (1u << 28) - 1;  // 28-bit first index in a leaf
+
+__host__ __device__ inline uint32_t make_leaf(uint32_t first, uint32_t count) {
+  return kLeafBit | (first << 3) | (count - 1u);
+}
+__host__ __device__ inline bool ref_is_leaf(uint32_t r) { return (r & kLeafBit) != 0u; }
+__host__ __device__ inline uint32_t leaf_first(uint32_t r) { return (r & 0x7FFFFFFFu) >> 3; }
+__host__ __device__ inline uint32_t leaf_count(uint32_t r) { return (r & 7u) + 1u; }
+
+// ---- FP32 4-wide node: 128 B, one cache line -------------------------------
+// Planes are stored structure-of-arrays inside the node so that one 16-byte load
+// fetches the same plane of all four children.
+struct alignas(16) NodeF32 {
+  float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
+  uint32_t child[4];
+  uint32_t pad[4];
+};
+static_assert(sizeof(NodeF32) == 128, "NodeF32 is 128 B");
+
+// ---- quantized 4-wide node: 64 B ---------------------------------------------
+// Child box planes are 8-bit integers q in a per-node FP32 frame:
+//   plane = fmaf(q, 2^e_axis, origin_axis)
+// The product q 2^e is exact, so each decoded plane is one correctly rounded
+// FP32 value; the builder picks q (floor for lower, ceil for upper planes, then
+// verified with this very expression) so every decoded box contains the exact
+// FP32 child box.  An empty slot has lo = 255, hi = 0 and child = kEmpty.
+struct alignas(16) NodeQ8 {
+  float ox, oy, oz;
+  uint32_t exps;  // byte k: int8 exponent of axis k (k = 0..2)
+  uint32_t lo_x, hi_x, lo_y, hi_y;  // 4 x u8 each (child c in byte c)
+  uint32_t lo_z, hi_z;
+  uint32_t child[4];
+  uint32_t pad[2];
+};
+static_assert(sizeof(NodeQ8) == 64, "NodeQ8 is 64 B");
+
+// ---- instance record: 64 B ------------------------------------------------------
+// r0..r2: rows of the inverse linear part A^-1 (xyz) and the translation t (w), so
+// that the object-space ray is o' = A^-1 (o - t), d' = A^-1 d (t stays in the
+// same units in both spaces).  The inverse is computed in FP64 at build.
+struct alignas(16) InstRec {
+  float r0[4], r1[4], r2[4];
+  uint32_t blas_root;  // absolute index of the prototype's root node
+  uint32_t inst_id;    // caller's instance index
+  uint32_t face_base;  // first unique face of the prototype (albedo index base)
+  uint32_t proto;      // prototype index
+};
+static_assert(sizeof(InstRec) == 64, "InstRec is 64 B");
+
+// Quads are stored in leaf order as 3 x float4:
+//   (v0.x v0.y v0.z v1.x) (v1.y v1.z v2.x v2.y) (v2.z v3.x v3.y v3.z)
+constexpr int kQuadFloat4 = 3;
+
+// Worst-case traversal stack: every 4-wide level pushes at most 3 entries.
+constexpr int kStackTotal = 192;
+
+}  // namespace rtq
