@@ -60,8 +60,8 @@ def lib():
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         L.orc_philox.argtypes = [P, P, P]
-        L.orc_trace.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
-        L.orc_trace_d.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P]
+        L.orc_trace.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P]
+        L.orc_trace_d.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.orc_render.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, P, P]
         L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P]
         _lib = L
@@ -99,6 +99,7 @@ class Hits:
     flags: np.ndarray
     cand: np.ndarray
     ncand: np.ndarray
+    scale: np.ndarray  # position scale of each answer (max of 1, |o|, |p|, hit-quad extent from o)
 
 
 class OracleScene:
@@ -147,11 +148,11 @@ class OracleScene:
         rr = None if r0 is None else np.ascontiguousarray(r0, dtype=np.float64)
         out = Hits(t=np.zeros(n), inst=np.zeros(n, np.int32), prim=np.zeros(n, np.int32),
                    half=np.zeros(n, np.int32), u=np.zeros(n), v=np.zeros(n), flags=np.zeros(n, np.uint32),
-                   cand=np.zeros((n, 8), np.int32), ncand=np.zeros(n, np.int32))
+                   cand=np.zeros((n, 8), np.int32), ncand=np.zeros(n, np.int32), scale=np.zeros(n))
         fn = lib().orc_trace_d if f64 else lib().orc_trace
         fn(self.h, n, _p(rays), _p(ex), _p(rr), 0 if brute else 1, 1 if any_hit else 0, _p(out.t),
                         _p(out.inst), _p(out.prim), _p(out.half), _p(out.u), _p(out.v), _p(out.flags),
-                        _p(out.cand), _p(out.ncand))
+                        _p(out.cand), _p(out.ncand), _p(out.scale))
         return out
 
     @staticmethod

@@ -283,6 +283,32 @@ double seg_dist(V3 o, V3 d, double s0, double s1, V3 a, V3 b, V3* q_out) {
   return norm(p - q);
 }
 
+// Distance from point p to triangle (a, b, c): the closest point is found by
+// classifying p against the Voronoi regions of the vertices, edges and face
+// (Ericson, "Real-Time Collision Detection", Section 5.1.5).
+double point_tri_dist(V3 p, V3 a, V3 b, V3 c) {
+  const V3 ab = b - a, ac = c - a, ap = p - a;
+  const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= 0 && d2 <= 0) return norm(p - a);
+  const V3 bp = p - b;
+  const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0 && d4 <= d3) return norm(p - b);
+  const double vc = d1 * d4 - d3 * d2;
+  if (vc <= 0 && d1 >= 0 && d3 <= 0) return norm(p - (a + (d1 / (d1 - d3)) * ab));
+  const V3 cp = p - c;
+  const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0 && d5 <= d6) return norm(p - c);
+  const double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0 && d2 >= 0 && d6 <= 0) return norm(p - (a + (d2 / (d2 - d6)) * ac));
+  const double va = d3 * d6 - d5 * d4;
+  if (va <= 0 && (d4 - d3) >= 0 && (d5 - d6) >= 0)
+    return norm(p - (b + ((d4 - d3) / ((d4 - d3) + (d5 - d6))) * (c - b)));
+  const double den = va + vb + vc;
+  if (!(den > 0)) return std::min(norm(p - a), std::min(norm(p - b), norm(p - c)));  // degenerate
+  const double v = vb / den, w = vc / den;
+  return norm(p - (a + v * ab + w * ac));
+}
+
 // ---------------------------------------------------------------- traversal
 inline bool slab(const Ray& r, const Box& b, double pad, double t_hi) {
   double tn = r.tmin, tf = t_hi;
@@ -359,7 +385,7 @@ struct TraceOut {
   int32_t ncand = 0;
   int32_t cand[8];  // up to 4 (inst, prim) pairs hit within the tie window
   double cos_abs = 0;  // |n.d| / |d| at the best hit
-  double S = 1;
+  double S = 1;        // position scale of the answer: max(1, |o|, |p|, extent of the hit quad seen from o)
 };
 
 // Closest hit by key, then the flag pass over the same candidate triangles.
@@ -388,33 +414,50 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   const bool hit = best.inst >= 0;
   const V3 p = hit ? r.o + best.t * r.d : r.o;
   const double Sv = std::max(1.0, std::max(maxabs(r.o), maxabs(p)));
-  out.S = Sv;
+  // FP32 answers carry errors proportional to the coordinates they are computed
+  // from: the ray origin, the hit point, and the vertices of the tested quad
+  // relative to the origin (a large quad seen from close by).  Every threshold
+  // below is 1e-6 times the largest of these.
+  auto extent = [&](const V3 w[4]) {
+    double e = 0.0;
+    for (int k = 0; k < 4; ++k) e = std::max(e, maxabs(w[k] - r.o));
+    return e;
+  };
+  double S_best = Sv;
   // pass 2: flags
   double t_end = std::isfinite(r.tmax) ? r.tmax + 1e-5 * r.tmax + 1e-6 * Sv / dn : kInf, win = 0;
   if (hit) {
-    win = 1e-5 * best.t + 1e-6 * Sv / dn;
-    t_end = best.t + win;
-    if (best.t * dn < 1e-6 * Sv + r0) out.flags |= F_NEAR_ORIGIN;
     V3 w[4];
     quad_world(S, best.inst, S.qo[S.iproto[best.inst]] + best.prim, w);
+    S_best = std::max(Sv, extent(w));
+    win = 1e-5 * best.t + 1e-6 * S_best / dn;
+    t_end = best.t + win;
+    if (best.t * dn < 1e-6 * S_best + r0) out.flags |= F_NEAR_ORIGIN;
     const V3 n = best.half == 0 ? cross(w[1] - w[0], w[3] - w[0]) : cross(w[3] - w[2], w[1] - w[2]);
     out.cos_abs = std::fabs(dot(n, r.d)) / (norm(n) * dn);
-    if (16.0 * std::ldexp(1.0, -24) * Sv > 1e-5 * best.t * dn * out.cos_abs) out.flags |= F_T_ILLCOND;
+    if (16.0 * std::ldexp(1.0, -24) * S_best > 1e-5 * best.t * dn * out.cos_abs) out.flags |= F_T_ILLCOND;
   }
+  out.S = S_best;
   const double s_hi = hit ? std::max(Sv, maxabs(r.o) + t_end * maxabs(r.d)) : std::max(Sv, S.scene_mag);
-  const double g_cull = 1e-6 * s_hi * 1.01 + r0;
+  const double g_cull = 1e-6 * 1.01 * (s_hi + maxabs(r.o) + S.scene_mag) + r0;
+  const V3 o0 = r.o + r.tmin * r.d;
   double t_lim = t_end;
   visit(S, r, mode, g_cull, t_lim, [&](int64_t inst, int64_t qg) {
     V3 w[4];
     quad_world(S, inst, qg, w);
     const int32_t prim = (int32_t)(qg - S.qo[S.iproto[inst]]);
+    const double Sq = std::max(Sv, extent(w));
     TriHit h[2];
     Key k[2];
     quad_hits(r, w, t_end, h, k, (int32_t)inst, prim);
     const bool same = hit && inst == best.inst && prim == best.prim;
     for (int s = 0; s < 2; ++s) {
+      const bool excluded = (int32_t)inst == ex.inst && prim == ex.prim && s == ex.half;
+      if (excluded) continue;
+      // a triangle next to the ray origin may be hit at t ~ 0 in FP32
+      const double dorg = s == 0 ? point_tri_dist(o0, w[0], w[1], w[3]) : point_tri_dist(o0, w[2], w[3], w[1]);
+      if (dorg < 1e-6 * Sq + r0) out.flags |= F_NEAR_ORIGIN;
       if (!h[s].hit) continue;
-      if (k[s].inst == ex.inst && k[s].prim == ex.prim && k[s].half == ex.half) continue;
       if (!same) {
         out.flags |= F_NEAR_TIE;
         bool dup = false;
@@ -433,13 +476,12 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
     for (int e = 0; e < 4; ++e) {
       V3 q;
       const double dist = seg_dist(r.o, r.d, r.tmin, t_end, w[E[e][0]], w[E[e][1]], &q);
-      const double g = 1e-6 * std::max(Sv, maxabs(q)) + r0;
-      if (dist < g) out.flags |= F_GRAZE;
+      if (dist < 1e-6 * std::max(Sq, maxabs(q)) + r0) out.flags |= F_GRAZE;
     }
     if (same) {
       V3 q;
       const double dist = seg_dist(r.o, r.d, r.tmin, t_end, w[1], w[3], &q);
-      if (dist < 1e-6 * std::max(Sv, maxabs(q)) + r0) out.flags |= F_DIAG;
+      if (dist < 1e-6 * std::max(Sq, maxabs(q)) + r0) out.flags |= F_DIAG;
     }
   });
   if (any_hit) out.flags &= ~(uint32_t)(F_NEAR_TIE | F_DIAG | F_T_ILLCOND);
@@ -708,13 +750,14 @@ int orc_scene_set_albedo(void* s, const double* albedo) {
 
 // rays: n x 8 (ox oy oz dx dy dz tmin tmax), FP32 (read as exact doubles) or FP64.
 // excl: n x 3 (inst, prim, half) or NULL; r0: per-ray origin uncertainty or NULL.
-// cand: n x 8 int32 ((inst, prim) x 4) or NULL.
+// cand: n x 8 int32 ((inst, prim) x 4) or NULL; scale: per-ray position scale of
+// the answer (max of 1, |o|, |p| and the hit quad's extent from o) or NULL.
 }  // extern "C"
 
 template <class T>
 static void trace_many(void* s, int64_t n, const T* rays, const int32_t* excl, const double* r0, int32_t mode,
                        int32_t any_hit, double* t, int32_t* inst, int32_t* prim, int32_t* half, double* u,
-                       double* v, uint32_t* flags, int32_t* cand, int32_t* ncand) {
+                       double* v, uint32_t* flags, int32_t* cand, int32_t* ncand, double* scale) {
   const Scene& S = *static_cast<Scene*>(s);
   parallel_for(n, threads(), [&](int64_t i, int) {
     const T* R = rays + 8 * i;
@@ -734,6 +777,7 @@ static void trace_many(void* s, int64_t n, const T* rays, const int32_t* excl, c
       for (int c = 0; c < 8; ++c) cand[8 * i + c] = c < 2 * o.ncand ? o.cand[c] : -1;
     }
     if (ncand) ncand[i] = o.ncand;
+    if (scale) scale[i] = o.S;
   });
 }
 
@@ -741,14 +785,14 @@ extern "C" {
 
 void orc_trace(void* s, int64_t n, const float* rays, const int32_t* excl, const double* r0, int32_t mode,
                int32_t any_hit, double* t, int32_t* inst, int32_t* prim, int32_t* half, double* u, double* v,
-               uint32_t* flags, int32_t* cand, int32_t* ncand) {
-  trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand);
+               uint32_t* flags, int32_t* cand, int32_t* ncand, double* scale) {
+  trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand, scale);
 }
 
 void orc_trace_d(void* s, int64_t n, const double* rays, const int32_t* excl, const double* r0, int32_t mode,
                  int32_t any_hit, double* t, int32_t* inst, int32_t* prim, int32_t* half, double* u, double* v,
-                 uint32_t* flags, int32_t* cand, int32_t* ncand) {
-  trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand);
+                 uint32_t* flags, int32_t* cand, int32_t* ncand, double* scale) {
+  trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand, scale);
 }
 
 // Image (or listed pixels) of n_cams pinhole cameras.  cam_f: n x 10 (eye, look,
@@ -825,10 +869,12 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
     resolve_pixel(cams, g, &view, &p);
     uint32_t fl = 0;
     double dsum = 0.0;
+    std::vector<int64_t> faces;  // every face on the pixel's paths
     for (int32_t smp = 0; smp < P.spp; ++smp) {
       PathRec rec;
       trace_path(S, P, cams[view], view, p, smp, mode, rec);
       fl |= rec.flags;
+      for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].face);
       if (grad_mode == 0) {
         // D_k = beta_k a_k c_k; S_k = sum_{j>=k} D_j + M.  Accumulate S_k / a_k.
         std::vector<double> beta(rec.nv + 1, 1.0);
@@ -856,9 +902,11 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
         }
         dsum += dL;
       }
-      if (face_tainted && rec.flags)
-        for (int k = 0; k < rec.nv; ++k) taint[tid][rec.v[k].face] = 1;
     }
+    // a flagged pixel's value may differ on the GPU, and it weights the gradient of
+    // every face on every path through the pixel: all of those faces are tainted
+    if (face_tainted && fl)
+      for (int64_t f : faces) taint[tid][f] = 1;
     if (grad_mode == 1) dI[i] = dsum / P.spp;
     if (pflags) pflags[i] = (uint8_t)(fl != 0);
   });

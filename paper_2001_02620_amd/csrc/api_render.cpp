@@ -1,20 +1,248 @@
-// Rendering entry points (placeholder until the render kernels land).
+// Rendering entry points of the C-ABI: camera set-up, scratch management and the
+// dispatch to the plain (multi-kernel) or persistent (single-launch) scheduler,
+// and the path-replay adjoint.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "../../include/rtq.h"
 #include "api_internal.h"
+#include "render_kernels.h"
+
+using namespace rtq;
+
+namespace {
+
+struct RenderScratch {
+  DeviceBuffers bufs;
+  int64_t paths_cap = 0;
+  bool plain = false;
+  int32_t cams_cap = 0;
+  CamDev* cams = nullptr;
+  float* slots = nullptr;
+  PlainBuffers pb{};
+};
+
+RenderScratch* scratch_of(rtq_scene* s) {
+  if (!s->render_state) s->render_state = new RenderScratch;
+  return static_cast<RenderScratch*>(s->render_state);
+}
+
+// Grow the scene's render scratch to hold n_paths paths (and the plain
+// scheduler's queues when asked).  Existing contents are not preserved.
+int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
+  RenderScratch* r = scratch_of(s);
+  if (r->paths_cap >= n_paths && r->cams_cap >= n_cams && (r->plain || !plain)) return RTQ_OK;
+  (void)hipDeviceSynchronize();
+  r->bufs.release();
+  const int64_t P = std::max<int64_t>(std::max(n_paths, r->paths_cap), 64);
+  const int32_t C = std::max(std::max(n_cams, r->cams_cap), 64);
+  const bool want_plain = plain || r->plain;
+  hipError_t e;
+  auto A = [&](size_t bytes) { return r->bufs.alloc(bytes, &e); };
+#define RALLOC(dst, bytes)                                              \
+  do {                                                                  \
+    dst = reinterpret_cast<decltype(dst)>(A(bytes));                    \
+    if (!dst) {                                                         \
+      r->bufs.release();                                                \
+      r->paths_cap = 0;                                                 \
+      r->cams_cap = 0;                                                  \
+      r->plain = false;                                                 \
+      return hip_error(e, "render scratch allocation");                 \
+    }                                                                   \
+  } while (0)
+  RALLOC(r->cams, C * sizeof(CamDev));
+  RALLOC(r->slots, P * sizeof(float));
+  if (want_plain) {
+    for (int k = 0; k < 2; ++k) {
+      ExtQueue& q = r->pb.q[k];
+      RALLOC(q.ox, P * 4);
+      RALLOC(q.oy, P * 4);
+      RALLOC(q.oz, P * 4);
+      RALLOC(q.dx, P * 4);
+      RALLOC(q.dy, P * 4);
+      RALLOC(q.dz, P * 4);
+      RALLOC(q.pid, P * 4);
+      RALLOC(q.beta, P * 4);
+      RALLOC(q.ex_rec, P * 4);
+      RALLOC(q.ex_qh, P * 4);
+    }
+    ShadowQueue& sq = r->pb.sq;
+    RALLOC(sq.ox, P * 4);
+    RALLOC(sq.oy, P * 4);
+    RALLOC(sq.oz, P * 4);
+    RALLOC(sq.pid, P * 4);
+    RALLOC(sq.contrib, P * 4);
+    RALLOC(sq.ex_rec, P * 4);
+    RALLOC(sq.ex_qh, P * 4);
+    RALLOC(r->pb.hits.t, P * 4);
+    RALLOC(r->pb.hits.rec, P * 4);
+    RALLOC(r->pb.hits.qh, P * 4);
+    RALLOC(r->pb.occ, P);
+    RALLOC(r->pb.counts, (2 * kMaxDepth + 2) * sizeof(uint32_t));
+  }
+#undef RALLOC
+  r->paths_cap = P;
+  r->cams_cap = C;
+  r->plain = want_plain;
+  s->scratch.total = r->bufs.total;
+  return RTQ_OK;
+}
+
+struct Prepared {
+  RenderParams rp;
+  int64_t n_pixels;
+  int fmt;
+  TraceLaunch tl;
+};
+
+int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
+            const rtq_render_opts* opts, bool plain_buffers, hipStream_t stream, Prepared* out) {
+  rtq_scene* s = const_cast<rtq_scene*>(cs);
+  if (!s || !cams || !opts) return set_error(RTQ_E_INVALID_ARG, "NULL scene, cameras or options");
+  if (n_cams < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one camera");
+  if (spp < 1) return set_error(RTQ_E_INVALID_ARG, "spp %d < 1", spp);
+  if (depth < 1 || depth > kMaxDepth) return set_error(RTQ_E_INVALID_ARG, "depth %d outside [1, %d]", depth, kMaxDepth);
+  if (opts->scheduler != RTQ_SCHED_PLAIN && opts->scheduler != RTQ_SCHED_PERSISTENT)
+    return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", opts->scheduler);
+  int rc = resolve_format(s, opts->node_format, &out->fmt);
+  if (rc) return rc;
+  rc = resolve_launch(s, opts->scheduler, opts->stack_depth, opts->block, opts->waves_per_cu, opts->refill, &out->tl);
+  if (rc) return rc;
+  out->tl.fmt = out->fmt;
+  const float L[3] = {opts->light_dir[0], opts->light_dir[1], opts->light_dir[2]};
+  if (!std::isfinite(L[0]) || !std::isfinite(L[1]) || !std::isfinite(L[2]) || !std::isfinite(opts->E) ||
+      !std::isfinite(opts->L_sky))
+    return set_error(RTQ_E_INVALID_ARG, "non-finite light parameters");
+  std::vector<CamDev> cd(n_cams);
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  int64_t path_base = 0, n_pixels = 0;
+  for (int32_t c = 0; c < n_cams; ++c) {
+    const rtq_camera& C = cams[c];
+    if (C.w < 1 || C.h < 1 || C.img_offset < 0)
+      return set_error(RTQ_E_INVALID_ARG, "camera %d: bad resolution or offset", c);
+    const double ex = C.eye[0], ey = C.eye[1], ez = C.eye[2];
+    double f[3] = {C.look[0] - ex, C.look[1] - ey, C.look[2] - ez};
+    const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const double up[3] = {C.up[0], C.up[1], C.up[2]};
+    double r[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    const double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(fn > 0.0) || !(rn > 0.0) || !(C.vfov_deg > 0.0f && C.vfov_deg < 180.0f))
+      return set_error(RTQ_E_INVALID_ARG, "camera %d: degenerate view (eye == look, up parallel, or bad fov)", c);
+    for (int k = 0; k < 3; ++k) {
+      f[k] /= fn;
+    }
+    // r = normalize(f x up) computed from the normalised f
+    double rr[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    const double rrn = std::sqrt(rr[0] * rr[0] + rr[1] * rr[1] + rr[2] * rr[2]);
+    for (int k = 0; k < 3; ++k) rr[k] /= rrn;
+    const double u[3] = {rr[1] * f[2] - rr[2] * f[1], rr[2] * f[0] - rr[0] * f[2], rr[0] * f[1] - rr[1] * f[0]};
+    CamDev& d = cd[c];
+    for (int k = 0; k < 3; ++k) {
+      d.eye[k] = C.eye[k];
+      d.f[k] = (float)f[k];
+      d.r[k] = (float)rr[k];
+      d.u[k] = (float)u[k];
+    }
+    d.tan_half = (float)std::tan(0.5 * (double)C.vfov_deg * 3.14159265358979323846 / 180.0);
+    d.aspect = (float)((double)C.w / (double)C.h);
+    d.w = C.w;
+    d.h = C.h;
+    d.img_offset = C.img_offset;
+    d.path_base = path_base;
+    const int64_t wh = (int64_t)C.w * C.h;
+    if (wh > (int64_t)0xFFFFFFFFll) return set_error(RTQ_E_LIMIT, "camera %d has more than 2^32 pixels", c);
+    path_base += wh * spp;
+    n_pixels = std::max(n_pixels, C.img_offset + wh);
+    ranges.push_back({C.img_offset, C.img_offset + wh});
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t k = 1; k < ranges.size(); ++k)
+    if (ranges[k].first < ranges[k - 1].second) return set_error(RTQ_E_INVALID_ARG, "camera image ranges overlap");
+  // the accumulation kernel walks views by increasing image offset
+  for (int32_t c = 1; c < n_cams; ++c)
+    if (cd[c].img_offset < cd[c - 1].img_offset)
+      return set_error(RTQ_E_INVALID_ARG, "camera image offsets must increase with the camera index");
+  {
+    std::lock_guard<std::mutex> lock(s->scratch_mu);
+    rc = ensure_scratch(s, path_base, n_cams, plain_buffers);
+    if (rc) return rc;
+  }
+  RenderScratch* sc = scratch_of(s);
+  const hipError_t e =
+      hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_error(e, "camera upload");
+  RenderParams& rp = out->rp;
+  rp.cams = sc->cams;
+  rp.n_cams = n_cams;
+  rp.spp = spp;
+  rp.depth = depth;
+  rp.key0 = (uint32_t)(opts->seed & 0xFFFFFFFFull);
+  rp.key1 = (uint32_t)(opts->seed >> 32) ^ opts->frame;
+  rp.lx = L[0];
+  rp.ly = L[1];
+  rp.lz = L[2];
+  rp.e_over_pi = (float)((double)opts->E / 3.14159265358979323846);
+  rp.L_sky = opts->L_sky;
+  rp.n_paths = path_base;
+  rp.slots = sc->slots;
+  out->n_pixels = n_pixels;
+  return RTQ_OK;
+}
+
+}  // namespace
 
 namespace rtq {
-void release_render_scratch(rtq_scene* s) { s->scratch.release(); }
+void release_render_scratch(rtq_scene* s) {
+  if (s->render_state) {
+    RenderScratch* r = static_cast<RenderScratch*>(s->render_state);
+    r->bufs.release();
+    delete r;
+    s->render_state = nullptr;
+  }
+  s->scratch.release();
+}
 }  // namespace rtq
 
 extern "C" {
-int rtq_render(const rtq_scene*, const rtq_camera*, int32_t, int32_t, int32_t, const rtq_render_opts*, float*,
-               hipStream_t) {
-  return rtq::set_error(RTQ_E_INVALID_ARG, "render not available");
+
+int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
+               const rtq_render_opts* opts, float* images, hipStream_t stream) {
+  if (!images) return set_error(RTQ_E_INVALID_ARG, "NULL image buffer");
+  if (!opts) return set_error(RTQ_E_INVALID_ARG, "NULL options");
+  const bool plain = opts->scheduler == RTQ_SCHED_PLAIN;
+  Prepared p;
+  int rc = prepare(s, cams, n_cams, spp, depth, opts, plain, stream, &p);
+  if (rc) return rc;
+  const SceneView sv = scene_view(s, p.fmt);
+  hipError_t e;
+  if (plain) {
+    RenderScratch* r = scratch_of(const_cast<rtq_scene*>(s));
+    e = launch_render_plain(sv, p.rp, r->pb, p.fmt, p.tl.stack_depth, p.tl.block, images, p.n_pixels,
+                            reinterpret_cast<unsigned long long*>(opts->counters), stream);
+  } else {
+    e = launch_render_persistent(sv, p.rp, p.fmt, p.tl, images, p.n_pixels,
+                                 reinterpret_cast<unsigned long long*>(opts->counters),
+                                 reinterpret_cast<unsigned long long*>(opts->view_done),
+                                 reinterpret_cast<unsigned long long*>(opts->start_tick), stream);
+  }
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "render launch");
 }
-int rtq_render_backward(const rtq_scene*, const rtq_camera*, int32_t, int32_t, int32_t, const rtq_render_opts*,
-                        const float*, float*, hipStream_t) {
-  return rtq::set_error(RTQ_E_INVALID_ARG, "render not available");
+
+int rtq_render_backward(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
+                        const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,
+                        hipStream_t stream) {
+  if (!grad_images || !grad_albedo) return set_error(RTQ_E_INVALID_ARG, "NULL gradient buffer");
+  Prepared p;
+  int rc = prepare(s, cams, n_cams, spp, depth, opts, false, stream, &p);
+  if (rc) return rc;
+  const SceneView sv = scene_view(s, p.fmt);
+  const hipError_t e =
+      launch_adjoint(sv, p.rp, p.fmt, p.tl.stack_depth, p.tl.block, grad_images, grad_albedo, stream);
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "adjoint launch");
 }
-}
+
+}  // extern "C"

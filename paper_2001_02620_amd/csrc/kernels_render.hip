@@ -1,1 +1,487 @@
-// render kernels
+// Path-tracing kernels.
+//
+// Plain scheduler (a wavefront path tracer after Laine, Karras, Aila 2013, one
+// kernel per stage): raygen -> per bounce [closest-hit queue trace -> shade
+// (appends shadow rays and extension rays with wave-aggregated compaction) ->
+// occlusion queue trace -> shadow resolve] -> accumulate.
+//
+// Persistent scheduler: one launch.  Resident waves pull path ids from a shared
+// counter; each lane runs one path, alternating extension and shadow rays in a
+// single traversal loop, and finished lanes are refilled with new paths
+// (regeneration) whenever enough of the wave is idle, across every view.
+//
+// Both schedulers evaluate each path with the same device functions in the same
+// order and write its radiance to its own slot; the image is the per-pixel mean
+// over samples in sample order, so both produce bit-identical images.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "render_device.h"
+#include "render_kernels.h"
+
+namespace rtq {
+
+// Wave-aggregated append: returns this lane's slot (valid where want is true).
+__device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter) {
+  const unsigned long long m = __ballot(want);
+  if (m == 0ull) return 0u;
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0u;
+  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+  const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  return base + rank;
+}
+
+// ---------------------------------------------------------------- plain scheduler
+__global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
+  const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pid == 0) counts[0] = (uint32_t)rp.n_paths;
+  if (pid >= rp.n_paths) return;
+  int view;
+  uint32_t pixel, sample;
+  const Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
+  q.ox[pid] = r.ox;
+  q.oy[pid] = r.oy;
+  q.oz[pid] = r.oz;
+  q.dx[pid] = r.dx;
+  q.dy[pid] = r.dy;
+  q.dz[pid] = r.dz;
+  q.pid[pid] = (uint32_t)pid;
+  q.beta[pid] = 1.0f;
+  q.ex_rec[pid] = kEmpty;
+  q.ex_qh[pid] = kEmpty;
+  rp.slots[pid] = 0.0f;
+}
+
+// Closest hit (ANY = false) of an extension queue, or occlusion (ANY = true) of a
+// shadow queue, one lane per entry.
+template <int FMT, bool ANY>
+__global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq, const uint32_t* count,
+                              QueueHits qh, uint8_t* occ, int depth) {
+  extern __shared__ uint2 lds[];
+  const int lane = threadIdx.x & 63;
+  const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
+  uint2 spill[kStackTotal];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)*count) return;
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  bool ok;
+  if (ANY) {
+    ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+    L.ex_rec = sq.ex_rec[i];
+    const uint32_t e = sq.ex_qh[i];
+    L.ex_quad = e & 0x7FFFFFFFu;
+    L.ex_half = e >> 31;
+    L.any = true;
+  } else {
+    ok = lane_init(L, sc, eq.ox[i], eq.oy[i], eq.oz[i], eq.dx[i], eq.dy[i], eq.dz[i], 0.0f, kInfF);
+    L.ex_rec = eq.ex_rec[i];
+    const uint32_t e = eq.ex_qh[i];
+    L.ex_quad = e == kEmpty ? kEmpty : (e & 0x7FFFFFFFu);
+    L.ex_half = e == kEmpty ? 0u : (e >> 31);
+  }
+  if (ok)
+    while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+    }
+  if (ANY) {
+    occ[i] = L.b_rec != kEmpty ? 1 : 0;
+  } else {
+    qh.t[i] = L.t_best;
+    qh.rec[i] = L.b_rec;
+    qh.qh[i] = L.b_rec == kEmpty ? kEmpty : (L.b_quad | (L.b_half << 31));
+  }
+}
+
+__global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const uint32_t* count_in, QueueHits qh,
+                        ExtQueue out, uint32_t* count_out, ShadowQueue sq, uint32_t* count_sq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < (int64_t)*count_in;
+  bool want_shadow = false, want_next = false;
+  float contrib = 0.0f, beta_next = 0.0f, ndx = 0.0f, ndy = 0.0f, ndz = 0.0f;
+  Shade s{};
+  uint32_t pid = 0u, rec = kEmpty, qhv = kEmpty;
+  if (live) {
+    pid = in.pid[i];
+    const float beta = in.beta[i];
+    rec = qh.rec[i];
+    if (rec == kEmpty) {
+      rp.slots[pid] += beta * rp.L_sky;  // escaped: constant sky
+    } else {
+      qhv = qh.qh[i];
+      const Ray3 r{in.ox[i], in.oy[i], in.oz[i], in.dx[i], in.dy[i], in.dz[i]};
+      s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31);
+      if (s.cosl > 0.0f) {
+        want_shadow = true;
+        contrib = nee_term(beta, s.a, s.cosl, rp);
+      }
+      if (b < rp.depth - 1) {
+        int view;
+        uint32_t pixel, sample;
+        path_coords(rp, (int64_t)pid, &view, &pixel, &sample);
+        bounce_dir(rp, pixel, sample, view, b, s, &ndx, &ndy, &ndz);
+        beta_next = beta * s.a;
+        want_next = true;
+      }
+    }
+  }
+  const uint32_t js = wave_append(want_shadow, count_sq);
+  if (want_shadow) {
+    sq.ox[js] = s.px;
+    sq.oy[js] = s.py;
+    sq.oz[js] = s.pz;
+    sq.pid[js] = pid;
+    sq.contrib[js] = contrib;
+    sq.ex_rec[js] = rec;
+    sq.ex_qh[js] = qhv;
+  }
+  const uint32_t jn = wave_append(want_next, count_out);
+  if (want_next) {
+    out.ox[jn] = s.px;
+    out.oy[jn] = s.py;
+    out.oz[jn] = s.pz;
+    out.dx[jn] = ndx;
+    out.dy[jn] = ndy;
+    out.dz[jn] = ndz;
+    out.pid[jn] = pid;
+    out.beta[jn] = beta_next;
+    out.ex_rec[jn] = rec;
+    out.ex_qh[jn] = qhv;
+  }
+}
+
+__global__ void k_shadow_resolve(RenderParams rp, ShadowQueue sq, const uint32_t* count, const uint8_t* occ) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)*count) return;
+  if (!occ[i]) rp.slots[sq.pid[i]] += sq.contrib[i];
+}
+
+// image[view pixel] = (sum over samples, in sample order) / spp
+__global__ void k_accum(RenderParams rp, float* image, int64_t n_pixels) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_pixels) return;
+  int lo = 0, hi = rp.n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rp.cams[mid].img_offset <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const CamDev& c = rp.cams[lo];
+  const int64_t wh = (int64_t)c.w * c.h;
+  const int64_t pixel = g - c.img_offset;
+  if (pixel >= wh) return;  // a gap between views: not part of any image
+  float sum = 0.0f;
+  for (int s = 0; s < rp.spp; ++s) sum += rp.slots[c.path_base + s * wh + pixel];
+  image[g] = sum / (float)rp.spp;
+}
+
+// counters[0..3] += closest, shadow, incoherent (bounce >= 1), paths
+__global__ void k_plain_stats(const uint32_t* counts, int depth, int64_t n_paths, unsigned long long* counters) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long ext = 0, sh = 0, inc = 0;
+  for (int b = 0; b < depth; ++b) {
+    ext += counts[b];
+    if (b >= 1) inc += counts[b];
+    sh += counts[kMaxDepth + 1 + b];
+  }
+  counters[0] += ext;
+  counters[1] += sh;
+  counters[2] += inc;
+  counters[3] += (unsigned long long)n_paths;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- persistent scheduler
+struct PathLane {
+  int64_t pid;
+  int view;
+  uint32_t pixel, sample;
+  int b;
+  float beta, radiance, pending, beta_next, ndx, ndy, ndz;
+  bool shadow, have_next;
+};
+
+template <int FMT, bool TS>
+__global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
+                                    unsigned long long* counter, unsigned long long* counters,
+                                    unsigned long long* view_done) {
+  extern __shared__ uint2 lds[];
+  const int lane = threadIdx.x & 63;
+  const Stack S{lds + (threadIdx.x >> 6) * depth_lds * 64, depth_lds, lane};
+  uint2 spill[kStackTotal];
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  PathLane P{};
+  bool has = false, exhausted = false, pending_done = false;
+  uint32_t n_ext = 0, n_sh = 0, n_inc = 0, n_paths = 0;
+  for (;;) {
+    const unsigned long long idle = __ballot(!has);
+    const int nidle = __popcll(idle);
+    if (!exhausted && (nidle >= refill || nidle == 64)) {
+      const int leader = __ffsll((long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(counter, (unsigned long long)nidle);
+      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+      base = ((unsigned long long)hi << 32) | lo;
+      if (!has) {
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+        const int64_t pid = (int64_t)(base + rank);
+        if (pid < rp.n_paths) {
+          P.pid = pid;
+          const Ray3 r = path_camera_ray(rp, pid, &P.view, &P.pixel, &P.sample);
+          P.b = 0;
+          P.beta = 1.0f;
+          P.radiance = 0.0f;
+          P.shadow = false;
+          P.have_next = false;
+          L.ex_rec = kEmpty;
+          L.ex_quad = kEmpty;
+          L.ex_half = 0u;
+          pending_done = !lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF);
+          ++n_ext;
+          has = true;
+        }
+      }
+      if ((int64_t)(base + nidle) >= rp.n_paths) exhausted = true;
+    }
+    if (!__any(has)) {
+      if (exhausted) break;
+      continue;
+    }
+    if (has) {
+      for (;;) {
+        const bool fin = pending_done || lane_step<FMT, false>(L, sc, S, spill, vc);
+        pending_done = false;
+        if (fin) {
+          bool path_done = false;
+          if (!P.shadow) {
+            if (L.b_rec == kEmpty) {
+              P.radiance += P.beta * rp.L_sky;
+              path_done = true;
+            } else {
+              const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
+              const Shade s = shade_hit(sc, rp, r, L.t_best, L.b_rec, L.b_quad, L.b_half);
+              const uint32_t hrec = L.b_rec, hquad = L.b_quad, hhalf = L.b_half;
+              P.have_next = P.b < rp.depth - 1;
+              if (P.have_next) {
+                bounce_dir(rp, P.pixel, P.sample, P.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
+                P.beta_next = P.beta * s.a;
+              }
+              L.ex_rec = hrec;
+              L.ex_quad = hquad;
+              L.ex_half = hhalf;
+              if (s.cosl > 0.0f) {
+                P.pending = nee_term(P.beta, s.a, s.cosl, rp);
+                P.shadow = true;
+                pending_done = !lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+                L.any = true;
+                ++n_sh;
+              } else if (P.have_next) {
+                P.beta = P.beta_next;
+                ++P.b;
+                pending_done = !lane_init(L, sc, s.px, s.py, s.pz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
+                ++n_ext;
+                ++n_inc;
+              } else {
+                path_done = true;
+              }
+            }
+          } else {
+            if (L.b_rec == kEmpty) P.radiance += P.pending;
+            P.shadow = false;
+            if (P.have_next) {
+              P.beta = P.beta_next;
+              ++P.b;
+              pending_done = !lane_init(L, sc, L.wox, L.woy, L.woz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
+              ++n_ext;
+              ++n_inc;
+            } else {
+              path_done = true;
+            }
+          }
+          if (path_done) {
+            rp.slots[P.pid] = P.radiance;
+            ++n_paths;
+            if (TS) atomicMax(&view_done[P.view], (unsigned long long)wall_clock64());
+            has = false;
+            break;
+          }
+        }
+        if (!exhausted && __popcll(__ballot(1)) <= 64 - refill) break;
+      }
+    }
+  }
+  if (counters) {
+    // wave reduction, one atomic per counter per wave
+    unsigned long long v[4] = {n_ext, n_sh, n_inc, n_paths};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      unsigned long long x = v[k];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+      if (lane == 0) atomicAdd(&counters[k], x);
+    }
+  }
+}
+
+__global__ void k_start_tick(unsigned long long* t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) t[0] = (unsigned long long)wall_clock64();
+}
+
+// ---------------------------------------------------------------- adjoint
+// One lane per path: replay the path from its RNG counters with the same device
+// functions (identical hits), keep per vertex the face, beta_k and the NEE factor
+// c_k = (E / pi) cos_L V_k, then walk back: with V_K = L_sky if the path escaped
+// (else 0) and V_k = a_k (c_k + V_{k+1}), the derivative of the path value with
+// respect to the albedo at vertex k is beta_k (c_k + V_{k+1}).
+template <int FMT>
+__global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, float* grad_albedo, int depth_lds) {
+  extern __shared__ uint2 lds[];
+  const int lane = threadIdx.x & 63;
+  const Stack S{lds + (threadIdx.x >> 6) * depth_lds * 64, depth_lds, lane};
+  uint2 spill[kStackTotal];
+  const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pid >= rp.n_paths) return;
+  int view;
+  uint32_t pixel, sample;
+  Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
+  const float g = grad_img[rp.cams[view].img_offset + pixel] / (float)rp.spp;
+  if (g == 0.0f) return;
+  uint32_t face[kMaxDepth];
+  float betak[kMaxDepth], ck[kMaxDepth], ak[kMaxDepth];
+  int K = 0;
+  bool escaped = false;
+  float beta = 1.0f;
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  L.ex_rec = kEmpty;
+  L.ex_quad = kEmpty;
+  L.ex_half = 0u;
+  for (int b = 0; b < rp.depth; ++b) {
+    if (lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF))
+      while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+      }
+    if (L.b_rec == kEmpty) {
+      escaped = true;
+      break;
+    }
+    const Shade s = shade_hit(sc, rp, r, L.t_best, L.b_rec, L.b_quad, L.b_half);
+    const uint32_t hrec = L.b_rec, hquad = L.b_quad, hhalf = L.b_half;
+    float c = 0.0f;
+    if (s.cosl > 0.0f) {
+      L.ex_rec = hrec;
+      L.ex_quad = hquad;
+      L.ex_half = hhalf;
+      if (lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF)) {
+        L.any = true;
+        while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+        }
+      }
+      if (L.b_rec == kEmpty) c = nee_factor(s.cosl, rp);
+    }
+    face[K] = s.face;
+    betak[K] = beta;
+    ck[K] = c;
+    ak[K] = s.a;
+    ++K;
+    if (b == rp.depth - 1) break;
+    float dx, dy, dz;
+    bounce_dir(rp, pixel, sample, view, b, s, &dx, &dy, &dz);
+    r = Ray3{s.px, s.py, s.pz, dx, dy, dz};
+    beta = beta * s.a;
+    L.ex_rec = hrec;
+    L.ex_quad = hquad;
+    L.ex_half = hhalf;
+  }
+  float V = escaped ? rp.L_sky : 0.0f;
+  for (int k = K - 1; k >= 0; --k) {
+    const float cv = ck[k] + V;
+    unsafeAtomicAdd(&grad_albedo[face[k]], g * (betak[k] * cv));
+    V = ak[k] * cv;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
+                               int stack_depth, int block, float* image, int64_t n_pixels,
+                               unsigned long long* counters, hipStream_t s) {
+  const unsigned gp = blocks(rp.n_paths, 256);
+  const size_t lds = (size_t)block * stack_depth * sizeof(uint2);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, pb.counts, 2 * kMaxDepth + 2);
+  hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
+  for (int b = 0; b < rp.depth; ++b) {
+    const ExtQueue& qin = pb.q[b & 1];
+    const ExtQueue& qout = pb.q[(b + 1) & 1];
+    uint32_t* cin = pb.counts + b;
+    uint32_t* cout = pb.counts + b + 1;
+    uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
+    const unsigned gt = blocks(rp.n_paths, block);
+    if (fmt == 2)
+      hipLaunchKernelGGL((k_trace_queue<2, false>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, cin, pb.hits,
+                         pb.occ, stack_depth);
+    else
+      hipLaunchKernelGGL((k_trace_queue<1, false>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, cin, pb.hits,
+                         pb.occ, stack_depth);
+    hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq);
+    if (fmt == 2)
+      hipLaunchKernelGGL((k_trace_queue<2, true>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, csq, pb.hits,
+                         pb.occ, stack_depth);
+    else
+      hipLaunchKernelGGL((k_trace_queue<1, true>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, csq, pb.hits,
+                         pb.occ, stack_depth);
+    hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+  }
+  hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
+  if (counters)
+    hipLaunchKernelGGL(k_plain_stats, dim3(1), dim3(64), 0, s, pb.counts, rp.depth, rp.n_paths, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
+                                    float* image, int64_t n_pixels, unsigned long long* counters,
+                                    unsigned long long* view_done, unsigned long long* start_tick, hipStream_t s) {
+  const size_t lds = (size_t)tl.block * tl.stack_depth * sizeof(uint2);
+  hipError_t e = launch_zero_u64(tl.counter, 1, s);
+  if (e != hipSuccess) return e;
+  if (start_tick) hipLaunchKernelGGL(k_start_tick, dim3(1), dim3(64), 0, s, start_tick);
+  const bool ts = view_done != nullptr;
+  if (fmt == 2) {
+    if (ts)
+      hipLaunchKernelGGL((k_render_persistent<2, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
+    else
+      hipLaunchKernelGGL((k_render_persistent<2, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
+  } else {
+    if (ts)
+      hipLaunchKernelGGL((k_render_persistent<1, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
+    else
+      hipLaunchKernelGGL((k_render_persistent<1, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
+  }
+  hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
+                          const float* grad_img, float* grad_albedo, hipStream_t s) {
+  const size_t lds = (size_t)block * stack_depth * sizeof(uint2);
+  const unsigned g = blocks(rp.n_paths, block);
+  if (fmt == 2)
+    hipLaunchKernelGGL((k_adjoint<2>), dim3(g), dim3(block), lds, s, sc, rp, grad_img, grad_albedo, stack_depth);
+  else
+    hipLaunchKernelGGL((k_adjoint<1>), dim3(g), dim3(block), lds, s, sc, rp, grad_img, grad_albedo, stack_depth);
+  return hipGetLastError();
+}
+
+}  // namespace rtq

@@ -25,11 +25,14 @@ __device__ __forceinline__ void store_result(const Lane& L, const SceneView& sc,
   h.prim[i] = hit ? sc.quad_prim[L.b_quad] : -1;
 }
 
+template <bool ANY>
 __device__ __forceinline__ bool load_ray(Lane& L, const SceneView& sc, const RaysSoA& r, int64_t i) {
   L.ex_rec = kEmpty;
   L.ex_quad = kEmpty;
   L.ex_half = 0u;
-  return lane_init(L, sc, r.ox[i], r.oy[i], r.oz[i], r.dx[i], r.dy[i], r.dz[i], r.tmin[i], r.tmax[i]);
+  const bool ok = lane_init(L, sc, r.ox[i], r.oy[i], r.oz[i], r.dx[i], r.dy[i], r.dz[i], r.tmin[i], r.tmax[i]);
+  L.any = ANY;
+  return ok;
 }
 
 template <bool COUNT>
@@ -51,8 +54,8 @@ __global__ void k_trace_plain(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
   if (i >= n) return;
   Lane L;
   VisitCounters vc{0, 0, 0, 0};
-  if (load_ray(L, sc, rays, i))
-    while (!lane_step<FMT, ANY, COUNT>(L, sc, S, spill, vc)) {
+  if (load_ray<ANY>(L, sc, rays, i))
+    while (!lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
     }
   store_result<ANY>(L, sc, i, hits, occ);
   store_visits<COUNT>(visits, i, vc);
@@ -86,7 +89,7 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
         idx = (int64_t)(base + rank);
         if (idx < n) {
           vc = VisitCounters{0, 0, 0, 0};
-          if (load_ray(L, sc, rays, idx)) {
+          if (load_ray<ANY>(L, sc, rays, idx)) {
             has = true;
           } else {
             store_result<ANY>(L, sc, idx, hits, occ);
@@ -102,7 +105,7 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
     }
     if (has) {
       for (;;) {
-        if (lane_step<FMT, ANY, COUNT>(L, sc, S, spill, vc)) {
+        if (lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
           store_result<ANY>(L, sc, idx, hits, occ);
           store_visits<COUNT>(visits, idx, vc);
           has = false;
@@ -119,12 +122,12 @@ __global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Lane L;
-  if (load_ray(L, sc, rays, i)) {
+  if (load_ray<false>(L, sc, rays, i)) {
     for (uint32_t r = 0; r < sc.n_inst; ++r) {
       uint32_t root;
       enter_instance(L, sc.inst, r, &root);
       const uint32_t p = sc.inst[r].proto;
-      leaf_quads<false, false>(L, sc, (uint32_t)sc.proto_qbase[p], (uint32_t)sc.proto_nq[p], nullptr);
+      leaf_quads<false>(L, sc, (uint32_t)sc.proto_qbase[p], (uint32_t)sc.proto_nq[p], nullptr);
     }
   }
   store_result<false>(L, sc, i, hits, nullptr);

@@ -1,0 +1,188 @@
+// Device-side pieces of the Lambertian path tracer shared by every scheduler:
+// counter-based random numbers, pinhole camera rays, hit shading with next-event
+// estimation toward a directional light, and cosine-distributed bounces.
+//
+// Every scheduler calls exactly these functions in the same order per path, so
+// the per-path radiance is bit-identical whichever kernel runs the path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "trace_device.h"
+
+#pragma clang fp contract(off)
+
+namespace rtq {
+
+// One view.  The basis (f, r, u) is computed on the host in FP64 and rounded.
+struct CamDev {
+  float eye[3];
+  float f[3], r[3], u[3];
+  float tan_half, aspect;
+  int32_t w, h;
+  int64_t img_offset;  // first pixel of the view in the packed image
+  int64_t path_base;   // first path id of the view; paths are sample-major: base + s * w * h + pixel
+};
+
+struct RenderParams {
+  const CamDev* cams;
+  int32_t n_cams;
+  int32_t spp;
+  int32_t depth;
+  uint32_t key0, key1;  // Philox key: (seed_lo, seed_hi ^ frame)
+  float lx, ly, lz;     // unit direction toward the light
+  float e_over_pi;      // E / pi
+  float L_sky;
+  int64_t n_paths;
+  float* slots;         // per-path radiance
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011): ten rounds of two 32x32->64
+// multiplications with the round keys bumped by the Weyl constants in between.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    if (i > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Uniform in [0, 1): the top 24 bits, exactly representable in FP32.
+__device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-08f; }
+
+// path id -> (view, pixel, sample) by binary search over the views' path bases.
+__device__ __forceinline__ void path_coords(const RenderParams& rp, int64_t pid, int* view, uint32_t* pixel,
+                                            uint32_t* sample) {
+  int lo = 0, hi = rp.n_cams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rp.cams[mid].path_base <= pid) lo = mid;
+    else hi = mid - 1;
+  }
+  const CamDev& c = rp.cams[lo];
+  const int64_t wh = (int64_t)c.w * c.h;
+  const int64_t k = pid - c.path_base;
+  *view = lo;
+  *sample = (uint32_t)(k / wh);
+  *pixel = (uint32_t)(k - (int64_t)(*sample) * wh);
+}
+
+struct Ray3 {
+  float ox, oy, oz, dx, dy, dz;
+};
+
+// Pinhole camera ray through pixel (x, y) (row 0 at the top) jittered by (xi0, xi1).
+__device__ __forceinline__ Ray3 camera_ray(const CamDev& c, uint32_t pixel, float xi0, float xi1) {
+  const uint32_t x = pixel % (uint32_t)c.w, y = pixel / (uint32_t)c.w;
+  const float sx = (2.0f * ((float)x + xi0) / (float)c.w - 1.0f) * c.tan_half * c.aspect;
+  const float sy = (1.0f - 2.0f * ((float)y + xi1) / (float)c.h) * c.tan_half;
+  float dx = c.f[0] + sx * c.r[0] + sy * c.u[0];
+  float dy = c.f[1] + sx * c.r[1] + sy * c.u[1];
+  float dz = c.f[2] + sx * c.r[2] + sy * c.u[2];
+  const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  return Ray3{c.eye[0], c.eye[1], c.eye[2], dx * inv, dy * inv, dz * inv};
+}
+
+struct Shade {
+  float px, py, pz;  // hit point
+  float nx, ny, nz;  // unit geometric normal facing the incoming ray
+  float a;           // albedo
+  float cosl;        // n . light
+  uint32_t face;     // unique face index (albedo index)
+};
+
+// Geometric normal of the hit half in object space, mapped to world space by
+// A^-T (columns of the stored inverse rows), normalised and turned to face the
+// incoming ray; hit point p = o + t d; albedo of the unique prototype face.
+__device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderParams& rp, const Ray3& r, float t,
+                                           uint32_t rec, uint32_t quad, uint32_t half) {
+  const float4 f0 = sc.quads[3 * (size_t)quad + 0];
+  const float4 f1 = sc.quads[3 * (size_t)quad + 1];
+  const float4 f2 = sc.quads[3 * (size_t)quad + 2];
+  // v0 = f0.xyz, v1 = (f0.w, f1.x, f1.y), v2 = (f1.z, f1.w, f2.x), v3 = (f2.y, f2.z, f2.w)
+  float ax, ay, az, bx, by, bz;
+  if (half == 0u) {  // (v1 - v0) x (v3 - v0)
+    ax = f0.w - f0.x; ay = f1.x - f0.y; az = f1.y - f0.z;
+    bx = f2.y - f0.x; by = f2.z - f0.y; bz = f2.w - f0.z;
+  } else {           // (v3 - v2) x (v1 - v2)
+    ax = f2.y - f1.z; ay = f2.z - f1.w; az = f2.w - f2.x;
+    bx = f0.w - f1.z; by = f1.x - f1.w; bz = f1.y - f2.x;
+  }
+  const float onx = ay * bz - az * by, ony = az * bx - ax * bz, onz = ax * by - ay * bx;
+  const InstRec& ir = sc.inst[rec];
+  const float4 r0 = *reinterpret_cast<const float4*>(ir.r0);
+  const float4 r1 = *reinterpret_cast<const float4*>(ir.r1);
+  const float4 r2 = *reinterpret_cast<const float4*>(ir.r2);
+  float nx = r0.x * onx + r1.x * ony + r2.x * onz;
+  float ny = r0.y * onx + r1.y * ony + r2.y * onz;
+  float nz = r0.z * onx + r1.z * ony + r2.z * onz;
+  const float inv = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+  nx *= inv;
+  ny *= inv;
+  nz *= inv;
+  if (nx * r.dx + ny * r.dy + nz * r.dz > 0.0f) {
+    nx = -nx;
+    ny = -ny;
+    nz = -nz;
+  }
+  Shade s;
+  s.px = r.ox + t * r.dx;
+  s.py = r.oy + t * r.dy;
+  s.pz = r.oz + t * r.dz;
+  s.nx = nx;
+  s.ny = ny;
+  s.nz = nz;
+  s.face = ir.face_base + (uint32_t)sc.quad_prim[quad];
+  s.a = sc.albedo[s.face];
+  s.cosl = nx * rp.lx + ny * rp.ly + nz * rp.lz;
+  return s;
+}
+
+// Next-event contribution of a visible light: beta * (a / pi) * E * cos_L.
+__device__ __forceinline__ float nee_term(float beta, float a, float cosl, const RenderParams& rp) {
+  return beta * (a * rp.e_over_pi * cosl);
+}
+// The factor c = (E / pi) cos_L that multiplies beta * a (used by the adjoint).
+__device__ __forceinline__ float nee_factor(float cosl, const RenderParams& rp) { return rp.e_over_pi * cosl; }
+
+// Cosine-distributed direction about n from (u1, u2): local
+// (sqrt(u1) cos 2 pi u2, sqrt(u1) sin 2 pi u2, sqrt(1 - u1)) in the orthonormal
+// basis of Duff et al. 2017.
+__device__ __forceinline__ void cosine_dir(float nx, float ny, float nz, float u1, float u2, float* dx, float* dy,
+                                           float* dz) {
+  const float sg = nz >= 0.0f ? 1.0f : -1.0f;
+  const float a = -1.0f / (sg + nz);
+  const float b = nx * ny * a;
+  const float t1x = 1.0f + sg * nx * nx * a, t1y = sg * b, t1z = -sg * nx;
+  const float t2x = b, t2y = sg + ny * ny * a, t2z = -ny;
+  const float rr = sqrtf(u1);
+  float sn, cs;
+  sincospif(2.0f * u2, &sn, &cs);
+  const float lx = rr * cs, ly = rr * sn, lz = sqrtf(1.0f - u1);
+  *dx = lx * t1x + ly * t2x + lz * nx;
+  *dy = lx * t1y + ly * t2y + lz * ny;
+  *dz = lx * t1z + ly * t2z + lz * nz;
+}
+
+// Camera ray of path `pid` (jitter from words 0, 1 of the bounce-0 counter).
+__device__ __forceinline__ Ray3 path_camera_ray(const RenderParams& rp, int64_t pid, int* view, uint32_t* pixel,
+                                                uint32_t* sample) {
+  path_coords(rp, pid, view, pixel, sample);
+  const uint4 w = philox4x32_10(make_uint4(*pixel, *sample, (uint32_t)*view, 0u), rp.key0, rp.key1);
+  return camera_ray(rp.cams[*view], *pixel, u01(w.x), u01(w.y));
+}
+
+// Bounce direction after hit b of a path (words 2, 3 of counter (pixel, sample, view, b)).
+__device__ __forceinline__ void bounce_dir(const RenderParams& rp, uint32_t pixel, uint32_t sample, int view, int b,
+                                           const Shade& s, float* dx, float* dy, float* dz) {
+  const uint4 w = philox4x32_10(make_uint4(pixel, sample, (uint32_t)view, (uint32_t)b), rp.key0, rp.key1);
+  cosine_dir(s.nx, s.ny, s.nz, u01(w.z), u01(w.w), dx, dy, dz);
+}
+
+}  // namespace rtq

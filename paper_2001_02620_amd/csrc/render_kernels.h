@@ -1,0 +1,54 @@
+// Internal interface of the path-tracing kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "render_device.h"
+
+namespace rtq {
+
+constexpr int kMaxDepth = 16;  // closest-hit rays per path
+
+// Extension-ray queue (structure of arrays).  ex_qh packs the spawning
+// triangle's leaf-ordered quad (bits 0..30) and half (bit 31); kEmpty = none.
+struct ExtQueue {
+  float *ox, *oy, *oz, *dx, *dy, *dz;
+  uint32_t* pid;
+  float* beta;
+  uint32_t *ex_rec, *ex_qh;
+};
+
+// Shadow-ray queue: direction is the light direction.
+struct ShadowQueue {
+  float *ox, *oy, *oz;
+  uint32_t* pid;
+  float* contrib;
+  uint32_t *ex_rec, *ex_qh;
+};
+
+// Closest hits of an extension queue (internal form).
+struct QueueHits {
+  float* t;
+  uint32_t* rec;
+  uint32_t* qh;
+};
+
+struct PlainBuffers {
+  ExtQueue q[2];
+  ShadowQueue sq;
+  QueueHits hits;
+  uint8_t* occ;
+  uint32_t* counts;  // [0, kMaxDepth]: extension queue sizes; [kMaxDepth + 1, ...): shadow queue sizes
+};
+
+hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
+                               int stack_depth, int block, float* image, int64_t n_pixels,
+                               unsigned long long* counters, hipStream_t s);
+hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
+                                    float* image, int64_t n_pixels, unsigned long long* counters,
+                                    unsigned long long* view_done, unsigned long long* start_tick, hipStream_t s);
+hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
+                          const float* grad_img, float* grad_albedo, hipStream_t s);
+
+}  // namespace rtq

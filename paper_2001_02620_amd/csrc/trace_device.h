@@ -69,6 +69,7 @@ struct Lane {
   float b_u, b_v;
   // exclusion (spawning triangle) as (record, leaf-ordered quad, half)
   uint32_t ex_rec, ex_quad, ex_half;
+  bool any;  // any-hit query: stop at the first accepted hit
 };
 
 __device__ __forceinline__ float rcp_exact(float d) { return 1.0f / d; }
@@ -291,8 +292,8 @@ __device__ __forceinline__ uint2 pop(Lane& L, const Stack& S, const uint2* spill
 
 // Candidate hit (t, record, quad, half) against the best so far, by key.
 __device__ __forceinline__ bool better(const Lane& L, const SceneView& sc, float t, uint32_t quad, uint32_t half) {
-  if (t < L.t_best) return true;
-  if (t > L.t_best || L.b_rec == kEmpty) return t < L.t_best;
+  if (L.b_rec == kEmpty) return true;  // the caller already checked t <= t_best (= tmax)
+  if (t != L.t_best) return t < L.t_best;
   if (L.inst_id != L.b_inst) return L.inst_id < L.b_inst;
   const int32_t pa = sc.quad_prim[quad], pb = sc.quad_prim[L.b_quad];
   if (pa != pb) return pa < pb;
@@ -300,8 +301,8 @@ __device__ __forceinline__ bool better(const Lane& L, const SceneView& sc, float
 }
 
 // Test quads [first, first + count) of the current instance.  Returns true if
-// any-hit mode found a hit.
-template <bool ANY, bool COUNT>
+// an any-hit query found a hit.
+template <bool COUNT>
 __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_t first, uint32_t count,
                                            uint32_t* ctr_quads) {
   for (uint32_t q = first; q < first + count; ++q) {
@@ -320,13 +321,13 @@ __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_
     const float e31 = edge(s3, s1);
     const float e12 = edge(s1, s2);
     const float e23 = edge(s2, s3);
-    const float t_lim = ANY ? L.tmax : L.t_best;
+    const float t_lim = L.any ? L.tmax : L.t_best;
     const TriResult ra = tri_finish(e13, e30, e01, s0, s1, s3, L.tmin, t_lim);
     const TriResult rb = tri_finish(e31, e12, e23, s2, s3, s1, L.tmin, t_lim);
     const bool exq = (L.rec == L.ex_rec) && (q == L.ex_quad);
     const bool oka = ra.hit && !(exq && L.ex_half == 0u);
     const bool okb = rb.hit && !(exq && L.ex_half == 1u);
-    if (ANY) {
+    if (L.any) {
       if (oka || okb) {
         L.t_best = oka ? ra.t : rb.t;
         L.b_rec = L.rec;
@@ -387,6 +388,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   L.rec = kEmpty;
   L.inst_id = kEmpty;
   L.cur = 0u;  // TLAS root
+  L.any = false;
   const bool finite = __builtin_isfinite(ox) && __builtin_isfinite(oy) && __builtin_isfinite(oz) &&
                       __builtin_isfinite(dx) && __builtin_isfinite(dy) && __builtin_isfinite(dz) &&
                       !(dx == 0.0f && dy == 0.0f && dz == 0.0f) && !(tmin != tmin) && !(tmax != tmax);
@@ -399,7 +401,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
 }
 
 // One traversal step.  Returns true when the lane's traversal is complete.
-template <int FMT, bool ANY, bool COUNT>
+template <int FMT, bool COUNT>
 __device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
   using Codec = NodeCodec<FMT>;
@@ -443,9 +445,9 @@ __device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const St
     L.cur = root;
     return false;
   }
-  const bool found = leaf_quads<ANY, COUNT>(L, sc, leaf_first(L.cur), leaf_count(L.cur), &vc.quads);
+  const bool found = leaf_quads<COUNT>(L, sc, leaf_first(L.cur), leaf_count(L.cur), &vc.quads);
   L.cur = kEmpty;
-  return ANY && found;
+  return found;
 }
 
 }  // namespace rtq

@@ -53,7 +53,8 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0):
     * unflagged rays (no near tie, graze or near-origin flag): identical
       (instance, primitive); t within 1e-5 relative unless t is ill-conditioned;
       u, v within uv_factor * 2^-24 * S / (shortest world edge * |cos|), the FP32
-      position error carried into the quad's parameterisation;
+      position error carried into the quad's parameterisation, with S the
+      oracle's position scale of the answer;
     * flagged rays: a hit reported by the GPU is one of the oracle's candidates.
     Returns the fraction of flagged rays.
     """
@@ -75,15 +76,13 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0):
     if hit.any():
         W = world_quads(scene, o.inst[hit], o.prim[hit])
         r = rays[hit].astype(np.float64)
-        p = r[:, 0:3] + o.t[hit][:, None] * r[:, 3:6]
-        S = np.maximum(1.0, np.maximum(np.abs(r[:, 0:3]).max(1), np.abs(p).max(1)))
         edges = np.stack([np.linalg.norm(W[:, (k + 1) % 4] - W[:, k], axis=1) for k in range(4)], 1)
         half = o.half[hit]
         A = np.where(half[:, None] == 0, W[:, 1] - W[:, 0], W[:, 3] - W[:, 2])
         B = np.where(half[:, None] == 0, W[:, 3] - W[:, 0], W[:, 1] - W[:, 2])
         n = np.cross(A, B)
         cos = np.abs((n * r[:, 3:6]).sum(1)) / (np.linalg.norm(n, axis=1) * np.linalg.norm(r[:, 3:6], axis=1))
-        tol = uv_factor * 2.0 ** -24 * S / (edges.min(1) * np.maximum(cos, 1e-3))
+        tol = uv_factor * 2.0 ** -24 * o.scale[hit] / (edges.min(1) * np.maximum(cos, 1e-3))
         du = np.abs(g["u"][hit] - o.u[hit])
         dv = np.abs(g["v"][hit] - o.v[hit])
         assert (du <= tol).all() and (dv <= tol).all(), f"uv error {max(du.max(), dv.max())}"

@@ -39,7 +39,11 @@ def multi_mesh_scene(meshes, albedos=None, xforms=None, protos=None):
 
 
 def floor_scene(albedo=0.5, half=5000.0, extra=None):
-    meshes = [axis_quad(-half, half, -half, half, 0.0)]
+    """Large floor quad at z = 0, shifted by half/2 along x and y so that its
+    diagonal (x + y = half) stays far from the origin, where the test cameras look
+    (a bounce ray leaving next to the diagonal may meet the other half at t ~ 0)."""
+    c = 0.5 * half
+    meshes = [axis_quad(-half + c, half + c, -half + c, half + c, 0.0)]
     albs = [albedo]
     if extra is not None:
         for m, a in extra:

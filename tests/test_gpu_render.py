@@ -1,0 +1,192 @@
+"""Parity of the HIP path tracer and its adjoint (through the C-ABI) with the
+oracle, and bit-identity of the two schedulers."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_02620_amd import scenegen as sg
+from tests import scenes as ts
+from tests.gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+rtq = pytest.importorskip("paper_2001_02620_amd")
+
+SCHEDS = [
+    dict(node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PLAIN),
+    dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PLAIN),
+    dict(node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PERSISTENT),
+    dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT),
+    dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT, stack_depth=4, refill=1, block=64,
+         waves_per_cu=2),
+    dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT, stack_depth=24, refill=40, block=128),
+]
+
+
+def _render(S, cams, st, **kw):
+    import torch
+    img = rtq.render(S, cams, st, **kw)
+    torch.cuda.synchronize()
+    return img.cpu().numpy()
+
+
+def _compare_image(gpu, ref, flags, rel=1e-4):
+    ok = flags == 0
+    err = np.abs(gpu.astype(np.float64) - ref)
+    bad = ok & (err > rel * np.abs(ref) + 1e-7)
+    if bad.any():
+        k = np.nonzero(bad)[0][:8]
+        raise AssertionError(f"{bad.sum()} unflagged pixels differ: idx {k} gpu {gpu[k]} oracle {ref[k]}")
+    return 1.0 - ok.mean()
+
+
+def _multi_view_scene():
+    scene = sg.tiny_scene(21, n_inst=24, n_protos=3, nq=8, spread=3.0)
+    cams = [sg.Camera((0.0, -12.0, 2.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 45.0, 37, 23),
+            sg.Camera((9.0, 4.0, 6.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 60.0, 64, 64),
+            sg.Camera((-3.0, 2.0, 10.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 30.0, 5, 70)]
+    return scene, cams
+
+
+@pytest.mark.parametrize("cfg", ["config1", "multiview"])
+def test_schedulers_bit_identical_and_match_oracle(cfg):
+    log(f"case: render {cfg}")
+    if cfg == "config1":
+        scene, cams, st = sg.config1()
+    else:
+        scene, cams = _multi_view_scene()
+        st = sg.RenderSettings(spp=3, depth=5, seed=77, frame=2)
+    S = rtq.Scene(scene)
+    import torch
+    imgs = []
+    for kw in SCHEDS:
+        log("  scheduler", kw)
+        cnt = torch.zeros(4, dtype=torch.uint64, device="cuda")
+        imgs.append((_render(S, cams, st, counters=cnt, **kw), cnt.cpu().numpy()))
+    ref_img, ref_cnt = imgs[0]
+    for (img, cnt), kw in zip(imgs[1:], SCHEDS[1:]):
+        assert (img.view(np.uint32) == ref_img.view(np.uint32)).all(), f"image differs for {kw}"
+        assert (cnt == ref_cnt).all(), f"ray counts differ for {kw}: {cnt} vs {ref_cnt}"
+    o = oracle.OracleScene(scene)
+    ref, fl, stats = o.render(cams, st)
+    frac = _compare_image(ref_img, ref, fl)
+    log(f"  flagged pixels {frac:.4f}; gpu rays {ref_cnt}; oracle {stats}")
+    assert frac < 0.1
+    n_paths = sum(c.w * c.h for c in cams) * st.spp
+    assert ref_cnt[3] == n_paths
+    if frac == 0.0:
+        assert ref_cnt[0] == stats["closest"] and ref_cnt[1] == stats["shadow"]
+
+
+def test_closed_form_images_gpu():
+    log("case: closed-form images")
+    a = float(np.float32(0.35))
+    st = sg.RenderSettings(spp=2, depth=2, seed=9)
+    cams = [sg.Camera((0.0, 0.0, 10.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 30.0, 16, 16)]
+    for kw in SCHEDS[:4]:
+        img = _render(rtq.Scene(ts.floor_scene(albedo=a)), cams, st, **kw)
+        cosl = st.light_dir[2]
+        np.testing.assert_allclose(img, a * cosl + a * st.L_sky, rtol=2e-6)
+        empty = ts.multi_mesh_scene([ts.axis_quad(-1, 1, -1, 1, 0.0)], xforms=[[1, 0, 0, 0, 0, 1, 0, 500, 0, 0, 1, 0]])
+        img = _render(rtq.Scene(empty), cams, st, **kw)
+        assert (img == np.float32(st.L_sky)).all()
+
+
+def test_cosine_sampling_form_factor_gpu():
+    """The view-factor scene of the oracle pin: per-pixel parity with the oracle
+    on unflagged pixels, and the mean escape fraction of cosine-sampled bounces
+    equal to 1 - F within 5 sigma."""
+    log("case: cosine sampling view factor")
+    a_f, h, half = 0.5, 1.0, 0.4
+    ceil = ts.axis_quad(-half, half, -half, half, h)
+    scene = ts.floor_scene(albedo=a_f, half=50.0, extra=[(ceil, 0.5)])
+    cams = [sg.Camera((0.0, 0.0, 0.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.01, 64, 64)]
+    st = sg.RenderSettings(spp=64, depth=2, seed=78)
+    img = _render(rtq.Scene(scene), cams, st, scheduler=rtq.SCHED_PERSISTENT).astype(np.float64)
+    ref, fl, _ = oracle.OracleScene(scene).render(cams, st)
+    frac = _compare_image(img.astype(np.float32), ref, fl)
+    assert frac < 0.05
+    F = 4 * ts.form_factor_corner(half, half, h)
+    cosl = 2 / math.sqrt(6.0)
+    escape = (img - a_f * cosl) / (a_f * st.L_sky)
+    n = img.size * st.spp
+    assert abs(escape.mean() - (1 - F)) < 5 * math.sqrt(F * (1 - F) / n)
+
+
+def _fd_faces(rng, g_or, taint, k=64):
+    mx = np.abs(g_or).max()
+    cand = np.nonzero((np.abs(g_or) > 1e-6 * mx) & (taint == 0))[0]
+    return rng.choice(cand, size=min(k, cand.size), replace=False)
+
+
+def test_adjoint_config4_vs_oracle_and_fd():
+    """Config 4: L2 loss against a target rendered with albedo + U[-0.1, 0.1];
+    the adjoint against the oracle's FP64 path-replay gradient (1e-3 relative)
+    and against central finite differences of the GPU renderer (h = 1e-2)."""
+    import torch
+    from paper_2001_02620_amd.autograd import RenderAlbedo
+    log("case: config 4 adjoint")
+    scene, cams, st = sg.config4()
+    S = rtq.Scene(scene)
+    rng = np.random.default_rng(2001026204)
+    alb = scene.albedo.astype(np.float32)
+    tgt_alb = (alb + rng.uniform(-0.1, 0.1, alb.shape)).astype(np.float32)
+    opts = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+    a_t = torch.from_numpy(tgt_alb).cuda()
+    with torch.no_grad():
+        T = RenderAlbedo.apply(a_t, S, cams, st, opts).clone()
+    a = torch.from_numpy(alb).cuda().requires_grad_(True)
+    I = RenderAlbedo.apply(a, S, cams, st, opts)
+    N = I.numel()
+    loss = ((I.double() - T.double()) ** 2).sum() / N
+    loss.backward()
+    g_gpu = a.grad.cpu().numpy().astype(np.float64)
+    # oracle FP64 gradient of the same loss at the same albedo (target from the GPU image
+    # would mix precisions; use the oracle's own target image)
+    o = oracle.OracleScene(scene)
+    o.set_albedo(tgt_alb.astype(np.float64))
+    T_or, _, _ = o.render(cams, st)
+    o.set_albedo(alb.astype(np.float64))
+    I_or, fl, _ = o.render(cams, st)
+    g_or, _, taint = o.grad(cams, st, 2 * (I_or - T_or) / N)
+    faces = _fd_faces(rng, g_or, taint)
+    assert faces.size >= 32
+    rel = np.abs(g_gpu[faces] - g_or[faces]) / np.abs(g_or[faces])
+    log(f"  adjoint vs oracle: max rel {rel.max():.2e} over {faces.size} faces")
+    assert (rel <= 1e-3).all()
+    # GPU central differences on the same faces
+    h = 1e-2
+
+    def loss_at(av):
+        with torch.no_grad():
+            Iv = RenderAlbedo.apply(torch.from_numpy(av).cuda(), S, cams, st, opts)
+            return float(((Iv.double() - T.double()) ** 2).sum() / N)
+
+    worst = 0.0
+    for f in faces[:16]:
+        ap = alb.copy()
+        am = alb.copy()
+        ap[f] += h
+        am[f] -= h
+        fd = (loss_at(ap) - loss_at(am)) / (2 * h)
+        worst = max(worst, abs(fd - g_gpu[f]) / abs(g_gpu[f]))
+    log(f"  adjoint vs GPU finite differences: max rel {worst:.2e}")
+    assert worst <= 1e-3
+
+
+def test_render_argument_errors():
+    import torch
+    scene, cams, st = sg.config1(n_inst=10)
+    S = rtq.Scene(scene)
+    bad = sg.RenderSettings(spp=1, depth=0)
+    with pytest.raises(rtq.RtqError):
+        rtq.render(S, cams, bad)
+    bad = sg.RenderSettings(spp=0, depth=2)
+    with pytest.raises(rtq.RtqError):
+        rtq.render(S, cams, bad)
+    with pytest.raises(rtq.RtqError):
+        rtq.render(S, [sg.Camera((0, 0, 0), (0, 0, 0), (0, 0, 1), 40.0, 8, 8)], st)
+    with pytest.raises(rtq.RtqError):
+        rtq.render(S, cams, sg.RenderSettings(spp=1, depth=17))
