@@ -98,7 +98,8 @@ typedef struct {
  * synchronizes the device it builds on.
  * Errors: INVALID_ARG (NULL pointer, n_quads < 1, vertex index out of range,
  * non-finite vertex or transform, proto index out of range), SINGULAR_XFORM,
- * LIMIT (more than 2^28 quads in one prototype or 2^31 nodes), OOM, HIP.
+ * LIMIT (more than 2^28 unique quads or instances, 2^31 nodes, or BVHs deeper
+ * than the traversal stack allows), OOM, HIP.
  */
 int rtq_scene_build(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
                     const rtq_build_opts* opts, rtq_scene** out);
@@ -142,7 +143,7 @@ typedef struct {
 typedef struct {
   int32_t node_format; /* RTQ_NODE_FP32 or RTQ_NODE_Q8; 0 = Q8 if built, else FP32 */
   int32_t scheduler;   /* RTQ_SCHED_* */
-  int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 24 */
+  int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 16 */
   int32_t block;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
   int32_t waves_per_cu;/* persistent scheduler: resident waves per CU; 0 = 16 */
   int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 16 */
@@ -191,6 +192,15 @@ typedef struct {
   uint64_t* view_done; /* optional device [n_cams]: wall-clock tick at which each
                           view's last path finished (persistent scheduler only) */
   uint64_t* start_tick;/* optional device [1]: wall-clock tick at kernel start */
+  uint64_t* visits;    /* optional device [4]: top-level nodes, instances entered,
+                          bottom-level nodes and quads tested, summed over every
+                          ray (accumulated; selects a slower counting variant) */
+  float* dump_rays;    /* optional device 8 x dump_cap floats, structure of arrays
+                          (ox, oy, oz, dx, dy, dz, tmin, tmax): extension rays of
+                          bounce >= 1, plain scheduler only */
+  int64_t dump_cap;    /* capacity of dump_rays in rays */
+  uint64_t* dump_count;/* device [1]: rays appended to dump_rays (accumulated; the
+                          count may exceed dump_cap, rays beyond it are dropped) */
 } rtq_render_opts;
 
 /*

@@ -80,7 +80,8 @@ class _RenderOpts(ctypes.Structure):
                 ("E", ctypes.c_float), ("L_sky", ctypes.c_float), ("node_format", ctypes.c_int32),
                 ("scheduler", ctypes.c_int32), ("stack_depth", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32), ("counters", ctypes.c_void_p),
-                ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p)]
+                ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
+                ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -286,7 +287,7 @@ def camera_structs(cams) -> tuple:
 
 
 def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
-                counters=None, view_done=None, start_tick=None):
+                counters=None, view_done=None, start_tick=None, visits=None, dump_rays=None, dump_count=None):
     o = _RenderOpts()
     o.seed = int(settings.seed)
     o.frame = int(settings.frame)
@@ -302,6 +303,10 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.counters = _ptr(counters)
     o.view_done = _ptr(view_done)
     o.start_tick = _ptr(start_tick)
+    o.visits = _ptr(visits)
+    o.dump_rays = _ptr(dump_rays)
+    o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 8
+    o.dump_count = _ptr(dump_count)
     return o
 
 

@@ -217,17 +217,23 @@ int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32
   Prepared p;
   int rc = prepare(s, cams, n_cams, spp, depth, opts, plain, stream, &p);
   if (rc) return rc;
+  if (opts->dump_rays && (opts->dump_cap < 1 || !opts->dump_count))
+    return set_error(RTQ_E_INVALID_ARG, "dump_rays needs dump_cap >= 1 and dump_count");
   const SceneView sv = scene_view(s, p.fmt);
+  RenderExtras ex;
+  ex.counters = reinterpret_cast<unsigned long long*>(opts->counters);
+  ex.visits = reinterpret_cast<unsigned long long*>(opts->visits);
+  ex.dump = opts->dump_rays;
+  ex.dump_cap = opts->dump_cap;
+  ex.dump_count = reinterpret_cast<unsigned long long*>(opts->dump_count);
+  ex.view_done = reinterpret_cast<unsigned long long*>(opts->view_done);
+  ex.start_tick = reinterpret_cast<unsigned long long*>(opts->start_tick);
   hipError_t e;
   if (plain) {
     RenderScratch* r = scratch_of(const_cast<rtq_scene*>(s));
-    e = launch_render_plain(sv, p.rp, r->pb, p.fmt, p.tl.stack_depth, p.tl.block, images, p.n_pixels,
-                            reinterpret_cast<unsigned long long*>(opts->counters), stream);
+    e = launch_render_plain(sv, p.rp, r->pb, p.fmt, p.tl.stack_depth, p.tl.block, images, p.n_pixels, ex, stream);
   } else {
-    e = launch_render_persistent(sv, p.rp, p.fmt, p.tl, images, p.n_pixels,
-                                 reinterpret_cast<unsigned long long*>(opts->counters),
-                                 reinterpret_cast<unsigned long long*>(opts->view_done),
-                                 reinterpret_cast<unsigned long long*>(opts->start_tick), stream);
+    e = launch_render_persistent(sv, p.rp, p.fmt, p.tl, images, p.n_pixels, ex, stream);
   }
   return e == hipSuccess ? RTQ_OK : hip_error(e, "render launch");
 }

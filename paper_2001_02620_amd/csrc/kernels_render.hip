@@ -34,6 +34,30 @@ __device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter) {
   return base + rank;
 }
 
+// Sum per-lane visit counters over the wave; one atomic per counter per wave.
+// Must be reached by every lane of the wave.
+__device__ __forceinline__ void wave_add_visits(const VisitCounters& vc, unsigned long long* visits) {
+  unsigned long long v[4] = {vc.tlas, vc.inst, vc.blas, vc.quads};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    unsigned long long x = v[k];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&visits[k], x);
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_append64(bool want, unsigned long long* counter) {
+  const unsigned long long m = __ballot(want);
+  if (m == 0ull) return 0ull;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0ull;
+  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+  const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  return (((unsigned long long)hi << 32) | lo) + rank;
+}
+
 // ---------------------------------------------------------------- plain scheduler
 __global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
   const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -57,46 +81,50 @@ __global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
 
 // Closest hit (ANY = false) of an extension queue, or occlusion (ANY = true) of a
 // shadow queue, one lane per entry.
-template <int FMT, bool ANY>
+template <int FMT, bool ANY, bool COUNT>
 __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq, const uint32_t* count,
-                              QueueHits qh, uint8_t* occ, int depth) {
+                              QueueHits qh, uint8_t* occ, int depth, unsigned long long* visits) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
   uint2 spill[kStackTotal];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)*count) return;
-  Lane L;
+  const bool live = i < (int64_t)*count;
   VisitCounters vc{0, 0, 0, 0};
-  bool ok;
-  if (ANY) {
-    ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
-    L.ex_rec = sq.ex_rec[i];
-    const uint32_t e = sq.ex_qh[i];
-    L.ex_quad = e & 0x7FFFFFFFu;
-    L.ex_half = e >> 31;
-    L.any = true;
-  } else {
-    ok = lane_init(L, sc, eq.ox[i], eq.oy[i], eq.oz[i], eq.dx[i], eq.dy[i], eq.dz[i], 0.0f, kInfF);
-    L.ex_rec = eq.ex_rec[i];
-    const uint32_t e = eq.ex_qh[i];
-    L.ex_quad = e == kEmpty ? kEmpty : (e & 0x7FFFFFFFu);
-    L.ex_half = e == kEmpty ? 0u : (e >> 31);
-  }
-  if (ok)
-    while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+  if (live) {
+    Lane L;
+    bool ok;
+    if (ANY) {
+      ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+      L.ex_rec = sq.ex_rec[i];
+      const uint32_t e = sq.ex_qh[i];
+      L.ex_quad = e & 0x7FFFFFFFu;
+      L.ex_half = e >> 31;
+      L.any = true;
+    } else {
+      ok = lane_init(L, sc, eq.ox[i], eq.oy[i], eq.oz[i], eq.dx[i], eq.dy[i], eq.dz[i], 0.0f, kInfF);
+      L.ex_rec = eq.ex_rec[i];
+      const uint32_t e = eq.ex_qh[i];
+      L.ex_quad = e == kEmpty ? kEmpty : (e & 0x7FFFFFFFu);
+      L.ex_half = e == kEmpty ? 0u : (e >> 31);
     }
-  if (ANY) {
-    occ[i] = L.b_rec != kEmpty ? 1 : 0;
-  } else {
-    qh.t[i] = L.t_best;
-    qh.rec[i] = L.b_rec;
-    qh.qh[i] = L.b_rec == kEmpty ? kEmpty : (L.b_quad | (L.b_half << 31));
+    if (ok)
+      while (!lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
+      }
+    if (ANY) {
+      occ[i] = L.b_rec != kEmpty ? 1 : 0;
+    } else {
+      qh.t[i] = L.t_best;
+      qh.rec[i] = L.b_rec;
+      qh.qh[i] = L.b_rec == kEmpty ? kEmpty : (L.b_quad | (L.b_half << 31));
+    }
   }
+  if (COUNT) wave_add_visits(vc, visits);
 }
 
 __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const uint32_t* count_in, QueueHits qh,
-                        ExtQueue out, uint32_t* count_out, ShadowQueue sq, uint32_t* count_sq) {
+                        ExtQueue out, uint32_t* count_out, ShadowQueue sq, uint32_t* count_sq, float* dump,
+                        long long dump_cap, unsigned long long* dump_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < (int64_t)*count_in;
   bool want_shadow = false, want_next = false;
@@ -149,6 +177,20 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     out.beta[jn] = beta_next;
     out.ex_rec[jn] = rec;
     out.ex_qh[jn] = qhv;
+  }
+  if (dump) {  // keep a copy of the incoherent (bounce >= 1) extension rays
+    const unsigned long long jd = wave_append64(want_next, dump_count);
+    if (want_next && jd < (unsigned long long)dump_cap) {
+      const size_t c = (size_t)dump_cap;
+      dump[0 * c + jd] = s.px;
+      dump[1 * c + jd] = s.py;
+      dump[2 * c + jd] = s.pz;
+      dump[3 * c + jd] = ndx;
+      dump[4 * c + jd] = ndy;
+      dump[5 * c + jd] = ndz;
+      dump[6 * c + jd] = 0.0f;
+      dump[7 * c + jd] = kInfF;
+    }
   }
 }
 
@@ -207,10 +249,10 @@ struct PathLane {
   bool shadow, have_next;
 };
 
-template <int FMT, bool TS>
+template <int FMT, bool TS, bool COUNT>
 __global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
                                     unsigned long long* counter, unsigned long long* counters,
-                                    unsigned long long* view_done) {
+                                    unsigned long long* view_done, unsigned long long* visits) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S{lds + (threadIdx.x >> 6) * depth_lds * 64, depth_lds, lane};
@@ -258,7 +300,7 @@ __global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds
     }
     if (has) {
       for (;;) {
-        const bool fin = pending_done || lane_step<FMT, false>(L, sc, S, spill, vc);
+        const bool fin = pending_done || lane_step<FMT, COUNT>(L, sc, S, spill, vc);
         pending_done = false;
         if (fin) {
           bool path_done = false;
@@ -319,6 +361,7 @@ __global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds
       }
     }
   }
+  if (COUNT) wave_add_visits(vc, visits);
   if (counters) {
     // wave reduction, one atomic per counter per wave
     unsigned long long v[4] = {n_ext, n_sh, n_inc, n_paths};
@@ -411,63 +454,78 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
-                               int stack_depth, int block, float* image, int64_t n_pixels,
-                               unsigned long long* counters, hipStream_t s) {
+template <int FMT, bool COUNT>
+static void plain_bounce(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int b, int stack_depth,
+                         int block, const RenderExtras& ex, hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
+  const unsigned gt = blocks(rp.n_paths, block);
   const size_t lds = (size_t)block * stack_depth * sizeof(uint2);
+  const ExtQueue& qin = pb.q[b & 1];
+  const ExtQueue& qout = pb.q[(b + 1) & 1];
+  uint32_t* cin = pb.counts + b;
+  uint32_t* cout = pb.counts + b + 1;
+  uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
+  hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, cin,
+                     pb.hits, pb.occ, stack_depth, ex.visits);
+  hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
+                     ex.dump, ex.dump_cap, ex.dump_count);
+  hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, csq,
+                     pb.hits, pb.occ, stack_depth, ex.visits);
+  hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+}
+
+hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
+                               int stack_depth, int block, float* image, int64_t n_pixels, const RenderExtras& ex,
+                               hipStream_t s) {
+  const unsigned gp = blocks(rp.n_paths, 256);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, pb.counts, 2 * kMaxDepth + 2);
   hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
+  const bool cnt = ex.visits != nullptr;
   for (int b = 0; b < rp.depth; ++b) {
-    const ExtQueue& qin = pb.q[b & 1];
-    const ExtQueue& qout = pb.q[(b + 1) & 1];
-    uint32_t* cin = pb.counts + b;
-    uint32_t* cout = pb.counts + b + 1;
-    uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
-    const unsigned gt = blocks(rp.n_paths, block);
-    if (fmt == 2)
-      hipLaunchKernelGGL((k_trace_queue<2, false>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, cin, pb.hits,
-                         pb.occ, stack_depth);
-    else
-      hipLaunchKernelGGL((k_trace_queue<1, false>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, cin, pb.hits,
-                         pb.occ, stack_depth);
-    hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq);
-    if (fmt == 2)
-      hipLaunchKernelGGL((k_trace_queue<2, true>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, csq, pb.hits,
-                         pb.occ, stack_depth);
-    else
-      hipLaunchKernelGGL((k_trace_queue<1, true>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, csq, pb.hits,
-                         pb.occ, stack_depth);
-    hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+    if (fmt == 2) {
+      if (cnt) plain_bounce<2, true>(sc, rp, pb, b, stack_depth, block, ex, s);
+      else plain_bounce<2, false>(sc, rp, pb, b, stack_depth, block, ex, s);
+    } else {
+      if (cnt) plain_bounce<1, true>(sc, rp, pb, b, stack_depth, block, ex, s);
+      else plain_bounce<1, false>(sc, rp, pb, b, stack_depth, block, ex, s);
+    }
   }
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
-  if (counters)
-    hipLaunchKernelGGL(k_plain_stats, dim3(1), dim3(64), 0, s, pb.counts, rp.depth, rp.n_paths, counters);
+  if (ex.counters)
+    hipLaunchKernelGGL(k_plain_stats, dim3(1), dim3(64), 0, s, pb.counts, rp.depth, rp.n_paths, ex.counters);
   return hipGetLastError();
 }
 
-hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
-                                    float* image, int64_t n_pixels, unsigned long long* counters,
-                                    unsigned long long* view_done, unsigned long long* start_tick, hipStream_t s) {
+template <int FMT, bool TS, bool COUNT>
+static void persistent_launch(const SceneView& sc, const RenderParams& rp, const TraceLaunch& tl,
+                              const RenderExtras& ex, hipStream_t s) {
   const size_t lds = (size_t)tl.block * tl.stack_depth * sizeof(uint2);
+  hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                     tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
+}
+
+hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
+                                    float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s) {
   hipError_t e = launch_zero_u64(tl.counter, 1, s);
   if (e != hipSuccess) return e;
-  if (start_tick) hipLaunchKernelGGL(k_start_tick, dim3(1), dim3(64), 0, s, start_tick);
-  const bool ts = view_done != nullptr;
+  if (ex.start_tick) hipLaunchKernelGGL(k_start_tick, dim3(1), dim3(64), 0, s, ex.start_tick);
+  const bool ts = ex.view_done != nullptr, cnt = ex.visits != nullptr;
   if (fmt == 2) {
-    if (ts)
-      hipLaunchKernelGGL((k_render_persistent<2, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
-    else
-      hipLaunchKernelGGL((k_render_persistent<2, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
+    if (cnt) {
+      if (ts) persistent_launch<2, true, true>(sc, rp, tl, ex, s);
+      else persistent_launch<2, false, true>(sc, rp, tl, ex, s);
+    } else {
+      if (ts) persistent_launch<2, true, false>(sc, rp, tl, ex, s);
+      else persistent_launch<2, false, false>(sc, rp, tl, ex, s);
+    }
   } else {
-    if (ts)
-      hipLaunchKernelGGL((k_render_persistent<1, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
-    else
-      hipLaunchKernelGGL((k_render_persistent<1, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                         tl.stack_depth, tl.refill, tl.counter, counters, view_done);
+    if (cnt) {
+      if (ts) persistent_launch<1, true, true>(sc, rp, tl, ex, s);
+      else persistent_launch<1, false, true>(sc, rp, tl, ex, s);
+    } else {
+      if (ts) persistent_launch<1, true, false>(sc, rp, tl, ex, s);
+      else persistent_launch<1, false, false>(sc, rp, tl, ex, s);
+    }
   }
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
   return hipGetLastError();

@@ -42,12 +42,22 @@ struct PlainBuffers {
   uint32_t* counts;  // [0, kMaxDepth]: extension queue sizes; [kMaxDepth + 1, ...): shadow queue sizes
 };
 
+// Optional instrumentation of a render call.
+struct RenderExtras {
+  unsigned long long* counters;    // [4] closest, shadow, incoherent rays, paths
+  unsigned long long* visits;      // [4] top nodes, instances, bottom nodes, quads
+  float* dump;                     // 8 x dump_cap SoA
+  long long dump_cap;
+  unsigned long long* dump_count;
+  unsigned long long* view_done;
+  unsigned long long* start_tick;
+};
+
 hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
-                               int stack_depth, int block, float* image, int64_t n_pixels,
-                               unsigned long long* counters, hipStream_t s);
+                               int stack_depth, int block, float* image, int64_t n_pixels, const RenderExtras& ex,
+                               hipStream_t s);
 hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
-                                    float* image, int64_t n_pixels, unsigned long long* counters,
-                                    unsigned long long* view_done, unsigned long long* start_tick, hipStream_t s);
+                                    float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s);
 hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
                           const float* grad_img, float* grad_albedo, hipStream_t s);
 
