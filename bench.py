@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--incoherent-rays", type=int, default=16_000_000)
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
     ap.add_argument("--profile", action="store_true", help="only the timed quantized-persistent frames")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU: this build has no multi-GPU path "
@@ -91,6 +93,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(2 ** 28, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied 5 x 1 GiB")
+        return
     t0 = time.time()
     scene, cams, st = sg.config2(scale=args.scale)
     log(f"scene: {scene.n_quads} unique quads, {scene.n_instances} instances, "
