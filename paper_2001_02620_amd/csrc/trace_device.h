@@ -69,7 +69,8 @@ struct Lane {
   float b_u, b_v;
   // exclusion (spawning triangle) as (record, leaf-ordered quad, half)
   uint32_t ex_rec, ex_quad, ex_half;
-  bool any;  // any-hit query: stop at the first accepted hit
+  bool any;   // any-hit query: stop at the first accepted hit
+  bool done;  // traversal finished
 };
 
 __device__ __forceinline__ float rcp_exact(float d) { return 1.0f / d; }
@@ -389,65 +390,110 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   L.inst_id = kEmpty;
   L.cur = 0u;  // TLAS root
   L.any = false;
+  L.done = false;
   const bool finite = __builtin_isfinite(ox) && __builtin_isfinite(oy) && __builtin_isfinite(oz) &&
                       __builtin_isfinite(dx) && __builtin_isfinite(dy) && __builtin_isfinite(dz) &&
                       !(dx == 0.0f && dy == 0.0f && dz == 0.0f) && !(tmin != tmin) && !(tmax != tmax);
   if (!finite || sc.n_inst == 0u) {
     L.cur = kEmpty;
+    L.done = true;
     return false;
   }
   set_world_box_ray(L, sc.pad_rel);
   return true;
 }
 
-// One traversal step.  Returns true when the lane's traversal is complete.
-template <int FMT, bool COUNT>
-__device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
-                                          VisitCounters& vc) {
-  using Codec = NodeCodec<FMT>;
-  if (L.cur == kEmpty) {
+// Resolve an empty current reference: leave the instance when its subtree is
+// exhausted, pop the next entry whose entry distance is not behind the closest
+// hit, or finish.
+__device__ __forceinline__ void advance(Lane& L, const SceneView& sc, const Stack& S, const uint2* spill) {
+  while (L.cur == kEmpty) {
     if (L.inst_sp >= 0 && L.sp == L.inst_sp) {  // leave the instance
       L.inst_sp = -1;
       set_world_box_ray(L, sc.pad_rel);
-      return false;
     }
-    if (L.sp == 0) return true;
+    if (L.sp == 0) {
+      L.done = true;
+      return;
+    }
     const uint2 e = pop(L, S, spill);
     if (__uint_as_float(e.y) <= L.t_cull) L.cur = e.x;
-    return false;
   }
-  if (!ref_is_leaf(L.cur)) {
-    float tn[4];
-    uint32_t ch[4];
-    const bool top = L.inst_sp < 0;
-    if (COUNT) {
-      if (top) ++vc.tlas;
-      else ++vc.blas;
-    }
-    Codec::test(L, top ? sc.tlas : sc.blas, L.cur, L.t_cull, tn, ch);
-    // near-first: sort the four (t, ref) pairs, continue with the nearest
-    cswap(tn[0], ch[0], tn[1], ch[1]);
-    cswap(tn[2], ch[2], tn[3], ch[3]);
-    cswap(tn[0], ch[0], tn[2], ch[2]);
-    cswap(tn[1], ch[1], tn[3], ch[3]);
-    cswap(tn[1], ch[1], tn[2], ch[2]);
-    if (tn[3] < kInfF) push(L, S, spill, ch[3], tn[3]);
-    if (tn[2] < kInfF) push(L, S, spill, ch[2], tn[2]);
-    if (tn[1] < kInfF) push(L, S, spill, ch[1], tn[1]);
-    L.cur = tn[0] < kInfF ? ch[0] : kEmpty;
-    return false;
+}
+
+// Node step: test the four children, continue with the nearest, push the others
+// (farthest first) with their entry distances.
+template <int FMT, bool COUNT>
+__device__ __forceinline__ void node_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
+                                          VisitCounters& vc) {
+  float tn[4];
+  uint32_t ch[4];
+  const bool top = L.inst_sp < 0;
+  if (COUNT) {
+    if (top) ++vc.tlas;
+    else ++vc.blas;
   }
-  if (L.inst_sp < 0) {  // top-level leaf: enter the instance
-    if (COUNT) ++vc.inst;
-    uint32_t root;
-    enter_instance(L, sc.inst, leaf_first(L.cur), &root);
-    L.inst_sp = L.sp;
-    L.cur = root;
-    return false;
+  NodeCodec<FMT>::test(L, top ? sc.tlas : sc.blas, L.cur, L.t_cull, tn, ch);
+  cswap(tn[0], ch[0], tn[1], ch[1]);
+  cswap(tn[2], ch[2], tn[3], ch[3]);
+  cswap(tn[0], ch[0], tn[2], ch[2]);
+  cswap(tn[1], ch[1], tn[3], ch[3]);
+  cswap(tn[1], ch[1], tn[2], ch[2]);
+  if (tn[3] < kInfF) push(L, S, spill, ch[3], tn[3]);
+  if (tn[2] < kInfF) push(L, S, spill, ch[2], tn[2]);
+  if (tn[1] < kInfF) push(L, S, spill, ch[1], tn[1]);
+  L.cur = tn[0] < kInfF ? ch[0] : kEmpty;
+  advance(L, sc, S, spill);
+}
+
+// Instance step: a top-level leaf -- transform the ray and descend into the
+// prototype's bottom-level root.
+template <bool COUNT>
+__device__ __forceinline__ void inst_step(Lane& L, const SceneView& sc, VisitCounters& vc) {
+  if (COUNT) ++vc.inst;
+  uint32_t root;
+  enter_instance(L, sc.inst, leaf_first(L.cur), &root);
+  L.inst_sp = L.sp;
+  L.cur = root;
+}
+
+// Quad step: test the first quad of the current bottom-level leaf.
+template <bool COUNT>
+__device__ __forceinline__ void quad_step(Lane& L, const SceneView& sc, const Stack& S, const uint2* spill,
+                                          VisitCounters& vc) {
+  const uint32_t first = leaf_first(L.cur), count = leaf_count(L.cur);
+  if (leaf_quads<COUNT>(L, sc, first, 1u, &vc.quads)) {  // any-hit query answered
+    L.cur = kEmpty;
+    L.done = true;
+    return;
   }
-  const bool found = leaf_quads<COUNT>(L, sc, leaf_first(L.cur), leaf_count(L.cur), &vc.quads);
-  L.cur = kEmpty;
-  return found;
+  L.cur = count > 1u ? make_leaf(first + 1u, count - 1u) : kEmpty;
+  advance(L, sc, S, spill);
+}
+
+// One traversal step of the wave.  The lanes that take part vote: the wave runs
+// only the step kind (node test, instance entry or quad test) that most of them
+// need, the others wait.  Running one kind per iteration avoids paying for
+// every branch whenever any lane needs it.  Returns true once this lane is done.
+template <int FMT, bool COUNT>
+__device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
+                                          VisitCounters& vc) {
+  if (L.cur == kEmpty && !L.done) advance(L, sc, S, spill);
+  const bool leaf = ref_is_leaf(L.cur);
+  const bool want_node = !L.done && !leaf;
+  const bool want_inst = !L.done && leaf && L.inst_sp < 0;
+  const bool want_quad = !L.done && leaf && L.inst_sp >= 0;
+  const int cn = __popcll(__ballot(want_node));
+  const int ci = __popcll(__ballot(want_inst));
+  const int cq = __popcll(__ballot(want_quad));
+  if (cn >= ci && cn >= cq) {
+    if (want_node) node_step<FMT, COUNT>(L, sc, S, spill, vc);
+  } else if (cq >= ci) {
+    if (want_quad) quad_step<COUNT>(L, sc, S, spill, vc);
+  } else {
+    if (want_inst) inst_step<COUNT>(L, sc, vc);
+  }
+  return L.done;
 }
 
 }  // namespace rtq
