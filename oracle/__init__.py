@@ -63,7 +63,8 @@ def lib():
         L.orc_trace.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.orc_trace_d.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P, P, P, P]
         L.orc_render.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, P, P]
-        L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P]
+        L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P, i32]
+        L.orc_path.argtypes = [P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -188,9 +189,12 @@ class OracleScene:
         stats = dict(closest=st[0], shadow=st[1], incoherent=st[2], flagged_pixels=st[3])
         return img, fl, stats
 
-    def grad(self, cams, settings, gpix: np.ndarray, pixels: Optional[np.ndarray] = None, brute: bool = False):
+    def grad(self, cams, settings, gpix: np.ndarray, pixels: Optional[np.ndarray] = None, brute: bool = False,
+             taint: str = "pixel"):
         """Path-replay gradient of sum_p gpix[p] * I_p w.r.t. per-face albedo.
-        Returns (grad [Q] f64, pixel flags, face tainted-by-flagged-path mask)."""
+        Returns (grad [Q] f64, pixel flags, tainted-face mask).  taint="pixel" marks
+        every face on any path of a flagged pixel; taint="path" only the faces on
+        flagged paths (valid when both sides use these same pixel weights)."""
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
@@ -199,10 +203,11 @@ class OracleScene:
         assert g.shape == (n,)
         out = np.zeros(self.n_quads)
         fl = np.zeros(n, np.uint8)
-        taint = np.zeros(self.n_quads, np.uint8)
+        tmask = np.zeros(self.n_quads, np.uint8)
         lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,
-                       0 if brute else 1, _p(g), 0, None, _p(out), None, _p(fl), _p(taint))
-        return out, fl, taint
+                       0 if brute else 1, _p(g), 0, None, _p(out), None, _p(fl), _p(tmask),
+                       1 if taint == "path" else 0)
+        return out, fl, tmask
 
     def tangent(self, cams, settings, tangent: np.ndarray, pixels: Optional[np.ndarray] = None):
         """Forward-mode (dual number) derivative of each pixel along a per-face tangent."""
@@ -215,5 +220,25 @@ class OracleScene:
         dI = np.zeros(n)
         fl = np.zeros(n, np.uint8)
         lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,
-                       1, None, 1, _p(tg), None, _p(dI), _p(fl), None)
+                       1, None, 1, _p(tg), None, _p(dI), _p(fl), None, 0)
         return dI, fl
+
+    def path(self, cams, settings, pixel: int, sample: int):
+        """The vertices of one path: list of dicts (inst, prim, half, t, albedo,
+        shadow: -1 none / 0 visible / 1 occluded, flags, shadow_flags), escaped, path flags."""
+        cf, ci, _ = self._cams(cams)
+        pi, pu, pd = self._params(settings)
+        nv = np.zeros(1, np.int32)
+        oi = np.zeros(6 * 64, np.int32)
+        od = np.zeros(2 * 64)
+        esc = np.zeros(1, np.int32)
+        pf = np.zeros(1, np.uint32)
+        lib().orc_path(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), int(pixel), int(sample), _p(nv),
+                       _p(oi), _p(od), _p(esc), _p(pf))
+        verts = []
+        for k in range(int(nv[0])):
+            verts.append(dict(inst=int(oi[6 * k]), prim=int(oi[6 * k + 1]), half=int(oi[6 * k + 2]),
+                              shadow=int(oi[6 * k + 3]), flags=int(oi[6 * k + 4]) & 0xFFFFFFFF,
+                              shadow_flags=int(oi[6 * k + 5]) & 0xFFFFFFFF, t=float(od[2 * k]),
+                              albedo=float(od[2 * k + 1])))
+        return verts, bool(esc[0]), int(pf[0])

@@ -62,7 +62,7 @@ enum : uint32_t {
   F_GRAZE = 2u,        // the ray passes within the graze distance of a boundary edge
   F_NEAR_ORIGIN = 4u,  // the hit lies within the graze distance of the ray origin
   F_T_ILLCOND = 8u,    // FP32 t cannot be trusted to 1e-5 (grazing incidence)
-  F_DIAG = 16u,        // the two halves of the hit quad are within the window / graze distance
+  F_DIAG = 16u,        // the other half of the hit quad is hit within the tie window
   F_SHADE = 32u,       // render only: shading decision within rounding (n.d, n.l, n_z ~ 0)
 };
 
@@ -478,10 +478,13 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
       const double dist = seg_dist(r.o, r.d, r.tmin, t_end, w[E[e][0]], w[E[e][1]], &q);
       if (dist < 1e-6 * std::max(Sq, maxabs(q)) + r0) out.flags |= F_GRAZE;
     }
-    if (same) {
+    {
+      // the diagonal v1-v3 is a real boundary too: the two halves of a non-planar
+      // quad overlap in projection on one side of it and leave an uncovered sliver
+      // on the other, so a ray grazing it may hit this quad or miss it entirely
       V3 q;
       const double dist = seg_dist(r.o, r.d, r.tmin, t_end, w[1], w[3], &q);
-      if (dist < 1e-6 * std::max(Sq, maxabs(q)) + r0) out.flags |= F_DIAG;
+      if (dist < 1e-6 * std::max(Sq, maxabs(q)) + r0) out.flags |= F_GRAZE;
     }
   });
   if (any_hit) out.flags &= ~(uint32_t)(F_NEAR_TIE | F_DIAG | F_T_ILLCOND);
@@ -544,6 +547,10 @@ struct Vertex {
   int64_t face;
   double a;      // albedo at the vertex
   double c;      // (E / pi) * cos_L * visibility: the NEE factor without beta and albedo
+  int32_t inst, prim, half;  // the hit
+  double t;
+  uint32_t flags, shadow_flags;
+  int32_t shadow;  // -1 no shadow ray, 0 visible, 1 occluded
 };
 struct PathRec {
   int nv = 0;
@@ -586,17 +593,28 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
     const double a = S.albedo[face];
-    Vertex vx{face, a, 0.0};
+    Vertex vx{face, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
     const double cl = dot(n, L);
     if (std::fabs(cl) < 1e-6) rec.flags |= F_SHADE;
-    // origin uncertainty of rays leaving p: FP32 position error amplified by the incidence angle
-    const double r1 = 16.0 * std::ldexp(1.0, -24) * h.S / std::max(h.cos_abs, 1e-3);
+    // origin uncertainty of rays leaving p: the FP32 position error of this hit
+    // plus the incoming ray's own origin uncertainty, both stretched along the
+    // surface by the incidence angle
+    const double r1 = (16.0 * std::ldexp(1.0, -24) * h.S + r0) / std::max(h.cos_abs, 1e-3);
     const Excl here{h.best.inst, h.best.prim, h.best.half};
+    vx.inst = h.best.inst;
+    vx.prim = h.best.prim;
+    vx.half = h.best.half;
+    vx.t = h.best.t;
+    vx.flags = h.flags;
+    vx.shadow = -1;
+    vx.shadow_flags = 0;
     if (cl > 0) {
       Ray sr{p, L, 0.0, kInf};
       TraceOut o = trace_one(S, sr, here, r1, mode, true);
       rec.n_shadow++;
       rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
+      vx.shadow = o.best.inst >= 0 ? 1 : 0;
+      vx.shadow_flags = o.flags;
       if (o.best.inst < 0) vx.c = P.E / kPi * cl;
     }
     rec.v[rec.nv++] = vx;
@@ -840,6 +858,33 @@ void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_ca
     }
 }
 
+// One path, vertex by vertex (debugging and tests): per hit k < *nv writes
+// out_i[6k..6k+5] = (inst, prim, half, shadow state, flags, shadow flags) and
+// out_d[2k..2k+1] = (t, albedo); *escaped = 1 if the path left the scene.
+void orc_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
+              const uint64_t* pu, const double* pd, int64_t g, int32_t sample, int32_t* nv, int32_t* out_i,
+              double* out_d, int32_t* escaped, uint32_t* path_flags) {
+  const Scene& S = *static_cast<Scene*>(s);
+  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  std::vector<Cam> cams;
+  for (int c = 0; c < n_cams; ++c) cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
+  int32_t view;
+  int64_t p;
+  resolve_pixel(cams, g, &view, &p);
+  PathRec rec;
+  trace_path(S, P, cams[view], view, p, sample, 1, rec);
+  *nv = rec.nv;
+  for (int k = 0; k < rec.nv; ++k) {
+    const Vertex& v = rec.v[k];
+    const int32_t vals[6] = {v.inst, v.prim, v.half, v.shadow, (int32_t)v.flags, (int32_t)v.shadow_flags};
+    for (int j = 0; j < 6; ++j) out_i[6 * k + j] = vals[j];
+    out_d[2 * k] = v.t;
+    out_d[2 * k + 1] = v.a;
+  }
+  *escaped = rec.escaped ? 1 : 0;
+  *path_flags = rec.flags;
+}
+
 // Gradient of sum_p g_p * I_p with respect to per-face albedo, paths held fixed.
 // mode 0: path replay, dI/da_f = (1/spp) sum_s sum_{k: f_k = f} S_k / a_k with
 //         S_k = sum_{j >= k} D_j + M (contributions from vertex k onward).
@@ -848,7 +893,7 @@ void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_ca
 void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
               const uint64_t* pu, const double* pd, const int64_t* pix, int64_t n_pix, int32_t mode,
               const double* gpix, int32_t grad_mode, const double* tangent, double* grad_albedo, double* dI,
-              uint8_t* pflags, uint8_t* face_tainted) {
+              uint8_t* pflags, uint8_t* face_tainted, int32_t taint_per_path) {
   const Scene& S = *static_cast<Scene*>(s);
   Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
   std::vector<Cam> cams;
@@ -874,7 +919,8 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
       PathRec rec;
       trace_path(S, P, cams[view], view, p, smp, mode, rec);
       fl |= rec.flags;
-      for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].face);
+      if (!taint_per_path || rec.flags)
+        for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].face);
       if (grad_mode == 0) {
         // D_k = beta_k a_k c_k; S_k = sum_{j>=k} D_j + M.  Accumulate S_k / a_k.
         std::vector<double> beta(rec.nv + 1, 1.0);
@@ -903,8 +949,10 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
         dsum += dL;
       }
     }
-    // a flagged pixel's value may differ on the GPU, and it weights the gradient of
-    // every face on every path through the pixel: all of those faces are tainted
+    // per pixel: a flagged pixel's value may differ on the GPU, and it weights the
+    // gradient of every face on every path through the pixel, so all of them are
+    // tainted.  Per path (when both sides use the same pixel weights): only the
+    // faces on flagged paths.
     if (face_tainted && fl)
       for (int64_t f : faces) taint[tid][f] = 1;
     if (grad_mode == 1) dI[i] = dsum / P.spp;
