@@ -139,6 +139,7 @@ typedef struct {
 
 #define RTQ_SCHED_PLAIN 0      /* one ray per lane for its whole traversal */
 #define RTQ_SCHED_PERSISTENT 1 /* resident waves refill finished lanes from a shared ray counter */
+#define RTQ_SCHED_MEGAKERNEL 2 /* rendering only: the whole frame in one persistent launch */
 
 typedef struct {
   int32_t node_format; /* RTQ_NODE_FP32 or RTQ_NODE_Q8; 0 = Q8 if built, else FP32 */
@@ -184,20 +185,24 @@ typedef struct {
   float E;             /* light irradiance */
   float L_sky;         /* constant sky radiance */
   int32_t node_format; /* as rtq_trace_opts */
-  int32_t scheduler;   /* RTQ_SCHED_PLAIN: one kernel per stage and bounce;
-                          RTQ_SCHED_PERSISTENT: one persistent wavefront kernel */
+  int32_t scheduler;   /* RTQ_SCHED_PLAIN: wavefront of one kernel per stage and bounce
+                          (queues of extension and shadow rays), one ray per lane;
+                          RTQ_SCHED_PERSISTENT: the same wavefront with persistent,
+                          lane-refilling traversal stages;
+                          RTQ_SCHED_MEGAKERNEL: one persistent launch per frame whose
+                          lanes run whole paths and are refilled with new paths */
   int32_t stack_depth, block, waves_per_cu, refill; /* as rtq_trace_opts */
   uint64_t* counters;  /* optional device [4]: closest rays, shadow rays, incoherent
                           (bounce >= 1) rays, paths; accumulated (caller zeroes) */
   uint64_t* view_done; /* optional device [n_cams]: wall-clock tick at which each
-                          view's last path finished (persistent scheduler only) */
+                          view's last path finished (megakernel scheduler only) */
   uint64_t* start_tick;/* optional device [1]: wall-clock tick at kernel start */
   uint64_t* visits;    /* optional device [4]: top-level nodes, instances entered,
                           bottom-level nodes and quads tested, summed over every
                           ray (accumulated; selects a slower counting variant) */
   float* dump_rays;    /* optional device 8 x dump_cap floats, structure of arrays
                           (ox, oy, oz, dx, dy, dz, tmin, tmax): extension rays of
-                          bounce >= 1, plain scheduler only */
+                          bounce >= 1 (plain and persistent schedulers) */
   int64_t dump_cap;    /* capacity of dump_rays in rays */
   uint64_t* dump_count;/* device [1]: rays appended to dump_rays (accumulated; the
                           count may exceed dump_cap, rays beyond it are dropped) */

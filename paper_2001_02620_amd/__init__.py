@@ -22,6 +22,7 @@ RTQ_NODE_FP32 = 1
 RTQ_NODE_Q8 = 2
 SCHED_PLAIN = 0
 SCHED_PERSISTENT = 1
+SCHED_MEGAKERNEL = 2
 
 ERRORS = {-1: "INVALID_ARG", -2: "SINGULAR_XFORM", -3: "OOM", -4: "HIP", -5: "LIMIT"}
 

@@ -92,9 +92,9 @@ int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t blo
     return set_error(RTQ_E_INVALID_ARG, "stack_depth %d outside [4, 64]", tl->stack_depth);
   if (tl->block < 64 || tl->block > 1024 || tl->block % 64)
     return set_error(RTQ_E_INVALID_ARG, "block %d must be a multiple of 64 in [64, 1024]", tl->block);
-  if ((size_t)tl->block * tl->stack_depth * 8 > (size_t)s->max_lds)
+  if ((size_t)tl->block * tl->stack_depth * kStackEntryBytes > (size_t)s->max_lds)
     return set_error(RTQ_E_INVALID_ARG, "block %d x stack_depth %d needs %d B of LDS, the device allows %d",
-                     tl->block, tl->stack_depth, tl->block * tl->stack_depth * 8, s->max_lds);
+                     tl->block, tl->stack_depth, tl->block * tl->stack_depth * kStackEntryBytes, s->max_lds);
   if (tl->refill < 1 || tl->refill > 64) return set_error(RTQ_E_INVALID_ARG, "refill %d outside [1, 64]", tl->refill);
   if (w < 1 || w > 32) return set_error(RTQ_E_INVALID_ARG, "waves_per_cu %d outside [1, 32]", w);
   const int waves_per_block = tl->block / 64;

@@ -83,6 +83,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
     RALLOC(r->pb.hits.qh, P * 4);
     RALLOC(r->pb.occ, P);
     RALLOC(r->pb.counts, (2 * kMaxDepth + 2) * sizeof(uint32_t));
+    RALLOC(r->pb.work, 2 * kMaxDepth * sizeof(unsigned long long));
   }
 #undef RALLOC
   r->paths_cap = P;
@@ -106,11 +107,13 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   if (n_cams < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one camera");
   if (spp < 1) return set_error(RTQ_E_INVALID_ARG, "spp %d < 1", spp);
   if (depth < 1 || depth > kMaxDepth) return set_error(RTQ_E_INVALID_ARG, "depth %d outside [1, %d]", depth, kMaxDepth);
-  if (opts->scheduler != RTQ_SCHED_PLAIN && opts->scheduler != RTQ_SCHED_PERSISTENT)
+  if (opts->scheduler != RTQ_SCHED_PLAIN && opts->scheduler != RTQ_SCHED_PERSISTENT &&
+      opts->scheduler != RTQ_SCHED_MEGAKERNEL)
     return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", opts->scheduler);
   int rc = resolve_format(s, opts->node_format, &out->fmt);
   if (rc) return rc;
-  rc = resolve_launch(s, opts->scheduler, opts->stack_depth, opts->block, opts->waves_per_cu, opts->refill, &out->tl);
+  rc = resolve_launch(s, opts->scheduler == RTQ_SCHED_PLAIN ? RTQ_SCHED_PLAIN : RTQ_SCHED_PERSISTENT,
+                      opts->stack_depth, opts->block, opts->waves_per_cu, opts->refill, &out->tl);
   if (rc) return rc;
   out->tl.fmt = out->fmt;
   const float L[3] = {opts->light_dir[0], opts->light_dir[1], opts->light_dir[2]};
@@ -171,6 +174,8 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
     rc = ensure_scratch(s, path_base, n_cams, plain_buffers);
     if (rc) return rc;
   }
+  if (path_base >= (int64_t)0xFFFFFFFFll)
+    return set_error(RTQ_E_LIMIT, "%lld paths per call exceed 2^32", (long long)path_base);
   RenderScratch* sc = scratch_of(s);
   const hipError_t e =
       hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);
@@ -213,9 +218,9 @@ int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32
                const rtq_render_opts* opts, float* images, hipStream_t stream) {
   if (!images) return set_error(RTQ_E_INVALID_ARG, "NULL image buffer");
   if (!opts) return set_error(RTQ_E_INVALID_ARG, "NULL options");
-  const bool plain = opts->scheduler == RTQ_SCHED_PLAIN;
+  const bool staged = opts->scheduler != RTQ_SCHED_MEGAKERNEL;
   Prepared p;
-  int rc = prepare(s, cams, n_cams, spp, depth, opts, plain, stream, &p);
+  int rc = prepare(s, cams, n_cams, spp, depth, opts, staged, stream, &p);
   if (rc) return rc;
   if (opts->dump_rays && (opts->dump_cap < 1 || !opts->dump_count))
     return set_error(RTQ_E_INVALID_ARG, "dump_rays needs dump_cap >= 1 and dump_count");
@@ -229,11 +234,11 @@ int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32
   ex.view_done = reinterpret_cast<unsigned long long*>(opts->view_done);
   ex.start_tick = reinterpret_cast<unsigned long long*>(opts->start_tick);
   hipError_t e;
-  if (plain) {
+  if (staged) {
     RenderScratch* r = scratch_of(const_cast<rtq_scene*>(s));
-    e = launch_render_plain(sv, p.rp, r->pb, p.fmt, p.tl.stack_depth, p.tl.block, images, p.n_pixels, ex, stream);
+    e = launch_render_wavefront(sv, p.rp, r->pb, p.fmt, p.tl, images, p.n_pixels, ex, stream);
   } else {
-    e = launch_render_persistent(sv, p.rp, p.fmt, p.tl, images, p.n_pixels, ex, stream);
+    e = launch_render_megakernel(sv, p.rp, p.fmt, p.tl, images, p.n_pixels, ex, stream);
   }
   return e == hipSuccess ? RTQ_OK : hip_error(e, "render launch");
 }

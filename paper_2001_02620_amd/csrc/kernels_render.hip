@@ -79,44 +79,106 @@ __global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
   rp.slots[pid] = 0.0f;
 }
 
+// Load queue entry i into a lane: an extension ray (closest hit) or a shadow
+// ray toward the light (any hit), with its spawning triangle excluded.
+template <bool ANY>
+__device__ __forceinline__ bool load_queue_ray(Lane& L, const SceneView& sc, const RenderParams& rp,
+                                               const ExtQueue& eq, const ShadowQueue& sq, int64_t i) {
+  bool ok;
+  if (ANY) {
+    ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+    L.ex_rec = sq.ex_rec[i];
+    L.ex_qh = sq.ex_qh[i];
+    L.any = true;
+  } else {
+    ok = lane_init(L, sc, eq.ox[i], eq.oy[i], eq.oz[i], eq.dx[i], eq.dy[i], eq.dz[i], 0.0f, kInfF);
+    L.ex_rec = eq.ex_rec[i];
+    L.ex_qh = eq.ex_qh[i];
+  }
+  return ok;
+}
+
+template <bool ANY>
+__device__ __forceinline__ void store_queue_result(const Lane& L, const QueueHits& qh, uint8_t* occ, int64_t i) {
+  if (ANY) {
+    occ[i] = L.b_rec != kEmpty ? 1 : 0;
+  } else {
+    qh.t[i] = L.t_best;
+    qh.rec[i] = L.b_rec;
+    qh.qh[i] = L.b_rec == kEmpty ? kEmpty : L.b_qh;
+  }
+}
+
 // Closest hit (ANY = false) of an extension queue, or occlusion (ANY = true) of a
 // shadow queue, one lane per entry.
 template <int FMT, bool ANY, bool COUNT>
 __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq, const uint32_t* count,
                               QueueHits qh, uint8_t* occ, int depth, unsigned long long* visits) {
   extern __shared__ uint2 lds[];
-  const int lane = threadIdx.x & 63;
-  const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
+  const Stack S = make_stack(lds, depth);
   uint2 spill[kStackTotal];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < (int64_t)*count;
   VisitCounters vc{0, 0, 0, 0};
   if (live) {
     Lane L;
-    bool ok;
-    if (ANY) {
-      ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
-      L.ex_rec = sq.ex_rec[i];
-      const uint32_t e = sq.ex_qh[i];
-      L.ex_quad = e & 0x7FFFFFFFu;
-      L.ex_half = e >> 31;
-      L.any = true;
-    } else {
-      ok = lane_init(L, sc, eq.ox[i], eq.oy[i], eq.oz[i], eq.dx[i], eq.dy[i], eq.dz[i], 0.0f, kInfF);
-      L.ex_rec = eq.ex_rec[i];
-      const uint32_t e = eq.ex_qh[i];
-      L.ex_quad = e == kEmpty ? kEmpty : (e & 0x7FFFFFFFu);
-      L.ex_half = e == kEmpty ? 0u : (e >> 31);
-    }
-    if (ok)
+    if (load_queue_ray<ANY>(L, sc, rp, eq, sq, i))
       while (!lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
       }
-    if (ANY) {
-      occ[i] = L.b_rec != kEmpty ? 1 : 0;
-    } else {
-      qh.t[i] = L.t_best;
-      qh.rec[i] = L.b_rec;
-      qh.qh[i] = L.b_rec == kEmpty ? kEmpty : (L.b_quad | (L.b_half << 31));
+    store_queue_result<ANY>(L, qh, occ, i);
+  }
+  if (COUNT) wave_add_visits(vc, visits);
+}
+
+// The same queue traversal as a persistent kernel: resident waves claim queue
+// entries from a counter and refill lanes whose ray has finished.
+template <int FMT, bool ANY, bool COUNT>
+__global__ void k_trace_queue_persistent(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq,
+                                         const uint32_t* count, QueueHits qh, uint8_t* occ, int depth, int refill,
+                                         unsigned long long* counter, unsigned long long* visits) {
+  extern __shared__ uint2 lds[];
+  const int lane = threadIdx.x & 63;
+  const Stack S = make_stack(lds, depth);
+  uint2 spill[kStackTotal];
+  const int64_t n = (int64_t)*count;
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  bool has = false, exhausted = n == 0;
+  int64_t idx = -1;
+  for (;;) {
+    const unsigned long long idle = __ballot(!has);
+    const int nidle = __popcll(idle);
+    if (!exhausted && (nidle >= refill || nidle == 64)) {
+      const int leader = __ffsll((long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(counter, (unsigned long long)nidle);
+      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+      base = ((unsigned long long)hi << 32) | lo;
+      if (!has) {
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+        idx = (int64_t)(base + rank);
+        if (idx < n) {
+          if (load_queue_ray<ANY>(L, sc, rp, eq, sq, idx)) has = true;
+          else store_queue_result<ANY>(L, qh, occ, idx);
+        }
+      }
+      if ((int64_t)(base + nidle) >= n) exhausted = true;
+    }
+    if (!__any(has)) {
+      if (exhausted) break;
+      continue;
+    }
+    if (has) {
+      for (;;) {
+        if (lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
+          store_queue_result<ANY>(L, qh, occ, idx);
+          has = false;
+          break;
+        }
+        if (!exhausted && __popcll(__ballot(1)) <= 64 - refill) break;
+      }
     }
   }
   if (COUNT) wave_add_visits(vc, visits);
@@ -240,27 +302,29 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 }
 
 // ---------------------------------------------------------------- persistent scheduler
+// Per-lane path state of the persistent scheduler (pixel coordinates are
+// re-derived from the path id when a bounce needs them).
 struct PathLane {
-  int64_t pid;
-  int view;
-  uint32_t pixel, sample;
+  uint32_t pid;
   int b;
   float beta, radiance, pending, beta_next, ndx, ndy, ndz;
   bool shadow, have_next;
 };
 
+// Five resident waves per SIMD: the traversal is latency bound, and five waves
+// fit with a handful of spilled registers.
 template <int FMT, bool TS, bool COUNT>
-__global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
+__global__ __attribute__((amdgpu_waves_per_eu(5))) void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
                                     unsigned long long* counter, unsigned long long* counters,
                                     unsigned long long* view_done, unsigned long long* visits) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
-  const Stack S{lds + (threadIdx.x >> 6) * depth_lds * 64, depth_lds, lane};
+  const Stack S = make_stack(lds, depth_lds);
   uint2 spill[kStackTotal];
   Lane L;
   VisitCounters vc{0, 0, 0, 0};
   PathLane P{};
-  bool has = false, exhausted = false, pending_done = false;
+  bool has = false, exhausted = false;
   uint32_t n_ext = 0, n_sh = 0, n_inc = 0, n_paths = 0;
   for (;;) {
     const unsigned long long idle = __ballot(!has);
@@ -277,17 +341,18 @@ __global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds
             __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
         const int64_t pid = (int64_t)(base + rank);
         if (pid < rp.n_paths) {
-          P.pid = pid;
-          const Ray3 r = path_camera_ray(rp, pid, &P.view, &P.pixel, &P.sample);
+          P.pid = (uint32_t)pid;
+          int view;
+          uint32_t pixel, sample;
+          const Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
           P.b = 0;
           P.beta = 1.0f;
           P.radiance = 0.0f;
           P.shadow = false;
           P.have_next = false;
           L.ex_rec = kEmpty;
-          L.ex_quad = kEmpty;
-          L.ex_half = 0u;
-          pending_done = !lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF);
+          L.ex_qh = kEmpty;
+          lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF);
           ++n_ext;
           has = true;
         }
@@ -300,62 +365,77 @@ __global__ void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds
     }
     if (has) {
       for (;;) {
-        const bool fin = pending_done || lane_step<FMT, COUNT>(L, sc, S, spill, vc);
-        pending_done = false;
-        if (fin) {
-          bool path_done = false;
-          if (!P.shadow) {
-            if (L.b_rec == kEmpty) {
-              P.radiance += P.beta * rp.L_sky;
-              path_done = true;
-            } else {
-              const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
-              const Shade s = shade_hit(sc, rp, r, L.t_best, L.b_rec, L.b_quad, L.b_half);
-              const uint32_t hrec = L.b_rec, hquad = L.b_quad, hhalf = L.b_half;
-              P.have_next = P.b < rp.depth - 1;
-              if (P.have_next) {
-                bounce_dir(rp, P.pixel, P.sample, P.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
-                P.beta_next = P.beta * s.a;
+        // vote among the traversal step kinds and "shade" (the lane's ray is
+        // finished): one kind per iteration, the most wanted
+        const int kind = step_kind(L);
+        const int cs = __popcll(__ballot(kind == 0));
+        const int ct = vote_kind(kind);
+        const int cmax = ct == 0 ? 0 : __popcll(__ballot(kind == ct));
+        if (cs > 0 && cs >= cmax) {
+          if (kind == 0) {
+            bool path_done = false;
+            if (!P.shadow) {
+              if (L.b_rec == kEmpty) {
+                P.radiance += P.beta * rp.L_sky;
+                path_done = true;
+              } else {
+                const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
+                const uint32_t hrec = L.b_rec, hqh = L.b_qh;
+                const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31);
+                P.have_next = P.b < rp.depth - 1;
+                if (P.have_next) {
+                  int view;
+                  uint32_t pixel, sample;
+                  path_coords(rp, (int64_t)P.pid, &view, &pixel, &sample);
+                  bounce_dir(rp, pixel, sample, view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
+                  P.beta_next = P.beta * s.a;
+                }
+                L.ex_rec = hrec;
+                L.ex_qh = hqh;
+                if (s.cosl > 0.0f) {
+                  P.pending = nee_term(P.beta, s.a, s.cosl, rp);
+                  P.shadow = true;
+                  lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+                  L.any = true;
+                  ++n_sh;
+                } else if (P.have_next) {
+                  P.beta = P.beta_next;
+                  ++P.b;
+                  lane_init(L, sc, s.px, s.py, s.pz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
+                  ++n_ext;
+                  ++n_inc;
+                } else {
+                  path_done = true;
+                }
               }
-              L.ex_rec = hrec;
-              L.ex_quad = hquad;
-              L.ex_half = hhalf;
-              if (s.cosl > 0.0f) {
-                P.pending = nee_term(P.beta, s.a, s.cosl, rp);
-                P.shadow = true;
-                pending_done = !lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
-                L.any = true;
-                ++n_sh;
-              } else if (P.have_next) {
+            } else {
+              if (L.b_rec == kEmpty) P.radiance += P.pending;
+              P.shadow = false;
+              if (P.have_next) {
                 P.beta = P.beta_next;
                 ++P.b;
-                pending_done = !lane_init(L, sc, s.px, s.py, s.pz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
+                lane_init(L, sc, L.wox, L.woy, L.woz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
                 ++n_ext;
                 ++n_inc;
               } else {
                 path_done = true;
               }
             }
-          } else {
-            if (L.b_rec == kEmpty) P.radiance += P.pending;
-            P.shadow = false;
-            if (P.have_next) {
-              P.beta = P.beta_next;
-              ++P.b;
-              pending_done = !lane_init(L, sc, L.wox, L.woy, L.woz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
-              ++n_ext;
-              ++n_inc;
-            } else {
-              path_done = true;
+            if (path_done) {
+              rp.slots[P.pid] = P.radiance;
+              ++n_paths;
+              if (TS) {
+                int view;
+                uint32_t pixel, sample;
+                path_coords(rp, (int64_t)P.pid, &view, &pixel, &sample);
+                atomicMax(&view_done[view], (unsigned long long)wall_clock64());
+              }
+              has = false;
+              break;
             }
           }
-          if (path_done) {
-            rp.slots[P.pid] = P.radiance;
-            ++n_paths;
-            if (TS) atomicMax(&view_done[P.view], (unsigned long long)wall_clock64());
-            has = false;
-            break;
-          }
+        } else if (kind == ct) {
+          run_step<FMT, COUNT>(kind, L, sc, S, spill, vc);
         }
         if (!exhausted && __popcll(__ballot(1)) <= 64 - refill) break;
       }
@@ -388,7 +468,7 @@ template <int FMT>
 __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, float* grad_albedo, int depth_lds) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
-  const Stack S{lds + (threadIdx.x >> 6) * depth_lds * 64, depth_lds, lane};
+  const Stack S = make_stack(lds, depth_lds);
   uint2 spill[kStackTotal];
   const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pid >= rp.n_paths) return;
@@ -405,8 +485,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
   Lane L;
   VisitCounters vc{0, 0, 0, 0};
   L.ex_rec = kEmpty;
-  L.ex_quad = kEmpty;
-  L.ex_half = 0u;
+  L.ex_qh = kEmpty;
   for (int b = 0; b < rp.depth; ++b) {
     if (lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF))
       while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
@@ -415,13 +494,12 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
       escaped = true;
       break;
     }
-    const Shade s = shade_hit(sc, rp, r, L.t_best, L.b_rec, L.b_quad, L.b_half);
-    const uint32_t hrec = L.b_rec, hquad = L.b_quad, hhalf = L.b_half;
+    const uint32_t hrec = L.b_rec, hqh = L.b_qh;
+    const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31);
     float c = 0.0f;
     if (s.cosl > 0.0f) {
       L.ex_rec = hrec;
-      L.ex_quad = hquad;
-      L.ex_half = hhalf;
+      L.ex_qh = hqh;
       if (lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF)) {
         L.any = true;
         while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
@@ -440,8 +518,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     r = Ray3{s.px, s.py, s.pz, dx, dy, dz};
     beta = beta * s.a;
     L.ex_rec = hrec;
-    L.ex_quad = hquad;
-    L.ex_half = hhalf;
+    L.ex_qh = hqh;
   }
   float V = escaped ? rp.L_sky : 0.0f;
   for (int k = K - 1; k >= 0; --k) {
@@ -455,39 +532,52 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
 static inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int FMT, bool COUNT>
-static void plain_bounce(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int b, int stack_depth,
-                         int block, const RenderExtras& ex, hipStream_t s) {
+static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int b,
+                             const TraceLaunch& tl, const RenderExtras& ex, hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
-  const unsigned gt = blocks(rp.n_paths, block);
-  const size_t lds = (size_t)block * stack_depth * sizeof(uint2);
+  const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   const ExtQueue& qin = pb.q[b & 1];
   const ExtQueue& qout = pb.q[(b + 1) & 1];
   uint32_t* cin = pb.counts + b;
   uint32_t* cout = pb.counts + b + 1;
   uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
-  hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, cin,
-                     pb.hits, pb.occ, stack_depth, ex.visits);
+  if (tl.persistent) {
+    hipLaunchKernelGGL((k_trace_queue_persistent<FMT, false, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                       qin, pb.sq, cin, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b, ex.visits);
+  } else {
+    const unsigned gt = blocks(rp.n_paths, tl.block);
+    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
+                       cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
+  }
   hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
                      ex.dump, ex.dump_cap, ex.dump_count);
-  hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(block), lds, s, sc, rp, qin, pb.sq, csq,
-                     pb.hits, pb.occ, stack_depth, ex.visits);
+  if (tl.persistent) {
+    hipLaunchKernelGGL((k_trace_queue_persistent<FMT, true, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                       qin, pb.sq, csq, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b + 1, ex.visits);
+  } else {
+    const unsigned gt = blocks(rp.n_paths, tl.block);
+    hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
+                       csq, pb.hits, pb.occ, tl.stack_depth, ex.visits);
+  }
   hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
 }
 
-hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
-                               int stack_depth, int block, float* image, int64_t n_pixels, const RenderExtras& ex,
-                               hipStream_t s) {
+hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
+                                   const TraceLaunch& tl, float* image, int64_t n_pixels, const RenderExtras& ex,
+                                   hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, pb.counts, 2 * kMaxDepth + 2);
+  hipError_t e = launch_zero_u64(pb.work, 2 * kMaxDepth, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
   const bool cnt = ex.visits != nullptr;
   for (int b = 0; b < rp.depth; ++b) {
     if (fmt == 2) {
-      if (cnt) plain_bounce<2, true>(sc, rp, pb, b, stack_depth, block, ex, s);
-      else plain_bounce<2, false>(sc, rp, pb, b, stack_depth, block, ex, s);
+      if (cnt) wavefront_bounce<2, true>(sc, rp, pb, b, tl, ex, s);
+      else wavefront_bounce<2, false>(sc, rp, pb, b, tl, ex, s);
     } else {
-      if (cnt) plain_bounce<1, true>(sc, rp, pb, b, stack_depth, block, ex, s);
-      else plain_bounce<1, false>(sc, rp, pb, b, stack_depth, block, ex, s);
+      if (cnt) wavefront_bounce<1, true>(sc, rp, pb, b, tl, ex, s);
+      else wavefront_bounce<1, false>(sc, rp, pb, b, tl, ex, s);
     }
   }
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
@@ -499,12 +589,12 @@ hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, cons
 template <int FMT, bool TS, bool COUNT>
 static void persistent_launch(const SceneView& sc, const RenderParams& rp, const TraceLaunch& tl,
                               const RenderExtras& ex, hipStream_t s) {
-  const size_t lds = (size_t)tl.block * tl.stack_depth * sizeof(uint2);
+  const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
                      tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
 }
 
-hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
+hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
                                     float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s) {
   hipError_t e = launch_zero_u64(tl.counter, 1, s);
   if (e != hipSuccess) return e;
@@ -533,7 +623,7 @@ hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp,
 
 hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
                           const float* grad_img, float* grad_albedo, hipStream_t s) {
-  const size_t lds = (size_t)block * stack_depth * sizeof(uint2);
+  const size_t lds = (size_t)block * stack_depth * kStackEntryBytes;
   const unsigned g = blocks(rp.n_paths, block);
   if (fmt == 2)
     hipLaunchKernelGGL((k_adjoint<2>), dim3(g), dim3(block), lds, s, sc, rp, grad_img, grad_albedo, stack_depth);

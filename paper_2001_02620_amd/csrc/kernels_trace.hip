@@ -21,15 +21,14 @@ __device__ __forceinline__ void store_result(const Lane& L, const SceneView& sc,
   h.t[i] = hit ? L.t_best : kInfF;
   h.u[i] = hit ? L.b_u : 0.0f;
   h.v[i] = hit ? L.b_v : 0.0f;
-  h.inst[i] = hit ? (int32_t)L.b_inst : -1;
-  h.prim[i] = hit ? sc.quad_prim[L.b_quad] : -1;
+  h.inst[i] = hit ? (int32_t)sc.inst[L.b_rec].inst_id : -1;
+  h.prim[i] = hit ? sc.quad_prim[L.b_qh & 0x7FFFFFFFu] : -1;
 }
 
 template <bool ANY>
 __device__ __forceinline__ bool load_ray(Lane& L, const SceneView& sc, const RaysSoA& r, int64_t i) {
   L.ex_rec = kEmpty;
-  L.ex_quad = kEmpty;
-  L.ex_half = 0u;
+  L.ex_qh = kEmpty;
   const bool ok = lane_init(L, sc, r.ox[i], r.oy[i], r.oz[i], r.dx[i], r.dy[i], r.dz[i], r.tmin[i], r.tmax[i]);
   L.any = ANY;
   return ok;
@@ -48,7 +47,7 @@ __global__ void k_trace_plain(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
                               int depth) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
-  const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
+  const Stack S = make_stack(lds, depth);
   uint2 spill[kStackTotal];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -66,7 +65,7 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
                                    uint32_t* visits, int depth, int refill, unsigned long long* counter) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
-  const Stack S{lds + (threadIdx.x >> 6) * depth * 64, depth, lane};
+  const Stack S = make_stack(lds, depth);
   uint2 spill[kStackTotal];
   Lane L;
   VisitCounters vc{0, 0, 0, 0};
@@ -136,7 +135,7 @@ __global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
 template <int FMT, bool ANY, bool COUNT>
 static hipError_t launch3(const SceneView& sc, const RaysSoA& r, int64_t n, const HitsSoA& h, uint8_t* occ,
                           uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
-  const size_t lds = (size_t)tl.block * tl.stack_depth * sizeof(uint2);
+  const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   if (tl.persistent) {
     hipError_t e = launch_zero_u64(tl.counter, 1, s);
     if (e != hipSuccess) return e;

@@ -40,6 +40,7 @@ struct PlainBuffers {
   QueueHits hits;
   uint8_t* occ;
   uint32_t* counts;  // [0, kMaxDepth]: extension queue sizes; [kMaxDepth + 1, ...): shadow queue sizes
+  unsigned long long* work;  // [2 kMaxDepth]: claim counters of the persistent queue traversals
 };
 
 // Optional instrumentation of a render call.
@@ -53,10 +54,12 @@ struct RenderExtras {
   unsigned long long* start_tick;
 };
 
-hipError_t launch_render_plain(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
-                               int stack_depth, int block, float* image, int64_t n_pixels, const RenderExtras& ex,
-                               hipStream_t s);
-hipError_t launch_render_persistent(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
+// Multi-kernel wavefront frame; tl.persistent selects lane-refilling traversal stages.
+hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
+                                   const TraceLaunch& tl, float* image, int64_t n_pixels, const RenderExtras& ex,
+                                   hipStream_t s);
+// Single persistent launch per frame.
+hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
                                     float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s);
 hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
                           const float* grad_img, float* grad_albedo, hipStream_t s);

@@ -38,7 +38,10 @@ struct SceneView {
   uint32_t n_inst;
 };
 
-constexpr float kRobust = 1.0f + 4.76837158203125e-07f;  // 1 + 2^-21 >= 1 + 2 gamma_3
+// Far-plane scale of the robust slab test: with reciprocals from v_rcp_f32
+// (at most 1 ulp) each slab distance carries four rounding factors, so the
+// far distance is scaled by 1 + 2^-20 >= 1 + 2 gamma_4 (Ize 2013).
+constexpr float kRobust = 1.0f + 9.5367431640625e-07f;
 constexpr float kSlack = 1.0f + 1.52587890625e-05f;      // 1 + 2^-16
 constexpr float kInfF = __builtin_huge_valf();
 
@@ -53,34 +56,36 @@ struct Lane {
   float onx, ony, onz;  // origin used for near planes (world level: widened)
   float ofx, ofy, ofz;  // origin used for far planes
   float ix, iy, iz;     // reciprocal direction
-  // object-space ray for the watertight leaf test (Woop, Benthin, Wald 2013)
-  float lox, loy, loz;
+  // shear of the watertight leaf test (Woop, Benthin, Wald 2013); inside an
+  // instance the leaf test uses the object-space origin (on*) as its origin
   float Sx, Sy, Sz;
-  int kx, ky, kz;
+  int kz;            // dominant axis of the object-space direction
   // traversal
   uint32_t cur;      // reference to process next, kEmpty = pop
   int sp;            // stack size
   int inst_sp;       // stack size when the current instance was entered, -1 at top level
   uint32_t rec;      // current instance record
-  uint32_t inst_id;  // its caller-visible id
-  // best hit so far
+  // best hit so far: record, leaf-ordered quad | half << 31
   float t_best, t_cull;
-  uint32_t b_rec, b_quad, b_half, b_inst;
+  uint32_t b_rec, b_qh;
   float b_u, b_v;
-  // exclusion (spawning triangle) as (record, leaf-ordered quad, half)
-  uint32_t ex_rec, ex_quad, ex_half;
+  // exclusion (spawning triangle): record, leaf-ordered quad | half << 31 (kEmpty: none)
+  uint32_t ex_rec, ex_qh;
   bool any;   // any-hit query: stop at the first accepted hit
   bool done;  // traversal finished
 };
 
-__device__ __forceinline__ float rcp_exact(float d) { return 1.0f / d; }
+// Hardware reciprocal (v_rcp_f32, 1 ulp): used for the slab test and the
+// leaf test's shear and t.  Every traversal variant evaluates the same
+// expressions, so the hits stay identical across variants.
+__device__ __forceinline__ float rcp_fast(float d) { return __builtin_amdgcn_rcpf(d); }
 
 // Set the box-test ray for the top level: the world ray with its origin widened
 // by pad = pad_rel |o|_inf toward the near and far planes.
 __device__ __forceinline__ void set_world_box_ray(Lane& L, float pad_rel) {
-  L.ix = rcp_exact(L.wdx);
-  L.iy = rcp_exact(L.wdy);
-  L.iz = rcp_exact(L.wdz);
+  L.ix = rcp_fast(L.wdx);
+  L.iy = rcp_fast(L.wdy);
+  L.iz = rcp_fast(L.wdz);
   const float m = fmaxf(fabsf(L.wox), fmaxf(fabsf(L.woy), fabsf(L.woz)));
   const float pad = pad_rel * m;
   // near plane of a positive-direction axis is lo: widen by moving the origin up
@@ -107,25 +112,22 @@ __device__ __forceinline__ void enter_instance(Lane& L, const InstRec* __restric
   const float dx = a.x * L.wdx + a.y * L.wdy + a.z * L.wdz;
   const float dy = b.x * L.wdx + b.y * L.wdy + b.z * L.wdz;
   const float dz = c.x * L.wdx + c.y * L.wdy + c.z * L.wdz;
-  L.ix = rcp_exact(dx);
-  L.iy = rcp_exact(dy);
-  L.iz = rcp_exact(dz);
-  L.onx = L.ofx = L.lox = ox;
-  L.ony = L.ofy = L.loy = oy;
-  L.onz = L.ofz = L.loz = oz;
+  L.ix = rcp_fast(dx);
+  L.iy = rcp_fast(dy);
+  L.iz = rcp_fast(dz);
+  L.onx = L.ofx = ox;
+  L.ony = L.ofy = oy;
+  L.onz = L.ofz = oz;
   const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
-  int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-  int kx = kz == 2 ? 0 : kz + 1;
-  int ky = kx == 2 ? 0 : kx + 1;
-  L.kx = kx;
-  L.ky = ky;
+  const int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  const int kx = kz == 2 ? 0 : kz + 1;
+  const int ky = kx == 2 ? 0 : kx + 1;
   L.kz = kz;
   const float dkz = pick3(dx, dy, dz, kz);
-  L.Sx = pick3(dx, dy, dz, kx) / dkz;
-  L.Sy = pick3(dx, dy, dz, ky) / dkz;
-  L.Sz = 1.0f / dkz;
+  L.Sz = rcp_fast(dkz);
+  L.Sx = pick3(dx, dy, dz, kx) * L.Sz;
+  L.Sy = pick3(dx, dy, dz, ky) * L.Sz;
   L.rec = r;
-  L.inst_id = m.y;
   *blas_root = m.x;
 }
 
@@ -136,10 +138,12 @@ __device__ __forceinline__ void enter_instance(Lane& L, const InstRec* __restric
 struct Sv {
   float X, Y, Z;
 };
-__device__ __forceinline__ Sv shear(const Lane& L, float vx, float vy, float vz) {
-  const float ax = vx - L.lox, ay = vy - L.loy, az = vz - L.loz;
-  const float akx = pick3(ax, ay, az, L.kx);
-  const float aky = pick3(ax, ay, az, L.ky);
+// The two other axes follow kz cyclically; no swap is needed for a two-sided
+// test (a swap only flips the sign of every edge function).
+__device__ __forceinline__ Sv shear(const Lane& L, int kx, int ky, float vx, float vy, float vz) {
+  const float ax = vx - L.onx, ay = vy - L.ony, az = vz - L.onz;
+  const float akx = pick3(ax, ay, az, kx);
+  const float aky = pick3(ax, ay, az, ky);
   const float akz = pick3(ax, ay, az, L.kz);
   Sv s;
   s.X = akx - L.Sx * akz;
@@ -157,18 +161,46 @@ struct TriResult {
   float t, U, V, W, det;
 };
 
+// Edge function in FP64: both products of FP32 operands are exact, so the one
+// rounding of the difference keeps the exact sign (and zero only when exact).
+__device__ __forceinline__ double edge64(const Sv& P, const Sv& Q) {
+  return (double)Q.X * (double)P.Y - (double)Q.Y * (double)P.X;
+}
+
 // Triangle (A, B, C) with precomputed edge functions U = e(B, C), V = e(C, A),
 // W = e(A, B).  Two-sided: all three of one sign (zeros allowed), det != 0.
+// Rounding is monotonic, so a non-zero FP32 edge value has the exact sign of the
+// edge function of the sheared FP32 vertices; a zero may come from cancellation
+// (for instance a distant triangle seen edge-on, whose edge lines all pass close
+// to the ray) and is then re-evaluated in FP64, as Woop, Benthin and Wald
+// prescribe.  Mixed strict signs are exact and reject at once.
 __device__ __forceinline__ TriResult tri_finish(float U, float V, float W, const Sv& A, const Sv& B, const Sv& C,
                                                 float tmin, float tmax) {
   TriResult r;
   r.hit = false;
   const bool neg = (U < 0.0f) || (V < 0.0f) || (W < 0.0f);
   const bool pos = (U > 0.0f) || (V > 0.0f) || (W > 0.0f);
+  if (neg && pos) return r;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    const double u = edge64(B, C), v = edge64(C, A), w = edge64(A, B);
+    const bool n64 = (u < 0.0) || (v < 0.0) || (w < 0.0);
+    const bool p64 = (u > 0.0) || (v > 0.0) || (w > 0.0);
+    const double det = u + v + w;
+    if ((n64 && p64) || det == 0.0) return r;
+    const double T = u * (double)A.Z + v * (double)B.Z + w * (double)C.Z;
+    const float t = (float)(T / det);
+    r.hit = (t > tmin) && (t <= tmax);
+    r.t = t;
+    // barycentrics already divided: u = V * rcp(det) with det = 1
+    r.U = (float)(u / det);
+    r.V = (float)(v / det);
+    r.W = (float)(w / det);
+    r.det = 1.0f;
+    return r;
+  }
   const float det = U + V + W;
-  if ((neg && pos) || det == 0.0f) return r;
   const float T = U * A.Z + V * B.Z + W * C.Z;
-  const float t = T / det;
+  const float t = T * rcp_fast(det);
   r.hit = (t > tmin) && (t <= tmax);
   r.t = t;
   r.U = U;
@@ -179,11 +211,34 @@ __device__ __forceinline__ TriResult tri_finish(float U, float V, float W, const
 }
 
 // ---- stack ---------------------------------------------------------------------------
+// LDS holds the top `depth` entries of every lane of a wave: references as
+// [depth][64] u32 and entry distances as [depth][64] u16 (the upper half of the
+// FP32 value, rounded toward -inf, so a popped entry is never culled wrongly).
+// Deeper entries spill to a private array.
 struct Stack {
-  uint2* lds;  // this wave's [depth][64] region
-  int depth;   // LDS entries per lane
+  uint32_t* ref;
+  uint16_t* tq;
+  int depth;  // LDS entries per lane
   int lane;
 };
+
+constexpr int kStackEntryBytes = 6;
+
+// Stack region of wave w in a block's dynamic LDS (6 bytes per entry and lane).
+__device__ __forceinline__ Stack make_stack(void* lds, int depth) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  uint32_t* refs = reinterpret_cast<uint32_t*>(lds);
+  uint16_t* ts = reinterpret_cast<uint16_t*>(refs + (size_t)waves * depth * 64);
+  return Stack{refs + wave * depth * 64, ts + wave * depth * 64, depth, lane};
+}
+
+// FP32 -> upper 16 bits, rounded toward -inf.
+__device__ __forceinline__ uint16_t t_down16(float t) {
+  uint32_t b = __float_as_uint(t);
+  if ((b & 0x80000000u) && (b & 0xFFFFu)) b += 0x10000u;  // negative: away from zero
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float t_up32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---- box tests --------------------------------------------------------------------
 // Ordered robust slab test of four children; returns entry distances (kInfF when
@@ -278,27 +333,34 @@ __device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32
 }
 
 __device__ __forceinline__ void push(Lane& L, const Stack& S, uint2* spill, uint32_t ref, float t) {
-  const uint2 e = make_uint2(ref, __float_as_uint(t));
-  if (L.sp < S.depth)
-    S.lds[L.sp * 64 + S.lane] = e;
-  else
-    spill[L.sp - S.depth] = e;
+  if (L.sp < S.depth) {
+    S.ref[L.sp * 64 + S.lane] = ref;
+    S.tq[L.sp * 64 + S.lane] = t_down16(t);
+  } else {
+    spill[L.sp - S.depth] = make_uint2(ref, __float_as_uint(t));
+  }
   ++L.sp;
 }
 
+// Pop the top entry: (reference, lower bound of its entry distance).
 __device__ __forceinline__ uint2 pop(Lane& L, const Stack& S, const uint2* spill) {
   --L.sp;
-  return L.sp < S.depth ? S.lds[L.sp * 64 + S.lane] : spill[L.sp - S.depth];
+  if (L.sp < S.depth)
+    return make_uint2(S.ref[L.sp * 64 + S.lane], __float_as_uint(t_up32(S.tq[L.sp * 64 + S.lane])));
+  return spill[L.sp - S.depth];
 }
 
-// Candidate hit (t, record, quad, half) against the best so far, by key.
+// Candidate hit (t, record, quad, half) against the best so far, by key
+// (t, instance id, primitive id, half).  Ids are looked up only on exact ties.
 __device__ __forceinline__ bool better(const Lane& L, const SceneView& sc, float t, uint32_t quad, uint32_t half) {
   if (L.b_rec == kEmpty) return true;  // the caller already checked t <= t_best (= tmax)
   if (t != L.t_best) return t < L.t_best;
-  if (L.inst_id != L.b_inst) return L.inst_id < L.b_inst;
-  const int32_t pa = sc.quad_prim[quad], pb = sc.quad_prim[L.b_quad];
+  const uint32_t ia = sc.inst[L.rec].inst_id, ib = sc.inst[L.b_rec].inst_id;
+  if (ia != ib) return ia < ib;
+  const uint32_t bq = L.b_qh & 0x7FFFFFFFu;
+  const int32_t pa = sc.quad_prim[quad], pb = sc.quad_prim[bq];
   if (pa != pb) return pa < pb;
-  return half < L.b_half;
+  return half < (L.b_qh >> 31);
 }
 
 // Test quads [first, first + count) of the current instance.  Returns true if
@@ -306,15 +368,17 @@ __device__ __forceinline__ bool better(const Lane& L, const SceneView& sc, float
 template <bool COUNT>
 __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_t first, uint32_t count,
                                            uint32_t* ctr_quads) {
+  const int kx = L.kz == 2 ? 0 : L.kz + 1;
+  const int ky = kx == 2 ? 0 : kx + 1;
   for (uint32_t q = first; q < first + count; ++q) {
     if (COUNT) ++*ctr_quads;
     const float4 f0 = sc.quads[3 * (size_t)q + 0];
     const float4 f1 = sc.quads[3 * (size_t)q + 1];
     const float4 f2 = sc.quads[3 * (size_t)q + 2];
-    const Sv s0 = shear(L, f0.x, f0.y, f0.z);
-    const Sv s1 = shear(L, f0.w, f1.x, f1.y);
-    const Sv s2 = shear(L, f1.z, f1.w, f2.x);
-    const Sv s3 = shear(L, f2.y, f2.z, f2.w);
+    const Sv s0 = shear(L, kx, ky, f0.x, f0.y, f0.z);
+    const Sv s1 = shear(L, kx, ky, f0.w, f1.x, f1.y);
+    const Sv s2 = shear(L, kx, ky, f1.z, f1.w, f2.x);
+    const Sv s3 = shear(L, kx, ky, f2.y, f2.z, f2.w);
     // half A = (v0, v1, v3), half B = (v2, v3, v1); e(v1, v3) is shared (negated)
     const float e13 = edge(s1, s3);
     const float e30 = edge(s3, s0);
@@ -325,14 +389,14 @@ __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_
     const float t_lim = L.any ? L.tmax : L.t_best;
     const TriResult ra = tri_finish(e13, e30, e01, s0, s1, s3, L.tmin, t_lim);
     const TriResult rb = tri_finish(e31, e12, e23, s2, s3, s1, L.tmin, t_lim);
-    const bool exq = (L.rec == L.ex_rec) && (q == L.ex_quad);
-    const bool oka = ra.hit && !(exq && L.ex_half == 0u);
-    const bool okb = rb.hit && !(exq && L.ex_half == 1u);
+    const bool exq = L.rec == L.ex_rec;
+    const bool oka = ra.hit && !(exq && L.ex_qh == q);
+    const bool okb = rb.hit && !(exq && L.ex_qh == (q | 0x80000000u));
     if (L.any) {
       if (oka || okb) {
         L.t_best = oka ? ra.t : rb.t;
         L.b_rec = L.rec;
-        L.b_quad = q;
+        L.b_qh = oka ? q : (q | 0x80000000u);
         return true;
       }
       continue;
@@ -340,20 +404,18 @@ __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_
     if (oka && better(L, sc, ra.t, q, 0u)) {
       L.t_best = ra.t;
       L.b_rec = L.rec;
-      L.b_inst = L.inst_id;
-      L.b_quad = q;
-      L.b_half = 0u;
-      L.b_u = ra.V / ra.det;
-      L.b_v = ra.W / ra.det;
+      L.b_qh = q;
+      const float r = rcp_fast(ra.det);
+      L.b_u = ra.V * r;
+      L.b_v = ra.W * r;
     }
     if (okb && better(L, sc, rb.t, q, 1u)) {
       L.t_best = rb.t;
       L.b_rec = L.rec;
-      L.b_inst = L.inst_id;
-      L.b_quad = q;
-      L.b_half = 1u;
-      L.b_u = 1.0f - rb.V / rb.det;
-      L.b_v = 1.0f - rb.W / rb.det;
+      L.b_qh = q | 0x80000000u;
+      const float r = rcp_fast(rb.det);
+      L.b_u = 1.0f - rb.V * r;
+      L.b_v = 1.0f - rb.W * r;
     }
     L.t_cull = L.t_best * kSlack;
   }
@@ -379,15 +441,12 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   L.t_best = tmax;
   L.t_cull = tmax * kSlack;
   L.b_rec = kEmpty;
-  L.b_quad = kEmpty;
-  L.b_half = 0u;
-  L.b_inst = kEmpty;
+  L.b_qh = kEmpty;
   L.b_u = 0.0f;
   L.b_v = 0.0f;
   L.sp = 0;
   L.inst_sp = -1;
   L.rec = kEmpty;
-  L.inst_id = kEmpty;
   L.cur = 0u;  // TLAS root
   L.any = false;
   L.done = false;
@@ -471,6 +530,32 @@ __device__ __forceinline__ void quad_step(Lane& L, const SceneView& sc, const St
   advance(L, sc, S, spill);
 }
 
+// Step kinds of a lane: 0 = traversal done, 1 = node test, 2 = instance entry,
+// 3 = quad test.
+__device__ __forceinline__ int step_kind(const Lane& L) {
+  if (L.done) return 0;
+  if (!ref_is_leaf(L.cur)) return 1;
+  return L.inst_sp < 0 ? 2 : 3;
+}
+
+template <int FMT, bool COUNT>
+__device__ __forceinline__ void run_step(int kind, Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
+                                         VisitCounters& vc) {
+  if (kind == 1) node_step<FMT, COUNT>(L, sc, S, spill, vc);
+  else if (kind == 2) inst_step<COUNT>(L, sc, vc);
+  else quad_step<COUNT>(L, sc, S, spill, vc);
+}
+
+// Wave-uniform choice among the step kinds the participating lanes need: the
+// kind with the most lanes (ties favour node, then quad, then instance).
+__device__ __forceinline__ int vote_kind(int kind) {
+  const int cn = __popcll(__ballot(kind == 1));
+  const int ci = __popcll(__ballot(kind == 2));
+  const int cq = __popcll(__ballot(kind == 3));
+  if (cn >= ci && cn >= cq) return cn ? 1 : 0;
+  return cq >= ci ? 3 : 2;
+}
+
 // One traversal step of the wave.  The lanes that take part vote: the wave runs
 // only the step kind (node test, instance entry or quad test) that most of them
 // need, the others wait.  Running one kind per iteration avoids paying for
@@ -478,21 +563,9 @@ __device__ __forceinline__ void quad_step(Lane& L, const SceneView& sc, const St
 template <int FMT, bool COUNT>
 __device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
-  if (L.cur == kEmpty && !L.done) advance(L, sc, S, spill);
-  const bool leaf = ref_is_leaf(L.cur);
-  const bool want_node = !L.done && !leaf;
-  const bool want_inst = !L.done && leaf && L.inst_sp < 0;
-  const bool want_quad = !L.done && leaf && L.inst_sp >= 0;
-  const int cn = __popcll(__ballot(want_node));
-  const int ci = __popcll(__ballot(want_inst));
-  const int cq = __popcll(__ballot(want_quad));
-  if (cn >= ci && cn >= cq) {
-    if (want_node) node_step<FMT, COUNT>(L, sc, S, spill, vc);
-  } else if (cq >= ci) {
-    if (want_quad) quad_step<COUNT>(L, sc, S, spill, vc);
-  } else {
-    if (want_inst) inst_step<COUNT>(L, sc, vc);
-  }
+  const int kind = step_kind(L);
+  const int chosen = vote_kind(kind);
+  if (chosen != 0 && kind == chosen) run_step<FMT, COUNT>(kind, L, sc, S, spill, vc);
   return L.done;
 }
 

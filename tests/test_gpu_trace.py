@@ -67,6 +67,25 @@ def test_bvh_variants_equal_brute_force_config1():
     log(f"  flagged fraction {frac:.4f}")
 
 
+def test_edge_on_sliver_rays_config1():
+    """Two rays of the config-1 scene pass far from quads that they see edge-on:
+    in FP32 two edge functions of such a quad cancel to exactly zero and the
+    third is one ulp, which a test accepting zeros as inside takes for a vertex
+    hit tens of units from the ray.  The FP64 re-evaluation of zero edge values
+    must reject them, in the brute-force reference and in every variant."""
+    log("case: config 1 scene, edge-on sliver rays")
+    scene, cams, _ = sg.config1()
+    S = rtq.Scene(scene)
+    rays = sg.random_rays(np.random.default_rng(4), 20000, -80, 80, -50, 50)[[162, 3709]]
+    o = oracle.OracleScene(scene).trace(rays)
+    assert list(o.inst) == [626, -1] and (o.flags == 0).all()
+    R = to_dev(rays)
+    ref = hits_np(rtq.trace_brute(S, R))
+    assert list(ref["inst"]) == [626, -1] and list(ref["prim"]) == [464, -1]
+    for var in VARIANTS:
+        assert_hits_identical(ref, hits_np(rtq.trace_closest(S, R, **var)), str(var))
+
+
 def test_camera_rays_config1_vs_oracle():
     log("case: config 1 camera rays through pixel centres")
     scene, cams, _ = sg.config1()
