@@ -57,8 +57,10 @@ void DeviceBuffers::release() {
 
 SceneView scene_view(const rtq_scene* s, int fmt) {
   SceneView v;
-  v.tlas = reinterpret_cast<const uint4*>(fmt == RTQ_NODE_Q8 ? s->tlas_q8 : s->tlas_f32);
-  v.blas = reinterpret_cast<const uint4*>(fmt == RTQ_NODE_Q8 ? s->blas_q8 : s->blas_f32);
+  v.nodes = reinterpret_cast<const uint4*>(fmt == RTQ_NODE_Q8 ? s->nodes_q8 : s->nodes_f32);
+  v.rec_pmax = s->rec_pmax;
+  v.p_world = s->p_world;
+  v.tlas_root = s->tlas_root;
   v.quads = s->quads;
   v.quad_prim = s->quad_prim;
   v.inst = s->inst;
@@ -219,6 +221,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   std::vector<uint32_t> proto_root(n_protos), face_base(n_protos);
   std::vector<int32_t> proto_qbase(n_protos), proto_nq(n_protos);
   std::vector<float> proto_box(6 * (size_t)n_protos);
+  std::vector<float> proto_pmax(n_protos);
   uint64_t node_base = 0, quad_base = 0;
   int max_blas_depth = 0;
   for (int32_t p = 0; p < n_protos; ++p) {
@@ -237,6 +240,11 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     for (int a = 0; a < 3; ++a) {
       proto_box[6 * p + a] = blas[p].root_box.lo[a];
       proto_box[6 * p + 3 + a] = blas[p].root_box.hi[a];
+    }
+    proto_pmax[p] = level_pmax(blas[p]);
+    if (!(proto_pmax[p] < kMaxPlaneAbs)) {
+      delete s;
+      return set_error(RTQ_E_LIMIT, "prototype %d has coordinates beyond 2^60", p);
     }
     max_blas_depth = std::max(max_blas_depth, blas[p].depth);
     node_base += blas[p].f32.size();
@@ -276,18 +284,15 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy"));                  \
   } while (0)
 
-  {
-    std::vector<NodeF32> nf;
-    std::vector<NodeQ8> nq;
-    if (formats & RTQ_NODE_FP32) nf.reserve(n_blas_nodes);
-    if (formats & RTQ_NODE_Q8) nq.reserve(n_blas_nodes);
-    for (int32_t p = 0; p < n_protos; ++p) {
-      if (formats & RTQ_NODE_FP32) nf.insert(nf.end(), blas[p].f32.begin(), blas[p].f32.end());
-      if (formats & RTQ_NODE_Q8) nq.insert(nq.end(), blas[p].q8.begin(), blas[p].q8.end());
-      blas[p] = Bvh4{};  // release host memory early
-    }
-    if (formats & RTQ_NODE_FP32) UPLOAD(s->blas_f32, nf.data(), nf.size() * sizeof(NodeF32));
-    if (formats & RTQ_NODE_Q8) UPLOAD(s->blas_q8, nq.data(), nq.size() * sizeof(NodeQ8));
+  // bottom levels first; the top level is appended once it is built
+  std::vector<NodeF32> nf;
+  std::vector<NodeQ8> nq;
+  if (formats & RTQ_NODE_FP32) nf.reserve(n_blas_nodes);
+  if (formats & RTQ_NODE_Q8) nq.reserve(n_blas_nodes);
+  for (int32_t p = 0; p < n_protos; ++p) {
+    if (formats & RTQ_NODE_FP32) nf.insert(nf.end(), blas[p].f32.begin(), blas[p].f32.end());
+    if (formats & RTQ_NODE_Q8) nq.insert(nq.end(), blas[p].q8.begin(), blas[p].q8.end());
+    blas[p] = Bvh4{};  // release host memory early
   }
   UPLOAD(s->quads, quads.data(), quads.size() * sizeof(float4));
   UPLOAD(s->quad_prim, quad_prim.data(), quad_prim.size() * sizeof(int32_t));
@@ -369,13 +374,32 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     for (int a = 0; a < 3; ++a) none.lo[a] = none.hi[a] = 0.0f;
     build_bvh4(&none, 1, tp, tlas);  // placeholder root; n_inst = 0 makes every ray miss first
   }
-  if (!relocate(tlas, 0u, 0u)) return tfail(set_error(RTQ_E_LIMIT, "top-level reference overflow"));
+  if (n_blas_nodes + tlas.f32.size() >= (uint64_t)kLeafBit)
+    return tfail(set_error(RTQ_E_LIMIT, "node count exceeds 2^31"));
+  if (!relocate(tlas, (uint32_t)n_blas_nodes, 0u))
+    return tfail(set_error(RTQ_E_LIMIT, "top-level reference overflow"));
   if (3 * (tlas.depth + max_blas_depth) + 8 > kStackTotal)
     return tfail(set_error(RTQ_E_LIMIT, "BVH depth %d + %d exceeds the traversal stack", tlas.depth, max_blas_depth));
+  s->p_world = level_pmax(tlas);
+  if (!(s->p_world < kMaxPlaneAbs)) return tfail(set_error(RTQ_E_LIMIT, "instance boxes reach beyond 2^60"));
+  s->tlas_root = (uint32_t)n_blas_nodes;
   s->tlas_depth = tlas.depth;
   s->tlas_nodes = (int64_t)tlas.f32.size();
-  if (formats & RTQ_NODE_FP32) UPLOAD(s->tlas_f32, tlas.f32.data(), tlas.f32.size() * sizeof(NodeF32));
-  if (formats & RTQ_NODE_Q8) UPLOAD(s->tlas_q8, tlas.q8.data(), tlas.q8.size() * sizeof(NodeQ8));
+  if (formats & RTQ_NODE_FP32) {
+    nf.insert(nf.end(), tlas.f32.begin(), tlas.f32.end());
+    UPLOAD(s->nodes_f32, nf.data(), nf.size() * sizeof(NodeF32));
+    nf = std::vector<NodeF32>();
+  }
+  if (formats & RTQ_NODE_Q8) {
+    nq.insert(nq.end(), tlas.q8.begin(), tlas.q8.end());
+    UPLOAD(s->nodes_q8, nq.data(), nq.size() * sizeof(NodeQ8));
+    nq = std::vector<NodeQ8>();
+  }
+  {
+    std::vector<float> rec_pmax(Nn, 0.0f);
+    for (int64_t r = 0; r < N; ++r) rec_pmax[r] = proto_pmax[insts->proto[tlas.order[r]]];
+    UPLOAD(s->rec_pmax, rec_pmax.data(), rec_pmax.size() * sizeof(float));
+  }
   s->inst = reinterpret_cast<InstRec*>(s->bufs.alloc(Nn * sizeof(InstRec), &e));
   if (!s->inst) return tfail(hip_error(e, "hipMalloc"));
   if (N > 0) {

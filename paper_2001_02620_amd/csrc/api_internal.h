@@ -39,10 +39,11 @@ struct rtq_scene {
   double build_seconds = 0.0;
   float pad_rel = 0.0f;
   // device data (owned by bufs)
-  void* tlas_f32 = nullptr;
-  void* tlas_q8 = nullptr;
-  void* blas_f32 = nullptr;
-  void* blas_q8 = nullptr;
+  float p_world = 0.0f;    // bound on |world coordinate| of every top-level plane
+  uint32_t tlas_root = 0;  // top-level root: the nodes after every bottom level
+  void* nodes_f32 = nullptr;  // [bottom levels | top level], FP32 nodes
+  void* nodes_q8 = nullptr;   // same topology, quantized nodes
+  float* rec_pmax = nullptr;  // per instance record: bound on |object coordinate| of its prototype's planes
   float4* quads = nullptr;
   int32_t* quad_prim = nullptr;
   rtq::InstRec* inst = nullptr;

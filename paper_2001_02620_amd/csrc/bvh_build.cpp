@@ -335,6 +335,27 @@ void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
   }
 }
 
+float level_pmax(const Bvh4& b) {
+  double m = 0.0;
+  for (const NodeF32& n : b.f32)
+    for (int k = 0; k < 4; ++k) {
+      if (n.child[k] == kEmpty) continue;
+      const float v[6] = {n.lo_x[k], n.hi_x[k], n.lo_y[k], n.hi_y[k], n.lo_z[k], n.hi_z[k]};
+      for (float x : v) m = std::max(m, (double)std::fabs(x));
+    }
+  for (const NodeQ8& n : b.q8) {
+    const float org[3] = {n.ox, n.oy, n.oz};
+    for (int a = 0; a < 3; ++a) {
+      const int e = (int)(int8_t)((n.exps >> (8 * a)) & 0xFFu);
+      m = std::max(m, std::fabs((double)org[a]));
+      m = std::max(m, std::fabs((double)org[a] + 255.0 * std::ldexp(1.0, e)));
+    }
+  }
+  // round up so that the FP32 bound is not below the exact maximum
+  const float f = (float)m;
+  return (double)f >= m ? f : std::nextafter(f, std::numeric_limits<float>::infinity());
+}
+
 bool relocate(Bvh4& b, uint32_t node_base, uint32_t prim_base) {
   auto fix = [&](uint32_t& r) -> bool {
     if (r == kEmpty) return true;

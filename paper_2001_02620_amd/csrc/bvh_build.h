@@ -40,7 +40,17 @@ bool relocate(Bvh4& b, uint32_t node_base, uint32_t prim_base);
 // verified to contain the FP32 plane (lower <=, upper >=).
 NodeQ8 quantize_node(const NodeF32& n);
 
-// Decoded quantized plane exactly as the kernels compute it.
+// Decoded quantized plane, correctly rounded.  The kernels take distances to the
+// exact value origin + q 2^e, which lies within half an ulp of it; their slab
+// error bound covers that half ulp.
 float q8_decode(uint32_t q, int e, float origin);
+
+// Largest |coordinate| any box plane of this BVH can take: finite FP32 child
+// planes and, for quantized nodes, the node origin and origin + 255 2^e of every
+// axis.  The kernels scale their slab error bound with it.
+float level_pmax(const Bvh4& b);
+
+// Plane bound above which the slab constants could overflow.
+constexpr float kMaxPlaneAbs = 1152921504606846976.0f;  // 2^60
 
 }  // namespace rtq

@@ -434,9 +434,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(5))) void k_render_persistent(Scen
               break;
             }
           }
-        } else if (kind == ct) {
-          run_step<FMT, COUNT>(kind, L, sc, S, spill, vc);
+        } else {
+          run_step<FMT, COUNT>(ct, kind, L, sc, S, spill, vc);
         }
+        pop_step(L, sc, S, spill);
         if (!exhausted && __popcll(__ballot(1)) <= 64 - refill) break;
       }
     }

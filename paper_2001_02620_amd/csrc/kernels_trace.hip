@@ -124,9 +124,9 @@ __global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
   if (load_ray<false>(L, sc, rays, i)) {
     for (uint32_t r = 0; r < sc.n_inst; ++r) {
       uint32_t root;
-      enter_instance(L, sc.inst, r, &root);
+      enter_instance(L, sc, r, &root);
       const uint32_t p = sc.inst[r].proto;
-      leaf_quads<false>(L, sc, (uint32_t)sc.proto_qbase[p], (uint32_t)sc.proto_nq[p], nullptr);
+      leaf_quads(L, sc, (uint32_t)sc.proto_qbase[p], (uint32_t)sc.proto_nq[p]);
     }
   }
   store_result<false>(L, sc, i, hits, nullptr);

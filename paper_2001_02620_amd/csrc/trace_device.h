@@ -9,10 +9,12 @@
 // Exactness rules that make every traversal variant return the same hit:
 //   * the leaf test is one function used by every variant (FP32, watertight,
 //     contraction off), and its result depends only on (ray, instance, quad);
-//   * boxes are tested conservatively: robust slab test (Ize 2013: the far
-//     distance is scaled by 1 + 2 gamma_3), quantized boxes contain the exact
-//     boxes, instance world boxes are padded for the FP32 ray-transform error
-//     and the ray origin is widened by a per-ray pad at the top level;
+//   * boxes are tested conservatively: every slab distance is one fused
+//     multiply-add of a plane with per-level constants, and those constants are
+//     moved by an absolute bound on every rounding error of that evaluation (near
+//     distances down, far distances up); quantized boxes contain the exact boxes;
+//     instance world boxes are padded for the FP32 ray-transform error and the
+//     ray origin is widened by a per-ray pad at the top level;
 //   * a box is culled only when its entry distance exceeds t_best (1 + 2^-16);
 //   * among hits the smallest key (t, instance id, primitive id, half) wins.
 #pragma once
@@ -26,24 +28,29 @@
 namespace rtq {
 
 struct SceneView {
-  const uint4* tlas;          // TLAS nodes of the traced format
-  const uint4* blas;          // BLAS nodes of the traced format
+  const uint4* nodes;         // nodes of the traced format: every bottom level, then the top level
   const float4* quads;        // leaf-ordered quads, 3 float4 each
   const int32_t* quad_prim;   // leaf order -> quad index within its prototype
   const InstRec* inst;        // instance records in TLAS leaf order
+  const float* rec_pmax;      // per record: bound on |object coordinate| of its prototype's boxes
   const int32_t* proto_qbase; // first leaf-ordered quad of each prototype
   const int32_t* proto_nq;    // quads per prototype
   const float* albedo;        // per unique face (prototype order)
   float pad_rel;              // top-level origin pad per unit of |o|_inf
+  float p_world;              // bound on |world coordinate| of the top-level boxes
+  uint32_t tlas_root;         // index of the top-level root in `nodes`
   uint32_t n_inst;
 };
 
-// Far-plane scale of the robust slab test: with reciprocals from v_rcp_f32
-// (at most 1 ulp) each slab distance carries four rounding factors, so the
-// far distance is scaled by 1 + 2^-20 >= 1 + 2 gamma_4 (Ize 2013).
-constexpr float kRobust = 1.0f + 9.5367431640625e-07f;
-constexpr float kSlack = 1.0f + 1.52587890625e-05f;      // 1 + 2^-16
+constexpr float kSlack = 1.0f + 1.52587890625e-05f;  // 1 + 2^-16
 constexpr float kInfF = __builtin_huge_valf();
+// Slab-error bound per unit of (|plane| + |origin|) |1/d|: 2^-20 = 16 u covers
+// the reciprocal (1 ulp), the product and difference forming the level
+// constants, the node-frame constant of quantized nodes, the fused multiply-add
+// and the half-ulp by which a quantized plane may sit inside its decoded value.
+constexpr float kDeltaRel = 9.5367431640625e-07f;
+constexpr float kInvMax = 18446744073709551616.0f;         // 2^64
+constexpr float kInvMaxArg = 5.42101086242752217e-20f;     // 2^-64
 
 // Counter-free selection of component k (0, 1, 2) of (x, y, z).
 __device__ __forceinline__ float pick3(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
@@ -52,12 +59,15 @@ __device__ __forceinline__ float pick3(float x, float y, float z, int k) { retur
 struct Lane {
   // world ray
   float wox, woy, woz, wdx, wdy, wdz, tmin, tmax;
-  // ray of the current level for box tests
-  float onx, ony, onz;  // origin used for near planes (world level: widened)
-  float ofx, ofy, ofz;  // origin used for far planes
-  float ix, iy, iz;     // reciprocal direction
-  // shear of the watertight leaf test (Woop, Benthin, Wald 2013); inside an
-  // instance the leaf test uses the object-space origin (on*) as its origin
+  // slab constants of the current level: the distance to a plane p of axis a is
+  // fmaf(p, i_a, cn_a) for near planes (a lower bound) and fmaf(p, i_a, cf_a)
+  // for far planes (an upper bound)
+  float ix, iy, iz;
+  float cnx, cny, cnz;
+  float cfx, cfy, cfz;
+  // leaf test inside an instance: object-space origin and the shear of the
+  // watertight test (Woop, Benthin, Wald 2013)
+  float lox, loy, loz;
   float Sx, Sy, Sz;
   int kz;            // dominant axis of the object-space direction
   // traversal
@@ -80,31 +90,45 @@ struct Lane {
 // expressions, so the hits stay identical across variants.
 __device__ __forceinline__ float rcp_fast(float d) { return __builtin_amdgcn_rcpf(d); }
 
-// Set the box-test ray for the top level: the world ray with its origin widened
+// Reciprocal direction for the slab test.  Components below 2^-64 in magnitude
+// (zero included) take +-2^64, which keeps every slab constant finite; the
+// slab of such an axis then still brackets every distance the ray can reach
+// inside the level's bounds, and the error bound widens it further.
+__device__ __forceinline__ float slab_inv(float d) {
+  return fabsf(d) < kInvMaxArg ? copysignf(kInvMax, d) : rcp_fast(d);
+}
+
+// Constants of one axis: origin `on` for near planes and `of` for far planes,
+// `pmax` bounds |plane| over the level.
+__device__ __forceinline__ void slab_axis(float i, float on, float of, float pmax, float& cn, float& cf) {
+  const float delta = (pmax + fmaxf(fabsf(on), fabsf(of))) * fabsf(i) * kDeltaRel;
+  cn = -(on * i) - delta;
+  cf = -(of * i) + delta;
+}
+
+// Box-test constants for the top level: the world ray with its origin widened
 // by pad = pad_rel |o|_inf toward the near and far planes.
-__device__ __forceinline__ void set_world_box_ray(Lane& L, float pad_rel) {
-  L.ix = rcp_fast(L.wdx);
-  L.iy = rcp_fast(L.wdy);
-  L.iz = rcp_fast(L.wdz);
+__device__ __forceinline__ void set_world_level(Lane& L, const SceneView& sc) {
+  L.ix = slab_inv(L.wdx);
+  L.iy = slab_inv(L.wdy);
+  L.iz = slab_inv(L.wdz);
   const float m = fmaxf(fabsf(L.wox), fmaxf(fabsf(L.woy), fabsf(L.woz)));
-  const float pad = pad_rel * m;
+  const float pad = sc.pad_rel * m;
   // near plane of a positive-direction axis is lo: widen by moving the origin up
-  L.onx = L.ix >= 0.0f ? L.wox + pad : L.wox - pad;
-  L.ofx = L.ix >= 0.0f ? L.wox - pad : L.wox + pad;
-  L.ony = L.iy >= 0.0f ? L.woy + pad : L.woy - pad;
-  L.ofy = L.iy >= 0.0f ? L.woy - pad : L.woy + pad;
-  L.onz = L.iz >= 0.0f ? L.woz + pad : L.woz - pad;
-  L.ofz = L.iz >= 0.0f ? L.woz - pad : L.woz + pad;
+  const float sx = L.ix >= 0.0f ? pad : -pad, sy = L.iy >= 0.0f ? pad : -pad, sz = L.iz >= 0.0f ? pad : -pad;
+  slab_axis(L.ix, L.wox + sx, L.wox - sx, sc.p_world, L.cnx, L.cfx);
+  slab_axis(L.iy, L.woy + sy, L.woy - sy, sc.p_world, L.cny, L.cfy);
+  slab_axis(L.iz, L.woz + sz, L.woz - sz, sc.p_world, L.cnz, L.cfz);
 }
 
 // Enter instance `r`: transform the ray to object space, o' = A^-1 (o - t),
 // d' = A^-1 d, and prepare the box test and the shear of the leaf test.
-__device__ __forceinline__ void enter_instance(Lane& L, const InstRec* __restrict__ inst, uint32_t r,
-                                               uint32_t* blas_root) {
-  const float4 a = *reinterpret_cast<const float4*>(inst[r].r0);
-  const float4 b = *reinterpret_cast<const float4*>(inst[r].r1);
-  const float4 c = *reinterpret_cast<const float4*>(inst[r].r2);
-  const uint4 m = *reinterpret_cast<const uint4*>(&inst[r].blas_root);
+__device__ __forceinline__ void enter_instance(Lane& L, const SceneView& sc, uint32_t r, uint32_t* blas_root) {
+  const float4 a = *reinterpret_cast<const float4*>(sc.inst[r].r0);
+  const float4 b = *reinterpret_cast<const float4*>(sc.inst[r].r1);
+  const float4 c = *reinterpret_cast<const float4*>(sc.inst[r].r2);
+  const uint32_t root = sc.inst[r].blas_root;
+  const float pmax = sc.rec_pmax[r];
   const float px = L.wox - a.w, py = L.woy - b.w, pz = L.woz - c.w;
   const float ox = a.x * px + a.y * py + a.z * pz;
   const float oy = b.x * px + b.y * py + b.z * pz;
@@ -112,12 +136,15 @@ __device__ __forceinline__ void enter_instance(Lane& L, const InstRec* __restric
   const float dx = a.x * L.wdx + a.y * L.wdy + a.z * L.wdz;
   const float dy = b.x * L.wdx + b.y * L.wdy + b.z * L.wdz;
   const float dz = c.x * L.wdx + c.y * L.wdy + c.z * L.wdz;
-  L.ix = rcp_fast(dx);
-  L.iy = rcp_fast(dy);
-  L.iz = rcp_fast(dz);
-  L.onx = L.ofx = ox;
-  L.ony = L.ofy = oy;
-  L.onz = L.ofz = oz;
+  L.ix = slab_inv(dx);
+  L.iy = slab_inv(dy);
+  L.iz = slab_inv(dz);
+  slab_axis(L.ix, ox, ox, pmax, L.cnx, L.cfx);
+  slab_axis(L.iy, oy, oy, pmax, L.cny, L.cfy);
+  slab_axis(L.iz, oz, oz, pmax, L.cnz, L.cfz);
+  L.lox = ox;
+  L.loy = oy;
+  L.loz = oz;
   const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
   const int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
   const int kx = kz == 2 ? 0 : kz + 1;
@@ -128,7 +155,7 @@ __device__ __forceinline__ void enter_instance(Lane& L, const InstRec* __restric
   L.Sx = pick3(dx, dy, dz, kx) * L.Sz;
   L.Sy = pick3(dx, dy, dz, ky) * L.Sz;
   L.rec = r;
-  *blas_root = m.x;
+  *blas_root = root;
 }
 
 // ---- leaf test -----------------------------------------------------------------
@@ -141,13 +168,13 @@ struct Sv {
 // The two other axes follow kz cyclically; no swap is needed for a two-sided
 // test (a swap only flips the sign of every edge function).
 __device__ __forceinline__ Sv shear(const Lane& L, int kx, int ky, float vx, float vy, float vz) {
-  const float ax = vx - L.onx, ay = vy - L.ony, az = vz - L.onz;
+  const float ax = vx - L.lox, ay = vy - L.loy, az = vz - L.loz;
   const float akx = pick3(ax, ay, az, kx);
   const float aky = pick3(ax, ay, az, ky);
   const float akz = pick3(ax, ay, az, L.kz);
   Sv s;
-  s.X = akx - L.Sx * akz;
-  s.Y = aky - L.Sy * akz;
+  s.X = fmaf(-L.Sx, akz, akx);
+  s.Y = fmaf(-L.Sy, akz, aky);
   s.Z = L.Sz * akz;
   return s;
 }
@@ -199,7 +226,7 @@ __device__ __forceinline__ TriResult tri_finish(float U, float V, float W, const
     return r;
   }
   const float det = U + V + W;
-  const float T = U * A.Z + V * B.Z + W * C.Z;
+  const float T = fmaf(U, A.Z, fmaf(V, B.Z, W * C.Z));
   const float t = T * rcp_fast(det);
   r.hit = (t > tmin) && (t <= tmax);
   r.t = t;
@@ -216,86 +243,81 @@ __device__ __forceinline__ TriResult tri_finish(float U, float V, float W, const
 // FP32 value, rounded toward -inf, so a popped entry is never culled wrongly).
 // Deeper entries spill to a private array.
 struct Stack {
-  uint32_t* ref;
-  uint16_t* tq;
-  int depth;  // LDS entries per lane
-  int lane;
+  uint32_t* ref;  // this lane's column: entry j at ref[64 j]
+  uint16_t* tq;   // this lane's column of entry distances
+  int depth;      // LDS entries per lane
 };
 
 constexpr int kStackEntryBytes = 6;
 
-// Stack region of wave w in a block's dynamic LDS (6 bytes per entry and lane).
+// Stack region of this lane in a block's dynamic LDS (6 bytes per entry and lane).
 __device__ __forceinline__ Stack make_stack(void* lds, int depth) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
   uint32_t* refs = reinterpret_cast<uint32_t*>(lds);
   uint16_t* ts = reinterpret_cast<uint16_t*>(refs + (size_t)waves * depth * 64);
-  return Stack{refs + wave * depth * 64, ts + wave * depth * 64, depth, lane};
+  return Stack{refs + wave * depth * 64 + lane, ts + wave * depth * 64 + lane, depth};
 }
 
-// FP32 -> upper 16 bits, rounded toward -inf.
+// FP32 -> upper 16 bits, rounded toward -inf: a negative value with a non-zero
+// lower half rounds away from zero.
 __device__ __forceinline__ uint16_t t_down16(float t) {
-  uint32_t b = __float_as_uint(t);
-  if ((b & 0x80000000u) && (b & 0xFFFFu)) b += 0x10000u;  // negative: away from zero
-  return (uint16_t)(b >> 16);
+  const uint32_t b = __float_as_uint(t);
+  return (uint16_t)((b + ((uint32_t)((int32_t)b >> 31) & 0xFFFFu)) >> 16);
 }
 __device__ __forceinline__ float t_up32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---- box tests --------------------------------------------------------------------
-// Ordered robust slab test of four children; returns entry distances (kInfF when
-// missed).  lo/hi are the planes of axis x, y, z for each child.
+// Slab test of one child: near planes (nx, ny, nz), far planes (fx, fy, fz).
+// Returns the entry distance, or kInfF when the box is missed or lies beyond
+// t_lim.
 __device__ __forceinline__ float slab1(const Lane& L, float nx, float fx, float ny, float fy, float nz, float fz,
                                        float t_lim) {
-  const float tnx = (nx - L.onx) * L.ix, tfx = (fx - L.ofx) * L.ix;
-  const float tny = (ny - L.ony) * L.iy, tfy = (fy - L.ofy) * L.iy;
-  const float tnz = (nz - L.onz) * L.iz, tfz = (fz - L.ofz) * L.iz;
-  const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, L.tmin));
-  const float tf = fminf(fminf(tfx, tfy), tfz) * kRobust;
+  const float tn = fmaxf(fmaxf(fmaf(nx, L.ix, L.cnx), fmaf(ny, L.iy, L.cny)), fmaxf(fmaf(nz, L.iz, L.cnz), L.tmin));
+  const float tf = fminf(fminf(fmaf(fx, L.ix, L.cfx), fmaf(fy, L.iy, L.cfy)), fmaf(fz, L.iz, L.cfz));
   return tn <= fminf(tf, t_lim) ? tn : kInfF;
 }
 
 template <int FMT>
 struct NodeCodec;
 
-// FP32 nodes: 8 x 16 B loads (planes SoA, children).
+// Near/far plane of an axis: lo when the reciprocal direction is non-negative.
+__device__ __forceinline__ uint32_t sign_of(float i) { return __float_as_uint(i) >> 31; }
+
+// FP32 nodes: the near and far plane vectors of each axis are chosen by address
+// (6 x 16 B plane loads and the child references).  Empty slots have lo = +inf
+// and hi = -inf and miss for every ray.
 template <>
 struct NodeCodec<1> {
   static constexpr int kStride = 8;  // uint4 per node
   __device__ __forceinline__ static void test(const Lane& L, const uint4* __restrict__ base, uint32_t idx,
                                               float t_lim, float tn[4], uint32_t ch[4]) {
     const uint4* p = base + (size_t)idx * kStride;
-    const float4 lx = __builtin_bit_cast(float4, p[0]);
-    const float4 hx = __builtin_bit_cast(float4, p[1]);
-    const float4 ly = __builtin_bit_cast(float4, p[2]);
-    const float4 hy = __builtin_bit_cast(float4, p[3]);
-    const float4 lz = __builtin_bit_cast(float4, p[4]);
-    const float4 hz = __builtin_bit_cast(float4, p[5]);
+    const uint32_t sx = sign_of(L.ix), sy = sign_of(L.iy), sz = sign_of(L.iz);
+    const float4 nx = __builtin_bit_cast(float4, p[sx]);
+    const float4 fx = __builtin_bit_cast(float4, p[sx ^ 1u]);
+    const float4 ny = __builtin_bit_cast(float4, p[2u + sy]);
+    const float4 fy = __builtin_bit_cast(float4, p[3u - sy]);
+    const float4 nz = __builtin_bit_cast(float4, p[4u + sz]);
+    const float4 fz = __builtin_bit_cast(float4, p[5u - sz]);
     const uint4 c = p[6];
-    const bool sx = L.ix >= 0.0f, sy = L.iy >= 0.0f, sz = L.iz >= 0.0f;
-    const float LX[4] = {lx.x, lx.y, lx.z, lx.w}, HX[4] = {hx.x, hx.y, hx.z, hx.w};
-    const float LY[4] = {ly.x, ly.y, ly.z, ly.w}, HY[4] = {hy.x, hy.y, hy.z, hy.w};
-    const float LZ[4] = {lz.x, lz.y, lz.z, lz.w}, HZ[4] = {hz.x, hz.y, hz.z, hz.w};
     ch[0] = c.x;
     ch[1] = c.y;
     ch[2] = c.z;
     ch[3] = c.w;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float t = slab1(L, sx ? LX[k] : HX[k], sx ? HX[k] : LX[k], sy ? LY[k] : HY[k], sy ? HY[k] : LY[k],
-                            sz ? LZ[k] : HZ[k], sz ? HZ[k] : LZ[k], t_lim);
-      tn[k] = ch[k] == kEmpty ? kInfF : t;
-    }
+    tn[0] = slab1(L, nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, t_lim);
+    tn[1] = slab1(L, nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, t_lim);
+    tn[2] = slab1(L, nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, t_lim);
+    tn[3] = slab1(L, nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, t_lim);
   }
 };
 
-// Quantized nodes: 4 x 16 B loads; the near/far byte planes of all four children
-// are selected with one select per axis before decoding.
+// Quantized nodes: 4 x 16 B loads.  A plane is origin + q 2^e, so its distance is
+// fmaf(q, 2^e i, fmaf(origin, i, c)): two per-node constants per axis and one
+// fused multiply-add per plane.  The near/far byte planes of all four children
+// are selected with one select per axis.
 template <>
 struct NodeCodec<2> {
   static constexpr int kStride = 4;
-  __device__ __forceinline__ static float scale_of(uint32_t e8) {
-    const int e = (int)(int8_t)(e8 & 0xFFu);
-    return __int_as_float((e + 127) << 23);
-  }
   __device__ __forceinline__ static float ub(uint32_t w, int k) {
     return (float)((w >> (8 * k)) & 0xFFu);
   }
@@ -304,7 +326,13 @@ struct NodeCodec<2> {
     const uint4* p = base + (size_t)idx * kStride;
     const uint4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
     const float ox = __uint_as_float(q0.x), oy = __uint_as_float(q0.y), oz = __uint_as_float(q0.z);
-    const float ex = scale_of(q0.w), ey = scale_of(q0.w >> 8), ez = scale_of(q0.w >> 16);
+    // 2^e i is exact (a power-of-two scaling)
+    const float bx = __builtin_amdgcn_ldexpf(L.ix, (int)(int8_t)(q0.w & 0xFFu));
+    const float by = __builtin_amdgcn_ldexpf(L.iy, (int)(int8_t)((q0.w >> 8) & 0xFFu));
+    const float bz = __builtin_amdgcn_ldexpf(L.iz, (int)(int8_t)((q0.w >> 16) & 0xFFu));
+    const float nax = fmaf(ox, L.ix, L.cnx), fax = fmaf(ox, L.ix, L.cfx);
+    const float nay = fmaf(oy, L.iy, L.cny), fay = fmaf(oy, L.iy, L.cfy);
+    const float naz = fmaf(oz, L.iz, L.cnz), faz = fmaf(oz, L.iz, L.cfz);
     const bool sx = L.ix >= 0.0f, sy = L.iy >= 0.0f, sz = L.iz >= 0.0f;
     const uint32_t nx = sx ? q1.x : q1.y, fx = sx ? q1.y : q1.x;
     const uint32_t ny = sy ? q1.z : q1.w, fy = sy ? q1.w : q1.z;
@@ -315,9 +343,10 @@ struct NodeCodec<2> {
     ch[3] = q3.y;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float t = slab1(L, fmaf(ub(nx, k), ex, ox), fmaf(ub(fx, k), ex, ox), fmaf(ub(ny, k), ey, oy),
-                            fmaf(ub(fy, k), ey, oy), fmaf(ub(nz, k), ez, oz), fmaf(ub(fz, k), ez, oz), t_lim);
-      tn[k] = ch[k] == kEmpty ? kInfF : t;
+      const float n = fmaxf(fmaxf(fmaf(ub(nx, k), bx, nax), fmaf(ub(ny, k), by, nay)),
+                            fmaxf(fmaf(ub(nz, k), bz, naz), L.tmin));
+      const float f = fminf(fminf(fmaf(ub(fx, k), bx, fax), fmaf(ub(fy, k), by, fay)), fmaf(ub(fz, k), bz, faz));
+      tn[k] = (ch[k] != kEmpty && n <= fminf(f, t_lim)) ? n : kInfF;
     }
   }
 };
@@ -330,24 +359,6 @@ __device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32
   tb = t1;
   ra = r0;
   rb = r1;
-}
-
-__device__ __forceinline__ void push(Lane& L, const Stack& S, uint2* spill, uint32_t ref, float t) {
-  if (L.sp < S.depth) {
-    S.ref[L.sp * 64 + S.lane] = ref;
-    S.tq[L.sp * 64 + S.lane] = t_down16(t);
-  } else {
-    spill[L.sp - S.depth] = make_uint2(ref, __float_as_uint(t));
-  }
-  ++L.sp;
-}
-
-// Pop the top entry: (reference, lower bound of its entry distance).
-__device__ __forceinline__ uint2 pop(Lane& L, const Stack& S, const uint2* spill) {
-  --L.sp;
-  if (L.sp < S.depth)
-    return make_uint2(S.ref[L.sp * 64 + S.lane], __float_as_uint(t_up32(S.tq[L.sp * 64 + S.lane])));
-  return spill[L.sp - S.depth];
 }
 
 // Candidate hit (t, record, quad, half) against the best so far, by key
@@ -363,62 +374,64 @@ __device__ __forceinline__ bool better(const Lane& L, const SceneView& sc, float
   return half < (L.b_qh >> 31);
 }
 
-// Test quads [first, first + count) of the current instance.  Returns true if
-// an any-hit query found a hit.
-template <bool COUNT>
-__device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_t first, uint32_t count,
-                                           uint32_t* ctr_quads) {
+// Test quad q of the current instance on the lanes with `act` set; the other
+// lanes evaluate the same instructions on quad q (any valid index) and keep their
+// state.  Every update is a select, so no lane state is written under divergent
+// control flow.  Returns true on the lanes where an any-hit query found its hit.
+__device__ __forceinline__ bool quad_test(Lane& L, const SceneView& sc, bool act, uint32_t q) {
   const int kx = L.kz == 2 ? 0 : L.kz + 1;
   const int ky = kx == 2 ? 0 : kx + 1;
-  for (uint32_t q = first; q < first + count; ++q) {
-    if (COUNT) ++*ctr_quads;
-    const float4 f0 = sc.quads[3 * (size_t)q + 0];
-    const float4 f1 = sc.quads[3 * (size_t)q + 1];
-    const float4 f2 = sc.quads[3 * (size_t)q + 2];
-    const Sv s0 = shear(L, kx, ky, f0.x, f0.y, f0.z);
-    const Sv s1 = shear(L, kx, ky, f0.w, f1.x, f1.y);
-    const Sv s2 = shear(L, kx, ky, f1.z, f1.w, f2.x);
-    const Sv s3 = shear(L, kx, ky, f2.y, f2.z, f2.w);
-    // half A = (v0, v1, v3), half B = (v2, v3, v1); e(v1, v3) is shared (negated)
-    const float e13 = edge(s1, s3);
-    const float e30 = edge(s3, s0);
-    const float e01 = edge(s0, s1);
-    const float e31 = edge(s3, s1);
-    const float e12 = edge(s1, s2);
-    const float e23 = edge(s2, s3);
-    const float t_lim = L.any ? L.tmax : L.t_best;
-    const TriResult ra = tri_finish(e13, e30, e01, s0, s1, s3, L.tmin, t_lim);
-    const TriResult rb = tri_finish(e31, e12, e23, s2, s3, s1, L.tmin, t_lim);
-    const bool exq = L.rec == L.ex_rec;
-    const bool oka = ra.hit && !(exq && L.ex_qh == q);
-    const bool okb = rb.hit && !(exq && L.ex_qh == (q | 0x80000000u));
-    if (L.any) {
-      if (oka || okb) {
-        L.t_best = oka ? ra.t : rb.t;
-        L.b_rec = L.rec;
-        L.b_qh = oka ? q : (q | 0x80000000u);
-        return true;
-      }
-      continue;
-    }
-    if (oka && better(L, sc, ra.t, q, 0u)) {
-      L.t_best = ra.t;
-      L.b_rec = L.rec;
-      L.b_qh = q;
-      const float r = rcp_fast(ra.det);
-      L.b_u = ra.V * r;
-      L.b_v = ra.W * r;
-    }
-    if (okb && better(L, sc, rb.t, q, 1u)) {
-      L.t_best = rb.t;
-      L.b_rec = L.rec;
-      L.b_qh = q | 0x80000000u;
-      const float r = rcp_fast(rb.det);
-      L.b_u = 1.0f - rb.V * r;
-      L.b_v = 1.0f - rb.W * r;
-    }
-    L.t_cull = L.t_best * kSlack;
+  const float4 f0 = sc.quads[3 * (size_t)q + 0];
+  const float4 f1 = sc.quads[3 * (size_t)q + 1];
+  const float4 f2 = sc.quads[3 * (size_t)q + 2];
+  const Sv s0 = shear(L, kx, ky, f0.x, f0.y, f0.z);
+  const Sv s1 = shear(L, kx, ky, f0.w, f1.x, f1.y);
+  const Sv s2 = shear(L, kx, ky, f1.z, f1.w, f2.x);
+  const Sv s3 = shear(L, kx, ky, f2.y, f2.z, f2.w);
+  // half A = (v0, v1, v3), half B = (v2, v3, v1); e(v1, v3) is shared (negated)
+  const float e13 = edge(s1, s3);
+  const float e30 = edge(s3, s0);
+  const float e01 = edge(s0, s1);
+  const float e31 = edge(s3, s1);
+  const float e12 = edge(s1, s2);
+  const float e23 = edge(s2, s3);
+  const float t_lim = L.any ? L.tmax : L.t_best;
+  const TriResult ra = tri_finish(e13, e30, e01, s0, s1, s3, L.tmin, t_lim);
+  const TriResult rb = tri_finish(e31, e12, e23, s2, s3, s1, L.tmin, t_lim);
+  const bool exq = L.rec == L.ex_rec;
+  const bool oka = act && ra.hit && !(exq && L.ex_qh == q);
+  const bool okb = act && rb.hit && !(exq && L.ex_qh == (q | 0x80000000u));
+  if (L.any) {
+    // any-hit: the first accepted half answers the query
+    const bool hit = oka || okb;
+    L.t_best = hit ? (oka ? ra.t : rb.t) : L.t_best;
+    L.b_rec = hit ? L.rec : L.b_rec;
+    L.b_qh = hit ? (oka ? q : (q | 0x80000000u)) : L.b_qh;
+    return hit;
   }
+  const bool ua = oka && better(L, sc, ra.t, q, 0u);
+  const float ra_r = rcp_fast(ra.det);
+  L.t_best = ua ? ra.t : L.t_best;
+  L.b_rec = ua ? L.rec : L.b_rec;
+  L.b_qh = ua ? q : L.b_qh;
+  L.b_u = ua ? ra.V * ra_r : L.b_u;
+  L.b_v = ua ? ra.W * ra_r : L.b_v;
+  const bool ub = okb && better(L, sc, rb.t, q, 1u);
+  const float rb_r = rcp_fast(rb.det);
+  L.t_best = ub ? rb.t : L.t_best;
+  L.b_rec = ub ? L.rec : L.b_rec;
+  L.b_qh = ub ? (q | 0x80000000u) : L.b_qh;
+  L.b_u = ub ? 1.0f - rb.V * rb_r : L.b_u;
+  L.b_v = ub ? 1.0f - rb.W * rb_r : L.b_v;
+  L.t_cull = L.t_best * kSlack;
+  return false;
+}
+
+// Test quads [first, first + count) of the current instance on every lane.
+// Returns true if an any-hit query found a hit.
+__device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_t first, uint32_t count) {
+  for (uint32_t q = first; q < first + count; ++q)
+    if (quad_test(L, sc, true, q)) return true;
   return false;
 }
 
@@ -447,7 +460,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   L.sp = 0;
   L.inst_sp = -1;
   L.rec = kEmpty;
-  L.cur = 0u;  // TLAS root
+  L.cur = sc.tlas_root;
   L.any = false;
   L.done = false;
   const bool finite = __builtin_isfinite(ox) && __builtin_isfinite(oy) && __builtin_isfinite(oz) &&
@@ -458,96 +471,168 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
     L.done = true;
     return false;
   }
-  set_world_box_ray(L, sc.pad_rel);
+  set_world_level(L, sc);
   return true;
 }
 
-// Resolve an empty current reference: leave the instance when its subtree is
-// exhausted, pop the next entry whose entry distance is not behind the closest
-// hit, or finish.
-__device__ __forceinline__ void advance(Lane& L, const SceneView& sc, const Stack& S, const uint2* spill) {
-  while (L.cur == kEmpty) {
-    if (L.inst_sp >= 0 && L.sp == L.inst_sp) {  // leave the instance
-      L.inst_sp = -1;
-      set_world_box_ray(L, sc.pad_rel);
-    }
-    if (L.sp == 0) {
-      L.done = true;
-      return;
-    }
-    const uint2 e = pop(L, S, spill);
-    if (__uint_as_float(e.y) <= L.t_cull) L.cur = e.x;
-  }
-}
-
-// Node step: test the four children, continue with the nearest, push the others
-// (farthest first) with their entry distances.
+// Node step on the lanes with `act` set: test the four children, continue with
+// the nearest, push the others (farthest first) with their entry distances.
+// Lanes without `act` test the top-level root (any valid node) and keep their
+// state; only the stack stores are predicated.  When no lane of the wave can
+// reach the spill region the pushes go to LDS without a per-entry branch.
 template <int FMT, bool COUNT>
-__device__ __forceinline__ void node_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
+__device__ __forceinline__ void node_step(bool act, Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
   float tn[4];
   uint32_t ch[4];
-  const bool top = L.inst_sp < 0;
   if (COUNT) {
-    if (top) ++vc.tlas;
-    else ++vc.blas;
+    vc.tlas += (act && L.inst_sp < 0) ? 1u : 0u;
+    vc.blas += (act && L.inst_sp >= 0) ? 1u : 0u;
   }
-  NodeCodec<FMT>::test(L, top ? sc.tlas : sc.blas, L.cur, L.t_cull, tn, ch);
+  NodeCodec<FMT>::test(L, sc.nodes, act ? L.cur : sc.tlas_root, L.t_cull, tn, ch);
   cswap(tn[0], ch[0], tn[1], ch[1]);
   cswap(tn[2], ch[2], tn[3], ch[3]);
   cswap(tn[0], ch[0], tn[2], ch[2]);
   cswap(tn[1], ch[1], tn[3], ch[3]);
   cswap(tn[1], ch[1], tn[2], ch[2]);
-  if (tn[3] < kInfF) push(L, S, spill, ch[3], tn[3]);
-  if (tn[2] < kInfF) push(L, S, spill, ch[2], tn[2]);
-  if (tn[1] < kInfF) push(L, S, spill, ch[1], tn[1]);
-  L.cur = tn[0] < kInfF ? ch[0] : kEmpty;
-  advance(L, sc, S, spill);
-}
-
-// Instance step: a top-level leaf -- transform the ray and descend into the
-// prototype's bottom-level root.
-template <bool COUNT>
-__device__ __forceinline__ void inst_step(Lane& L, const SceneView& sc, VisitCounters& vc) {
-  if (COUNT) ++vc.inst;
-  uint32_t root;
-  enter_instance(L, sc.inst, leaf_first(L.cur), &root);
-  L.inst_sp = L.sp;
-  L.cur = root;
-}
-
-// Quad step: test the first quad of the current bottom-level leaf.
-template <bool COUNT>
-__device__ __forceinline__ void quad_step(Lane& L, const SceneView& sc, const Stack& S, const uint2* spill,
-                                          VisitCounters& vc) {
-  const uint32_t first = leaf_first(L.cur), count = leaf_count(L.cur);
-  if (leaf_quads<COUNT>(L, sc, first, 1u, &vc.quads)) {  // any-hit query answered
-    L.cur = kEmpty;
-    L.done = true;
-    return;
+  // sorted: the hit children are a prefix; child k goes to slot p_k
+  const bool v1 = act && tn[1] < kInfF, v2 = act && tn[2] < kInfF, v3 = act && tn[3] < kInfF;
+  const int sp = L.sp;
+  const int p3 = sp, p2 = sp + (v3 ? 1 : 0), p1 = p2 + (v2 ? 1 : 0);
+  if (!__any(act && sp + 3 > S.depth)) {
+    if (v3) {
+      S.ref[64 * p3] = ch[3];
+      S.tq[64 * p3] = t_down16(tn[3]);
+    }
+    if (v2) {
+      S.ref[64 * p2] = ch[2];
+      S.tq[64 * p2] = t_down16(tn[2]);
+    }
+    if (v1) {
+      S.ref[64 * p1] = ch[1];
+      S.tq[64 * p1] = t_down16(tn[1]);
+    }
+  } else {
+    const bool vk[3] = {v1, v2, v3};
+    const int pk[3] = {p1, p2, p3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (vk[k]) {
+        if (pk[k] < S.depth) {
+          S.ref[64 * pk[k]] = ch[k + 1];
+          S.tq[64 * pk[k]] = t_down16(tn[k + 1]);
+        } else {
+          spill[pk[k] - S.depth] = make_uint2(ch[k + 1], __float_as_uint(tn[k + 1]));
+        }
+      }
+    }
   }
-  L.cur = count > 1u ? make_leaf(first + 1u, count - 1u) : kEmpty;
-  advance(L, sc, S, spill);
+  L.sp = p1 + (v1 ? 1 : 0);
+  L.cur = act ? (tn[0] < kInfF ? ch[0] : kEmpty) : L.cur;
+}
+
+// Instance step on the lanes with `act` set: a top-level leaf -- transform the
+// ray and descend into the prototype's bottom-level root.  Other lanes read
+// record 0 and keep their state.
+template <bool COUNT>
+__device__ __forceinline__ void inst_step(bool act, Lane& L, const SceneView& sc, VisitCounters& vc) {
+  if (COUNT) vc.inst += act ? 1u : 0u;
+  Lane N = L;
+  uint32_t root;
+  enter_instance(N, sc, act ? leaf_first(L.cur) : 0u, &root);
+  L.ix = act ? N.ix : L.ix;
+  L.iy = act ? N.iy : L.iy;
+  L.iz = act ? N.iz : L.iz;
+  L.cnx = act ? N.cnx : L.cnx;
+  L.cny = act ? N.cny : L.cny;
+  L.cnz = act ? N.cnz : L.cnz;
+  L.cfx = act ? N.cfx : L.cfx;
+  L.cfy = act ? N.cfy : L.cfy;
+  L.cfz = act ? N.cfz : L.cfz;
+  L.lox = act ? N.lox : L.lox;
+  L.loy = act ? N.loy : L.loy;
+  L.loz = act ? N.loz : L.loz;
+  L.Sx = act ? N.Sx : L.Sx;
+  L.Sy = act ? N.Sy : L.Sy;
+  L.Sz = act ? N.Sz : L.Sz;
+  L.kz = act ? N.kz : L.kz;
+  L.rec = act ? N.rec : L.rec;
+  L.inst_sp = act ? L.sp : L.inst_sp;
+  L.cur = act ? root : L.cur;
+}
+
+// Quad step on the lanes with `act` set: test the first quad of the current
+// bottom-level leaf and keep the rest of the leaf as the current reference.
+template <bool COUNT>
+__device__ __forceinline__ void quad_step(bool act, Lane& L, const SceneView& sc, VisitCounters& vc) {
+  if (COUNT) vc.quads += act ? 1u : 0u;
+  const uint32_t first = leaf_first(L.cur), count = leaf_count(L.cur);
+  const bool answered = quad_test(L, sc, act, act ? first : 0u);
+  const uint32_t rest = count > 1u ? make_leaf(first + 1u, count - 1u) : kEmpty;
+  L.cur = act ? (answered ? kEmpty : rest) : L.cur;
+  L.done = L.done || answered;
+}
+
+// Pop step of the lanes whose current reference is empty: leave the instance
+// when its subtree is exhausted, then take the top entry unless it lies behind
+// the closest hit (the lane then pops again on its next step), or finish.
+__device__ __forceinline__ void pop_step(Lane& L, const SceneView& sc, const Stack& S, const uint2* spill) {
+  const bool need = !L.done && L.cur == kEmpty;
+  const bool leave = need && L.sp == L.inst_sp;
+  if (__any(leave)) {
+    Lane W = L;
+    set_world_level(W, sc);
+    L.ix = leave ? W.ix : L.ix;
+    L.iy = leave ? W.iy : L.iy;
+    L.iz = leave ? W.iz : L.iz;
+    L.cnx = leave ? W.cnx : L.cnx;
+    L.cny = leave ? W.cny : L.cny;
+    L.cnz = leave ? W.cnz : L.cnz;
+    L.cfx = leave ? W.cfx : L.cfx;
+    L.cfy = leave ? W.cfy : L.cfy;
+    L.cfz = leave ? W.cfz : L.cfz;
+    L.inst_sp = leave ? -1 : L.inst_sp;
+  }
+  const bool pop = need && L.sp > 0;
+  L.done = L.done || (need && L.sp == 0);
+  if (__any(pop)) {
+    const int sp = L.sp - (pop ? 1 : 0);
+    const int j = max(0, min(sp, S.depth - 1));
+    uint32_t ref = S.ref[64 * j];
+    float t = t_up32(S.tq[64 * j]);
+    if (pop && sp >= S.depth) {
+      const uint2 e = spill[sp - S.depth];
+      ref = e.x;
+      t = __uint_as_float(e.y);
+    }
+    L.sp = sp;
+    L.cur = (pop && t <= L.t_cull) ? ref : L.cur;
+  }
 }
 
 // Step kinds of a lane: 0 = traversal done, 1 = node test, 2 = instance entry,
-// 3 = quad test.
+// 3 = quad test, 4 = pop.
 __device__ __forceinline__ int step_kind(const Lane& L) {
   if (L.done) return 0;
+  if (L.cur == kEmpty) return 4;
   if (!ref_is_leaf(L.cur)) return 1;
   return L.inst_sp < 0 ? 2 : 3;
 }
 
+// Run the wave-uniform step kind `chosen` on the lanes whose own kind it is.  The
+// dispatch on `chosen` is a scalar branch and the steps are predicated, so no
+// lane state is merged through divergent control flow.
 template <int FMT, bool COUNT>
-__device__ __forceinline__ void run_step(int kind, Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
-                                         VisitCounters& vc) {
-  if (kind == 1) node_step<FMT, COUNT>(L, sc, S, spill, vc);
-  else if (kind == 2) inst_step<COUNT>(L, sc, vc);
-  else quad_step<COUNT>(L, sc, S, spill, vc);
+__device__ __forceinline__ void run_step(int chosen, int kind, Lane& L, const SceneView& sc, const Stack& S,
+                                         uint2* spill, VisitCounters& vc) {
+  if (chosen == 2) inst_step<COUNT>(kind == 2, L, sc, vc);
+  if (chosen == 1) node_step<FMT, COUNT>(kind == 1, L, sc, S, spill, vc);
+  if (chosen == 3) quad_step<COUNT>(kind == 3, L, sc, vc);
 }
 
 // Wave-uniform choice among the step kinds the participating lanes need: the
-// kind with the most lanes (ties favour node, then quad, then instance).
+// kind with the most lanes (ties favour node, then quad, then instance); 0 when
+// no lane needs one of them.
 __device__ __forceinline__ int vote_kind(int kind) {
   const int cn = __popcll(__ballot(kind == 1));
   const int ci = __popcll(__ballot(kind == 2));
@@ -559,13 +644,14 @@ __device__ __forceinline__ int vote_kind(int kind) {
 // One traversal step of the wave.  The lanes that take part vote: the wave runs
 // only the step kind (node test, instance entry or quad test) that most of them
 // need, the others wait.  Running one kind per iteration avoids paying for
-// every branch whenever any lane needs it.  Returns true once this lane is done.
+// every branch whenever any lane needs it.  Afterwards every lane without a
+// current reference pops one stack entry.  Returns true once this lane is done.
 template <int FMT, bool COUNT>
 __device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
   const int kind = step_kind(L);
-  const int chosen = vote_kind(kind);
-  if (chosen != 0 && kind == chosen) run_step<FMT, COUNT>(kind, L, sc, S, spill, vc);
+  run_step<FMT, COUNT>(vote_kind(kind), kind, L, sc, S, spill, vc);
+  pop_step(L, sc, S, spill);
   return L.done;
 }
 
