@@ -10,14 +10,19 @@ path with next-event estimation.  Inputs are seeded and synthetic and resident
 in HBM before timing starts.
 
 Reported (one JSON line):
-  value / ms_per_step  Mrays/s and ms/frame of the quantized-node persistent
-                       wavefront path (8-bit nodes, one launch per frame);
-  plain_fp32           the same for FP32 nodes and the multi-kernel scheduler,
-                       at bit-identical images;
+  value / ms_per_step  Mrays/s and ms/frame of the quantized wavefront (8-bit
+                       nodes; ray generation, shading and shadow resolution as
+                       kernels per bounce; closest-hit and shadow traversal as
+                       persistent lane-refilling kernels);
+  plain_fp32           the same for FP32 nodes and one-ray-per-lane traversal
+                       kernels, at bit-identical images;
+  ablation             node format x scheduler (plain, persistent stages,
+                       single persistent megakernel);
   incoherent           closest-hit throughput on the frame's bounce >= 1 rays,
                        quantized-persistent vs FP32-plain, at bit-identical hits;
-  roofline             algorithmic traversal bytes of the persistent kernel per
-                       launch over its measured duration, against 8 TB/s;
+  roofline             the frame's dominant kernel (closest-hit traversal of
+                       the bounce queues): algorithmic bytes per launch over its
+                       average launch time from HIP events, against 8 TB/s;
   cpu_baseline         the FP64 oracle on a bounded pixel sample, host cores.
 """
 import argparse
@@ -33,11 +38,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-B_NODE = {1: 128, 2: 64}   # bytes per 4-wide node: FP32, 8-bit
-B_INST = 64                # instance record
+# algorithmic bytes per ray of a traversal: ray in, hit out, and per visit
+B_NODE = {1: 128, 2: 64}   # 4-wide node: FP32, 8-bit
+B_INST = 56                # instance entry: FP32 inverse 3x4, BLAS root, prototype
 B_QUAD = 48                # four FP32 vertices
-B_RAY, B_HIT = 32, 20      # ray in, hit out
-B_SHADE = 4 + 48           # albedo + quad vertices for the normal, per shaded hit
+B_RAY, B_HIT = 32, 20
+DOMINANT = "k_trace_queue_persistent<Q8, closest-hit>"
+TRAFFIC_FILE = "traffic_trace_queue_q8_config2.md"
 
 
 def log(*a):
@@ -55,7 +62,7 @@ def kernel_sources_hash():
 def measured_traffic(kernel_key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
     when the kernels changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_render_persistent_q8_config2.md")
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -71,7 +78,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-pixels", type=int, default=2000000, help="pixels of the oracle's timed sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle's timed sample")
+    ap.add_argument("--cpu-pilot", type=int, default=4096, help="pixels of the pilot that sizes the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--incoherent-rays", type=int, default=16_000_000)
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
@@ -119,24 +127,29 @@ def main():
         st.frame = frame_idx
         rtq.render(S, cams, st, images=img, counters=counters, **kw)
 
-    def timed(kw, steps, warmup):
+    def timed(kw, steps, warmup, stage_timing=False):
         for i in range(warmup):
             frame(1000 + i, **kw)
         cnt = torch.zeros(4, dtype=torch.uint64, device="cuda")
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
+        if stage_timing:
+            rtq.render_timing(S)  # forget earlier timed calls
         w0 = time.perf_counter()
         for i in range(steps):
             evs[i][0].record()
-            frame(i, counters=cnt, **kw)
+            frame(i, counters=cnt, timing=stage_timing, **kw)
             evs[i][1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         ev_ms = [a.elapsed_time(b) for a, b in evs]
         c = cnt.cpu().numpy().astype(np.float64)
-        return dict(wall_ms=1e3 * wall / steps, ev_ms=float(np.mean(ev_ms)), ev_min=float(np.min(ev_ms)),
-                    ev_max=float(np.max(ev_ms)), closest=c[0] / steps, shadow=c[1] / steps,
-                    incoherent=c[2] / steps, rays=(c[0] + c[1]) / steps)
+        r = dict(wall_ms=1e3 * wall / steps, ev_ms=float(np.mean(ev_ms)), ev_min=float(np.min(ev_ms)),
+                 ev_max=float(np.max(ev_ms)), closest=c[0] / steps, shadow=c[1] / steps,
+                 incoherent=c[2] / steps, rays=(c[0] + c[1]) / steps)
+        if stage_timing:
+            r["stages"] = rtq.render_timing(S)
+        return r
 
     if args.profile:
         r = timed(Q8P, args.steps, args.warmup)
@@ -153,30 +166,38 @@ def main():
     assert equal_images, "quantized-persistent and FP32-plain images differ"
     visits = {}
     for name, kw in (("q8_persistent", Q8P), ("fp32_plain", F32)):
-        v = torch.zeros(4, dtype=torch.uint64, device="cuda")
+        v = torch.zeros(8, dtype=torch.uint64, device="cuda")
         cnt = torch.zeros(4, dtype=torch.uint64, device="cuda")
         st.frame = 0
         rtq.render(S, cams, st, images=img, counters=cnt, visits=v, **kw)
         torch.cuda.synchronize()
         vv = v.cpu().numpy().astype(np.float64)
         cc = cnt.cpu().numpy().astype(np.float64)
-        visits[name] = dict(tlas=vv[0], inst=vv[1], blas=vv[2], quads=vv[3], closest=cc[0], shadow=cc[1])
+        visits[name] = dict(closest=dict(zip(("tlas", "inst", "blas", "quads"), vv[:4]), rays=cc[0]),
+                            shadow=dict(zip(("tlas", "inst", "blas", "quads"), vv[4:]), rays=cc[1]))
     log(f"visits: {visits}")
 
-    # ---- timed frames
-    q8 = timed(Q8P, args.steps, args.warmup)
+    # ---- timed frames (the quantized wavefront with HIP events around its stages)
+    q8 = timed(Q8P, args.steps, args.warmup, stage_timing=True)
     log(f"q8 persistent: {q8}")
     f32 = timed(F32, args.steps, args.warmup)
     log(f"fp32 plain: {f32}")
     ablation = {}
-    for name, kw in (("q8_plain", dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PLAIN)),
-                     ("fp32_persistent", dict(node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PERSISTENT))):
-        r = timed(kw, max(3, args.steps // 2), 1)
-        ablation[name] = dict(ms_per_frame=r["wall_ms"], mrays_s=r["rays"] / (r["wall_ms"] * 1e3))
-    ablation["q8_persistent"] = dict(ms_per_frame=q8["wall_ms"], mrays_s=q8["rays"] / (q8["wall_ms"] * 1e3))
-    ablation["fp32_plain"] = dict(ms_per_frame=f32["wall_ms"], mrays_s=f32["rays"] / (f32["wall_ms"] * 1e3))
+    for fname, fmt in (("q8", rtq.RTQ_NODE_Q8), ("fp32", rtq.RTQ_NODE_FP32)):
+        for sname, sch in (("plain", rtq.SCHED_PLAIN), ("persistent", rtq.SCHED_PERSISTENT),
+                           ("megakernel", rtq.SCHED_MEGAKERNEL)):
+            key = f"{fname}_{sname}"
+            if key == "q8_persistent":
+                r = q8
+            elif key == "fp32_plain":
+                r = f32
+            else:
+                r = timed(dict(node_format=fmt, scheduler=sch), max(3, args.steps // 2), 1)
+            ablation[key] = dict(ms_per_frame=r["wall_ms"], mrays_s=r["rays"] / (r["wall_ms"] * 1e3))
+    log(f"ablation: {ablation}")
 
     # ---- incoherent rays: bounce >= 1 extension rays of frame 0
+    log("incoherent rays: dumping bounce >= 1 rays")
     cap = args.incoherent_rays
     dump = torch.empty(8 * cap, device="cuda")
     dcount = torch.zeros(1, dtype=torch.uint64, device="cuda")
@@ -184,8 +205,7 @@ def main():
     rtq.render(S, cams, st, images=img, dump_rays=dump, dump_count=dcount, **F32)
     torch.cuda.synchronize()
     nd = int(min(int(dcount.cpu().item()), cap))
-    rays = dump.view(8, cap)[:, :nd].t()  # [n, 8] view of the SoA dump (copied to SoA again by the binding)
-    rays = rays.contiguous()
+    rays = dump.view(8, cap)[:, :nd].t().contiguous()
     inc = {}
     hits_ref = None
     for name, kw in (("fp32_plain", dict(node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PLAIN)),
@@ -199,31 +219,48 @@ def main():
                        for k in ("t", "u", "v", "inst", "prim"))
             assert same, "incoherent hits differ between node formats / schedulers"
         reps = max(3, args.steps // 2)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        w0 = time.perf_counter()
+        ev0.record()
         for _ in range(reps):
             rtq.trace_closest(S, rays, **kw)
+        ev1.record()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - w0) / reps
+        dt = ev0.elapsed_time(ev1) * 1e-3 / reps
         inc[name] = dict(ms=1e3 * dt, mrays_s=nd / dt / 1e6)
     log(f"incoherent ({nd} rays): {inc}")
 
-    # ---- roofline of the persistent kernel (algorithmic bytes per launch)
-    v = visits["q8_persistent"]
-    alg_bytes = ((v["closest"] + v["shadow"]) * (B_RAY + B_HIT) + v["tlas"] * B_NODE[2] + v["inst"] * B_INST +
-                 v["blas"] * B_NODE[2] + v["quads"] * B_QUAD + v["closest"] * B_SHADE)
-    kern_s = q8["ev_ms"] * 1e-3
-    achieved = alg_bytes / kern_s / 1e9
+    # ---- roofline of the dominant kernel: closest-hit traversal of the bounce
+    # queues, one launch per bounce; per launch = per frame / launches per frame
+    v = visits["q8_persistent"]["closest"]
+    frame_bytes = (v["rays"] * (B_RAY + B_HIT) + v["tlas"] * B_NODE[2] + v["inst"] * B_INST +
+                   v["blas"] * B_NODE[2] + v["quads"] * B_QUAD)
+    stg = q8["stages"]["closest"]
+    launches_per_frame = stg["launches"] / args.steps
+    alg_bytes = frame_bytes / launches_per_frame
+    kern_ms = stg["ms"] / stg["launches"]
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     tr = measured_traffic(kernel_sources_hash())
 
-    # ---- CPU baseline: the oracle on a bounded sample of the same frame
+    # ---- CPU baseline: the oracle on a bounded sample of the same frame, sized
+    # from a short pilot so that the timed sample takes about cpu_seconds
     cpu = None
     if not args.no_cpu:
         import oracle
+        log("cpu baseline: building the oracle scene")
         o = oracle.OracleScene(scene)
         rng = np.random.default_rng(0)
-        pix = np.sort(rng.choice(n_pix, size=min(args.cpu_pixels, n_pix), replace=False))
+        order = rng.permutation(n_pix)
         st.frame = 0
+        # untimed warm-up (the oracle builds its per-prototype BVHs on first use)
+        o.render(cams, st, pixels=np.sort(order[-min(args.cpu_pilot, n_pix):]))
+        pilot = np.sort(order[:min(args.cpu_pilot, n_pix)])
+        w0 = time.perf_counter()
+        o.render(cams, st, pixels=pilot)
+        dt0 = time.perf_counter() - w0
+        n_cpu = int(min(n_pix, max(pilot.size, pilot.size * args.cpu_seconds / max(dt0, 1e-3))))
+        log(f"cpu baseline: pilot {pilot.size} px in {dt0:.1f} s; timing {n_cpu} px")
+        pix = np.sort(order[:n_cpu])
         w0 = time.perf_counter()
         _, fl, stats = o.render(cams, st, pixels=pix)
         dt = time.perf_counter() - w0
@@ -251,7 +288,8 @@ def main():
         "config": {
             "workload": "config2: 256 prototypes + 2048^2 terrain (%d unique quads), %d instances, "
                         "2 views 1920x1080, 1 spp, depth 8" % (scene.n_quads, scene.n_instances),
-            "node_format": "q8", "scheduler": "persistent", "parallelism": "single GPU",
+            "node_format": "q8", "scheduler": "wavefront, persistent traversal stages",
+            "parallelism": "single GPU",
         },
         "rays_per_frame": q8["rays"],
         "rays_per_pixel": q8["rays"] / n_pix,
@@ -264,12 +302,13 @@ def main():
                        "fp32_plain_mrays_s": round(inc["fp32_plain"]["mrays_s"], 2),
                        "speedup": round(inc["q8_persistent"]["mrays_s"] / inc["fp32_plain"]["mrays_s"], 3)},
         "ablation": {k: {kk: round(vv, 3) for kk, vv in d.items()} for k, d in ablation.items()},
+        "stages_ms_per_frame": {k: round(d["ms"] / args.steps, 3) for k, d in q8["stages"].items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if tr is None else tr,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "k_render_persistent<Q8>", "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel_ms": round(q8["ev_ms"], 3)},
+                     "kernel": DOMINANT, "algorithmic_bytes_per_launch": alg_bytes,
+                     "launches_per_frame": launches_per_frame, "kernel_ms": round(kern_ms, 3)},
         "cpu_baseline": cpu,
         "scene": {"build_s": round(info["build_seconds"], 2), "device_gib": round(info["device_bytes"] / 2**30, 3)},
     }

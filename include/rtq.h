@@ -144,9 +144,9 @@ typedef struct {
 typedef struct {
   int32_t node_format; /* RTQ_NODE_FP32 or RTQ_NODE_Q8; 0 = Q8 if built, else FP32 */
   int32_t scheduler;   /* RTQ_SCHED_* */
-  int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 16 */
+  int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 20 */
   int32_t block;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
-  int32_t waves_per_cu;/* persistent scheduler: resident waves per CU; 0 = 16 */
+  int32_t waves_per_cu;/* persistent scheduler: resident waves per CU; 0 = 24 */
   int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 16 */
   uint32_t* visits;    /* optional device n x 4 counters: top nodes, instances entered,
                           bottom nodes, quads tested (slower kernel variant) */
@@ -197,15 +197,19 @@ typedef struct {
   uint64_t* view_done; /* optional device [n_cams]: wall-clock tick at which each
                           view's last path finished (megakernel scheduler only) */
   uint64_t* start_tick;/* optional device [1]: wall-clock tick at kernel start */
-  uint64_t* visits;    /* optional device [4]: top-level nodes, instances entered,
-                          bottom-level nodes and quads tested, summed over every
-                          ray (accumulated; selects a slower counting variant) */
+  uint64_t* visits;    /* optional device [8]: top-level nodes, instances entered,
+                          bottom-level nodes and quads tested, summed over the
+                          closest-hit rays ([0..3]) and over the shadow rays
+                          ([4..7]) (accumulated; selects a slower counting variant) */
   float* dump_rays;    /* optional device 8 x dump_cap floats, structure of arrays
                           (ox, oy, oz, dx, dy, dz, tmin, tmax): extension rays of
                           bounce >= 1 (plain and persistent schedulers) */
   int64_t dump_cap;    /* capacity of dump_rays in rays */
   uint64_t* dump_count;/* device [1]: rays appended to dump_rays (accumulated; the
                           count may exceed dump_cap, rays beyond it are dropped) */
+  int32_t timing;      /* nonzero: record HIP events around the call's kernel
+                          launches on `stream` (no synchronisation); read them
+                          with rtq_render_timing */
 } rtq_render_opts;
 
 /*
@@ -221,6 +225,18 @@ typedef struct {
  */
 int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
                const rtq_render_opts* opts, float* images, hipStream_t stream);
+
+/*
+ * Kernel time of the render calls made with opts->timing set since the previous
+ * query, by stage: ms[0] closest-hit traversal launches (the megakernel launch
+ * under RTQ_SCHED_MEGAKERNEL), ms[1] shadow-ray traversal launches, ms[2] every
+ * other launch (ray generation, shading, shadow resolve, accumulation), ms[3]
+ * whole calls (first to last recorded event).  launches[k] counts the launches
+ * in ms[k] (launches[3] = calls).  Waits for the recorded events, then forgets
+ * them.  ms, launches: host arrays of 4, either may be NULL.  The event log
+ * holds at most 4096 events; calls beyond it are not timed (launches tells).
+ */
+int rtq_render_timing(rtq_scene* scene, float* ms, int32_t* launches);
 
 /*
  * Adjoint of rtq_render with respect to per-face albedo, paths held fixed:

@@ -82,7 +82,8 @@ class _RenderOpts(ctypes.Structure):
                 ("scheduler", ctypes.c_int32), ("stack_depth", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32), ("counters", ctypes.c_void_p),
                 ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
-                ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p)]
+                ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p),
+                ("timing", ctypes.c_int32)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -117,6 +118,7 @@ def load_library():
     L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
     L.rtq_render.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
     L.rtq_render_backward.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+    L.rtq_render_timing.argtypes = [P, P, P]
     for f in EXPORTS:
         if f not in ("rtq_last_error", "rtq_version", "rtq_scene_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -288,7 +290,8 @@ def camera_structs(cams) -> tuple:
 
 
 def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
-                counters=None, view_done=None, start_tick=None, visits=None, dump_rays=None, dump_count=None):
+                counters=None, view_done=None, start_tick=None, visits=None, dump_rays=None, dump_count=None,
+                timing=False):
     o = _RenderOpts()
     o.seed = int(settings.seed)
     o.frame = int(settings.frame)
@@ -308,6 +311,7 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.dump_rays = _ptr(dump_rays)
     o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 8
     o.dump_count = _ptr(dump_count)
+    o.timing = 1 if timing else 0
     return o
 
 
@@ -322,6 +326,17 @@ def render(scene: Scene, cams, settings, images=None, **opts):
     _check(load_library().rtq_render(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
                                      settings.depth, ctypes.byref(o), images.data_ptr(), _stream()))
     return images
+
+
+def render_timing(scene: Scene) -> dict:
+    """Kernel milliseconds and launch counts, by stage, of the render calls made
+    with timing=True since the previous query (waits for their events)."""
+    ms = (ctypes.c_float * 4)()
+    n = (ctypes.c_int32 * 4)()
+    _check(load_library().rtq_render_timing(scene.handle, ctypes.cast(ms, ctypes.c_void_p),
+                                            ctypes.cast(n, ctypes.c_void_p)))
+    names = ("closest", "shadow", "other", "call")
+    return {k: {"ms": float(ms[i]), "launches": int(n[i])} for i, k in enumerate(names)}
 
 
 def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None, **opts):

@@ -84,10 +84,10 @@ int resolve_format(const rtq_scene* s, int32_t req, int* fmt) {
 int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t block, int32_t waves, int32_t refill,
                    TraceLaunch* tl) {
   tl->persistent = sched;
-  tl->stack_depth = depth ? depth : 16;
+  tl->stack_depth = depth ? depth : 20;
   tl->block = block ? block : 256;
   tl->refill = refill ? refill : 16;
-  const int w = waves ? waves : 16;
+  const int w = waves ? waves : 24;
   if (sched != RTQ_SCHED_PLAIN && sched != RTQ_SCHED_PERSISTENT)
     return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", sched);
   if (tl->stack_depth < 4 || tl->stack_depth > 64)

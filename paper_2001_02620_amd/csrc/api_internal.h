@@ -58,6 +58,7 @@ struct rtq_scene {
   rtq::DeviceBuffers scratch;
   size_t scratch_paths = 0;
   void* render_state = nullptr;
+  void* stage_log = nullptr;  // HIP events of timed render calls (rtq_render_timing)
 };
 
 namespace rtq {

@@ -26,6 +26,67 @@ struct RenderScratch {
   PlainBuffers pb{};
 };
 
+}  // namespace
+
+namespace rtq {
+// Events recorded around the launches of timed render calls.  Events are pooled
+// and reused after a query; the pool is capped so that a caller who never queries
+// cannot grow it without bound.
+struct StageLog {
+  static constexpr size_t kMaxEvents = 4096;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> all, free_list;
+  std::vector<Rec> recs;
+  hipEvent_t call_first = nullptr, call_last = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> calls;
+  int dropped = 0;
+  hipEvent_t take() {
+    if (!free_list.empty()) {
+      hipEvent_t e = free_list.back();
+      free_list.pop_back();
+      return e;
+    }
+    if (all.size() >= kMaxEvents) return nullptr;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    all.push_back(e);
+    return e;
+  }
+  ~StageLog() {
+    for (hipEvent_t e : all) (void)hipEventDestroy(e);
+  }
+};
+
+hipEvent_t stage_begin(StageLog* log, hipStream_t s) {
+  if (!log) return nullptr;
+  hipEvent_t e = log->take();
+  if (!e) {
+    ++log->dropped;
+    return nullptr;
+  }
+  (void)hipEventRecord(e, s);
+  if (!log->call_first) log->call_first = e;
+  return e;
+}
+
+void stage_end(StageLog* log, int stage, hipEvent_t begin, hipStream_t s) {
+  if (!log || !begin) return;
+  hipEvent_t e = log->take();
+  if (!e) {
+    ++log->dropped;
+    return;
+  }
+  (void)hipEventRecord(e, s);
+  log->recs.push_back({stage, begin, e});
+  log->call_last = e;
+}
+}  // namespace rtq
+
+namespace {
+
 RenderScratch* scratch_of(rtq_scene* s) {
   if (!s->render_state) s->render_state = new RenderScratch;
   return static_cast<RenderScratch*>(s->render_state);
@@ -202,6 +263,10 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
 
 namespace rtq {
 void release_render_scratch(rtq_scene* s) {
+  if (s->stage_log) {
+    delete static_cast<StageLog*>(s->stage_log);
+    s->stage_log = nullptr;
+  }
   if (s->render_state) {
     RenderScratch* r = static_cast<RenderScratch*>(s->render_state);
     r->bufs.release();
@@ -233,6 +298,15 @@ int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32
   ex.dump_count = reinterpret_cast<unsigned long long*>(opts->dump_count);
   ex.view_done = reinterpret_cast<unsigned long long*>(opts->view_done);
   ex.start_tick = reinterpret_cast<unsigned long long*>(opts->start_tick);
+  ex.log = nullptr;
+  std::unique_lock<std::mutex> log_lock;
+  if (opts->timing) {
+    rtq_scene* ms = const_cast<rtq_scene*>(s);
+    log_lock = std::unique_lock<std::mutex>(ms->scratch_mu);
+    if (!ms->stage_log) ms->stage_log = new StageLog;
+    ex.log = static_cast<StageLog*>(ms->stage_log);
+    ex.log->call_first = ex.log->call_last = nullptr;
+  }
   hipError_t e;
   if (staged) {
     RenderScratch* r = scratch_of(const_cast<rtq_scene*>(s));
@@ -240,7 +314,48 @@ int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32
   } else {
     e = launch_render_megakernel(sv, p.rp, p.fmt, p.tl, images, p.n_pixels, ex, stream);
   }
+  if (ex.log && ex.log->call_first && ex.log->call_last)
+    ex.log->calls.push_back({ex.log->call_first, ex.log->call_last});
   return e == hipSuccess ? RTQ_OK : hip_error(e, "render launch");
+}
+
+int rtq_render_timing(rtq_scene* s, float* ms, int32_t* launches) {
+  if (!s) return set_error(RTQ_E_INVALID_ARG, "NULL scene");
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  int32_t cnt[4] = {0, 0, 0, 0};
+  std::lock_guard<std::mutex> lock(s->scratch_mu);
+  StageLog* log = static_cast<StageLog*>(s->stage_log);
+  int rc = RTQ_OK;
+  if (log) {
+    for (const StageLog::Rec& r : log->recs) {
+      float t = 0.0f;
+      hipError_t e = hipEventSynchronize(r.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+      if (e != hipSuccess) {
+        rc = hip_error(e, "stage event");
+        break;
+      }
+      acc[r.stage] += t;
+      ++cnt[r.stage];
+    }
+    for (const auto& c : log->calls) {
+      float t = 0.0f;
+      if (rc == RTQ_OK && hipEventSynchronize(c.second) == hipSuccess &&
+          hipEventElapsedTime(&t, c.first, c.second) == hipSuccess) {
+        acc[3] += t;
+        ++cnt[3];
+      }
+    }
+    log->free_list = log->all;
+    log->recs.clear();
+    log->calls.clear();
+    log->dropped = 0;
+  }
+  if (ms)
+    for (int k = 0; k < 4; ++k) ms[k] = acc[k];
+  if (launches)
+    for (int k = 0; k < 4; ++k) launches[k] = cnt[k];
+  return rc;
 }
 
 int rtq_render_backward(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,

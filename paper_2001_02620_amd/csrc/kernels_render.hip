@@ -322,7 +322,9 @@ __global__ __attribute__((amdgpu_waves_per_eu(5))) void k_render_persistent(Scen
   const Stack S = make_stack(lds, depth_lds);
   uint2 spill[kStackTotal];
   Lane L;
-  VisitCounters vc{0, 0, 0, 0};
+  VisitCounters vc{0, 0, 0, 0};      // current traversal
+  VisitCounters vc_sh{0, 0, 0, 0};   // finished shadow traversals (closest-hit ones stay in vc_cl)
+  VisitCounters vc_cl{0, 0, 0, 0};
   PathLane P{};
   bool has = false, exhausted = false;
   uint32_t n_ext = 0, n_sh = 0, n_inc = 0, n_paths = 0;
@@ -373,6 +375,14 @@ __global__ __attribute__((amdgpu_waves_per_eu(5))) void k_render_persistent(Scen
         const int cmax = ct == 0 ? 0 : __popcll(__ballot(kind == ct));
         if (cs > 0 && cs >= cmax) {
           if (kind == 0) {
+            if (COUNT) {
+              VisitCounters& acc = P.shadow ? vc_sh : vc_cl;
+              acc.tlas += vc.tlas;
+              acc.inst += vc.inst;
+              acc.blas += vc.blas;
+              acc.quads += vc.quads;
+              vc = VisitCounters{0, 0, 0, 0};
+            }
             bool path_done = false;
             if (!P.shadow) {
               if (L.b_rec == kEmpty) {
@@ -442,7 +452,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(5))) void k_render_persistent(Scen
       }
     }
   }
-  if (COUNT) wave_add_visits(vc, visits);
+  if (COUNT) {
+    wave_add_visits(vc_cl, visits);
+    wave_add_visits(vc_sh, visits + 4);
+  }
   if (counters) {
     // wave reduction, one atomic per counter per wave
     unsigned long long v[4] = {n_ext, n_sh, n_inc, n_paths};
@@ -542,6 +555,8 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
   uint32_t* cin = pb.counts + b;
   uint32_t* cout = pb.counts + b + 1;
   uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
+  unsigned long long* vis_sh = ex.visits ? ex.visits + 4 : nullptr;
+  hipEvent_t ev = stage_begin(ex.log, s);
   if (tl.persistent) {
     hipLaunchKernelGGL((k_trace_queue_persistent<FMT, false, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
                        qin, pb.sq, cin, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b, ex.visits);
@@ -550,27 +565,36 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
     hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
                        cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
   }
+  stage_end(ex.log, 0, ev, s);
+  ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
                      ex.dump, ex.dump_cap, ex.dump_count);
+  stage_end(ex.log, 2, ev, s);
+  ev = stage_begin(ex.log, s);
   if (tl.persistent) {
     hipLaunchKernelGGL((k_trace_queue_persistent<FMT, true, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                       qin, pb.sq, csq, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b + 1, ex.visits);
+                       qin, pb.sq, csq, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b + 1, vis_sh);
   } else {
     const unsigned gt = blocks(rp.n_paths, tl.block);
     hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
-                       csq, pb.hits, pb.occ, tl.stack_depth, ex.visits);
+                       csq, pb.hits, pb.occ, tl.stack_depth, vis_sh);
   }
+  stage_end(ex.log, 1, ev, s);
+  ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+  stage_end(ex.log, 2, ev, s);
 }
 
 hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
                                    const TraceLaunch& tl, float* image, int64_t n_pixels, const RenderExtras& ex,
                                    hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
+  hipEvent_t ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, pb.counts, 2 * kMaxDepth + 2);
   hipError_t e = launch_zero_u64(pb.work, 2 * kMaxDepth, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
+  stage_end(ex.log, 2, ev, s);
   const bool cnt = ex.visits != nullptr;
   for (int b = 0; b < rp.depth; ++b) {
     if (fmt == 2) {
@@ -581,9 +605,11 @@ hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, 
       else wavefront_bounce<1, false>(sc, rp, pb, b, tl, ex, s);
     }
   }
+  ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
   if (ex.counters)
     hipLaunchKernelGGL(k_plain_stats, dim3(1), dim3(64), 0, s, pb.counts, rp.depth, rp.n_paths, ex.counters);
+  stage_end(ex.log, 2, ev, s);
   return hipGetLastError();
 }
 
@@ -597,9 +623,12 @@ static void persistent_launch(const SceneView& sc, const RenderParams& rp, const
 
 hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
                                     float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s) {
+  hipEvent_t ev = stage_begin(ex.log, s);
   hipError_t e = launch_zero_u64(tl.counter, 1, s);
   if (e != hipSuccess) return e;
   if (ex.start_tick) hipLaunchKernelGGL(k_start_tick, dim3(1), dim3(64), 0, s, ex.start_tick);
+  stage_end(ex.log, 2, ev, s);
+  ev = stage_begin(ex.log, s);
   const bool ts = ex.view_done != nullptr, cnt = ex.visits != nullptr;
   if (fmt == 2) {
     if (cnt) {
@@ -618,7 +647,10 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
       else persistent_launch<1, false, false>(sc, rp, tl, ex, s);
     }
   }
+  stage_end(ex.log, 0, ev, s);
+  ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
+  stage_end(ex.log, 2, ev, s);
   return hipGetLastError();
 }
 

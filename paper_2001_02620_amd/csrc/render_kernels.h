@@ -43,15 +43,24 @@ struct PlainBuffers {
   unsigned long long* work;  // [2 kMaxDepth]: claim counters of the persistent queue traversals
 };
 
+// Host-side log of HIP events around a render call's launches (owned by the
+// scene).  stage_begin returns nullptr when log is nullptr or full; stage_end
+// records the matching end event and files the pair under `stage`
+// (0 closest-hit traversal, 1 shadow traversal, 2 other).
+struct StageLog;
+hipEvent_t stage_begin(StageLog* log, hipStream_t s);
+void stage_end(StageLog* log, int stage, hipEvent_t begin, hipStream_t s);
+
 // Optional instrumentation of a render call.
 struct RenderExtras {
   unsigned long long* counters;    // [4] closest, shadow, incoherent rays, paths
-  unsigned long long* visits;      // [4] top nodes, instances, bottom nodes, quads
+  unsigned long long* visits;      // [8] top nodes, instances, bottom nodes, quads: closest-hit rays, then shadow rays
   float* dump;                     // 8 x dump_cap SoA
   long long dump_cap;
   unsigned long long* dump_count;
   unsigned long long* view_done;
   unsigned long long* start_tick;
+  StageLog* log;                   // event log of a timed call, or nullptr
 };
 
 // Multi-kernel wavefront frame; tl.persistent selects lane-refilling traversal stages.
