@@ -220,7 +220,6 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   // ---- concatenate the bottom levels with absolute references
   std::vector<uint32_t> proto_root(n_protos), face_base(n_protos);
   std::vector<int32_t> proto_qbase(n_protos), proto_nq(n_protos);
-  std::vector<float> proto_box(6 * (size_t)n_protos);
   std::vector<float> proto_pmax(n_protos);
   uint64_t node_base = 0, quad_base = 0;
   int max_blas_depth = 0;
@@ -237,10 +236,6 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     face_base[p] = (uint32_t)quad_base;  // original-order face offset equals the leaf-order quad offset
     proto_qbase[p] = (int32_t)quad_base;
     proto_nq[p] = protos[p].n_quads;
-    for (int a = 0; a < 3; ++a) {
-      proto_box[6 * p + a] = blas[p].root_box.lo[a];
-      proto_box[6 * p + 3 + a] = blas[p].root_box.hi[a];
-    }
     proto_pmax[p] = level_pmax(blas[p]);
     if (!(proto_pmax[p] < kMaxPlaneAbs)) {
       delete s;
@@ -309,7 +304,8 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   float* d_x = nullptr;
   int32_t* d_proto = nullptr;
   uint32_t *d_root = nullptr, *d_face = nullptr;
-  float *d_pbox = nullptr, *d_cond = nullptr, *d_box = nullptr;
+  float *d_verts = nullptr, *d_cond = nullptr, *d_box = nullptr;
+  int64_t* d_voff = nullptr;
   int32_t* d_status = nullptr;
   InstRec* d_rec = nullptr;
   DeviceBuffers tmp;
@@ -331,7 +327,10 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   TALLOC(d_proto, Nn * sizeof(int32_t));
   TALLOC(d_root, n_protos * sizeof(uint32_t));
   TALLOC(d_face, n_protos * sizeof(uint32_t));
-  TALLOC(d_pbox, 6 * n_protos * sizeof(float));
+  std::vector<int64_t> vert_off(n_protos + 1, 0);
+  for (int32_t p = 0; p < n_protos; ++p) vert_off[p + 1] = vert_off[p] + protos[p].n_verts;
+  TALLOC(d_verts, std::max<int64_t>(3 * vert_off[n_protos], 1) * sizeof(float));
+  TALLOC(d_voff, (n_protos + 1) * sizeof(int64_t));
   TALLOC(d_cond, Nn * sizeof(float));
   TALLOC(d_box, 6 * Nn * sizeof(float));
   TALLOC(d_status, Nn * sizeof(int32_t));
@@ -342,9 +341,14 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   }
   TCHECK(hipMemcpy(d_root, proto_root.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
   TCHECK(hipMemcpy(d_face, face_base.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
-  TCHECK(hipMemcpy(d_pbox, proto_box.data(), 6 * n_protos * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  for (int32_t p = 0; p < n_protos; ++p)
+    if (protos[p].n_verts > 0)
+      TCHECK(hipMemcpy(d_verts + 3 * vert_off[p], protos[p].verts, 3 * (size_t)protos[p].n_verts * sizeof(float),
+                       hipMemcpyHostToDevice),
+             "hipMemcpy");
+  TCHECK(hipMemcpy(d_voff, vert_off.data(), (n_protos + 1) * sizeof(int64_t), hipMemcpyHostToDevice), "hipMemcpy");
   TCHECK(launch_invert_affine(d_x, d_proto, d_root, d_face, N, d_rec, d_cond, d_status, 0), "invert kernel");
-  TCHECK(launch_instance_aabb(d_x, d_proto, d_pbox, d_cond, N, d_box, 0), "aabb kernel");
+  TCHECK(launch_instance_aabb(d_x, d_proto, d_verts, d_voff, d_cond, N, d_box, 0), "aabb kernel");
   std::vector<int32_t> status(N);
   std::vector<float> cond(N);
   std::vector<Aabb> boxes(N);

@@ -57,27 +57,54 @@ __global__ void k_invert_affine_fp64(const float* __restrict__ X, const int32_t*
   status[i] = ok ? 0 : 1;
 }
 
-// World box of each instance: the eight corners of the prototype's object box
-// mapped through the FP64 transform, padded by 2^-17 cond (|t| + |box|) for the
-// FP32 ray-transform error, rounded outward to FP32.
-__global__ void k_instance_aabb(const float* __restrict__ X, const int32_t* __restrict__ proto,
-                                const float* __restrict__ proto_box, const float* __restrict__ cond, int64_t n,
-                                float* __restrict__ box) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// World box of each instance: the exact bounds of its prototype's vertices mapped
+// through the FP64 transform (one block per instance; every quad lies in the
+// convex hull of its vertices), padded by 2^-17 cond (|t| + |box|) for the FP32
+// ray-transform error and rounded outward to FP32.  For rotated instances this
+// is much tighter than the box of the eight transformed corners of the
+// prototype's object box.
+__global__ void __launch_bounds__(256) k_instance_aabb(const float* __restrict__ X, const int32_t* __restrict__ proto,
+                                                       const float* __restrict__ verts,
+                                                       const int64_t* __restrict__ vert_off,
+                                                       const float* __restrict__ cond, int64_t n,
+                                                       float* __restrict__ box) {
+  const int64_t i = blockIdx.x;
   if (i >= n) return;
   const float* x = X + 12 * i;
-  const float* pb = proto_box + 6 * proto[i];
+  double m[12];
+  for (int j = 0; j < 12; ++j) m[j] = (double)x[j];
+  const int32_t p = proto[i];
+  const int64_t v0 = vert_off[p], v1 = vert_off[p + 1];
   double lo[3] = {1e308, 1e308, 1e308}, hi[3] = {-1e308, -1e308, -1e308};
-  for (int c = 0; c < 8; ++c) {
-    const double v[3] = {(c & 1) ? pb[3] : pb[0], (c & 2) ? pb[4] : pb[1], (c & 4) ? pb[5] : pb[2]};
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+    const double a = verts[3 * v], b = verts[3 * v + 1], c = verts[3 * v + 2];
     for (int r = 0; r < 3; ++r) {
-      const double w = (double)x[4 * r] * v[0] + (double)x[4 * r + 1] * v[1] + (double)x[4 * r + 2] * v[2] +
-                       (double)x[4 * r + 3];
+      const double w = m[4 * r] * a + m[4 * r + 1] * b + m[4 * r + 2] * c + m[4 * r + 3];
       lo[r] = fmin(lo[r], w);
       hi[r] = fmax(hi[r], w);
     }
   }
-  double mag = fmax(fmax(fabs((double)x[3]), fabs((double)x[7])), fabs((double)x[11]));
+  // block reduction: wave shuffles, then one value per wave in LDS
+  for (int o = 32; o > 0; o >>= 1)
+    for (int r = 0; r < 3; ++r) {
+      lo[r] = fmin(lo[r], __shfl_xor(lo[r], o));
+      hi[r] = fmax(hi[r], __shfl_xor(hi[r], o));
+    }
+  __shared__ double red[4][6];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+    for (int r = 0; r < 3; ++r) {
+      red[wave][r] = lo[r];
+      red[wave][3 + r] = hi[r];
+    }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+    for (int r = 0; r < 3; ++r) {
+      lo[r] = fmin(lo[r], red[w][r]);
+      hi[r] = fmax(hi[r], red[w][3 + r]);
+    }
+  double mag = fmax(fmax(fabs(m[3]), fabs(m[7])), fabs(m[11]));
   for (int r = 0; r < 3; ++r) mag = fmax(mag, fmax(fabs(lo[r]), fabs(hi[r])));
   const double pad = ldexp(1.0, -17) * (double)cond[i] * mag;
   for (int r = 0; r < 3; ++r) {
@@ -109,10 +136,10 @@ hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint
   return hipGetLastError();
 }
 
-hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const float* proto_box, const float* cond,
-                                int64_t n, float* box, hipStream_t s) {
+hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const float* verts, const int64_t* vert_off,
+                                const float* cond, int64_t n, float* box, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_instance_aabb, dim3(grid_for(n, 256)), dim3(256), 0, s, X, proto, proto_box, cond, n, box);
+  hipLaunchKernelGGL(k_instance_aabb, dim3((unsigned)n), dim3(256), 0, s, X, proto, verts, vert_off, cond, n, box);
   return hipGetLastError();
 }
 
