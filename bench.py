@@ -20,8 +20,9 @@ Reported (one JSON line):
                        single persistent megakernel);
   incoherent           closest-hit throughput on the frame's bounce >= 1 rays,
                        quantized-persistent vs FP32-plain, at bit-identical hits;
-  roofline             the frame's dominant kernel (closest-hit traversal of
-                       the bounce queues): algorithmic bytes per launch over its
+  roofline             the frame's dominant kernel (the traversal launches, each
+                       tracing a bounce's shadow rays with the next bounce's
+                       extension rays): algorithmic bytes per launch over its
                        average launch time from HIP events, against 8 TB/s;
   cpu_baseline         the FP64 oracle on a bounded pixel sample, host cores.
 """
@@ -43,8 +44,8 @@ B_NODE = {1: 128, 2: 64}   # 4-wide node: FP32, 8-bit
 B_INST = 56                # instance entry: FP32 inverse 3x4, BLAS root, prototype
 B_QUAD = 48                # four FP32 vertices
 B_RAY, B_HIT = 32, 20
-DOMINANT = "k_trace_queue_persistent<Q8, closest-hit>"
-TRAFFIC_FILE = "traffic_trace_queue_q8_config2.md"
+DOMINANT = "k_trace_queue_mixed<Q8> (shadow rays of bounce b + extension rays of bounce b+1)"
+TRAFFIC_FILE = "traffic_trace_queue_mixed_q8_config2.md"
 
 
 def log(*a):
@@ -230,11 +231,14 @@ def main():
         inc[name] = dict(ms=1e3 * dt, mrays_s=nd / dt / 1e6)
     log(f"incoherent ({nd} rays): {inc}")
 
-    # ---- roofline of the dominant kernel: closest-hit traversal of the bounce
-    # queues, one launch per bounce; per launch = per frame / launches per frame
-    v = visits["q8_persistent"]["closest"]
-    frame_bytes = (v["rays"] * (B_RAY + B_HIT) + v["tlas"] * B_NODE[2] + v["inst"] * B_INST +
-                   v["blas"] * B_NODE[2] + v["quads"] * B_QUAD)
+    # ---- roofline of the dominant kernel: the traversal launches of the frame
+    # (depth + 1 per frame, each tracing one bounce's shadow rays and the next
+    # bounce's extension rays); per launch = per frame / launches per frame
+    frame_bytes = 0.0
+    for kind in ("closest", "shadow"):
+        v = visits["q8_persistent"][kind]
+        frame_bytes += (v["rays"] * (B_RAY + B_HIT) + v["tlas"] * B_NODE[2] + v["inst"] * B_INST +
+                        v["blas"] * B_NODE[2] + v["quads"] * B_QUAD)
     stg = q8["stages"]["closest"]
     launches_per_frame = stg["launches"] / args.steps
     alg_bytes = frame_bytes / launches_per_frame
@@ -302,7 +306,8 @@ def main():
                        "fp32_plain_mrays_s": round(inc["fp32_plain"]["mrays_s"], 2),
                        "speedup": round(inc["q8_persistent"]["mrays_s"] / inc["fp32_plain"]["mrays_s"], 3)},
         "ablation": {k: {kk: round(vv, 3) for kk, vv in d.items()} for k, d in ablation.items()},
-        "stages_ms_per_frame": {k: round(d["ms"] / args.steps, 3) for k, d in q8["stages"].items()},
+        "stages_ms_per_frame": {("traversal" if k == "closest" else k): round(d["ms"] / args.steps, 3)
+                                for k, d in q8["stages"].items() if k != "shadow"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if tr is None else tr,

@@ -82,7 +82,7 @@ typedef struct {
 typedef struct {
   int32_t formats;       /* RTQ_NODE_* mask to build; 0 = both */
   int32_t leaf_max;      /* quads per bottom-level leaf, 1..8; 0 = 4 */
-  int32_t sah_bins;      /* binned-SAH bins, 4..64; 0 = 16 */
+  int32_t sah_bins;      /* binned-SAH bins of the bottom levels, 4..64; 0 = 32 (the top level uses 64) */
   int32_t build_threads; /* host threads for the bottom-level builds; 0 = all */
   int32_t device;        /* HIP device ordinal; -1 = current */
 } rtq_build_opts;
@@ -147,7 +147,7 @@ typedef struct {
   int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 20 */
   int32_t block;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
   int32_t waves_per_cu;/* persistent scheduler: resident waves per CU; 0 = 24 */
-  int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 16 */
+  int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 24 */
   uint32_t* visits;    /* optional device n x 4 counters: top nodes, instances entered,
                           bottom nodes, quads tested (slower kernel variant) */
 } rtq_trace_opts;
@@ -188,7 +188,8 @@ typedef struct {
   int32_t scheduler;   /* RTQ_SCHED_PLAIN: wavefront of one kernel per stage and bounce
                           (queues of extension and shadow rays), one ray per lane;
                           RTQ_SCHED_PERSISTENT: the same wavefront with persistent,
-                          lane-refilling traversal stages;
+                          lane-refilling traversal stages, each tracing one
+                          bounce's shadow rays with the next bounce's extension rays;
                           RTQ_SCHED_MEGAKERNEL: one persistent launch per frame whose
                           lanes run whole paths and are refilled with new paths */
   int32_t stack_depth, block, waves_per_cu, refill; /* as rtq_trace_opts */
@@ -228,10 +229,12 @@ int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, i
 
 /*
  * Kernel time of the render calls made with opts->timing set since the previous
- * query, by stage: ms[0] closest-hit traversal launches (the megakernel launch
- * under RTQ_SCHED_MEGAKERNEL), ms[1] shadow-ray traversal launches, ms[2] every
- * other launch (ray generation, shading, shadow resolve, accumulation), ms[3]
- * whole calls (first to last recorded event).  launches[k] counts the launches
+ * query, by stage: ms[0] traversal launches (RTQ_SCHED_PLAIN: closest hits of
+ * each bounce; RTQ_SCHED_PERSISTENT: the depth + 1 launches that each trace one
+ * bounce's shadow rays together with the next bounce's extension rays;
+ * RTQ_SCHED_MEGAKERNEL: the megakernel), ms[1] shadow-ray traversal launches of
+ * RTQ_SCHED_PLAIN, ms[2] every other launch (ray generation, shading, shadow
+ * resolve, accumulation), ms[3] whole calls (first to last recorded event).  launches[k] counts the launches
  * in ms[k] (launches[3] = calls).  Waits for the recorded events, then forgets
  * them.  ms, launches: host arrays of 4, either may be NULL.  The event log
  * holds at most 4096 events; calls beyond it are not timed (launches tells).

@@ -86,7 +86,7 @@ int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t blo
   tl->persistent = sched;
   tl->stack_depth = depth ? depth : 20;
   tl->block = block ? block : 256;
-  tl->refill = refill ? refill : 16;
+  tl->refill = refill ? refill : 24;
   const int w = waves ? waves : 24;
   if (sched != RTQ_SCHED_PLAIN && sched != RTQ_SCHED_PERSISTENT)
     return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", sched);
@@ -129,7 +129,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   if (formats & ~(RTQ_NODE_FP32 | RTQ_NODE_Q8)) return set_error(RTQ_E_INVALID_ARG, "bad formats mask");
   BuildParams bp;
   bp.leaf_max = o.leaf_max ? o.leaf_max : 4;
-  bp.bins = o.sah_bins ? o.sah_bins : 16;
+  bp.bins = o.sah_bins ? o.sah_bins : 32;
   bp.want_q8 = true;  // the quantized nodes are cheap to derive; keep both topologies identical
   if (bp.leaf_max < 1 || bp.leaf_max > 8) return set_error(RTQ_E_INVALID_ARG, "leaf_max %d outside [1, 8]", bp.leaf_max);
   if (bp.bins < 4 || bp.bins > 64) return set_error(RTQ_E_INVALID_ARG, "sah_bins %d outside [4, 64]", bp.bins);
@@ -371,6 +371,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   Bvh4 tlas;
   BuildParams tp = bp;
   tp.leaf_max = 1;
+  tp.bins = std::max(bp.bins, 64);  // one box per instance: finer bins are cheap here
   if (N > 0) {
     build_bvh4(boxes.data(), N, tp, tlas);
   } else {

@@ -130,19 +130,24 @@ __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, Shadow
   if (COUNT) wave_add_visits(vc, visits);
 }
 
-// The same queue traversal as a persistent kernel: resident waves claim queue
-// entries from a counter and refill lanes whose ray has finished.
-template <int FMT, bool ANY, bool COUNT>
-__global__ void k_trace_queue_persistent(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq,
-                                         const uint32_t* count, QueueHits qh, uint8_t* occ, int depth, int refill,
-                                         unsigned long long* counter, unsigned long long* visits) {
+// Persistent traversal of an extension-ray queue (closest hits) and a shadow-ray
+// queue (occlusion) in one launch: entries [0, n_ext) are extension rays,
+// [n_ext, n_ext + n_sh) shadow rays.  Tracing the shadow rays of bounce b with
+// the extension rays of bounce b + 1 halves the traversal launches of a frame
+// and with them the drain at the end of each launch; the short any-hit rays
+// come last, where the launch drains.
+template <int FMT, bool COUNT>
+__global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, const uint32_t* count_ext,
+                                    ShadowQueue sq, const uint32_t* count_sh, QueueHits qh, uint8_t* occ, int depth,
+                                    int refill, unsigned long long* counter, unsigned long long* visits) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth);
   uint2 spill[kStackTotal];
-  const int64_t n = (int64_t)*count;
+  const int64_t n_ext = (int64_t)*count_ext;
+  const int64_t n = n_ext + (int64_t)*count_sh;
   Lane L;
-  VisitCounters vc{0, 0, 0, 0};
+  VisitCounters vc{0, 0, 0, 0}, vc_cl{0, 0, 0, 0}, vc_sh{0, 0, 0, 0};
   bool has = false, exhausted = n == 0;
   int64_t idx = -1;
   for (;;) {
@@ -158,10 +163,17 @@ __global__ void k_trace_queue_persistent(SceneView sc, RenderParams rp, ExtQueue
       if (!has) {
         const uint32_t rank =
             __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-        idx = (int64_t)(base + rank);
-        if (idx < n) {
-          if (load_queue_ray<ANY>(L, sc, rp, eq, sq, idx)) has = true;
-          else store_queue_result<ANY>(L, qh, occ, idx);
+        const int64_t k = (int64_t)(base + rank);
+        if (k < n) {
+          if (k < n_ext) {
+            idx = k;
+            if (load_queue_ray<false>(L, sc, rp, eq, sq, idx)) has = true;
+            else store_queue_result<false>(L, qh, occ, idx);
+          } else {
+            idx = k - n_ext;
+            if (load_queue_ray<true>(L, sc, rp, eq, sq, idx)) has = true;
+            else store_queue_result<true>(L, qh, occ, idx);
+          }
         }
       }
       if ((int64_t)(base + nidle) >= n) exhausted = true;
@@ -173,7 +185,16 @@ __global__ void k_trace_queue_persistent(SceneView sc, RenderParams rp, ExtQueue
     if (has) {
       for (;;) {
         if (lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
-          store_queue_result<ANY>(L, qh, occ, idx);
+          if (L.any) store_queue_result<true>(L, qh, occ, idx);
+          else store_queue_result<false>(L, qh, occ, idx);
+          if (COUNT) {
+            VisitCounters& acc = L.any ? vc_sh : vc_cl;
+            acc.tlas += vc.tlas;
+            acc.inst += vc.inst;
+            acc.blas += vc.blas;
+            acc.quads += vc.quads;
+            vc = VisitCounters{0, 0, 0, 0};
+          }
           has = false;
           break;
         }
@@ -181,7 +202,10 @@ __global__ void k_trace_queue_persistent(SceneView sc, RenderParams rp, ExtQueue
       }
     }
   }
-  if (COUNT) wave_add_visits(vc, visits);
+  if (COUNT) {
+    wave_add_visits(vc_cl, visits);
+    wave_add_visits(vc_sh, visits + 4);
+  }
 }
 
 __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const uint32_t* count_in, QueueHits qh,
@@ -545,10 +569,13 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Plain stages of bounce b: closest hits of its extension queue, shading,
+// occlusion of its shadow queue, shadow resolution; one ray per lane.
 template <int FMT, bool COUNT>
 static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int b,
                              const TraceLaunch& tl, const RenderExtras& ex, hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
+  const unsigned gt = blocks(rp.n_paths, tl.block);
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   const ExtQueue& qin = pb.q[b & 1];
   const ExtQueue& qout = pb.q[(b + 1) & 1];
@@ -557,32 +584,57 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
   uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
   unsigned long long* vis_sh = ex.visits ? ex.visits + 4 : nullptr;
   hipEvent_t ev = stage_begin(ex.log, s);
-  if (tl.persistent) {
-    hipLaunchKernelGGL((k_trace_queue_persistent<FMT, false, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                       qin, pb.sq, cin, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b, ex.visits);
-  } else {
-    const unsigned gt = blocks(rp.n_paths, tl.block);
-    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
-                       cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
-  }
+  hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, cin,
+                     pb.hits, pb.occ, tl.stack_depth, ex.visits);
   stage_end(ex.log, 0, ev, s);
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
                      ex.dump, ex.dump_cap, ex.dump_count);
   stage_end(ex.log, 2, ev, s);
   ev = stage_begin(ex.log, s);
-  if (tl.persistent) {
-    hipLaunchKernelGGL((k_trace_queue_persistent<FMT, true, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                       qin, pb.sq, csq, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + 2 * b + 1, vis_sh);
-  } else {
-    const unsigned gt = blocks(rp.n_paths, tl.block);
-    hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
-                       csq, pb.hits, pb.occ, tl.stack_depth, vis_sh);
-  }
+  hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, csq,
+                     pb.hits, pb.occ, tl.stack_depth, vis_sh);
   stage_end(ex.log, 1, ev, s);
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
   stage_end(ex.log, 2, ev, s);
+}
+
+template <int FMT, bool COUNT>
+static void mixed_launch(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, const TraceLaunch& tl,
+                         const RenderExtras& ex, const ExtQueue& eq, const uint32_t* cext, const uint32_t* csh,
+                         int slot, hipStream_t s) {
+  const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
+  hipEvent_t ev = stage_begin(ex.log, s);
+  hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq, cext,
+                     pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + slot, ex.visits);
+  stage_end(ex.log, 0, ev, s);
+}
+
+// Persistent stages: traverse(extension 0); then per bounce b: shade(b),
+// traverse(shadow b + extension b + 1), resolve(b).
+template <int FMT, bool COUNT>
+static void wavefront_persistent(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb,
+                                 const TraceLaunch& tl, const RenderExtras& ex, hipStream_t s) {
+  const unsigned gp = blocks(rp.n_paths, 256);
+  const uint32_t* zero = pb.counts + 2 * kMaxDepth + 1;  // cleared, never written
+  mixed_launch<FMT, COUNT>(sc, rp, pb, tl, ex, pb.q[0], pb.counts, zero, 0, s);
+  for (int b = 0; b < rp.depth; ++b) {
+    const ExtQueue& qin = pb.q[b & 1];
+    const ExtQueue& qout = pb.q[(b + 1) & 1];
+    uint32_t* cin = pb.counts + b;
+    uint32_t* cout = pb.counts + b + 1;
+    uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
+    hipEvent_t ev = stage_begin(ex.log, s);
+    hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
+                       ex.dump, ex.dump_cap, ex.dump_count);
+    stage_end(ex.log, 2, ev, s);
+    // after the last bounce the extension count stays zero: shadow rays only
+    mixed_launch<FMT, COUNT>(sc, rp, pb, tl, ex, qout, cout, csq, b + 1, s);
+    ev = stage_begin(ex.log, s);
+    hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+    stage_end(ex.log, 2, ev, s);
+  }
 }
 
 hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int fmt,
@@ -596,13 +648,23 @@ hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, 
   hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
   stage_end(ex.log, 2, ev, s);
   const bool cnt = ex.visits != nullptr;
-  for (int b = 0; b < rp.depth; ++b) {
+  if (tl.persistent) {
     if (fmt == 2) {
-      if (cnt) wavefront_bounce<2, true>(sc, rp, pb, b, tl, ex, s);
-      else wavefront_bounce<2, false>(sc, rp, pb, b, tl, ex, s);
+      if (cnt) wavefront_persistent<2, true>(sc, rp, pb, tl, ex, s);
+      else wavefront_persistent<2, false>(sc, rp, pb, tl, ex, s);
     } else {
-      if (cnt) wavefront_bounce<1, true>(sc, rp, pb, b, tl, ex, s);
-      else wavefront_bounce<1, false>(sc, rp, pb, b, tl, ex, s);
+      if (cnt) wavefront_persistent<1, true>(sc, rp, pb, tl, ex, s);
+      else wavefront_persistent<1, false>(sc, rp, pb, tl, ex, s);
+    }
+  } else {
+    for (int b = 0; b < rp.depth; ++b) {
+      if (fmt == 2) {
+        if (cnt) wavefront_bounce<2, true>(sc, rp, pb, b, tl, ex, s);
+        else wavefront_bounce<2, false>(sc, rp, pb, b, tl, ex, s);
+      } else {
+        if (cnt) wavefront_bounce<1, true>(sc, rp, pb, b, tl, ex, s);
+        else wavefront_bounce<1, false>(sc, rp, pb, b, tl, ex, s);
+      }
     }
   }
   ev = stage_begin(ex.log, s);
