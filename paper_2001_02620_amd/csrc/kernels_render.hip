@@ -335,10 +335,10 @@ struct PathLane {
   bool shadow, have_next;
 };
 
-// Five resident waves per SIMD: the traversal is latency bound, and five waves
-// fit with a handful of spilled registers.
+// At least four resident waves per SIMD (up to 128 registers per lane: the path
+// state comes on top of the traversal state).
 template <int FMT, bool TS, bool COUNT>
-__global__ __attribute__((amdgpu_waves_per_eu(5))) void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
+__global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
                                     unsigned long long* counter, unsigned long long* counters,
                                     unsigned long long* view_done, unsigned long long* visits) {
   extern __shared__ uint2 lds[];

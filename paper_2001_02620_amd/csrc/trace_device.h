@@ -65,6 +65,11 @@ struct Lane {
   float ix, iy, iz;
   float cnx, cny, cnz;
   float cfx, cfy, cfz;
+  // the same constants of the top level, kept to restore them on leaving an
+  // instance without recomputing the reciprocals
+  float wix, wiy, wiz;
+  float wcnx, wcny, wcnz;
+  float wcfx, wcfy, wcfz;
   // leaf test inside an instance: object-space origin and the shear of the
   // watertight test (Woop, Benthin, Wald 2013)
   float lox, loy, loz;
@@ -242,10 +247,13 @@ __device__ __forceinline__ TriResult tri_finish(float U, float V, float W, const
 // [depth][64] u32 and entry distances as [depth][64] u16 (the upper half of the
 // FP32 value, rounded toward -inf, so a popped entry is never culled wrongly).
 // Deeper entries spill to a private array.
+typedef __attribute__((address_space(3))) uint32_t LdsU32;  // LDS-qualified element types
+typedef __attribute__((address_space(3))) uint16_t LdsU16;
+
 struct Stack {
-  uint32_t* ref;  // this lane's column: entry j at ref[64 j]
-  uint16_t* tq;   // this lane's column of entry distances
-  int depth;      // LDS entries per lane
+  LdsU32* ref;  // this lane's column: entry j at ref[64 j]
+  LdsU16* tq;   // this lane's column of entry distances
+  int depth;    // LDS entries per lane
 };
 
 constexpr int kStackEntryBytes = 6;
@@ -253,8 +261,8 @@ constexpr int kStackEntryBytes = 6;
 // Stack region of this lane in a block's dynamic LDS (6 bytes per entry and lane).
 __device__ __forceinline__ Stack make_stack(void* lds, int depth) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
-  uint32_t* refs = reinterpret_cast<uint32_t*>(lds);
-  uint16_t* ts = reinterpret_cast<uint16_t*>(refs + (size_t)waves * depth * 64);
+  LdsU32* refs = (LdsU32*)lds;
+  LdsU16* ts = (LdsU16*)(refs + (size_t)waves * depth * 64);
   return Stack{refs + wave * depth * 64 + lane, ts + wave * depth * 64 + lane, depth};
 }
 
@@ -472,6 +480,15 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
     return false;
   }
   set_world_level(L, sc);
+  L.wix = L.ix;
+  L.wiy = L.iy;
+  L.wiz = L.iz;
+  L.wcnx = L.cnx;
+  L.wcny = L.cny;
+  L.wcnz = L.cnz;
+  L.wcfx = L.cfx;
+  L.wcfy = L.cfy;
+  L.wcfz = L.cfz;
   return true;
 }
 
@@ -580,17 +597,15 @@ __device__ __forceinline__ void pop_step(Lane& L, const SceneView& sc, const Sta
   const bool need = !L.done && L.cur == kEmpty;
   const bool leave = need && L.sp == L.inst_sp;
   if (__any(leave)) {
-    Lane W = L;
-    set_world_level(W, sc);
-    L.ix = leave ? W.ix : L.ix;
-    L.iy = leave ? W.iy : L.iy;
-    L.iz = leave ? W.iz : L.iz;
-    L.cnx = leave ? W.cnx : L.cnx;
-    L.cny = leave ? W.cny : L.cny;
-    L.cnz = leave ? W.cnz : L.cnz;
-    L.cfx = leave ? W.cfx : L.cfx;
-    L.cfy = leave ? W.cfy : L.cfy;
-    L.cfz = leave ? W.cfz : L.cfz;
+    L.ix = leave ? L.wix : L.ix;
+    L.iy = leave ? L.wiy : L.iy;
+    L.iz = leave ? L.wiz : L.iz;
+    L.cnx = leave ? L.wcnx : L.cnx;
+    L.cny = leave ? L.wcny : L.cny;
+    L.cnz = leave ? L.wcnz : L.cnz;
+    L.cfx = leave ? L.wcfx : L.cfx;
+    L.cfy = leave ? L.wcfy : L.cfy;
+    L.cfz = leave ? L.wcfz : L.cfz;
     L.inst_sp = leave ? -1 : L.inst_sp;
   }
   const bool pop = need && L.sp > 0;
@@ -598,8 +613,10 @@ __device__ __forceinline__ void pop_step(Lane& L, const SceneView& sc, const Sta
   if (__any(pop)) {
     const int sp = L.sp - (pop ? 1 : 0);
     const int j = max(0, min(sp, S.depth - 1));
-    uint32_t ref = S.ref[64 * j];
-    float t = t_up32(S.tq[64 * j]);
+    // volatile keeps these LDS reads apart from the spill read below (merged,
+    // they become one flat load that waits for vector memory)
+    uint32_t ref = *(volatile LdsU32*)(S.ref + 64 * j);
+    float t = t_up32(*(volatile LdsU16*)(S.tq + 64 * j));
     if (pop && sp >= S.depth) {
       const uint2 e = spill[sp - S.depth];
       ref = e.x;
