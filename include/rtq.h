@@ -147,7 +147,7 @@ typedef struct {
   int32_t stack_depth; /* LDS stack entries per lane, 4..64 (deeper entries spill); 0 = 20 */
   int32_t block;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
   int32_t waves_per_cu;/* persistent scheduler: resident waves per CU; 0 = 24 */
-  int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 24 */
+  int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 16 */
   uint32_t* visits;    /* optional device n x 4 counters: top nodes, instances entered,
                           bottom nodes, quads tested (slower kernel variant) */
 } rtq_trace_opts;

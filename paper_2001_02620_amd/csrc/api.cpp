@@ -86,7 +86,7 @@ int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t blo
   tl->persistent = sched;
   tl->stack_depth = depth ? depth : 20;
   tl->block = block ? block : 256;
-  tl->refill = refill ? refill : 24;
+  tl->refill = refill ? refill : 16;
   const int w = waves ? waves : 24;
   if (sched != RTQ_SCHED_PLAIN && sched != RTQ_SCHED_PERSISTENT)
     return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", sched);
@@ -102,7 +102,7 @@ int resolve_launch(const rtq_scene* s, int32_t sched, int32_t depth, int32_t blo
   const int waves_per_block = tl->block / 64;
   tl->grid = std::max(1, (s->n_cu * w + waves_per_block - 1) / waves_per_block);
   const uint32_t slot = s->counter_next.fetch_add(1) % rtq_scene::kCounterSlots;
-  tl->counter = s->counters + slot;
+  tl->counter = s->counters + (size_t)slot * kClaimWords;
   return RTQ_OK;
 }
 
@@ -414,7 +414,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     TCHECK(launch_gather_inst(d_rec, d_order, N, s->inst, 0), "gather kernel");
   }
   s->counters = reinterpret_cast<unsigned long long*>(
-      s->bufs.alloc(rtq_scene::kCounterSlots * sizeof(unsigned long long), &e));
+      s->bufs.alloc((size_t)rtq_scene::kCounterSlots * kClaimWords * sizeof(unsigned long long), &e));
   if (!s->counters) return tfail(hip_error(e, "hipMalloc"));
   TCHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
   tmp.release();

@@ -144,7 +144,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
     RALLOC(r->pb.hits.qh, P * 4);
     RALLOC(r->pb.occ, P);
     RALLOC(r->pb.counts, (2 * kMaxDepth + 2) * sizeof(uint32_t));
-    RALLOC(r->pb.work, 2 * kMaxDepth * sizeof(unsigned long long));
+    RALLOC(r->pb.work, (size_t)(kMaxDepth + 1) * kClaimWords * sizeof(unsigned long long));
   }
 #undef RALLOC
   r->paths_cap = P;

@@ -149,34 +149,24 @@ __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, 
   Lane L;
   VisitCounters vc{0, 0, 0, 0}, vc_cl{0, 0, 0, 0}, vc_sh{0, 0, 0, 0};
   bool has = false, exhausted = n == 0;
+  ClaimState claim = claim_init();
   int64_t idx = -1;
   for (;;) {
     const unsigned long long idle = __ballot(!has);
     const int nidle = __popcll(idle);
     if (!exhausted && (nidle >= refill || nidle == 64)) {
-      const int leader = __ffsll((long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(counter, (unsigned long long)nidle);
-      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
-      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
-      base = ((unsigned long long)hi << 32) | lo;
-      if (!has) {
-        const uint32_t rank =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-        const int64_t k = (int64_t)(base + rank);
-        if (k < n) {
-          if (k < n_ext) {
-            idx = k;
-            if (load_queue_ray<false>(L, sc, rp, eq, sq, idx)) has = true;
-            else store_queue_result<false>(L, qh, occ, idx);
-          } else {
-            idx = k - n_ext;
-            if (load_queue_ray<true>(L, sc, rp, eq, sq, idx)) has = true;
-            else store_queue_result<true>(L, qh, occ, idx);
-          }
+      const int64_t k = claim_take(claim, counter, n, idle, nidle, &exhausted);
+      if (k >= 0) {
+        if (k < n_ext) {
+          idx = k;
+          if (load_queue_ray<false>(L, sc, rp, eq, sq, idx)) has = true;
+          else store_queue_result<false>(L, qh, occ, idx);
+        } else {
+          idx = k - n_ext;
+          if (load_queue_ray<true>(L, sc, rp, eq, sq, idx)) has = true;
+          else store_queue_result<true>(L, qh, occ, idx);
         }
       }
-      if ((int64_t)(base + nidle) >= n) exhausted = true;
     }
     if (!__any(has)) {
       if (exhausted) break;
@@ -350,23 +340,16 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
   VisitCounters vc_sh{0, 0, 0, 0};   // finished shadow traversals (closest-hit ones stay in vc_cl)
   VisitCounters vc_cl{0, 0, 0, 0};
   PathLane P{};
-  bool has = false, exhausted = false;
+  bool has = false, exhausted = rp.n_paths == 0;
+  ClaimState claim = claim_init();
   uint32_t n_ext = 0, n_sh = 0, n_inc = 0, n_paths = 0;
   for (;;) {
     const unsigned long long idle = __ballot(!has);
     const int nidle = __popcll(idle);
     if (!exhausted && (nidle >= refill || nidle == 64)) {
-      const int leader = __ffsll((long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(counter, (unsigned long long)nidle);
-      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
-      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
-      base = ((unsigned long long)hi << 32) | lo;
-      if (!has) {
-        const uint32_t rank =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-        const int64_t pid = (int64_t)(base + rank);
-        if (pid < rp.n_paths) {
+      const int64_t pid = claim_take(claim, counter, rp.n_paths, idle, nidle, &exhausted);
+      {
+        if (pid >= 0) {
           P.pid = (uint32_t)pid;
           int view;
           uint32_t pixel, sample;
@@ -383,7 +366,6 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
           has = true;
         }
       }
-      if ((int64_t)(base + nidle) >= rp.n_paths) exhausted = true;
     }
     if (!__any(has)) {
       if (exhausted) break;
@@ -607,7 +589,8 @@ static void mixed_launch(const SceneView& sc, const RenderParams& rp, const Plai
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   hipEvent_t ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq, cext,
-                     pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + slot, ex.visits);
+                     pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + (size_t)slot * kClaimWords,
+                     ex.visits);
   stage_end(ex.log, 0, ev, s);
 }
 
@@ -643,7 +626,7 @@ hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, 
   const unsigned gp = blocks(rp.n_paths, 256);
   hipEvent_t ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, pb.counts, 2 * kMaxDepth + 2);
-  hipError_t e = launch_zero_u64(pb.work, 2 * kMaxDepth, s);
+  hipError_t e = launch_zero_u64(pb.work, (kMaxDepth + 1) * kClaimWords, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
   stage_end(ex.log, 2, ev, s);
@@ -686,7 +669,7 @@ static void persistent_launch(const SceneView& sc, const RenderParams& rp, const
 hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
                                     float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s) {
   hipEvent_t ev = stage_begin(ex.log, s);
-  hipError_t e = launch_zero_u64(tl.counter, 1, s);
+  hipError_t e = launch_zero_u64(tl.counter, kClaimWords, s);
   if (e != hipSuccess) return e;
   if (ex.start_tick) hipLaunchKernelGGL(k_start_tick, dim3(1), dim3(64), 0, s, ex.start_tick);
   stage_end(ex.log, 2, ev, s);

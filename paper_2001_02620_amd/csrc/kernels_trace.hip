@@ -70,33 +70,24 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
   Lane L;
   VisitCounters vc{0, 0, 0, 0};
   bool has = false;
-  bool exhausted = false;  // wave-uniform
+  bool exhausted = n == 0;  // wave-uniform
+  ClaimState claim = claim_init();
   int64_t idx = -1;
   for (;;) {
     const unsigned long long idle = __ballot(!has);
     const int nidle = __popcll(idle);
     if (!exhausted && (nidle >= refill || nidle == 64)) {
-      const int leader = __ffsll((long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(counter, (unsigned long long)nidle);
-      const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
-      const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
-      base = ((unsigned long long)hi << 32) | lo;
-      if (!has) {
-        const uint32_t rank =
-            __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
-        idx = (int64_t)(base + rank);
-        if (idx < n) {
-          vc = VisitCounters{0, 0, 0, 0};
-          if (load_ray<ANY>(L, sc, rays, idx)) {
-            has = true;
-          } else {
-            store_result<ANY>(L, sc, idx, hits, occ);
-            store_visits<COUNT>(visits, idx, vc);
-          }
+      const int64_t k = claim_take(claim, counter, n, idle, nidle, &exhausted);
+      if (k >= 0) {
+        idx = k;
+        vc = VisitCounters{0, 0, 0, 0};
+        if (load_ray<ANY>(L, sc, rays, idx)) {
+          has = true;
+        } else {
+          store_result<ANY>(L, sc, idx, hits, occ);
+          store_visits<COUNT>(visits, idx, vc);
         }
       }
-      if ((int64_t)(base + nidle) >= n) exhausted = true;
     }
     if (!__any(has)) {
       if (exhausted) break;
@@ -137,7 +128,7 @@ static hipError_t launch3(const SceneView& sc, const RaysSoA& r, int64_t n, cons
                           uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   if (tl.persistent) {
-    hipError_t e = launch_zero_u64(tl.counter, 1, s);
+    hipError_t e = launch_zero_u64(tl.counter, kClaimWords, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_trace_persistent<FMT, ANY, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, r, n, h,
                        occ, visits, tl.stack_depth, tl.refill, tl.counter);

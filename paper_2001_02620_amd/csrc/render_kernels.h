@@ -40,7 +40,7 @@ struct PlainBuffers {
   QueueHits hits;
   uint8_t* occ;
   uint32_t* counts;  // [0, kMaxDepth]: extension queue sizes; [kMaxDepth + 1, ...): shadow queue sizes
-  unsigned long long* work;  // [2 kMaxDepth]: claim counters of the persistent queue traversals
+  unsigned long long* work;  // [(kMaxDepth + 1) kClaimWords]: claim counters of the persistent traversal launches
 };
 
 // Host-side log of HIP events around a render call's launches (owned by the

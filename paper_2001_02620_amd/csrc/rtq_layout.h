@@ -74,4 +74,10 @@ constexpr int kQuadFloat4 = 3;
 // Worst-case traversal stack: every 4-wide level pushes at most 3 entries.
 constexpr int kStackTotal = 192;
 
+// Work counters of one persistent launch: kClaimSlices counters, each on its own
+// 128-byte line (kClaimStride 64-bit words apart).
+constexpr int kClaimSlices = 8;
+constexpr int kClaimStride = 16;
+constexpr int kClaimWords = kClaimSlices * kClaimStride;
+
 }  // namespace rtq

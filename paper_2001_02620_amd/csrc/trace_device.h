@@ -447,6 +447,50 @@ struct VisitCounters {
   uint32_t tlas, inst, blas, quads;
 };
 
+// ---- work claiming of the persistent kernels ------------------------------------
+// The work indices [0, n) of a launch are dealt to kClaimSlices interleaved
+// slices (index i belongs to slice i mod kClaimSlices), each with its own
+// counter.  A wave claims from its home slice (its block index mod the slice
+// count) and moves to the next slice once that one is used up, so the atomics of
+// a launch spread over kClaimSlices counters instead of serialising on one, and
+// every slice keeps the order of the indices.  Fields are wave-uniform.
+struct ClaimState {
+  int slice;  // slice claimed from
+  int dry;    // consecutive slices found used up
+};
+
+__device__ __forceinline__ ClaimState claim_init() { return ClaimState{(int)(blockIdx.x % kClaimSlices), 0}; }
+
+// Claim work for the idle lanes (mask `idle`, nidle >= 1 of them).  Returns this
+// lane's work index, or -1 for a busy lane and when nothing was claimed for it;
+// sets *exhausted once every slice is used up.
+__device__ __forceinline__ int64_t claim_take(ClaimState& C, unsigned long long* ctr, int64_t n,
+                                              unsigned long long idle, int nidle, bool* exhausted) {
+  const int lane = threadIdx.x & 63;
+  const bool is_idle = ((idle >> lane) & 1ull) != 0ull;
+  const uint32_t rank =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+  const int leader = __ffsll((long long)__ballot(1)) - 1;
+  while (C.dry < kClaimSlices) {
+    const int h = C.slice;
+    const int64_t len = n > h ? (n - h + kClaimSlices - 1) / kClaimSlices : 0;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[h * kClaimStride], (unsigned long long)nidle);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+    base = ((unsigned long long)hi << 32) | lo;
+    if ((int64_t)base < len) {
+      C.dry = 0;
+      const int64_t j = (int64_t)base + rank;
+      return (is_idle && j < len) ? j * kClaimSlices + h : -1;
+    }
+    C.slice = h + 1 == kClaimSlices ? 0 : h + 1;
+    ++C.dry;
+  }
+  *exhausted = true;
+  return -1;
+}
+
 // Initialise a lane for world ray (o, d, tmin, tmax).  Returns false (miss) for
 // non-finite input or a zero direction.
 __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox, float oy, float oz, float dx,
