@@ -210,7 +210,14 @@ typedef struct {
                           count may exceed dump_cap, rays beyond it are dropped) */
   int32_t timing;      /* nonzero: record HIP events around the call's kernel
                           launches on `stream` (no synchronisation); read them
-                          with rtq_render_timing */
+                          with rtq_render_timing (with graph set: the whole
+                          graph launch, reported under calls only) */
+  int32_t graph;       /* nonzero: capture the call's launches into a HIP graph
+                          on first use and replay it on later calls with the same
+                          configuration (cameras, sizes, buffers, options; the
+                          seed and frame may change).  Graphs are kept in the
+                          scene and dropped when its render scratch grows.
+                          Replays of one scene must not overlap in time. */
 } rtq_render_opts;
 
 /*

@@ -83,7 +83,7 @@ class _RenderOpts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32), ("counters", ctypes.c_void_p),
                 ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
                 ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -291,7 +291,7 @@ def camera_structs(cams) -> tuple:
 
 def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
                 counters=None, view_done=None, start_tick=None, visits=None, dump_rays=None, dump_count=None,
-                timing=False):
+                timing=False, graph=False):
     o = _RenderOpts()
     o.seed = int(settings.seed)
     o.frame = int(settings.frame)
@@ -312,6 +312,7 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 8
     o.dump_count = _ptr(dump_count)
     o.timing = 1 if timing else 0
+    o.graph = 1 if graph else 0
     return o
 
 

@@ -5,7 +5,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <mutex>
+#include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rtq.h"
@@ -16,6 +19,14 @@ using namespace rtq;
 
 namespace {
 
+// A captured render call: the graph of its launches and the claim counters its
+// persistent launches use (its own, so replays never share counters with eager
+// calls).
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  unsigned long long* counter = nullptr;
+};
+
 struct RenderScratch {
   DeviceBuffers bufs;
   int64_t paths_cap = 0;
@@ -23,7 +34,18 @@ struct RenderScratch {
   int32_t cams_cap = 0;
   CamDev* cams = nullptr;
   float* slots = nullptr;
+  uint32_t* keys = nullptr;  // [2] RNG key of the current call
   PlainBuffers pb{};
+  // captured calls, keyed by everything their launches bake in
+  std::unordered_map<std::string, GraphEntry> graphs;
+  DeviceBuffers graph_bufs;
+  hipStream_t capture_stream = nullptr;
+  void clear_graphs() {
+    for (auto& kv : graphs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs.clear();
+    graph_bufs.release();
+  }
 };
 
 }  // namespace
@@ -98,6 +120,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
   RenderScratch* r = scratch_of(s);
   if (r->paths_cap >= n_paths && r->cams_cap >= n_cams && (r->plain || !plain)) return RTQ_OK;
   (void)hipDeviceSynchronize();
+  r->clear_graphs();  // their launches point into the buffers released here
   r->bufs.release();
   const int64_t P = std::max<int64_t>(std::max(n_paths, r->paths_cap), 64);
   const int32_t C = std::max(std::max(n_cams, r->cams_cap), 64);
@@ -117,6 +140,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
   } while (0)
   RALLOC(r->cams, C * sizeof(CamDev));
   RALLOC(r->slots, P * sizeof(float));
+  RALLOC(r->keys, 64);
   if (want_plain) {
     for (int k = 0; k < 2; ++k) {
       ExtQueue& q = r->pb.q[k];
@@ -241,13 +265,15 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   const hipError_t e =
       hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_error(e, "camera upload");
+  const hipError_t ek = launch_set_keys(sc->keys, (uint32_t)(opts->seed & 0xFFFFFFFFull),
+                                         (uint32_t)(opts->seed >> 32) ^ opts->frame, stream);
+  if (ek != hipSuccess) return hip_error(ek, "key upload");
   RenderParams& rp = out->rp;
   rp.cams = sc->cams;
   rp.n_cams = n_cams;
   rp.spp = spp;
   rp.depth = depth;
-  rp.key0 = (uint32_t)(opts->seed & 0xFFFFFFFFull);
-  rp.key1 = (uint32_t)(opts->seed >> 32) ^ opts->frame;
+  rp.keys = sc->keys;
   rp.lx = L[0];
   rp.ly = L[1];
   rp.lz = L[2];
@@ -261,6 +287,65 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
 
 }  // namespace
 
+namespace {
+
+// Capture (first use) or replay the launches of one render call.  The key holds
+// every value that the launches bake in: pointers, sizes, grid shapes and the
+// render constants; the RNG key is read from device memory, written before the
+// graph runs, so frames with other seeds replay the same graph.
+int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prepared& p, bool staged, float* images,
+                 RenderExtras ex, hipStream_t stream) {
+  char key[512];
+  const RenderParams& rp = p.rp;
+  std::snprintf(key, sizeof(key),
+                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p", staged ? 1 : 0,
+                p.fmt, p.tl.persistent, p.tl.stack_depth, p.tl.block, p.tl.refill, p.tl.grid, rp.n_cams, rp.spp,
+                (long long)rp.depth, (long long)rp.n_paths, rp.lx, rp.ly, rp.lz, rp.e_over_pi, rp.L_sky,
+                (const void*)rp.cams, (const void*)rp.slots, (const void*)images, (void*)ex.counters,
+                (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
+                (void*)ex.start_tick, (void*)sv.nodes);
+  const std::string k(key);
+  auto it = r->graphs.find(k);
+  if (it == r->graphs.end()) {
+    hipError_t e;
+    if (!r->capture_stream) {
+      e = hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_error(e, "capture stream");
+    }
+    GraphEntry g;
+    g.counter = reinterpret_cast<unsigned long long*>(
+        r->graph_bufs.alloc(kClaimWords * sizeof(unsigned long long), &e));
+    if (!g.counter) return hip_error(e, "graph counters");
+    // captured work runs only when the graph is launched on the caller's
+    // stream, after that stream's camera and key uploads
+    TraceLaunch tl = p.tl;
+    tl.counter = g.counter;
+    RenderExtras cex = ex;
+    cex.log = nullptr;  // no events inside a graph
+    e = hipStreamBeginCapture(r->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "begin capture");
+    hipError_t el = staged ? launch_render_wavefront(sv, rp, r->pb, p.fmt, tl, images, p.n_pixels, cex, r->capture_stream)
+                           : launch_render_megakernel(sv, rp, p.fmt, tl, images, p.n_pixels, cex, r->capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(r->capture_stream, &graph);
+    if (el != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_error(el, "render capture");
+    }
+    if (e != hipSuccess) return hip_error(e, "end capture");
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_error(e, "graph instantiate");
+    it = r->graphs.emplace(k, g).first;
+  }
+  hipEvent_t ev = stage_begin(ex.log, stream);
+  const hipError_t e = hipGraphLaunch(it->second.exec, stream);
+  stage_end(ex.log, -1, ev, stream);
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "graph launch");
+}
+
+}  // namespace
+
 namespace rtq {
 void release_render_scratch(rtq_scene* s) {
   if (s->stage_log) {
@@ -269,6 +354,8 @@ void release_render_scratch(rtq_scene* s) {
   }
   if (s->render_state) {
     RenderScratch* r = static_cast<RenderScratch*>(s->render_state);
+    r->clear_graphs();
+    if (r->capture_stream) (void)hipStreamDestroy(r->capture_stream);
     r->bufs.release();
     delete r;
     s->render_state = nullptr;
@@ -308,8 +395,16 @@ int rtq_render(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32
     ex.log->call_first = ex.log->call_last = nullptr;
   }
   hipError_t e;
+  RenderScratch* r = scratch_of(const_cast<rtq_scene*>(s));
+  if (opts->graph) {
+    std::unique_lock<std::mutex> graph_lock;
+    if (!log_lock.owns_lock()) graph_lock = std::unique_lock<std::mutex>(const_cast<rtq_scene*>(s)->scratch_mu);
+    int grc = render_graph(const_cast<rtq_scene*>(s), r, sv, p, staged, images, ex, stream);
+    if (ex.log && ex.log->call_first && ex.log->call_last)
+      ex.log->calls.push_back({ex.log->call_first, ex.log->call_last});
+    return grc;
+  }
   if (staged) {
-    RenderScratch* r = scratch_of(const_cast<rtq_scene*>(s));
     e = launch_render_wavefront(sv, p.rp, r->pb, p.fmt, p.tl, images, p.n_pixels, ex, stream);
   } else {
     e = launch_render_megakernel(sv, p.rp, p.fmt, p.tl, images, p.n_pixels, ex, stream);
@@ -328,6 +423,7 @@ int rtq_render_timing(rtq_scene* s, float* ms, int32_t* launches) {
   int rc = RTQ_OK;
   if (log) {
     for (const StageLog::Rec& r : log->recs) {
+      if (r.stage < 0) continue;  // call marker of a graph launch
       float t = 0.0f;
       hipError_t e = hipEventSynchronize(r.b);
       if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);

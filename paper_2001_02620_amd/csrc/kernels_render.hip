@@ -310,6 +310,13 @@ __global__ void k_plain_stats(const uint32_t* counts, int depth, int64_t n_paths
   counters[3] += (unsigned long long)n_paths;
 }
 
+__global__ void k_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1) {
+  if (threadIdx.x == 0) {
+    keys[0] = k0;
+    keys[1] = k1;
+  }
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -696,6 +703,11 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
   stage_end(ex.log, 2, ev, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_keys, dim3(1), dim3(64), 0, s, keys, k0, k1);
   return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ struct RenderParams {
   int32_t n_cams;
   int32_t spp;
   int32_t depth;
-  uint32_t key0, key1;  // Philox key: (seed_lo, seed_hi ^ frame)
+  const uint32_t* keys; // device [2]: Philox key (seed_lo, seed_hi ^ frame), written at the start of each call
   float lx, ly, lz;     // unit direction toward the light
   float e_over_pi;      // E / pi
   float L_sky;
@@ -174,14 +174,14 @@ __device__ __forceinline__ void cosine_dir(float nx, float ny, float nz, float u
 __device__ __forceinline__ Ray3 path_camera_ray(const RenderParams& rp, int64_t pid, int* view, uint32_t* pixel,
                                                 uint32_t* sample) {
   path_coords(rp, pid, view, pixel, sample);
-  const uint4 w = philox4x32_10(make_uint4(*pixel, *sample, (uint32_t)*view, 0u), rp.key0, rp.key1);
+  const uint4 w = philox4x32_10(make_uint4(*pixel, *sample, (uint32_t)*view, 0u), rp.keys[0], rp.keys[1]);
   return camera_ray(rp.cams[*view], *pixel, u01(w.x), u01(w.y));
 }
 
 // Bounce direction after hit b of a path (words 2, 3 of counter (pixel, sample, view, b)).
 __device__ __forceinline__ void bounce_dir(const RenderParams& rp, uint32_t pixel, uint32_t sample, int view, int b,
                                            const Shade& s, float* dx, float* dy, float* dz) {
-  const uint4 w = philox4x32_10(make_uint4(pixel, sample, (uint32_t)view, (uint32_t)b), rp.key0, rp.key1);
+  const uint4 w = philox4x32_10(make_uint4(pixel, sample, (uint32_t)view, (uint32_t)b), rp.keys[0], rp.keys[1]);
   cosine_dir(s.nx, s.ny, s.nz, u01(w.z), u01(w.w), dx, dy, dz);
 }
 

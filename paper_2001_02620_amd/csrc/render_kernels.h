@@ -72,5 +72,8 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
                                     float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s);
 hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
                           const float* grad_img, float* grad_albedo, hipStream_t s);
+// Write the call's RNG key to device memory (kept outside captured graphs, so a
+// replayed frame picks up the key of its own call).
+hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, hipStream_t s);
 
 }  // namespace rtq

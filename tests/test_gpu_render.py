@@ -190,6 +190,50 @@ def test_adjoint_config4_vs_oracle_and_fd():
     assert worst <= 1e-3
 
 
+@pytest.mark.parametrize("sched", [rtq.SCHED_PERSISTENT, rtq.SCHED_MEGAKERNEL, rtq.SCHED_PLAIN])
+def test_graph_replays_match_eager(sched):
+    """Captured render calls (uneven views in one call): every replay, with other
+    eager work and synchronisations between replays, equals the eager frame bit
+    for bit; a new frame index changes the image; new cameras capture anew."""
+    import torch
+    log(f"case: graph replay, scheduler {sched}")
+    scene, cams = _multi_view_scene()
+    S = rtq.Scene(scene)
+    st = sg.light_settings(2, 4, 77)
+    kw = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=sched)
+    eager = {}
+    for f in range(4):
+        st.frame = f
+        eager[f] = _render(S, cams, st, **kw)
+    assert not np.array_equal(eager[0], eager[1])
+    other = sg.light_settings(1, 2, 5)
+    n = sum(c.w * c.h for c in cams)
+    img = torch.empty(n, device="cuda")
+    for rep in range(3):
+        for f in (0, 1, 2, 3, 1):
+            st.frame = f
+            rtq.render(S, cams, st, images=img, graph=True, **kw)
+            torch.cuda.synchronize()
+            got = img.cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), eager[f].view(np.uint32)), (rep, f)
+            _render(S, cams[:1], other, **kw)  # eager work between replays
+    # another camera set: a second graph, still equal to eager
+    cams2 = cams[1:]
+    st.frame = 2
+    ref2 = _render(S, cams2, st, **kw)
+    for _ in range(2):
+        img2 = rtq.render(S, cams2, st, graph=True, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(img2.cpu().numpy().view(np.uint32), ref2.view(np.uint32))
+    # timing of graph calls: whole calls only
+    rtq.render_timing(S)
+    for f in range(3):
+        st.frame = f
+        rtq.render(S, cams, st, images=img, graph=True, timing=True, **kw)
+    t = rtq.render_timing(S)
+    assert t["call"]["launches"] == 3 and t["call"]["ms"] > 0.0 and t["closest"]["launches"] == 0
+
+
 def test_render_argument_errors():
     import torch
     scene, cams, st = sg.config1(n_inst=10)
