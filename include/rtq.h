@@ -48,7 +48,7 @@ extern "C" {
 #define RTQ_E_SINGULAR_XFORM (-2) /* an instance transform cannot be inverted */
 #define RTQ_E_OOM (-3)            /* device or host allocation failed */
 #define RTQ_E_HIP (-4)            /* a HIP runtime call failed */
-#define RTQ_E_LIMIT (-5)          /* a size exceeds an encoding limit of the node formats */
+#define RTQ_E_LIMIT (-5)          /* a size exceeds an encoding or dispatch limit */
 
 /* Message describing the last error on this thread (never NULL). */
 const char* rtq_last_error(void);
@@ -155,6 +155,8 @@ typedef struct {
 /*
  * Closest hit of n rays (device SoA in, device SoA out), enqueued on `stream`.
  * opts may be NULL.  Zero-length or NaN directions miss.  n may be 0.
+ * Errors: LIMIT when n exceeds 2^31 - 1 (a dispatch counts its work-items in
+ * 32 bits); INVALID_ARG for NULL arrays or options out of range.
  */
 int rtq_trace_closest(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits,
                       const rtq_trace_opts* opts, hipStream_t stream);
@@ -229,7 +231,8 @@ typedef struct {
  * the mean over its spp samples, summed in sample order, so every scheduler
  * produces bit-identical images.  cams: host memory.  Scratch memory is
  * allocated on first use and kept in the scene handle.
- * Errors: INVALID_ARG (spp < 1, depth < 1 or > 16, w or h < 1, NULL images).
+ * Errors: INVALID_ARG (spp < 1, depth < 1 or > 16, w or h < 1, NULL images);
+ * LIMIT when the call has more than 2^31 - 1 paths (sum of w h spp).
  */
 int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
                const rtq_render_opts* opts, float* images, hipStream_t stream);
@@ -247,6 +250,23 @@ int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, i
  * holds at most 4096 events; calls beyond it are not timed (launches tells).
  */
 int rtq_render_timing(rtq_scene* scene, float* ms, int32_t* launches);
+
+/*
+ * One path of rtq_render traced alone (same RNG counters, hits and shading as
+ * the render kernels; node format and stack depth from opts), for path-level
+ * checks: path (view, pixel, sample) with pixel = row * w + column.  Per vertex
+ * k < *n_vert: vert_i[6k..6k+5] = (instance id, primitive, half, shadow: -1 no
+ * shadow ray / 0 light visible / 1 occluded, unique face, 0) and
+ * vert_f[10k..10k+9] = (t, albedo, cosine to the light, radiance after the
+ * vertex, origin xyz and direction xyz of the ray that found the vertex);
+ * *escaped = 1 if the path left the scene; *radiance = its total.
+ * vert_i: host, 6 depth int32; vert_f: host, 10 depth floats.  Synchronises
+ * `stream`.  Errors: INVALID_ARG (view, pixel or sample out of range, NULL
+ * outputs), as rtq_render otherwise.
+ */
+int rtq_render_path(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
+                    const rtq_render_opts* opts, int32_t view, int64_t pixel, int32_t sample, int32_t* vert_i,
+                    float* vert_f, int32_t* n_vert, int32_t* escaped, float* radiance, hipStream_t stream);
 
 /*
  * Adjoint of rtq_render with respect to per-face albedo, paths held fixed:

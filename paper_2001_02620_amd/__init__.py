@@ -91,7 +91,7 @@ _lib = None
 
 EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destroy", "rtq_scene_get_info",
            "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
-           "rtq_render_backward"]
+           "rtq_render_backward", "rtq_render_timing", "rtq_render_path"]
 
 
 def load_library():
@@ -119,6 +119,8 @@ def load_library():
     L.rtq_render.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
     L.rtq_render_backward.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
     L.rtq_render_timing.argtypes = [P, P, P]
+    L.rtq_render_path.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32,
+                                  ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P]
     for f in EXPORTS:
         if f not in ("rtq_last_error", "rtq_version", "rtq_scene_destroy"):
             getattr(L, f).restype = ctypes.c_int
@@ -338,6 +340,27 @@ def render_timing(scene: Scene) -> dict:
                                             ctypes.cast(n, ctypes.c_void_p)))
     names = ("closest", "shadow", "other", "call")
     return {k: {"ms": float(ms[i]), "launches": int(n[i])} for i, k in enumerate(names)}
+
+
+def render_path(scene: Scene, cams, settings, view: int, pixel: int, sample: int, **opts):
+    """One path traced alone: (vertices, escaped, radiance); each vertex a dict
+    (inst, prim, half, shadow, face, t, albedo, cosl, radiance, origin and
+    direction of the ray that found it)."""
+    arr, _ = camera_structs(cams)
+    o = render_opts(settings, **opts)
+    d = settings.depth
+    vi = (ctypes.c_int32 * (6 * d))()
+    vf = (ctypes.c_float * (10 * d))()
+    nv, esc, rad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(load_library().rtq_render_path(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
+                                          d, ctypes.byref(o), view, pixel, sample, ctypes.cast(vi, ctypes.c_void_p),
+                                          ctypes.cast(vf, ctypes.c_void_p), ctypes.byref(nv), ctypes.byref(esc),
+                                          ctypes.byref(rad), _stream()))
+    verts = [dict(inst=vi[6 * k], prim=vi[6 * k + 1], half=vi[6 * k + 2], shadow=vi[6 * k + 3], face=vi[6 * k + 4],
+                  t=vf[10 * k], albedo=vf[10 * k + 1], cosl=vf[10 * k + 2], radiance=vf[10 * k + 3],
+                  origin=tuple(vf[10 * k + 4:10 * k + 7]), direction=tuple(vf[10 * k + 7:10 * k + 10]))
+             for k in range(nv.value)]
+    return verts, bool(esc.value), float(rad.value)
 
 
 def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None, **opts):

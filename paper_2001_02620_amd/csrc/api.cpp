@@ -475,6 +475,8 @@ int rtq_scene_set_albedo(rtq_scene* s, const float* albedo_dev, int64_t n, hipSt
 static int check_rays(const rtq_scene* s, const rtq_rays* r, int64_t n) {
   if (!s || !r) return set_error(RTQ_E_INVALID_ARG, "NULL scene or rays");
   if (n < 0) return set_error(RTQ_E_INVALID_ARG, "negative ray count");
+  // a dispatch counts its work-items in 32 bits (one ray per lane in the plain kernels)
+  if (n > (int64_t)0x7FFFFFFF) return set_error(RTQ_E_LIMIT, "%lld rays per call exceed 2^31 - 1", (long long)n);
   if (n > 0 && (!r->ox || !r->oy || !r->oz || !r->dx || !r->dy || !r->dz || !r->tmin || !r->tmax))
     return set_error(RTQ_E_INVALID_ARG, "NULL ray array");
   return RTQ_OK;

@@ -259,8 +259,9 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
     rc = ensure_scratch(s, path_base, n_cams, plain_buffers);
     if (rc) return rc;
   }
-  if (path_base >= (int64_t)0xFFFFFFFFll)
-    return set_error(RTQ_E_LIMIT, "%lld paths per call exceed 2^32", (long long)path_base);
+  // path ids are 32-bit, and a dispatch counts its work-items in 32 bits
+  if (path_base > (int64_t)0x7FFFFFFF)
+    return set_error(RTQ_E_LIMIT, "%lld paths per call exceed 2^31 - 1", (long long)path_base);
   RenderScratch* sc = scratch_of(s);
   const hipError_t e =
       hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);
@@ -452,6 +453,46 @@ int rtq_render_timing(rtq_scene* s, float* ms, int32_t* launches) {
   if (launches)
     for (int k = 0; k < 4; ++k) launches[k] = cnt[k];
   return rc;
+}
+
+int rtq_render_path(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
+                    const rtq_render_opts* opts, int32_t view, int64_t pixel, int32_t sample, int32_t* vert_i,
+                    float* vert_f, int32_t* n_vert, int32_t* escaped, float* radiance, hipStream_t stream) {
+  if (!vert_i || !vert_f || !n_vert || !escaped || !radiance) return set_error(RTQ_E_INVALID_ARG, "NULL output");
+  if (!cams || view < 0 || view >= n_cams) return set_error(RTQ_E_INVALID_ARG, "view %d outside [0, %d)", view, n_cams);
+  const int64_t wh = (int64_t)cams[view].w * cams[view].h;
+  if (pixel < 0 || pixel >= wh || sample < 0 || sample >= spp)
+    return set_error(RTQ_E_INVALID_ARG, "pixel or sample out of range");
+  Prepared p;
+  int rc = prepare(s, cams, n_cams, spp, depth, opts, false, stream, &p);
+  if (rc) return rc;
+  int64_t base = 0;
+  for (int32_t c = 0; c < view; ++c) base += (int64_t)cams[c].w * cams[c].h * spp;
+  const int64_t pid = base + (int64_t)sample * wh + pixel;
+  hipError_t e;
+  DeviceBuffers tmp;
+  int32_t* d_i = reinterpret_cast<int32_t*>(tmp.alloc(6 * kMaxDepth * sizeof(int32_t) + 64, &e));
+  float* d_f = reinterpret_cast<float*>(tmp.alloc((10 * kMaxDepth + 1) * sizeof(float), &e));
+  int32_t* d_o = reinterpret_cast<int32_t*>(tmp.alloc(64, &e));
+  if (!d_i || !d_f || !d_o) {
+    tmp.release();
+    return hip_error(e, "hipMalloc");
+  }
+  const SceneView sv = scene_view(s, p.fmt);
+  e = launch_path_record(sv, p.rp, p.fmt, p.tl.stack_depth, pid, d_i, d_f, d_o, stream);
+  int32_t ho[2] = {0, 0};
+  float hf[10 * kMaxDepth + 1];
+  if (e == hipSuccess) e = hipMemcpyAsync(vert_i, d_i, 6 * depth * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hf, d_f, sizeof(hf), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ho, d_o, sizeof(ho), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  tmp.release();
+  if (e != hipSuccess) return hip_error(e, "path record");
+  for (int k = 0; k < 10 * depth; ++k) vert_f[k] = hf[k];
+  *n_vert = ho[0];
+  *escaped = ho[1];
+  *radiance = hf[10 * kMaxDepth];
+  return RTQ_OK;
 }
 
 int rtq_render_backward(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "rtq_layout.h"
 
@@ -58,18 +60,18 @@ __global__ void k_invert_affine_fp64(const float* __restrict__ X, const int32_t*
 }
 
 // World box of each instance: the exact bounds of its prototype's vertices mapped
-// through the FP64 transform (one block per instance; every quad lies in the
-// convex hull of its vertices), padded by 2^-17 cond (|t| + |box|) for the FP32
-// ray-transform error and rounded outward to FP32.  For rotated instances this
-// is much tighter than the box of the eight transformed corners of the
-// prototype's object box.
-__global__ void __launch_bounds__(256) k_instance_aabb(const float* __restrict__ X, const int32_t* __restrict__ proto,
-                                                       const float* __restrict__ verts,
-                                                       const int64_t* __restrict__ vert_off,
-                                                       const float* __restrict__ cond, int64_t n,
-                                                       float* __restrict__ box) {
-  const int64_t i = blockIdx.x;
-  if (i >= n) return;
+// through the FP64 transform (one block per instance at a time; every quad lies
+// in the convex hull of its vertices), padded by 2^-17 cond (|t| + |box|) for the
+// FP32 ray-transform error and rounded outward to FP32.  For rotated instances
+// this is much tighter than the box of the eight transformed corners of the
+// prototype's object box.  Blocks stride over the instances: a dispatch counts
+// its work-items in 32 bits, so one block per instance would stop at 2^24
+// instances of 256 lanes.
+__device__ __forceinline__ void instance_aabb_one(const float* __restrict__ X, const int32_t* __restrict__ proto,
+                                                  const float* __restrict__ verts,
+                                                  const int64_t* __restrict__ vert_off,
+                                                  const float* __restrict__ cond, int64_t i,
+                                                  float* __restrict__ box, double (*red)[6]) {
   const float* x = X + 12 * i;
   double m[12];
   for (int j = 0; j < 12; ++j) m[j] = (double)x[j];
@@ -90,7 +92,6 @@ __global__ void __launch_bounds__(256) k_instance_aabb(const float* __restrict__
       lo[r] = fmin(lo[r], __shfl_xor(lo[r], o));
       hi[r] = fmax(hi[r], __shfl_xor(hi[r], o));
     }
-  __shared__ double red[4][6];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0)
     for (int r = 0; r < 3; ++r) {
@@ -98,19 +99,30 @@ __global__ void __launch_bounds__(256) k_instance_aabb(const float* __restrict__
       red[wave][3 + r] = hi[r];
     }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      for (int r = 0; r < 3; ++r) {
+        lo[r] = fmin(lo[r], red[w][r]);
+        hi[r] = fmax(hi[r], red[w][3 + r]);
+      }
+    double mag = fmax(fmax(fabs(m[3]), fabs(m[7])), fabs(m[11]));
+    for (int r = 0; r < 3; ++r) mag = fmax(mag, fmax(fabs(lo[r]), fabs(hi[r])));
+    const double pad = ldexp(1.0, -17) * (double)cond[i] * mag;
     for (int r = 0; r < 3; ++r) {
-      lo[r] = fmin(lo[r], red[w][r]);
-      hi[r] = fmax(hi[r], red[w][3 + r]);
+      box[6 * i + r] = __double2float_rd(lo[r] - pad);
+      box[6 * i + 3 + r] = __double2float_ru(hi[r] + pad);
     }
-  double mag = fmax(fmax(fabs(m[3]), fabs(m[7])), fabs(m[11]));
-  for (int r = 0; r < 3; ++r) mag = fmax(mag, fmax(fabs(lo[r]), fabs(hi[r])));
-  const double pad = ldexp(1.0, -17) * (double)cond[i] * mag;
-  for (int r = 0; r < 3; ++r) {
-    box[6 * i + r] = __double2float_rd(lo[r] - pad);
-    box[6 * i + 3 + r] = __double2float_ru(hi[r] + pad);
   }
+  __syncthreads();  // red is reused by the block's next instance
+}
+
+__global__ void __launch_bounds__(256) k_instance_aabb(const float* __restrict__ X, const int32_t* __restrict__ proto,
+                                                       const float* __restrict__ verts,
+                                                       const int64_t* __restrict__ vert_off,
+                                                       const float* __restrict__ cond, int64_t n,
+                                                       float* __restrict__ box) {
+  __shared__ double red[4][6];
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) instance_aabb_one(X, proto, verts, vert_off, cond, i, box, red);
 }
 
 __global__ void k_gather_inst(const InstRec* __restrict__ in, const uint32_t* __restrict__ order, int64_t n,
@@ -139,7 +151,8 @@ hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint
 hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const float* verts, const int64_t* vert_off,
                                 const float* cond, int64_t n, float* box, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_instance_aabb, dim3((unsigned)n), dim3(256), 0, s, X, proto, verts, vert_off, cond, n, box);
+  const unsigned grid = (unsigned)std::min<int64_t>(n, 65536);
+  hipLaunchKernelGGL(k_instance_aabb, dim3(grid), dim3(256), 0, s, X, proto, verts, vert_off, cond, n, box);
   return hipGetLastError();
 }
 

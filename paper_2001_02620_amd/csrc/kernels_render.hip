@@ -481,6 +481,85 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
   }
 }
 
+// One path traced by one lane with the device functions of the render kernels
+// (camera ray, closest hit, shading, shadow ray, bounce), recording per vertex
+// rec_i[6 k ..] = (instance id, primitive, half, shadow: -1 none / 0 visible /
+// 1 occluded, unique face, 0) and rec_f[10 k ..] = (t, albedo, cos to the light,
+// radiance after the vertex, origin xyz and direction xyz of the ray that found
+// it).  out[0] = vertices, out[1] = 1 if the path escaped, and
+// rec_f[10 kMaxDepth] holds the final radiance.
+template <int FMT>
+__global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int depth_lds, int32_t* rec_i,
+                              float* rec_f, int32_t* out) {
+  extern __shared__ uint2 lds[];
+  const Stack S = make_stack(lds, depth_lds);
+  uint2 spill[kStackTotal];
+  if (threadIdx.x != 0) return;
+  VisitCounters vc{0, 0, 0, 0};
+  int view;
+  uint32_t pixel, sample;
+  Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
+  float beta = 1.0f, radiance = 0.0f;
+  uint32_t ex_rec = kEmpty, ex_qh = kEmpty;
+  int n = 0, escaped = 0;
+  for (int b = 0; b < rp.depth; ++b) {
+    Lane L;
+    L.ex_rec = ex_rec;
+    L.ex_qh = ex_qh;
+    if (lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF))
+      while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+      }
+    if (L.b_rec == kEmpty) {
+      radiance += beta * rp.L_sky;
+      escaped = 1;
+      break;
+    }
+    const uint32_t hqh = L.b_qh;
+    const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31);
+    int shadow = -1;
+    if (sh.cosl > 0.0f) {
+      const float pending = nee_term(beta, sh.a, sh.cosl, rp);
+      Lane Ls;
+      Ls.ex_rec = L.b_rec;
+      Ls.ex_qh = hqh;
+      if (lane_init(Ls, sc, sh.px, sh.py, sh.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF)) {
+        Ls.any = true;
+        while (!lane_step<FMT, false>(Ls, sc, S, spill, vc)) {
+        }
+      }
+      shadow = Ls.b_rec != kEmpty ? 1 : 0;
+      if (shadow == 0) radiance += pending;
+    }
+    rec_i[6 * n + 0] = (int32_t)sc.inst[L.b_rec].inst_id;
+    rec_i[6 * n + 1] = sc.quad_prim[hqh & 0x7FFFFFFFu];
+    rec_i[6 * n + 2] = (int32_t)(hqh >> 31);
+    rec_i[6 * n + 3] = shadow;
+    rec_i[6 * n + 4] = (int32_t)sh.face;
+    rec_i[6 * n + 5] = 0;
+    rec_f[10 * n + 0] = L.t_best;
+    rec_f[10 * n + 1] = sh.a;
+    rec_f[10 * n + 2] = sh.cosl;
+    rec_f[10 * n + 3] = radiance;
+    rec_f[10 * n + 4] = r.ox;
+    rec_f[10 * n + 5] = r.oy;
+    rec_f[10 * n + 6] = r.oz;
+    rec_f[10 * n + 7] = r.dx;
+    rec_f[10 * n + 8] = r.dy;
+    rec_f[10 * n + 9] = r.dz;
+    ++n;
+    if (b == rp.depth - 1) break;
+    float dx, dy, dz;
+    bounce_dir(rp, pixel, sample, view, b, sh, &dx, &dy, &dz);
+    beta = beta * sh.a;
+    r = Ray3{sh.px, sh.py, sh.pz, dx, dy, dz};
+    ex_rec = L.b_rec;
+    ex_qh = hqh;
+  }
+  out[0] = n;
+  out[1] = escaped;
+  rec_f[10 * kMaxDepth] = radiance;
+}
+
 __global__ void k_start_tick(unsigned long long* t) {
   if (threadIdx.x == 0 && blockIdx.x == 0) t[0] = (unsigned long long)wall_clock64();
 }
@@ -703,6 +782,16 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
   stage_end(ex.log, 2, ev, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_path_record(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int64_t pid,
+                              int32_t* rec_i, float* rec_f, int32_t* out, hipStream_t s) {
+  const size_t lds = (size_t)64 * stack_depth * kStackEntryBytes;
+  if (fmt == 2)
+    hipLaunchKernelGGL((k_path_record<2>), dim3(1), dim3(64), lds, s, sc, rp, pid, stack_depth, rec_i, rec_f, out);
+  else
+    hipLaunchKernelGGL((k_path_record<1>), dim3(1), dim3(64), lds, s, sc, rp, pid, stack_depth, rec_i, rec_f, out);
   return hipGetLastError();
 }
 

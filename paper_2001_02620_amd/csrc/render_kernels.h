@@ -72,6 +72,9 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
                                     float* image, int64_t n_pixels, const RenderExtras& ex, hipStream_t s);
 hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int block,
                           const float* grad_img, float* grad_albedo, hipStream_t s);
+// Trace path `pid` alone and record its vertices (see k_path_record).
+hipError_t launch_path_record(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int64_t pid,
+                              int32_t* rec_i, float* rec_f, int32_t* out, hipStream_t s);
 // Write the call's RNG key to device memory (kept outside captured graphs, so a
 // replayed frame picks up the key of its own call).
 hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, hipStream_t s);

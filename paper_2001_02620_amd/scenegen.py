@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional, Tuple
+from typing import List, Optional, Tuple, Callable
 
 import numpy as np
 
@@ -281,14 +281,16 @@ def _log_uniform_int(rng, lo, hi, n):
 
 def island(seed: int, n_protos: int, n_inst: int, quad_lo: int = 2000, quad_hi: int = 200000,
            terrain_n: int = 2048, half: float = 1000.0, amp: float = 100.0,
-           cluster_frac: float = 0.0, n_clusters: int = 0, target_quads: Optional[int] = None):
+           cluster_frac: float = 0.0, n_clusters: int = 0, target_quads: Optional[int] = None,
+           progress: Optional[Callable[[str], None]] = None):
     """Prototype zoo instanced over a procedural terrain (configs 2, 3 and 5).
 
     Half the prototypes are noise-displaced grids with quad aspect U[1, 8] (long
     thin quads), half are closed cube-sphere shells; prototype size is
     log-uniform in [0.2, 20] m.  The terrain is the last prototype, instanced
     once with the identity.  With ``target_quads`` the prototype count grows
-    until the unique quad total reaches it.
+    until the unique quad total reaches it.  ``progress`` (optional) receives a
+    line every 512 prototypes.
     """
     rng = np.random.default_rng(seed)
     counts = list(_log_uniform_int(rng, quad_lo, quad_hi, n_protos))
@@ -298,6 +300,8 @@ def island(seed: int, n_protos: int, n_inst: int, quad_lo: int = 2000, quad_hi: 
     P = len(counts)
     protos = []
     for p in range(P):
+        if progress is not None and p % 512 == 0:
+            progress(f"generating prototype {p} of {P}")
         size = math.exp(rng.uniform(math.log(0.2), math.log(20.0)))
         c = int(counts[p])
         if p % 2 == 0:
@@ -349,14 +353,16 @@ def config2(seed: Optional[int] = None, scale: float = 1.0, res: Tuple[int, int]
     return scene, cams, light_settings(1, 8, seed)
 
 
-def config3(seed: Optional[int] = None, scale: float = 1.0, clustered: bool = True):
+def config3(seed: Optional[int] = None, scale: float = 1.0, clustered: bool = True,
+            progress: Optional[Callable[[str], None]] = None):
     """Config-2 generator grown to 20M instances / ~100M unique quads, 30% of the
     instances in tight clusters; 1920x1080 ground view, 4 spp, depth 8."""
     seed = SEED_BASE + 3 if seed is None else seed
     n_inst = max(8, int(round(20_000_000 * scale)))
     target = int(96_000_000 * scale)
     scene, fbm = island(seed, 256, n_inst, target_quads=target,
-                        cluster_frac=0.3 if clustered else 0.0, n_clusters=max(1, int(10000 * scale)))
+                        cluster_frac=0.3 if clustered else 0.0, n_clusters=max(1, int(10000 * scale)),
+                        progress=progress)
     g_eye = (-900.0, -900.0, float(fbm(-900.0, -900.0)) + 20.0)
     g_look = (0.0, 0.0, float(fbm(0.0, 0.0)))
     cams = [Camera(g_eye, g_look, (0.0, 0.0, 1.0), 50.0, 1920, 1080)]
@@ -374,14 +380,14 @@ def config5_cameras(rng: np.random.Generator, fbm: FBm, n_views: int = 64):
     return cams
 
 
-def config5(seed: Optional[int] = None, scale: float = 1.0):
+def config5(seed: Optional[int] = None, scale: float = 1.0, progress: Optional[Callable[[str], None]] = None):
     """40M instances, 250M unique quads, 64 square views of side log-uniform in
     [64, 1024], 1 spp, depth 6, all views in one launch."""
     seed = SEED_BASE + 5 if seed is None else seed
     n_inst = max(8, int(round(40_000_000 * scale)))
     target = int(246_000_000 * scale)
     scene, fbm = island(seed, 256, n_inst, target_quads=target,
-                        cluster_frac=0.3, n_clusters=max(1, int(20000 * scale)))
+                        cluster_frac=0.3, n_clusters=max(1, int(20000 * scale)), progress=progress)
     cams = config5_cameras(np.random.default_rng(seed + 1), fbm)
     return scene, cams, light_settings(1, 6, seed)
 

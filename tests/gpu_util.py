@@ -94,3 +94,54 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0):
         if (o.flags[i] & (oracle.F_GRAZE | oracle.F_NEAR_ORIGIN)) == 0:
             assert (int(gi[i]), int(gp[i])) in cands, f"ray {i}: gpu hit not among the oracle candidates"
     return flagged.mean()
+
+
+def camera_rays(cams, rng, n_per_cam):
+    """FP32 rays from each camera's eye through uniformly jittered image points
+    (pinhole model of the render), tmin 0, tmax +inf: [n, 8]."""
+    import math
+    out = []
+    for c in cams:
+        f = np.array(c.look, dtype=np.float64) - np.array(c.eye, dtype=np.float64)
+        f /= np.linalg.norm(f)
+        r = np.cross(f, c.up)
+        r /= np.linalg.norm(r)
+        u = np.cross(r, f)
+        th = math.tan(math.radians(c.vfov_deg) / 2)
+        xs = rng.uniform(0, c.w, n_per_cam)
+        ys = rng.uniform(0, c.h, n_per_cam)
+        d = f + ((2 * xs / c.w - 1) * th * c.w / c.h)[:, None] * r + ((1 - 2 * ys / c.h) * th)[:, None] * u
+        rr = np.zeros((n_per_cam, 8), np.float32)
+        rr[:, 0:3] = c.eye
+        rr[:, 3:6] = d
+        rr[:, 7] = np.inf
+        out.append(rr)
+    return np.concatenate(out)
+
+
+def compare_paths(rtq, oracle, S, o, cams, st, rng, n_paths, **kw):
+    """Paths traced alone on the GPU (rtq_render_path) against the oracle's FP64
+    paths: instance, primitive, half, shadow outcome and t of every vertex up to
+    the first vertex the oracle flags.  Returns the number of vertices compared."""
+    offs = np.cumsum([0] + [c.w * c.h for c in cams])
+    compared = 0
+    for g in rng.choice(int(offs[-1]), size=n_paths, replace=False):
+        view = int(np.searchsorted(offs, g, side="right") - 1)
+        p = int(g - offs[view])
+        s_ = int(rng.integers(0, st.spp))
+        gv, gesc, _ = rtq.render_path(S, cams, st, view, p, s_, **kw)
+        ov, oesc, pflags = o.path(cams, st, int(g), s_)
+        for k, y in enumerate(ov):
+            if (y["flags"] & oracle.ID_FLAGS) or y["shadow_flags"]:
+                break
+            assert k < len(gv), (g, s_, k, "gpu path ended early")
+            x = gv[k]
+            assert (x["inst"], x["prim"], x["half"]) == (y["inst"], y["prim"], y["half"]), (g, s_, k, x, y)
+            assert abs(x["t"] - y["t"]) <= 1e-5 * y["t"] or (y["flags"] & oracle.F_T_ILLCOND), (g, s_, k, x, y)
+            compared += 1
+            if y["flags"] & oracle.F_SHADE:
+                break
+            assert x["shadow"] == y["shadow"], (g, s_, k, x, y)
+        else:
+            assert gesc == oesc or pflags, (g, s_, gesc, oesc)
+    return compared

@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_2001_02620_amd import scenegen as sg
 from tests import scenes as ts
-from tests.gpu_util import log
+from tests.gpu_util import compare_paths, log
 
 pytestmark = pytest.mark.gpu
 
@@ -234,6 +234,42 @@ def test_graph_replays_match_eager(sched):
     assert t["call"]["launches"] == 3 and t["call"]["ms"] > 0.0 and t["closest"]["launches"] == 0
 
 
+def test_path_records_match_frame_and_oracle():
+    """rtq_render_path traces one path alone: its radiance equals the frame's pixel
+    bit for bit (1 spp), and its vertices (instance, primitive, half, shadow)
+    equal the oracle's FP64 path up to the first vertex the oracle flags."""
+    import torch
+    log("case: path records, config 1")
+    scene, cams, st = sg.config1()
+    S = rtq.Scene(scene)
+    o = oracle.OracleScene(scene)
+    kw = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+    st.frame = 3
+    img = _render(S, cams, st, **kw)
+    rng = np.random.default_rng(9)
+    n_pix = cams[0].w * cams[0].h
+    compared = 0
+    for p in rng.choice(n_pix, size=256, replace=False):
+        gv, gesc, grad = rtq.render_path(S, cams, st, 0, int(p), 0, **kw)
+        assert np.float32(grad).view(np.uint32) == img[p].view(np.uint32), (p, grad, img[p])
+        ov, oesc, pflags = o.path(cams, st, int(p), 0)
+        for k, y in enumerate(ov):
+            if (y["flags"] & oracle.ID_FLAGS) or y["shadow_flags"]:
+                break
+            assert k < len(gv), (p, k, "gpu path ended early")
+            x = gv[k]
+            assert (x["inst"], x["prim"], x["half"]) == (y["inst"], y["prim"], y["half"]), (p, k, x, y)
+            assert abs(x["t"] - y["t"]) <= 1e-5 * y["t"] or (y["flags"] & oracle.F_T_ILLCOND), (p, k, x, y)
+            compared += 1
+            if y["flags"] & oracle.F_SHADE:  # shading decisions near a threshold: stop here
+                break
+            assert x["shadow"] == y["shadow"], (p, k, x, y)
+        else:
+            assert gesc == oesc or pflags, (p, gesc, oesc)
+    log(f"  {compared} vertices compared")
+    assert compared >= 64
+
+
 def test_render_argument_errors():
     import torch
     scene, cams, st = sg.config1(n_inst=10)
@@ -248,3 +284,37 @@ def test_render_argument_errors():
         rtq.render(S, [sg.Camera((0, 0, 0), (0, 0, 0), (0, 0, 1), 40.0, 8, 8)], st)
     with pytest.raises(rtq.RtqError):
         rtq.render(S, cams, sg.RenderSettings(spp=1, depth=17))
+
+
+def test_config2_full_frame_bench_launch_vs_oracle():
+    """The full-size config-2 frame (1M instances, two 1920x1080 views, depth 8)
+    rendered the way the benchmark times it (quantized nodes, persistent
+    wavefront, default launch, stage timing on): bit-identical to the FP32 plain
+    frame and to a captured-graph replay; 256 sampled pixels match the oracle's
+    FP64 paths; 64 sampled paths match the oracle vertex by vertex."""
+    import torch
+    log("case: config 2 full size, benchmark launch")
+    scene, cams, st = sg.config2()
+    S = rtq.Scene(scene)
+    q8 = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+    st.frame = 2
+    a = _render(S, cams, st, timing=True, **q8)
+    rtq.render_timing(S)
+    b = _render(S, cams, st, node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PLAIN)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), "Q8 persistent and FP32 plain frames differ"
+    g1 = _render(S, cams, st, graph=True, **q8)
+    g2 = _render(S, cams, st, graph=True, **q8)
+    assert np.array_equal(a.view(np.uint32), g1.view(np.uint32))
+    assert np.array_equal(a.view(np.uint32), g2.view(np.uint32))
+    log("  frames bit-identical")
+    o = oracle.OracleScene(scene)
+    rng = np.random.default_rng(12)
+    n_pix = sum(c.w * c.h for c in cams)
+    pix = np.sort(rng.choice(n_pix, size=256, replace=False))
+    ref, fl, _ = o.render(cams, st, pixels=pix)
+    frac = _compare_image(a[pix], ref, fl)
+    log(f"  256 sampled pixels, flagged {frac:.4f}")
+    assert frac < 0.5
+    nv = compare_paths(rtq, oracle, S, o, cams, st, rng, 64, **q8)
+    log(f"  64 sampled paths, {nv} vertices compared")
+    assert nv >= 32
