@@ -256,9 +256,10 @@ def main():
         rng = np.random.default_rng(0)
         order = rng.permutation(n_pix)
         st.frame = 0
-        # untimed warm-up (the oracle builds its per-prototype BVHs on first use)
-        o.render(cams, st, pixels=np.sort(order[-min(args.cpu_pilot, n_pix):]))
+        # untimed warm-up of the pilot pixels (the oracle builds its per-prototype
+        # BVHs on first use), then the timed pilot on the warmed oracle
         pilot = np.sort(order[:min(args.cpu_pilot, n_pix)])
+        o.render(cams, st, pixels=pilot)
         w0 = time.perf_counter()
         o.render(cams, st, pixels=pilot)
         dt0 = time.perf_counter() - w0
