@@ -1,18 +1,23 @@
 // Path-tracing kernels.
 //
 // Plain scheduler (a wavefront path tracer after Laine, Karras, Aila 2013, one
-// kernel per stage): raygen -> per bounce [closest-hit queue trace -> shade
-// (appends shadow rays and extension rays with wave-aggregated compaction) ->
-// occlusion queue trace -> shadow resolve] -> accumulate.
+// kernel per stage, one ray per lane): raygen -> per bounce [closest-hit queue
+// trace -> shade (appends shadow rays and extension rays with block-aggregated
+// compaction) -> occlusion queue trace -> shadow resolve] -> accumulate.
 //
-// Persistent scheduler: one launch.  Resident waves pull path ids from a shared
-// counter; each lane runs one path, alternating extension and shadow rays in a
+// Persistent scheduler: the same stages, but each traversal launch is
+// persistent (resident waves refill idle lanes from sliced claim counters) and
+// traces the shadow rays of bounce b together with the extension rays of
+// bounce b + 1.
+//
+// Megakernel: one launch.  Resident waves pull path ids from the claim
+// counters; each lane runs one path, alternating extension and shadow rays in a
 // single traversal loop, and finished lanes are refilled with new paths
-// (regeneration) whenever enough of the wave is idle, across every view.
+// whenever enough of the wave is idle, across every view.
 //
-// Both schedulers evaluate each path with the same device functions in the same
+// All schedulers evaluate each path with the same device functions in the same
 // order and write its radiance to its own slot; the image is the per-pixel mean
-// over samples in sample order, so both produce bit-identical images.
+// over samples in sample order, so they produce bit-identical images.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,16 +27,37 @@
 
 namespace rtq {
 
-// Wave-aggregated append: returns this lane's slot (valid where want is true).
-__device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter) {
-  const unsigned long long m = __ballot(want);
-  if (m == 0ull) return 0u;
-  const int leader = __ffsll((long long)m) - 1;
-  uint32_t base = 0u;
-  if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-  base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-  const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-  return base + rank;
+// Threads per block of the shading kernel.
+constexpr int kShadeBlock = 512;
+
+// Block-aggregated append to two queues (one atomic per queue per block, since
+// atomics on one counter serialise): sets *ja / *jb to this thread's slots where
+// wa / wb hold.  Every thread of a kShadeBlock-thread block must call it.
+__device__ __forceinline__ void block_append2(bool wa, bool wb, uint32_t* ca, uint32_t* cb, uint32_t* ja,
+                                              uint32_t* jb) {
+  constexpr int kWaves = kShadeBlock / 64;
+  __shared__ uint32_t wcnt[2][kWaves];
+  __shared__ uint32_t base[2];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const unsigned long long ma = __ballot(wa), mb = __ballot(wb);
+  if (lane == 0) {
+    wcnt[0][w] = (uint32_t)__popcll(ma);
+    wcnt[1][w] = (uint32_t)__popcll(mb);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    uint32_t tot = 0u;
+    for (int k = 0; k < kWaves; ++k) tot += wcnt[threadIdx.x][k];
+    base[threadIdx.x] = tot ? atomicAdd(threadIdx.x == 0 ? ca : cb, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t pa = base[0], pb = base[1];
+  for (int k = 0; k < w; ++k) {
+    pa += wcnt[0][k];
+    pb += wcnt[1][k];
+  }
+  *ja = pa + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+  *jb = pb + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
 }
 
 // Sum per-lane visit counters over the wave; one atomic per counter per wave.
@@ -46,6 +72,7 @@ __device__ __forceinline__ void wave_add_visits(const VisitCounters& vc, unsigne
   }
 }
 
+// Wave-aggregated append: returns this lane's slot (valid where want is true).
 __device__ __forceinline__ unsigned long long wave_append64(bool want, unsigned long long* counter) {
   const unsigned long long m = __ballot(want);
   if (m == 0ull) return 0ull;
@@ -231,7 +258,8 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
       }
     }
   }
-  const uint32_t js = wave_append(want_shadow, count_sq);
+  uint32_t js, jn;
+  block_append2(want_shadow, want_next, count_sq, count_out, &js, &jn);
   if (want_shadow) {
     sq.ox[js] = s.px;
     sq.oy[js] = s.py;
@@ -241,7 +269,6 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     sq.ex_rec[js] = rec;
     sq.ex_qh[js] = qhv;
   }
-  const uint32_t jn = wave_append(want_next, count_out);
   if (want_next) {
     out.ox[jn] = s.px;
     out.oy[jn] = s.py;
@@ -643,6 +670,7 @@ template <int FMT, bool COUNT>
 static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb, int b,
                              const TraceLaunch& tl, const RenderExtras& ex, hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
+  const unsigned gs = blocks(rp.n_paths, kShadeBlock);
   const unsigned gt = blocks(rp.n_paths, tl.block);
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   const ExtQueue& qin = pb.q[b & 1];
@@ -656,7 +684,7 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
                      pb.hits, pb.occ, tl.stack_depth, ex.visits);
   stage_end(ex.log, 0, ev, s);
   ev = stage_begin(ex.log, s);
-  hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
+  hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
                      ex.dump, ex.dump_cap, ex.dump_count);
   stage_end(ex.log, 2, ev, s);
   ev = stage_begin(ex.log, s);
@@ -686,6 +714,7 @@ template <int FMT, bool COUNT>
 static void wavefront_persistent(const SceneView& sc, const RenderParams& rp, const PlainBuffers& pb,
                                  const TraceLaunch& tl, const RenderExtras& ex, hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
+  const unsigned gs = blocks(rp.n_paths, kShadeBlock);
   const uint32_t* zero = pb.counts + 2 * kMaxDepth + 1;  // cleared, never written
   mixed_launch<FMT, COUNT>(sc, rp, pb, tl, ex, pb.q[0], pb.counts, zero, 0, s);
   for (int b = 0; b < rp.depth; ++b) {
@@ -695,8 +724,8 @@ static void wavefront_persistent(const SceneView& sc, const RenderParams& rp, co
     uint32_t* cout = pb.counts + b + 1;
     uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
     hipEvent_t ev = stage_begin(ex.log, s);
-    hipLaunchKernelGGL(k_shade, dim3(gp), dim3(256), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
-                       ex.dump, ex.dump_cap, ex.dump_count);
+    hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq,
+                       csq, ex.dump, ex.dump_cap, ex.dump_count);
     stage_end(ex.log, 2, ev, s);
     // after the last bounce the extension count stays zero: shadow rays only
     mixed_launch<FMT, COUNT>(sc, rp, pb, tl, ex, qout, cout, csq, b + 1, s);
