@@ -85,6 +85,9 @@ typedef struct {
   int32_t sah_bins;      /* binned-SAH bins of the bottom levels, 4..64; 0 = 32 (the top level uses 64) */
   int32_t build_threads; /* host threads for the bottom-level builds; 0 = all */
   int32_t device;        /* HIP device ordinal; -1 = current */
+  int32_t open_pct;      /* top-level entries added by opening instances into subtrees of their
+                            bottom-level BVH (partial re-braiding), in percent of the instance
+                            count; 0 = default (50), negative = none.  Hits do not depend on it. */
 } rtq_build_opts;
 
 /*
@@ -114,6 +117,7 @@ typedef struct {
   int32_t formats;                    /* RTQ_NODE_* built */
   int64_t device_bytes;               /* all device memory held by the scene */
   double build_seconds;               /* wall time of rtq_scene_build */
+  int64_t n_top_entries;              /* top-level leaves: instances plus the subtrees opened ones add */
 } rtq_scene_info;
 
 int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);

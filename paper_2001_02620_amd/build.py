@@ -21,6 +21,7 @@ SOURCES = [
     "api.cpp",
     "api_render.cpp",
     "bvh_build.cpp",
+    "rebraid.cpp",
     "kernels_build.hip",
     "kernels_trace.hip",
     "kernels_render.hip",

@@ -17,6 +17,7 @@
 #include "api_internal.h"
 #include "bvh_build.h"
 #include "kernels.h"
+#include "rebraid.h"
 
 using namespace rtq;
 
@@ -64,11 +65,11 @@ SceneView scene_view(const rtq_scene* s, int fmt) {
   v.quads = s->quads;
   v.quad_prim = s->quad_prim;
   v.inst = s->inst;
-  v.proto_qbase = s->proto_qbase;
-  v.proto_nq = s->proto_nq;
+  v.rec_qfirst = s->rec_qfirst;
+  v.rec_nq = s->rec_nq;
   v.albedo = s->albedo;
   v.pad_rel = s->pad_rel;
-  v.n_inst = (uint32_t)s->n_inst;
+  v.n_rec = (uint32_t)s->n_rec;
   return v;
 }
 
@@ -114,6 +115,10 @@ extern "C" {
 const char* rtq_last_error(void) { return g_err.c_str(); }
 
 const char* rtq_version(void) { return "rtq 0.1 (gfx950)"; }
+
+// Extra top-level entries from opened instances, in percent of the instance
+// count, when the caller leaves rtq_build_opts.open_pct at 0.
+constexpr int32_t kDefaultOpenPct = 50;
 
 static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
                       const rtq_build_opts* opts, rtq_scene** out) {
@@ -279,21 +284,20 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy"));                  \
   } while (0)
 
-  // bottom levels first; the top level is appended once it is built
+  // bottom levels first; the top level is appended once it is built.  The FP32
+  // nodes stay on the host in any case: opening instances reads their boxes.
   std::vector<NodeF32> nf;
   std::vector<NodeQ8> nq;
-  if (formats & RTQ_NODE_FP32) nf.reserve(n_blas_nodes);
+  nf.reserve(n_blas_nodes);
   if (formats & RTQ_NODE_Q8) nq.reserve(n_blas_nodes);
   for (int32_t p = 0; p < n_protos; ++p) {
-    if (formats & RTQ_NODE_FP32) nf.insert(nf.end(), blas[p].f32.begin(), blas[p].f32.end());
+    nf.insert(nf.end(), blas[p].f32.begin(), blas[p].f32.end());
     if (formats & RTQ_NODE_Q8) nq.insert(nq.end(), blas[p].q8.begin(), blas[p].q8.end());
     blas[p] = Bvh4{};  // release host memory early
   }
   UPLOAD(s->quads, quads.data(), quads.size() * sizeof(float4));
   UPLOAD(s->quad_prim, quad_prim.data(), quad_prim.size() * sizeof(int32_t));
   UPLOAD(s->albedo, albedo.data(), albedo.size() * sizeof(float));
-  UPLOAD(s->proto_qbase, proto_qbase.data(), proto_qbase.size() * sizeof(int32_t));
-  UPLOAD(s->proto_nq, proto_nq.data(), proto_nq.size() * sizeof(int32_t));
   s->blas_nodes = (int64_t)n_blas_nodes;
   s->blas_depth = max_blas_depth;
   quads = std::vector<float4>();
@@ -367,17 +371,42 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   }
   s->pad_rel = std::ldexp(1.0f, -17) * cond_max;
 
-  // ---- top level over the padded instance boxes (one instance per leaf)
+  // ---- top-level entries: every instance, large ones opened into subtrees.
+  // The host pad bound uses the padded box, so it is at least the device's.
+  std::vector<TopEntry> entries;
+  {
+    std::vector<double> pad(N);
+    for (int64_t i = 0; i < N; ++i) {
+      const float* x = insts->xform + 12 * i;
+      double mag = std::max(std::max(std::fabs((double)x[3]), std::fabs((double)x[7])), std::fabs((double)x[11]));
+      for (int r = 0; r < 3; ++r)
+        mag = std::max(mag, std::max(std::fabs((double)boxes[i].lo[r]), std::fabs((double)boxes[i].hi[r])));
+      pad[i] = std::ldexp(1.0, -17) * (double)cond[i] * mag;
+    }
+    OpenParams op;
+    const int32_t pct = o.open_pct == 0 ? kDefaultOpenPct : std::max(o.open_pct, 0);
+    op.budget = std::min<int64_t>(N * (int64_t)pct / 100, (int64_t)kMaxLeafFirst - N);
+    entries = open_instances(N, insts->xform, insts->proto, boxes.data(), pad.data(), proto_root, proto_qbase,
+                             proto_nq, nf, op);
+  }
+  const int64_t E = (int64_t)entries.size();
+  s->n_rec = E;
+  if (!(formats & RTQ_NODE_FP32)) nf = std::vector<NodeF32>();
+
+  // ---- top level over the padded entry boxes (one entry per leaf)
   Bvh4 tlas;
   BuildParams tp = bp;
   tp.leaf_max = 1;
-  tp.bins = std::max(bp.bins, 64);  // one box per instance: finer bins are cheap here
-  if (N > 0) {
-    build_bvh4(boxes.data(), N, tp, tlas);
+  tp.bins = std::max(bp.bins, 64);  // one box per entry: finer bins are cheap here
+  if (E > 0) {
+    std::vector<Aabb> eb(E);
+    for (int64_t k = 0; k < E; ++k) eb[k] = entries[k].box;
+    boxes = std::vector<Aabb>();
+    build_bvh4(eb.data(), E, tp, tlas);
   } else {
     Aabb none;
     for (int a = 0; a < 3; ++a) none.lo[a] = none.hi[a] = 0.0f;
-    build_bvh4(&none, 1, tp, tlas);  // placeholder root; n_inst = 0 makes every ray miss first
+    build_bvh4(&none, 1, tp, tlas);  // placeholder root; n_rec = 0 makes every ray miss first
   }
   if (n_blas_nodes + tlas.f32.size() >= (uint64_t)kLeafBit)
     return tfail(set_error(RTQ_E_LIMIT, "node count exceeds 2^31"));
@@ -400,18 +429,33 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     UPLOAD(s->nodes_q8, nq.data(), nq.size() * sizeof(NodeQ8));
     nq = std::vector<NodeQ8>();
   }
+  // records in top-level leaf order
+  const int64_t En = std::max<int64_t>(E, 1);
   {
-    std::vector<float> rec_pmax(Nn, 0.0f);
-    for (int64_t r = 0; r < N; ++r) rec_pmax[r] = proto_pmax[insts->proto[tlas.order[r]]];
+    std::vector<float> rec_pmax(En, 0.0f);
+    std::vector<uint32_t> rec_qfirst(En, 0u), rec_nq(En, 0u), order(En, 0u), root(En, 0u);
+    for (int64_t r = 0; r < E; ++r) {
+      const TopEntry& t = entries[tlas.order[r]];
+      rec_pmax[r] = proto_pmax[insts->proto[t.inst]];
+      rec_qfirst[r] = t.q_first;
+      rec_nq[r] = t.q_count;
+      order[r] = t.inst;
+      root[r] = t.ref;
+    }
+    entries = std::vector<TopEntry>();
     UPLOAD(s->rec_pmax, rec_pmax.data(), rec_pmax.size() * sizeof(float));
-  }
-  s->inst = reinterpret_cast<InstRec*>(s->bufs.alloc(Nn * sizeof(InstRec), &e));
-  if (!s->inst) return tfail(hip_error(e, "hipMalloc"));
-  if (N > 0) {
-    uint32_t* d_order;
-    TALLOC(d_order, N * sizeof(uint32_t));
-    TCHECK(hipMemcpy(d_order, tlas.order.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
-    TCHECK(launch_gather_inst(d_rec, d_order, N, s->inst, 0), "gather kernel");
+    UPLOAD(s->rec_qfirst, rec_qfirst.data(), rec_qfirst.size() * sizeof(uint32_t));
+    UPLOAD(s->rec_nq, rec_nq.data(), rec_nq.size() * sizeof(uint32_t));
+    s->inst = reinterpret_cast<InstRec*>(s->bufs.alloc(En * sizeof(InstRec), &e));
+    if (!s->inst) return tfail(hip_error(e, "hipMalloc"));
+    if (E > 0) {
+      uint32_t *d_order, *d_eroot;
+      TALLOC(d_order, E * sizeof(uint32_t));
+      TALLOC(d_eroot, E * sizeof(uint32_t));
+      TCHECK(hipMemcpy(d_order, order.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+      TCHECK(hipMemcpy(d_eroot, root.data(), E * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+      TCHECK(launch_gather_inst(d_rec, d_order, d_eroot, E, s->inst, 0), "gather kernel");
+    }
   }
   s->counters = reinterpret_cast<unsigned long long*>(
       s->bufs.alloc((size_t)rtq_scene::kCounterSlots * kClaimWords * sizeof(unsigned long long), &e));
@@ -460,6 +504,7 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->formats = s->formats;
   info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total);
   info->build_seconds = s->build_seconds;
+  info->n_top_entries = s->n_rec;
   return RTQ_OK;
 }
 

@@ -34,6 +34,7 @@ struct rtq_scene {
   int max_lds = 65536;  // bytes of LDS one block may use
   int32_t n_protos = 0;
   int64_t n_inst = 0, n_quads = 0, n_instanced_quads = 0;
+  int64_t n_rec = 0;  // top-level entries (instances, opened ones counted per subtree)
   int64_t tlas_nodes = 0, blas_nodes = 0;
   int tlas_depth = 0, blas_depth = 0;
   double build_seconds = 0.0;
@@ -47,8 +48,8 @@ struct rtq_scene {
   float4* quads = nullptr;
   int32_t* quad_prim = nullptr;
   rtq::InstRec* inst = nullptr;
-  int32_t* proto_qbase = nullptr;
-  int32_t* proto_nq = nullptr;
+  uint32_t* rec_qfirst = nullptr;  // per record: quad range of the subtree it enters
+  uint32_t* rec_nq = nullptr;
   float* albedo = nullptr;
   unsigned long long* counters = nullptr;  // ring of persistent-kernel work counters
   mutable std::atomic<uint32_t> counter_next{0};

@@ -13,7 +13,9 @@ hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint
                                 hipStream_t s);
 hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const float* verts, const int64_t* vert_off,
                                 const float* cond, int64_t n, float* box, hipStream_t s);
-hipError_t launch_gather_inst(const InstRec* in, const uint32_t* order, int64_t n, InstRec* out, hipStream_t s);
+// out[k] = in[order[k]] with its bottom-level entry reference replaced by root[k].
+hipError_t launch_gather_inst(const InstRec* in, const uint32_t* order, const uint32_t* root, int64_t n, InstRec* out,
+                              hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 
 struct RaysSoA {

@@ -125,11 +125,13 @@ __global__ void __launch_bounds__(256) k_instance_aabb(const float* __restrict__
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) instance_aabb_one(X, proto, verts, vert_off, cond, i, box, red);
 }
 
-__global__ void k_gather_inst(const InstRec* __restrict__ in, const uint32_t* __restrict__ order, int64_t n,
-                              InstRec* __restrict__ out) {
+__global__ void k_gather_inst(const InstRec* __restrict__ in, const uint32_t* __restrict__ order,
+                              const uint32_t* __restrict__ root, int64_t n, InstRec* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out[i] = in[order[i]];
+  InstRec r = in[order[i]];
+  r.blas_root = root[i];
+  out[i] = r;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -156,9 +158,10 @@ hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const floa
   return hipGetLastError();
 }
 
-hipError_t launch_gather_inst(const InstRec* in, const uint32_t* order, int64_t n, InstRec* out, hipStream_t s) {
+hipError_t launch_gather_inst(const InstRec* in, const uint32_t* order, const uint32_t* root, int64_t n, InstRec* out,
+                              hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_inst, dim3(grid_for(n, 256)), dim3(256), 0, s, in, order, n, out);
+  hipLaunchKernelGGL(k_gather_inst, dim3(grid_for(n, 256)), dim3(256), 0, s, in, order, root, n, out);
   return hipGetLastError();
 }
 

@@ -113,11 +113,10 @@ __global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
   if (i >= n) return;
   Lane L;
   if (load_ray<false>(L, sc, rays, i)) {
-    for (uint32_t r = 0; r < sc.n_inst; ++r) {
+    for (uint32_t r = 0; r < sc.n_rec; ++r) {
       uint32_t root;
       enter_instance(L, sc, r, &root);
-      const uint32_t p = sc.inst[r].proto;
-      leaf_quads(L, sc, (uint32_t)sc.proto_qbase[p], (uint32_t)sc.proto_nq[p]);
+      leaf_quads(L, sc, sc.rec_qfirst[r], sc.rec_nq[r]);
     }
   }
   store_result<false>(L, sc, i, hits, nullptr);

@@ -31,15 +31,16 @@ struct SceneView {
   const uint4* nodes;         // nodes of the traced format: every bottom level, then the top level
   const float4* quads;        // leaf-ordered quads, 3 float4 each
   const int32_t* quad_prim;   // leaf order -> quad index within its prototype
-  const InstRec* inst;        // instance records in TLAS leaf order
+  const InstRec* inst;        // top-level entries in TLAS leaf order: an instance's record, entered
+                              // at its bottom-level root or at one subtree of an opened instance
   const float* rec_pmax;      // per record: bound on |object coordinate| of its prototype's boxes
-  const int32_t* proto_qbase; // first leaf-ordered quad of each prototype
-  const int32_t* proto_nq;    // quads per prototype
+  const uint32_t* rec_qfirst; // per record: first leaf-ordered quad of the subtree it enters
+  const uint32_t* rec_nq;     // per record: quads of that subtree
   const float* albedo;        // per unique face (prototype order)
   float pad_rel;              // top-level origin pad per unit of |o|_inf
   float p_world;              // bound on |world coordinate| of the top-level boxes
   uint32_t tlas_root;         // index of the top-level root in `nodes`
-  uint32_t n_inst;
+  uint32_t n_rec;             // records (0 for a scene without instances)
 };
 
 constexpr float kSlack = 1.0f + 1.52587890625e-05f;  // 1 + 2^-16
@@ -530,7 +531,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   const bool finite = __builtin_isfinite(ox) && __builtin_isfinite(oy) && __builtin_isfinite(oz) &&
                       __builtin_isfinite(dx) && __builtin_isfinite(dy) && __builtin_isfinite(dz) &&
                       !(dx == 0.0f && dy == 0.0f && dz == 0.0f) && !(tmin != tmin) && !(tmax != tmax);
-  if (!finite || sc.n_inst == 0u) {
+  if (!finite || sc.n_rec == 0u) {
     L.cur = kEmpty;
     L.done = true;
     return false;

@@ -240,3 +240,49 @@ def test_config2_sampled_rays_vs_oracle():
     o = oracle.OracleScene(scene).trace(rays)
     frac = compare_with_oracle(scene, rays, ref, o)
     log(f"  hit fraction {(o.inst >= 0).mean():.3f} flagged {frac:.4f}")
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "config1", "config2_small"])
+def test_opened_instances_keep_hits_and_images(cfg):
+    """Opening instances into subtrees in the top level (rtq_build_opts.open_pct)
+    changes which entries a ray visits, never its hits: closest hits of every
+    opening budget equal the unopened scene's and the brute-force reference bit
+    for bit, and so do rendered frames."""
+    import torch
+    log(f"case: opened instances, {cfg}")
+    rng = np.random.default_rng(17)
+    if cfg == "tiny":
+        scene = sg.tiny_scene(8, n_inst=5, n_protos=2, nq=8, spread=1.2)
+        cams = [sg.Camera((0.0, -9.0, 1.5), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 50.0, 40, 30)]
+        st = sg.RenderSettings(spp=2, depth=4, seed=3)
+        rays = _tiny_rays(8, 20000)
+    elif cfg == "config1":
+        scene, cams, st = sg.config1()
+        rays = sg.random_rays(rng, 20000, -80, 80, -50, 50)
+    else:
+        scene, cams, st = sg.config2(scale=0.01, res=(96, 64))
+        rays = sg.random_rays(rng, 20000, [-1000, -1000, 0], [1000, 1000, 150], [-1000, -1000, -50],
+                              [1000, 1000, 100])
+    R = to_dev(rays)
+    ref = img = None
+    for pct in (-1, 0, 400, 100000):
+        S = rtq.Scene(scene, open_pct=pct)
+        info = S.info()
+        log(f"  open_pct {pct}: {info['n_top_entries']} top-level entries for {info['n_instances']} instances")
+        if pct == -1:
+            assert info["n_top_entries"] == info["n_instances"]
+        if pct == 100000:
+            assert info["n_top_entries"] > info["n_instances"]
+        h = hits_np(rtq.trace_closest(S, R, node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT))
+        hb = hits_np(rtq.trace_brute(S, R))
+        assert_hits_identical(hb, h, f"open_pct {pct} vs its brute force")
+        st.frame = 1
+        im = rtq.render(S, cams, st, node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+        torch.cuda.synchronize()
+        im = im.cpu().numpy()
+        if ref is None:
+            ref, img = h, im
+        else:
+            assert_hits_identical(ref, h, f"open_pct {pct} vs unopened")
+            assert np.array_equal(img.view(np.uint32), im.view(np.uint32)), f"open_pct {pct}: image differs"
+        S.close()
