@@ -256,8 +256,8 @@ def main():
         rng = np.random.default_rng(0)
         order = rng.permutation(n_pix)
         st.frame = 0
-        # untimed warm-up of the pilot pixels (the oracle builds its per-prototype
-        # BVHs on first use), then the timed pilot on the warmed oracle
+        # untimed warm-up of the pilot pixels (pages the oracle's scene in), then
+        # the timed pilot
         pilot = np.sort(order[:min(args.cpu_pilot, n_pix)])
         o.render(cams, st, pixels=pilot)
         w0 = time.perf_counter()
@@ -265,11 +265,18 @@ def main():
         dt0 = time.perf_counter() - w0
         n_cpu = int(min(n_pix, max(pilot.size, pilot.size * args.cpu_seconds / max(dt0, 1e-3))))
         log(f"cpu baseline: pilot {pilot.size} px in {dt0:.1f} s; timing {n_cpu} px")
-        pix = np.sort(order[:n_cpu])
-        o.render(cams, st, pixels=pix)  # untimed: builds the prototype BVHs this sample reaches
-        w0 = time.perf_counter()
-        _, fl, stats = o.render(cams, st, pixels=pix)
-        dt = time.perf_counter() - w0
+        # per-pixel cost varies a lot, so a small pilot drains unevenly over the
+        # host threads and underestimates the rate: re-size once if the sample
+        # came out well short of its target length
+        for attempt in range(2):
+            pix = np.sort(order[:n_cpu])
+            w0 = time.perf_counter()
+            _, fl, stats = o.render(cams, st, pixels=pix)
+            dt = time.perf_counter() - w0
+            if attempt == 1 or dt >= 0.7 * args.cpu_seconds or n_cpu == n_pix:
+                break
+            n_cpu = int(min(n_pix, n_cpu * args.cpu_seconds / max(dt, 1e-3)))
+            log(f"cpu baseline: {pix.size} px took {dt:.1f} s; timing {n_cpu} px")
         cpu = {"value": (stats["closest"] + stats["shadow"]) / dt / 1e6, "unit": "Mrays/s",
                "cores": oracle.get_threads(), "kind": "oracle",
                "sample": f"{pix.size} random pixels of frame 0 (both views), all paths, FP64 with flags; "

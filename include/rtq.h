@@ -118,6 +118,9 @@ typedef struct {
   int64_t device_bytes;               /* all device memory held by the scene */
   double build_seconds;               /* wall time of rtq_scene_build */
   int64_t n_top_entries;              /* top-level leaves: instances plus the subtrees opened ones add */
+  double build_phase_seconds[4];      /* bottom levels (host); instance inverses and boxes (device) and
+                                         bottom-level upload; opening instances (host); top level
+                                         (host) and its upload */
 } rtq_scene_info;
 
 int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);

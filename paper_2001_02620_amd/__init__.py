@@ -53,7 +53,8 @@ class _Info(ctypes.Structure):
                 ("n_unique_quads", ctypes.c_int64), ("n_instanced_quads", ctypes.c_int64),
                 ("tlas_nodes", ctypes.c_int64), ("blas_nodes", ctypes.c_int64), ("tlas_depth", ctypes.c_int32),
                 ("blas_depth_max", ctypes.c_int32), ("formats", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double), ("n_top_entries", ctypes.c_int64)]
+                ("build_seconds", ctypes.c_double), ("n_top_entries", ctypes.c_int64),
+                ("build_phase_seconds", ctypes.c_double * 4)]
 
 
 class _Rays(ctypes.Structure):
@@ -192,7 +193,9 @@ class Scene:
     def info(self) -> dict:
         i = _Info()
         _check(load_library().rtq_scene_get_info(self.handle, ctypes.byref(i)))
-        return {k: getattr(i, k) for k, _ in _Info._fields_}
+        out = {k: getattr(i, k) for k, _ in _Info._fields_}
+        out["build_phase_seconds"] = list(i.build_phase_seconds)
+        return out
 
     def set_albedo(self, albedo) -> None:
         assert albedo.dtype.is_floating_point and albedo.numel() == self.n_quads and albedo.is_cuda

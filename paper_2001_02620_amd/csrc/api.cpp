@@ -123,6 +123,9 @@ constexpr int32_t kDefaultOpenPct = 50;
 static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
                       const rtq_build_opts* opts, rtq_scene** out) {
   const auto t0 = std::chrono::steady_clock::now();
+  auto since = [](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+  };
   if (!out) return set_error(RTQ_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!protos || n_protos < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one prototype");
@@ -176,33 +179,47 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   std::vector<int32_t> order_p(n_protos);
   for (int32_t p = 0; p < n_protos; ++p) order_p[p] = p;
   std::sort(order_p.begin(), order_p.end(), [&](int a, int b) { return protos[a].n_quads > protos[b].n_quads; });
-  int nthreads = o.build_threads > 0 ? o.build_threads : (int)std::max(1u, std::thread::hardware_concurrency());
-  nthreads = std::min(nthreads, n_protos);
-  std::atomic<int32_t> next{0};
+  const int nthreads_all =
+      o.build_threads > 0 ? o.build_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  // prototypes of kBigProto quads or more are built one at a time on every
+  // thread (they come first in order_p); the rest concurrently, one per thread
+  constexpr int32_t kBigProto = 1 << 18;
+  int32_t n_big = 0;
+  while (n_big < n_protos && protos[order_p[n_big]].n_quads >= kBigProto) ++n_big;
+  const int nthreads = std::min(nthreads_all, std::max(1, n_protos - n_big));
+  std::atomic<int32_t> next{n_big};
+  auto build_proto = [&](int32_t p, int threads, std::vector<Aabb>& boxes) {
+    const rtq_prototype& P = protos[p];
+    boxes.resize(P.n_quads);
+    for (int32_t q = 0; q < P.n_quads; ++q) {
+      Aabb b;
+      for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::numeric_limits<float>::infinity();
+        b.hi[a] = -std::numeric_limits<float>::infinity();
+      }
+      for (int c = 0; c < 4; ++c) {
+        const float* v = P.verts + 3 * (int64_t)P.quads[4 * (int64_t)q + c];
+        for (int a = 0; a < 3; ++a) {
+          b.lo[a] = std::min(b.lo[a], v[a]);
+          b.hi[a] = std::max(b.hi[a], v[a]);
+        }
+      }
+      boxes[q] = b;
+    }
+    BuildParams pp = bp;
+    pp.threads = threads;
+    build_bvh4(boxes.data(), P.n_quads, pp, blas[p]);
+  };
+  {
+    std::vector<Aabb> boxes;
+    for (int32_t k = 0; k < n_big; ++k) build_proto(order_p[k], nthreads_all, boxes);
+  }
   auto worker = [&]() {
     std::vector<Aabb> boxes;
     for (;;) {
       const int32_t k = next.fetch_add(1);
       if (k >= n_protos) break;
-      const int32_t p = order_p[k];
-      const rtq_prototype& P = protos[p];
-      boxes.resize(P.n_quads);
-      for (int32_t q = 0; q < P.n_quads; ++q) {
-        Aabb b;
-        for (int a = 0; a < 3; ++a) {
-          b.lo[a] = std::numeric_limits<float>::infinity();
-          b.hi[a] = -std::numeric_limits<float>::infinity();
-        }
-        for (int c = 0; c < 4; ++c) {
-          const float* v = P.verts + 3 * (int64_t)P.quads[4 * (int64_t)q + c];
-          for (int a = 0; a < 3; ++a) {
-            b.lo[a] = std::min(b.lo[a], v[a]);
-            b.hi[a] = std::max(b.hi[a], v[a]);
-          }
-        }
-        boxes[q] = b;
-      }
-      build_bvh4(boxes.data(), P.n_quads, bp, blas[p]);
+      build_proto(order_p[k], 1, boxes);
     }
   };
   {
@@ -212,6 +229,8 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   }
 
   rtq_scene* s = new rtq_scene;
+  s->build_phase[0] = since(t0);
+  auto t1 = std::chrono::steady_clock::now();
   s->device = dev;
   s->formats = formats;
   s->n_protos = n_protos;
@@ -371,6 +390,8 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   }
   s->pad_rel = std::ldexp(1.0f, -17) * cond_max;
 
+  s->build_phase[1] = since(t1);
+  t1 = std::chrono::steady_clock::now();
   // ---- top-level entries: every instance, large ones opened into subtrees.
   // The host pad bound uses the padded box, so it is at least the device's.
   std::vector<TopEntry> entries;
@@ -386,18 +407,22 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     OpenParams op;
     const int32_t pct = o.open_pct == 0 ? kDefaultOpenPct : std::max(o.open_pct, 0);
     op.budget = std::min<int64_t>(N * (int64_t)pct / 100, (int64_t)kMaxLeafFirst - N);
+    op.threads = nthreads_all;
     entries = open_instances(N, insts->xform, insts->proto, boxes.data(), pad.data(), proto_root, proto_qbase,
                              proto_nq, nf, op);
   }
   const int64_t E = (int64_t)entries.size();
   s->n_rec = E;
   if (!(formats & RTQ_NODE_FP32)) nf = std::vector<NodeF32>();
+  s->build_phase[2] = since(t1);
+  t1 = std::chrono::steady_clock::now();
 
   // ---- top level over the padded entry boxes (one entry per leaf)
   Bvh4 tlas;
   BuildParams tp = bp;
   tp.leaf_max = 1;
   tp.bins = std::max(bp.bins, 64);  // one box per entry: finer bins are cheap here
+  tp.threads = nthreads_all;
   if (E > 0) {
     std::vector<Aabb> eb(E);
     for (int64_t k = 0; k < E; ++k) eb[k] = entries[k].box;
@@ -463,7 +488,8 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   TCHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
   tmp.release();
   for (int64_t i = 0; i < N; ++i) s->n_instanced_quads += protos[insts->proto[i]].n_quads;
-  s->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  s->build_phase[3] = since(t1);
+  s->build_seconds = since(t0);
   *out = s;
   return RTQ_OK;
 #undef UPLOAD
@@ -505,6 +531,7 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total);
   info->build_seconds = s->build_seconds;
   info->n_top_entries = s->n_rec;
+  for (int k = 0; k < 4; ++k) info->build_phase_seconds[k] = s->build_phase[k];
   return RTQ_OK;
 }
 

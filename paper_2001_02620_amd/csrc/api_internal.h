@@ -38,6 +38,7 @@ struct rtq_scene {
   int64_t tlas_nodes = 0, blas_nodes = 0;
   int tlas_depth = 0, blas_depth = 0;
   double build_seconds = 0.0;
+  double build_phase[4] = {0.0, 0.0, 0.0, 0.0};  // see rtq_scene_info.build_phase_seconds
   float pad_rel = 0.0f;
   // device data (owned by bufs)
   float p_world = 0.0f;    // bound on |world coordinate| of every top-level plane

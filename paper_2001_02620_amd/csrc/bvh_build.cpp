@@ -4,9 +4,11 @@
 #include "bvh_build.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <thread>
 
 namespace rtq {
 
@@ -43,23 +45,69 @@ struct Node2 {
   int32_t first = 0, count = 0;  // leaf when count > 0
 };
 
+// Run fn(t) for t in [0, T) on T threads (the caller's thread takes t = 0).
+template <class Fn>
+void run_threads(int T, Fn&& fn) {
+  if (T <= 1) {
+    fn(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (int t = 1; t < T; ++t) th.emplace_back([&fn, t] { fn(t); });
+  fn(0);
+  for (auto& x : th) x.join();
+}
+
+// Top-down binned SAH build of a binary BVH.  Jobs with many primitives are
+// split one at a time, each with its bounds, bins and partition computed on all
+// threads; the remaining subtrees are built concurrently, one per thread, in
+// node ranges reserved in advance.  Every partition is stable and every
+// reduction is a min/max or an integer sum, so the tree does not depend on the
+// thread count.
 struct Builder {
   const Aabb* in;
   const BuildParams& p;
+  int threads;
   std::vector<float> cx, cy, cz;
-  std::vector<uint32_t> idx;
+  std::vector<uint32_t> idx, tmp;
   std::vector<Node2> nodes;
-  Builder(const Aabb* boxes, int64_t n, const BuildParams& prm) : in(boxes), p(prm) {
+
+  struct Job {
+    int32_t node;
+    int64_t first, count;
+    int depth;
+  };
+  // bounds and per-axis bins of a range of primitives
+  struct Bins {
+    Box b, cb;
+    std::vector<Box> bb;      // 3 x B
+    std::vector<int64_t> bc;  // 3 x B
+  };
+  // per-thread scratch, reused across jobs
+  struct Scratch {
+    std::vector<Bins> part;
+    std::vector<Box> bb;
+    std::vector<int64_t> bc, right_count, nl;
+    std::vector<double> right_area;
+    std::vector<uint32_t> buf;
+  };
+
+  Builder(const Aabb* boxes, int64_t n, const BuildParams& prm, int nthreads)
+      : in(boxes), p(prm), threads(std::max(1, nthreads)) {
     cx.resize(n);
     cy.resize(n);
     cz.resize(n);
     idx.resize(n);
-    for (int64_t i = 0; i < n; ++i) {
-      cx[i] = 0.5f * (in[i].lo[0] + in[i].hi[0]);
-      cy[i] = 0.5f * (in[i].lo[1] + in[i].hi[1]);
-      cz[i] = 0.5f * (in[i].lo[2] + in[i].hi[2]);
-      idx[i] = (uint32_t)i;
-    }
+    run_threads(threads, [&](int t) {
+      const int64_t a = n * t / threads, e = n * (t + 1) / threads;
+      for (int64_t i = a; i < e; ++i) {
+        cx[i] = 0.5f * (in[i].lo[0] + in[i].hi[0]);
+        cy[i] = 0.5f * (in[i].lo[1] + in[i].hi[1]);
+        cz[i] = 0.5f * (in[i].lo[2] + in[i].hi[2]);
+        idx[i] = (uint32_t)i;
+      }
+    });
   }
   float cen(uint32_t i, int k) const { return k == 0 ? cx[i] : (k == 1 ? cy[i] : cz[i]); }
   Box box_of(uint32_t i) const {
@@ -71,108 +119,221 @@ struct Builder {
     return b;
   }
 
-  void run() {
-    const int64_t n = (int64_t)idx.size();
-    nodes.reserve(2 * n / std::max(1, p.leaf_max) + 2);
-    nodes.push_back(Node2{});
-    struct Job {
-      int32_t node;
-      int64_t first, count;
-      int depth;
-    };
-    std::vector<Job> jobs{{0, 0, n, 0}};
+  void bounds(int64_t a, int64_t e, Box& b, Box& cb) const {
+    for (int64_t i = a; i < e; ++i) {
+      const uint32_t q = idx[i];
+      b.grow(box_of(q));
+      cb.grow_pt(cx[q], cy[q], cz[q]);
+    }
+  }
+  void bin(int64_t a, int64_t e, const Box& cb, Bins& out) const {
     const int B = p.bins;
-    std::vector<Box> bb(B);
-    std::vector<int64_t> bc(B);
-    std::vector<double> right_area(B);
-    std::vector<int64_t> right_count(B);
+    for (int ax = 0; ax < 3; ++ax) {
+      const float lo = cb.lo[ax], ext = cb.hi[ax] - cb.lo[ax];
+      if (!(ext > 0.0f)) continue;
+      const float scale = (float)B / ext;
+      for (int64_t i = a; i < e; ++i) {
+        const uint32_t q = idx[i];
+        const int k = std::min(B - 1, (int)((cen(q, ax) - lo) * scale));
+        out.bb[ax * B + k].grow(box_of(q));
+        out.bc[ax * B + k]++;
+      }
+    }
+  }
+
+  // Bounds, SAH split and partition of job j on T threads.  Returns the split
+  // position, or -1 when j becomes a leaf.
+  int64_t split(const Job& j, int T, Scratch& S) {
+    const int B = p.bins;
+    const int64_t f = j.first, c = j.count;
+    if (c < 4096) T = 1;
+    std::vector<Bins>& part = S.part;
+    if ((int)part.size() < T) part.resize(T);
+    for (int t = 0; t < T; ++t) {
+      part[t].b = Box{};
+      part[t].cb = Box{};
+      part[t].bb.assign(3 * B, Box{});
+      part[t].bc.assign(3 * B, 0);
+    }
+    run_threads(T, [&](int t) { bounds(f + c * t / T, f + c * (t + 1) / T, part[t].b, part[t].cb); });
+    Box b, cb;
+    for (int t = 0; t < T; ++t) {
+      b.grow(part[t].b);
+      cb.grow(part[t].cb);
+    }
+    nodes[j.node].b = b;
+    const double A = std::max(b.area(), 1e-300);
+    int best_axis = -1, best_bin = -1;
+    double best_cost = std::numeric_limits<double>::infinity();
+    if (c > 1) {
+      run_threads(T, [&](int t) { bin(f + c * t / T, f + c * (t + 1) / T, cb, part[t]); });
+      std::vector<double>& right_area = S.right_area;
+      std::vector<int64_t>& right_count = S.right_count;
+      right_area.resize(B);
+      right_count.resize(B);
+      for (int ax = 0; ax < 3; ++ax) {
+        if (!(cb.hi[ax] - cb.lo[ax] > 0.0f)) continue;
+        std::vector<Box>& bb = S.bb;
+        std::vector<int64_t>& bc = S.bc;
+        bb.assign(B, Box{});
+        bc.assign(B, 0);
+        for (int t = 0; t < T; ++t)
+          for (int k = 0; k < B; ++k) {
+            bb[k].grow(part[t].bb[ax * B + k]);
+            bc[k] += part[t].bc[ax * B + k];
+          }
+        Box acc;
+        int64_t cnt = 0;
+        for (int k = B - 1; k > 0; --k) {
+          acc.grow(bb[k]);
+          cnt += bc[k];
+          right_area[k] = acc.area();
+          right_count[k] = cnt;
+        }
+        acc = Box{};
+        cnt = 0;
+        for (int k = 0; k < B - 1; ++k) {
+          acc.grow(bb[k]);
+          cnt += bc[k];
+          const int64_t rc = right_count[k + 1];
+          if (cnt == 0 || rc == 0) continue;
+          const double cost = 1.0 + (acc.area() * (double)cnt + right_area[k + 1] * (double)rc) / A;
+          if (cost < best_cost) {
+            best_cost = cost;
+            best_axis = ax;
+            best_bin = k;
+          }
+        }
+      }
+    }
+    const bool can_leaf = c <= p.leaf_max;
+    if (c == 1 || (can_leaf && (best_axis < 0 || (double)c <= best_cost))) {
+      nodes[j.node].first = (int32_t)f;
+      nodes[j.node].count = (int32_t)c;
+      return -1;
+    }
+    int64_t mid;
+    if (best_axis >= 0 && j.depth < 48) {
+      const float lo = cb.lo[best_axis], scale = (float)B / (cb.hi[best_axis] - cb.lo[best_axis]);
+      auto left = [&](uint32_t q) { return std::min(B - 1, (int)((cen(q, best_axis) - lo) * scale)) <= best_bin; };
+      if (T == 1) {
+        // stable: left elements compacted in place, right ones through S.buf
+        S.buf.clear();
+        int64_t w = f;
+        for (int64_t i = f; i < f + c; ++i) {
+          const uint32_t q = idx[i];
+          if (left(q)) idx[w++] = q;
+          else S.buf.push_back(q);
+        }
+        std::copy(S.buf.begin(), S.buf.end(), idx.begin() + w);
+        mid = w;
+      } else {
+        // stable two-pass partition through tmp: count, then scatter
+        std::vector<int64_t>& nl = S.nl;
+        nl.assign(T + 1, 0);
+        run_threads(T, [&](int t) {
+          int64_t k = 0;
+          for (int64_t i = f + c * t / T; i < f + c * (t + 1) / T; ++i) k += left(idx[i]) ? 1 : 0;
+          nl[t + 1] = k;
+        });
+        for (int t = 0; t < T; ++t) nl[t + 1] += nl[t];
+        const int64_t total_left = nl[T];
+        run_threads(T, [&](int t) {
+          const int64_t a = f + c * t / T, e = f + c * (t + 1) / T;
+          int64_t wl = f + nl[t], wr = f + total_left + (a - f - nl[t]);
+          for (int64_t i = a; i < e; ++i) {
+            const uint32_t q = idx[i];
+            if (left(q)) tmp[wl++] = q;
+            else tmp[wr++] = q;
+          }
+        });
+        run_threads(T, [&](int t) {
+          std::copy(tmp.begin() + f + c * t / T, tmp.begin() + f + c * (t + 1) / T, idx.begin() + f + c * t / T);
+        });
+        mid = f + total_left;
+      }
+    } else {
+      // no usable SAH split (identical centroids, or too deep): object median
+      int ax = 0;
+      float e = -1.0f;
+      for (int k = 0; k < 3; ++k)
+        if (cb.hi[k] - cb.lo[k] > e) {
+          e = cb.hi[k] - cb.lo[k];
+          ax = k;
+        }
+      mid = f + c / 2;
+      std::nth_element(idx.begin() + f, idx.begin() + mid, idx.begin() + f + c,
+                       [&](uint32_t a, uint32_t d) { return cen(a, ax) < cen(d, ax); });
+    }
+    if (mid == f || mid == f + c) mid = f + c / 2;
+    return mid;
+  }
+
+  // Depth-first build of the subtree of j on the calling thread; children take
+  // node slots from *next.
+  void subtree(const Job& root, int32_t* next) {
+    Scratch S;
+    std::vector<Job> jobs{root};
     while (!jobs.empty()) {
       const Job j = jobs.back();
       jobs.pop_back();
-      Box b, cb;
-      for (int64_t i = j.first; i < j.first + j.count; ++i) {
-        const uint32_t q = idx[i];
-        b.grow(box_of(q));
-        cb.grow_pt(cx[q], cy[q], cz[q]);
-      }
-      nodes[j.node].b = b;
-      const double A = std::max(b.area(), 1e-300);
-      // best binned SAH split over the three axes
-      int best_axis = -1, best_bin = -1;
-      double best_cost = std::numeric_limits<double>::infinity();
-      if (j.count > 1)
-        for (int ax = 0; ax < 3; ++ax) {
-          const float lo = cb.lo[ax], ext = cb.hi[ax] - cb.lo[ax];
-          if (!(ext > 0.0f)) continue;
-          const float scale = (float)B / ext;
-          for (int k = 0; k < B; ++k) {
-            bb[k] = Box{};
-            bc[k] = 0;
-          }
-          for (int64_t i = j.first; i < j.first + j.count; ++i) {
-            const uint32_t q = idx[i];
-            const int k = std::min(B - 1, (int)((cen(q, ax) - lo) * scale));
-            bb[k].grow(box_of(q));
-            bc[k]++;
-          }
-          Box acc;
-          int64_t cnt = 0;
-          for (int k = B - 1; k > 0; --k) {
-            acc.grow(bb[k]);
-            cnt += bc[k];
-            right_area[k] = acc.area();
-            right_count[k] = cnt;
-          }
-          acc = Box{};
-          cnt = 0;
-          for (int k = 0; k < B - 1; ++k) {
-            acc.grow(bb[k]);
-            cnt += bc[k];
-            const int64_t rc = right_count[k + 1];
-            if (cnt == 0 || rc == 0) continue;
-            const double cost = 1.0 + (acc.area() * (double)cnt + right_area[k + 1] * (double)rc) / A;
-            if (cost < best_cost) {
-              best_cost = cost;
-              best_axis = ax;
-              best_bin = k;
-            }
-          }
-        }
-      const bool can_leaf = j.count <= p.leaf_max;
-      if (j.count == 1 || (can_leaf && (best_axis < 0 || (double)j.count <= best_cost))) {
-        nodes[j.node].first = (int32_t)j.first;
-        nodes[j.node].count = (int32_t)j.count;
-        continue;
-      }
-      int64_t mid;
-      if (best_axis >= 0 && j.depth < 48) {
-        const float lo = cb.lo[best_axis], scale = (float)B / (cb.hi[best_axis] - cb.lo[best_axis]);
-        auto it = std::partition(idx.begin() + j.first, idx.begin() + j.first + j.count, [&](uint32_t q) {
-          return std::min(B - 1, (int)((cen(q, best_axis) - lo) * scale)) <= best_bin;
-        });
-        mid = it - idx.begin();
-      } else {
-        // no usable SAH split (identical centroids, or too deep): object median
-        int ax = 0;
-        float e = -1.0f;
-        for (int k = 0; k < 3; ++k)
-          if (cb.hi[k] - cb.lo[k] > e) {
-            e = cb.hi[k] - cb.lo[k];
-            ax = k;
-          }
-        mid = j.first + j.count / 2;
-        std::nth_element(idx.begin() + j.first, idx.begin() + mid, idx.begin() + j.first + j.count,
-                         [&](uint32_t a, uint32_t c) { return cen(a, ax) < cen(c, ax); });
-      }
-      if (mid == j.first || mid == j.first + j.count) mid = j.first + j.count / 2;
-      const int32_t l = (int32_t)nodes.size();
-      nodes.push_back(Node2{});
-      nodes.push_back(Node2{});
+      const int64_t mid = split(j, 1, S);
+      if (mid < 0) continue;
+      const int32_t l = *next;
+      *next += 2;
       nodes[j.node].l = l;
       nodes[j.node].r = l + 1;
       jobs.push_back({l, j.first, mid - j.first, j.depth + 1});
       jobs.push_back({l + 1, mid, j.first + j.count - mid, j.depth + 1});
     }
+  }
+
+  void run() {
+    const int64_t n = (int64_t)idx.size();
+    nodes.assign(2 * n + 1, Node2{});
+    int32_t next = 1;
+    if (threads == 1 || n < 65536) {
+      subtree({0, 0, n, 0}, &next);
+      nodes.resize(next);
+      return;
+    }
+    tmp.resize(n);
+    // large jobs, breadth first, each split on every thread
+    const int64_t big = std::max<int64_t>(65536, n / (16 * threads));
+    std::vector<Job> queue{{0, 0, n, 0}}, small;
+    Scratch S;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const Job j = queue[h];
+      const int64_t mid = split(j, threads, S);
+      if (mid < 0) continue;
+      const int32_t l = next;
+      next += 2;
+      nodes[j.node].l = l;
+      nodes[j.node].r = l + 1;
+      const Job kids[2] = {{l, j.first, mid - j.first, j.depth + 1}, {l + 1, mid, j.first + j.count - mid, j.depth + 1}};
+      for (const Job& k : kids) (k.count >= big ? queue : small).push_back(k);
+    }
+    tmp = std::vector<uint32_t>();
+    // the rest: one subtree per task; a subtree of c primitives has at most
+    // 2c - 2 nodes below its root, reserved in list order
+    std::vector<int32_t> base(small.size());
+    int64_t at = next;
+    for (size_t k = 0; k < small.size(); ++k) {
+      base[k] = (int32_t)at;
+      at += 2 * small[k].count - 2;
+    }
+    std::vector<size_t> order(small.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return small[a].count > small[b].count; });
+    std::atomic<size_t> take{0};
+    run_threads(threads, [&](int) {
+      for (;;) {
+        const size_t k = take.fetch_add(1);
+        if (k >= order.size()) break;
+        int32_t nx = base[order[k]];
+        subtree(small[order[k]], &nx);
+      }
+    });
   }
 };
 
@@ -269,7 +430,7 @@ void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
   out.q8.clear();
   out.order.clear();
   out.depth = 0;
-  Builder bld(boxes, n, p);
+  Builder bld(boxes, n, p, p.threads);
   bld.run();
   out.order = bld.idx;
   const std::vector<Node2>& N = bld.nodes;
@@ -331,7 +492,11 @@ void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
   }
   if (p.want_q8) {
     out.q8.resize(out.f32.size());
-    for (size_t i = 0; i < out.f32.size(); ++i) out.q8[i] = quantize_node(out.f32[i]);
+    const int64_t m = (int64_t)out.f32.size();
+    const int T = m < 65536 ? 1 : std::max(1, p.threads);
+    run_threads(T, [&](int t) {
+      for (int64_t i = m * t / T; i < m * (t + 1) / T; ++i) out.q8[i] = quantize_node(out.f32[i]);
+    });
   }
 }
 

@@ -26,6 +26,7 @@ struct BuildParams {
   int bins = 16;     // SAH bins per axis
   bool want_f32 = true;
   bool want_q8 = true;
+  int threads = 1;   // host threads for this build (the tree does not depend on it)
 };
 
 // Build over n primitive boxes.  Leaves reference [first, first + count) of

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <queue>
+#include <thread>
 #include <utility>
 
 namespace rtq {
@@ -149,11 +150,22 @@ std::vector<TopEntry> open_instances(int64_t n, const float* xform, const int32_
   };
 
   using Item = std::pair<double, uint32_t>;  // (priority, entry index)
-  std::priority_queue<Item> heap;
-  for (int64_t i = 0; i < n; ++i) {
-    const double g = priority(out[i]);
-    if (g > 0.0) heap.push({g, (uint32_t)i});
+  std::vector<double> g0(n);
+  {
+    const int T = n < 65536 ? 1 : std::max(1, params.threads);
+    std::vector<std::thread> th;
+    auto part = [&](int t) {
+      for (int64_t i = n * t / T; i < n * (t + 1) / T; ++i) g0[i] = priority(out[i]);
+    };
+    for (int t = 1; t < T; ++t) th.emplace_back(part, t);
+    part(0);
+    for (auto& x : th) x.join();
   }
+  std::vector<Item> init;
+  for (int64_t i = 0; i < n; ++i)
+    if (g0[i] > 0.0) init.push_back({g0[i], (uint32_t)i});
+  g0 = std::vector<double>();
+  std::priority_queue<Item> heap(std::less<Item>(), std::move(init));
   int64_t extra = 0;
   while (!heap.empty()) {
     const uint32_t ei = heap.top().second;

@@ -36,6 +36,7 @@ struct OpenParams {
   int64_t budget = 0;       // extra entries allowed beyond one per instance
   double max_ratio = 1.5;   // open a node only if its children's world surface
                             // area is at most this multiple of its own
+  int threads = 1;          // host threads for the per-instance priorities
 };
 
 // Entries for n instances.  inst_box[i] is the padded world box of instance i
