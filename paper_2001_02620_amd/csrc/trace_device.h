@@ -367,7 +367,10 @@ struct NodeCodec<2> {
       const float n = fmaxf(fmaxf(fmaf(ub(nx, k), bx, nax), fmaf(ub(ny, k), by, nay)),
                             fmaxf(fmaf(ub(nz, k), bz, naz), L.tmin));
       const float f = fminf(fminf(fmaf(ub(fx, k), bx, fax), fmaf(ub(fy, k), by, fay)), fmaf(ub(fz, k), bz, faz));
-      tn[k] = (ch[k] != kEmpty && n <= fminf(f, t_lim)) ? n : kInfF;
+      // no test for empty slots: their byte box is inverted (lo 255, hi 0), so
+      // they miss unless the slab slack exceeds the node's whole extent, and a
+      // pushed kEmpty is popped and dropped like a miss
+      tn[k] = n <= fminf(f, t_lim) ? n : kInfF;
     }
   }
 };
