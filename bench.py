@@ -23,7 +23,9 @@ Reported (one JSON line):
   roofline             the frame's dominant kernel (the traversal launches, each
                        tracing a bounce's shadow rays with the next bounce's
                        extension rays): algorithmic bytes per launch over its
-                       average launch time from HIP events, against 8 TB/s;
+                       average launch time from HIP events, against 8 TB/s,
+                       with the committed counters' HBM traffic and VALU issue
+                       rate while the kernel sources are unchanged;
   cpu_baseline         the FP64 oracle on a bounded pixel sample, host cores.
 """
 import argparse
@@ -60,18 +62,20 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when the kernels changed since the counters were taken."""
+def measured_counters(kernel_key):
+    """HBM bytes per launch and VALU issue rate from the committed rocprofv3
+    counter summary: (bytes, VALU wave-instructions per CU-cycle), each None when
+    absent or when the kernels changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
-        return None
+        return None, None
     txt = open(path).read()
     m = re.search(r"sources_hash:\s*(\w+)", txt)
+    if not m or m.group(1) != kernel_key:
+        return None, None
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_key:
-        return None
-    return float(b.group(1))
+    v = re.search(r"valu_issue_per_cu_cycle:\s*([0-9.eE+]+)", txt)
+    return (float(b.group(1)) if b else None), (float(v.group(1)) if v else None)
 
 
 def main():
@@ -244,7 +248,7 @@ def main():
     alg_bytes = frame_bytes / launches_per_frame
     kern_ms = stg["ms"] / stg["launches"]
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    tr = measured_traffic(kernel_sources_hash())
+    tr, valu = measured_counters(kernel_sources_hash())
 
     # ---- CPU baseline: the oracle on a bounded sample of the same frame, sized
     # from a short pilot so that the timed sample takes about cpu_seconds
@@ -322,7 +326,11 @@ def main():
                      "traffic": None if tr is None else tr,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": DOMINANT, "algorithmic_bytes_per_launch": alg_bytes,
-                     "launches_per_frame": launches_per_frame, "kernel_ms": round(kern_ms, 3)},
+                     "launches_per_frame": launches_per_frame, "kernel_ms": round(kern_ms, 3),
+                     # the launch is bound by VALU issue, not HBM: the measured issue rate
+                     "valu_issue": None if valu is None else {
+                         "achieved": valu, "peak": 1.0, "frac": valu,
+                         "unit": "VALU wave-instructions per CU-cycle (rocprofv3 SQ_INSTS_VALU / GRBM_GUI_ACTIVE)"}},
         "cpu_baseline": cpu,
         "scene": {"build_s": round(info["build_seconds"], 2), "device_gib": round(info["device_bytes"] / 2**30, 3)},
     }
