@@ -58,9 +58,10 @@ constexpr float kSlack = 1.0f + 1.52587890625e-05f;  // 1 + 2^-16
 #endif
 constexpr float kInfF = __builtin_huge_valf();
 // Slab-error bound per unit of (|plane| + |origin|) |1/d|: 2^-20 = 16 u covers
-// the reciprocal (1 ulp), the product and difference forming the level
-// constants, the node-frame constant of quantized nodes, the fused multiply-add
-// and the half-ulp by which a quantized plane may sit inside its decoded value.
+// the reciprocal (1 ulp), the fused multiply-add forming the level constants,
+// the node-frame constant of quantized nodes, the fused multiply-add of the
+// plane and the half-ulp by which a quantized plane may sit inside its decoded
+// value.
 constexpr float kDeltaRel = 9.5367431640625e-07f;
 constexpr float kInvMax = 18446744073709551616.0f;         // 2^64
 constexpr float kInvMaxArg = 5.42101086242752217e-20f;     // 2^-64
@@ -120,8 +121,8 @@ __device__ __forceinline__ float slab_inv(float d) {
 // `pmax` bounds |plane| over the level.
 __device__ __forceinline__ void slab_axis(float i, float on, float of, float pmax, float& cn, float& cf) {
   const float delta = (pmax + fmaxf(fabsf(on), fabsf(of))) * fabsf(i) * kDeltaRel;
-  cn = -(on * i) - delta;
-  cf = -(of * i) + delta;
+  cn = fmaf(-on, i, -delta);
+  cf = fmaf(-of, i, delta);
 }
 
 // Box-test constants for the top level: the world ray with its origin widened
@@ -148,12 +149,12 @@ __device__ __forceinline__ void enter_instance(Lane& L, const SceneView& sc, uin
   const uint32_t root = sc.inst[r].blas_root;
   const float pmax = sc.rec_pmax[r];
   const float px = L.wox - a.w, py = L.woy - b.w, pz = L.woz - c.w;
-  const float ox = a.x * px + a.y * py + a.z * pz;
-  const float oy = b.x * px + b.y * py + b.z * pz;
-  const float oz = c.x * px + c.y * py + c.z * pz;
-  const float dx = a.x * L.wdx + a.y * L.wdy + a.z * L.wdz;
-  const float dy = b.x * L.wdx + b.y * L.wdy + b.z * L.wdz;
-  const float dz = c.x * L.wdx + c.y * L.wdy + c.z * L.wdz;
+  const float ox = fmaf(a.x, px, fmaf(a.y, py, a.z * pz));
+  const float oy = fmaf(b.x, px, fmaf(b.y, py, b.z * pz));
+  const float oz = fmaf(c.x, px, fmaf(c.y, py, c.z * pz));
+  const float dx = fmaf(a.x, L.wdx, fmaf(a.y, L.wdy, a.z * L.wdz));
+  const float dy = fmaf(b.x, L.wdx, fmaf(b.y, L.wdy, b.z * L.wdz));
+  const float dz = fmaf(c.x, L.wdx, fmaf(c.y, L.wdy, c.z * L.wdz));
   L.ix = slab_inv(dx);
   L.iy = slab_inv(dy);
   L.iz = slab_inv(dz);
