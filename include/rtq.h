@@ -55,6 +55,37 @@ const char* rtq_last_error(void);
 /* Library version string. */
 const char* rtq_version(void);
 
+/* ------------------------------------------------------------- host BVH */
+/*
+ * The scene builder's bottom-level construction on its own, on the host, over
+ * arbitrary boxes (Section 5.2: one BVH per object; here binned SAH, collapsed
+ * to 4-wide nodes, emitted as FP32 and as 8-bit quantized nodes).  For
+ * inspecting the acceleration structure and for host-side checks; no device is
+ * touched.
+ *   boxes: host, n x 6 FP32 (lo x y z, hi x y z); n >= 1.
+ *   leaf_max: primitives per leaf, 1..8.  bins: SAH bins per axis, 4..64.
+ *   threads: host threads, 0 = all; the result does not depend on it.
+ * Node layouts (little-endian, node 0 is the root):
+ *   FP32, 128 B: float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
+ *                uint32 child[4]; uint32 pad[4].
+ *   Q8, 64 B:    float origin[3]; uint32 exps (byte a: int8 exponent of axis a);
+ *                uint32 lo_x, hi_x, lo_y, hi_y, lo_z, hi_z (byte c: child c);
+ *                uint32 child[4]; uint32 pad[2].  A plane decodes to
+ *                fmaf(q, 2^e, origin), which contains the FP32 plane.
+ *   child: 0xFFFFFFFF empty; bit 31 set: leaf of primitives
+ *          order[first .. first + count) with first = (c >> 3) & 0x0FFFFFFF and
+ *          count = (c & 7) + 1; otherwise the index of an internal node.
+ * *out owns the arrays; rtq_host_bvh_get returns pointers into it, valid until
+ * rtq_host_bvh_destroy.  Errors: INVALID_ARG (NULL, n < 1, non-finite or
+ * inverted box, parameter out of range), LIMIT (n >= 2^28), OOM.
+ */
+typedef struct rtq_host_bvh rtq_host_bvh;
+int rtq_host_bvh_build(const float* boxes, int64_t n, int32_t leaf_max, int32_t bins, int32_t threads,
+                       rtq_host_bvh** out);
+int rtq_host_bvh_get(const rtq_host_bvh* bvh, const void** nodes_f32, const void** nodes_q8, int64_t* n_nodes,
+                     const uint32_t** order, int32_t* depth);
+void rtq_host_bvh_destroy(rtq_host_bvh* bvh);
+
 /* ------------------------------------------------------------------ scene */
 typedef struct rtq_scene rtq_scene;
 

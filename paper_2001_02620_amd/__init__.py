@@ -92,7 +92,8 @@ _lib = None
 
 EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destroy", "rtq_scene_get_info",
            "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
-           "rtq_render_backward", "rtq_render_timing", "rtq_render_path"]
+           "rtq_render_backward", "rtq_render_timing", "rtq_render_path", "rtq_host_bvh_build", "rtq_host_bvh_get",
+           "rtq_host_bvh_destroy"]
 
 
 def load_library():
@@ -117,13 +118,17 @@ def load_library():
     L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
+    L.rtq_host_bvh_build.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
+    L.rtq_host_bvh_get.argtypes = [P, P, P, P, P, P]
+    L.rtq_host_bvh_destroy.argtypes = [P]
+    L.rtq_host_bvh_destroy.restype = None
     L.rtq_render.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
     L.rtq_render_backward.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
     L.rtq_render_timing.argtypes = [P, P, P]
     L.rtq_render_path.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32,
                                   ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P]
     for f in EXPORTS:
-        if f not in ("rtq_last_error", "rtq_version", "rtq_scene_destroy"):
+        if f not in ("rtq_last_error", "rtq_version", "rtq_scene_destroy", "rtq_host_bvh_destroy"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -378,6 +383,35 @@ def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None,
                                               settings.spp, settings.depth, ctypes.byref(o), g.data_ptr(),
                                               grad_albedo.data_ptr(), _stream()))
     return grad_albedo
+
+
+# ----------------------------------------------------------------------------- host BVH
+NODE_F32 = np.dtype([("lo_x", "<f4", 4), ("hi_x", "<f4", 4), ("lo_y", "<f4", 4), ("hi_y", "<f4", 4),
+                     ("lo_z", "<f4", 4), ("hi_z", "<f4", 4), ("child", "<u4", 4), ("pad", "<u4", 4)])
+NODE_Q8 = np.dtype([("origin", "<f4", 3), ("exps", "<u4"), ("lo_x", "<u4"), ("hi_x", "<u4"), ("lo_y", "<u4"),
+                    ("hi_y", "<u4"), ("lo_z", "<u4"), ("hi_z", "<u4"), ("child", "<u4", 4), ("pad", "<u4", 2)])
+
+
+def host_bvh(boxes, leaf_max: int = 4, bins: int = 32, threads: int = 0) -> dict:
+    """The scene builder's 4-wide BVH over host boxes ([n, 6] lo xyz, hi xyz),
+    built on the host (no device): dict of FP32 nodes, quantized nodes (numpy
+    structured arrays), leaf order and depth."""
+    L = load_library()
+    b = np.ascontiguousarray(boxes, dtype=np.float32).reshape(-1, 6)
+    h = ctypes.c_void_p()
+    _check(L.rtq_host_bvh_build(b.ctypes.data, b.shape[0], int(leaf_max), int(bins), int(threads), ctypes.byref(h)))
+    try:
+        pf, pq, po = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        nn, depth = ctypes.c_int64(), ctypes.c_int32()
+        _check(L.rtq_host_bvh_get(h, ctypes.byref(pf), ctypes.byref(pq), ctypes.byref(nn), ctypes.byref(po),
+                                  ctypes.byref(depth)))
+        n = nn.value
+        f32 = np.frombuffer(ctypes.string_at(pf.value, n * NODE_F32.itemsize), dtype=NODE_F32).copy()
+        q8 = np.frombuffer(ctypes.string_at(pq.value, n * NODE_Q8.itemsize), dtype=NODE_Q8).copy()
+        order = np.frombuffer(ctypes.string_at(po.value, 4 * b.shape[0]), dtype=np.uint32).copy()
+    finally:
+        L.rtq_host_bvh_destroy(h)
+    return {"f32": f32, "q8": q8, "order": order, "depth": depth.value}
 
 
 def version() -> str:

@@ -589,6 +589,50 @@ int rtq_trace_occluded(const rtq_scene* s, const rtq_rays* rays, int64_t n, uint
   return trace_common(s, rays, n, nullptr, occluded, opts, stream);
 }
 
+int rtq_host_bvh_build(const float* boxes, int64_t n, int32_t leaf_max, int32_t bins, int32_t threads,
+                       rtq_host_bvh** out) {
+  if (!out) return set_error(RTQ_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!boxes || n < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one box");
+  if (n > (int64_t)kMaxLeafFirst) return set_error(RTQ_E_LIMIT, "%lld boxes exceed 2^28", (long long)n);
+  if (leaf_max < 1 || leaf_max > 8) return set_error(RTQ_E_INVALID_ARG, "leaf_max %d outside [1, 8]", leaf_max);
+  if (bins < 4 || bins > 64) return set_error(RTQ_E_INVALID_ARG, "bins %d outside [4, 64]", bins);
+  try {
+    std::vector<Aabb> b(n);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int a = 0; a < 3; ++a) {
+        b[i].lo[a] = boxes[6 * i + a];
+        b[i].hi[a] = boxes[6 * i + 3 + a];
+        if (!std::isfinite(b[i].lo[a]) || !std::isfinite(b[i].hi[a]) || b[i].lo[a] > b[i].hi[a])
+          return set_error(RTQ_E_INVALID_ARG, "box %lld is not finite or is inverted", (long long)i);
+      }
+    }
+    BuildParams p;
+    p.leaf_max = leaf_max;
+    p.bins = bins;
+    p.threads = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    rtq_host_bvh* h = new rtq_host_bvh;
+    build_bvh4(b.data(), n, p, h->bvh);
+    *out = h;
+    return RTQ_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(RTQ_E_OOM, "host allocation failed");
+  }
+}
+
+int rtq_host_bvh_get(const rtq_host_bvh* h, const void** nodes_f32, const void** nodes_q8, int64_t* n_nodes,
+                     const uint32_t** order, int32_t* depth) {
+  if (!h) return set_error(RTQ_E_INVALID_ARG, "NULL bvh");
+  if (nodes_f32) *nodes_f32 = h->bvh.f32.data();
+  if (nodes_q8) *nodes_q8 = h->bvh.q8.data();
+  if (n_nodes) *n_nodes = (int64_t)h->bvh.f32.size();
+  if (order) *order = h->bvh.order.data();
+  if (depth) *depth = h->bvh.depth;
+  return RTQ_OK;
+}
+
+void rtq_host_bvh_destroy(rtq_host_bvh* h) { delete h; }
+
 int rtq_trace_brute(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hits* hits, hipStream_t stream) {
   int rc = check_rays(s, rays, n);
   if (rc) return rc;

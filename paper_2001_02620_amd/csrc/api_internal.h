@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/rtq.h"
+#include "bvh_build.h"
 #include "kernels.h"
 #include "rtq_layout.h"
 #include "trace_device.h"
@@ -25,6 +26,10 @@ int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 
 }  // namespace rtq
+
+struct rtq_host_bvh {
+  rtq::Bvh4 bvh;
+};
 
 struct rtq_scene {
   static constexpr int kCounterSlots = 256;
