@@ -18,6 +18,7 @@ Reported (one JSON line):
                        kernels, at bit-identical images;
   ablation             node format x scheduler (plain, persistent stages,
                        single persistent megakernel);
+  graph_replay         the headline path replayed from a captured HIP graph;
   incoherent           closest-hit throughput on the frame's bounce >= 1 rays,
                        quantized-persistent vs FP32-plain, at bit-identical hits;
   roofline             the frame's dominant kernel (the traversal launches, each
@@ -200,6 +201,10 @@ def main():
                 r = timed(dict(node_format=fmt, scheduler=sch), max(3, args.steps // 2), 1)
             ablation[key] = dict(ms_per_frame=r["wall_ms"], mrays_s=r["rays"] / (r["wall_ms"] * 1e3))
     log(f"ablation: {ablation}")
+    # the headline path replayed from a captured HIP graph (same launches)
+    g = timed(dict(Q8P, graph=True), args.steps, args.warmup)
+    graph_replay = dict(ms_per_frame=g["wall_ms"], mrays_s=g["rays"] / (g["wall_ms"] * 1e3))
+    log(f"graph replay: {graph_replay}")
 
     # ---- incoherent rays: bounce >= 1 extension rays of frame 0
     log("incoherent rays: dumping bounce >= 1 rays")
@@ -319,6 +324,7 @@ def main():
                        "fp32_plain_mrays_s": round(inc["fp32_plain"]["mrays_s"], 2),
                        "speedup": round(inc["q8_persistent"]["mrays_s"] / inc["fp32_plain"]["mrays_s"], 3)},
         "ablation": {k: {kk: round(vv, 3) for kk, vv in d.items()} for k, d in ablation.items()},
+        "graph_replay": {k: round(v, 3) for k, v in graph_replay.items()},
         "stages_ms_per_frame": {("traversal" if k == "closest" else k): round(d["ms"] / args.steps, 3)
                                 for k, d in q8["stages"].items() if k != "shadow"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
