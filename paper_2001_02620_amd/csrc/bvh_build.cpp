@@ -99,8 +99,9 @@ struct Builder {
     cy.resize(n);
     cz.resize(n);
     idx.resize(n);
-    run_threads(threads, [&](int t) {
-      const int64_t a = n * t / threads, e = n * (t + 1) / threads;
+    const int T = n < 65536 ? 1 : threads;
+    run_threads(T, [&](int t) {
+      const int64_t a = n * t / T, e = n * (t + 1) / T;
       for (int64_t i = a; i < e; ++i) {
         cx[i] = 0.5f * (in[i].lo[0] + in[i].hi[0]);
         cy[i] = 0.5f * (in[i].lo[1] + in[i].hi[1]);
