@@ -127,8 +127,10 @@ struct Builder {
       cb.grow_pt(cx[q], cy[q], cz[q]);
     }
   }
-  void bin(int64_t a, int64_t e, const Box& cb, Bins& out) const {
-    const int B = p.bins;
+  // bins for a job of c primitives: the configured count, but no more than
+  // max(32, c) (more bins than primitives only cost time)
+  int bins_for(int64_t c) const { return (int)std::min<int64_t>(p.bins, std::max<int64_t>(32, c)); }
+  void bin(int64_t a, int64_t e, const Box& cb, int B, Bins& out) const {
     for (int ax = 0; ax < 3; ++ax) {
       const float lo = cb.lo[ax], ext = cb.hi[ax] - cb.lo[ax];
       if (!(ext > 0.0f)) continue;
@@ -145,8 +147,8 @@ struct Builder {
   // Bounds, SAH split and partition of job j on T threads.  Returns the split
   // position, or -1 when j becomes a leaf.
   int64_t split(const Job& j, int T, Scratch& S) {
-    const int B = p.bins;
     const int64_t f = j.first, c = j.count;
+    const int B = bins_for(c);
     if (c < 4096) T = 1;
     std::vector<Bins>& part = S.part;
     if ((int)part.size() < T) part.resize(T);
@@ -167,7 +169,7 @@ struct Builder {
     int best_axis = -1, best_bin = -1;
     double best_cost = std::numeric_limits<double>::infinity();
     if (c > 1) {
-      run_threads(T, [&](int t) { bin(f + c * t / T, f + c * (t + 1) / T, cb, part[t]); });
+      run_threads(T, [&](int t) { bin(f + c * t / T, f + c * (t + 1) / T, cb, B, part[t]); });
       std::vector<double>& right_area = S.right_area;
       std::vector<int64_t>& right_count = S.right_count;
       right_area.resize(B);

@@ -23,7 +23,7 @@ struct Bvh4 {
 
 struct BuildParams {
   int leaf_max = 4;  // primitives per leaf (1..8)
-  int bins = 16;     // SAH bins per axis
+  int bins = 16;     // SAH bins per axis (a job of c primitives uses at most max(32, c))
   bool want_f32 = true;
   bool want_q8 = true;
   int threads = 1;   // host threads for this build (the tree does not depend on it)
