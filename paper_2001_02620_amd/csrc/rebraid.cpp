@@ -21,21 +21,22 @@ double area(const Box64& b) {
 }
 
 // World box of an object-space box under [A | t]: centre A c + t, half extent
-// |A| e.  Evaluated in FP64 from FP32 inputs; its rounding error (a few units
-// of 2^-53 of the magnitudes) is far below the pad added afterwards.
+// |A| e, evaluated in FP64 from FP32 inputs and widened by a bound on its
+// rounding error (far below the pad added afterwards).
 Box64 transform_box(const double* m, const float* lo, const float* hi) {
   Box64 w;
   for (int r = 0; r < 3; ++r) {
-    double c = m[4 * r + 3], e = 0.0;
+    double c = m[4 * r + 3], e = 0.0, mag = std::fabs(m[4 * r + 3]);
     for (int k = 0; k < 3; ++k) {
       const double ck = 0.5 * ((double)lo[k] + (double)hi[k]);
       const double ek = 0.5 * ((double)hi[k] - (double)lo[k]);
       c += m[4 * r + k] * ck;
       e += std::fabs(m[4 * r + k]) * ek;
+      mag += std::fabs(m[4 * r + k]) * (std::fabs(ck) + ek);
     }
-    // the half-sum and half-difference of two floats are exact in FP64; widen
-    // by a relative 2^-40 for the products and sums above
-    const double slack = std::ldexp(std::fabs(c) + e, -40);
+    // a few FP64 roundings, each within 2^-53 of the magnitudes involved:
+    // widen by 2^-40 of them
+    const double slack = std::ldexp(mag, -40);
     w.lo[r] = c - e - slack;
     w.hi[r] = c + e + slack;
   }
