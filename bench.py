@@ -14,6 +14,7 @@ Reported (one JSON line):
                        nodes; ray generation, shading and shadow resolution as
                        kernels per bounce; closest-hit and shadow traversal as
                        persistent lane-refilling kernels);
+  frame_ms_percentiles p10 / p50 / p90 of the timed frames (HIP events);
   plain_fp32           the same for FP32 nodes and one-ray-per-lane traversal
                        kernels, at bit-identical images;
   ablation             node format x scheduler (plain, persistent stages,
@@ -151,7 +152,8 @@ def main():
         ev_ms = [a.elapsed_time(b) for a, b in evs]
         c = cnt.cpu().numpy().astype(np.float64)
         r = dict(wall_ms=1e3 * wall / steps, ev_ms=float(np.mean(ev_ms)), ev_min=float(np.min(ev_ms)),
-                 ev_max=float(np.max(ev_ms)), closest=c[0] / steps, shadow=c[1] / steps,
+                 ev_max=float(np.max(ev_ms)), ev_pct={f"p{q}": float(np.percentile(ev_ms, q)) for q in (10, 50, 90)},
+                 closest=c[0] / steps, shadow=c[1] / steps,
                  incoherent=c[2] / steps, rays=(c[0] + c[1]) / steps)
         if stage_timing:
             r["stages"] = rtq.render_timing(S)
@@ -302,6 +304,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(q8["wall_ms"], 3),
+        "frame_ms_percentiles": {k: round(v, 3) for k, v in q8["ev_pct"].items()},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
