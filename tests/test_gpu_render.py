@@ -318,3 +318,21 @@ def test_config2_full_frame_bench_launch_vs_oracle():
     nv = compare_paths(rtq, oracle, S, o, cams, st, rng, 64, **q8)
     log(f"  64 sampled paths, {nv} vertices compared")
     assert nv >= 32
+
+
+def test_autotuner_quick_grid_keeps_images():
+    """The autotuner times launch configurations and refuses any whose image
+    differs from the FP32 plain one; on the quick grid every candidate passes
+    and each (format, scheduler) pair gets a configuration."""
+    from paper_2001_02620_amd.autotune import QUICK_GRID, autotune_render
+    log("case: autotuner, quick grid, config 1")
+    scene, cams, st = sg.config1()
+    S = rtq.Scene(scene)
+    res = autotune_render(S, cams, st, formats=(rtq.RTQ_NODE_Q8, rtq.RTQ_NODE_FP32),
+                          schedulers=(rtq.SCHED_PERSISTENT, rtq.SCHED_PLAIN), grid=QUICK_GRID, reps=1, cache=None)
+    for fmt in (rtq.RTQ_NODE_Q8, rtq.RTQ_NODE_FP32):
+        for sch in (rtq.SCHED_PERSISTENT, rtq.SCHED_PLAIN):
+            best = res[f"{fmt}/{sch}"]
+            assert best["opts"]["node_format"] == fmt and best["opts"]["scheduler"] == sch and best["ms"] > 0
+    assert len(res["table"]) >= 8
+    log(f"  {len(res['table'])} candidates, all bit-identical")
