@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target length of the oracle's timed sample")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target length of the oracle's timed sample")
     ap.add_argument("--cpu-pilot", type=int, default=4096, help="pixels of the pilot that sizes the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--incoherent-rays", type=int, default=16_000_000)

@@ -254,14 +254,14 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   for (int32_t c = 1; c < n_cams; ++c)
     if (cd[c].img_offset < cd[c - 1].img_offset)
       return set_error(RTQ_E_INVALID_ARG, "camera image offsets must increase with the camera index");
+  // path ids are 32-bit, and a dispatch counts its work-items in 32 bits
+  if (path_base > (int64_t)0x7FFFFFFF)
+    return set_error(RTQ_E_LIMIT, "%lld paths per call exceed 2^31 - 1", (long long)path_base);
   {
     std::lock_guard<std::mutex> lock(s->scratch_mu);
     rc = ensure_scratch(s, path_base, n_cams, plain_buffers);
     if (rc) return rc;
   }
-  // path ids are 32-bit, and a dispatch counts its work-items in 32 bits
-  if (path_base > (int64_t)0x7FFFFFFF)
-    return set_error(RTQ_E_LIMIT, "%lld paths per call exceed 2^31 - 1", (long long)path_base);
   RenderScratch* sc = scratch_of(s);
   const hipError_t e =
       hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);

@@ -284,6 +284,17 @@ def test_render_argument_errors():
         rtq.render(S, [sg.Camera((0, 0, 0), (0, 0, 0), (0, 0, 1), 40.0, 8, 8)], st)
     with pytest.raises(rtq.RtqError):
         rtq.render(S, cams, sg.RenderSettings(spp=1, depth=17))
+    # 2^31 paths in one call: LIMIT, checked before any scratch is allocated
+    import ctypes
+    big = [sg.Camera((0.0, -160.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 40.0, 65536, 32768)]
+    arr, total = rtq.camera_structs(big)
+    assert total == 2 ** 31
+    img = torch.zeros(1, device="cuda")
+    o = rtq.render_opts(st)
+    rc = rtq.load_library().rtq_render(S.handle, ctypes.cast(arr, ctypes.c_void_p), 1, 1, 2, ctypes.byref(o),
+                                       img.data_ptr(), None)
+    assert rc == -5, rc
+    torch.cuda.synchronize()
 
 
 def test_config2_full_frame_bench_launch_vs_oracle():

@@ -204,6 +204,17 @@ def test_argument_errors():
     with pytest.raises(rtq.RtqError) as ei:
         rtq.Scene(bad2)
     assert ei.value.code == -1
+    # more rays per call than a dispatch can count: LIMIT, before anything runs
+    import ctypes
+    soa, rs = rtq._rays_struct(R)
+    out = torch.zeros((5, 4), device="cuda")
+    hits = rtq._Hits(*[out[k].data_ptr() for k in range(5)])
+    L = rtq.load_library()
+    rc = L.rtq_trace_closest(S.handle, ctypes.byref(rs), 2 ** 31, ctypes.byref(hits), None, None)
+    assert rc == -5, rc
+    rc = L.rtq_trace_occluded(S.handle, ctypes.byref(rs), 2 ** 31, out.data_ptr(), None, None)
+    assert rc == -5, rc
+    torch.cuda.synchronize()
 
 
 def test_config2_sampled_rays_vs_oracle():
