@@ -57,6 +57,7 @@ def lib():
         L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64]
         L.orc_scene_destroy.argtypes = [P]
         L.orc_scene_set_albedo.argtypes = [P, P]
+        L.orc_scene_set_textures.argtypes = [P, P, i32]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         L.orc_philox.argtypes = [P, P, P]
@@ -118,6 +119,7 @@ class OracleScene:
         )
         k = self._keep
         self.n_quads = int(k["quads"].shape[0])
+        self.tex_res = 0
         self.h = lib().orc_scene_create(_p(k["verts"]), k["verts"].shape[0], _p(k["quads"]), k["quads"].shape[0],
                                         _p(k["vo"]), _p(k["qo"]), k["qo"].shape[0] - 1, _p(k["albedo"]),
                                         _p(k["ip"]), _p(k["x"]), k["ip"].shape[0])
@@ -136,6 +138,20 @@ class OracleScene:
         a = np.ascontiguousarray(albedo, dtype=np.float64)
         assert a.shape == (self.n_quads,)
         lib().orc_scene_set_albedo(self.h, _p(a))
+
+    def set_textures(self, texels: Optional[np.ndarray]) -> None:
+        """Per-face textures [n_quads, res, res] (row v, column u; FP32 values read
+        exactly), or None to shade with the per-face albedo again.  The gradient
+        functions require no textures."""
+        if texels is None:
+            assert lib().orc_scene_set_textures(self.h, None, 0) == 0
+            self.tex_res = 0
+            return
+        t = np.ascontiguousarray(np.asarray(texels, dtype=np.float32), dtype=np.float64)
+        assert t.ndim == 3 and t.shape[0] == self.n_quads and t.shape[1] == t.shape[2] >= 1
+        assert lib().orc_scene_set_textures(self.h, _p(t), int(t.shape[1])) == 0
+        self._tex = t
+        self.tex_res = int(t.shape[1])
 
     def trace(self, rays: np.ndarray, excl: Optional[np.ndarray] = None, r0: Optional[np.ndarray] = None,
               brute: bool = False, any_hit: bool = False) -> Hits:
@@ -195,6 +211,7 @@ class OracleScene:
         Returns (grad [Q] f64, pixel flags, tainted-face mask).  taint="pixel" marks
         every face on any path of a flagged pixel; taint="path" only the faces on
         flagged paths (valid when both sides use these same pixel weights)."""
+        assert self.tex_res == 0, "gradients are defined for per-face albedo, not textures"
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
@@ -211,6 +228,7 @@ class OracleScene:
 
     def tangent(self, cams, settings, tangent: np.ndarray, pixels: Optional[np.ndarray] = None):
         """Forward-mode (dual number) derivative of each pixel along a per-face tangent."""
+        assert self.tex_res == 0, "gradients are defined for per-face albedo, not textures"
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)

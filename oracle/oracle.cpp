@@ -147,6 +147,9 @@ struct Scene {
   std::vector<int32_t> quads;      // 4 per quad, local vertex index
   std::vector<int64_t> vo, qo;     // per-prototype offsets
   std::vector<double> albedo;      // per unique quad
+  // optional per-face textures: res x res values per unique quad, row v, column u
+  std::vector<double> tex;
+  int32_t tex_res = 0;
   int64_t N = 0;
   std::vector<int32_t> iproto;
   std::vector<double> X;           // 12 per instance: row-major [A | t] (FP32 values)
@@ -592,7 +595,22 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (std::fabs(nd) < 1e-3) rec.flags |= F_SHADE;
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
-    const double a = S.albedo[face];
+    double a = S.albedo[face];
+    if (S.tex_res > 0) {
+      // the texel of (u, v): nearest, on a res x res grid over the quad.  Which
+      // texel a hit near a texel edge lands on depends on rounding: flag hits
+      // whose world distance to an inner texel edge is below 1e-5 S (the
+      // position error of the FP32 hit is about 1e-6 S)
+      const int R = S.tex_res;
+      const double lu = std::max(norm(wq[1] - wq[0]), norm(wq[2] - wq[3]));
+      const double lv = std::max(norm(wq[3] - wq[0]), norm(wq[2] - wq[1]));
+      const double gu = h.best.u * R, gv = h.best.v * R;
+      for (int k = 1; k < R; ++k)
+        if (std::fabs(gu - k) * lu / R < 1e-5 * h.S || std::fabs(gv - k) * lv / R < 1e-5 * h.S) rec.flags |= F_SHADE;
+      const int tx = std::min(std::max((int)std::floor(gu), 0), R - 1);
+      const int ty = std::min(std::max((int)std::floor(gv), 0), R - 1);
+      a = S.tex[((size_t)face * R + ty) * R + tx];
+    }
     Vertex vx{face, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
     const double cl = dot(n, L);
     if (std::fabs(cl) < 1e-6) rec.flags |= F_SHADE;
@@ -763,6 +781,18 @@ void orc_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
 int orc_scene_set_albedo(void* s, const double* albedo) {
   Scene* S = static_cast<Scene*>(s);
   for (size_t i = 0; i < S->albedo.size(); ++i) S->albedo[i] = albedo[i];
+  return 0;
+}
+
+// Per-face textures (Section 5.3: a Ptex lookup at the hit's face and (u, v)),
+// here synthetic: res x res values per unique quad in face order, row v, column
+// u; res = 0 removes them.
+int orc_scene_set_textures(void* s, const double* texels, int32_t res) {
+  Scene* S = static_cast<Scene*>(s);
+  if (res < 0 || (res > 0 && !texels)) return -1;
+  S->tex_res = res;
+  S->tex.clear();
+  if (res > 0) S->tex.assign(texels, texels + S->albedo.size() * (size_t)res * (size_t)res);
   return 0;
 }
 

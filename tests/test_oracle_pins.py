@@ -458,3 +458,73 @@ def test_gradient_floor_closed_form(ora):
     g, _, _ = oracle.OracleScene(scene).grad(cams, st, np.full(n, 1.0 / n))
     cosl = st.light_dir[2]
     assert abs(g[0] - ((st.E / math.pi) * cosl + st.L_sky)) < 1e-12
+
+
+# ------------------------------------------------------------- textures (5.3)
+def test_constant_textures_reproduce_per_face_albedo(ora):
+    """A texture whose texels all equal the face's albedo shades exactly as the
+    per-face albedo does: the lookup picks the hit face's own texture."""
+    scene = sg.tiny_scene(4, n_inst=4, n_protos=2, nq=4, spread=1.0)
+    cams = [sg.Camera((0.5, -6.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 50.0, 20, 16)]
+    st = sg.RenderSettings(spp=2, depth=3, seed=21)
+    o = oracle.OracleScene(scene)
+    ref, _, _ = o.render(cams, st)
+    for R in (1, 3):
+        o.set_textures(np.repeat(scene.albedo[:, None, None], R * R, axis=1).reshape(-1, R, R))
+        img, _, _ = o.render(cams, st)
+        assert np.array_equal(img, ref), R
+    o.set_textures(None)
+    img, _, _ = o.render(cams, st)
+    assert np.array_equal(img, ref)
+
+
+@pytest.mark.parametrize("rot", [False, True])
+def test_textured_floor_closed_form(ora, rot):
+    """One 8 x 8 floor quad with a 4 x 4 texture seen from above under a distant
+    light: a pixel whose footprint lies inside one texel shows that texel's value
+    times (E / pi) cos(theta_L); others lie between the texels they cover.  With
+    the instance turned by 90 degrees about z the texture turns with it: texels
+    live in the face's own (u, v), not in world space."""
+    R = 4
+    verts, quads = ts.axis_quad(-4.0, 4.0, -4.0, 4.0, 0.0)
+    xf = [0, -1, 0, 0, 1, 0, 0, 0, 0, 0, 1, 0] if rot else [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]
+    scene = ts.multi_mesh_scene([(verts, quads)], xforms=[xf])
+    tex = (0.1 + 0.05 * np.arange(R * R, dtype=np.float32)).reshape(1, R, R).astype(np.float32)
+    res = 24
+    cams = _down_camera(res=res, eye=(0.0, 0.0, 3.5), vfov=90.0)
+    st = sg.RenderSettings(spp=2, depth=1, seed=17)
+    o = oracle.OracleScene(scene)
+    o.set_textures(tex)
+    img, fl, _ = o.render(cams, st)
+    cosl = st.light_dir[2]
+    th = math.tan(math.radians(90.0) / 2)
+
+    def texel(px, py):
+        sx = (2 * px / res - 1) * th
+        sy = (1 - 2 * py / res) * th
+        x, y = 3.5 * sx, 3.5 * sy  # the floor point under the pixel corner
+        if rot:  # object point of a world point under the 90 degree turn
+            x, y = y, -x
+        u, v = (x + 4.0) / 8.0, (y + 4.0) / 8.0  # v0 = (-4, -4), v1 = (4, -4), v3 = (-4, 4)
+        return min(int(v * R), R - 1), min(int(u * R), R - 1)
+
+    img = img.reshape(res, res)
+    fl = fl.reshape(res, res)
+    inside = 0
+    for y in range(res):
+        for x in range(res):
+            cells = {texel(x + i, y + j) for i in (0, 1) for j in (0, 1)}
+            vals = [float(tex[0][c]) * cosl for c in cells]
+            if len(cells) == 1:
+                assert not fl[y, x]
+                assert abs(img[y, x] - vals[0]) < 1e-12, (x, y)
+                inside += 1
+            else:
+                assert min(vals) - 1e-12 <= img[y, x] <= max(vals) + 1e-12, (x, y)
+    assert inside > res * res // 2
+    # the turned instance shows a different image: the lookup is not in world space
+    if rot:
+        o2 = oracle.OracleScene(ts.multi_mesh_scene([(verts, quads)]))
+        o2.set_textures(tex)
+        img2, _, _ = o2.render(cams, st)
+        assert not np.array_equal(img2.reshape(res, res), img)
