@@ -20,6 +20,8 @@ Reported (one JSON line):
   ablation             node format x scheduler (plain, persistent stages,
                        single persistent megakernel);
   graph_replay         the headline path replayed from a captured HIP graph;
+  textured             the headline path with per-face 4x4 textures in place
+                       of per-face albedo (equal images in both paths checked);
   incoherent           closest-hit throughput on the frame's bounce >= 1 rays,
                        quantized-persistent vs FP32-plain, at bit-identical hits;
   roofline             the frame's dominant kernel (the traversal launches, each
@@ -208,6 +210,22 @@ def main():
     graph_replay = dict(ms_per_frame=g["wall_ms"], mrays_s=g["rays"] / (g["wall_ms"] * 1e3))
     log(f"graph replay: {graph_replay}")
 
+    # ---- the same frame shaded from per-face textures (4 x 4 texels per face,
+    # nearest texel at the hit's (u, v)) instead of per-face albedo
+    tex_res = 4
+    gen = torch.Generator(device="cuda").manual_seed(1234)
+    S.set_textures(torch.rand((S.n_quads, tex_res, tex_res), device="cuda", generator=gen) * 0.9 + 0.05)
+    frame(0, **F32)
+    a = img.clone()
+    frame(0, **Q8P)
+    torch.cuda.synchronize()
+    tex_equal = bool(torch.equal(a.view(torch.int32), img.view(torch.int32)))
+    assert tex_equal, "textured images differ between the two paths"
+    t = timed(Q8P, max(3, args.steps // 2), 1)
+    S.set_textures(None)
+    textured = dict(tex_res=tex_res, ms_per_frame=t["wall_ms"], mrays_s=t["rays"] / (t["wall_ms"] * 1e3))
+    log(f"textured: {textured}")
+
     # ---- incoherent rays: bounce >= 1 extension rays of frame 0
     log("incoherent rays: dumping bounce >= 1 rays")
     cap = args.incoherent_rays
@@ -328,6 +346,7 @@ def main():
                        "speedup": round(inc["q8_persistent"]["mrays_s"] / inc["fp32_plain"]["mrays_s"], 3)},
         "ablation": {k: {kk: round(vv, 3) for kk, vv in d.items()} for k, d in ablation.items()},
         "graph_replay": {k: round(v, 3) for k, v in graph_replay.items()},
+        "textured": {k: round(v, 3) if isinstance(v, float) else v for k, v in textured.items()},
         "stages_ms_per_frame": {("traversal" if k == "closest" else k): round(d["ms"] / args.steps, 3)
                                 for k, d in q8["stages"].items() if k != "shadow"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

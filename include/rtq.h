@@ -146,7 +146,7 @@ typedef struct {
   int64_t tlas_nodes, blas_nodes;
   int32_t tlas_depth, blas_depth_max; /* 4-wide node levels */
   int32_t formats;                    /* RTQ_NODE_* built */
-  int64_t device_bytes;               /* all device memory held by the scene */
+  int64_t device_bytes;               /* all device memory held by the scene (textures included) */
   double build_seconds;               /* wall time of rtq_scene_build */
   int64_t n_top_entries;              /* top-level leaves: instances plus the subtrees opened ones add */
   double build_phase_seconds[4];      /* bottom levels (host); instance inverses and boxes (device) and
@@ -161,6 +161,29 @@ int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);
  * prototype order) without rebuilding.  Enqueued on `stream` (a device copy).
  */
 int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, hipStream_t stream);
+
+/*
+ * Per-face textures (Section 5.3: the diffuse colour of nearly every face comes
+ * from a Ptex texture, looked up by face id and the hit's coordinates on the
+ * face).  Here each unique quad carries res x res values, read at the nearest
+ * texel of the hit's (u, v) (v0 -> (0, 0), v1 -> (1, 0), v2 -> (1, 1),
+ * v3 -> (0, 1)), and that value replaces the face's albedo in shading, in every
+ * scheduler and node format.  No filtering, no mip levels, no borders shared
+ * with adjacent faces.
+ *
+ * texels_dev: device memory, n_unique_quads * res * res floats, face-major in
+ * prototype order, then row v, then column u: texel (tx, ty) of face f at
+ * [(f * res + ty) * res + tx]; it is copied into memory the scene owns (freed by
+ * rtq_scene_destroy), the caller keeps its buffer.  res = 0 (texels_dev may be
+ * NULL) removes the textures.  Waits for all work on the device, then enqueues
+ * the copy on `stream`; renders on other streams are ordered by the caller.
+ * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES] or NULL
+ * texels with res > 0; RTQ_E_HIP when the allocation or copy fails.
+ * rtq_render_backward rejects a textured scene (its gradient is with respect
+ * to the per-face albedo).
+ */
+#define RTQ_MAX_TEX_RES 64
+int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t res, hipStream_t stream);
 
 /* ------------------------------------------------------------------ tracing */
 /* Rays and hits are structure-of-arrays in device memory, one element per ray. */
@@ -258,6 +281,15 @@ typedef struct {
                           seed and frame may change).  Graphs are kept in the
                           scene and dropped when its render scratch grows.
                           Replays of one scene must not overlap in time. */
+  int32_t accumulate;  /* progressive refinement (Section 5.4: one sample per pixel
+                          per frame, frames accumulated over time): the number k
+                          of frames already averaged in `images`.  0 writes this
+                          call's mean m; k > 0 blends it in as
+                          images += (m - images) / (k + 1), so frames rendered with
+                          accumulate = 0, 1, ..., K - 1 (and different `frame`
+                          values) leave the running mean of their K images.  It
+                          changes nothing but that blend (graphs replay with any
+                          k).  Ignored by rtq_render_backward and rtq_render_path. */
 } rtq_render_opts;
 
 /*
@@ -269,8 +301,9 @@ typedef struct {
  * the mean over its spp samples, summed in sample order, so every scheduler
  * produces bit-identical images.  cams: host memory.  Scratch memory is
  * allocated on first use and kept in the scene handle.
- * Errors: INVALID_ARG (spp < 1, depth < 1 or > 16, w or h < 1, NULL images);
- * LIMIT when the call has more than 2^31 - 1 paths (sum of w h spp).
+ * Errors: INVALID_ARG (spp < 1, depth < 1 or > 16, w or h < 1, NULL images,
+ * accumulate < 0); LIMIT when the call has more than 2^31 - 1 paths (sum of
+ * w h spp).
  */
 int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
                const rtq_render_opts* opts, float* images, hipStream_t stream);
@@ -295,7 +328,7 @@ int rtq_render_timing(rtq_scene* scene, float* ms, int32_t* launches);
  * checks: path (view, pixel, sample) with pixel = row * w + column.  Per vertex
  * k < *n_vert: vert_i[6k..6k+5] = (instance id, primitive, half, shadow: -1 no
  * shadow ray / 0 light visible / 1 occluded, unique face, 0) and
- * vert_f[10k..10k+9] = (t, albedo, cosine to the light, radiance after the
+ * vert_f[10k..10k+9] = (t, albedo or texel, cosine to the light, radiance after the
  * vertex, origin xyz and direction xyz of the ray that found the vertex);
  * *escaped = 1 if the path left the scene; *radiance = its total.
  * vert_i: host, 6 depth int32; vert_f: host, 10 depth floats.  Synchronises
@@ -311,7 +344,8 @@ int rtq_render_path(const rtq_scene* scene, const rtq_camera* cams, int32_t n_ca
  * grad_albedo[f] += sum over pixels p of grad_images[p] * dI_p / d albedo[f].
  * Each path is replayed from its RNG counters (same hits as the forward pass).
  * grad_albedo: device, n_unique_quads floats, zeroed by the caller, accumulated
- * with atomics (summation order is not fixed).
+ * with atomics (summation order is not fixed).  Errors: RTQ_E_INVALID_ARG on a
+ * scene with textures (rtq_scene_set_textures), as rtq_render otherwise.
  */
 int rtq_render_backward(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp,
                         int32_t depth, const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,

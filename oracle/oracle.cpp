@@ -596,17 +596,21 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
     double a = S.albedo[face];
+    uint32_t tex_flag = 0;
     if (S.tex_res > 0) {
       // the texel of (u, v): nearest, on a res x res grid over the quad.  Which
       // texel a hit near a texel edge lands on depends on rounding: flag hits
-      // whose world distance to an inner texel edge is below 1e-5 S (the
-      // position error of the FP32 hit is about 1e-6 S)
+      // whose world distance to an inner texel edge is below 1e-5 S / |cos|
+      // (the position error of an FP32 hit is about 1e-6 S, stretched by
+      // 1 / |cos| across the face at grazing incidence)
       const int R = S.tex_res;
       const double lu = std::max(norm(wq[1] - wq[0]), norm(wq[2] - wq[3]));
       const double lv = std::max(norm(wq[3] - wq[0]), norm(wq[2] - wq[1]));
       const double gu = h.best.u * R, gv = h.best.v * R;
+      const double tol = 1e-5 * h.S / std::max(std::fabs(nd), 1e-3);
       for (int k = 1; k < R; ++k)
-        if (std::fabs(gu - k) * lu / R < 1e-5 * h.S || std::fabs(gv - k) * lv / R < 1e-5 * h.S) rec.flags |= F_SHADE;
+        if (std::fabs(gu - k) * lu / R < tol || std::fabs(gv - k) * lv / R < tol) tex_flag = F_SHADE;
+      rec.flags |= tex_flag;
       const int tx = std::min(std::max((int)std::floor(gu), 0), R - 1);
       const int ty = std::min(std::max((int)std::floor(gv), 0), R - 1);
       a = S.tex[((size_t)face * R + ty) * R + tx];
@@ -623,7 +627,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     vx.prim = h.best.prim;
     vx.half = h.best.half;
     vx.t = h.best.t;
-    vx.flags = h.flags;
+    vx.flags = h.flags | tex_flag;
     vx.shadow = -1;
     vx.shadow_flags = 0;
     if (cl > 0) {

@@ -84,7 +84,7 @@ class _RenderOpts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32), ("counters", ctypes.c_void_p),
                 ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
                 ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p),
-                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -93,7 +93,7 @@ _lib = None
 EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destroy", "rtq_scene_get_info",
            "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
            "rtq_render_backward", "rtq_render_timing", "rtq_render_path", "rtq_host_bvh_build", "rtq_host_bvh_get",
-           "rtq_host_bvh_destroy"]
+           "rtq_host_bvh_destroy", "rtq_scene_set_textures"]
 
 
 def load_library():
@@ -115,6 +115,7 @@ def load_library():
     L.rtq_scene_destroy.argtypes = [P]
     L.rtq_scene_get_info.argtypes = [P, P]
     L.rtq_scene_set_albedo.argtypes = [P, P, ctypes.c_int64, P]
+    L.rtq_scene_set_textures.argtypes = [P, P, ctypes.c_int32, P]
     L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
@@ -207,6 +208,20 @@ class Scene:
         a = albedo.contiguous().float()
         _check(load_library().rtq_scene_set_albedo(self.handle, a.data_ptr(), a.numel(), _stream()))
         self._albedo_keep = a
+
+    def set_textures(self, texels) -> None:
+        """Per-face textures: a device tensor [n_quads, res, res] (row v, column u),
+        read at the nearest texel of each hit's (u, v) in place of the face's
+        albedo; None removes them."""
+        if texels is None:
+            _check(load_library().rtq_scene_set_textures(self.handle, None, 0, _stream()))
+            self._tex_keep = None
+            return
+        assert texels.is_cuda and texels.dim() == 3 and texels.shape[0] == self.n_quads
+        assert texels.shape[1] == texels.shape[2]
+        t = texels.contiguous().float()
+        _check(load_library().rtq_scene_set_textures(self.handle, t.data_ptr(), int(t.shape[1]), _stream()))
+        self._tex_keep = t
 
     def close(self):
         if getattr(self, "_h", None):
@@ -301,7 +316,7 @@ def camera_structs(cams) -> tuple:
 
 def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
                 counters=None, view_done=None, start_tick=None, visits=None, dump_rays=None, dump_count=None,
-                timing=False, graph=False):
+                timing=False, graph=False, accumulate=0):
     o = _RenderOpts()
     o.seed = int(settings.seed)
     o.frame = int(settings.frame)
@@ -323,6 +338,7 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.dump_count = _ptr(dump_count)
     o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0
+    o.accumulate = int(accumulate)
     return o
 
 

@@ -68,6 +68,8 @@ SceneView scene_view(const rtq_scene* s, int fmt) {
   v.rec_qfirst = s->rec_qfirst;
   v.rec_nq = s->rec_nq;
   v.albedo = s->albedo;
+  v.tex = s->tex;
+  v.tex_res = s->tex_res;
   v.pad_rel = s->pad_rel;
   v.n_rec = (uint32_t)s->n_rec;
   return v;
@@ -516,6 +518,7 @@ void rtq_scene_destroy(rtq_scene* s) {
   (void)hipDeviceSynchronize();
   release_render_scratch(s);
   s->bufs.release();
+  if (s->tex) (void)hipFree(s->tex);
   delete s;
 }
 
@@ -530,7 +533,7 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->tlas_depth = s->tlas_depth;
   info->blas_depth_max = s->blas_depth;
   info->formats = s->formats;
-  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total);
+  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes);
   info->build_seconds = s->build_seconds;
   info->n_top_entries = s->n_rec;
   for (int k = 0; k < 4; ++k) info->build_phase_seconds[k] = s->build_phase[k];
@@ -544,6 +547,36 @@ int rtq_scene_set_albedo(rtq_scene* s, const float* albedo_dev, int64_t n, hipSt
                      (long long)s->n_quads);
   const hipError_t e = hipMemcpyAsync(s->albedo, albedo_dev, n * sizeof(float), hipMemcpyDeviceToDevice, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "hipMemcpyAsync");
+}
+
+int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, hipStream_t stream) {
+  if (!s) return set_error(RTQ_E_INVALID_ARG, "NULL scene");
+  if (res < 0 || res > RTQ_MAX_TEX_RES)
+    return set_error(RTQ_E_INVALID_ARG, "texture resolution %d outside [0, %d]", res, RTQ_MAX_TEX_RES);
+  if (res > 0 && !texels_dev) return set_error(RTQ_E_INVALID_ARG, "NULL texels");
+  hipError_t e = hipSetDevice(s->device);
+  if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+  // renders already queued may still read the old texels
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
+  const size_t bytes = (size_t)s->n_quads * (size_t)res * (size_t)res * sizeof(float);
+  if (res == 0 || bytes != s->tex_bytes) {
+    if (s->tex) (void)hipFree(s->tex);
+    s->tex = nullptr;
+    s->tex_res = 0;
+    s->tex_bytes = 0;
+    if (res == 0) return RTQ_OK;
+    e = hipMalloc(reinterpret_cast<void**>(&s->tex), bytes);
+    if (e != hipSuccess) {
+      s->tex = nullptr;
+      return hip_error(e, "texture allocation");
+    }
+    s->tex_bytes = bytes;
+  }
+  e = hipMemcpyAsync(s->tex, texels_dev, bytes, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync");
+  s->tex_res = res;
+  return RTQ_OK;
 }
 
 static int check_rays(const rtq_scene* s, const rtq_rays* r, int64_t n) {

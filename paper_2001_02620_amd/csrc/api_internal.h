@@ -57,6 +57,9 @@ struct rtq_scene {
   uint32_t* rec_qfirst = nullptr;  // per record: quad range of the subtree it enters
   uint32_t* rec_nq = nullptr;
   float* albedo = nullptr;
+  float* tex = nullptr;  // per-face textures (own allocation, rtq_scene_set_textures)
+  int32_t tex_res = 0;
+  size_t tex_bytes = 0;
   unsigned long long* counters = nullptr;  // ring of persistent-kernel work counters
   mutable std::atomic<uint32_t> counter_next{0};
   rtq::DeviceBuffers bufs;

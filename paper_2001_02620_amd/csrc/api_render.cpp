@@ -166,6 +166,8 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
     RALLOC(r->pb.hits.t, P * 4);
     RALLOC(r->pb.hits.rec, P * 4);
     RALLOC(r->pb.hits.qh, P * 4);
+    RALLOC(r->pb.hits.u, P * 4);
+    RALLOC(r->pb.hits.v, P * 4);
     RALLOC(r->pb.occ, P);
     RALLOC(r->pb.counts, (2 * kMaxDepth + 2) * sizeof(uint32_t));
     RALLOC(r->pb.work, (size_t)(kMaxDepth + 1) * kClaimWords * sizeof(unsigned long long));
@@ -192,6 +194,7 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   if (n_cams < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one camera");
   if (spp < 1) return set_error(RTQ_E_INVALID_ARG, "spp %d < 1", spp);
   if (depth < 1 || depth > kMaxDepth) return set_error(RTQ_E_INVALID_ARG, "depth %d outside [1, %d]", depth, kMaxDepth);
+  if (opts->accumulate < 0) return set_error(RTQ_E_INVALID_ARG, "accumulate %d < 0", opts->accumulate);
   if (opts->scheduler != RTQ_SCHED_PLAIN && opts->scheduler != RTQ_SCHED_PERSISTENT &&
       opts->scheduler != RTQ_SCHED_MEGAKERNEL)
     return set_error(RTQ_E_INVALID_ARG, "unknown scheduler %d", opts->scheduler);
@@ -267,7 +270,8 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
       hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_error(e, "camera upload");
   const hipError_t ek = launch_set_keys(sc->keys, (uint32_t)(opts->seed & 0xFFFFFFFFull),
-                                         (uint32_t)(opts->seed >> 32) ^ opts->frame, stream);
+                                         (uint32_t)(opts->seed >> 32) ^ opts->frame, (uint32_t)opts->accumulate,
+                                         stream);
   if (ek != hipSuccess) return hip_error(ek, "key upload");
   RenderParams& rp = out->rp;
   rp.cams = sc->cams;
@@ -291,20 +295,21 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
 namespace {
 
 // Capture (first use) or replay the launches of one render call.  The key holds
-// every value that the launches bake in: pointers, sizes, grid shapes and the
-// render constants; the RNG key is read from device memory, written before the
+// every value that the launches bake in: pointers, sizes, grid shapes, the
+// render constants and the scene's texture buffer; the RNG key and the
+// accumulated frame count are read from device memory, written before the
 // graph runs, so frames with other seeds replay the same graph.
 int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prepared& p, bool staged, float* images,
                  RenderExtras ex, hipStream_t stream) {
   char key[512];
   const RenderParams& rp = p.rp;
   std::snprintf(key, sizeof(key),
-                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p", staged ? 1 : 0,
+                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p|%p %d", staged ? 1 : 0,
                 p.fmt, p.tl.persistent, p.tl.stack_depth, p.tl.block, p.tl.refill, p.tl.grid, rp.n_cams, rp.spp,
                 (long long)rp.depth, (long long)rp.n_paths, rp.lx, rp.ly, rp.lz, rp.e_over_pi, rp.L_sky,
                 (const void*)rp.cams, (const void*)rp.slots, (const void*)images, (void*)ex.counters,
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
-                (void*)ex.start_tick, (void*)sv.nodes);
+                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res);
   const std::string k(key);
   auto it = r->graphs.find(k);
   if (it == r->graphs.end()) {
@@ -499,6 +504,8 @@ int rtq_render_backward(const rtq_scene* s, const rtq_camera* cams, int32_t n_ca
                         const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,
                         hipStream_t stream) {
   if (!grad_images || !grad_albedo) return set_error(RTQ_E_INVALID_ARG, "NULL gradient buffer");
+  if (s && s->tex_res > 0)
+    return set_error(RTQ_E_INVALID_ARG, "the adjoint is with respect to per-face albedo; the scene has textures");
   Prepared p;
   int rc = prepare(s, cams, n_cams, spp, depth, opts, false, stream, &p);
   if (rc) return rc;

@@ -126,19 +126,26 @@ __device__ __forceinline__ bool load_queue_ray(Lane& L, const SceneView& sc, con
 }
 
 template <bool ANY>
-__device__ __forceinline__ void store_queue_result(const Lane& L, const QueueHits& qh, uint8_t* occ, int64_t i) {
+__device__ __forceinline__ void store_queue_result(const Lane& L, const QueueHits& qh, uint8_t* occ, int64_t i,
+                                                   bool tex) {
   if (ANY) {
     occ[i] = L.b_rec != kEmpty ? 1 : 0;
   } else {
     qh.t[i] = L.t_best;
     qh.rec[i] = L.b_rec;
     qh.qh[i] = L.b_rec == kEmpty ? kEmpty : L.b_qh;
+    if (tex) {
+      qh.u[i] = L.b_u;
+      qh.v[i] = L.b_v;
+    }
   }
 }
 
 // Closest hit (ANY = false) of an extension queue, or occlusion (ANY = true) of a
-// shadow queue, one lane per entry.
-template <int FMT, bool ANY, bool COUNT>
+// shadow queue, one lane per entry.  TEX: the scene has textures, so closest
+// hits also store (u, v); without it the compiler drops their arithmetic from
+// the quad test.
+template <int FMT, bool ANY, bool COUNT, bool TEX>
 __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq, const uint32_t* count,
                               QueueHits qh, uint8_t* occ, int depth, unsigned long long* visits) {
   extern __shared__ uint2 lds[];
@@ -152,7 +159,7 @@ __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, Shadow
     if (load_queue_ray<ANY>(L, sc, rp, eq, sq, i))
       while (!lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
       }
-    store_queue_result<ANY>(L, qh, occ, i);
+    store_queue_result<ANY>(L, qh, occ, i, TEX);
   }
   if (COUNT) wave_add_visits(vc, visits);
 }
@@ -163,7 +170,7 @@ __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, Shadow
 // the extension rays of bounce b + 1 halves the traversal launches of a frame
 // and with them the drain at the end of each launch; the short any-hit rays
 // come last, where the launch drains.
-template <int FMT, bool COUNT>
+template <int FMT, bool COUNT, bool TEX>
 __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, const uint32_t* count_ext,
                                     ShadowQueue sq, const uint32_t* count_sh, QueueHits qh, uint8_t* occ, int depth,
                                     int refill, unsigned long long* counter, unsigned long long* visits) {
@@ -187,11 +194,11 @@ __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, 
         if (k < n_ext) {
           idx = k;
           if (load_queue_ray<false>(L, sc, rp, eq, sq, idx)) has = true;
-          else store_queue_result<false>(L, qh, occ, idx);
+          else store_queue_result<false>(L, qh, occ, idx, TEX);
         } else {
           idx = k - n_ext;
           if (load_queue_ray<true>(L, sc, rp, eq, sq, idx)) has = true;
-          else store_queue_result<true>(L, qh, occ, idx);
+          else store_queue_result<true>(L, qh, occ, idx, TEX);
         }
       }
     }
@@ -202,8 +209,8 @@ __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, 
     if (has) {
       for (;;) {
         if (lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
-          if (L.any) store_queue_result<true>(L, qh, occ, idx);
-          else store_queue_result<false>(L, qh, occ, idx);
+          if (L.any) store_queue_result<true>(L, qh, occ, idx, TEX);
+          else store_queue_result<false>(L, qh, occ, idx, TEX);
           if (COUNT) {
             VisitCounters& acc = L.any ? vc_sh : vc_cl;
             acc.tlas += vc.tlas;
@@ -243,7 +250,9 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     } else {
       qhv = qh.qh[i];
       const Ray3 r{in.ox[i], in.oy[i], in.oz[i], in.dx[i], in.dy[i], in.dz[i]};
-      s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31);
+      const bool tex = sc.tex_res > 0;
+      s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31, tex ? qh.u[i] : 0.0f,
+                    tex ? qh.v[i] : 0.0f);
       if (s.cosl > 0.0f) {
         want_shadow = true;
         contrib = nee_term(beta, s.a, s.cosl, rp);
@@ -319,7 +328,10 @@ __global__ void k_accum(RenderParams rp, float* image, int64_t n_pixels) {
   if (pixel >= wh) return;  // a gap between views: not part of any image
   float sum = 0.0f;
   for (int s = 0; s < rp.spp; ++s) sum += rp.slots[c.path_base + s * wh + pixel];
-  image[g] = sum / (float)rp.spp;
+  const float m = sum / (float)rp.spp;
+  // progressive refinement: keys[2] frames are already averaged in the image
+  const uint32_t k = rp.keys[2];
+  image[g] = k == 0u ? m : image[g] + (m - image[g]) / (float)(k + 1u);
 }
 
 // counters[0..3] += closest, shadow, incoherent (bounce >= 1), paths
@@ -337,10 +349,11 @@ __global__ void k_plain_stats(const uint32_t* counts, int depth, int64_t n_paths
   counters[3] += (unsigned long long)n_paths;
 }
 
-__global__ void k_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1) {
+__global__ void k_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, uint32_t acc) {
   if (threadIdx.x == 0) {
     keys[0] = k0;
     keys[1] = k1;
+    keys[2] = acc;
   }
 }
 
@@ -361,7 +374,7 @@ struct PathLane {
 
 // At least four resident waves per SIMD (up to 128 registers per lane: the path
 // state comes on top of the traversal state).
-template <int FMT, bool TS, bool COUNT>
+template <int FMT, bool TS, bool COUNT, bool TEX>
 __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
                                     unsigned long long* counter, unsigned long long* counters,
                                     unsigned long long* view_done, unsigned long long* visits) {
@@ -431,7 +444,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
               } else {
                 const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
                 const uint32_t hrec = L.b_rec, hqh = L.b_qh;
-                const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31);
+                const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31,
+                                          TEX ? L.b_u : 0.0f, TEX ? L.b_v : 0.0f);
                 P.have_next = P.b < rp.depth - 1;
                 if (P.have_next) {
                   int view;
@@ -542,7 +556,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
       break;
     }
     const uint32_t hqh = L.b_qh;
-    const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31);
+    const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     int shadow = -1;
     if (sh.cosl > 0.0f) {
       const float pending = nee_term(beta, sh.a, sh.cosl, rp);
@@ -628,7 +642,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
       break;
     }
     const uint32_t hrec = L.b_rec, hqh = L.b_qh;
-    const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31);
+    const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     float c = 0.0f;
     if (s.cosl > 0.0f) {
       L.ex_rec = hrec;
@@ -680,15 +694,19 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
   uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
   unsigned long long* vis_sh = ex.visits ? ex.visits + 4 : nullptr;
   hipEvent_t ev = stage_begin(ex.log, s);
-  hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, cin,
-                     pb.hits, pb.occ, tl.stack_depth, ex.visits);
+  if (sc.tex_res > 0)
+    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT, true>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
+                       cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
+  else
+    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT, false>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
+                       cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
   stage_end(ex.log, 0, ev, s);
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
                      ex.dump, ex.dump_cap, ex.dump_count);
   stage_end(ex.log, 2, ev, s);
   ev = stage_begin(ex.log, s);
-  hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, csq,
+  hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT, false>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, csq,
                      pb.hits, pb.occ, tl.stack_depth, vis_sh);
   stage_end(ex.log, 1, ev, s);
   ev = stage_begin(ex.log, s);
@@ -702,9 +720,13 @@ static void mixed_launch(const SceneView& sc, const RenderParams& rp, const Plai
                          int slot, hipStream_t s) {
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   hipEvent_t ev = stage_begin(ex.log, s);
-  hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq, cext,
-                     pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, pb.work + (size_t)slot * kClaimWords,
-                     ex.visits);
+  unsigned long long* work = pb.work + (size_t)slot * kClaimWords;
+  if (sc.tex_res > 0)
+    hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq,
+                       cext, pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, work, ex.visits);
+  else
+    hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq,
+                       cext, pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, work, ex.visits);
   stage_end(ex.log, 0, ev, s);
 }
 
@@ -777,8 +799,12 @@ template <int FMT, bool TS, bool COUNT>
 static void persistent_launch(const SceneView& sc, const RenderParams& rp, const TraceLaunch& tl,
                               const RenderExtras& ex, hipStream_t s) {
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
-  hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                     tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
+  if (sc.tex_res > 0)
+    hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                       tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
+  else
+    hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
+                       tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
 }
 
 hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,
@@ -824,8 +850,8 @@ hipError_t launch_path_record(const SceneView& sc, const RenderParams& rp, int f
   return hipGetLastError();
 }
 
-hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_keys, dim3(1), dim3(64), 0, s, keys, k0, k1);
+hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, uint32_t acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_keys, dim3(1), dim3(64), 0, s, keys, k0, k1, acc);
   return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ struct RenderParams {
   int32_t n_cams;
   int32_t spp;
   int32_t depth;
-  const uint32_t* keys; // device [2]: Philox key (seed_lo, seed_hi ^ frame), written at the start of each call
+  const uint32_t* keys; // device [3]: Philox key (seed_lo, seed_hi ^ frame) and the frames already
+                        // averaged in the image, written at the start of each call
   float lx, ly, lz;     // unit direction toward the light
   float e_over_pi;      // E / pi
   float L_sky;
@@ -97,11 +98,24 @@ struct Shade {
   uint32_t face;     // unique face index (albedo index)
 };
 
+// Texture value of face `face` at (u, v) (Section 5.3: looked up by face id and
+// the hit's coordinates on the face): the nearest of tex_res x tex_res texels
+// over the face's unit square.  Clamping in float first keeps the index in
+// range for any u, v (NaN included: fmaxf returns the other operand).
+__device__ __forceinline__ float face_texel(const SceneView& sc, uint32_t face, float u, float v) {
+  const int R = sc.tex_res;
+  const float hi = (float)(R - 1);
+  const int tx = (int)fminf(fmaxf(u * (float)R, 0.0f), hi);
+  const int ty = (int)fminf(fmaxf(v * (float)R, 0.0f), hi);
+  return sc.tex[((size_t)face * R + ty) * R + tx];
+}
+
 // Geometric normal of the hit half in object space, mapped to world space by
 // A^-T (columns of the stored inverse rows), normalised and turned to face the
-// incoming ray; hit point p = o + t d; albedo of the unique prototype face.
+// incoming ray; hit point p = o + t d; albedo of the unique prototype face, or
+// its texel at the hit's (u, v) when the scene has textures.
 __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderParams& rp, const Ray3& r, float t,
-                                           uint32_t rec, uint32_t quad, uint32_t half) {
+                                           uint32_t rec, uint32_t quad, uint32_t half, float u, float v) {
   const float4 f0 = sc.quads[3 * (size_t)quad + 0];
   const float4 f1 = sc.quads[3 * (size_t)quad + 1];
   const float4 f2 = sc.quads[3 * (size_t)quad + 2];
@@ -139,7 +153,7 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   s.ny = ny;
   s.nz = nz;
   s.face = ir.face_base + (uint32_t)sc.quad_prim[quad];
-  s.a = sc.albedo[s.face];
+  s.a = sc.tex_res > 0 ? face_texel(sc, s.face, u, v) : sc.albedo[s.face];
   s.cosl = nx * rp.lx + ny * rp.ly + nz * rp.lz;
   return s;
 }

@@ -32,6 +32,7 @@ struct QueueHits {
   float* t;
   uint32_t* rec;
   uint32_t* qh;
+  float *u, *v;  // written only for a scene with textures
 };
 
 struct PlainBuffers {
@@ -77,6 +78,6 @@ hipError_t launch_path_record(const SceneView& sc, const RenderParams& rp, int f
                               int32_t* rec_i, float* rec_f, int32_t* out, hipStream_t s);
 // Write the call's RNG key to device memory (kept outside captured graphs, so a
 // replayed frame picks up the key of its own call).
-hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, hipStream_t s);
+hipError_t launch_set_keys(uint32_t* keys, uint32_t k0, uint32_t k1, uint32_t acc, hipStream_t s);
 
 }  // namespace rtq

@@ -37,6 +37,8 @@ struct SceneView {
   const uint32_t* rec_qfirst; // per record: first leaf-ordered quad of the subtree it enters
   const uint32_t* rec_nq;     // per record: quads of that subtree
   const float* albedo;        // per unique face (prototype order)
+  const float* tex;           // per unique face: tex_res x tex_res texels (row v, column u), or null
+  int32_t tex_res;            // texels per side; 0 shades with `albedo`
   float pad_rel;              // top-level origin pad per unit of |o|_inf
   float p_world;              // bound on |world coordinate| of the top-level boxes
   uint32_t tlas_root;         // index of the top-level root in `nodes`
