@@ -293,10 +293,12 @@ typedef struct {
 } rtq_render_opts;
 
 /*
- * Path-trace n_cams pinhole views (Section 5.4, progressive 1 spp frames; here
- * spp samples per call) with a Lambertian BSDF, next-event estimation toward
- * one directional light, and a constant sky.  depth counts closest-hit rays per
- * path including the camera ray.  `images` is a packed FP32 device buffer; view
+ * Path-trace n_cams pinhole views (Section 5.4: progressive 1 spp frames; here
+ * spp samples per call, frames averaged with opts.accumulate) with a
+ * Lambertian BSDF (albedo per face, or a texel of the face's texture when the
+ * scene has textures), next-event estimation toward one directional light,
+ * and a constant sky.  depth counts closest-hit rays per path including the
+ * camera ray.  `images` is a packed FP32 device buffer; view
  * c occupies [img_offset, img_offset + w h), row 0 at the top.  Each pixel is
  * the mean over its spp samples, summed in sample order, so every scheduler
  * produces bit-identical images.  cams: host memory.  Scratch memory is
