@@ -176,7 +176,9 @@ class OracleScene:
     def _params(settings):
         pi = np.array([settings.spp, settings.depth], dtype=np.int32)
         pu = np.array([settings.seed, settings.frame], dtype=np.uint64)
-        pd = np.array(list(settings.light_dir) + [settings.E, settings.L_sky], dtype=np.float64)
+        al = np.asarray(settings.area_lights, dtype=np.float32).reshape(-1, 10).astype(np.float64)
+        pd = np.array(list(settings.light_dir) + [settings.E, settings.L_sky, al.shape[0]] + al.ravel().tolist(),
+                      dtype=np.float64)
         if not (1 <= settings.depth <= 64):
             raise ValueError("depth must be in [1, 64]")
         return pi, pu, pd

@@ -522,7 +522,17 @@ struct Params {
   uint32_t frame;
   double light[3];
   double E, L_sky;
+  int n_area = 0;               // quad area lights
+  const double* area = nullptr;  // 10 per light: corner, edge 1, edge 2, emitted radiance
 };
+
+// pd: light direction (3), E, L_sky, number of area lights, then 10 per light.
+Params make_params(const int32_t* pi, const uint64_t* pu, const double* pd) {
+  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  P.n_area = (int)pd[5];
+  P.area = pd + 6;
+  return P;
+}
 
 struct Cam {
   V3 eye, f, r, u;
@@ -617,7 +627,19 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     }
     Vertex vx{face, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
     const double cl = dot(n, L);
-    if (std::fabs(cl) < 1e-6) rec.flags |= F_SHADE;
+    // next-event estimation: with area lights, one of the nl = 1 + n_area
+    // lights (0: the directional light) is picked with equal probability from
+    // word 0 of counter (pixel, sample, view, 2^31 + b), as an integer, and its
+    // estimate is weighted by nl
+    const int nl = 1 + P.n_area;
+    int j = 0;
+    uint32_t wl[4] = {0u, 0u, 0u, 0u};
+    if (P.n_area > 0) {
+      uint32_t ctr3[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x80000000u | (uint32_t)b};
+      philox(ctr3, key, wl);
+      j = (int)(((uint64_t)(wl[0] >> 8) * (uint64_t)nl) >> 24);
+    }
+    if (j == 0 && std::fabs(cl) < 1e-6) rec.flags |= F_SHADE;
     // origin uncertainty of rays leaving p: the FP32 position error of this hit
     // plus the incoming ray's own origin uncertainty, both stretched along the
     // surface by the incidence angle
@@ -630,14 +652,38 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     vx.flags = h.flags | tex_flag;
     vx.shadow = -1;
     vx.shadow_flags = 0;
-    if (cl > 0) {
+    if (j == 0 && cl > 0) {
       Ray sr{p, L, 0.0, kInf};
       TraceOut o = trace_one(S, sr, here, r1, mode, true);
       rec.n_shadow++;
       rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
       vx.shadow = o.best.inst >= 0 ? 1 : 0;
       vx.shadow_flags = o.flags;
-      if (o.best.inst < 0) vx.c = P.E / kPi * cl;
+      if (o.best.inst < 0) vx.c = nl * (P.E / kPi * cl);
+    } else if (j > 0) {
+      // area light j - 1: the parallelogram c + s e1 + t e2, (s, t) uniform from
+      // words 1, 2, emitting Le from the side e1 x e2 faces.  Its estimate of
+      // the irradiance is Le A cos_p cos_l / d^2 for the sampled point x at
+      // distance d; the shadow ray runs from p to x (direction x - p, tmax 1)
+      const double* Lq = P.area + 10 * (j - 1);
+      const V3 c0{Lq[0], Lq[1], Lq[2]}, e1{Lq[3], Lq[4], Lq[5]}, e2{Lq[6], Lq[7], Lq[8]};
+      const V3 x = c0 + unit(wl[1]) * e1 + unit(wl[2]) * e2;
+      const V3 wi = x - p;
+      const double d2 = dot(wi, wi), dd = std::sqrt(d2);
+      const V3 nlv = cross(e1, e2);
+      const double A = norm(nlv);
+      const double cp = dd > 0 ? dot(n, wi) / dd : 0.0;
+      const double cq = dd > 0 && A > 0 ? -dot(nlv, wi) / (A * dd) : 0.0;
+      if (std::fabs(cp) < 1e-6 || std::fabs(cq) < 1e-6 || dd < 1e-6 * h.S) rec.flags |= F_SHADE;
+      if (cp > 0 && cq > 0) {
+        Ray sr{p, wi, 0.0, 1.0};
+        TraceOut o = trace_one(S, sr, here, r1, mode, true);
+        rec.n_shadow++;
+        rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
+        vx.shadow = o.best.inst >= 0 ? 1 : 0;
+        vx.shadow_flags = o.flags;
+        if (o.best.inst < 0) vx.c = nl * (Lq[9] * A * cp * cq / (kPi * d2));
+      }
     }
     rec.v[rec.nv++] = vx;
     if (b == P.depth - 1) return;
@@ -855,7 +901,7 @@ void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_ca
                 const uint64_t* pu, const double* pd, const int64_t* pix, int64_t n_pix, int32_t mode,
                 double* image, uint8_t* pflags, double* stats) {
   const Scene& S = *static_cast<Scene*>(s);
-  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  const Params P = make_params(pi, pu, pd);
   std::vector<Cam> cams;
   int64_t total = 0;
   for (int c = 0; c < n_cams; ++c) {
@@ -899,7 +945,7 @@ void orc_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
               const uint64_t* pu, const double* pd, int64_t g, int32_t sample, int32_t* nv, int32_t* out_i,
               double* out_d, int32_t* escaped, uint32_t* path_flags) {
   const Scene& S = *static_cast<Scene*>(s);
-  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  const Params P = make_params(pi, pu, pd);
   std::vector<Cam> cams;
   for (int c = 0; c < n_cams; ++c) cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
   int32_t view;
@@ -929,7 +975,7 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
               const double* gpix, int32_t grad_mode, const double* tangent, double* grad_albedo, double* dI,
               uint8_t* pflags, uint8_t* face_tainted, int32_t taint_per_path) {
   const Scene& S = *static_cast<Scene*>(s);
-  Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
+  const Params P = make_params(pi, pu, pd);
   std::vector<Cam> cams;
   int64_t total = 0;
   for (int c = 0; c < n_cams; ++c) {

@@ -91,6 +91,9 @@ class RenderSettings:
         default_factory=lambda: tuple((np.array([1.0, -1.0, 2.0]) / math.sqrt(6.0)).tolist()))
     E: float = math.pi
     L_sky: float = 0.25
+    # quad area lights: (corner xyz, edge-1 xyz, edge-2 xyz, emitted radiance)
+    # each, emitting from the side that edge 1 x edge 2 faces
+    area_lights: Tuple[Tuple[float, ...], ...] = ()
 
 
 # ----------------------------------------------------------------------------

@@ -528,3 +528,54 @@ def test_textured_floor_closed_form(ora, rot):
         o2.set_textures(tex)
         img2, _, _ = o2.render(cams, st)
         assert not np.array_equal(img2.reshape(res, res), img)
+
+
+# ------------------------------------------------------------ area lights (5.4)
+def _area_setup(E, half=0.4, h=1.0, extra=None, flip=False):
+    a_f = float(np.float32(0.5))
+    scene = ts.floor_scene(albedo=a_f, half=50.0, extra=extra)
+    # a 2 half x 2 half square at height h centred over the origin; edge 1 x edge 2
+    # points down (toward the floor) unless flipped
+    e1, e2 = (0.0, 2 * half, 0.0), (2 * half, 0.0, 0.0)
+    if flip:
+        e1, e2 = e2, e1
+    light = (-half, -half, h) + e1 + e2 + (1.0,)
+    cams = [sg.Camera((0.0, 0.0, 0.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.01, 32, 32)]
+    st = sg.RenderSettings(spp=64, depth=1, seed=91, E=E, area_lights=(light,))
+    return scene, cams, st, a_f
+
+
+@pytest.mark.parametrize("E", [0.0, math.pi])
+def test_area_light_form_factor(ora, E):
+    """Floor point under a parallel square light of radiance Le: the irradiance is
+    pi Le F, with F the view factor of the square (closed form), so the outgoing
+    radiance is a Le F; with the directional light on as well (one of the two
+    lights picked per hit, weighted by 2) it is a ((E / pi) cos_L + Le F)."""
+    half, h = 0.4, 1.0
+    scene, cams, st, a_f = _area_setup(E, half, h)
+    img, fl, _ = oracle.OracleScene(scene).render(cams, st)
+    assert (fl == 0).all()
+    F = 4 * ts.form_factor_corner(half, half, h)
+    expect = a_f * ((E / math.pi) * st.light_dir[2] + F)
+    se = img.std() / math.sqrt(img.size)
+    assert se < 0.01 * expect
+    assert abs(img.mean() - expect) < 5 * se, (img.mean(), expect, se)
+
+
+def test_area_light_shadow_segment_and_facing(ora):
+    """The shadow ray of an area-light sample ends at the sampled point: an
+    occluder between the floor and the light blackens the image, one beyond the
+    light changes nothing (bit for bit), and a light facing away gives nothing."""
+    scene, cams, st, _ = _area_setup(0.0)
+    ref, _, _ = oracle.OracleScene(scene).render(cams, st)
+    assert ref.min() >= 0.0 and ref.max() > 0.0
+    # (asymmetric, so that the quads' diagonals stay clear of every shadow ray)
+    below = ts.axis_quad(-3.0, 3.5, -3.0, 4.0, 0.75)
+    above = ts.axis_quad(-3.0, 3.5, -3.0, 4.0, 1.5)
+    img, fl, _ = oracle.OracleScene(_area_setup(0.0, extra=[(below, 0.5)])[0]).render(cams, st)
+    assert (img == 0.0).all() and (fl == 0).all()
+    img, fl, _ = oracle.OracleScene(_area_setup(0.0, extra=[(above, 0.5)])[0]).render(cams, st)
+    assert np.array_equal(img, ref) and (fl == 0).all()
+    scene_f, _, st_f, _ = _area_setup(0.0, flip=True)
+    img, _, _ = oracle.OracleScene(scene_f).render(cams, st_f)
+    assert (img == 0.0).all()
