@@ -290,22 +290,38 @@ typedef struct {
                           values) leave the running mean of their K images.  It
                           changes nothing but that blend (graphs replay with any
                           k).  Ignored by rtq_render_backward and rtq_render_path. */
+  int32_t n_area_lights;     /* quad area lights (Section 4.1: besides an environment
+                                light the scene has 23 quad-shaped key lights),
+                                0..RTQ_MAX_AREA_LIGHTS */
+  const float* area_lights;  /* host, 10 floats per light: corner xyz, edge-1 xyz, edge-2
+                                xyz, emitted radiance Le; the light is the parallelogram
+                                corner + s e1 + t e2, s, t in [0, 1), emitting from the
+                                side e1 x e2 faces, and is not seen by camera or bounce
+                                rays.  With n > 0 lights, each hit's next-event estimate
+                                picks one of the n + 1 lights (the directional one
+                                included) with equal probability, weighted by n + 1; an
+                                area light is sampled uniformly over its area and its
+                                shadow ray ends at the sampled point.  Copied to the
+                                device during the call. */
 } rtq_render_opts;
+
+#define RTQ_MAX_AREA_LIGHTS 64
 
 /*
  * Path-trace n_cams pinhole views (Section 5.4: progressive 1 spp frames; here
  * spp samples per call, frames averaged with opts.accumulate) with a
  * Lambertian BSDF (albedo per face, or a texel of the face's texture when the
- * scene has textures), next-event estimation toward one directional light,
- * and a constant sky.  depth counts closest-hit rays per path including the
+ * scene has textures), next-event estimation toward one directional light
+ * (and optional quad area lights, opts.area_lights), and a constant sky.  depth counts closest-hit rays per path including the
  * camera ray.  `images` is a packed FP32 device buffer; view
  * c occupies [img_offset, img_offset + w h), row 0 at the top.  Each pixel is
  * the mean over its spp samples, summed in sample order, so every scheduler
  * produces bit-identical images.  cams: host memory.  Scratch memory is
  * allocated on first use and kept in the scene handle.
  * Errors: INVALID_ARG (spp < 1, depth < 1 or > 16, w or h < 1, NULL images,
- * accumulate < 0); LIMIT when the call has more than 2^31 - 1 paths (sum of
- * w h spp).
+ * accumulate < 0, area-light count outside [0, RTQ_MAX_AREA_LIGHTS], NULL or
+ * non-finite area lights); LIMIT when the call has more than 2^31 - 1 paths
+ * (sum of w h spp).
  */
 int rtq_render(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp, int32_t depth,
                const rtq_render_opts* opts, float* images, hipStream_t stream);

@@ -627,7 +627,8 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     }
     Vertex vx{face, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
     const double cl = dot(n, L);
-    // next-event estimation: with area lights, one of the nl = 1 + n_area
+    // next-event estimation (Section 4.1 names the scene's quad-shaped key
+    // lights): with area lights, one of the nl = 1 + n_area
     // lights (0: the directional light) is picked with equal probability from
     // word 0 of counter (pixel, sample, view, 2^31 + b), as an integer, and its
     // estimate is weighted by nl

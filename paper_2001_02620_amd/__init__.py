@@ -84,7 +84,8 @@ class _RenderOpts(ctypes.Structure):
                 ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32), ("counters", ctypes.c_void_p),
                 ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
                 ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p),
-                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32), ("accumulate", ctypes.c_int32),
+                ("n_area_lights", ctypes.c_int32), ("area_lights", ctypes.c_void_p)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -339,6 +340,10 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0
     o.accumulate = int(accumulate)
+    al = np.ascontiguousarray(np.asarray(getattr(settings, "area_lights", ()), dtype=np.float32).reshape(-1, 10))
+    o.n_area_lights = al.shape[0]
+    o._area_keep = al  # the library reads it during the call
+    o.area_lights = al.ctypes.data if al.shape[0] else None
     return o
 
 

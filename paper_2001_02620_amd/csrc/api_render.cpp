@@ -34,7 +34,8 @@ struct RenderScratch {
   int32_t cams_cap = 0;
   CamDev* cams = nullptr;
   float* slots = nullptr;
-  uint32_t* keys = nullptr;  // [2] RNG key of the current call
+  uint32_t* keys = nullptr;  // [3] RNG key and accumulated frames of the current call
+  float* alights = nullptr;  // RTQ_MAX_AREA_LIGHTS x 10: area lights of the current call
   PlainBuffers pb{};
   // captured calls, keyed by everything their launches bake in
   std::unordered_map<std::string, GraphEntry> graphs;
@@ -141,6 +142,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
   RALLOC(r->cams, C * sizeof(CamDev));
   RALLOC(r->slots, P * sizeof(float));
   RALLOC(r->keys, 64);
+  RALLOC(r->alights, RTQ_MAX_AREA_LIGHTS * 10 * sizeof(float));
   if (want_plain) {
     for (int k = 0; k < 2; ++k) {
       ExtQueue& q = r->pb.q[k];
@@ -163,6 +165,10 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
     RALLOC(sq.contrib, P * 4);
     RALLOC(sq.ex_rec, P * 4);
     RALLOC(sq.ex_qh, P * 4);
+    RALLOC(sq.dx, P * 4);
+    RALLOC(sq.dy, P * 4);
+    RALLOC(sq.dz, P * 4);
+    RALLOC(sq.tmax, P * 4);
     RALLOC(r->pb.hits.t, P * 4);
     RALLOC(r->pb.hits.rec, P * 4);
     RALLOC(r->pb.hits.qh, P * 4);
@@ -208,6 +214,11 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   if (!std::isfinite(L[0]) || !std::isfinite(L[1]) || !std::isfinite(L[2]) || !std::isfinite(opts->E) ||
       !std::isfinite(opts->L_sky))
     return set_error(RTQ_E_INVALID_ARG, "non-finite light parameters");
+  if (opts->n_area_lights < 0 || opts->n_area_lights > RTQ_MAX_AREA_LIGHTS)
+    return set_error(RTQ_E_INVALID_ARG, "%d area lights outside [0, %d]", opts->n_area_lights, RTQ_MAX_AREA_LIGHTS);
+  if (opts->n_area_lights > 0 && !opts->area_lights) return set_error(RTQ_E_INVALID_ARG, "NULL area lights");
+  for (int32_t k = 0; k < 10 * opts->n_area_lights; ++k)
+    if (!std::isfinite(opts->area_lights[k])) return set_error(RTQ_E_INVALID_ARG, "non-finite area light %d", k / 10);
   std::vector<CamDev> cd(n_cams);
   std::vector<std::pair<int64_t, int64_t>> ranges;
   int64_t path_base = 0, n_pixels = 0;
@@ -269,6 +280,11 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   const hipError_t e =
       hipMemcpyAsync(sc->cams, cd.data(), n_cams * sizeof(CamDev), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_error(e, "camera upload");
+  if (opts->n_area_lights > 0) {
+    const hipError_t ea = hipMemcpyAsync(sc->alights, opts->area_lights, 10 * sizeof(float) * opts->n_area_lights,
+                                         hipMemcpyHostToDevice, stream);
+    if (ea != hipSuccess) return hip_error(ea, "area light upload");
+  }
   const hipError_t ek = launch_set_keys(sc->keys, (uint32_t)(opts->seed & 0xFFFFFFFFull),
                                          (uint32_t)(opts->seed >> 32) ^ opts->frame, (uint32_t)opts->accumulate,
                                          stream);
@@ -286,6 +302,8 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   rp.L_sky = opts->L_sky;
   rp.n_paths = path_base;
   rp.slots = sc->slots;
+  rp.alights = sc->alights;
+  rp.n_alights = opts->n_area_lights;
   out->n_pixels = n_pixels;
   return RTQ_OK;
 }
@@ -296,20 +314,22 @@ namespace {
 
 // Capture (first use) or replay the launches of one render call.  The key holds
 // every value that the launches bake in: pointers, sizes, grid shapes, the
-// render constants and the scene's texture buffer; the RNG key and the
-// accumulated frame count are read from device memory, written before the
-// graph runs, so frames with other seeds replay the same graph.
+// render constants, the scene's texture buffer and the number of area lights;
+// the RNG key, the accumulated frame count and the area lights themselves are
+// read from device memory, written before the graph runs, so frames with other
+// seeds or moved lights replay the same graph.
 int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prepared& p, bool staged, float* images,
                  RenderExtras ex, hipStream_t stream) {
   char key[512];
   const RenderParams& rp = p.rp;
   std::snprintf(key, sizeof(key),
-                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p|%p %d", staged ? 1 : 0,
+                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p|%p %d|%d",
+                staged ? 1 : 0,
                 p.fmt, p.tl.persistent, p.tl.stack_depth, p.tl.block, p.tl.refill, p.tl.grid, rp.n_cams, rp.spp,
                 (long long)rp.depth, (long long)rp.n_paths, rp.lx, rp.ly, rp.lz, rp.e_over_pi, rp.L_sky,
                 (const void*)rp.cams, (const void*)rp.slots, (const void*)images, (void*)ex.counters,
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
-                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res);
+                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights);
   const std::string k(key);
   auto it = r->graphs.find(k);
   if (it == r->graphs.end()) {

@@ -107,13 +107,18 @@ __global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
 }
 
 // Load queue entry i into a lane: an extension ray (closest hit) or a shadow
-// ray toward the light (any hit), with its spawning triangle excluded.
+// ray (any hit: toward the directional light, or, in a scene with area lights,
+// along its stored direction up to its stored tmax), with its spawning triangle
+// excluded.
 template <bool ANY>
 __device__ __forceinline__ bool load_queue_ray(Lane& L, const SceneView& sc, const RenderParams& rp,
                                                const ExtQueue& eq, const ShadowQueue& sq, int64_t i) {
   bool ok;
   if (ANY) {
-    ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+    if (rp.n_alights > 0)
+      ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], sq.dx[i], sq.dy[i], sq.dz[i], 0.0f, sq.tmax[i]);
+    else
+      ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
     L.ex_rec = sq.ex_rec[i];
     L.ex_qh = sq.ex_qh[i];
     L.any = true;
@@ -123,6 +128,14 @@ __device__ __forceinline__ bool load_queue_ray(Lane& L, const SceneView& sc, con
     L.ex_qh = eq.ex_qh[i];
   }
   return ok;
+}
+
+// Optional scene features that select kernel variants: textures (closest hits
+// carry (u, v)) and area lights (shadow rays carry a direction and a tmax).
+constexpr int kFeatTex = 1;
+constexpr int kFeatArea = 2;
+static inline int scene_features(const SceneView& sc, const RenderParams& rp) {
+  return (sc.tex_res > 0 ? kFeatTex : 0) | (rp.n_alights > 0 ? kFeatArea : 0);
 }
 
 template <bool ANY>
@@ -142,12 +155,16 @@ __device__ __forceinline__ void store_queue_result(const Lane& L, const QueueHit
 }
 
 // Closest hit (ANY = false) of an extension queue, or occlusion (ANY = true) of a
-// shadow queue, one lane per entry.  TEX: the scene has textures, so closest
-// hits also store (u, v); without it the compiler drops their arithmetic from
-// the quad test.
-template <int FMT, bool ANY, bool COUNT, bool TEX>
+// shadow queue, one lane per entry.  FEAT (scene_features): with kFeatTex the
+// scene has textures, so closest hits also store (u, v); without it the
+// compiler drops their arithmetic from the quad test.  Without kFeatArea every
+// shadow ray goes to the directional light with tmax = +inf, a constant the
+// compiler folds into the traversal.
+template <int FMT, bool ANY, bool COUNT, int FEAT>
 __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq, const uint32_t* count,
                               QueueHits qh, uint8_t* occ, int depth, unsigned long long* visits) {
+  constexpr bool TEX = (FEAT & kFeatTex) != 0;
+  if (!(FEAT & kFeatArea)) rp.n_alights = 0;
   extern __shared__ uint2 lds[];
   const Stack S = make_stack(lds, depth);
   uint2 spill[kStackTotal];
@@ -170,10 +187,12 @@ __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, Shadow
 // the extension rays of bounce b + 1 halves the traversal launches of a frame
 // and with them the drain at the end of each launch; the short any-hit rays
 // come last, where the launch drains.
-template <int FMT, bool COUNT, bool TEX>
+template <int FMT, bool COUNT, int FEAT>
 __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, const uint32_t* count_ext,
                                     ShadowQueue sq, const uint32_t* count_sh, QueueHits qh, uint8_t* occ, int depth,
                                     int refill, unsigned long long* counter, unsigned long long* visits) {
+  constexpr bool TEX = (FEAT & kFeatTex) != 0;
+  if (!(FEAT & kFeatArea)) rp.n_alights = 0;
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth);
@@ -240,6 +259,7 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
   bool want_shadow = false, want_next = false;
   float contrib = 0.0f, beta_next = 0.0f, ndx = 0.0f, ndy = 0.0f, ndz = 0.0f;
   Shade s{};
+  NeeSample ns{false, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   uint32_t pid = 0u, rec = kEmpty, qhv = kEmpty;
   if (live) {
     pid = in.pid[i];
@@ -253,14 +273,16 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
       const bool tex = sc.tex_res > 0;
       s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31, tex ? qh.u[i] : 0.0f,
                     tex ? qh.v[i] : 0.0f);
-      if (s.cosl > 0.0f) {
+      const bool next = b < rp.depth - 1;
+      int view = 0;
+      uint32_t pixel = 0u, sample = 0u;
+      if (next || rp.n_alights > 0) path_coords(rp, (int64_t)pid, &view, &pixel, &sample);
+      ns = nee_sample(rp, s, pixel, sample, view, b);
+      if (ns.want) {
         want_shadow = true;
-        contrib = nee_term(beta, s.a, s.cosl, rp);
+        contrib = nee_contrib(beta, s, ns, rp);
       }
-      if (b < rp.depth - 1) {
-        int view;
-        uint32_t pixel, sample;
-        path_coords(rp, (int64_t)pid, &view, &pixel, &sample);
+      if (next) {
         bounce_dir(rp, pixel, sample, view, b, s, &ndx, &ndy, &ndz);
         beta_next = beta * s.a;
         want_next = true;
@@ -277,6 +299,12 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     sq.contrib[js] = contrib;
     sq.ex_rec[js] = rec;
     sq.ex_qh[js] = qhv;
+    if (rp.n_alights > 0) {
+      sq.dx[js] = ns.dx;
+      sq.dy[js] = ns.dy;
+      sq.dz[js] = ns.dz;
+      sq.tmax[js] = ns.tmax;
+    }
   }
   if (want_next) {
     out.ox[jn] = s.px;
@@ -374,10 +402,12 @@ struct PathLane {
 
 // At least four resident waves per SIMD (up to 128 registers per lane: the path
 // state comes on top of the traversal state).
-template <int FMT, bool TS, bool COUNT, bool TEX>
+template <int FMT, bool TS, bool COUNT, int FEAT>
 __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(SceneView sc, RenderParams rp, int depth_lds, int refill,
                                     unsigned long long* counter, unsigned long long* counters,
                                     unsigned long long* view_done, unsigned long long* visits) {
+  constexpr bool TEX = (FEAT & kFeatTex) != 0;
+  if (!(FEAT & kFeatArea)) rp.n_alights = 0;
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth_lds);
@@ -447,19 +477,20 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                 const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31,
                                           TEX ? L.b_u : 0.0f, TEX ? L.b_v : 0.0f);
                 P.have_next = P.b < rp.depth - 1;
+                int view = 0;
+                uint32_t pixel = 0u, sample = 0u;
+                if (P.have_next || rp.n_alights > 0) path_coords(rp, (int64_t)P.pid, &view, &pixel, &sample);
                 if (P.have_next) {
-                  int view;
-                  uint32_t pixel, sample;
-                  path_coords(rp, (int64_t)P.pid, &view, &pixel, &sample);
                   bounce_dir(rp, pixel, sample, view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
                   P.beta_next = P.beta * s.a;
                 }
                 L.ex_rec = hrec;
                 L.ex_qh = hqh;
-                if (s.cosl > 0.0f) {
-                  P.pending = nee_term(P.beta, s.a, s.cosl, rp);
+                const NeeSample ns = nee_sample(rp, s, pixel, sample, view, P.b);
+                if (ns.want) {
+                  P.pending = nee_contrib(P.beta, s, ns, rp);
                   P.shadow = true;
-                  lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
+                  lane_init(L, sc, s.px, s.py, s.pz, ns.dx, ns.dy, ns.dz, 0.0f, ns.tmax);
                   L.any = true;
                   ++n_sh;
                 } else if (P.have_next) {
@@ -558,12 +589,13 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     const uint32_t hqh = L.b_qh;
     const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     int shadow = -1;
-    if (sh.cosl > 0.0f) {
-      const float pending = nee_term(beta, sh.a, sh.cosl, rp);
+    const NeeSample ns = nee_sample(rp, sh, pixel, sample, view, b);
+    if (ns.want) {
+      const float pending = nee_contrib(beta, sh, ns, rp);
       Lane Ls;
       Ls.ex_rec = L.b_rec;
       Ls.ex_qh = hqh;
-      if (lane_init(Ls, sc, sh.px, sh.py, sh.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF)) {
+      if (lane_init(Ls, sc, sh.px, sh.py, sh.pz, ns.dx, ns.dy, ns.dz, 0.0f, ns.tmax)) {
         Ls.any = true;
         while (!lane_step<FMT, false>(Ls, sc, S, spill, vc)) {
         }
@@ -644,15 +676,16 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     const uint32_t hrec = L.b_rec, hqh = L.b_qh;
     const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     float c = 0.0f;
-    if (s.cosl > 0.0f) {
+    const NeeSample ns = nee_sample(rp, s, pixel, sample, view, b);
+    if (ns.want) {
       L.ex_rec = hrec;
       L.ex_qh = hqh;
-      if (lane_init(L, sc, s.px, s.py, s.pz, rp.lx, rp.ly, rp.lz, 0.0f, kInfF)) {
+      if (lane_init(L, sc, s.px, s.py, s.pz, ns.dx, ns.dy, ns.dz, 0.0f, ns.tmax)) {
         L.any = true;
         while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
         }
       }
-      if (L.b_rec == kEmpty) c = nee_factor(s.cosl, rp);
+      if (L.b_rec == kEmpty) c = ns.c;
     }
     face[K] = s.face;
     betak[K] = beta;
@@ -694,11 +727,12 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
   uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
   unsigned long long* vis_sh = ex.visits ? ex.visits + 4 : nullptr;
   hipEvent_t ev = stage_begin(ex.log, s);
-  if (sc.tex_res > 0)
-    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT, true>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
-                       cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
+  const int feat = scene_features(sc, rp);
+  if (feat & kFeatTex)
+    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT, kFeatTex>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin,
+                       pb.sq, cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
   else
-    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT, false>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
+    hipLaunchKernelGGL((k_trace_queue<FMT, false, COUNT, 0>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq,
                        cin, pb.hits, pb.occ, tl.stack_depth, ex.visits);
   stage_end(ex.log, 0, ev, s);
   ev = stage_begin(ex.log, s);
@@ -706,8 +740,12 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
                      ex.dump, ex.dump_cap, ex.dump_count);
   stage_end(ex.log, 2, ev, s);
   ev = stage_begin(ex.log, s);
-  hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT, false>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, csq,
-                     pb.hits, pb.occ, tl.stack_depth, vis_sh);
+  if (feat & kFeatArea)
+    hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT, kFeatArea>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin,
+                       pb.sq, csq, pb.hits, pb.occ, tl.stack_depth, vis_sh);
+  else
+    hipLaunchKernelGGL((k_trace_queue<FMT, true, COUNT, 0>), dim3(gt), dim3(tl.block), lds, s, sc, rp, qin, pb.sq, csq,
+                       pb.hits, pb.occ, tl.stack_depth, vis_sh);
   stage_end(ex.log, 1, ev, s);
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
@@ -721,12 +759,16 @@ static void mixed_launch(const SceneView& sc, const RenderParams& rp, const Plai
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   hipEvent_t ev = stage_begin(ex.log, s);
   unsigned long long* work = pb.work + (size_t)slot * kClaimWords;
-  if (sc.tex_res > 0)
-    hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq,
-                       cext, pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, work, ex.visits);
-  else
-    hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq,
-                       cext, pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, work, ex.visits);
+#define RTQ_MIXED(F)                                                                                             \
+  hipLaunchKernelGGL((k_trace_queue_mixed<FMT, COUNT, F>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, eq, cext, \
+                     pb.sq, csh, pb.hits, pb.occ, tl.stack_depth, tl.refill, work, ex.visits)
+  switch (scene_features(sc, rp)) {
+    case 0: RTQ_MIXED(0); break;
+    case kFeatTex: RTQ_MIXED(kFeatTex); break;
+    case kFeatArea: RTQ_MIXED(kFeatArea); break;
+    default: RTQ_MIXED(kFeatTex | kFeatArea); break;
+  }
+#undef RTQ_MIXED
   stage_end(ex.log, 0, ev, s);
 }
 
@@ -799,12 +841,16 @@ template <int FMT, bool TS, bool COUNT>
 static void persistent_launch(const SceneView& sc, const RenderParams& rp, const TraceLaunch& tl,
                               const RenderExtras& ex, hipStream_t s) {
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
-  if (sc.tex_res > 0)
-    hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT, true>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                       tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
-  else
-    hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT, false>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp,
-                       tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits);
+#define RTQ_MEGA(F)                                                                                        \
+  hipLaunchKernelGGL((k_render_persistent<FMT, TS, COUNT, F>), dim3(tl.grid), dim3(tl.block), lds, s, sc, rp, \
+                     tl.stack_depth, tl.refill, tl.counter, ex.counters, ex.view_done, ex.visits)
+  switch (scene_features(sc, rp)) {
+    case 0: RTQ_MEGA(0); break;
+    case kFeatTex: RTQ_MEGA(kFeatTex); break;
+    case kFeatArea: RTQ_MEGA(kFeatArea); break;
+    default: RTQ_MEGA(kFeatTex | kFeatArea); break;
+  }
+#undef RTQ_MEGA
 }
 
 hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp, int fmt, const TraceLaunch& tl,

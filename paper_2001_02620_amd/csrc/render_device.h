@@ -36,6 +36,8 @@ struct RenderParams {
   float L_sky;
   int64_t n_paths;
   float* slots;         // per-path radiance
+  const float* alights; // quad area lights, 10 floats each: corner, edge 1, edge 2, radiance
+  int32_t n_alights;
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011): ten rounds of two 32x32->64
@@ -164,6 +166,62 @@ __device__ __forceinline__ float nee_term(float beta, float a, float cosl, const
 }
 // The factor c = (E / pi) cos_L that multiplies beta * a (used by the adjoint).
 __device__ __forceinline__ float nee_factor(float cosl, const RenderParams& rp) { return rp.e_over_pi * cosl; }
+
+// The shadow ray of one next-event estimate and the factor c that multiplies
+// beta * a when it is unoccluded.
+struct NeeSample {
+  bool want;           // a shadow ray is traced
+  float dx, dy, dz;    // its direction (toward the directional light, or to the sampled point)
+  float tmax;          // +inf, or 1 for an area-light sample (the ray ends at the point)
+  float c;
+};
+
+// Next-event estimate at hit s of path (pixel, sample, view), bounce b.
+// Without area lights: the directional light, c = (E / pi) cos_L.  With n area
+// lights one of the nl = n + 1 lights is picked with equal probability (light
+// 0 is the directional one) from word 0 of counter (pixel, sample, view,
+// 2^31 + b), in integer arithmetic, and weighted by nl.  Area light j is the
+// parallelogram x = c + s e1 + t e2, (s, t) uniform from words 1 and 2, emitting
+// radiance Le from the side e1 x e2 faces: c = nl Le A cos_p cos_l / (pi d^2)
+// for the sampled point at distance d, A = |e1 x e2|.
+__device__ __forceinline__ NeeSample nee_sample(const RenderParams& rp, const Shade& s, uint32_t pixel,
+                                                uint32_t sample, int view, int b) {
+  NeeSample r{s.cosl > 0.0f, rp.lx, rp.ly, rp.lz, kInfF, nee_factor(s.cosl, rp)};
+  if (rp.n_alights == 0) return r;
+  const uint4 w = philox4x32_10(make_uint4(pixel, sample, (uint32_t)view, 0x80000000u | (uint32_t)b), rp.keys[0],
+                                rp.keys[1]);
+  const uint32_t nl = (uint32_t)rp.n_alights + 1u;
+  const uint32_t j = (uint32_t)(((uint64_t)(w.x >> 8) * nl) >> 24);
+  if (j == 0u) {
+    r.c = (float)nl * r.c;
+    return r;
+  }
+  const float* q = rp.alights + 10 * (j - 1u);
+  const float su = u01(w.y), sv = u01(w.z);
+  const float wx = q[0] + su * q[3] + sv * q[6] - s.px;
+  const float wy = q[1] + su * q[4] + sv * q[7] - s.py;
+  const float wz = q[2] + su * q[5] + sv * q[8] - s.pz;
+  const float d2 = wx * wx + wy * wy + wz * wz;
+  const float inv_d = 1.0f / sqrtf(d2);
+  const float nx = q[4] * q[8] - q[5] * q[7], ny = q[5] * q[6] - q[3] * q[8], nz = q[3] * q[7] - q[4] * q[6];
+  const float A = sqrtf(nx * nx + ny * ny + nz * nz);
+  const float cp = (s.nx * wx + s.ny * wy + s.nz * wz) * inv_d;
+  const float cq = -(nx * wx + ny * wy + nz * wz) * inv_d / A;
+  r.want = cp > 0.0f && cq > 0.0f;
+  r.dx = wx;
+  r.dy = wy;
+  r.dz = wz;
+  r.tmax = 1.0f;
+  r.c = (float)nl * (q[9] * A * cp * cq / (3.14159265358979323846f * d2));
+  return r;
+}
+
+// beta * a * c, in the directional light's own rounding order when the scene
+// has no area lights.
+__device__ __forceinline__ float nee_contrib(float beta, const Shade& s, const NeeSample& ns,
+                                             const RenderParams& rp) {
+  return rp.n_alights == 0 ? nee_term(beta, s.a, s.cosl, rp) : beta * (s.a * ns.c);
+}
 
 // Cosine-distributed direction about n from (u1, u2): local
 // (sqrt(u1) cos 2 pi u2, sqrt(u1) sin 2 pi u2, sqrt(1 - u1)) in the orthonormal

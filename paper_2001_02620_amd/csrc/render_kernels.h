@@ -25,6 +25,7 @@ struct ShadowQueue {
   uint32_t* pid;
   float* contrib;
   uint32_t *ex_rec, *ex_qh;
+  float *dx, *dy, *dz, *tmax;  // written only for a scene with area lights
 };
 
 // Closest hits of an extension queue (internal form).

@@ -397,8 +397,14 @@ def _grad_setup(seed=31, res=12, spp=2, depth=3):
     return scene, cams, st
 
 
-def test_gradient_prb_forward_mode_and_fd_agree(ora):
+AREA_LIGHTS = ((-1.5, -1.5, 4.0, 0.0, 3.0, 0.0, 3.0, 0.0, 0.0, 2.0),
+               (3.0, -1.0, -1.0, 0.0, 0.0, 2.0, 0.0, 2.0, 0.0, 1.5))
+
+
+@pytest.mark.parametrize("lights", [(), AREA_LIGHTS])
+def test_gradient_prb_forward_mode_and_fd_agree(ora, lights):
     scene, cams, st = _grad_setup()
+    st.area_lights = lights
     o = oracle.OracleScene(scene)
     rng = np.random.default_rng(2)
     alb = scene.albedo.astype(np.float64)
@@ -530,7 +536,7 @@ def test_textured_floor_closed_form(ora, rot):
         assert not np.array_equal(img2.reshape(res, res), img)
 
 
-# ------------------------------------------------------------ area lights (5.4)
+# ---------------------------------------------------------- area lights (4.1)
 def _area_setup(E, half=0.4, h=1.0, extra=None, flip=False):
     a_f = float(np.float32(0.5))
     scene = ts.floor_scene(albedo=a_f, half=50.0, extra=extra)
