@@ -22,6 +22,8 @@ Reported (one JSON line):
   graph_replay         the headline path replayed from a captured HIP graph;
   textured             the headline path with per-face 4x4 textures in place
                        of per-face albedo (equal images in both paths checked);
+  area_lights          the headline path with four quad area lights besides
+                       the sun (equal images in both paths checked);
   incoherent           closest-hit throughput on the frame's bounce >= 1 rays,
                        quantized-persistent vs FP32-plain, at bit-identical hits;
   roofline             the frame's dominant kernel (the traversal launches, each
@@ -226,6 +228,20 @@ def main():
     textured = dict(tex_res=tex_res, ms_per_frame=t["wall_ms"], mrays_s=t["rays"] / (t["wall_ms"] * 1e3))
     log(f"textured: {textured}")
 
+    # ---- the same frame with four 100 m x 100 m area lights 400 m above the
+    # terrain (besides the sun): one of the five lights sampled per hit
+    st.area_lights = tuple((cx - 50.0, cy - 50.0, 400.0, 0.0, 100.0, 0.0, 100.0, 0.0, 0.0, 16.0)
+                           for cx in (-400.0, 400.0) for cy in (-400.0, 400.0))
+    frame(0, **F32)
+    a = img.clone()
+    frame(0, **Q8P)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), img.view(torch.int32)), "area-light images differ between the two paths"
+    t = timed(Q8P, max(3, args.steps // 2), 1)
+    st.area_lights = ()
+    area = dict(n_lights=4, ms_per_frame=t["wall_ms"], mrays_s=t["rays"] / (t["wall_ms"] * 1e3))
+    log(f"area lights: {area}")
+
     # ---- incoherent rays: bounce >= 1 extension rays of frame 0
     log("incoherent rays: dumping bounce >= 1 rays")
     cap = args.incoherent_rays
@@ -347,6 +363,7 @@ def main():
         "ablation": {k: {kk: round(vv, 3) for kk, vv in d.items()} for k, d in ablation.items()},
         "graph_replay": {k: round(v, 3) for k, v in graph_replay.items()},
         "textured": {k: round(v, 3) if isinstance(v, float) else v for k, v in textured.items()},
+        "area_lights": {k: round(v, 3) if isinstance(v, float) else v for k, v in area.items()},
         "stages_ms_per_frame": {("traversal" if k == "closest" else k): round(d["ms"] / args.steps, 3)
                                 for k, d in q8["stages"].items() if k != "shadow"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
