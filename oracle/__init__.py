@@ -58,6 +58,7 @@ def lib():
         L.orc_scene_destroy.argtypes = [P]
         L.orc_scene_set_albedo.argtypes = [P, P]
         L.orc_scene_set_textures.argtypes = [P, P, i32]
+        L.orc_scene_set_environment.argtypes = [P, P, i32, i32]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         L.orc_philox.argtypes = [P, P, P]
@@ -152,6 +153,17 @@ class OracleScene:
         assert lib().orc_scene_set_textures(self.h, _p(t), int(t.shape[1])) == 0
         self._tex = t
         self.tex_res = int(t.shape[1])
+
+    def set_environment(self, texels: Optional[np.ndarray]) -> None:
+        """Environment map [h, w] (row 0 around +z; FP32 values read exactly)
+        seen by escaping rays in place of the constant sky, or None."""
+        if texels is None:
+            assert lib().orc_scene_set_environment(self.h, None, 0, 0) == 0
+            return
+        t = np.ascontiguousarray(np.asarray(texels, dtype=np.float32), dtype=np.float64)
+        assert t.ndim == 2 and t.shape[0] >= 1 and t.shape[1] >= 1
+        assert lib().orc_scene_set_environment(self.h, _p(t), int(t.shape[1]), int(t.shape[0])) == 0
+        self._env = t
 
     def trace(self, rays: np.ndarray, excl: Optional[np.ndarray] = None, r0: Optional[np.ndarray] = None,
               brute: bool = False, any_hit: bool = False) -> Hits:

@@ -150,6 +150,9 @@ struct Scene {
   // optional per-face textures: res x res values per unique quad, row v, column u
   std::vector<double> tex;
   int32_t tex_res = 0;
+  // optional environment map: env_w x env_h radiance values, equirectangular
+  std::vector<double> env;
+  int32_t env_w = 0, env_h = 0;
   int64_t N = 0;
   std::vector<int32_t> iproto;
   std::vector<double> X;           // 12 per instance: row-major [A | t] (FP32 values)
@@ -569,9 +572,33 @@ struct PathRec {
   int nv = 0;
   Vertex v[64];
   bool escaped = false;
+  double L_esc = 0.0;  // radiance seen by the escaping ray (sky or environment map)
   uint32_t flags = 0;
   int n_closest = 0, n_shadow = 0, n_incoherent = 0;
 };
+
+// Radiance of the environment toward direction d (Section 4.1 names the
+// scene's textured environment light): an equirectangular map of env_w x env_h
+// texels with u = (atan2(d_y, d_x) + pi) / (2 pi) along a row and
+// v = acos(d_z) / pi down the rows (row 0 around +z), read at the nearest texel.
+// Which texel a direction next to a texel boundary falls in depends on
+// rounding: flag directions whose angular distance to a boundary, times
+// sin(theta), is below 1e-5, and directions within 1e-3 of a pole.
+double env_radiance(const Scene& S, V3 d, uint32_t* flags) {
+  d = normalize(d);
+  const double th = std::acos(std::min(1.0, std::max(-1.0, d.z)));
+  const double st = std::sin(th);
+  const double u = (std::atan2(d.y, d.x) + kPi) / (2.0 * kPi), v = th / kPi;
+  const int W = S.env_w, H = S.env_h;
+  const double gu = u * W, gv = v * H;
+  const double du = std::fabs(gu - std::round(gu)) * (2.0 * kPi / W) * st;
+  const double kv = std::round(gv);
+  const double dv = (kv >= 1 && kv <= H - 1) ? std::fabs(gv - kv) * (kPi / H) * st : 1.0;
+  if (du < 1e-5 || dv < 1e-5 || st < 1e-3) *flags |= F_SHADE;
+  const int tx = std::min(std::max((int)std::floor(gu), 0), W - 1);
+  const int ty = std::min(std::max((int)std::floor(gv), 0), H - 1);
+  return S.env[(size_t)ty * W + tx];
+}
 
 void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, int64_t pix, int32_t sample,
                 int mode, PathRec& rec) {
@@ -593,6 +620,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     rec.flags |= h.flags & ~(uint32_t)F_T_ILLCOND;
     if (h.best.inst < 0) {
       rec.escaped = true;
+      rec.L_esc = S.env_w > 0 ? env_radiance(S, ray.d, &rec.flags) : P.L_sky;
       return;
     }
     V3 wq[4];
@@ -712,7 +740,7 @@ double path_value(const Params& P, const PathRec& rec) {
     L += beta * rec.v[k].a * rec.v[k].c;
     beta *= rec.v[k].a;
   }
-  if (rec.escaped) L += beta * P.L_sky;
+  if (rec.escaped) L += beta * rec.L_esc;
   return L;
 }
 
@@ -844,6 +872,19 @@ int orc_scene_set_textures(void* s, const double* texels, int32_t res) {
   S->tex_res = res;
   S->tex.clear();
   if (res > 0) S->tex.assign(texels, texels + S->albedo.size() * (size_t)res * (size_t)res);
+  return 0;
+}
+
+// Environment map (the scene's textured environment light, Section 4.1):
+// w x h radiance values, row-major, row 0 around +z; w = 0 removes it and
+// escaping rays see the constant sky again.
+int orc_scene_set_environment(void* s, const double* texels, int32_t w, int32_t h) {
+  Scene* S = static_cast<Scene*>(s);
+  if (w < 0 || h < 0 || (w > 0 && (h < 1 || !texels))) return -1;
+  S->env_w = w > 0 ? w : 0;
+  S->env_h = w > 0 ? h : 0;
+  S->env.clear();
+  if (w > 0) S->env.assign(texels, texels + (size_t)w * (size_t)h);
   return 0;
 }
 
@@ -1006,7 +1047,7 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
         // D_k = beta_k a_k c_k; S_k = sum_{j>=k} D_j + M.  Accumulate S_k / a_k.
         std::vector<double> beta(rec.nv + 1, 1.0);
         for (int k = 0; k < rec.nv; ++k) beta[k + 1] = beta[k] * rec.v[k].a;
-        double tail = rec.escaped ? beta[rec.nv] * P.L_sky : 0.0;
+        double tail = rec.escaped ? beta[rec.nv] * rec.L_esc : 0.0;
         for (int k = rec.nv - 1; k >= 0; --k) {
           tail += beta[k] * rec.v[k].a * rec.v[k].c;  // now tail = S_k
           gacc[tid][rec.v[k].face] += gpix[i] * tail / rec.v[k].a / P.spp;
@@ -1024,8 +1065,8 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
           beta = nb;
         }
         if (rec.escaped) {
-          L += beta * P.L_sky;
-          dL += dbeta * P.L_sky;
+          L += beta * rec.L_esc;
+          dL += dbeta * rec.L_esc;
         }
         dsum += dL;
       }

@@ -585,3 +585,54 @@ def test_area_light_shadow_segment_and_facing(ora):
     scene_f, _, st_f, _ = _area_setup(0.0, flip=True)
     img, _, _ = oracle.OracleScene(scene_f).render(cams, st_f)
     assert (img == 0.0).all()
+
+
+# ------------------------------------------------------ environment map (4.1)
+def test_environment_constant_map_is_the_sky(ora):
+    scene = sg.tiny_scene(4, n_inst=4, n_protos=2, nq=4, spread=1.0)
+    cams = [sg.Camera((0.5, -6.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 70.0, 20, 16)]
+    st = sg.RenderSettings(spp=2, depth=3, seed=21)
+    o = oracle.OracleScene(scene)
+    ref, _, _ = o.render(cams, st)
+    o.set_environment(np.full((3, 7), st.L_sky, np.float32))
+    img, _, _ = o.render(cams, st)
+    assert np.array_equal(img, ref)
+    o.set_environment(None)
+    img, _, _ = o.render(cams, st)
+    assert np.array_equal(img, ref)
+
+
+def test_environment_map_orientation(ora):
+    """Escaping camera rays read the texel of their direction: an 8 x 4 map,
+    column from the azimuth atan2(y, x) starting at -pi, row from the polar angle
+    from +z (texel indices worked out by hand for each direction)."""
+    empty = ts.multi_mesh_scene([ts.axis_quad(-1, 1, -1, 1, 0.0)], xforms=[[1, 0, 0, 0, 0, 1, 0, 500, 0, 0, 1, 0]])
+    env = (np.arange(32, dtype=np.float32) + 1.0).reshape(4, 8)
+    o = oracle.OracleScene(empty)
+    o.set_environment(env)
+    st = sg.RenderSettings(spp=2, depth=2, seed=3)
+    # direction -> (column, row)
+    cases = [((1.0, 0.2, 0.3), (4, 1)), ((-1.0, -0.2, -0.3), (0, 2)), ((0.2, 1.0, -0.3), (5, 2)),
+             ((0.05, -0.1, 1.0), (2, 0))]
+    for d, (tx, ty) in cases:
+        up = (0.0, 0.0, 1.0) if abs(d[2]) < 0.9 else (0.0, 1.0, 0.0)
+        cams = [sg.Camera((0.0, 0.0, 0.0), d, up, 0.01, 4, 4)]
+        img, fl, _ = o.render(cams, st)
+        assert (fl == 0).all()
+        assert (img == env[ty, tx]).all(), (d, img[0], env[ty, tx])
+
+
+def test_environment_floor_sees_upper_hemisphere(ora):
+    """A floor under an environment whose upper rows hold c_up and lower rows
+    c_dn, sun off: every bounce ray escapes upward, so an unflagged pixel at
+    depth 2 is exactly a c_up."""
+    a = float(np.float32(0.5))
+    c_up, c_dn = float(np.float32(0.7)), float(np.float32(3.0))
+    env = np.array([[c_up] * 6, [c_up] * 6, [c_dn] * 6, [c_dn] * 6], np.float32)
+    o = oracle.OracleScene(ts.floor_scene(albedo=a))
+    o.set_environment(env)
+    st = sg.RenderSettings(spp=4, depth=2, seed=12, E=0.0)
+    img, fl, _ = o.render(_down_camera(res=24, eye=(0.0, 0.0, 3.0), vfov=60.0), st)
+    ok = fl == 0
+    assert ok.mean() > 0.9
+    np.testing.assert_allclose(img[ok], a * c_up, rtol=1e-12)
