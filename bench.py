@@ -24,6 +24,8 @@ Reported (one JSON line):
                        of per-face albedo (equal images in both paths checked);
   area_lights          the headline path with four quad area lights besides
                        the sun (equal images in both paths checked);
+  environment          the headline path under a 2048x1024 environment map in
+                       place of the constant sky (equal images checked);
   incoherent           closest-hit throughput on the frame's bounce >= 1 rays,
                        quantized-persistent vs FP32-plain, at bit-identical hits;
   roofline             the frame's dominant kernel (the traversal launches, each
@@ -242,6 +244,18 @@ def main():
     area = dict(n_lights=4, ms_per_frame=t["wall_ms"], mrays_s=t["rays"] / (t["wall_ms"] * 1e3))
     log(f"area lights: {area}")
 
+    # ---- the same frame under a 2048 x 1024 environment map instead of the sky
+    S.set_environment(torch.rand((1024, 2048), device="cuda", generator=gen) * 0.5)
+    frame(0, **F32)
+    a = img.clone()
+    frame(0, **Q8P)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.int32), img.view(torch.int32)), "environment images differ between the two paths"
+    t = timed(Q8P, max(3, args.steps // 2), 1)
+    S.set_environment(None)
+    envmap = dict(w=2048, h=1024, ms_per_frame=t["wall_ms"], mrays_s=t["rays"] / (t["wall_ms"] * 1e3))
+    log(f"environment: {envmap}")
+
     # ---- incoherent rays: bounce >= 1 extension rays of frame 0
     log("incoherent rays: dumping bounce >= 1 rays")
     cap = args.incoherent_rays
@@ -364,6 +378,7 @@ def main():
         "graph_replay": {k: round(v, 3) for k, v in graph_replay.items()},
         "textured": {k: round(v, 3) if isinstance(v, float) else v for k, v in textured.items()},
         "area_lights": {k: round(v, 3) if isinstance(v, float) else v for k, v in area.items()},
+        "environment": {k: round(v, 3) if isinstance(v, float) else v for k, v in envmap.items()},
         "stages_ms_per_frame": {("traversal" if k == "closest" else k): round(d["ms"] / args.steps, 3)
                                 for k, d in q8["stages"].items() if k != "shadow"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -185,6 +185,25 @@ int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, h
 #define RTQ_MAX_TEX_RES 64
 int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t res, hipStream_t stream);
 
+/*
+ * Environment map (Section 4.1: the scene has a textured environment light):
+ * the radiance a path sees when its ray leaves the scene, in place of the
+ * constant sky L_sky.  An equirectangular map of w x h values: direction d
+ * (normalised) has u = (atan2(d_y, d_x) + pi) / (2 pi) along a row and
+ * v = acos(d_z) / pi down the rows (row 0 around +z), read at the nearest
+ * texel.  It is seen by camera and bounce rays only (no next-event estimate
+ * toward it).
+ *
+ * texels_dev: device memory, h rows of w floats, copied into memory the scene
+ * owns (freed by rtq_scene_destroy); w = 0 (texels_dev may be NULL) removes the
+ * map.  Waits for all work on the device, then enqueues the copy on `stream`;
+ * renders on other streams are ordered by the caller.  Errors:
+ * RTQ_E_INVALID_ARG for w or h outside [1, RTQ_MAX_ENV_SIDE] (w = 0 aside) or
+ * NULL texels; RTQ_E_HIP when the allocation or copy fails.
+ */
+#define RTQ_MAX_ENV_SIDE 16384
+int rtq_scene_set_environment(rtq_scene* scene, const float* texels_dev, int32_t w, int32_t h, hipStream_t stream);
+
 /* ------------------------------------------------------------------ tracing */
 /* Rays and hits are structure-of-arrays in device memory, one element per ray. */
 typedef struct {
@@ -312,7 +331,8 @@ typedef struct {
  * spp samples per call, frames averaged with opts.accumulate) with a
  * Lambertian BSDF (albedo per face, or a texel of the face's texture when the
  * scene has textures), next-event estimation toward one directional light
- * (and optional quad area lights, opts.area_lights), and a constant sky.  depth counts closest-hit rays per path including the
+ * (and optional quad area lights, opts.area_lights), and a constant sky (or an
+ * environment map, rtq_scene_set_environment).  depth counts closest-hit rays per path including the
  * camera ray.  `images` is a packed FP32 device buffer; view
  * c occupies [img_offset, img_offset + w h), row 0 at the top.  Each pixel is
  * the mean over its spp samples, summed in sample order, so every scheduler

@@ -94,7 +94,7 @@ _lib = None
 EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destroy", "rtq_scene_get_info",
            "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
            "rtq_render_backward", "rtq_render_timing", "rtq_render_path", "rtq_host_bvh_build", "rtq_host_bvh_get",
-           "rtq_host_bvh_destroy", "rtq_scene_set_textures"]
+           "rtq_host_bvh_destroy", "rtq_scene_set_textures", "rtq_scene_set_environment"]
 
 
 def load_library():
@@ -117,6 +117,7 @@ def load_library():
     L.rtq_scene_get_info.argtypes = [P, P]
     L.rtq_scene_set_albedo.argtypes = [P, P, ctypes.c_int64, P]
     L.rtq_scene_set_textures.argtypes = [P, P, ctypes.c_int32, P]
+    L.rtq_scene_set_environment.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P]
     L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
@@ -223,6 +224,19 @@ class Scene:
         t = texels.contiguous().float()
         _check(load_library().rtq_scene_set_textures(self.handle, t.data_ptr(), int(t.shape[1]), _stream()))
         self._tex_keep = t
+
+    def set_environment(self, texels) -> None:
+        """Environment map seen by escaping rays: a device tensor [h, w] (row 0
+        around +z, columns from azimuth -pi), or None for the constant sky."""
+        if texels is None:
+            _check(load_library().rtq_scene_set_environment(self.handle, None, 0, 0, _stream()))
+            self._env_keep = None
+            return
+        assert texels.is_cuda and texels.dim() == 2
+        t = texels.contiguous().float()
+        _check(load_library().rtq_scene_set_environment(self.handle, t.data_ptr(), int(t.shape[1]), int(t.shape[0]),
+                                                        _stream()))
+        self._env_keep = t
 
     def close(self):
         if getattr(self, "_h", None):

@@ -70,6 +70,9 @@ SceneView scene_view(const rtq_scene* s, int fmt) {
   v.albedo = s->albedo;
   v.tex = s->tex;
   v.tex_res = s->tex_res;
+  v.env = s->env;
+  v.env_w = s->env_w;
+  v.env_h = s->env_h;
   v.pad_rel = s->pad_rel;
   v.n_rec = (uint32_t)s->n_rec;
   return v;
@@ -519,6 +522,7 @@ void rtq_scene_destroy(rtq_scene* s) {
   release_render_scratch(s);
   s->bufs.release();
   if (s->tex) (void)hipFree(s->tex);
+  if (s->env) (void)hipFree(s->env);
   delete s;
 }
 
@@ -533,7 +537,7 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->tlas_depth = s->tlas_depth;
   info->blas_depth_max = s->blas_depth;
   info->formats = s->formats;
-  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes);
+  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes + s->env_bytes);
   info->build_seconds = s->build_seconds;
   info->n_top_entries = s->n_rec;
   for (int k = 0; k < 4; ++k) info->build_phase_seconds[k] = s->build_phase[k];
@@ -576,6 +580,35 @@ int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, h
   e = hipMemcpyAsync(s->tex, texels_dev, bytes, hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync");
   s->tex_res = res;
+  return RTQ_OK;
+}
+
+int rtq_scene_set_environment(rtq_scene* s, const float* texels_dev, int32_t w, int32_t h, hipStream_t stream) {
+  if (!s) return set_error(RTQ_E_INVALID_ARG, "NULL scene");
+  if (w < 0 || w > RTQ_MAX_ENV_SIDE || (w > 0 && (h < 1 || h > RTQ_MAX_ENV_SIDE)))
+    return set_error(RTQ_E_INVALID_ARG, "environment map %d x %d outside [1, %d]^2", w, h, RTQ_MAX_ENV_SIDE);
+  if (w > 0 && !texels_dev) return set_error(RTQ_E_INVALID_ARG, "NULL environment texels");
+  hipError_t e = hipSetDevice(s->device);
+  if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+  // renders already queued may still read the old map
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
+  const size_t bytes = w > 0 ? (size_t)w * (size_t)h * sizeof(float) : 0;
+  if (s->env) (void)hipFree(s->env);
+  s->env = nullptr;
+  s->env_w = s->env_h = 0;
+  s->env_bytes = 0;
+  if (w == 0) return RTQ_OK;
+  e = hipMalloc(reinterpret_cast<void**>(&s->env), bytes);
+  if (e != hipSuccess) {
+    s->env = nullptr;
+    return hip_error(e, "environment allocation");
+  }
+  s->env_bytes = bytes;
+  e = hipMemcpyAsync(s->env, texels_dev, bytes, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync");
+  s->env_w = w;
+  s->env_h = h;
   return RTQ_OK;
 }
 

@@ -60,6 +60,9 @@ struct rtq_scene {
   float* tex = nullptr;  // per-face textures (own allocation, rtq_scene_set_textures)
   int32_t tex_res = 0;
   size_t tex_bytes = 0;
+  float* env = nullptr;  // environment map (own allocation, rtq_scene_set_environment)
+  int32_t env_w = 0, env_h = 0;
+  size_t env_bytes = 0;
   unsigned long long* counters = nullptr;  // ring of persistent-kernel work counters
   mutable std::atomic<uint32_t> counter_next{0};
   rtq::DeviceBuffers bufs;

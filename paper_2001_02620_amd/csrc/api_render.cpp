@@ -314,7 +314,8 @@ namespace {
 
 // Capture (first use) or replay the launches of one render call.  The key holds
 // every value that the launches bake in: pointers, sizes, grid shapes, the
-// render constants, the scene's texture buffer and the number of area lights;
+// render constants, the scene's texture and environment buffers and the number
+// of area lights;
 // the RNG key, the accumulated frame count and the area lights themselves are
 // read from device memory, written before the graph runs, so frames with other
 // seeds or moved lights replay the same graph.
@@ -323,13 +324,14 @@ int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prep
   char key[512];
   const RenderParams& rp = p.rp;
   std::snprintf(key, sizeof(key),
-                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p|%p %d|%d",
+                "%d|%d|%d %d %d %d|%d %d %d|%lld %lld|%a %a %a %a %a|%p %p %p|%p %p %p %lld %p %p %p|%p|%p %d|%d|%p %d %d",
                 staged ? 1 : 0,
                 p.fmt, p.tl.persistent, p.tl.stack_depth, p.tl.block, p.tl.refill, p.tl.grid, rp.n_cams, rp.spp,
                 (long long)rp.depth, (long long)rp.n_paths, rp.lx, rp.ly, rp.lz, rp.e_over_pi, rp.L_sky,
                 (const void*)rp.cams, (const void*)rp.slots, (const void*)images, (void*)ex.counters,
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
-                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights);
+                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights,
+                (const void*)sv.env, (int)sv.env_w, (int)sv.env_h);
   const std::string k(key);
   auto it = r->graphs.find(k);
   if (it == r->graphs.end()) {

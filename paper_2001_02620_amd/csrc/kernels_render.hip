@@ -266,7 +266,7 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     const float beta = in.beta[i];
     rec = qh.rec[i];
     if (rec == kEmpty) {
-      rp.slots[pid] += beta * rp.L_sky;  // escaped: constant sky
+      rp.slots[pid] += beta * escape_radiance(sc, rp, in.dx[i], in.dy[i], in.dz[i]);  // escaped: sky
     } else {
       qhv = qh.qh[i];
       const Ray3 r{in.ox[i], in.oy[i], in.oz[i], in.dx[i], in.dy[i], in.dz[i]};
@@ -469,7 +469,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
             bool path_done = false;
             if (!P.shadow) {
               if (L.b_rec == kEmpty) {
-                P.radiance += P.beta * rp.L_sky;
+                P.radiance += P.beta * escape_radiance(sc, rp, L.wdx, L.wdy, L.wdz);
                 path_done = true;
               } else {
                 const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
@@ -582,7 +582,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
       while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
       }
     if (L.b_rec == kEmpty) {
-      radiance += beta * rp.L_sky;
+      radiance += beta * escape_radiance(sc, rp, r.dx, r.dy, r.dz);
       escaped = 1;
       break;
     }
@@ -640,7 +640,8 @@ __global__ void k_start_tick(unsigned long long* t) {
 // ---------------------------------------------------------------- adjoint
 // One lane per path: replay the path from its RNG counters with the same device
 // functions (identical hits), keep per vertex the face, beta_k and the NEE factor
-// c_k = (E / pi) cos_L V_k, then walk back: with V_K = L_sky if the path escaped
+// c_k = (E / pi) cos_L V_k, then walk back: with V_K the sky (or environment)
+// radiance of the escaping ray if the path escaped
 // (else 0) and V_k = a_k (c_k + V_{k+1}), the derivative of the path value with
 // respect to the albedo at vertex k is beta_k (c_k + V_{k+1}).
 template <int FMT>
@@ -700,7 +701,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     L.ex_rec = hrec;
     L.ex_qh = hqh;
   }
-  float V = escaped ? rp.L_sky : 0.0f;
+  float V = escaped ? escape_radiance(sc, rp, r.dx, r.dy, r.dz) : 0.0f;
   for (int k = K - 1; k >= 0; --k) {
     const float cv = ck[k] + V;
     unsafeAtomicAdd(&grad_albedo[face[k]], g * (betak[k] * cv));

@@ -160,6 +160,23 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   return s;
 }
 
+// Radiance seen by a ray leaving the scene along d: the constant sky, or the
+// nearest texel of the environment map (Section 4.1 names the scene's textured
+// environment light), an equirectangular map with u = (atan2(d_y, d_x) + pi) /
+// (2 pi) along a row and v = acos(d_z) / pi down the rows (row 0 around +z).
+__device__ __forceinline__ float escape_radiance(const SceneView& sc, const RenderParams& rp, float dx, float dy,
+                                                 float dz) {
+  if (sc.env_w == 0) return rp.L_sky;
+  const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  const float z = fminf(fmaxf(dz * inv, -1.0f), 1.0f);
+  const float u = (atan2f(dy, dx) + 3.14159265358979323846f) / 6.28318530717958647692f;
+  const float v = acosf(z) / 3.14159265358979323846f;
+  // clamped in float first, so the index stays in range for any direction
+  const int tx = (int)fminf(fmaxf(u * (float)sc.env_w, 0.0f), (float)(sc.env_w - 1));
+  const int ty = (int)fminf(fmaxf(v * (float)sc.env_h, 0.0f), (float)(sc.env_h - 1));
+  return sc.env[(size_t)ty * sc.env_w + tx];
+}
+
 // Next-event contribution of a visible light: beta * (a / pi) * E * cos_L.
 __device__ __forceinline__ float nee_term(float beta, float a, float cosl, const RenderParams& rp) {
   return beta * (a * rp.e_over_pi * cosl);

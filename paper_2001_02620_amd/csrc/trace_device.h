@@ -39,6 +39,8 @@ struct SceneView {
   const float* albedo;        // per unique face (prototype order)
   const float* tex;           // per unique face: tex_res x tex_res texels (row v, column u), or null
   int32_t tex_res;            // texels per side; 0 shades with `albedo`
+  const float* env;           // environment map, env_w x env_h radiance values, or null
+  int32_t env_w, env_h;       // 0: escaping rays see the constant sky
   float pad_rel;              // top-level origin pad per unit of |o|_inf
   float p_world;              // bound on |world coordinate| of the top-level boxes
   uint32_t tlas_root;         // index of the top-level root in `nodes`
