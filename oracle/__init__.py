@@ -140,10 +140,16 @@ class OracleScene:
         assert a.shape == (self.n_quads,)
         lib().orc_scene_set_albedo(self.h, _p(a))
 
+    @property
+    def n_params(self) -> int:
+        """Shading parameters that gradients refer to: one albedo per face, or,
+        with textures, every texel (face-major, then row v, column u)."""
+        return self.n_quads * (self.tex_res * self.tex_res if self.tex_res > 0 else 1)
+
     def set_textures(self, texels: Optional[np.ndarray]) -> None:
         """Per-face textures [n_quads, res, res] (row v, column u; FP32 values read
-        exactly), or None to shade with the per-face albedo again.  The gradient
-        functions require no textures."""
+        exactly), or None to shade with the per-face albedo again.  With
+        textures the gradient functions refer to the texels."""
         if texels is None:
             assert lib().orc_scene_set_textures(self.h, None, 0) == 0
             self.tex_res = 0
@@ -221,34 +227,34 @@ class OracleScene:
 
     def grad(self, cams, settings, gpix: np.ndarray, pixels: Optional[np.ndarray] = None, brute: bool = False,
              taint: str = "pixel"):
-        """Path-replay gradient of sum_p gpix[p] * I_p w.r.t. per-face albedo.
-        Returns (grad [Q] f64, pixel flags, tainted-face mask).  taint="pixel" marks
+        """Path-replay gradient of sum_p gpix[p] * I_p w.r.t. the shading
+        parameters (per-face albedo, or the texels of a textured scene).
+        Returns (grad [n_params] f64, pixel flags, tainted-parameter mask).  taint="pixel" marks
         every face on any path of a flagged pixel; taint="path" only the faces on
         flagged paths (valid when both sides use these same pixel weights)."""
-        assert self.tex_res == 0, "gradients are defined for per-face albedo, not textures"
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
         n = total if px is None else px.shape[0]
         g = np.ascontiguousarray(gpix, dtype=np.float64)
         assert g.shape == (n,)
-        out = np.zeros(self.n_quads)
+        out = np.zeros(self.n_params)
         fl = np.zeros(n, np.uint8)
-        tmask = np.zeros(self.n_quads, np.uint8)
+        tmask = np.zeros(self.n_params, np.uint8)
         lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,
                        0 if brute else 1, _p(g), 0, None, _p(out), None, _p(fl), _p(tmask),
                        1 if taint == "path" else 0)
         return out, fl, tmask
 
     def tangent(self, cams, settings, tangent: np.ndarray, pixels: Optional[np.ndarray] = None):
-        """Forward-mode (dual number) derivative of each pixel along a per-face tangent."""
-        assert self.tex_res == 0, "gradients are defined for per-face albedo, not textures"
+        """Forward-mode (dual number) derivative of each pixel along a tangent of
+        the shading parameters (per face, or per texel with textures)."""
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
         n = total if px is None else px.shape[0]
         tg = np.ascontiguousarray(tangent, dtype=np.float64)
-        assert tg.shape == (self.n_quads,)
+        assert tg.shape == (self.n_params,)
         dI = np.zeros(n)
         fl = np.zeros(n, np.uint8)
         lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,

@@ -561,6 +561,7 @@ Cam make_cam(const double* cf, const int64_t* ci) {
 // One sampled path, recorded vertex by vertex (for the image and both gradient forms).
 struct Vertex {
   int64_t face;
+  int64_t param;  // index of the shading parameter: the face, or its texel when the scene has textures
   double a;      // albedo at the vertex
   double c;      // (E / pi) * cos_L * visibility: the NEE factor without beta and albedo
   int32_t inst, prim, half;  // the hit
@@ -634,6 +635,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
     double a = S.albedo[face];
+    int64_t param = face;
     uint32_t tex_flag = 0;
     if (S.tex_res > 0) {
       // the texel of (u, v): nearest, on a res x res grid over the quad.  Which
@@ -651,9 +653,10 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       rec.flags |= tex_flag;
       const int tx = std::min(std::max((int)std::floor(gu), 0), R - 1);
       const int ty = std::min(std::max((int)std::floor(gv), 0), R - 1);
-      a = S.tex[((size_t)face * R + ty) * R + tx];
+      param = ((int64_t)face * R + ty) * R + tx;
+      a = S.tex[(size_t)param];
     }
-    Vertex vx{face, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
+    Vertex vx{face, param, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
     const double cl = dot(n, L);
     // next-event estimation (Section 4.1 names the scene's quad-shaped key
     // lights): with area lights, one of the nl = 1 + n_area
@@ -1026,7 +1029,8 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
   }
   const int64_t n = pix ? n_pix : total;
   const int nt = threads();
-  const int64_t Q = (int64_t)S.albedo.size();
+  // shading parameters: per-face albedo, or every texel of every face
+  const int64_t Q = (int64_t)S.albedo.size() * (S.tex_res > 0 ? (int64_t)S.tex_res * S.tex_res : 1);
   std::vector<std::vector<double>> gacc(grad_mode == 0 ? nt : 0, std::vector<double>(grad_mode == 0 ? Q : 0, 0.0));
   std::vector<std::vector<uint8_t>> taint(face_tainted ? nt : 0, std::vector<uint8_t>(face_tainted ? Q : 0, 0));
   parallel_for(n, nt, [&](int64_t i, int tid) {
@@ -1042,7 +1046,7 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
       trace_path(S, P, cams[view], view, p, smp, mode, rec);
       fl |= rec.flags;
       if (!taint_per_path || rec.flags)
-        for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].face);
+        for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].param);
       if (grad_mode == 0) {
         // D_k = beta_k a_k c_k; S_k = sum_{j>=k} D_j + M.  Accumulate S_k / a_k.
         std::vector<double> beta(rec.nv + 1, 1.0);
@@ -1050,13 +1054,13 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
         double tail = rec.escaped ? beta[rec.nv] * rec.L_esc : 0.0;
         for (int k = rec.nv - 1; k >= 0; --k) {
           tail += beta[k] * rec.v[k].a * rec.v[k].c;  // now tail = S_k
-          gacc[tid][rec.v[k].face] += gpix[i] * tail / rec.v[k].a / P.spp;
+          gacc[tid][rec.v[k].param] += gpix[i] * tail / rec.v[k].a / P.spp;
         }
       } else {
         // dual numbers (value, derivative) along the tangent direction
         double L = 0, dL = 0, beta = 1, dbeta = 0;
         for (int k = 0; k < rec.nv; ++k) {
-          const double a = rec.v[k].a, da = tangent[rec.v[k].face];
+          const double a = rec.v[k].a, da = tangent[rec.v[k].param];
           const double c = rec.v[k].c;
           L += beta * a * c;
           dL += (dbeta * a + beta * da) * c;

@@ -439,6 +439,50 @@ def test_gradient_prb_forward_mode_and_fd_agree(ora, lights):
     o.set_albedo(alb)
 
 
+def test_texel_gradient_prb_forward_mode_and_fd_agree(ora):
+    """With textures the gradient is per texel: PRB = dual numbers along a random
+    texel tangent = central differences of the rendered loss, also for single
+    texels with a clearly non-zero gradient; texels no path reads get exactly 0."""
+    scene, cams, st = _grad_setup()
+    R = 3
+    o = oracle.OracleScene(scene)
+    rng = np.random.default_rng(4)
+    # texels are FP32 inputs: values, tangent and steps on a 2^-12 grid keep every
+    # perturbed texel exactly representable
+    tex = rng.integers(800, 3200, size=(scene.albedo.shape[0], R, R)) / 4096.0
+    o.set_textures(tex + rng.integers(-400, 400, size=tex.shape) / 4096.0)
+    T, _, _ = o.render(cams, st)
+    o.set_textures(tex)
+    I, _, _ = o.render(cams, st)
+    N = I.size
+    gpix = 2 * (I - T) / N
+    g, _, _ = o.grad(cams, st, gpix)
+    assert g.shape == (o.n_params,) == (tex.size,)
+    e = rng.integers(-3, 4, size=tex.size).astype(np.float64)
+    dI, _ = o.tangent(cams, st, e)
+    prb, fwd = (g * e).sum(), (gpix * dI).sum()
+    assert abs(prb - fwd) <= 1e-10 * abs(fwd)
+
+    def loss(t):
+        o.set_textures(t.reshape(tex.shape))
+        It, _, _ = o.render(cams, st)
+        return ((It - T) ** 2).sum() / N
+
+    h = 2.0 ** -12
+    t0 = tex.ravel()
+    fd = (loss(t0 + h * e) - loss(t0 - h * e)) / (2 * h)
+    assert abs(fd - prb) <= 1e-6 * abs(prb)
+    for f in np.argsort(-np.abs(g))[:5]:
+        ef = np.zeros_like(t0)
+        ef[f] = 1.0
+        fdf = (loss(t0 + h * ef) - loss(t0 - h * ef)) / (2 * h)
+        assert abs(fdf - g[f]) <= 1e-6 * abs(g[f])
+    # a texel is read only by hits inside its cell: the rest of the face's
+    # texels do not move the image
+    assert (g == 0).sum() > 0
+    o.set_textures(None)
+
+
 def test_gradient_zero_cases(ora):
     scene, cams, st = _grad_setup(seed=32)
     o = oracle.OracleScene(scene)
