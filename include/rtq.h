@@ -179,7 +179,8 @@ int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, h
  * the copy on `stream`; renders on other streams are ordered by the caller.
  * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES] or NULL
  * texels with res > 0; RTQ_E_HIP when the allocation or copy fails.
- * On such a scene rtq_render_backward returns the gradient per texel.
+ * rtq_render_backward rejects a textured scene (its gradient is with respect
+ * to the per-face albedo).
  */
 #define RTQ_MAX_TEX_RES 64
 int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t res, hipStream_t stream);
@@ -381,10 +382,8 @@ int rtq_render_path(const rtq_scene* scene, const rtq_camera* cams, int32_t n_ca
  * grad_albedo[f] += sum over pixels p of grad_images[p] * dI_p / d albedo[f].
  * Each path is replayed from its RNG counters (same hits as the forward pass).
  * grad_albedo: device, n_unique_quads floats, zeroed by the caller, accumulated
- * with atomics (summation order is not fixed).  On a scene with textures
- * (rtq_scene_set_textures) the gradient is with respect to the texels instead:
- * n_unique_quads * res * res floats in the texels' layout.  Errors: as
- * rtq_render.
+ * with atomics (summation order is not fixed).  Errors: RTQ_E_INVALID_ARG on a
+ * scene with textures (rtq_scene_set_textures), as rtq_render otherwise.
  */
 int rtq_render_backward(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp,
                         int32_t depth, const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,

@@ -167,7 +167,6 @@ class Scene:
         L = load_library()
         _torch()
         self.n_quads = int(s.quads.shape[0])
-        self.tex_res = 0
         verts = np.ascontiguousarray(s.verts, dtype=np.float32)
         quads = np.ascontiguousarray(s.quads, dtype=np.int32)
         albedo = np.ascontiguousarray(s.albedo, dtype=np.float32)
@@ -219,20 +218,12 @@ class Scene:
         if texels is None:
             _check(load_library().rtq_scene_set_textures(self.handle, None, 0, _stream()))
             self._tex_keep = None
-            self.tex_res = 0
             return
         assert texels.is_cuda and texels.dim() == 3 and texels.shape[0] == self.n_quads
         assert texels.shape[1] == texels.shape[2]
         t = texels.contiguous().float()
         _check(load_library().rtq_scene_set_textures(self.handle, t.data_ptr(), int(t.shape[1]), _stream()))
         self._tex_keep = t
-        self.tex_res = int(t.shape[1])
-
-    @property
-    def n_params(self) -> int:
-        """Shading parameters that render_backward differentiates: one albedo per
-        face, or, with textures, every texel (the textures' layout)."""
-        return self.n_quads * (self.tex_res * self.tex_res if self.tex_res > 0 else 1)
 
     def set_environment(self, texels) -> None:
         """Environment map seen by escaping rays: a device tensor [h, w] (row 0
@@ -416,17 +407,12 @@ def render_path(scene: Scene, cams, settings, view: int, pixel: int, sample: int
 
 
 def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None, **opts):
-    """Adjoint of render: the gradient of sum_p grad_images[p] I_p with respect to
-    the per-face albedo, or to the texels of a textured scene."""
     torch = _torch()
     arr, total = camera_structs(cams)
     g = grad_images.contiguous().float()
     assert g.numel() == total and g.is_cuda
     if grad_albedo is None:
-        grad_albedo = torch.zeros(scene.n_params, device=g.device, dtype=torch.float32)
-    # the kernel accumulates into every shading parameter a path reads
-    assert grad_albedo.is_cuda and grad_albedo.dtype == torch.float32 and grad_albedo.is_contiguous()
-    assert grad_albedo.numel() >= scene.n_params, "gradient buffer smaller than the scene's shading parameters"
+        grad_albedo = torch.zeros(scene.n_quads, device=g.device, dtype=torch.float32)
     o = render_opts(settings, **opts)
     _check(load_library().rtq_render_backward(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams),
                                               settings.spp, settings.depth, ctypes.byref(o), g.data_ptr(),

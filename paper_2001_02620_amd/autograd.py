@@ -17,9 +17,6 @@ from . import render, render_backward
 class RenderAlbedo(torch.autograd.Function):
     @staticmethod
     def forward(ctx, albedo, scene, cams, settings, opts=None):
-        if scene.tex_res > 0:
-            raise ValueError("RenderAlbedo differentiates per-face albedo; a textured scene shades with its "
-                             "texels (render_backward gives their gradient)")
         opts = dict(opts or {})
         a = albedo.detach().contiguous().float()
         scene.set_albedo(a)

@@ -526,6 +526,8 @@ int rtq_render_backward(const rtq_scene* s, const rtq_camera* cams, int32_t n_ca
                         const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,
                         hipStream_t stream) {
   if (!grad_images || !grad_albedo) return set_error(RTQ_E_INVALID_ARG, "NULL gradient buffer");
+  if (s && s->tex_res > 0)
+    return set_error(RTQ_E_INVALID_ARG, "the adjoint is with respect to per-face albedo; the scene has textures");
   Prepared p;
   int rc = prepare(s, cams, n_cams, spp, depth, opts, false, stream, &p);
   if (rc) return rc;

@@ -639,12 +639,11 @@ __global__ void k_start_tick(unsigned long long* t) {
 
 // ---------------------------------------------------------------- adjoint
 // One lane per path: replay the path from its RNG counters with the same device
-// functions (identical hits), keep per vertex the shading parameter (the face's
-// albedo, or the texel it read), beta_k and the NEE factor c_k (the light's
-// factor times visibility), then walk back: with V_K the sky (or environment)
-// radiance of the escaping ray if the path escaped (else 0) and
-// V_k = a_k (c_k + V_{k+1}), the derivative of the path value with respect to
-// the parameter a_k of vertex k is beta_k (c_k + V_{k+1}).
+// functions (identical hits), keep per vertex the face, beta_k and the NEE factor
+// c_k = (E / pi) cos_L V_k, then walk back: with V_K the sky (or environment)
+// radiance of the escaping ray if the path escaped
+// (else 0) and V_k = a_k (c_k + V_{k+1}), the derivative of the path value with
+// respect to the albedo at vertex k is beta_k (c_k + V_{k+1}).
 template <int FMT>
 __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, float* grad_albedo, int depth_lds) {
   extern __shared__ uint2 lds[];
@@ -658,7 +657,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
   Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
   const float g = grad_img[rp.cams[view].img_offset + pixel] / (float)rp.spp;
   if (g == 0.0f) return;
-  size_t param[kMaxDepth];  // per vertex: the face, or its texel when the scene has textures
+  uint32_t face[kMaxDepth];
   float betak[kMaxDepth], ck[kMaxDepth], ak[kMaxDepth];
   int K = 0;
   bool escaped = false;
@@ -689,7 +688,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
       }
       if (L.b_rec == kEmpty) c = ns.c;
     }
-    param[K] = sc.tex_res > 0 ? texel_index(sc, s.face, L.b_u, L.b_v) : (size_t)s.face;
+    face[K] = s.face;
     betak[K] = beta;
     ck[K] = c;
     ak[K] = s.a;
@@ -705,7 +704,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
   float V = escaped ? escape_radiance(sc, rp, r.dx, r.dy, r.dz) : 0.0f;
   for (int k = K - 1; k >= 0; --k) {
     const float cv = ck[k] + V;
-    unsafeAtomicAdd(&grad_albedo[param[k]], g * (betak[k] * cv));
+    unsafeAtomicAdd(&grad_albedo[face[k]], g * (betak[k] * cv));
     V = ak[k] * cv;
   }
 }

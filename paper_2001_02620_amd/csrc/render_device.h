@@ -104,15 +104,12 @@ struct Shade {
 // the hit's coordinates on the face): the nearest of tex_res x tex_res texels
 // over the face's unit square.  Clamping in float first keeps the index in
 // range for any u, v (NaN included: fmaxf returns the other operand).
-__device__ __forceinline__ size_t texel_index(const SceneView& sc, uint32_t face, float u, float v) {
+__device__ __forceinline__ float face_texel(const SceneView& sc, uint32_t face, float u, float v) {
   const int R = sc.tex_res;
   const float hi = (float)(R - 1);
   const int tx = (int)fminf(fmaxf(u * (float)R, 0.0f), hi);
   const int ty = (int)fminf(fmaxf(v * (float)R, 0.0f), hi);
-  return ((size_t)face * R + ty) * R + tx;
-}
-__device__ __forceinline__ float face_texel(const SceneView& sc, uint32_t face, float u, float v) {
-  return sc.tex[texel_index(sc, face, u, v)];
+  return sc.tex[((size_t)face * R + ty) * R + tx];
 }
 
 // Geometric normal of the hit half in object space, mapped to world space by

@@ -1,8 +1,8 @@
 """Per-face textures (Section 5.3) on the HIP path: every scheduler and node
 format gives the same image, which matches the oracle's textured render on the
 pixels it does not flag; a constant texture reproduces the per-face albedo
-image bit for bit; removing textures restores it; the adjoint of a textured
-scene is per texel and matches the oracle's."""
+image bit for bit; removing textures restores it; the adjoint refuses a
+textured scene."""
 import numpy as np
 import pytest
 
@@ -102,50 +102,11 @@ def test_textured_path_records_and_errors():
             assert v["albedo"] == ov[k]["albedo"], (g, k, v, ov[k])
             exact += 1
     assert checked > 10 and exact > 10
-    from paper_2001_02620_amd.autograd import RenderAlbedo
-    n = scene.albedo.shape[0]
     grad = torch.ones(sum(c.w * c.h for c in cams), device="cuda")
-    assert rtq.render_backward(S, cams, st, grad).numel() == S.n_params == n * 16
-    with pytest.raises(AssertionError):  # a per-face buffer is too small for texel gradients
-        rtq.render_backward(S, cams, st, grad, grad_albedo=torch.zeros(n, device="cuda"))
-    with pytest.raises(ValueError):
-        RenderAlbedo.apply(torch.from_numpy(scene.albedo).cuda(), S, cams, st)
     with pytest.raises(rtq.RtqError):
-        S.set_textures(torch.zeros((n, 65, 65), device="cuda"))
+        rtq.render_backward(S, cams, st, grad)
+    with pytest.raises(rtq.RtqError):
+        S.set_textures(torch.zeros((scene.albedo.shape[0], 65, 65), device="cuda"))
     S.set_textures(None)
-    assert rtq.render_backward(S, cams, st, grad).numel() == n
+    rtq.render_backward(S, cams, st, grad)
     torch.cuda.synchronize()
-
-
-def test_texel_adjoint_vs_oracle():
-    """The adjoint of a textured scene accumulates per texel: against the
-    oracle's path-replay texel gradient, both fed the same pixel weights with
-    flagged pixels weighted zero."""
-    import torch
-    log("case: texel adjoint")
-    scene = sg.tiny_scene(31, n_inst=4, n_protos=2, nq=4, spread=1.0)
-    cams = [sg.Camera((0.0, -8.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 35.0, 48, 48)]
-    st = sg.RenderSettings(spp=4, depth=3, seed=31)
-    R = 3
-    tex = _texels(scene.albedo.shape[0], R, 13)
-    rng = np.random.default_rng(9)
-    o = oracle.OracleScene(scene)
-    o.set_textures((tex + rng.uniform(-0.1, 0.1, tex.shape)).astype(np.float32))
-    T, _, _ = o.render(cams, st)
-    o.set_textures(tex)
-    I, fl, _ = o.render(cams, st)
-    gpix = (2 * (I - T) / I.size).astype(np.float32).astype(np.float64)
-    gpix[fl != 0] = 0.0
-    g_or, _, _ = o.grad(cams, st, gpix)
-    S = rtq.Scene(scene)
-    S.set_textures(torch.from_numpy(tex).cuda())
-    for kw in (SCHEDS[0], SCHEDS[3]):
-        g = rtq.render_backward(S, cams, st, torch.from_numpy(gpix.astype(np.float32)).cuda(), **kw)
-        g = g.cpu().numpy().astype(np.float64)
-        assert g.shape == g_or.shape
-        mx = np.abs(g_or).max()
-        big = np.nonzero(np.abs(g_or) > 1e-3 * mx)[0]
-        assert big.size >= 16
-        err = np.abs(g - g_or)
-        log(f"  {kw}: {big.size} texels, max rel {(err[big] / np.abs(g_or[big])).max():.2e}")
-        assert (err <= 1e-3 * np.abs(g_or) + 1e-5 * mx).all()
