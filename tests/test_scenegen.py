@@ -40,3 +40,45 @@ def test_config4_recipe():
     s, cams, st = sg.config4()
     assert s.n_quads == 16 * 32 * 32 and s.n_instances == 1000
     assert [(c.w, c.h) for c in cams] == [(512, 512)] and st.spp == 4 and st.depth == 4
+
+
+def test_shoemake_rotations_are_uniform_rotations():
+    R = sg.shoemake_rotations(np.random.default_rng(3), 20000)
+    assert np.allclose(np.einsum("nji,njk->nik", R, R), np.eye(3), atol=1e-12)
+    assert np.allclose(np.linalg.det(R), 1.0, atol=1e-12)
+    # Haar measure: E[R] = 0 and E[R_ij^2] = 1/3
+    assert np.abs(R.mean(axis=0)).max() < 0.02
+    assert np.abs((R ** 2).mean(axis=0) - 1.0 / 3.0).max() < 0.02
+
+
+@pytest.mark.parametrize("n", [1, 2, 7])
+def test_shell_is_closed_and_faces_outward(n):
+    v, q = sg.shell_proto(np.random.default_rng(n), n, 1.0, 0.05)
+    assert q.shape == (6 * n * n, 4) and v.shape[0] == 6 * n * n + 2  # Euler: V - E + F = 2
+    edges = np.sort(np.stack([q, np.roll(q, -1, axis=1)], axis=-1).reshape(-1, 2), axis=1)
+    _, counts = np.unique(edges, axis=0, return_counts=True)
+    assert (counts == 2).all(), "an edge is not shared by exactly two quads"
+    # directed edges appear once each way: consistent orientation
+    directed = np.stack([q, np.roll(q, -1, axis=1)], axis=-1).reshape(-1, 2)
+    assert np.unique(directed, axis=0).shape[0] == directed.shape[0]
+    c = v[q].astype(np.float64)
+    nrm = np.cross(c[:, 1] - c[:, 0], c[:, 3] - c[:, 0])
+    assert (np.einsum("ij,ij->i", nrm, c.mean(axis=1)) > 0).all(), "a quad faces inward"
+
+
+def test_grid_topology():
+    q = sg.grid_quads(5, 3)
+    assert q.shape == (15, 4) and q.min() == 0 and q.max() == 6 * 4 - 1
+    edges = np.sort(np.stack([q, np.roll(q, -1, axis=1)], axis=-1).reshape(-1, 2), axis=1)
+    _, counts = np.unique(edges, axis=0, return_counts=True)
+    # interior edges shared by two quads, boundary edges (2 (5 + 3)) by one
+    assert (counts <= 2).all() and (counts == 1).sum() == 2 * (5 + 3)
+
+
+def test_scaled_big_configs():
+    s3, c3, st3 = sg.config3(scale=0.0005)
+    assert s3.n_instances == 10_000 and len(c3) == 1 and (st3.spp, st3.depth) == (4, 8)
+    s5, c5, st5 = sg.config5(scale=0.0002)
+    assert s5.n_instances == 8_000 and len(c5) == 64 and (st5.spp, st5.depth) == (1, 6)
+    sides = np.array([c.w for c in c5])
+    assert (sides >= 64).all() and (sides <= 1024).all() and all(c.w == c.h for c in c5)
