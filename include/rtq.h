@@ -18,8 +18,10 @@
  *    (build) or by the work enqueued on the stream (trace, render); the caller
  *    keeps them alive until that work completes.
  *  - Enqueuing calls (trace, render, backward, set_albedo) are asynchronous on
- *    the given stream and never synchronize the device.  Argument errors are
- *    reported synchronously, before anything is enqueued.
+ *    the given stream and never synchronize the device; set_textures and
+ *    set_environment wait for the device first (they may free memory that
+ *    queued work reads).  Argument errors are reported synchronously, before
+ *    anything is enqueued.
  *  - A quad is (v0, v1, v2, v3), counter-clockwise.  It is traced as the two
  *    triangles A = (v0, v1, v3) and B = (v2, v3, v1), both sides visible.  The hit
  *    parameterisation is v0 -> (u, v) = (0, 0), v1 -> (1, 0), v2 -> (1, 1),
