@@ -28,13 +28,21 @@ F_DIAG = 16
 F_SHADE = 32
 ID_FLAGS = F_NEAR_TIE | F_GRAZE | F_NEAR_ORIGIN
 
+# verdicts of OracleScene.accept (closest hit) and OracleScene.check_path
+ACCEPT_CODES = {1: "not a possible answer", 2: "miss while a certain hit exists", 3: "t outside its tolerance"}
+PATH_CODES = {1: "camera ray", 2: "hit is not a possible answer", 3: "escape while a certain hit exists",
+              4: "t outside its tolerance", 5: "face index", 6: "shading value", 7: "shadow ray cast or not",
+              8: "shadow outcome", 9: "next origin is not the FP32 hit point", 10: "next direction",
+              11: "path length", 12: "radiance", -1: "bad arguments"}
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle: plain C++17, -O3, no fast-math, std::thread."""
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["g++", "-std=c++17", "-O3", "-march=x86-64-v3", "-fno-fast-math", "-fPIC", "-shared", "-pthread",
+    cmd = ["g++", "-std=c++17", "-O3", "-march=x86-64-v3", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+           "-pthread",
            "-Wall", "-o", tmp, _SRC]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)
@@ -67,6 +75,9 @@ def lib():
         L.orc_render.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, P, P]
         L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P, i32]
         L.orc_path.argtypes = [P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
+        L.orc_accept.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P]
+        L.orc_check_path.argtypes = [P, P, P, i32, P, P, P, i32, i64, i32, i32, P, P, i32, ctypes.c_float, P]
+        L.orc_check_path.restype = i32
         _lib = L
     return _lib
 
@@ -190,6 +201,48 @@ class OracleScene:
                         _p(out.cand), _p(out.ncand), _p(out.scale))
         return out
 
+    def accept(self, rays: np.ndarray, inst: np.ndarray, prim: Optional[np.ndarray] = None,
+               t: Optional[np.ndarray] = None, half: Optional[np.ndarray] = None,
+               excl: Optional[np.ndarray] = None, r0: Optional[np.ndarray] = None, any_hit: bool = False,
+               brute: bool = False):
+        """Whether each answer (closest: inst, prim, t and optionally half, inst -1 for a
+        miss; any_hit: inst = 1 occluded / 0 not) is one an FP32 traversal may give
+        for the FP32 ray.  Returns (code [n] int32, 0 = valid, see ACCEPT_CODES;
+        info [n] int32 bits: 1 the certain hit, 2 t check waived, 4 other answers possible)."""
+        rays = np.ascontiguousarray(rays, dtype=np.float32)
+        n = rays.shape[0]
+        gi = np.ascontiguousarray(inst, dtype=np.int32)
+        gp = None if prim is None else np.ascontiguousarray(prim, dtype=np.int32)
+        gh = None if half is None else np.ascontiguousarray(half, dtype=np.int32)
+        gt = None if t is None else np.ascontiguousarray(t, dtype=np.float32)
+        if not any_hit:
+            assert gp is not None and gt is not None
+        ex = None if excl is None else np.ascontiguousarray(excl, dtype=np.int32)
+        rr = None if r0 is None else np.ascontiguousarray(r0, dtype=np.float64)
+        out = np.zeros(n, np.int32)
+        info = np.zeros(n, np.int32)
+        lib().orc_accept(self.h, n, _p(rays), _p(ex), _p(rr), 0 if brute else 1, 1 if any_hit else 0, _p(gi),
+                         _p(gp), _p(gh), _p(gt), _p(out), _p(info))
+        return out, info
+
+    def check_path(self, cams, settings, cam: int, local: int, sample: int, nv: int, vi: np.ndarray,
+                   vf: np.ndarray, escaped: bool, radiance: float):
+        """Check a GPU path record (rtq_render_path: vi 6 int32 and vf 10 float32 per
+        recorded ray, the escaping ray last) step by step along its own rays.
+        Returns (code, stats): code 0 = valid, else PATH_CODES[code]; stats: failing
+        ray, FP64 radiance along the path, vertices, certain answers, t checks
+        waived, shading decisions within rounding of a threshold."""
+        cf, ci, _ = self._cams(cams)
+        pi, pu, pd = self._params(settings)
+        vi = np.ascontiguousarray(vi, dtype=np.int32)
+        vf = np.ascontiguousarray(vf, dtype=np.float32)
+        st = np.zeros(6)
+        code = lib().orc_check_path(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), int(cam), int(local),
+                                    int(sample), int(nv), _p(vi), _p(vf), 1 if escaped else 0, float(radiance),
+                                    _p(st))
+        return int(code), dict(ray=int(st[0]), L=float(st[1]), vertices=int(st[2]), certain=int(st[3]),
+                               t_waived=int(st[4]), ambiguous_shading=int(st[5]))
+
     @staticmethod
     def _params(settings):
         pi = np.array([settings.spp, settings.depth], dtype=np.int32)
@@ -206,10 +259,12 @@ class OracleScene:
         cf = np.array([list(c.eye) + list(c.look) + list(c.up) + [c.vfov_deg] for c in cams], dtype=np.float64)
         off = 0
         ci = []
-        for c in cams:
-            ci.append([c.w, c.h, off])
-            off += c.w * c.h
-        return np.ascontiguousarray(cf), np.array(ci, dtype=np.int64), off
+        for k, c in enumerate(cams):
+            vid = getattr(c, "view_id", None)
+            tile = getattr(c, "tile", None) or (0, 0, c.w, c.h)
+            ci.append([c.w, c.h, off, k if vid is None else vid] + [int(x) for x in tile])
+            off += tile[2] * tile[3]
+        return np.ascontiguousarray(cf), np.array(ci, dtype=np.int64).reshape(-1, 8), off
 
     def render(self, cams, settings, pixels: Optional[np.ndarray] = None, brute: bool = False):
         """Returns (image or per-listed-pixel radiance [f64], pixel flags [u8], stats dict)."""

@@ -497,6 +497,176 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   return out;
 }
 
+// ---------------------------------------------------------------- acceptance
+// Every answer an FP32 traversal may legitimately give for one ray.  The FP32
+// test of a triangle can disagree with the exact test only where rounding can
+// move the ray across the triangle's boundary, or its hit across an end of the
+// ray's interval:
+//  * the ray passes within the graze distance of one of the triangle's edges,
+//    measured in the plane orthogonal to the ray (the watertight test decides
+//    inside/outside there, from edge functions of the projected vertices);
+//  * the triangle lies within the graze distance of the ray's start point
+//    (its FP32 t may fall on either side of tmin);
+//  * its hit lies within the tie window of tmax.
+// A triangle hit by the exact test with none of these near is a *certain*
+// hit: every FP32 traversal finds it.  A triangle is a *possible* answer when
+// rounding can make it a hit.  The closest certain hit C bounds the answer: a
+// traversal reports C, or a possible answer no farther than C plus its tie
+// window; without a certain hit a miss is acceptable too.  The graze distance
+// is the one the flags use, 1e-6 of the position scale plus the origin
+// uncertainty r0.
+
+// Distance from the line {o + s d : s real} to the segment [a, b], measured in
+// the plane orthogonal to d (equal to the 3D distance from the line).
+double line_seg_dist(V3 o, V3 d, V3 a, V3 b) {
+  const double dd = dot(d, d);
+  const V3 qa = a - o, qb = b - o;
+  const V3 pa = qa - (dot(qa, d) / dd) * d;
+  const V3 pb = qb - (dot(qb, d) / dd) * d;
+  const V3 e = pb - pa;
+  const double ee = dot(e, e);
+  const double u = ee > 0.0 ? std::min(1.0, std::max(0.0, -dot(pa, e) / ee)) : 0.0;
+  return norm(pa + u * e);
+}
+
+struct Cand {
+  Key k;           // t: where the ray meets the triangle's plane
+  bool certain;    // hit by every FP32 traversal
+  bool illcond;    // its FP32 t cannot be trusted to 1e-5
+  double win;      // tie window at its t
+};
+
+struct AcceptSet {
+  bool ray_ok = true;      // finite origin and non-zero direction
+  bool has_certain = false;
+  Cand certain;            // the closest certain hit
+  std::vector<Cand> cand;  // possible answers no farther than the certain hit's window
+};
+
+// One triangle (w0, w1, w2) of quad (inst, prim), half `half`, against ray r:
+// whether it is a possible answer and whether it is a certain hit.
+struct TriClass {
+  bool possible = false, certain = false, illcond = false;
+  double t = kInf, S = 1.0;
+};
+TriClass classify_tri(const Ray& r, double dn, double Sv, V3 w0, V3 w1, V3 w2, const V3 wq[4], double r0) {
+  TriClass c;
+  double ext = 0.0;
+  for (int k = 0; k < 4; ++k) ext = std::max(ext, std::max(maxabs(wq[k] - r.o), maxabs(wq[k])));
+  const double Sq = std::max(Sv, ext);
+  c.S = Sq;
+  const double thr = 1e-6 * Sq + r0;
+  const V3 n = cross(w1 - w0, w2 - w0);
+  const double nn = dot(n, n);
+  if (!(nn > 0.0)) return c;  // degenerate: never hit (its edge functions sum to zero)
+  const double den = dot(n, r.d);
+  const V3 o0 = r.o + r.tmin * r.d;
+  const bool near_org = point_tri_dist(o0, w0, w1, w2) < thr;
+  const double g = std::min(line_seg_dist(r.o, r.d, w0, w1),
+                            std::min(line_seg_dist(r.o, r.d, w1, w2), line_seg_dist(r.o, r.d, w2, w0)));
+  const bool graze = g < thr;
+  if (den == 0.0) {
+    // parallel to the plane: only rounding can produce a hit
+    c.possible = near_org;
+    c.t = r.tmin;
+    c.illcond = true;
+    return c;
+  }
+  const double t = dot(n, w0 - r.o) / den;
+  c.t = t;
+  const V3 p = r.o + t * r.d;
+  const double c0 = dot(cross(w2 - w1, p - w1), n);
+  const double c1 = dot(cross(w0 - w2, p - w2), n);
+  const double c2 = dot(cross(w1 - w0, p - w0), n);
+  const bool inside = c0 >= 0 && c1 >= 0 && c2 >= 0;
+  const bool in_iv = t > r.tmin && t <= r.tmax;
+  const bool near_tmax = std::isfinite(r.tmax) && std::fabs(t - r.tmax) <= 1e-5 * r.tmax + 1e-6 * Sq / dn;
+  const double cosv = std::fabs(den) / (std::sqrt(nn) * dn);
+  c.illcond = 16.0 * std::ldexp(1.0, -24) * Sq > 1e-5 * std::fabs(t) * dn * cosv;
+  c.certain = inside && in_iv && !graze && !near_org && !near_tmax;
+  c.possible = (inside || graze) && (in_iv || near_org || near_tmax);
+  return c;
+}
+
+AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, int mode) {
+  AcceptSet A;
+  const double dn = norm(r.d);
+  if (!(dn > 0.0) || !std::isfinite(dn) || !std::isfinite(maxabs(r.o))) {
+    A.ray_ok = false;
+    return A;
+  }
+  const double Sv = std::max(1.0, maxabs(r.o));
+  auto each_tri = [&](int64_t inst, int64_t qg, auto&& fn) {
+    V3 w[4];
+    quad_world(S, inst, qg, w);
+    const int32_t prim = (int32_t)(qg - S.qo[S.iproto[inst]]);
+    for (int h = 0; h < 2; ++h) {
+      if ((int32_t)inst == ex.inst && prim == ex.prim && h == ex.half) continue;
+      const TriClass c = h == 0 ? classify_tri(r, dn, Sv, w[0], w[1], w[3], w, r0)
+                                : classify_tri(r, dn, Sv, w[2], w[3], w[1], w, r0);
+      fn((int32_t)inst, prim, h, c);
+    }
+  };
+  // pass 1: the closest certain hit (the search range shrinks only on certain hits)
+  double t_hi = r.tmax;
+  const double g_enum = 1e-6 * 1.01 * (std::max(Sv, S.scene_mag) + maxabs(r.o) + S.scene_mag) + r0;
+  visit(S, r, mode, g_enum, t_hi, [&](int64_t inst, int64_t qg) {
+    each_tri(inst, qg, [&](int32_t i, int32_t pr, int h, const TriClass& c) {
+      if (!c.certain) return;
+      Cand cd{Key{c.t, i, pr, h, 0, 0}, true, c.illcond, 1e-5 * c.t + 1e-6 * c.S / dn};
+      if (!A.has_certain || key_less(cd.k, A.certain.k)) {
+        A.certain = cd;
+        A.has_certain = true;
+      }
+    });
+    if (A.has_certain) t_hi = std::min(t_hi, A.certain.k.t + A.certain.win);
+  });
+  // pass 2: every possible answer up to the certain hit's window.  A triangle
+  // whose edge grazes the ray may lie up to (graze distance) / |cos| beyond its
+  // plane crossing; the enumeration reaches 1e-3 of the scene scale further.
+  const double t_lim = A.has_certain ? A.certain.k.t + A.certain.win : r.tmax;
+  double t_enum = std::isfinite(t_lim) ? t_lim + 1e-3 * std::max(Sv, S.scene_mag) / dn : kInf;
+  visit(S, r, mode, g_enum, t_enum, [&](int64_t inst, int64_t qg) {
+    each_tri(inst, qg, [&](int32_t i, int32_t pr, int h, const TriClass& c) {
+      if (!c.possible || c.t > t_lim) return;
+      A.cand.push_back(Cand{Key{c.t, i, pr, h, 0, 0}, c.certain, c.illcond, 1e-5 * std::fabs(c.t) + 1e-6 * c.S / dn});
+    });
+  });
+  return A;
+}
+
+// Verdict on one closest-hit answer (inst, prim, half; half < 0 = either) at
+// parameter t_gpu: 0 valid, 1 not a possible answer, 2 a miss while a certain
+// hit exists, 3 t outside its tolerance.  *info: bit 1 the answer is the
+// certain hit, bit 2 its t check was waived (ill-conditioned).
+int judge_closest(const AcceptSet& A, int32_t inst, int32_t prim, int32_t half, double t_gpu, int* info) {
+  *info = 0;
+  if (!A.ray_ok) return inst < 0 ? 0 : 1;
+  if (inst < 0) return A.has_certain ? 2 : 0;
+  const Cand* best = nullptr;
+  for (const Cand& c : A.cand)
+    if (c.k.inst == inst && c.k.prim == prim && (half < 0 || c.k.half == half)) {
+      if (!best || std::fabs(c.k.t - t_gpu) < std::fabs(best->k.t - t_gpu)) best = &c;
+    }
+  if (!best) return 1;
+  if (A.has_certain && A.certain.k.inst == inst && A.certain.k.prim == prim &&
+      (half < 0 || A.certain.k.half == half))
+    *info |= 1;
+  if (best->illcond) {
+    *info |= 2;
+    return 0;
+  }
+  return std::fabs(t_gpu - best->k.t) <= best->win ? 0 : 3;
+}
+
+// Verdict on one any-hit answer: 0 valid, 1 occluded without any possible
+// occluder, 2 unoccluded while a certain occluder exists.
+int judge_any(const AcceptSet& A, bool occluded) {
+  if (!A.ray_ok) return occluded ? 1 : 0;
+  if (occluded) return A.cand.empty() && !A.has_certain ? 1 : 0;
+  return A.has_certain ? 2 : 0;
+}
+
 // ---------------------------------------------------------------- RNG
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011).
 void philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
@@ -537,12 +707,17 @@ Params make_params(const int32_t* pi, const uint64_t* pu, const double* pd) {
   return P;
 }
 
+// A pinhole view, or the rectangle (tx, ty, tw, th) of it that a call renders
+// (Section 5.5 deals the tiles of a frame to the workers); its paths draw
+// random numbers by (pixel of the whole view, sample, view id, bounce).
 struct Cam {
   V3 eye, f, r, u;
   double tan_half, aspect;
   int64_t w, h, off;
+  int64_t view_id, tx, ty, tw, th;
 };
 
+// ci: w, h, image offset of the rectangle, view id, tile x, y, width, height.
 Cam make_cam(const double* cf, const int64_t* ci) {
   Cam c;
   c.eye = {cf[0], cf[1], cf[2]};
@@ -554,6 +729,11 @@ Cam make_cam(const double* cf, const int64_t* ci) {
   c.w = ci[0];
   c.h = ci[1];
   c.off = ci[2];
+  c.view_id = ci[3];
+  c.tx = ci[4];
+  c.ty = ci[5];
+  c.tw = ci[6];
+  c.th = ci[7];
   c.aspect = (double)c.w / (double)c.h;
   return c;
 }
@@ -747,6 +927,287 @@ double path_value(const Params& P, const PathRec& rec) {
   return L;
 }
 
+// ---------------------------------------------------------------- path replay check
+// A GPU path recorded vertex by vertex (the ray that found each vertex, the
+// hit, the shadow-ray outcome, the shading value) is checked step by step
+// along its own rays, so that no check depends on an earlier rounding choice:
+//  * each recorded hit (or escape) is an acceptable answer for the recorded FP32
+//    ray with the previous triangle excluded, and its t lies within tolerance;
+//  * the next ray starts at the FP32 hit point o + t d, formed as the renderer
+//    forms it (one rounding per operation), and points along the cosine sample
+//    of the same random words about the exact normal of the hit triangle;
+//  * shading decisions (normal side, whether a shadow ray is cast, texel,
+//    environment texel) equal the exact ones unless they lie within rounding of
+//    a threshold, where either side is accepted and the GPU's side is followed;
+//  * each shadow outcome is acceptable for the shadow ray from the FP32 point;
+//  * the path's radiance, re-evaluated in FP64 along these decisions, matches
+//    the GPU's value to 1e-4 relative.
+struct PathCheck {
+  int code = 0;     // 0 valid; otherwise the first failed check (see orc_check_path)
+  int vertex = -1;  // the vertex (or ray) where it failed
+  double L = 0.0;   // FP64 radiance along the GPU's decisions
+  int n_vert = 0, n_certain = 0, n_waived = 0, n_ambiguous_shading = 0;
+};
+
+inline float f32(double x) { return (float)x; }
+
+// Cosine sample about the unit normal n with words (u1, u2), in the basis of
+// Duff et al. 2017; `flip` uses the other branch of the sign choice (n_z ~ 0).
+V3 cosine_sample(V3 n, double u1, double u2, bool flip) {
+  double sg = n.z >= 0 ? 1.0 : -1.0;
+  if (flip) sg = -sg;
+  const double aa = -1.0 / (sg + n.z);
+  const double bb = n.x * n.y * aa;
+  const V3 t1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
+  const V3 t2{bb, sg + n.y * n.y * aa, -n.y};
+  const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
+  return (rr * std::cos(phi)) * t1 + (rr * std::sin(phi)) * t2 + std::sqrt(1.0 - u1) * n;
+}
+
+// Environment texels a direction may read: the exact one, and its neighbours
+// across a texel boundary within rounding (angular distance times sin(theta)
+// below 1e-5) or near a pole (within 1e-3).
+int env_candidates(const Scene& S, V3 d, double out[9]) {
+  d = normalize(d);
+  const double th = std::acos(std::min(1.0, std::max(-1.0, d.z)));
+  const double st = std::sin(th);
+  const double u = (std::atan2(d.y, d.x) + kPi) / (2.0 * kPi), v = th / kPi;
+  const int W = S.env_w, H = S.env_h;
+  const double gu = u * W, gv = v * H;
+  const int tx = std::min(std::max((int)std::floor(gu), 0), W - 1);
+  const int ty = std::min(std::max((int)std::floor(gv), 0), H - 1);
+  const double du = std::fabs(gu - std::round(gu)) * (2.0 * kPi / W) * st;
+  const double dv = std::fabs(gv - std::round(gv)) * (kPi / H) * st;
+  const bool pole = st < 1e-3;
+  int xs[3] = {tx, tx, tx}, ys[3] = {ty, ty, ty};
+  int nx = 1, ny = 1;
+  if (du < 1e-5 || pole) {
+    xs[nx++] = std::max(tx - 1, 0);
+    xs[nx++] = std::min(tx + 1, W - 1);
+  }
+  if (dv < 1e-5 || pole) {
+    ys[ny++] = std::max(ty - 1, 0);
+    ys[ny++] = std::min(ty + 1, H - 1);
+  }
+  int n = 0;
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b) out[n++] = S.env[(size_t)ys[b] * W + xs[a]];
+  return n;
+}
+
+// vi: 6 words per recorded ray (instance, primitive, half, shadow -1/0/1, face, 0);
+// vf: 10 floats per recorded ray (t, shading value, cosine to the light,
+// radiance so far, origin xyz, direction xyz).  Rays 0 .. nv-1 found vertices;
+// when the path escaped, ray nv is the escaping ray (its words are ignored but
+// origin and direction).
+PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, int64_t pix, int32_t sample,
+                     int nv, const int32_t* vi, const float* vf, bool escaped, float radiance, int mode) {
+  PathCheck R;
+  auto fail = [&](int code, int k) {
+    if (R.code == 0) {
+      R.code = code;
+      R.vertex = k;
+    }
+    return R;
+  };
+  const uint32_t key[2] = {(uint32_t)(P.seed & 0xffffffffu), (uint32_t)(P.seed >> 32) ^ P.frame};
+  // the light direction as the device holds it (rounded to FP32)
+  const V3 Lf{(double)f32(P.light[0]), (double)f32(P.light[1]), (double)f32(P.light[2])};
+  const V3 L{P.light[0], P.light[1], P.light[2]};
+  if (nv < 0 || nv > P.depth || (!escaped && nv != P.depth)) return fail(11, nv);
+  auto ray_of = [&](int k) {
+    const float* f = vf + 10 * k;
+    return Ray{{(double)f[4], (double)f[5], (double)f[6]}, {(double)f[7], (double)f[8], (double)f[9]}, 0.0, kInf};
+  };
+  // camera ray: eye exactly, direction within FP32 rounding of the FP64 one
+  {
+    uint32_t w[4];
+    uint32_t ctr[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0u};
+    philox(ctr, key, w);
+    const int64_t x = pix % cam.w, y = pix / cam.w;
+    const double sx = (2.0 * ((double)x + unit(w[0])) / (double)cam.w - 1.0) * cam.tan_half * cam.aspect;
+    const double sy = (1.0 - 2.0 * ((double)y + unit(w[1])) / (double)cam.h) * cam.tan_half;
+    const V3 d = normalize(cam.f + sx * cam.r + sy * cam.u);
+    const Ray r0 = ray_of(0);
+    if (r0.o.x != (double)f32(cam.eye.x) || r0.o.y != (double)f32(cam.eye.y) || r0.o.z != (double)f32(cam.eye.z))
+      return fail(1, 0);
+    if (norm(r0.d - d) > 1e-5) return fail(1, 0);
+  }
+  Excl ex;
+  double beta = 1.0;
+  double Lsum = 0.0;
+  std::vector<double> esc_vals;
+  for (int k = 0; k <= nv; ++k) {
+    if (k == nv && !escaped) break;
+    const Ray ray = ray_of(k);
+    const AcceptSet A = accept_set(S, ray, ex, 0.0, mode);
+    if (k == nv) {
+      // the escaping ray: a miss must be acceptable
+      int info = 0;
+      if (judge_closest(A, -1, -1, -1, kInf, &info)) return fail(3, k);
+      if (S.env_w > 0) {
+        double c[9];
+        const int n = env_candidates(S, ray.d, c);
+        for (int j = 0; j < n; ++j) esc_vals.push_back(c[j]);
+      } else {
+        esc_vals.push_back(P.L_sky);
+      }
+      break;
+    }
+    const int32_t* I = vi + 6 * k;
+    const float* F = vf + 10 * k;
+    const int32_t inst = I[0], prim = I[1], half = I[2], shadow = I[3];
+    if (inst < 0 || inst >= S.N || prim < 0 || half < 0 || half > 1) return fail(2, k);
+    const int32_t pr = S.iproto[inst];
+    if (prim >= S.qo[pr + 1] - S.qo[pr]) return fail(2, k);
+    int info = 0;
+    const int jc = judge_closest(A, inst, prim, half, (double)F[0], &info);
+    if (jc == 1) return fail(2, k);
+    if (jc == 3) return fail(4, k);
+    R.n_vert++;
+    if (info & 1) R.n_certain++;
+    if (info & 2) R.n_waived++;
+    const int64_t face = S.qo[pr] + prim;
+    if (I[4] != (int32_t)face) return fail(5, k);
+    V3 wq[4];
+    quad_world(S, inst, face, wq);
+    V3 n = half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
+    n = normalize(n);
+    const V3 dh = normalize(ray.d);
+    const double nd = dot(n, dh);
+    // the FP32 hit point, formed as the renderer forms it
+    const float t32 = F[0];
+    const V3 pg{(double)f32((double)F[4] + (double)f32((double)t32 * (double)F[7])),
+                (double)f32((double)F[5] + (double)f32((double)t32 * (double)F[8])),
+                (double)f32((double)F[6] + (double)f32((double)t32 * (double)F[9]))};
+    const bool has_next = k + 1 < nv || (escaped && k + 1 == nv);
+    // which side the normal faces: toward the incoming ray, unless the ray
+    // grazes the surface; then the GPU's choice shows in its next direction or
+    // in the sign of its cosine to the light
+    double side = nd > 0 ? -1.0 : 1.0;
+    if (std::fabs(nd) < 1e-3) {
+      R.n_ambiguous_shading++;
+      if (has_next) {
+        const Ray nr = ray_of(k + 1);
+        side = dot(n, nr.d) >= 0 ? 1.0 : -1.0;
+      } else if (std::fabs((double)F[2]) > 1e-6) {
+        side = ((double)F[2] * dot(n, L) >= 0) ? 1.0 : -1.0;
+      }
+    }
+    n = side * n;
+    // shading value: the face's albedo, or a texel at the hit's (u, v)
+    double a = S.albedo[face];
+    if (S.tex_res > 0) {
+      // barycentric (u, v) of the plane point along the recorded ray
+      const V3 w0 = half == 0 ? wq[0] : wq[2], w1 = half == 0 ? wq[1] : wq[3], w2 = half == 0 ? wq[3] : wq[1];
+      const V3 nt = cross(w1 - w0, w2 - w0);
+      const double tt = dot(nt, w0 - ray.o) / dot(nt, ray.d);
+      const V3 p = ray.o + tt * ray.d;
+      const double nn = dot(nt, nt);
+      const double l1 = dot(cross(w0 - w2, p - w2), nt) / nn, l2 = dot(cross(w1 - w0, p - w0), nt) / nn;
+      const double u = half == 0 ? l1 : 1.0 - l1, v = half == 0 ? l2 : 1.0 - l2;
+      const int Rr = S.tex_res;
+      const double lu = std::max(norm(wq[1] - wq[0]), norm(wq[2] - wq[3]));
+      const double lv = std::max(norm(wq[3] - wq[0]), norm(wq[2] - wq[1]));
+      double Sq = std::max(1.0, std::max(maxabs(ray.o), maxabs(p)));
+      for (int q = 0; q < 4; ++q) Sq = std::max(Sq, maxabs(wq[q] - ray.o));
+      const double tol = 1e-5 * Sq / std::max(std::fabs(nd), 1e-3);
+      const int tx = std::min(std::max((int)std::floor(u * Rr), 0), Rr - 1);
+      const int ty = std::min(std::max((int)std::floor(v * Rr), 0), Rr - 1);
+      bool found = false;
+      for (int dx = -1; dx <= 1 && !found; ++dx)
+        for (int dy = -1; dy <= 1 && !found; ++dy) {
+          const int x2 = tx + dx, y2 = ty + dy;
+          if (x2 < 0 || y2 < 0 || x2 >= Rr || y2 >= Rr) continue;
+          // a neighbour is acceptable only across an edge within rounding
+          if (dx != 0 && std::fabs(u * Rr - (dx > 0 ? tx + 1 : tx)) * lu / Rr >= tol) continue;
+          if (dy != 0 && std::fabs(v * Rr - (dy > 0 ? ty + 1 : ty)) * lv / Rr >= tol) continue;
+          const double val = S.tex[((size_t)face * Rr + y2) * Rr + x2];
+          if (f32(val) == F[1]) {
+            a = val;
+            found = true;
+          }
+        }
+      if (!found) return fail(6, k);
+    } else if (f32(a) != F[1]) {
+      return fail(6, k);
+    }
+    // next-event estimate
+    const int nl = 1 + P.n_area;
+    int j = 0;
+    uint32_t wl[4] = {0u, 0u, 0u, 0u};
+    if (P.n_area > 0) {
+      uint32_t ctr3[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x80000000u | (uint32_t)k};
+      philox(ctr3, key, wl);
+      j = (int)(((uint64_t)(wl[0] >> 8) * (uint64_t)nl) >> 24);
+    }
+    const Excl here{inst, prim, half};
+    double c = 0.0;
+    bool want_certain = false, skip_certain = false;
+    Ray sr{pg, Lf, 0.0, kInf};
+    double cval = 0.0;
+    if (j == 0) {
+      const double cl = dot(n, L);
+      want_certain = cl > 1e-6;
+      skip_certain = cl < -1e-6;
+      cval = nl * (P.E / kPi * cl);
+    } else {
+      const double* Lq = P.area + 10 * (j - 1);
+      const V3 c0{Lq[0], Lq[1], Lq[2]}, e1{Lq[3], Lq[4], Lq[5]}, e2{Lq[6], Lq[7], Lq[8]};
+      const V3 x = c0 + unit(wl[1]) * e1 + unit(wl[2]) * e2;
+      const V3 wi = x - pg;
+      const double d2 = dot(wi, wi), dd = std::sqrt(d2);
+      const V3 nlv = cross(e1, e2);
+      const double Ar = norm(nlv);
+      const double cp = dot(n, wi) / dd, cq = -dot(nlv, wi) / (Ar * dd);
+      want_certain = cp > 1e-6 && cq > 1e-6;
+      skip_certain = cp < -1e-6 || cq < -1e-6;
+      cval = nl * (Lq[9] * Ar * cp * cq / (kPi * d2));
+      sr = Ray{pg, wi, 0.0, 1.0};
+    }
+    if (!want_certain && !skip_certain) R.n_ambiguous_shading++;
+    if (shadow < 0 && want_certain) return fail(7, k);
+    if (shadow >= 0 && skip_certain) return fail(7, k);
+    if (shadow >= 0) {
+      const AcceptSet As = accept_set(S, sr, here, 0.0, mode);
+      if (judge_any(As, shadow == 1)) return fail(8, k);
+      if (shadow == 0) c = cval;
+    }
+    Lsum += beta * a * c;
+    if (!has_next) break;
+    // the next ray: from the FP32 hit point along the cosine sample
+    const Ray nr = ray_of(k + 1);
+    if (nr.o.x != pg.x || nr.o.y != pg.y || nr.o.z != pg.z) return fail(9, k + 1);
+    uint32_t w2[4];
+    uint32_t ctr2[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, (uint32_t)k};
+    philox(ctr2, key, w2);
+    const V3 de = cosine_sample(n, unit(w2[2]), unit(w2[3]), false);
+    double err = norm(nr.d - de);
+    if (std::fabs(n.z) < 1e-6) {
+      R.n_ambiguous_shading++;
+      err = std::min(err, norm(nr.d - cosine_sample(n, unit(w2[2]), unit(w2[3]), true)));
+    }
+    if (err > 1e-5) return fail(10, k + 1);
+    beta *= a;
+    ex = here;
+  }
+  // radiance: the FP64 value along these decisions, for each environment
+  // texel the escaping ray may read
+  if (esc_vals.empty()) esc_vals.push_back(0.0);
+  double best = kInf, Lbest = 0.0;
+  for (double e : esc_vals) {
+    const double Lv = Lsum + (escaped ? beta * e : 0.0);
+    const double err = std::fabs((double)radiance - Lv);
+    if (err < best) {
+      best = err;
+      Lbest = Lv;
+    }
+  }
+  R.L = Lbest;
+  if (best > 1e-4 * std::fabs(Lbest) + 1e-7) return fail(12, nv);
+  return R;
+}
+
 template <class Fn>
 void parallel_for(int64_t n, int nthreads, Fn&& fn) {
   if (nthreads <= 1 || n < 2) {
@@ -775,14 +1236,16 @@ int threads() {
   return h ? (int)h : 1;
 }
 
-void resolve_pixel(const std::vector<Cam>& cams, int64_t g, int32_t* view, int64_t* pix) {
+// Packed image index g -> camera entry, pixel of the whole view (row-major).
+void resolve_pixel(const std::vector<Cam>& cams, int64_t g, int32_t* cam, int64_t* pix) {
   for (size_t c = 0; c < cams.size(); ++c)
-    if (g >= cams[c].off && g < cams[c].off + cams[c].w * cams[c].h) {
-      *view = (int32_t)c;
-      *pix = g - cams[c].off;
+    if (g >= cams[c].off && g < cams[c].off + cams[c].tw * cams[c].th) {
+      const int64_t local = g - cams[c].off;
+      *cam = (int32_t)c;
+      *pix = (cams[c].ty + local / cams[c].tw) * cams[c].w + cams[c].tx + local % cams[c].tw;
       return;
     }
-  *view = -1;
+  *cam = -1;
   *pix = -1;
 }
 
@@ -938,6 +1401,71 @@ void orc_trace_d(void* s, int64_t n, const double* rays, const int32_t* excl, co
   trace_many(s, n, rays, excl, r0, mode, any_hit, t, inst, prim, half, u, v, flags, cand, ncand, scale);
 }
 
+// Whether each GPU answer is one an FP32 traversal may give (see accept_set).
+// rays: n x 8 FP32; excl: n x 3 or NULL; r0: per ray or NULL.  Closest hit
+// (any_hit = 0): g_inst, g_prim (-1 = miss), g_half (NULL = either half), g_t.
+// Any hit: g_inst[i] = 1 occluded, 0 not.  out[i]: 0 valid; closest: 1 not a
+// possible answer, 2 a miss while a certain hit exists, 3 t outside its
+// tolerance; any hit: 1 occluded without a possible occluder, 2 unoccluded
+// while a certain occluder exists.  info[i] (may be NULL): bit 1 the answer is
+// the certain hit, bit 2 its t check was waived (ill-conditioned), bit 4 the ray
+// has possible answers other than the certain hit.
+void orc_accept(void* s, int64_t n, const float* rays, const int32_t* excl, const double* r0, int32_t mode,
+                int32_t any_hit, const int32_t* g_inst, const int32_t* g_prim, const int32_t* g_half,
+                const float* g_t, int32_t* out, int32_t* info) {
+  const Scene& S = *static_cast<Scene*>(s);
+  parallel_for(n, threads(), [&](int64_t i, int) {
+    const float* R = rays + 8 * i;
+    Ray r{{(double)R[0], (double)R[1], (double)R[2]}, {(double)R[3], (double)R[4], (double)R[5]}, (double)R[6],
+          (double)R[7]};
+    Excl ex;
+    if (excl) ex = {excl[3 * i], excl[3 * i + 1], excl[3 * i + 2]};
+    const AcceptSet A = accept_set(S, r, ex, r0 ? r0[i] : 0.0, mode);
+    int inf = 0;
+    if (any_hit) {
+      out[i] = judge_any(A, g_inst[i] != 0);
+    } else {
+      out[i] = judge_closest(A, g_inst[i], g_inst[i] < 0 ? -1 : g_prim[i], g_half ? g_half[i] : -1,
+                             (double)g_t[i], &inf);
+    }
+    size_t others = 0;
+    for (const Cand& c : A.cand)
+      if (!A.has_certain || c.k.inst != A.certain.k.inst || c.k.prim != A.certain.k.prim) ++others;
+    if (others || !A.has_certain) inf |= 4;
+    if (info) info[i] = inf;
+  });
+}
+
+// Check one GPU path (cam entry `cam`, pixel `local` of its rectangle, sample)
+// against the scene along its own recorded rays (see check_path).  Returns 0
+// when valid, else the first failed check: 1 camera ray, 2 a hit that is not a
+// possible answer, 3 an escape while a certain hit exists, 4 t outside its
+// tolerance, 5 face index, 6 shading value (albedo or texel), 7 shadow ray cast
+// or not against a clear decision, 8 shadow outcome, 9 next origin is not the
+// FP32 hit point, 10 next direction, 11 path length, 12 radiance.  stats
+// (may be NULL): [failing ray, FP64 radiance, vertices, certain answers,
+// t checks waived, shading decisions within rounding of a threshold].
+int32_t orc_check_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
+                       const uint64_t* pu, const double* pd, int32_t cam, int64_t local, int32_t sample, int32_t nv,
+                       const int32_t* vi, const float* vf, int32_t escaped, float radiance, double* stats) {
+  const Scene& S = *static_cast<Scene*>(s);
+  const Params P = make_params(pi, pu, pd);
+  if (cam < 0 || cam >= n_cams) return -1;
+  const Cam c = make_cam(cam_f + 10 * cam, cam_i + 8 * cam);
+  if (local < 0 || local >= c.tw * c.th) return -1;
+  const int64_t pix = (c.ty + local / c.tw) * c.w + c.tx + local % c.tw;
+  const PathCheck R = check_path(S, P, c, (int32_t)c.view_id, pix, sample, nv, vi, vf, escaped != 0, radiance, 1);
+  if (stats) {
+    stats[0] = R.vertex;
+    stats[1] = R.L;
+    stats[2] = R.n_vert;
+    stats[3] = R.n_certain;
+    stats[4] = R.n_waived;
+    stats[5] = R.n_ambiguous_shading;
+  }
+  return R.code;
+}
+
 // Image (or listed pixels) of n_cams pinhole cameras.  cam_f: n x 10 (eye, look,
 // up, vfov); cam_i: n x 3 (w, h, offset of the view in the packed image).
 // pix: global packed pixel indices, or NULL for every pixel.  stats (may be NULL):
@@ -950,7 +1478,7 @@ void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_ca
   std::vector<Cam> cams;
   int64_t total = 0;
   for (int c = 0; c < n_cams; ++c) {
-    cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
+    cams.push_back(make_cam(cam_f + 10 * c, cam_i + 8 * c));
     total += cams.back().w * cams.back().h;
   }
   const int64_t n = pix ? n_pix : total;
@@ -965,7 +1493,7 @@ void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_ca
     uint32_t fl = 0;
     for (int32_t smp = 0; smp < P.spp; ++smp) {
       PathRec rec;
-      trace_path(S, P, cams[view], view, p, smp, mode, rec);
+      trace_path(S, P, cams[view], (int32_t)cams[view].view_id, p, smp, mode, rec);
       sum += path_value(P, rec);
       fl |= rec.flags;
       st[4 * tid + 0] += rec.n_closest;
@@ -992,12 +1520,12 @@ void orc_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
   const Scene& S = *static_cast<Scene*>(s);
   const Params P = make_params(pi, pu, pd);
   std::vector<Cam> cams;
-  for (int c = 0; c < n_cams; ++c) cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
+  for (int c = 0; c < n_cams; ++c) cams.push_back(make_cam(cam_f + 10 * c, cam_i + 8 * c));
   int32_t view;
   int64_t p;
   resolve_pixel(cams, g, &view, &p);
   PathRec rec;
-  trace_path(S, P, cams[view], view, p, sample, 1, rec);
+  trace_path(S, P, cams[view], (int32_t)cams[view].view_id, p, sample, 1, rec);
   *nv = rec.nv;
   for (int k = 0; k < rec.nv; ++k) {
     const Vertex& v = rec.v[k];
@@ -1024,7 +1552,7 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
   std::vector<Cam> cams;
   int64_t total = 0;
   for (int c = 0; c < n_cams; ++c) {
-    cams.push_back(make_cam(cam_f + 10 * c, cam_i + 3 * c));
+    cams.push_back(make_cam(cam_f + 10 * c, cam_i + 8 * c));
     total += cams.back().w * cams.back().h;
   }
   const int64_t n = pix ? n_pix : total;
@@ -1043,7 +1571,7 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
     std::vector<int64_t> faces;  // every face on the pixel's paths
     for (int32_t smp = 0; smp < P.spp; ++smp) {
       PathRec rec;
-      trace_path(S, P, cams[view], view, p, smp, mode, rec);
+      trace_path(S, P, cams[view], (int32_t)cams[view].view_id, p, smp, mode, rec);
       fl |= rec.flags;
       if (!taint_per_path || rec.flags)
         for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].param);
