@@ -161,6 +161,9 @@ int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);
 /*
  * Replace the per-face albedo (device memory, n = total unique quads, in
  * prototype order) without rebuilding.  Enqueued on `stream` (a device copy).
+ * Not part of the paper's system (its colours come from Ptex textures, Section
+ * 5.3): this library's addition for gradient-driven loops over the albedo
+ * (rtq_render_backward).
  */
 int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, hipStream_t stream);
 
@@ -212,11 +215,19 @@ typedef struct {
   const float *ox, *oy, *oz; /* origin */
   const float *dx, *dy, *dz; /* direction, need not be normalised; t is in its units */
   const float *tmin, *tmax;  /* accepted interval tmin < t <= tmax */
+  const uint32_t* exclude;   /* optional (NULL: none), 2 words per ray: the hit reference
+                                (rtq_hits.ref) of a triangle the ray must not hit -- the one a
+                                secondary or shadow ray leaves; the pair 0xFFFFFFFF 0xFFFFFFFF
+                                excludes nothing */
 } rtq_rays;
 
 typedef struct {
   float *t, *u, *v;      /* miss: t = +inf, u = v = 0 */
   int32_t *inst, *prim;  /* miss: -1, -1; prim is the quad index within its prototype */
+  uint32_t* ref;         /* optional (NULL: not written), 2 words per ray: an opaque reference of the
+                            hit triangle (top-level entry; leaf-ordered quad, and the half in bit 31)
+                            valid for this scene, for rtq_rays.exclude of rays that leave it; a miss
+                            writes 0xFFFFFFFF 0xFFFFFFFF */
 } rtq_hits;
 
 #define RTQ_SCHED_PLAIN 0      /* one ray per lane for its whole traversal */
@@ -235,7 +246,10 @@ typedef struct {
 } rtq_trace_opts;
 
 /*
- * Closest hit of n rays (device SoA in, device SoA out), enqueued on `stream`.
+ * Closest hit of n rays (device SoA in, device SoA out), enqueued on `stream`:
+ * the ray query of the path tracer's camera and bounce rays (Section 5.2:
+ * instances of quad meshes traced directly; Section 5.3: the hit carries the
+ * primitive id and the coordinates on the quad that a texture lookup needs).
  * opts may be NULL.  Zero-length or NaN directions miss.  n may be 0.
  * Errors: LIMIT when n exceeds 2^31 - 1 (a dispatch counts its work-items in
  * 32 bits); INVALID_ARG for NULL arrays or options out of range.
@@ -243,7 +257,12 @@ typedef struct {
 int rtq_trace_closest(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits,
                       const rtq_trace_opts* opts, hipStream_t stream);
 
-/* Occlusion: occluded[i] = 1 if any hit with tmin < t <= tmax exists, else 0. */
+/*
+ * Occlusion: occluded[i] = 1 if any hit with tmin < t <= tmax exists, else 0 --
+ * the shadow-ray query of next-event estimation (Section 5.4 samples the
+ * scene's lights at every path vertex).  Arguments and errors as
+ * rtq_trace_closest.
+ */
 int rtq_trace_occluded(const rtq_scene* scene, const rtq_rays* rays, int64_t n, uint8_t* occluded,
                        const rtq_trace_opts* opts, hipStream_t stream);
 
@@ -255,11 +274,24 @@ int rtq_trace_occluded(const rtq_scene* scene, const rtq_rays* rays, int64_t n, 
 int rtq_trace_brute(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits, hipStream_t stream);
 
 /* ------------------------------------------------------------------ rendering */
+/*
+ * One pinhole view, or a rectangle of one (Section 5.5: image-parallel
+ * rendering deals the tiles of a frame to the workers).  The random-number
+ * counter of a path is (pixel of the whole view, sample, view_id, bounce), so a
+ * view rendered whole in one call, or tile by tile in several calls (or on
+ * several devices), gives bit-identical pixels as long as view_id, the view's
+ * parameters and the render options are the same.
+ */
 typedef struct {
   float eye[3], look[3], up[3];
   float vfov_deg;
-  int32_t w, h;
-  int64_t img_offset; /* first pixel of this view in the packed image buffer */
+  int32_t w, h;        /* resolution of the whole view */
+  int64_t img_offset;  /* first pixel of the rendered rectangle in the packed image buffer */
+  int32_t view_id;     /* the view's index in the random-number counter, >= 0.  Cameras of one call
+                          need distinct ids unless they are tiles of one view. */
+  int32_t tile_x, tile_y, tile_w, tile_h; /* rendered rectangle: columns [tile_x, tile_x + tile_w),
+                          rows [tile_y, tile_y + tile_h); tile_w = tile_h = 0 renders the whole view.
+                          Its pixels are stored row by row from img_offset (tile_w per row). */
 } rtq_camera;
 
 typedef struct {
@@ -279,16 +311,23 @@ typedef struct {
   int32_t stack_depth, block, waves_per_cu, refill; /* as rtq_trace_opts */
   uint64_t* counters;  /* optional device [4]: closest rays, shadow rays, incoherent
                           (bounce >= 1) rays, paths; accumulated (caller zeroes) */
-  uint64_t* view_done; /* optional device [n_cams]: wall-clock tick at which each
-                          view's last path finished (megakernel scheduler only) */
-  uint64_t* start_tick;/* optional device [1]: wall-clock tick at kernel start */
+  uint64_t* view_done; /* optional device [n_cams], zeroed by the caller: the
+                          wall-clock tick (the device's constant-rate clock,
+                          s_memrealtime) at which each camera entry's last path
+                          finished, in every scheduler (per-view latency of a
+                          batch of views, Section 6 reports per-view frame times) */
+  uint64_t* start_tick;/* optional device [1]: wall-clock tick at the start of the
+                          call's first kernel */
   uint64_t* visits;    /* optional device [8]: top-level nodes, instances entered,
                           bottom-level nodes and quads tested, summed over the
                           closest-hit rays ([0..3]) and over the shadow rays
                           ([4..7]) (accumulated; selects a slower counting variant) */
-  float* dump_rays;    /* optional device 8 x dump_cap floats, structure of arrays
-                          (ox, oy, oz, dx, dy, dz, tmin, tmax): extension rays of
-                          bounce >= 1 (plain and persistent schedulers) */
+  float* dump_rays;    /* optional device 10 x dump_cap 32-bit words, structure of
+                          arrays: ox, oy, oz, dx, dy, dz, tmin, tmax (FP32), then the
+                          two words of the hit reference of the triangle the ray
+                          leaves (uint32, as rtq_hits.ref, for rtq_rays.exclude):
+                          extension rays of bounce >= 1 (plain and persistent
+                          schedulers) */
   int64_t dump_cap;    /* capacity of dump_rays in rays */
   uint64_t* dump_count;/* device [1]: rays appended to dump_rays (accumulated; the
                           count may exceed dump_cap, rays beyond it are dropped) */
@@ -365,12 +404,15 @@ int rtq_render_timing(rtq_scene* scene, float* ms, int32_t* launches);
 /*
  * One path of rtq_render traced alone (same RNG counters, hits and shading as
  * the render kernels; node format and stack depth from opts), for path-level
- * checks: path (view, pixel, sample) with pixel = row * w + column.  Per vertex
+ * checks: path (view, pixel, sample) with view the camera entry and pixel the
+ * index within its rendered rectangle (row * width + column).  Per vertex
  * k < *n_vert: vert_i[6k..6k+5] = (instance id, primitive, half, shadow: -1 no
  * shadow ray / 0 light visible / 1 occluded, unique face, 0) and
  * vert_f[10k..10k+9] = (t, albedo or texel, cosine to the light, radiance after the
  * vertex, origin xyz and direction xyz of the ray that found the vertex);
- * *escaped = 1 if the path left the scene; *radiance = its total.
+ * *escaped = 1 if the path left the scene, and then record *n_vert holds the
+ * escaping ray (ids -1, t = +inf, its origin and direction); *radiance = the
+ * path's total.
  * vert_i: host, 6 depth int32; vert_f: host, 10 depth floats.  Synchronises
  * `stream`.  Errors: INVALID_ARG (view, pixel or sample out of range, NULL
  * outputs), as rtq_render otherwise.
@@ -380,6 +422,8 @@ int rtq_render_path(const rtq_scene* scene, const rtq_camera* cams, int32_t n_ca
                     float* vert_f, int32_t* n_vert, int32_t* escaped, float* radiance, hipStream_t stream);
 
 /*
+ * Not part of the paper's system: this library's addition, a path-replay
+ * adjoint (after Vicini, Speierer and Jakob 2021) of the renderer above.
  * Adjoint of rtq_render with respect to per-face albedo, paths held fixed:
  * grad_albedo[f] += sum over pixels p of grad_images[p] * dI_p / d albedo[f].
  * Each path is replayed from its RNG counters (same hits as the forward pass).

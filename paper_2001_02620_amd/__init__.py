@@ -58,11 +58,11 @@ class _Info(ctypes.Structure):
 
 
 class _Rays(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_void_p) for k in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin", "tmax")]
+    _fields_ = [(k, ctypes.c_void_p) for k in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin", "tmax", "exclude")]
 
 
 class _Hits(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_void_p) for k in ("t", "u", "v", "inst", "prim")]
+    _fields_ = [(k, ctypes.c_void_p) for k in ("t", "u", "v", "inst", "prim", "ref")]
 
 
 class _TraceOpts(ctypes.Structure):
@@ -74,7 +74,8 @@ class _TraceOpts(ctypes.Structure):
 class _Camera(ctypes.Structure):
     _fields_ = [("eye", ctypes.c_float * 3), ("look", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
                 ("vfov_deg", ctypes.c_float), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
-                ("img_offset", ctypes.c_int64)]
+                ("img_offset", ctypes.c_int64), ("view_id", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
 
 
 class _RenderOpts(ctypes.Structure):
@@ -257,15 +258,21 @@ class Hits:
     v: object
     inst: object
     prim: object
+    ref: object = None  # [n, 2] int32 view of the opaque hit references, when asked for
 
 
-def _rays_struct(rays):
-    """rays: CUDA float32 tensor [n, 8] (ox oy oz dx dy dz tmin tmax) -> SoA copy + struct."""
+def _rays_struct(rays, exclude=None):
+    """rays: CUDA float32 tensor [n, 8] (ox oy oz dx dy dz tmin tmax) -> SoA copy + struct;
+    exclude: optional CUDA int32 tensor [n, 2] of hit references (Hits.ref) not to hit."""
     torch = _torch()
     assert rays.is_cuda and rays.dim() == 2 and rays.shape[1] == 8
     soa = rays.to(torch.float32).t().contiguous()
-    st = _Rays(*[soa[k].data_ptr() for k in range(8)])
-    return soa, st
+    ex = None
+    if exclude is not None:
+        assert exclude.is_cuda and exclude.shape == (rays.shape[0], 2) and exclude.dtype == torch.int32
+        ex = exclude.contiguous()
+    st = _Rays(*[soa[k].data_ptr() for k in range(8)], _ptr(ex))
+    return (soa, ex), st
 
 
 def _trace_opts(node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
@@ -273,14 +280,17 @@ def _trace_opts(node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, wa
     return _TraceOpts(node_format, scheduler, stack_depth, block, waves_per_cu, refill, _ptr(visits))
 
 
-def trace_closest(scene: Scene, rays, **opts) -> Hits:
+def trace_closest(scene: Scene, rays, exclude=None, want_ref: bool = False, **opts) -> Hits:
+    """Closest hits of rays [n, 8]; exclude: optional [n, 2] int32 hit references
+    of triangles the rays leave; want_ref: also return each hit's reference."""
     torch = _torch()
     n = rays.shape[0]
-    soa, st = _rays_struct(rays)
+    soa, st = _rays_struct(rays, exclude)
     dev = rays.device
     h = Hits(torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev),
-             torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
-    hs = _Hits(h.t.data_ptr(), h.u.data_ptr(), h.v.data_ptr(), h.inst.data_ptr(), h.prim.data_ptr())
+             torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+             torch.empty((n, 2), dtype=torch.int32, device=dev) if want_ref else None)
+    hs = _Hits(h.t.data_ptr(), h.u.data_ptr(), h.v.data_ptr(), h.inst.data_ptr(), h.prim.data_ptr(), _ptr(h.ref))
     o = _trace_opts(**opts)
     _check(load_library().rtq_trace_closest(scene.handle, ctypes.byref(st), n, ctypes.byref(hs), ctypes.byref(o),
                                             _stream()))
@@ -288,10 +298,10 @@ def trace_closest(scene: Scene, rays, **opts) -> Hits:
     return h
 
 
-def trace_occluded(scene: Scene, rays, **opts):
+def trace_occluded(scene: Scene, rays, exclude=None, **opts):
     torch = _torch()
     n = rays.shape[0]
-    soa, st = _rays_struct(rays)
+    soa, st = _rays_struct(rays, exclude)
     occ = torch.empty(n, dtype=torch.uint8, device=rays.device)
     o = _trace_opts(**opts)
     _check(load_library().rtq_trace_occluded(scene.handle, ctypes.byref(st), n, occ.data_ptr(), ctypes.byref(o),
@@ -300,14 +310,14 @@ def trace_occluded(scene: Scene, rays, **opts):
     return occ
 
 
-def trace_brute(scene: Scene, rays) -> Hits:
+def trace_brute(scene: Scene, rays, exclude=None) -> Hits:
     torch = _torch()
     n = rays.shape[0]
-    soa, st = _rays_struct(rays)
+    soa, st = _rays_struct(rays, exclude)
     dev = rays.device
     h = Hits(torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev),
              torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
-    hs = _Hits(h.t.data_ptr(), h.u.data_ptr(), h.v.data_ptr(), h.inst.data_ptr(), h.prim.data_ptr())
+    hs = _Hits(h.t.data_ptr(), h.u.data_ptr(), h.v.data_ptr(), h.inst.data_ptr(), h.prim.data_ptr(), None)
     _check(load_library().rtq_trace_brute(scene.handle, ctypes.byref(st), n, ctypes.byref(hs), _stream()))
     h._keep = soa
     return h
@@ -315,6 +325,9 @@ def trace_brute(scene: Scene, rays) -> Hits:
 
 # ----------------------------------------------------------------------------- rendering
 def camera_structs(cams) -> tuple:
+    """C cameras packed one after the other in the image buffer; a camera's
+    view id defaults to its position in the list, its rectangle to the whole
+    view.  Returns (array, total pixels)."""
     arr = (_Camera * len(cams))()
     off = 0
     for k, c in enumerate(cams):
@@ -325,7 +338,13 @@ def camera_structs(cams) -> tuple:
         arr[k].w = c.w
         arr[k].h = c.h
         arr[k].img_offset = off
-        off += c.w * c.h
+        vid = getattr(c, "view_id", None)
+        arr[k].view_id = k if vid is None else int(vid)
+        tile = getattr(c, "tile", None)
+        if tile is None:
+            tile = (0, 0, 0, 0)
+        arr[k].tile_x, arr[k].tile_y, arr[k].tile_w, arr[k].tile_h = (int(x) for x in tile)
+        off += (c.w * c.h) if tile[2] == 0 and tile[3] == 0 else tile[2] * tile[3]
     return arr, off
 
 
@@ -349,7 +368,7 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.start_tick = _ptr(start_tick)
     o.visits = _ptr(visits)
     o.dump_rays = _ptr(dump_rays)
-    o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 8
+    o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 10
     o.dump_count = _ptr(dump_count)
     o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0
@@ -404,6 +423,22 @@ def render_path(scene: Scene, cams, settings, view: int, pixel: int, sample: int
                   origin=tuple(vf[10 * k + 4:10 * k + 7]), direction=tuple(vf[10 * k + 7:10 * k + 10]))
              for k in range(nv.value)]
     return verts, bool(esc.value), float(rad.value)
+
+
+def render_path_raw(scene: Scene, cams, settings, view: int, pixel: int, sample: int, **opts):
+    """One path traced alone, as recorded by the library: (n_vert, vi [depth, 6]
+    int32, vf [depth, 10] float32, escaped, radiance); when the path escaped, row
+    n_vert holds the escaping ray."""
+    arr, _ = camera_structs(cams)
+    o = render_opts(settings, **opts)
+    d = settings.depth
+    vi = np.zeros((d, 6), np.int32)
+    vf = np.zeros((d, 10), np.float32)
+    nv, esc, rad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(load_library().rtq_render_path(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
+                                          d, ctypes.byref(o), view, pixel, sample, vi.ctypes.data, vf.ctypes.data,
+                                          ctypes.byref(nv), ctypes.byref(esc), ctypes.byref(rad), _stream()))
+    return nv.value, vi, vf, bool(esc.value), np.float32(rad.value)
 
 
 def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None, **opts):

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -233,7 +234,11 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     for (auto& t : th) t.join();
   }
 
-  rtq_scene* s = new rtq_scene;
+  // owned by `holder` until the build succeeds: every failure below (an early
+  // return or a host allocation failure thrown out of the builders) frees the
+  // scene and its device buffers, and `tmp` frees itself
+  std::unique_ptr<rtq_scene> holder(new rtq_scene);
+  rtq_scene* s = holder.get();
   s->build_phase[0] = since(t0);
   auto t1 = std::chrono::steady_clock::now();
   s->device = dev;
@@ -254,11 +259,9 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   int max_blas_depth = 0;
   for (int32_t p = 0; p < n_protos; ++p) {
     if (node_base + blas[p].f32.size() >= (uint64_t)kLeafBit) {
-      delete s;
       return set_error(RTQ_E_LIMIT, "bottom-level node count exceeds 2^31");
     }
     if (!relocate(blas[p], (uint32_t)node_base, (uint32_t)quad_base)) {
-      delete s;
       return set_error(RTQ_E_LIMIT, "reference overflow while relocating prototype %d", p);
     }
     proto_root[p] = (uint32_t)node_base;
@@ -267,7 +270,6 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     proto_nq[p] = protos[p].n_quads;
     proto_pmax[p] = level_pmax(blas[p]);
     if (!(proto_pmax[p] < kMaxPlaneAbs)) {
-      delete s;
       return set_error(RTQ_E_LIMIT, "prototype %d has coordinates beyond 2^60", p);
     }
     max_blas_depth = std::max(max_blas_depth, blas[p].depth);
@@ -295,17 +297,12 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     for (int32_t q = 0; q < P.n_quads; ++q) albedo[qb + q] = P.albedo ? P.albedo[q] : 0.5f;
   }
 
-  auto fail = [&](int code) {
-    s->bufs.release();
-    delete s;
-    return code;
-  };
 #define UPLOAD(dst, src, bytes)                                                   \
   do {                                                                            \
     dst = reinterpret_cast<decltype(dst)>(s->bufs.alloc((bytes), &e));            \
-    if (!dst) return fail(hip_error(e, "hipMalloc"));                             \
+    if (!dst) return hip_error(e, "hipMalloc");                                   \
     e = hipMemcpy((void*)dst, (src), (bytes), hipMemcpyHostToDevice);             \
-    if (e != hipSuccess) return fail(hip_error(e, "hipMemcpy"));                  \
+    if (e != hipSuccess) return hip_error(e, "hipMemcpy");                        \
   } while (0)
 
   // bottom levels first; the top level is appended once it is built.  The FP32
@@ -337,19 +334,15 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   int32_t* d_status = nullptr;
   InstRec* d_rec = nullptr;
   DeviceBuffers tmp;
-  auto tfail = [&](int code) {
-    tmp.release();
-    return fail(code);
-  };
 #define TALLOC(dst, bytes)                                                         \
   do {                                                                             \
     dst = reinterpret_cast<decltype(dst)>(tmp.alloc((bytes), &e));                 \
-    if (!dst) return tfail(hip_error(e, "hipMalloc"));                             \
+    if (!dst) return hip_error(e, "hipMalloc");                                    \
   } while (0)
 #define TCHECK(expr, what)                                                         \
   do {                                                                             \
     e = (expr);                                                                    \
-    if (e != hipSuccess) return tfail(hip_error(e, what));                         \
+    if (e != hipSuccess) return hip_error(e, what);                                \
   } while (0)
   TALLOC(d_x, 12 * Nn * sizeof(float));
   TALLOC(d_proto, Nn * sizeof(int32_t));
@@ -389,7 +382,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   for (int64_t i = 0; i < N; ++i) {
     if (status[i]) {
       const int code = set_error(RTQ_E_SINGULAR_XFORM, "instance %lld has a singular transform", (long long)i);
-      return tfail(code);
+      return code;
     }
     cond_max = std::max(cond_max, cond[i]);
   }
@@ -441,13 +434,13 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     build_bvh4(&none, 1, tp, tlas);  // placeholder root; n_rec = 0 makes every ray miss first
   }
   if (n_blas_nodes + tlas.f32.size() >= (uint64_t)kLeafBit)
-    return tfail(set_error(RTQ_E_LIMIT, "node count exceeds 2^31"));
+    return set_error(RTQ_E_LIMIT, "node count exceeds 2^31");
   if (!relocate(tlas, (uint32_t)n_blas_nodes, 0u))
-    return tfail(set_error(RTQ_E_LIMIT, "top-level reference overflow"));
+    return set_error(RTQ_E_LIMIT, "top-level reference overflow");
   if (3 * (tlas.depth + max_blas_depth) + 8 > kStackTotal)
-    return tfail(set_error(RTQ_E_LIMIT, "BVH depth %d + %d exceeds the traversal stack", tlas.depth, max_blas_depth));
+    return set_error(RTQ_E_LIMIT, "BVH depth %d + %d exceeds the traversal stack", tlas.depth, max_blas_depth);
   s->p_world = level_pmax(tlas);
-  if (!(s->p_world < kMaxPlaneAbs)) return tfail(set_error(RTQ_E_LIMIT, "instance boxes reach beyond 2^60"));
+  if (!(s->p_world < kMaxPlaneAbs)) return set_error(RTQ_E_LIMIT, "instance boxes reach beyond 2^60");
   s->tlas_root = (uint32_t)n_blas_nodes;
   s->tlas_depth = tlas.depth;
   s->tlas_nodes = (int64_t)tlas.f32.size();
@@ -479,7 +472,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     UPLOAD(s->rec_qfirst, rec_qfirst.data(), rec_qfirst.size() * sizeof(uint32_t));
     UPLOAD(s->rec_nq, rec_nq.data(), rec_nq.size() * sizeof(uint32_t));
     s->inst = reinterpret_cast<InstRec*>(s->bufs.alloc(En * sizeof(InstRec), &e));
-    if (!s->inst) return tfail(hip_error(e, "hipMalloc"));
+    if (!s->inst) return hip_error(e, "hipMalloc");
     if (E > 0) {
       uint32_t *d_order, *d_eroot;
       TALLOC(d_order, E * sizeof(uint32_t));
@@ -491,13 +484,13 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   }
   s->counters = reinterpret_cast<unsigned long long*>(
       s->bufs.alloc((size_t)rtq_scene::kCounterSlots * kClaimWords * sizeof(unsigned long long), &e));
-  if (!s->counters) return tfail(hip_error(e, "hipMalloc"));
+  if (!s->counters) return hip_error(e, "hipMalloc");
   TCHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
   tmp.release();
   for (int64_t i = 0; i < N; ++i) s->n_instanced_quads += protos[insts->proto[i]].n_quads;
   s->build_phase[3] = since(t1);
   s->build_seconds = since(t0);
-  *out = s;
+  *out = holder.release();
   return RTQ_OK;
 #undef UPLOAD
 #undef TALLOC
@@ -622,7 +615,9 @@ static int check_rays(const rtq_scene* s, const rtq_rays* r, int64_t n) {
   return RTQ_OK;
 }
 
-static RaysSoA soa(const rtq_rays* r) { return RaysSoA{r->ox, r->oy, r->oz, r->dx, r->dy, r->dz, r->tmin, r->tmax}; }
+static RaysSoA soa(const rtq_rays* r) {
+  return RaysSoA{r->ox, r->oy, r->oz, r->dx, r->dy, r->dz, r->tmin, r->tmax, r->exclude};
+}
 
 static int trace_common(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hits* hits, uint8_t* occ,
                         const rtq_trace_opts* opts, hipStream_t stream) {
@@ -638,7 +633,7 @@ static int trace_common(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq
   if (n == 0) return RTQ_OK;
   const SceneView sv = scene_view(s, fmt);
   HitsSoA h{};
-  if (hits) h = HitsSoA{hits->t, hits->u, hits->v, hits->inst, hits->prim};
+  if (hits) h = HitsSoA{hits->t, hits->u, hits->v, hits->inst, hits->prim, hits->ref};
   const hipError_t e = launch_trace(sv, soa(rays), n, hits ? &h : nullptr, occ, o.visits, tl, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "trace launch");
 }
@@ -707,7 +702,7 @@ int rtq_trace_brute(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hit
   if (!hits || (n > 0 && (!hits->t || !hits->u || !hits->v || !hits->inst || !hits->prim)))
     return set_error(RTQ_E_INVALID_ARG, "NULL hit array");
   const SceneView sv = scene_view(s, (s->formats & RTQ_NODE_FP32) ? RTQ_NODE_FP32 : RTQ_NODE_Q8);
-  const HitsSoA h{hits->t, hits->u, hits->v, hits->inst, hits->prim};
+  const HitsSoA h{hits->t, hits->u, hits->v, hits->inst, hits->prim, hits->ref};
   const hipError_t e = launch_trace_brute(sv, soa(rays), n, h, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "brute launch");
 }

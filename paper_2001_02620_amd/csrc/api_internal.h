@@ -15,9 +15,15 @@
 
 namespace rtq {
 
+// Device allocations owned together; freed by release() or on destruction, so
+// an early return or an exception on a failure path leaks nothing.
 struct DeviceBuffers {
   std::vector<void*> ptrs;
   size_t total = 0;
+  DeviceBuffers() = default;
+  DeviceBuffers(const DeviceBuffers&) = delete;
+  DeviceBuffers& operator=(const DeviceBuffers&) = delete;
+  ~DeviceBuffers() { release(); }
   void* alloc(size_t bytes, hipError_t* err);
   void release();
 };

@@ -186,9 +186,15 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
   return RTQ_OK;
 }
 
+// Pixels of the rectangle a camera renders (prepare() has validated it).
+int64_t rect_pixels(const rtq_camera& C) {
+  return C.tile_w == 0 && C.tile_h == 0 ? (int64_t)C.w * C.h : (int64_t)C.tile_w * C.tile_h;
+}
+
 struct Prepared {
   RenderParams rp;
   int64_t n_pixels;
+  std::string layout;  // every camera's size, rectangle, view id and image offset
   int fmt;
   TraceLaunch tl;
 };
@@ -220,12 +226,22 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   for (int32_t k = 0; k < 10 * opts->n_area_lights; ++k)
     if (!std::isfinite(opts->area_lights[k])) return set_error(RTQ_E_INVALID_ARG, "non-finite area light %d", k / 10);
   std::vector<CamDev> cd(n_cams);
+  out->layout.clear();
   std::vector<std::pair<int64_t, int64_t>> ranges;
   int64_t path_base = 0, n_pixels = 0;
   for (int32_t c = 0; c < n_cams; ++c) {
     const rtq_camera& C = cams[c];
     if (C.w < 1 || C.h < 1 || C.img_offset < 0)
       return set_error(RTQ_E_INVALID_ARG, "camera %d: bad resolution or offset", c);
+    if ((int64_t)C.w * C.h > (int64_t)0xFFFFFFFFll)
+      return set_error(RTQ_E_LIMIT, "camera %d has more than 2^32 pixels", c);
+    if (C.view_id < 0) return set_error(RTQ_E_INVALID_ARG, "camera %d: view_id %d < 0", c, C.view_id);
+    const bool whole = C.tile_w == 0 && C.tile_h == 0;
+    const int32_t tx = whole ? 0 : C.tile_x, ty = whole ? 0 : C.tile_y;
+    const int32_t tw = whole ? C.w : C.tile_w, th = whole ? C.h : C.tile_h;
+    if (tx < 0 || ty < 0 || tw < 1 || th < 1 || tw > C.w - tx || th > C.h - ty)
+      return set_error(RTQ_E_INVALID_ARG, "camera %d: tile (%d, %d, %d x %d) outside the %d x %d view", c, tx, ty,
+                       tw, th, C.w, C.h);
     const double ex = C.eye[0], ey = C.eye[1], ez = C.eye[2];
     double f[3] = {C.look[0] - ex, C.look[1] - ey, C.look[2] - ez};
     const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
@@ -253,13 +269,21 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
     d.aspect = (float)((double)C.w / (double)C.h);
     d.w = C.w;
     d.h = C.h;
+    d.view_id = C.view_id;
+    d.tx = tx;
+    d.ty = ty;
+    d.tw = tw;
+    d.th = th;
     d.img_offset = C.img_offset;
     d.path_base = path_base;
-    const int64_t wh = (int64_t)C.w * C.h;
-    if (wh > (int64_t)0xFFFFFFFFll) return set_error(RTQ_E_LIMIT, "camera %d has more than 2^32 pixels", c);
+    const int64_t wh = (int64_t)tw * th;
     path_base += wh * spp;
     n_pixels = std::max(n_pixels, C.img_offset + wh);
     ranges.push_back({C.img_offset, C.img_offset + wh});
+    char lay[128];
+    std::snprintf(lay, sizeof(lay), "%d %d %d %d %d %d %d %lld;", C.w, C.h, C.view_id, tx, ty, tw, th,
+                  (long long)C.img_offset);
+    out->layout += lay;
   }
   std::sort(ranges.begin(), ranges.end());
   for (size_t k = 1; k < ranges.size(); ++k)
@@ -332,7 +356,9 @@ int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prep
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
                 (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights,
                 (const void*)sv.env, (int)sv.env_w, (int)sv.env_h);
-  const std::string k(key);
+  // the accumulation grid and its bound bake in the packed image size, and the
+  // camera layout decides which image pixels a replay writes
+  const std::string k = std::string(key) + "|" + std::to_string((long long)p.n_pixels) + "|" + p.layout;
   auto it = r->graphs.find(k);
   if (it == r->graphs.end()) {
     hipError_t e;
@@ -487,14 +513,14 @@ int rtq_render_path(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, 
                     float* vert_f, int32_t* n_vert, int32_t* escaped, float* radiance, hipStream_t stream) {
   if (!vert_i || !vert_f || !n_vert || !escaped || !radiance) return set_error(RTQ_E_INVALID_ARG, "NULL output");
   if (!cams || view < 0 || view >= n_cams) return set_error(RTQ_E_INVALID_ARG, "view %d outside [0, %d)", view, n_cams);
-  const int64_t wh = (int64_t)cams[view].w * cams[view].h;
-  if (pixel < 0 || pixel >= wh || sample < 0 || sample >= spp)
-    return set_error(RTQ_E_INVALID_ARG, "pixel or sample out of range");
   Prepared p;
   int rc = prepare(s, cams, n_cams, spp, depth, opts, false, stream, &p);
   if (rc) return rc;
+  const int64_t wh = rect_pixels(cams[view]);
+  if (pixel < 0 || pixel >= wh || sample < 0 || sample >= spp)
+    return set_error(RTQ_E_INVALID_ARG, "pixel or sample out of range");
   int64_t base = 0;
-  for (int32_t c = 0; c < view; ++c) base += (int64_t)cams[c].w * cams[c].h * spp;
+  for (int32_t c = 0; c < view; ++c) base += rect_pixels(cams[c]) * spp;
   const int64_t pid = base + (int64_t)sample * wh + pixel;
   hipError_t e;
   DeviceBuffers tmp;

@@ -20,10 +20,12 @@ hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 
 struct RaysSoA {
   const float *ox, *oy, *oz, *dx, *dy, *dz, *tmin, *tmax;
+  const uint32_t* exclude;  // optional: per ray (record, quad | half << 31) of the triangle it leaves
 };
 struct HitsSoA {
   float *t, *u, *v;
   int32_t *inst, *prim;
+  uint32_t* ref;  // optional: per ray (record, quad | half << 31) of the hit
 };
 
 struct TraceLaunch {

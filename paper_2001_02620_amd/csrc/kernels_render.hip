@@ -85,14 +85,31 @@ __device__ __forceinline__ unsigned long long wave_append64(bool want, unsigned 
   return (((unsigned long long)hi << 32) | lo) + rank;
 }
 
+// Per-view completion stamps: view_done[cam] = max over the view's paths of the
+// wall-clock tick at which the path ended, so it holds the tick at which the
+// view's last path finished.  One atomic per wave and distinct camera among the
+// lanes whose path ends here.  Must be reached by every lane of the wave.
+__device__ __forceinline__ void wave_stamp_views(bool ends, int cam, unsigned long long* view_done) {
+  unsigned long long pend = __ballot(ends);
+  if (pend == 0ull) return;
+  const unsigned long long now = (unsigned long long)wall_clock64();
+  const int lane = (int)(threadIdx.x & 63);
+  while (pend != 0ull) {
+    const int leader = __ffsll((long long)pend) - 1;
+    const int c = __builtin_amdgcn_readlane(cam, leader);
+    const unsigned long long same = __ballot(ends && cam == c);
+    if (lane == leader) atomicMax(&view_done[c], now);
+    pend &= ~same;
+  }
+}
+
 // ---------------------------------------------------------------- plain scheduler
 __global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
   const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pid == 0) counts[0] = (uint32_t)rp.n_paths;
   if (pid >= rp.n_paths) return;
-  int view;
-  uint32_t pixel, sample;
-  const Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
+  PathId id;
+  const Ray3 r = path_camera_ray(rp, pid, &id);
   q.ox[pid] = r.ox;
   q.oy[pid] = r.oy;
   q.oz[pid] = r.oz;
@@ -253,7 +270,7 @@ __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, 
 
 __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const uint32_t* count_in, QueueHits qh,
                         ExtQueue out, uint32_t* count_out, ShadowQueue sq, uint32_t* count_sq, float* dump,
-                        long long dump_cap, unsigned long long* dump_count) {
+                        long long dump_cap, unsigned long long* dump_count, unsigned long long* view_done) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < (int64_t)*count_in;
   bool want_shadow = false, want_next = false;
@@ -274,16 +291,15 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
       s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31, tex ? qh.u[i] : 0.0f,
                     tex ? qh.v[i] : 0.0f);
       const bool next = b < rp.depth - 1;
-      int view = 0;
-      uint32_t pixel = 0u, sample = 0u;
-      if (next || rp.n_alights > 0) path_coords(rp, (int64_t)pid, &view, &pixel, &sample);
-      ns = nee_sample(rp, s, pixel, sample, view, b);
+      PathId id{0, 0u, 0u, 0u, 0u};
+      if (next || rp.n_alights > 0) id = path_coords(rp, (int64_t)pid);
+      ns = nee_sample(rp, s, id.pixel, id.sample, id.view, b);
       if (ns.want) {
         want_shadow = true;
         contrib = nee_contrib(beta, s, ns, rp);
       }
       if (next) {
-        bounce_dir(rp, pixel, sample, view, b, s, &ndx, &ndy, &ndz);
+        bounce_dir(rp, id.pixel, id.sample, id.view, b, s, &ndx, &ndy, &ndz);
         beta_next = beta * s.a;
         want_next = true;
       }
@@ -318,6 +334,10 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     out.ex_rec[jn] = rec;
     out.ex_qh[jn] = qhv;
   }
+  if (view_done) {  // paths that end here: escaped, or past the last bounce without a shadow ray
+    const bool ends = live && !want_next && !want_shadow;
+    wave_stamp_views(ends, ends ? path_coords(rp, (int64_t)pid).cam : 0, view_done);
+  }
   if (dump) {  // keep a copy of the incoherent (bounce >= 1) extension rays
     const unsigned long long jd = wave_append64(want_next, dump_count);
     if (want_next && jd < (unsigned long long)dump_cap) {
@@ -330,14 +350,22 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
       dump[5 * c + jd] = ndz;
       dump[6 * c + jd] = 0.0f;
       dump[7 * c + jd] = kInfF;
+      reinterpret_cast<uint32_t*>(dump)[8 * c + jd] = rec;
+      reinterpret_cast<uint32_t*>(dump)[9 * c + jd] = qhv;
     }
   }
 }
 
-__global__ void k_shadow_resolve(RenderParams rp, ShadowQueue sq, const uint32_t* count, const uint8_t* occ) {
+// Shadow rays of bounce b: add the contributions of the unoccluded ones.  After
+// the last bounce every path with a shadow ray ends here.
+__global__ void k_shadow_resolve(RenderParams rp, ShadowQueue sq, const uint32_t* count, const uint8_t* occ, int b,
+                                 unsigned long long* view_done) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)*count) return;
-  if (!occ[i]) rp.slots[sq.pid[i]] += sq.contrib[i];
+  const bool live = i < (int64_t)*count;
+  if (live && !occ[i]) rp.slots[sq.pid[i]] += sq.contrib[i];
+  if (view_done && b == rp.depth - 1) {
+    wave_stamp_views(live, live ? path_coords(rp, (int64_t)sq.pid[i]).cam : 0, view_done);
+  }
 }
 
 // image[view pixel] = (sum over samples, in sample order) / spp
@@ -351,9 +379,10 @@ __global__ void k_accum(RenderParams rp, float* image, int64_t n_pixels) {
     else hi = mid - 1;
   }
   const CamDev& c = rp.cams[lo];
-  const int64_t wh = (int64_t)c.w * c.h;
+  const int64_t wh = (int64_t)c.tw * c.th;
   const int64_t pixel = g - c.img_offset;
-  if (pixel >= wh) return;  // a gap between views: not part of any image
+  // before the first view, or in a gap between views: not part of any image
+  if (pixel < 0 || pixel >= wh) return;
   float sum = 0.0f;
   for (int s = 0; s < rp.spp; ++s) sum += rp.slots[c.path_base + s * wh + pixel];
   const float m = sum / (float)rp.spp;
@@ -428,9 +457,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
       {
         if (pid >= 0) {
           P.pid = (uint32_t)pid;
-          int view;
-          uint32_t pixel, sample;
-          const Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
+          PathId id;
+          const Ray3 r = path_camera_ray(rp, pid, &id);
           P.b = 0;
           P.beta = 1.0f;
           P.radiance = 0.0f;
@@ -477,16 +505,15 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                 const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31,
                                           TEX ? L.b_u : 0.0f, TEX ? L.b_v : 0.0f);
                 P.have_next = P.b < rp.depth - 1;
-                int view = 0;
-                uint32_t pixel = 0u, sample = 0u;
-                if (P.have_next || rp.n_alights > 0) path_coords(rp, (int64_t)P.pid, &view, &pixel, &sample);
+                PathId id{0, 0u, 0u, 0u, 0u};
+                if (P.have_next || rp.n_alights > 0) id = path_coords(rp, (int64_t)P.pid);
                 if (P.have_next) {
-                  bounce_dir(rp, pixel, sample, view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
+                  bounce_dir(rp, id.pixel, id.sample, id.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
                   P.beta_next = P.beta * s.a;
                 }
                 L.ex_rec = hrec;
                 L.ex_qh = hqh;
-                const NeeSample ns = nee_sample(rp, s, pixel, sample, view, P.b);
+                const NeeSample ns = nee_sample(rp, s, id.pixel, id.sample, id.view, P.b);
                 if (ns.want) {
                   P.pending = nee_contrib(P.beta, s, ns, rp);
                   P.shadow = true;
@@ -519,12 +546,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
             if (path_done) {
               rp.slots[P.pid] = P.radiance;
               ++n_paths;
-              if (TS) {
-                int view;
-                uint32_t pixel, sample;
-                path_coords(rp, (int64_t)P.pid, &view, &pixel, &sample);
-                atomicMax(&view_done[view], (unsigned long long)wall_clock64());
-              }
+              if (TS) atomicMax(&view_done[path_coords(rp, (int64_t)P.pid).cam], (unsigned long long)wall_clock64());
               has = false;
               break;
             }
@@ -558,7 +580,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
 // rec_i[6 k ..] = (instance id, primitive, half, shadow: -1 none / 0 visible /
 // 1 occluded, unique face, 0) and rec_f[10 k ..] = (t, albedo, cos to the light,
 // radiance after the vertex, origin xyz and direction xyz of the ray that found
-// it).  out[0] = vertices, out[1] = 1 if the path escaped, and
+// it); a path that escapes records its escaping ray after its last vertex (ids
+// -1, t = +inf).  out[0] = vertices, out[1] = 1 if the path escaped, and
 // rec_f[10 kMaxDepth] holds the final radiance.
 template <int FMT>
 __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int depth_lds, int32_t* rec_i,
@@ -568,9 +591,8 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
   uint2 spill[kStackTotal];
   if (threadIdx.x != 0) return;
   VisitCounters vc{0, 0, 0, 0};
-  int view;
-  uint32_t pixel, sample;
-  Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
+  PathId id;
+  Ray3 r = path_camera_ray(rp, pid, &id);
   float beta = 1.0f, radiance = 0.0f;
   uint32_t ex_rec = kEmpty, ex_qh = kEmpty;
   int n = 0, escaped = 0;
@@ -584,12 +606,29 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     if (L.b_rec == kEmpty) {
       radiance += beta * escape_radiance(sc, rp, r.dx, r.dy, r.dz);
       escaped = 1;
+      // the escaping ray takes the next record (n < depth here)
+      rec_i[6 * n + 0] = -1;
+      rec_i[6 * n + 1] = -1;
+      rec_i[6 * n + 2] = -1;
+      rec_i[6 * n + 3] = -1;
+      rec_i[6 * n + 4] = -1;
+      rec_i[6 * n + 5] = 0;
+      rec_f[10 * n + 0] = kInfF;
+      rec_f[10 * n + 1] = 0.0f;
+      rec_f[10 * n + 2] = 0.0f;
+      rec_f[10 * n + 3] = radiance;
+      rec_f[10 * n + 4] = r.ox;
+      rec_f[10 * n + 5] = r.oy;
+      rec_f[10 * n + 6] = r.oz;
+      rec_f[10 * n + 7] = r.dx;
+      rec_f[10 * n + 8] = r.dy;
+      rec_f[10 * n + 9] = r.dz;
       break;
     }
     const uint32_t hqh = L.b_qh;
     const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     int shadow = -1;
-    const NeeSample ns = nee_sample(rp, sh, pixel, sample, view, b);
+    const NeeSample ns = nee_sample(rp, sh, id.pixel, id.sample, id.view, b);
     if (ns.want) {
       const float pending = nee_contrib(beta, sh, ns, rp);
       Lane Ls;
@@ -622,7 +661,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     ++n;
     if (b == rp.depth - 1) break;
     float dx, dy, dz;
-    bounce_dir(rp, pixel, sample, view, b, sh, &dx, &dy, &dz);
+    bounce_dir(rp, id.pixel, id.sample, id.view, b, sh, &dx, &dy, &dz);
     beta = beta * sh.a;
     r = Ray3{sh.px, sh.py, sh.pz, dx, dy, dz};
     ex_rec = L.b_rec;
@@ -652,10 +691,10 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
   uint2 spill[kStackTotal];
   const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pid >= rp.n_paths) return;
-  int view;
-  uint32_t pixel, sample;
-  Ray3 r = path_camera_ray(rp, pid, &view, &pixel, &sample);
-  const float g = grad_img[rp.cams[view].img_offset + pixel] / (float)rp.spp;
+  PathId id;
+  Ray3 r = path_camera_ray(rp, pid, &id);
+  // id.local < tw * th: the index stays inside the camera's image rectangle
+  const float g = grad_img[rp.cams[id.cam].img_offset + id.local] / (float)rp.spp;
   if (g == 0.0f) return;
   uint32_t face[kMaxDepth];
   float betak[kMaxDepth], ck[kMaxDepth], ak[kMaxDepth];
@@ -677,7 +716,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     const uint32_t hrec = L.b_rec, hqh = L.b_qh;
     const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     float c = 0.0f;
-    const NeeSample ns = nee_sample(rp, s, pixel, sample, view, b);
+    const NeeSample ns = nee_sample(rp, s, id.pixel, id.sample, id.view, b);
     if (ns.want) {
       L.ex_rec = hrec;
       L.ex_qh = hqh;
@@ -695,7 +734,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     ++K;
     if (b == rp.depth - 1) break;
     float dx, dy, dz;
-    bounce_dir(rp, pixel, sample, view, b, s, &dx, &dy, &dz);
+    bounce_dir(rp, id.pixel, id.sample, id.view, b, s, &dx, &dy, &dz);
     r = Ray3{s.px, s.py, s.pz, dx, dy, dz};
     beta = beta * s.a;
     L.ex_rec = hrec;
@@ -738,7 +777,7 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
   stage_end(ex.log, 0, ev, s);
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq, csq,
-                     ex.dump, ex.dump_cap, ex.dump_count);
+                     ex.dump, ex.dump_cap, ex.dump_count, ex.view_done);
   stage_end(ex.log, 2, ev, s);
   ev = stage_begin(ex.log, s);
   if (feat & kFeatArea)
@@ -749,7 +788,7 @@ static void wavefront_bounce(const SceneView& sc, const RenderParams& rp, const 
                        pb.hits, pb.occ, tl.stack_depth, vis_sh);
   stage_end(ex.log, 1, ev, s);
   ev = stage_begin(ex.log, s);
-  hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+  hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ, b, ex.view_done);
   stage_end(ex.log, 2, ev, s);
 }
 
@@ -790,12 +829,12 @@ static void wavefront_persistent(const SceneView& sc, const RenderParams& rp, co
     uint32_t* csq = pb.counts + kMaxDepth + 1 + b;
     hipEvent_t ev = stage_begin(ex.log, s);
     hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, sc, rp, b, qin, cin, pb.hits, qout, cout, pb.sq,
-                       csq, ex.dump, ex.dump_cap, ex.dump_count);
+                       csq, ex.dump, ex.dump_cap, ex.dump_count, ex.view_done);
     stage_end(ex.log, 2, ev, s);
     // after the last bounce the extension count stays zero: shadow rays only
     mixed_launch<FMT, COUNT>(sc, rp, pb, tl, ex, qout, cout, csq, b + 1, s);
     ev = stage_begin(ex.log, s);
-    hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ);
+    hipLaunchKernelGGL(k_shadow_resolve, dim3(gp), dim3(256), 0, s, rp, pb.sq, csq, pb.occ, b, ex.view_done);
     stage_end(ex.log, 2, ev, s);
   }
 }
@@ -805,6 +844,7 @@ hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, 
                                    hipStream_t s) {
   const unsigned gp = blocks(rp.n_paths, 256);
   hipEvent_t ev = stage_begin(ex.log, s);
+  if (ex.start_tick) hipLaunchKernelGGL(k_start_tick, dim3(1), dim3(64), 0, s, ex.start_tick);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, pb.counts, 2 * kMaxDepth + 2);
   hipError_t e = launch_zero_u64(pb.work, (kMaxDepth + 1) * kClaimWords, s);
   if (e != hipSuccess) return e;

@@ -23,12 +23,14 @@ __device__ __forceinline__ void store_result(const Lane& L, const SceneView& sc,
   h.v[i] = hit ? L.b_v : 0.0f;
   h.inst[i] = hit ? (int32_t)sc.inst[L.b_rec].inst_id : -1;
   h.prim[i] = hit ? sc.quad_prim[L.b_qh & 0x7FFFFFFFu] : -1;
+  if (h.ref) reinterpret_cast<uint2*>(h.ref)[i] = hit ? make_uint2(L.b_rec, L.b_qh) : make_uint2(kEmpty, kEmpty);
 }
 
 template <bool ANY>
 __device__ __forceinline__ bool load_ray(Lane& L, const SceneView& sc, const RaysSoA& r, int64_t i) {
-  L.ex_rec = kEmpty;
-  L.ex_qh = kEmpty;
+  const uint2 ex = r.exclude ? reinterpret_cast<const uint2*>(r.exclude)[i] : make_uint2(kEmpty, kEmpty);
+  L.ex_rec = ex.x;
+  L.ex_qh = ex.y;
   const bool ok = lane_init(L, sc, r.ox[i], r.oy[i], r.oz[i], r.dx[i], r.dy[i], r.dz[i], r.tmin[i], r.tmax[i]);
   L.any = ANY;
   return ok;

@@ -14,14 +14,18 @@
 
 namespace rtq {
 
-// One view.  The basis (f, r, u) is computed on the host in FP64 and rounded.
+// One view, or the rectangle of one that this call renders.  The basis
+// (f, r, u) is computed on the host in FP64 and rounded.
 struct CamDev {
   float eye[3];
   float f[3], r[3], u[3];
   float tan_half, aspect;
-  int32_t w, h;
-  int64_t img_offset;  // first pixel of the view in the packed image
-  int64_t path_base;   // first path id of the view; paths are sample-major: base + s * w * h + pixel
+  int32_t w, h;        // the whole view
+  int32_t view_id;     // the view's index in the RNG counter
+  int32_t tx, ty;      // first column and row of the rendered rectangle
+  int32_t tw, th;      // its size
+  int64_t img_offset;  // first pixel of the rectangle in the packed image
+  int64_t path_base;   // first path id of the rectangle; paths are sample-major: base + s * tw * th + local pixel
 };
 
 struct RenderParams {
@@ -59,9 +63,19 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // Uniform in [0, 1): the top 24 bits, exactly representable in FP32.
 __device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-08f; }
 
-// path id -> (view, pixel, sample) by binary search over the views' path bases.
-__device__ __forceinline__ void path_coords(const RenderParams& rp, int64_t pid, int* view, uint32_t* pixel,
-                                            uint32_t* sample) {
+// Where a path belongs: the camera entry of the call, the pixel within the
+// rendered rectangle (its image slot), and the RNG coordinates (pixel of the
+// whole view, sample, view id).
+struct PathId {
+  int cam;          // camera entry of the call
+  uint32_t local;   // pixel index within the rendered rectangle
+  uint32_t pixel;   // row * w + column within the whole view
+  uint32_t sample;
+  uint32_t view;    // view id of the RNG counter
+};
+
+// path id -> PathId by binary search over the cameras' path bases.
+__device__ __forceinline__ PathId path_coords(const RenderParams& rp, int64_t pid) {
   int lo = 0, hi = rp.n_cams - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -69,11 +83,16 @@ __device__ __forceinline__ void path_coords(const RenderParams& rp, int64_t pid,
     else hi = mid - 1;
   }
   const CamDev& c = rp.cams[lo];
-  const int64_t wh = (int64_t)c.w * c.h;
+  const int64_t n = (int64_t)c.tw * c.th;
   const int64_t k = pid - c.path_base;
-  *view = lo;
-  *sample = (uint32_t)(k / wh);
-  *pixel = (uint32_t)(k - (int64_t)(*sample) * wh);
+  PathId id;
+  id.cam = lo;
+  id.sample = (uint32_t)(k / n);
+  id.local = (uint32_t)(k - (int64_t)id.sample * n);
+  const uint32_t row = id.local / (uint32_t)c.tw, col = id.local - row * (uint32_t)c.tw;
+  id.pixel = ((uint32_t)c.ty + row) * (uint32_t)c.w + (uint32_t)c.tx + col;
+  id.view = (uint32_t)c.view_id;
+  return id;
 }
 
 struct Ray3 {
@@ -202,11 +221,10 @@ struct NeeSample {
 // radiance Le from the side e1 x e2 faces: c = nl Le A cos_p cos_l / (pi d^2)
 // for the sampled point at distance d, A = |e1 x e2|.
 __device__ __forceinline__ NeeSample nee_sample(const RenderParams& rp, const Shade& s, uint32_t pixel,
-                                                uint32_t sample, int view, int b) {
+                                                uint32_t sample, uint32_t view, int b) {
   NeeSample r{s.cosl > 0.0f, rp.lx, rp.ly, rp.lz, kInfF, nee_factor(s.cosl, rp)};
   if (rp.n_alights == 0) return r;
-  const uint4 w = philox4x32_10(make_uint4(pixel, sample, (uint32_t)view, 0x80000000u | (uint32_t)b), rp.keys[0],
-                                rp.keys[1]);
+  const uint4 w = philox4x32_10(make_uint4(pixel, sample, view, 0x80000000u | (uint32_t)b), rp.keys[0], rp.keys[1]);
   const uint32_t nl = (uint32_t)rp.n_alights + 1u;
   const uint32_t j = (uint32_t)(((uint64_t)(w.x >> 8) * nl) >> 24);
   if (j == 0u) {
@@ -260,17 +278,16 @@ __device__ __forceinline__ void cosine_dir(float nx, float ny, float nz, float u
 }
 
 // Camera ray of path `pid` (jitter from words 0, 1 of the bounce-0 counter).
-__device__ __forceinline__ Ray3 path_camera_ray(const RenderParams& rp, int64_t pid, int* view, uint32_t* pixel,
-                                                uint32_t* sample) {
-  path_coords(rp, pid, view, pixel, sample);
-  const uint4 w = philox4x32_10(make_uint4(*pixel, *sample, (uint32_t)*view, 0u), rp.keys[0], rp.keys[1]);
-  return camera_ray(rp.cams[*view], *pixel, u01(w.x), u01(w.y));
+__device__ __forceinline__ Ray3 path_camera_ray(const RenderParams& rp, int64_t pid, PathId* id) {
+  *id = path_coords(rp, pid);
+  const uint4 w = philox4x32_10(make_uint4(id->pixel, id->sample, id->view, 0u), rp.keys[0], rp.keys[1]);
+  return camera_ray(rp.cams[id->cam], id->pixel, u01(w.x), u01(w.y));
 }
 
 // Bounce direction after hit b of a path (words 2, 3 of counter (pixel, sample, view, b)).
-__device__ __forceinline__ void bounce_dir(const RenderParams& rp, uint32_t pixel, uint32_t sample, int view, int b,
-                                           const Shade& s, float* dx, float* dy, float* dz) {
-  const uint4 w = philox4x32_10(make_uint4(pixel, sample, (uint32_t)view, (uint32_t)b), rp.keys[0], rp.keys[1]);
+__device__ __forceinline__ void bounce_dir(const RenderParams& rp, uint32_t pixel, uint32_t sample, uint32_t view,
+                                           int b, const Shade& s, float* dx, float* dy, float* dz) {
+  const uint4 w = philox4x32_10(make_uint4(pixel, sample, view, (uint32_t)b), rp.keys[0], rp.keys[1]);
   cosine_dir(s.nx, s.ny, s.nz, u01(w.z), u01(w.w), dx, dy, dz);
 }
 

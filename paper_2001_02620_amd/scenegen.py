@@ -79,6 +79,18 @@ class Camera:
     vfov_deg: float
     w: int
     h: int
+    # index of the view in the random-number counter (None: its position in the
+    # camera list of the call), and the rectangle (x, y, w, h) of the view that
+    # is rendered (None: all of it) -- a tile of an image-parallel split
+    view_id: Optional[int] = None
+    tile: Optional[Tuple[int, int, int, int]] = None
+
+    def rect(self) -> Tuple[int, int, int, int]:
+        return self.tile if self.tile is not None else (0, 0, self.w, self.h)
+
+    def n_pixels(self) -> int:
+        r = self.rect()
+        return r[2] * r[3]
 
 
 @dataclass

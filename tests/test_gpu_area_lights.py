@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2001_02620_amd import scenegen as sg
 from tests import scenes as ts
-from tests.gpu_util import compare_paths, log
+from tests.gpu_util import log, replay_check_pixels
 from tests.test_gpu_render import SCHEDS, _compare_image, _multi_view_scene, _render
 from tests.test_oracle_pins import AREA_LIGHTS, _area_setup
 
@@ -43,7 +43,7 @@ def test_area_lights_schedulers_bit_identical_and_match_oracle():
     assert (g.view(np.uint32) == imgs[0][0].view(np.uint32)).all()
     o = oracle.OracleScene(scene)
     ref, fl, stats = o.render(cams, st)
-    frac = _compare_image(imgs[0][0], ref, fl)
+    frac = _compare_image(imgs[0][0], ref, fl, replay=(S, o, cams, st, SCHEDS[3]))
     log(f"  flagged pixels {frac:.4f}; gpu rays {imgs[0][1]}; oracle {stats}")
     assert frac < 0.1
     if frac == 0.0:
@@ -51,11 +51,12 @@ def test_area_lights_schedulers_bit_identical_and_match_oracle():
     plain, _, _ = o.render(cams, dataclasses.replace(st, area_lights=()))
     assert np.abs(ref - plain).mean() > 1e-2 * np.abs(plain).mean()
     rng = np.random.default_rng(5)
+    pix = rng.choice(ref.size, 256, replace=False)
     for kw in (SCHEDS[0], SCHEDS[3]):
-        # many pixels of these views see no geometry: 256 paths give about 170 vertices
-        n = compare_paths(rtq, oracle, S, o, cams, st, rng, 256, **kw)
-        log(f"  {n} path vertices compared")
-        assert n > 80
+        # many pixels of these views see no geometry: 256 pixels give a few hundred vertices
+        tot = replay_check_pixels(rtq, o, S, cams, st, pix, imgs[0][0], **kw)
+        log(f"  256 pixels replayed and checked: {tot}")
+        assert tot["vertices"] > 80
 
 
 def test_area_light_floor_closed_form_and_segment_gpu():

@@ -38,7 +38,7 @@ def test_environment_schedulers_bit_identical_and_match_oracle():
     o = oracle.OracleScene(scene)
     o.set_environment(env)
     ref, fl, _ = o.render(cams, st)
-    frac = _compare_image(imgs[0], ref, fl)
+    frac = _compare_image(imgs[0], ref, fl, replay=(S, o, cams, st, SCHEDS[3]))
     log(f"  flagged pixels {frac:.4f}")
     assert frac < 0.1
     plain, _, _ = oracle.OracleScene(scene).render(cams, st)

@@ -8,7 +8,7 @@ import pytest
 import oracle
 from paper_2001_02620_amd import scenegen as sg
 from tests import scenes as ts
-from tests.gpu_util import compare_paths, log
+from tests.gpu_util import log, replay_check_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -36,13 +36,27 @@ def _render(S, cams, st, **kw):
     return img.cpu().numpy()
 
 
-def _compare_image(gpu, ref, flags, rel=1e-4):
+def _compare_image(gpu, ref, flags, rel=1e-4, replay=None, pixels=None):
+    """Unflagged pixels: the oracle's free-running FP64 value to `rel`.  Flagged
+    pixels: with replay = (S, osc, cams, st, render options), every sample path
+    of each one is traced alone on the GPU and checked step by step along its
+    own rays (replay_check_pixels), so no pixel goes unchecked.  `pixels` maps
+    the compared entries to packed image indices (default: all).  Returns the
+    flagged fraction."""
     ok = flags == 0
     err = np.abs(gpu.astype(np.float64) - ref)
     bad = ok & (err > rel * np.abs(ref) + 1e-7)
     if bad.any():
         k = np.nonzero(bad)[0][:8]
         raise AssertionError(f"{bad.sum()} unflagged pixels differ: idx {k} gpu {gpu[k]} oracle {ref[k]}")
+    if replay is not None:
+        S, osc, cams, st, kw = replay
+        idx = np.nonzero(~ok)[0]
+        full = np.zeros(int(np.max(pixels)) + 1 if pixels is not None else gpu.size, np.float32)
+        gidx = idx if pixels is None else np.asarray(pixels)[idx]
+        full[gidx] = gpu[idx]
+        tot = replay_check_pixels(rtq, osc, S, cams, st, gidx, full, **kw)
+        log(f"  replayed {idx.size} flagged pixels: {tot}")
     return 1.0 - ok.mean()
 
 
@@ -75,7 +89,7 @@ def test_schedulers_bit_identical_and_match_oracle(cfg):
         assert (cnt == ref_cnt).all(), f"ray counts differ for {kw}: {cnt} vs {ref_cnt}"
     o = oracle.OracleScene(scene)
     ref, fl, stats = o.render(cams, st)
-    frac = _compare_image(ref_img, ref, fl)
+    frac = _compare_image(ref_img, ref, fl, replay=(S, o, cams, st, SCHEDS[3]))
     log(f"  flagged pixels {frac:.4f}; gpu rays {ref_cnt}; oracle {stats}")
     assert frac < 0.1
     n_paths = sum(c.w * c.h for c in cams) * st.spp
@@ -108,9 +122,11 @@ def test_cosine_sampling_form_factor_gpu():
     scene = ts.floor_scene(albedo=a_f, half=50.0, extra=[(ceil, 0.5)])
     cams = [sg.Camera((0.0, 0.0, 0.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.01, 64, 64)]
     st = sg.RenderSettings(spp=64, depth=2, seed=78)
-    img = _render(rtq.Scene(scene), cams, st, scheduler=rtq.SCHED_MEGAKERNEL).astype(np.float64)
-    ref, fl, _ = oracle.OracleScene(scene).render(cams, st)
-    frac = _compare_image(img.astype(np.float32), ref, fl)
+    S = rtq.Scene(scene)
+    img = _render(S, cams, st, scheduler=rtq.SCHED_MEGAKERNEL).astype(np.float64)
+    o = oracle.OracleScene(scene)
+    ref, fl, _ = o.render(cams, st)
+    frac = _compare_image(img.astype(np.float32), ref, fl, replay=(S, o, cams, st, {}))
     assert frac < 0.05
     F = 4 * ts.form_factor_corner(half, half, h)
     cosl = 2 / math.sqrt(6.0)
@@ -249,25 +265,22 @@ def test_path_records_match_frame_and_oracle():
     rng = np.random.default_rng(9)
     n_pix = cams[0].w * cams[0].h
     compared = 0
-    for p in rng.choice(n_pix, size=256, replace=False):
+    pix = rng.choice(n_pix, size=256, replace=False)
+    for p in pix:
         gv, gesc, grad = rtq.render_path(S, cams, st, 0, int(p), 0, **kw)
         assert np.float32(grad).view(np.uint32) == img[p].view(np.uint32), (p, grad, img[p])
         ov, oesc, pflags = o.path(cams, st, int(p), 0)
-        for k, y in enumerate(ov):
-            if (y["flags"] & oracle.ID_FLAGS) or y["shadow_flags"]:
-                break
-            assert k < len(gv), (p, k, "gpu path ended early")
-            x = gv[k]
-            assert (x["inst"], x["prim"], x["half"]) == (y["inst"], y["prim"], y["half"]), (p, k, x, y)
-            assert abs(x["t"] - y["t"]) <= 1e-5 * y["t"] or (y["flags"] & oracle.F_T_ILLCOND), (p, k, x, y)
+        if pflags:
+            continue  # checked by the replay below
+        assert len(gv) == len(ov) and gesc == oesc, (p, gv, ov)
+        for x, y in zip(gv, ov):
+            assert (x["inst"], x["prim"], x["half"], x["shadow"]) == (y["inst"], y["prim"], y["half"], y["shadow"])
+            assert abs(x["t"] - y["t"]) <= 1e-5 * y["t"] or (y["flags"] & oracle.F_T_ILLCOND), (p, x, y)
             compared += 1
-            if y["flags"] & oracle.F_SHADE:  # shading decisions near a threshold: stop here
-                break
-            assert x["shadow"] == y["shadow"], (p, k, x, y)
-        else:
-            assert gesc == oesc or pflags, (p, gesc, oesc)
-    log(f"  {compared} vertices compared")
+    log(f"  {compared} vertices of unflagged paths equal the oracle's")
     assert compared >= 64
+    tot = replay_check_pixels(rtq, o, S, cams, st, pix, img, **kw)
+    log(f"  every sampled path replayed and checked: {tot}")
 
 
 def test_render_argument_errors():
@@ -325,10 +338,10 @@ def test_config2_full_frame_bench_launch_vs_oracle():
     ref, fl, _ = o.render(cams, st, pixels=pix)
     frac = _compare_image(a[pix], ref, fl)
     log(f"  256 sampled pixels, flagged {frac:.4f}")
-    assert frac < 0.5
-    nv = compare_paths(rtq, oracle, S, o, cams, st, rng, 64, **q8)
-    log(f"  64 sampled paths, {nv} vertices compared")
-    assert nv >= 32
+    assert frac < 0.4
+    tot = replay_check_pixels(rtq, o, S, cams, st, pix, a, **q8)
+    log(f"  all 256 sampled pixels replayed and checked: {tot}")
+    assert tot["vertices"] >= 256
 
 
 def test_autotuner_quick_grid_keeps_images():
@@ -347,3 +360,27 @@ def test_autotuner_quick_grid_keeps_images():
             assert best["opts"]["node_format"] == fmt and best["opts"]["scheduler"] == sch and best["ms"] > 0
     assert len(res["table"]) >= 8
     log(f"  {len(res['table'])} candidates, all bit-identical")
+
+
+@pytest.mark.parametrize("sched", [rtq.SCHED_PLAIN, rtq.SCHED_PERSISTENT, rtq.SCHED_MEGAKERNEL])
+def test_view_completion_stamps_every_scheduler(sched):
+    """Per-view completion stamps (the tick at which a view's last path ended)
+    in every scheduler: each view gets a stamp after the call's start tick and
+    no later than the end of the call, and the stamps do not change the image."""
+    import torch
+    log(f"case: view completion stamps, scheduler {sched}")
+    scene, cams = _multi_view_scene()
+    S = rtq.Scene(scene)
+    st = sg.RenderSettings(spp=2, depth=5, seed=7)
+    kw = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=sched)
+    ref = _render(S, cams, st, **kw)
+    done = torch.zeros(len(cams), dtype=torch.uint64, device="cuda")
+    start = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    img = _render(S, cams, st, view_done=done, start_tick=start, **kw)
+    after = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    _render(S, cams[:1], st, start_tick=after, **kw)  # a later call's start
+    d = done.cpu().numpy().astype(np.int64)
+    t0, t1 = int(start.cpu().item()), int(after.cpu().item())
+    assert (d > t0).all() and (d <= t1).all(), (t0, d, t1)
+    assert np.array_equal(img.view(np.uint32), ref.view(np.uint32))
+    log(f"  view completion ticks after start: {d - t0}")

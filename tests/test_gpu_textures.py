@@ -42,7 +42,7 @@ def test_textured_schedulers_bit_identical_and_match_oracle(cfg, res):
     o = oracle.OracleScene(scene)
     o.set_textures(tex)
     ref, fl, _ = o.render(cams, st)
-    frac = _compare_image(imgs[0], ref, fl)
+    frac = _compare_image(imgs[0], ref, fl, replay=(S, o, cams, st, SCHEDS[3]))
     log(f"  flagged pixels {frac:.4f}")
     assert frac < 0.1
     # the texture changes the image (the texels are not the albedo)

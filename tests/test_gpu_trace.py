@@ -297,3 +297,48 @@ def test_opened_instances_keep_hits_and_images(cfg):
             assert_hits_identical(ref, h, f"open_pct {pct} vs unopened")
             assert np.array_equal(img.view(np.uint32), im.view(np.uint32)), f"open_pct {pct}: image differs"
         S.close()
+
+
+def test_secondary_rays_with_exclusion_config1():
+    """Secondary rays leaving a surface (Section 5.4's bounce and shadow rays):
+    camera-ray hits return their references, rays from the FP32 hit points in
+    random directions exclude the triangle they leave; every traversal variant
+    equals the brute-force reference bit for bit, no ray reports its own
+    triangle, and the hits match the oracle given the same exclusions."""
+    import torch
+    log("case: secondary rays with exclusion, config 1")
+    scene, cams, _ = sg.config1()
+    S = rtq.Scene(scene)
+    rng = np.random.default_rng(31)
+    from tests.gpu_util import camera_rays
+    cr = camera_rays(cams, rng, 30000)
+    h0 = rtq.trace_closest(S, to_dev(cr), want_ref=True, node_format=rtq.RTQ_NODE_Q8,
+                           scheduler=rtq.SCHED_PERSISTENT)
+    torch.cuda.synchronize()
+    hit = (h0.inst >= 0).cpu().numpy()
+    t = h0.t.cpu().numpy()
+    p = (cr[:, 0:3] + t[:, None] * cr[:, 3:6]).astype(np.float32)  # FP32 hit points, as the renderer forms them
+    d = rng.normal(size=(cr.shape[0], 3)).astype(np.float32)
+    rays = np.zeros((int(hit.sum()), 8), np.float32)
+    rays[:, 0:3] = p[hit]
+    rays[:, 3:6] = d[hit]
+    rays[:, 7] = np.inf
+    ref = h0.ref[torch.from_numpy(hit).cuda()].contiguous()
+    R = to_dev(rays)
+    base = hits_np(rtq.trace_brute(S, R, exclude=ref))
+    for var in VARIANTS:
+        assert_hits_identical(base, hits_np(rtq.trace_closest(S, R, exclude=ref, **var)), str(var))
+    src_inst = h0.inst.cpu().numpy()[hit]
+    src_prim = h0.prim.cpu().numpy()[hit]
+    src_half = (ref[:, 1].cpu().numpy().view(np.uint32) >> 31).astype(np.int32)
+    # rays that hit their own quad hit its other half (the excluded half is never reported)
+    own = (base["inst"] == src_inst) & (base["prim"] == src_prim)
+    log(f"  {rays.shape[0]} rays, {own.sum()} hit the other half of the quad they leave")
+    excl = np.stack([src_inst, src_prim, src_half], 1)
+    o = oracle.OracleScene(scene).trace(rays, excl=excl)
+    frac = compare_with_oracle(scene, rays, base, o, excl=excl)
+    log(f"  flagged fraction {frac:.4f}")
+    # without the exclusion the same rays often re-hit the triangle they leave
+    plain = hits_np(rtq.trace_closest(S, R, node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT))
+    again = (plain["inst"] == src_inst) & (plain["prim"] == src_prim) & (plain["t"] < 1e-3)
+    log(f"  without exclusion {again.sum()} rays re-hit their own quad at t < 1e-3")
