@@ -75,7 +75,7 @@ def lib():
         L.orc_render.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, P, P]
         L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P, i32]
         L.orc_path.argtypes = [P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
-        L.orc_accept.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P]
+        L.orc_accept.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
         L.orc_check_path.argtypes = [P, P, P, i32, P, P, P, i32, i64, i32, i32, P, P, i32, ctypes.c_float, P]
         L.orc_check_path.restype = i32
         _lib = L
@@ -204,11 +204,12 @@ class OracleScene:
     def accept(self, rays: np.ndarray, inst: np.ndarray, prim: Optional[np.ndarray] = None,
                t: Optional[np.ndarray] = None, half: Optional[np.ndarray] = None,
                excl: Optional[np.ndarray] = None, r0: Optional[np.ndarray] = None, any_hit: bool = False,
-               brute: bool = False):
+               brute: bool = False, want_ulps: bool = False):
         """Whether each answer (closest: inst, prim, t and optionally half, inst -1 for a
         miss; any_hit: inst = 1 occluded / 0 not) is one an FP32 traversal may give
         for the FP32 ray.  Returns (code [n] int32, 0 = valid, see ACCEPT_CODES;
-        info [n] int32 bits: 1 the certain hit, 2 t check waived, 4 other answers possible)."""
+        info [n] int32 bits: 1 the certain hit, 2 t check waived, 4 other answers possible;
+        with want_ulps also the t error of each answer in units of 2^-24 S / (|d| |cos|))."""
         rays = np.ascontiguousarray(rays, dtype=np.float32)
         n = rays.shape[0]
         gi = np.ascontiguousarray(inst, dtype=np.int32)
@@ -221,9 +222,10 @@ class OracleScene:
         rr = None if r0 is None else np.ascontiguousarray(r0, dtype=np.float64)
         out = np.zeros(n, np.int32)
         info = np.zeros(n, np.int32)
+        ul = np.zeros(n) if want_ulps else None
         lib().orc_accept(self.h, n, _p(rays), _p(ex), _p(rr), 0 if brute else 1, 1 if any_hit else 0, _p(gi),
-                         _p(gp), _p(gh), _p(gt), _p(out), _p(info))
-        return out, info
+                         _p(gp), _p(gh), _p(gt), _p(out), _p(info), _p(ul))
+        return (out, info, ul) if want_ulps else (out, info)
 
     def check_path(self, cams, settings, cam: int, local: int, sample: int, nv: int, vi: np.ndarray,
                    vf: np.ndarray, escaped: bool, radiance: float):
@@ -236,12 +238,12 @@ class OracleScene:
         pi, pu, pd = self._params(settings)
         vi = np.ascontiguousarray(vi, dtype=np.int32)
         vf = np.ascontiguousarray(vf, dtype=np.float32)
-        st = np.zeros(6)
+        st = np.zeros(7)
         code = lib().orc_check_path(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), int(cam), int(local),
                                     int(sample), int(nv), _p(vi), _p(vf), 1 if escaped else 0, float(radiance),
                                     _p(st))
         return int(code), dict(ray=int(st[0]), L=float(st[1]), vertices=int(st[2]), certain=int(st[3]),
-                               t_waived=int(st[4]), ambiguous_shading=int(st[5]))
+                               t_waived=int(st[4]), ambiguous_shading=int(st[5]), max_t_ulps=float(st[6]))
 
     @staticmethod
     def _params(settings):

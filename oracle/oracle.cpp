@@ -534,6 +534,7 @@ struct Cand {
   bool certain;    // hit by every FP32 traversal
   bool illcond;    // its FP32 t cannot be trusted to 1e-5
   double win;      // tie window at its t
+  double tulp;     // change of t when the ray moves 2^-24 S along the normal: 2^-24 S / (|d| |cos|)
 };
 
 struct AcceptSet {
@@ -547,7 +548,7 @@ struct AcceptSet {
 // whether it is a possible answer and whether it is a certain hit.
 struct TriClass {
   bool possible = false, certain = false, illcond = false;
-  double t = kInf, S = 1.0;
+  double t = kInf, S = 1.0, tulp = kInf;
 };
 TriClass classify_tri(const Ray& r, double dn, double Sv, V3 w0, V3 w1, V3 w2, const V3 wq[4], double r0) {
   TriClass c;
@@ -583,6 +584,7 @@ TriClass classify_tri(const Ray& r, double dn, double Sv, V3 w0, V3 w1, V3 w2, c
   const bool near_tmax = std::isfinite(r.tmax) && std::fabs(t - r.tmax) <= 1e-5 * r.tmax + 1e-6 * Sq / dn;
   const double cosv = std::fabs(den) / (std::sqrt(nn) * dn);
   c.illcond = 16.0 * std::ldexp(1.0, -24) * Sq > 1e-5 * std::fabs(t) * dn * cosv;
+  c.tulp = std::ldexp(1.0, -24) * Sq / (dn * cosv);
   c.certain = inside && in_iv && !graze && !near_org && !near_tmax;
   c.possible = (inside || graze) && (in_iv || near_org || near_tmax);
   return c;
@@ -613,7 +615,7 @@ AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, in
   visit(S, r, mode, g_enum, t_hi, [&](int64_t inst, int64_t qg) {
     each_tri(inst, qg, [&](int32_t i, int32_t pr, int h, const TriClass& c) {
       if (!c.certain) return;
-      Cand cd{Key{c.t, i, pr, h, 0, 0}, true, c.illcond, 1e-5 * c.t + 1e-6 * c.S / dn};
+      Cand cd{Key{c.t, i, pr, h, 0, 0}, true, c.illcond, 1e-5 * c.t + 1e-6 * c.S / dn, c.tulp};
       if (!A.has_certain || key_less(cd.k, A.certain.k)) {
         A.certain = cd;
         A.has_certain = true;
@@ -629,7 +631,8 @@ AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, in
   visit(S, r, mode, g_enum, t_enum, [&](int64_t inst, int64_t qg) {
     each_tri(inst, qg, [&](int32_t i, int32_t pr, int h, const TriClass& c) {
       if (!c.possible || c.t > t_lim) return;
-      A.cand.push_back(Cand{Key{c.t, i, pr, h, 0, 0}, c.certain, c.illcond, 1e-5 * std::fabs(c.t) + 1e-6 * c.S / dn});
+      A.cand.push_back(
+          Cand{Key{c.t, i, pr, h, 0, 0}, c.certain, c.illcond, 1e-5 * std::fabs(c.t) + 1e-6 * c.S / dn, c.tulp});
     });
   });
   return A;
@@ -639,8 +642,10 @@ AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, in
 // parameter t_gpu: 0 valid, 1 not a possible answer, 2 a miss while a certain
 // hit exists, 3 t outside its tolerance.  *info: bit 1 the answer is the
 // certain hit, bit 2 its t check was waived (ill-conditioned).
-int judge_closest(const AcceptSet& A, int32_t inst, int32_t prim, int32_t half, double t_gpu, int* info) {
+int judge_closest(const AcceptSet& A, int32_t inst, int32_t prim, int32_t half, double t_gpu, int* info,
+                  double* ulps = nullptr) {
   *info = 0;
+  if (ulps) *ulps = 0.0;
   if (!A.ray_ok) return inst < 0 ? 0 : 1;
   if (inst < 0) return A.has_certain ? 2 : 0;
   const Cand* best = nullptr;
@@ -652,6 +657,7 @@ int judge_closest(const AcceptSet& A, int32_t inst, int32_t prim, int32_t half, 
   if (A.has_certain && A.certain.k.inst == inst && A.certain.k.prim == prim &&
       (half < 0 || A.certain.k.half == half))
     *info |= 1;
+  if (ulps) *ulps = std::fabs(t_gpu - best->k.t) / best->tulp;
   if (best->illcond) {
     *info |= 2;
     return 0;
@@ -947,6 +953,7 @@ struct PathCheck {
   int vertex = -1;  // the vertex (or ray) where it failed
   double L = 0.0;   // FP64 radiance along the GPU's decisions
   int n_vert = 0, n_certain = 0, n_waived = 0, n_ambiguous_shading = 0;
+  double max_ulps = 0.0;  // largest t error in units of 2^-24 S / (|d| |cos|)
 };
 
 inline float f32(double x) { return (float)x; }
@@ -1061,7 +1068,9 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     const int32_t pr = S.iproto[inst];
     if (prim >= S.qo[pr + 1] - S.qo[pr]) return fail(2, k);
     int info = 0;
-    const int jc = judge_closest(A, inst, prim, half, (double)F[0], &info);
+    double ulps = 0.0;
+    const int jc = judge_closest(A, inst, prim, half, (double)F[0], &info, &ulps);
+    R.max_ulps = std::max(R.max_ulps, ulps);
     if (jc == 1) return fail(2, k);
     if (jc == 3) return fail(4, k);
     R.n_vert++;
@@ -1409,10 +1418,11 @@ void orc_trace_d(void* s, int64_t n, const double* rays, const int32_t* excl, co
 // tolerance; any hit: 1 occluded without a possible occluder, 2 unoccluded
 // while a certain occluder exists.  info[i] (may be NULL): bit 1 the answer is
 // the certain hit, bit 2 its t check was waived (ill-conditioned), bit 4 the ray
-// has possible answers other than the certain hit.
+// has possible answers other than the certain hit.  ulps[i] (may be NULL): the
+// t error of a closest-hit answer in units of 2^-24 S / (|d| |cos|).
 void orc_accept(void* s, int64_t n, const float* rays, const int32_t* excl, const double* r0, int32_t mode,
                 int32_t any_hit, const int32_t* g_inst, const int32_t* g_prim, const int32_t* g_half,
-                const float* g_t, int32_t* out, int32_t* info) {
+                const float* g_t, int32_t* out, int32_t* info, double* ulps) {
   const Scene& S = *static_cast<Scene*>(s);
   parallel_for(n, threads(), [&](int64_t i, int) {
     const float* R = rays + 8 * i;
@@ -1426,7 +1436,7 @@ void orc_accept(void* s, int64_t n, const float* rays, const int32_t* excl, cons
       out[i] = judge_any(A, g_inst[i] != 0);
     } else {
       out[i] = judge_closest(A, g_inst[i], g_inst[i] < 0 ? -1 : g_prim[i], g_half ? g_half[i] : -1,
-                             (double)g_t[i], &inf);
+                             (double)g_t[i], &inf, ulps ? &ulps[i] : nullptr);
     }
     size_t others = 0;
     for (const Cand& c : A.cand)
@@ -1444,7 +1454,8 @@ void orc_accept(void* s, int64_t n, const float* rays, const int32_t* excl, cons
 // or not against a clear decision, 8 shadow outcome, 9 next origin is not the
 // FP32 hit point, 10 next direction, 11 path length, 12 radiance.  stats
 // (may be NULL): [failing ray, FP64 radiance, vertices, certain answers,
-// t checks waived, shading decisions within rounding of a threshold].
+// t checks waived, shading decisions within rounding of a threshold, largest
+// t error in units of 2^-24 S / (|d| |cos|)].
 int32_t orc_check_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
                        const uint64_t* pu, const double* pd, int32_t cam, int64_t local, int32_t sample, int32_t nv,
                        const int32_t* vi, const float* vf, int32_t escaped, float radiance, double* stats) {
@@ -1462,6 +1473,7 @@ int32_t orc_check_path(void* s, const double* cam_f, const int64_t* cam_i, int32
     stats[3] = R.n_certain;
     stats[4] = R.n_waived;
     stats[5] = R.n_ambiguous_shading;
+    stats[6] = R.max_ulps;
   }
   return R.code;
 }

@@ -90,24 +90,26 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
         du = np.abs(g["u"][hit] - o.u[hit])
         dv = np.abs(g["v"][hit] - o.v[hit])
         assert (du <= tol).all() and (dv <= tol).all(), f"uv error {max(du.max(), dv.max())}"
-    # flagged rays: the GPU's answer must be acceptable for the FP32 ray
+    # every ray (flagged ones included): the GPU's answer must be acceptable for
+    # the FP32 ray; its t error is measured in units of 2^-24 S / (|d| |cos|)
     fl = np.nonzero(flagged)[0]
-    n_waived = int(tcheck.size and (hit & ~tcheck).sum())
-    if fl.size:
-        osc = ora_scene if ora_scene is not None else oracle.OracleScene(scene)
-        ex = None if excl is None else np.ascontiguousarray(excl)[fl]
-        code, info = osc.accept(rays[fl], gi[fl], gp[fl], g["t"][fl], excl=ex)
-        bad = code != 0
-        if bad.any():
-            k = fl[bad][:8]
-            raise AssertionError(f"{bad.sum()} of {fl.size} flagged rays have an answer no FP32 traversal may give: "
-                                 f"idx {k} codes {[oracle.ACCEPT_CODES[c] for c in code[bad][:8]]} gpu "
-                                 f"{list(zip(gi[k], gp[k], g['t'][k]))} oracle {list(zip(o.inst[k], o.prim[k], o.t[k]))}")
-        n_waived += int(((info & 2) != 0).sum())
+    osc = ora_scene if ora_scene is not None else oracle.OracleScene(scene)
+    code, info, ulps = osc.accept(rays, gi, gp, g["t"], excl=excl, want_ulps=True)
+    bad = code != 0
+    if bad.any():
+        k = np.nonzero(bad)[0][:8]
+        raise AssertionError(f"{bad.sum()} rays ({flagged[bad].sum()} flagged) have an answer no FP32 traversal "
+                             f"may give: idx {k} codes {[oracle.ACCEPT_CODES[c] for c in code[bad][:8]]} gpu "
+                             f"{list(zip(gi[k], gp[k], g['t'][k]))} oracle {list(zip(o.inst[k], o.prim[k], o.t[k]))}")
+    waived = (info & 2) != 0
+    u = ulps[gi >= 0]
+    log(f"    rays {rays.shape[0]}: flagged {fl.size}, t checks waived {int(waived.sum())}, t error in "
+        f"2^-24 S/(|d||cos|): p99 {np.percentile(u, 99) if u.size else 0:.2f} max {u.max() if u.size else 0:.2f}")
     if stats is not None:
-        stats["t_waived"] = stats.get("t_waived", 0) + n_waived
+        stats["t_waived"] = stats.get("t_waived", 0) + int(waived.sum())
         stats["rays"] = stats.get("rays", 0) + int(rays.shape[0])
         stats["flagged"] = stats.get("flagged", 0) + int(fl.size)
+        stats["max_t_ulps"] = max(stats.get("max_t_ulps", 0.0), float(u.max()) if u.size else 0.0)
     return flagged.mean()
 
 
@@ -144,7 +146,7 @@ def replay_check_pixels(rtq, osc, S, cams, st, pixels, img, **kw):
     Returns counts (paths, vertices, certain answers, t checks waived, shading
     decisions near a threshold)."""
     offs = np.cumsum([0] + [c.n_pixels() if hasattr(c, "n_pixels") else c.w * c.h for c in cams])
-    tot = dict(paths=0, vertices=0, certain=0, t_waived=0, ambiguous_shading=0)
+    tot = dict(paths=0, vertices=0, certain=0, t_waived=0, ambiguous_shading=0, max_t_ulps=0.0)
     for g in np.asarray(pixels):
         view = int(np.searchsorted(offs, g, side="right") - 1)
         p = int(g - offs[view])
@@ -160,6 +162,7 @@ def replay_check_pixels(rtq, osc, S, cams, st, pixels, img, **kw):
             tot["paths"] += 1
             for k in ("vertices", "certain", "t_waived", "ambiguous_shading"):
                 tot[k] += info[k]
+            tot["max_t_ulps"] = max(tot["max_t_ulps"], info["max_t_ulps"])
         mean = np.float32(acc / np.float32(st.spp))
         assert mean.view(np.uint32) == np.float32(img[g]).view(np.uint32), (g, mean, img[g])
         ref /= st.spp
