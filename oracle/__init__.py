@@ -208,7 +208,8 @@ class OracleScene:
         """Whether each answer (closest: inst, prim, t and optionally half, inst -1 for a
         miss; any_hit: inst = 1 occluded / 0 not) is one an FP32 traversal may give
         for the FP32 ray.  Returns (code [n] int32, 0 = valid, see ACCEPT_CODES;
-        info [n] int32 bits: 1 the certain hit, 2 t check waived, 4 other answers possible;
+        info [n] int32 bits: 1 the certain hit, 2 t ill-conditioned (held to the FP32 bound of
+        16 units of 2^-24 S / (|d| |cos|) instead of 1e-5 relative), 4 other answers possible;
         with want_ulps also the t error of each answer in units of 2^-24 S / (|d| |cos|))."""
         rays = np.ascontiguousarray(rays, dtype=np.float32)
         n = rays.shape[0]
@@ -232,8 +233,10 @@ class OracleScene:
         """Check a GPU path record (rtq_render_path: vi 6 int32 and vf 10 float32 per
         recorded ray, the escaping ray last) step by step along its own rays.
         Returns (code, stats): code 0 = valid, else PATH_CODES[code]; stats: failing
-        ray, FP64 radiance along the path, vertices, certain answers, t checks
-        waived, shading decisions within rounding of a threshold."""
+        ray, FP64 radiance along the path, vertices, certain answers, vertices
+        whose t is ill-conditioned (held to the FP32 bound), shading decisions
+        within rounding of a threshold, largest t error in units of
+        2^-24 S / (|d| |cos|)."""
         cf, ci, _ = self._cams(cams)
         pi, pu, pd = self._params(settings)
         vi = np.ascontiguousarray(vi, dtype=np.int32)

@@ -640,8 +640,10 @@ AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, in
 
 // Verdict on one closest-hit answer (inst, prim, half; half < 0 = either) at
 // parameter t_gpu: 0 valid, 1 not a possible answer, 2 a miss while a certain
-// hit exists, 3 t outside its tolerance.  *info: bit 1 the answer is the
-// certain hit, bit 2 its t check was waived (ill-conditioned).
+// hit exists, 3 t outside its tolerance (1e-5 relative plus the tie window's
+// absolute term; where t is ill-conditioned, 16 units of 2^-24 S / (|d| |cos|)).
+// *info: bit 1 the answer is the certain hit, bit 2 t is ill-conditioned (held
+// to the FP32 bound).
 int judge_closest(const AcceptSet& A, int32_t inst, int32_t prim, int32_t half, double t_gpu, int* info,
                   double* ulps = nullptr) {
   *info = 0;
@@ -657,12 +659,15 @@ int judge_closest(const AcceptSet& A, int32_t inst, int32_t prim, int32_t half, 
   if (A.has_certain && A.certain.k.inst == inst && A.certain.k.prim == prim &&
       (half < 0 || A.certain.k.half == half))
     *info |= 1;
-  if (ulps) *ulps = std::fabs(t_gpu - best->k.t) / best->tulp;
+  const double err = std::fabs(t_gpu - best->k.t);
+  if (ulps) *ulps = err / best->tulp;
   if (best->illcond) {
+    // FP32 cannot resolve t to 1e-5 here: t is held to the FP32 bound instead,
+    // 16 units of 2^-24 S along the normal, carried along the ray
     *info |= 2;
-    return 0;
+    return err <= 16.0 * best->tulp + best->win ? 0 : 3;
   }
-  return std::fabs(t_gpu - best->k.t) <= best->win ? 0 : 3;
+  return err <= best->win ? 0 : 3;
 }
 
 // Verdict on one any-hit answer: 0 valid, 1 occluded without any possible
@@ -952,7 +957,7 @@ struct PathCheck {
   int code = 0;     // 0 valid; otherwise the first failed check (see orc_check_path)
   int vertex = -1;  // the vertex (or ray) where it failed
   double L = 0.0;   // FP64 radiance along the GPU's decisions
-  int n_vert = 0, n_certain = 0, n_waived = 0, n_ambiguous_shading = 0;
+  int n_vert = 0, n_certain = 0, n_waived = 0, n_ambiguous_shading = 0;  // n_waived: t ill-conditioned
   double max_ulps = 0.0;  // largest t error in units of 2^-24 S / (|d| |cos|)
 };
 
@@ -1417,7 +1422,7 @@ void orc_trace_d(void* s, int64_t n, const double* rays, const int32_t* excl, co
 // possible answer, 2 a miss while a certain hit exists, 3 t outside its
 // tolerance; any hit: 1 occluded without a possible occluder, 2 unoccluded
 // while a certain occluder exists.  info[i] (may be NULL): bit 1 the answer is
-// the certain hit, bit 2 its t check was waived (ill-conditioned), bit 4 the ray
+// the certain hit, bit 2 its t is ill-conditioned (held to the FP32 bound), bit 4 the ray
 // has possible answers other than the certain hit.  ulps[i] (may be NULL): the
 // t error of a closest-hit answer in units of 2^-24 S / (|d| |cos|).
 void orc_accept(void* s, int64_t n, const float* rays, const int32_t* excl, const double* r0, int32_t mode,

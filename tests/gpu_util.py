@@ -59,8 +59,10 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
       give (the oracle's acceptance check over every triangle near the ray),
       with its t within tolerance unless ill-conditioned -- every flagged ray is
       checked.
+    Where t is ill-conditioned (FP32 cannot resolve it to 1e-5) it is held to
+    the FP32 bound, 16 units of 2^-24 S / (|d| |cos|), by the acceptance check.
     Returns the fraction of flagged rays; `stats` (a dict, optional) receives
-    the count of t checks waived as ill-conditioned.
+    counts and the largest t error in those units.
     """
     flagged = (o.flags & oracle.ID_FLAGS) != 0
     ok = ~flagged
@@ -103,7 +105,7 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
                              f"{list(zip(gi[k], gp[k], g['t'][k]))} oracle {list(zip(o.inst[k], o.prim[k], o.t[k]))}")
     waived = (info & 2) != 0
     u = ulps[gi >= 0]
-    log(f"    rays {rays.shape[0]}: flagged {fl.size}, t checks waived {int(waived.sum())}, t error in "
+    log(f"    rays {rays.shape[0]}: flagged {fl.size}, t ill-conditioned (FP32 bound) {int(waived.sum())}, t error in "
         f"2^-24 S/(|d||cos|): p99 {np.percentile(u, 99) if u.size else 0:.2f} max {u.max() if u.size else 0:.2f}")
     if stats is not None:
         stats["t_waived"] = stats.get("t_waived", 0) + int(waived.sum())
@@ -143,8 +145,9 @@ def replay_check_pixels(rtq, osc, S, cams, st, pixels, img, **kw):
     FP64 radiance to 1e-4).  The pixel must equal the mean of its recorded
     paths' radiance bit for bit (FP32 sum in sample order over spp, as the
     accumulation forms it) and the mean of the oracle's replay values to 1e-4.
-    Returns counts (paths, vertices, certain answers, t checks waived, shading
-    decisions near a threshold)."""
+    Returns counts (paths, vertices, certain answers, vertices whose t is
+    ill-conditioned and held to the FP32 bound, shading decisions near a
+    threshold) and the largest t error in units of 2^-24 S / (|d| |cos|)."""
     offs = np.cumsum([0] + [c.n_pixels() if hasattr(c, "n_pixels") else c.w * c.h for c in cams])
     tot = dict(paths=0, vertices=0, certain=0, t_waived=0, ambiguous_shading=0, max_t_ulps=0.0)
     for g in np.asarray(pixels):

@@ -319,6 +319,17 @@ def test_acceptance_single_quad_closed_form(ora):
     assert acc(-1, -1, -1, np.inf)[0] == 2           # a miss
     assert acc(0, 0, 0, np.float32(2.0 * (1 + 1e-4)))[0] == 3
     assert acc(0, 0, 0, np.float32(2.0 * (1 + 2e-6)))[0] == 0
+    # an ill-conditioned t (a grazing hit far from the origin) is held to the
+    # FP32 bound, 16 units of 2^-24 S / (|d| |cos|), not waived
+    rg = _rays([[-399.5, 0.5, 0.04]], [[1.0, 0.0, -1e-4]]).astype(np.float32)
+    r64 = rg.astype(np.float64)
+    tg = -r64[0, 2] / r64[0, 5]
+    hg = o.trace(rg)
+    assert hg.inst[0] == 0 and (hg.flags[0] & oracle.F_T_ILLCOND)
+    unit = 2.0 ** -24 * hg.scale[0] / abs(r64[0, 5])  # |d| |cos| = |d_z| on the floor
+    for k, want in ((0.0, 0), (8.0, 0), (40.0, 3)):
+        code, info = o.accept(rg, [0], [0], [np.float32(tg + k * unit)])
+        assert code[0] == want and (info[0] & 2), (k, code, info)
 
 
 def test_acceptance_shared_edge_and_ties(ora):
