@@ -322,10 +322,11 @@ typedef struct {
                           bottom-level nodes and quads tested, summed over the
                           closest-hit rays ([0..3]) and over the shadow rays
                           ([4..7]) (accumulated; selects a slower counting variant) */
-  float* dump_rays;    /* optional device 10 x dump_cap 32-bit words, structure of
+  float* dump_rays;    /* optional device 12 x dump_cap 32-bit words, structure of
                           arrays: ox, oy, oz, dx, dy, dz, tmin, tmax (FP32), then the
                           two words of the hit reference of the triangle the ray
-                          leaves (uint32, as rtq_hits.ref, for rtq_rays.exclude):
+                          leaves (uint32, as rtq_hits.ref, for rtq_rays.exclude),
+                          then that triangle's instance id and primitive | half << 31:
                           extension rays of bounce >= 1 (plain and persistent
                           schedulers) */
   int64_t dump_cap;    /* capacity of dump_rays in rays */

@@ -368,7 +368,7 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.start_tick = _ptr(start_tick)
     o.visits = _ptr(visits)
     o.dump_rays = _ptr(dump_rays)
-    o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 10
+    o.dump_cap = 0 if dump_rays is None else dump_rays.numel() // 12
     o.dump_count = _ptr(dump_count)
     o.timing = 1 if timing else 0
     o.graph = 1 if graph else 0

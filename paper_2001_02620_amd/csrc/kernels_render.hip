@@ -350,8 +350,11 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
       dump[5 * c + jd] = ndz;
       dump[6 * c + jd] = 0.0f;
       dump[7 * c + jd] = kInfF;
-      reinterpret_cast<uint32_t*>(dump)[8 * c + jd] = rec;
-      reinterpret_cast<uint32_t*>(dump)[9 * c + jd] = qhv;
+      uint32_t* du = reinterpret_cast<uint32_t*>(dump);
+      du[8 * c + jd] = rec;
+      du[9 * c + jd] = qhv;
+      du[10 * c + jd] = sc.inst[rec].inst_id;
+      du[11 * c + jd] = (uint32_t)sc.quad_prim[qhv & 0x7FFFFFFFu] | (qhv & 0x80000000u);
     }
   }
 }
