@@ -258,6 +258,23 @@ int rtq_trace_closest(const rtq_scene* scene, const rtq_rays* rays, int64_t n, r
                       const rtq_trace_opts* opts, hipStream_t stream);
 
 /*
+ * rtq_trace_closest with the persistent scheduler, allocating nothing: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid it).  Same arguments, results and
+ * errors as rtq_trace_closest; opts.scheduler is ignored (always persistent).
+ * The persistent launch's claim counters (1 KiB) live in a static device array
+ * the library holds on each device it runs on until the process ends, instead
+ * of the scene's counter ring; the call clears them with a kernel before its
+ * launch.  Every call on one device shares that array: calls that overlap in
+ * time on one device race and must be ordered by the caller (one stream, or
+ * events).  The first call on a device looks the array's address up
+ * (hipGetSymbolAddress, no allocation).  Errors as rtq_trace_closest, plus
+ * RTQ_E_HIP if the address lookup fails.
+ */
+int rtq_trace_closest_noalloc(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits,
+                              const rtq_trace_opts* opts, hipStream_t stream);
+
+/*
  * Occlusion: occluded[i] = 1 if any hit with tmin < t <= tmax exists, else 0 --
  * the shadow-ray query of next-event estimation (Section 5.4 samples the
  * scene's lights at every path vertex).  Arguments and errors as

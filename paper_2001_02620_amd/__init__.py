@@ -95,7 +95,8 @@ _lib = None
 EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destroy", "rtq_scene_get_info",
            "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
            "rtq_render_backward", "rtq_render_timing", "rtq_render_path", "rtq_host_bvh_build", "rtq_host_bvh_get",
-           "rtq_host_bvh_destroy", "rtq_scene_set_textures", "rtq_scene_set_environment"]
+           "rtq_host_bvh_destroy", "rtq_scene_set_textures", "rtq_scene_set_environment",
+           "rtq_trace_closest_noalloc"]
 
 
 def load_library():
@@ -121,6 +122,7 @@ def load_library():
     L.rtq_scene_set_environment.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P]
     L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    L.rtq_trace_closest_noalloc.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
     L.rtq_host_bvh_build.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
     L.rtq_host_bvh_get.argtypes = [P, P, P, P, P, P]

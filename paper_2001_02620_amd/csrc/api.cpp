@@ -646,6 +646,32 @@ int rtq_trace_closest(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_h
   return trace_common(s, rays, n, hits, nullptr, opts, stream);
 }
 
+int rtq_trace_closest_noalloc(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hits* hits,
+                              const rtq_trace_opts* opts, hipStream_t stream) {
+  if (!hits) return set_error(RTQ_E_INVALID_ARG, "NULL hits");
+  if (n > 0 && (!hits->t || !hits->u || !hits->v || !hits->inst || !hits->prim))
+    return set_error(RTQ_E_INVALID_ARG, "NULL hit array");
+  int rc = check_rays(s, rays, n);
+  if (rc) return rc;
+  rtq_trace_opts o{};
+  if (opts) o = *opts;
+  int fmt;
+  if ((rc = resolve_format(s, o.node_format, &fmt))) return rc;
+  TraceLaunch tl;
+  if ((rc = resolve_launch(s, RTQ_SCHED_PERSISTENT, o.stack_depth, o.block, o.waves_per_cu, o.refill, &tl)))
+    return rc;
+  tl.fmt = fmt;
+  unsigned long long* ctr = nullptr;
+  hipError_t e = noalloc_counters(s->device, &ctr);
+  if (e != hipSuccess) return hip_error(e, "claim counter address (hipGetSymbolAddress)");
+  tl.counter = ctr;  // in place of the scene's counter ring; cleared by a fill kernel before the launch
+  if (n == 0) return RTQ_OK;
+  const SceneView sv = scene_view(s, fmt);
+  const HitsSoA h{hits->t, hits->u, hits->v, hits->inst, hits->prim, hits->ref};
+  e = launch_trace(sv, soa(rays), n, &h, nullptr, o.visits, tl, stream);
+  return e == hipSuccess ? RTQ_OK : hip_error(e, "trace launch");
+}
+
 int rtq_trace_occluded(const rtq_scene* s, const rtq_rays* rays, int64_t n, uint8_t* occluded,
                        const rtq_trace_opts* opts, hipStream_t stream) {
   if (n > 0 && !occluded) return set_error(RTQ_E_INVALID_ARG, "NULL occluded array");

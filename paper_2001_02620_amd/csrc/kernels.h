@@ -40,6 +40,9 @@ struct TraceLaunch {
 
 hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA* hits, uint8_t* occ,
                         uint32_t* visits, const TraceLaunch& tl, hipStream_t s);
+// Device address of the allocation-free query's claim counters (kClaimWords
+// words, a static device array) on `device`; looked up once per device.
+hipError_t noalloc_counters(int device, unsigned long long** out);
 hipError_t launch_trace_brute(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA& hits,
                               hipStream_t s);
 

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "kernels.h"
 #include "trace_device.h"
 
@@ -158,6 +161,36 @@ hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, con
   if (n == 0) return hipSuccess;
   return tl.fmt == 2 ? launch2<2>(sc, rays, n, hits, occ, visits, tl, s)
                      : launch2<1>(sc, rays, n, hits, occ, visits, tl, s);
+}
+
+// Claim counters of the allocation-free ray query (rtq_trace_closest_noalloc):
+// one persistent launch's worth, kClaimWords 64-bit words (1 KiB), held by every
+// device the library runs on until the process ends.  Host code never uses
+// this name as an address: noalloc_counters() returns the device's own address
+// of the array.
+static __device__ __align__(256) unsigned long long scratch[kClaimWords];
+
+hipError_t noalloc_counters(int device, unsigned long long** out) {
+  static std::mutex mu;
+  static std::map<int, unsigned long long*> addr;  // per device, looked up once
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  addr[device] = static_cast<unsigned long long*>(p);
+  *out = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_trace_brute(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA& hits,
