@@ -179,12 +179,12 @@ def main():
     torch.cuda.synchronize()
     nd = int(min(int(dcount.cpu().item()), cap))
     planes = dump.view(12, cap)[:, :nd]
-    rays = planes[:8].t().contiguous()
+    rays = planes[:8].contiguous()  # structure of arrays [8, n], traced in place
     excl = planes[8:10].view(torch.int32).t().contiguous()
     log(f"incoherent rays: {nd} of {int(dcount.cpu().item())} bounce >= 1 rays of frame 0")
 
     def query(kw):
-        return rtq.trace_closest(S, rays, exclude=excl, **kw)
+        return rtq.trace_closest(S, rays, exclude=excl, soa_in=True, **kw)
 
     def timed_queries(kw, steps, warmup):
         for _ in range(warmup):
@@ -253,7 +253,8 @@ def main():
     inc_visits = {}
     for name, fmt in (("q8", rtq.RTQ_NODE_Q8), ("fp32", rtq.RTQ_NODE_FP32)):
         v = torch.zeros((nd, 4), dtype=torch.int32, device="cuda")
-        rtq.trace_closest(S, rays, exclude=excl, node_format=fmt, scheduler=rtq.SCHED_PERSISTENT, visits=v)
+        rtq.trace_closest(S, rays, exclude=excl, soa_in=True, node_format=fmt, scheduler=rtq.SCHED_PERSISTENT,
+                          visits=v)
         torch.cuda.synchronize()
         inc_visits[name] = v.to(torch.float64).sum(0).cpu().numpy()
         del v
@@ -347,16 +348,16 @@ def main():
         torch.cuda.synchronize()
         m2 = int(min(int(c2.cpu().item()), cap))
         pl2 = d2.view(12, cap)[:, :m2]
-        r2, e2 = pl2[:8].t().contiguous(), pl2[8:10].view(torch.int32).t().contiguous()
+        r2, e2 = pl2[:8].contiguous(), pl2[8:10].view(torch.int32).t().contiguous()
         out2 = {"workload": "config2: 1M instances, 14M unique quads, 2 views 1920x1080, 1 spp, depth 8",
                 "incoherent_rays": m2}
         for name, kw in (("q8_persistent", Q8P), ("fp32_plain", F32)):
             for _ in range(2):
-                rtq.trace_closest(S2, r2, exclude=e2, **kw)
+                rtq.trace_closest(S2, r2, exclude=e2, soa_in=True, **kw)
             torch.cuda.synchronize()
             w0 = time.perf_counter()
             for _ in range(5):
-                rtq.trace_closest(S2, r2, exclude=e2, **kw)
+                rtq.trace_closest(S2, r2, exclude=e2, soa_in=True, **kw)
             torch.cuda.synchronize()
             inc_ms = (time.perf_counter() - w0) / 5 * 1e3
             for i in range(3):
@@ -385,7 +386,7 @@ def main():
         import oracle
         log("cpu baseline: building the oracle scene")
         o = oracle.OracleScene(scene)
-        rs = rays.cpu().numpy()
+        rs = rays.t().contiguous().cpu().numpy()
         ex_pub = planes[10:12].view(torch.int32).t().contiguous().cpu().numpy()
         excl3 = np.stack([ex_pub[:, 0], ex_pub[:, 1] & 0x7FFFFFFF, (ex_pub[:, 1].view(np.uint32) >> 31)
                           .astype(np.int32)], 1)

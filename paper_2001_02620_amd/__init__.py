@@ -263,15 +263,22 @@ class Hits:
     ref: object = None  # [n, 2] int32 view of the opaque hit references, when asked for
 
 
-def _rays_struct(rays, exclude=None):
-    """rays: CUDA float32 tensor [n, 8] (ox oy oz dx dy dz tmin tmax) -> SoA copy + struct;
+def _rays_struct(rays, exclude=None, soa_in=False):
+    """rays: CUDA float32 tensor [n, 8] (ox oy oz dx dy dz tmin tmax) -> SoA copy + struct,
+    or, with soa_in, a contiguous float32 tensor [8, n] used in place (no copy);
     exclude: optional CUDA int32 tensor [n, 2] of hit references (Hits.ref) not to hit."""
     torch = _torch()
-    assert rays.is_cuda and rays.dim() == 2 and rays.shape[1] == 8
-    soa = rays.to(torch.float32).t().contiguous()
+    if soa_in:
+        assert rays.is_cuda and rays.dim() == 2 and rays.shape[0] == 8 and rays.dtype == torch.float32
+        assert rays.is_contiguous()
+        soa = rays
+    else:
+        assert rays.is_cuda and rays.dim() == 2 and rays.shape[1] == 8
+        soa = rays.to(torch.float32).t().contiguous()
+    n = soa.shape[1]
     ex = None
     if exclude is not None:
-        assert exclude.is_cuda and exclude.shape == (rays.shape[0], 2) and exclude.dtype == torch.int32
+        assert exclude.is_cuda and exclude.shape == (n, 2) and exclude.dtype == torch.int32
         ex = exclude.contiguous()
     st = _Rays(*[soa[k].data_ptr() for k in range(8)], _ptr(ex))
     return (soa, ex), st
@@ -282,12 +289,13 @@ def _trace_opts(node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, wa
     return _TraceOpts(node_format, scheduler, stack_depth, block, waves_per_cu, refill, _ptr(visits))
 
 
-def trace_closest(scene: Scene, rays, exclude=None, want_ref: bool = False, **opts) -> Hits:
-    """Closest hits of rays [n, 8]; exclude: optional [n, 2] int32 hit references
-    of triangles the rays leave; want_ref: also return each hit's reference."""
+def trace_closest(scene: Scene, rays, exclude=None, want_ref: bool = False, soa_in: bool = False, **opts) -> Hits:
+    """Closest hits of rays [n, 8] (or [8, n] structure of arrays with soa_in);
+    exclude: optional [n, 2] int32 hit references of triangles the rays leave;
+    want_ref: also return each hit's reference."""
     torch = _torch()
-    n = rays.shape[0]
-    soa, st = _rays_struct(rays, exclude)
+    n = rays.shape[1] if soa_in else rays.shape[0]
+    soa, st = _rays_struct(rays, exclude, soa_in)
     dev = rays.device
     h = Hits(torch.empty(n, device=dev), torch.empty(n, device=dev), torch.empty(n, device=dev),
              torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
