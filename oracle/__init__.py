@@ -75,6 +75,7 @@ def lib():
         L.orc_render.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, P, P]
         L.orc_grad.argtypes = [P, P, P, i32, P, P, P, P, i64, i32, P, i32, P, P, P, P, P, i32]
         L.orc_path.argtypes = [P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
+        L.orc_flag_breakdown.argtypes = [P, P, P, i32, P, P, P, P, i64, P]
         L.orc_accept.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
         L.orc_check_path.argtypes = [P, P, P, i32, P, P, P, i32, i64, i32, i32, P, P, i32, ctypes.c_float, P]
         L.orc_check_path.restype = i32
@@ -227,6 +228,19 @@ class OracleScene:
         lib().orc_accept(self.h, n, _p(rays), _p(ex), _p(rr), 0 if brute else 1, 1 if any_hit else 0, _p(gi),
                          _p(gp), _p(gh), _p(gt), _p(out), _p(info), _p(ul))
         return (out, info, ul) if want_ulps else (out, info)
+
+    def flag_breakdown(self, cams, settings, pixels: np.ndarray) -> np.ndarray:
+        """Flags by kind and bounce over the listed packed pixels (every sample):
+        [16, 8] counts; row b = closest-hit rays of bounce b; columns: near tie,
+        graze, near origin, ill-conditioned t, diagonal, shading within
+        rounding, flagged shadow rays, all closest-hit rays."""
+        cf, ci, _ = self._cams(cams)
+        pi, pu, pd = self._params(settings)
+        px = np.ascontiguousarray(pixels, dtype=np.int64)
+        out = np.zeros(16 * 8)
+        lib().orc_flag_breakdown(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), px.shape[0],
+                                 _p(out))
+        return out.reshape(16, 8)
 
     def check_path(self, cams, settings, cam: int, local: int, sample: int, nv: int, vi: np.ndarray,
                    vf: np.ndarray, escaped: bool, radiance: float):

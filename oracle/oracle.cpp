@@ -766,6 +766,7 @@ struct PathRec {
   bool escaped = false;
   double L_esc = 0.0;  // radiance seen by the escaping ray (sky or environment map)
   uint32_t flags = 0;
+  uint32_t esc_flags = 0;  // flags of the escaping ray (when the path escaped)
   int n_closest = 0, n_shadow = 0, n_incoherent = 0;
 };
 
@@ -812,7 +813,9 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     rec.flags |= h.flags & ~(uint32_t)F_T_ILLCOND;
     if (h.best.inst < 0) {
       rec.escaped = true;
-      rec.L_esc = S.env_w > 0 ? env_radiance(S, ray.d, &rec.flags) : P.L_sky;
+      rec.esc_flags = h.flags;
+      rec.L_esc = S.env_w > 0 ? env_radiance(S, ray.d, &rec.esc_flags) : P.L_sky;
+      rec.flags |= rec.esc_flags & ~(uint32_t)F_T_ILLCOND;
       return;
     }
     V3 wq[4];
@@ -822,7 +825,8 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     V3 n = h.best.half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
     n = normalize(n);
     const double nd = dot(n, ray.d);
-    if (std::fabs(nd) < 1e-3) rec.flags |= F_SHADE;
+    uint32_t vshade = 0;  // shading decisions of this vertex within rounding of a threshold
+    if (std::fabs(nd) < 1e-3) vshade |= F_SHADE;
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
     double a = S.albedo[face];
@@ -862,7 +866,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       philox(ctr3, key, wl);
       j = (int)(((uint64_t)(wl[0] >> 8) * (uint64_t)nl) >> 24);
     }
-    if (j == 0 && std::fabs(cl) < 1e-6) rec.flags |= F_SHADE;
+    if (j == 0 && std::fabs(cl) < 1e-6) vshade |= F_SHADE;
     // origin uncertainty of rays leaving p: the FP32 position error of this hit
     // plus the incoming ray's own origin uncertainty, both stretched along the
     // surface by the incidence angle
@@ -897,7 +901,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       const double A = norm(nlv);
       const double cp = dd > 0 ? dot(n, wi) / dd : 0.0;
       const double cq = dd > 0 && A > 0 ? -dot(nlv, wi) / (A * dd) : 0.0;
-      if (std::fabs(cp) < 1e-6 || std::fabs(cq) < 1e-6 || dd < 1e-6 * h.S) rec.flags |= F_SHADE;
+      if (std::fabs(cp) < 1e-6 || std::fabs(cq) < 1e-6 || dd < 1e-6 * h.S) vshade |= F_SHADE;
       if (cp > 0 && cq > 0) {
         Ray sr{p, wi, 0.0, 1.0};
         TraceOut o = trace_one(S, sr, here, r1, mode, true);
@@ -908,12 +912,17 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
         if (o.best.inst < 0) vx.c = nl * (Lq[9] * A * cp * cq / (kPi * d2));
       }
     }
+    vx.flags |= vshade;
+    rec.flags |= vshade;
     rec.v[rec.nv++] = vx;
     if (b == P.depth - 1) return;
     uint32_t ctr2[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, (uint32_t)b};
     philox(ctr2, key, w);
     const double u1 = unit(w[2]), u2 = unit(w[3]);
-    if (std::fabs(n.z) < 1e-6) rec.flags |= F_SHADE;
+    if (std::fabs(n.z) < 1e-6) {
+      rec.flags |= F_SHADE;
+      rec.v[rec.nv - 1].flags |= F_SHADE;
+    }
     const double sg = n.z >= 0 ? 1.0 : -1.0;
     const double aa = -1.0 / (sg + n.z);
     const double bb = n.x * n.y * aa;
@@ -1449,6 +1458,46 @@ void orc_accept(void* s, int64_t n, const float* rays, const int32_t* excl, cons
     if (others || !A.has_certain) inf |= 4;
     if (info) info[i] = inf;
   });
+}
+
+// Flags by kind and bounce over the listed packed pixels (all samples): hist
+// is [16 x 8] doubles; row b counts the closest-hit rays of bounce b (b >= 15
+// folded into row 15): columns 0..5 those carrying F_NEAR_TIE, F_GRAZE,
+// F_NEAR_ORIGIN, F_T_ILLCOND, F_DIAG, F_SHADE (the ray, its vertex's shading
+// decisions, or the environment texel of an escaping ray), column 6 the
+// bounce's shadow rays carrying any flag, column 7 every closest-hit ray.
+void orc_flag_breakdown(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
+                        const uint64_t* pu, const double* pd, const int64_t* pix, int64_t n_pix, double* hist) {
+  const Scene& S = *static_cast<Scene*>(s);
+  const Params P = make_params(pi, pu, pd);
+  std::vector<Cam> cams;
+  for (int c = 0; c < n_cams; ++c) cams.push_back(make_cam(cam_f + 10 * c, cam_i + 8 * c));
+  const int nt = threads();
+  std::vector<std::vector<double>> h(nt, std::vector<double>(16 * 8, 0.0));
+  parallel_for(n_pix, nt, [&](int64_t i, int tid) {
+    int32_t view;
+    int64_t p;
+    resolve_pixel(cams, pix[i], &view, &p);
+    for (int32_t smp = 0; smp < P.spp; ++smp) {
+      PathRec rec;
+      trace_path(S, P, cams[view], (int32_t)cams[view].view_id, p, smp, 1, rec);
+      auto add = [&](int b, uint32_t fl) {
+        const int r = std::min(b, 15);
+        for (int k = 0; k < 6; ++k)
+          if (fl & (1u << k)) h[tid][8 * r + k] += 1;
+        h[tid][8 * r + 7] += 1;
+      };
+      for (int k = 0; k < rec.nv; ++k) {
+        add(k, rec.v[k].flags);
+        if (rec.v[k].shadow >= 0 && rec.v[k].shadow_flags) h[tid][8 * std::min(k, 15) + 6] += 1;
+      }
+      if (rec.escaped) add(rec.nv, rec.esc_flags);
+    }
+  });
+  for (int k = 0; k < 16 * 8; ++k) {
+    hist[k] = 0;
+    for (int t = 0; t < nt; ++t) hist[k] += h[t][k];
+  }
 }
 
 // Check one GPU path (cam entry `cam`, pixel `local` of its rectangle, sample)
