@@ -264,7 +264,8 @@ class OracleScene:
 
     @staticmethod
     def _params(settings):
-        pi = np.array([settings.spp, settings.depth], dtype=np.int32)
+        pi = np.array([settings.spp, settings.depth, 1 if getattr(settings, "env_nee", False) else 0],
+                      dtype=np.int32)
         pu = np.array([settings.seed, settings.frame], dtype=np.uint64)
         al = np.asarray(settings.area_lights, dtype=np.float32).reshape(-1, 10).astype(np.float64)
         pd = np.array(list(settings.light_dir) + [settings.E, settings.L_sky, al.shape[0]] + al.ravel().tolist(),

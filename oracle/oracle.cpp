@@ -153,6 +153,9 @@ struct Scene {
   // optional environment map: env_w x env_h radiance values, equirectangular
   std::vector<double> env;
   int32_t env_w = 0, env_h = 0;
+  // its importance-sampling table: texel k (row-major) is drawn with
+  // probability (env_T[k] - env_T[k - 1]) / 2^32 (see env_table)
+  std::vector<uint64_t> env_T;
   int64_t N = 0;
   std::vector<int32_t> iproto;
   std::vector<double> X;           // 12 per instance: row-major [A | t] (FP32 values)
@@ -708,13 +711,16 @@ struct Params {
   double E, L_sky;
   int n_area = 0;               // quad area lights
   const double* area = nullptr;  // 10 per light: corner, edge 1, edge 2, emitted radiance
+  bool env_nee = false;          // next-event estimation toward the environment map
 };
 
-// pd: light direction (3), E, L_sky, number of area lights, then 10 per light.
+// pi: spp, depth, environment next-event estimation (0/1); pd: light
+// direction (3), E, L_sky, number of area lights, then 10 per light.
 Params make_params(const int32_t* pi, const uint64_t* pu, const double* pd) {
   Params P{pi[0], pi[1], pu[0], (uint32_t)pu[1], {pd[0], pd[1], pd[2]}, pd[3], pd[4]};
   P.n_area = (int)pd[5];
   P.area = pd + 6;
+  P.env_nee = pi[2] != 0;
   return P;
 }
 
@@ -793,6 +799,55 @@ double env_radiance(const Scene& S, V3 d, uint32_t* flags) {
   return S.env[(size_t)ty * W + tx];
 }
 
+// Importance sampling of the environment map (Section 4.1 names the scene's
+// textured environment light; next-event estimation toward it).  Texel k = ty W
+// + tx covers azimuths [-pi + 2 pi tx / W, -pi + 2 pi (tx + 1) / W) and polar
+// angles [pi ty / H, pi (ty + 1) / H), a solid angle
+// Omega_ty = (2 pi / W) (cos(pi ty / H) - cos(pi (ty + 1) / H)).  It is drawn
+// with probability p_k proportional to L_k Omega_ty, quantised to 32 bits:
+// T_k = floor(2^32 C_k / C_total), C the running sum of L Omega in texel order
+// (FP64), p_k = (T_k - T_{k-1}) / 2^32, so the draw (the first k with a
+// 32-bit word w < T_k) is an integer decision.  The direction is uniform in
+// solid angle within the texel; its density is p_k / Omega_ty.
+double env_omega(const Scene& S, int ty) {
+  const double H = S.env_h;
+  return (2.0 * kPi / S.env_w) * (std::cos(kPi * ty / H) - std::cos(kPi * (ty + 1) / H));
+}
+
+void env_table(Scene& S) {
+  const int64_t n = (int64_t)S.env_w * S.env_h;
+  S.env_T.assign(n, 0);
+  double total = 0.0;
+  for (int64_t k = 0; k < n; ++k) total += S.env[k] * env_omega(S, (int)(k / S.env_w));
+  double cum = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    cum += S.env[k] * env_omega(S, (int)(k / S.env_w));
+    S.env_T[k] = total > 0.0 ? (uint64_t)std::floor(std::ldexp(cum / total, 32)) : (uint64_t)((k + 1) * 4294967296.0 / n);
+  }
+  S.env_T[n - 1] = (uint64_t)1 << 32;
+}
+
+// probability of texel k
+inline double env_p(const Scene& S, int64_t k) {
+  return std::ldexp((double)(S.env_T[k] - (k > 0 ? S.env_T[k - 1] : 0)), -32);
+}
+
+// the texel a direction reads (nearest, as the escape lookup)
+int64_t env_texel(const Scene& S, V3 d) {
+  d = normalize(d);
+  const double th = std::acos(std::min(1.0, std::max(-1.0, d.z)));
+  const double u = (std::atan2(d.y, d.x) + kPi) / (2.0 * kPi), v = th / kPi;
+  const int tx = std::min(std::max((int)std::floor(u * S.env_w), 0), S.env_w - 1);
+  const int ty = std::min(std::max((int)std::floor(v * S.env_h), 0), S.env_h - 1);
+  return (int64_t)ty * S.env_w + tx;
+}
+
+// density (per solid angle) of the environment sampling toward direction d
+inline double env_pdf(const Scene& S, int64_t k) { return env_p(S, k) / env_omega(S, (int)(k / S.env_w)); }
+
+// Power-heuristic weight of strategy a against b (Veach 1997).
+inline double mis_power(double a, double b) { return a * a / (a * a + b * b); }
+
 void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, int64_t pix, int32_t sample,
                 int mode, PathRec& rec) {
   const uint32_t key[2] = {(uint32_t)(P.seed & 0xffffffffu), (uint32_t)(P.seed >> 32) ^ P.frame};
@@ -806,6 +861,9 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
   Ray ray{cam.eye, normalize(cam.f + sx * cam.r + sy * cam.u), 0.0, kInf};
   Excl ex;
   double r0 = 0.0;
+  double pdf_bsdf = 0.0;  // density of the cosine sample that produced the current ray (bounce >= 1)
+  const bool env_light = P.env_nee && S.env_w > 0;
+  const int nl = 1 + P.n_area + (env_light ? 1 : 0);
   for (int b = 0; b < P.depth; ++b) {
     TraceOut h = trace_one(S, ray, ex, r0, mode, false);
     rec.n_closest++;
@@ -815,6 +873,9 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       rec.escaped = true;
       rec.esc_flags = h.flags;
       rec.L_esc = S.env_w > 0 ? env_radiance(S, ray.d, &rec.esc_flags) : P.L_sky;
+      // with next-event estimation toward the map, an escaping bounce ray is
+      // the other strategy for the same light: weighted against it
+      if (env_light && b >= 1) rec.L_esc *= mis_power(pdf_bsdf, env_pdf(S, env_texel(S, ray.d)) / nl);
       rec.flags |= rec.esc_flags & ~(uint32_t)F_T_ILLCOND;
       return;
     }
@@ -854,14 +915,14 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     Vertex vx{face, param, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
     const double cl = dot(n, L);
     // next-event estimation (Section 4.1 names the scene's quad-shaped key
-    // lights): with area lights, one of the nl = 1 + n_area
-    // lights (0: the directional light) is picked with equal probability from
-    // word 0 of counter (pixel, sample, view, 2^31 + b), as an integer, and its
+    // lights and its environment light): with area lights or a sampled
+    // environment, one of the nl = 1 + n_area (+ 1) lights (0: the directional
+    // light, last: the environment) is picked with equal probability from word
+    // 0 of counter (pixel, sample, view, 2^31 + b), as an integer, and its
     // estimate is weighted by nl
-    const int nl = 1 + P.n_area;
     int j = 0;
     uint32_t wl[4] = {0u, 0u, 0u, 0u};
-    if (P.n_area > 0) {
+    if (nl > 1) {
       uint32_t ctr3[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x80000000u | (uint32_t)b};
       philox(ctr3, key, wl);
       j = (int)(((uint64_t)(wl[0] >> 8) * (uint64_t)nl) >> 24);
@@ -887,6 +948,36 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       vx.shadow = o.best.inst >= 0 ? 1 : 0;
       vx.shadow_flags = o.flags;
       if (o.best.inst < 0) vx.c = nl * (P.E / kPi * cl);
+    } else if (env_light && j == nl - 1) {
+      // the environment: texel k from word 1 (the first k with w1 < T_k), a
+      // direction uniform in solid angle within it from words 2, 3; estimate
+      // nl L_k cos_p w / (pi pdf), w the power-heuristic weight against the
+      // cosine sample (density cos_p / pi)
+      const int64_t nt = (int64_t)S.env_w * S.env_h;
+      int64_t lo = 0, hi = nt - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if ((uint64_t)wl[1] < S.env_T[mid]) hi = mid;
+        else lo = mid + 1;
+      }
+      const int tx = (int)(lo % S.env_w), ty = (int)(lo / S.env_w);
+      const double phi = -kPi + 2.0 * kPi * (tx + unit(wl[2])) / S.env_w;
+      const double z0 = std::cos(kPi * ty / S.env_h), z1 = std::cos(kPi * (ty + 1) / S.env_h);
+      const double z = z0 - unit(wl[3]) * (z0 - z1);
+      const double sr_ = std::sqrt(std::max(0.0, 1.0 - z * z));
+      const V3 de{sr_ * std::cos(phi), sr_ * std::sin(phi), z};
+      const double cp = dot(n, de);
+      if (std::fabs(cp) < 1e-6) vshade |= F_SHADE;
+      if (cp > 0) {
+        Ray sr{p, de, 0.0, kInf};
+        TraceOut o = trace_one(S, sr, here, r1, mode, true);
+        rec.n_shadow++;
+        rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
+        vx.shadow = o.best.inst >= 0 ? 1 : 0;
+        vx.shadow_flags = o.flags;
+        const double pdf = env_pdf(S, lo);
+        if (o.best.inst < 0) vx.c = nl * (S.env[lo] * cp * mis_power(pdf / nl, cp / kPi) / (kPi * pdf));
+      }
     } else if (j > 0) {
       // area light j - 1: the parallelogram c + s e1 + t e2, (s, t) uniform from
       // words 1, 2, emitting Le from the side e1 x e2 faces.  Its estimate of
@@ -930,6 +1021,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     const V3 t2{bb, sg + n.y * n.y * aa, -n.y};
     const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
     const V3 dnew = (rr * std::cos(phi)) * t1 + (rr * std::sin(phi)) * t2 + std::sqrt(1.0 - u1) * n;
+    pdf_bsdf = std::sqrt(1.0 - u1) / kPi;
     ray = Ray{p, dnew, 0.0, kInf};
     ex = here;
     r0 = r1;
@@ -988,7 +1080,7 @@ V3 cosine_sample(V3 n, double u1, double u2, bool flip) {
 // Environment texels a direction may read: the exact one, and its neighbours
 // across a texel boundary within rounding (angular distance times sin(theta)
 // below 1e-5) or near a pole (within 1e-3).
-int env_candidates(const Scene& S, V3 d, double out[9]) {
+int env_candidates(const Scene& S, V3 d, double out[9], int64_t idx[9]) {
   d = normalize(d);
   const double th = std::acos(std::min(1.0, std::max(-1.0, d.z)));
   const double st = std::sin(th);
@@ -1012,7 +1104,11 @@ int env_candidates(const Scene& S, V3 d, double out[9]) {
   }
   int n = 0;
   for (int a = 0; a < nx; ++a)
-    for (int b = 0; b < ny; ++b) out[n++] = S.env[(size_t)ys[b] * W + xs[a]];
+    for (int b = 0; b < ny; ++b) {
+      idx[n] = (int64_t)ys[b] * W + xs[a];
+      out[n] = S.env[idx[n]];
+      ++n;
+    }
   return n;
 }
 
@@ -1057,6 +1153,9 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
   Excl ex;
   double beta = 1.0;
   double Lsum = 0.0;
+  double pdf_bsdf = 0.0;  // density of the cosine sample behind the current ray
+  const bool env_light = P.env_nee && S.env_w > 0;
+  const int nl = 1 + P.n_area + (env_light ? 1 : 0);
   std::vector<double> esc_vals;
   for (int k = 0; k <= nv; ++k) {
     if (k == nv && !escaped) break;
@@ -1068,8 +1167,14 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       if (judge_closest(A, -1, -1, -1, kInf, &info)) return fail(3, k);
       if (S.env_w > 0) {
         double c[9];
-        const int n = env_candidates(S, ray.d, c);
-        for (int j = 0; j < n; ++j) esc_vals.push_back(c[j]);
+        int64_t kk[9];
+        const int n = env_candidates(S, ray.d, c, kk);
+        for (int j = 0; j < n; ++j) {
+          // with next-event estimation toward the map, an escaping bounce ray
+          // is weighted against it (as the path loop does)
+          const double w = env_light && k >= 1 ? mis_power(pdf_bsdf, env_pdf(S, kk[j]) / nl) : 1.0;
+          esc_vals.push_back(c[j] * w);
+        }
       } else {
         esc_vals.push_back(P.L_sky);
       }
@@ -1156,10 +1261,9 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       return fail(6, k);
     }
     // next-event estimate
-    const int nl = 1 + P.n_area;
     int j = 0;
     uint32_t wl[4] = {0u, 0u, 0u, 0u};
-    if (P.n_area > 0) {
+    if (nl > 1) {
       uint32_t ctr3[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x80000000u | (uint32_t)k};
       philox(ctr3, key, wl);
       j = (int)(((uint64_t)(wl[0] >> 8) * (uint64_t)nl) >> 24);
@@ -1174,6 +1278,26 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       want_certain = cl > 1e-6;
       skip_certain = cl < -1e-6;
       cval = nl * (P.E / kPi * cl);
+    } else if (env_light && j == nl - 1) {
+      const int64_t nt = (int64_t)S.env_w * S.env_h;
+      int64_t lo = 0, hi = nt - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if ((uint64_t)wl[1] < S.env_T[mid]) hi = mid;
+        else lo = mid + 1;
+      }
+      const int tx = (int)(lo % S.env_w), ty = (int)(lo / S.env_w);
+      const double phi = -kPi + 2.0 * kPi * (tx + unit(wl[2])) / S.env_w;
+      const double z0 = std::cos(kPi * ty / S.env_h), z1 = std::cos(kPi * (ty + 1) / S.env_h);
+      const double z = z0 - unit(wl[3]) * (z0 - z1);
+      const double sr_ = std::sqrt(std::max(0.0, 1.0 - z * z));
+      const V3 de{sr_ * std::cos(phi), sr_ * std::sin(phi), z};
+      const double cp = dot(n, de);
+      want_certain = cp > 1e-6;
+      skip_certain = cp < -1e-6;
+      const double pdf = env_pdf(S, lo);
+      cval = nl * (S.env[lo] * cp * mis_power(pdf / nl, cp / kPi) / (kPi * pdf));
+      sr = Ray{pg, de, 0.0, kInf};
     } else {
       const double* Lq = P.area + 10 * (j - 1);
       const V3 c0{Lq[0], Lq[1], Lq[2]}, e1{Lq[3], Lq[4], Lq[5]}, e2{Lq[6], Lq[7], Lq[8]};
@@ -1211,6 +1335,7 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       err = std::min(err, norm(nr.d - cosine_sample(n, unit(w2[2]), unit(w2[3]), true)));
     }
     if (err > 1e-5) return fail(10, k + 1);
+    pdf_bsdf = std::sqrt(1.0 - unit(w2[2])) / kPi;
     beta *= a;
     ex = here;
   }
@@ -1373,7 +1498,11 @@ int orc_scene_set_environment(void* s, const double* texels, int32_t w, int32_t 
   S->env_w = w > 0 ? w : 0;
   S->env_h = w > 0 ? h : 0;
   S->env.clear();
-  if (w > 0) S->env.assign(texels, texels + (size_t)w * (size_t)h);
+  S->env_T.clear();
+  if (w > 0) {
+    S->env.assign(texels, texels + (size_t)w * (size_t)h);
+    env_table(*S);
+  }
   return 0;
 }
 

@@ -106,6 +106,8 @@ class RenderSettings:
     # quad area lights: (corner xyz, edge-1 xyz, edge-2 xyz, emitted radiance)
     # each, emitting from the side that edge 1 x edge 2 faces
     area_lights: Tuple[Tuple[float, ...], ...] = ()
+    # next-event estimation toward the environment map (when the scene has one)
+    env_nee: bool = False
 
 
 # ----------------------------------------------------------------------------
