@@ -193,18 +193,20 @@ int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t re
 /*
  * Environment map (Section 4.1: the scene has a textured environment light):
  * the radiance a path sees when its ray leaves the scene, in place of the
- * constant sky L_sky.  An equirectangular map of w x h values: direction d
+ * constant sky L_sky, and, with rtq_render_opts.env_nee, a light sampled by
+ * next-event estimation.  An equirectangular map of w x h values: direction d
  * (normalised) has u = (atan2(d_y, d_x) + pi) / (2 pi) along a row and
  * v = acos(d_z) / pi down the rows (row 0 around +z), read at the nearest
- * texel.  It is seen by camera and bounce rays only (no next-event estimate
- * toward it).
+ * texel.  The call also builds the map's sampling table (texel k drawn with
+ * probability (T_k - T_{k-1}) / 2^32, T_k = floor(2^32 C_k / C_total), C the
+ * running sum in texel order of radiance x solid angle).
  *
  * texels_dev: device memory, h rows of w floats, copied into memory the scene
  * owns (freed by rtq_scene_destroy); w = 0 (texels_dev may be NULL) removes the
- * map.  Waits for all work on the device, then enqueues the copy on `stream`;
- * renders on other streams are ordered by the caller.  Errors:
- * RTQ_E_INVALID_ARG for w or h outside [1, RTQ_MAX_ENV_SIDE] (w = 0 aside) or
- * NULL texels; RTQ_E_HIP when the allocation or copy fails.
+ * map.  Waits for all work on the device, then copies the map synchronously.
+ * Errors: RTQ_E_INVALID_ARG for w or h outside [1, RTQ_MAX_ENV_SIDE] (w = 0
+ * aside), NULL texels, or a negative or non-finite texel; RTQ_E_HIP when the
+ * allocation or copy fails.
  */
 #define RTQ_MAX_ENV_SIDE 16384
 int rtq_scene_set_environment(rtq_scene* scene, const float* texels_dev, int32_t w, int32_t h, hipStream_t stream);
@@ -381,6 +383,16 @@ typedef struct {
                                 area light is sampled uniformly over its area and its
                                 shadow ray ends at the sampled point.  Copied to the
                                 device during the call. */
+  int32_t env_nee;           /* nonzero, with an environment map set: the map becomes one
+                                more light of the next-event choice (Section 4.1: the
+                                scene's textured environment light).  A texel is drawn
+                                with probability proportional to radiance x solid angle
+                                (a 32-bit table built by rtq_scene_set_environment), a
+                                direction uniformly in solid angle within it; that
+                                estimate and the radiance an escaping bounce ray reads
+                                are weighted against each other by the power heuristic.
+                                Unbiased either way; lower variance for small bright
+                                regions of the map. */
 } rtq_render_opts;
 
 #define RTQ_MAX_AREA_LIGHTS 64

@@ -86,7 +86,7 @@ class _RenderOpts(ctypes.Structure):
                 ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
                 ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("graph", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("n_area_lights", ctypes.c_int32), ("area_lights", ctypes.c_void_p)]
+                ("n_area_lights", ctypes.c_int32), ("area_lights", ctypes.c_void_p), ("env_nee", ctypes.c_int32)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -387,6 +387,7 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     o.n_area_lights = al.shape[0]
     o._area_keep = al  # the library reads it during the call
     o.area_lights = al.ctypes.data if al.shape[0] else None
+    o.env_nee = 1 if getattr(settings, "env_nee", False) else 0
     return o
 
 

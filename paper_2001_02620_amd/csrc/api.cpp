@@ -74,6 +74,7 @@ SceneView scene_view(const rtq_scene* s, int fmt) {
   v.env = s->env;
   v.env_w = s->env_w;
   v.env_h = s->env_h;
+  v.env_T = s->env_T;
   v.pad_rel = s->pad_rel;
   v.n_rec = (uint32_t)s->n_rec;
   return v;
@@ -516,6 +517,7 @@ void rtq_scene_destroy(rtq_scene* s) {
   s->bufs.release();
   if (s->tex) (void)hipFree(s->tex);
   if (s->env) (void)hipFree(s->env);
+  if (s->env_T) (void)hipFree(s->env_T);
   delete s;
 }
 
@@ -586,20 +588,57 @@ int rtq_scene_set_environment(rtq_scene* s, const float* texels_dev, int32_t w, 
   // renders already queued may still read the old map
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
-  const size_t bytes = w > 0 ? (size_t)w * (size_t)h * sizeof(float) : 0;
+  const size_t n = w > 0 ? (size_t)w * (size_t)h : 0;
+  const size_t bytes = n * sizeof(float);
   if (s->env) (void)hipFree(s->env);
+  if (s->env_T) (void)hipFree(s->env_T);
   s->env = nullptr;
+  s->env_T = nullptr;
   s->env_w = s->env_h = 0;
   s->env_bytes = 0;
   if (w == 0) return RTQ_OK;
+  // the sampling table of next-event estimation toward the map: texel
+  // k = ty w + tx has weight L_k Omega_ty, Omega_ty = (2 pi / w)
+  // (cos(pi ty / h) - cos(pi (ty + 1) / h)) its solid angle; T_k =
+  // floor(2^32 C_k / C_total) with C the running FP64 sum in texel order, the
+  // last entry 2^32; texel k is drawn with probability (T_k - T_{k-1}) / 2^32
+  std::vector<float> host(n);
+  e = hipMemcpy(host.data(), texels_dev, bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(e, "environment read-back");
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(host[k]) || host[k] < 0.0f)
+      return set_error(RTQ_E_INVALID_ARG, "environment texel %zu is negative or not finite", k);
+  std::vector<double> omega(h);
+  for (int32_t ty = 0; ty < h; ++ty)
+    omega[ty] = (2.0 * 3.14159265358979323846 / w) *
+                (std::cos(3.14159265358979323846 * ty / h) - std::cos(3.14159265358979323846 * (ty + 1) / h));
+  double total = 0.0;
+  for (size_t k = 0; k < n; ++k) total += (double)host[k] * omega[k / w];
+  std::vector<unsigned long long> T(n);
+  double cum = 0.0;
+  for (size_t k = 0; k < n; ++k) {
+    cum += (double)host[k] * omega[k / w];
+    T[k] = total > 0.0 ? (unsigned long long)std::floor(std::ldexp(cum / total, 32))
+                       : (unsigned long long)((double)(k + 1) * 4294967296.0 / (double)n);
+  }
+  T[n - 1] = 1ull << 32;
   e = hipMalloc(reinterpret_cast<void**>(&s->env), bytes);
   if (e != hipSuccess) {
     s->env = nullptr;
     return hip_error(e, "environment allocation");
   }
-  s->env_bytes = bytes;
-  e = hipMemcpyAsync(s->env, texels_dev, bytes, hipMemcpyDeviceToDevice, stream);
-  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync");
+  e = hipMalloc(reinterpret_cast<void**>(&s->env_T), n * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    (void)hipFree(s->env);
+    s->env = nullptr;
+    s->env_T = nullptr;
+    return hip_error(e, "environment table allocation");
+  }
+  s->env_bytes = bytes + n * sizeof(unsigned long long);
+  e = hipMemcpy(s->env, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->env_T, T.data(), n * sizeof(unsigned long long), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_error(e, "environment upload");
+  (void)stream;
   s->env_w = w;
   s->env_h = h;
   return RTQ_OK;

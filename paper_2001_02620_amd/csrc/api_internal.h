@@ -69,6 +69,7 @@ struct rtq_scene {
   float* env = nullptr;  // environment map (own allocation, rtq_scene_set_environment)
   int32_t env_w = 0, env_h = 0;
   size_t env_bytes = 0;
+  unsigned long long* env_T = nullptr;  // its sampling table (own allocation)
   unsigned long long* counters = nullptr;  // ring of persistent-kernel work counters
   mutable std::atomic<uint32_t> counter_next{0};
   rtq::DeviceBuffers bufs;

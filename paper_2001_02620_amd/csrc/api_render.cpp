@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -156,6 +157,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
       RALLOC(q.beta, P * 4);
       RALLOC(q.ex_rec, P * 4);
       RALLOC(q.ex_qh, P * 4);
+      RALLOC(q.pdf, P * 4);
     }
     ShadowQueue& sq = r->pb.sq;
     RALLOC(sq.ox, P * 4);
@@ -328,6 +330,7 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   rp.slots = sc->slots;
   rp.alights = sc->alights;
   rp.n_alights = opts->n_area_lights;
+  rp.env_nee = (opts->env_nee && s->env_w > 0) ? 1 : 0;
   out->n_pixels = n_pixels;
   return RTQ_OK;
 }
@@ -356,6 +359,8 @@ int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prep
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
                 (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights,
                 (const void*)sv.env, (int)sv.env_w, (int)sv.env_h);
+  std::snprintf(key + std::strlen(key), sizeof(key) - std::strlen(key), "|%d %p", (int)rp.env_nee,
+                (const void*)sv.env_T);
   // the accumulation grid and its bound bake in the packed image size, and the
   // camera layout decides which image pixels a replay writes
   const std::string k = std::string(key) + "|" + std::to_string((long long)p.n_pixels) + "|" + p.layout;

@@ -132,7 +132,7 @@ __device__ __forceinline__ bool load_queue_ray(Lane& L, const SceneView& sc, con
                                                const ExtQueue& eq, const ShadowQueue& sq, int64_t i) {
   bool ok;
   if (ANY) {
-    if (rp.n_alights > 0)
+    if (nee_sampled(rp))
       ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], sq.dx[i], sq.dy[i], sq.dz[i], 0.0f, sq.tmax[i]);
     else
       ok = lane_init(L, sc, sq.ox[i], sq.oy[i], sq.oz[i], rp.lx, rp.ly, rp.lz, 0.0f, kInfF);
@@ -152,7 +152,7 @@ __device__ __forceinline__ bool load_queue_ray(Lane& L, const SceneView& sc, con
 constexpr int kFeatTex = 1;
 constexpr int kFeatArea = 2;
 static inline int scene_features(const SceneView& sc, const RenderParams& rp) {
-  return (sc.tex_res > 0 ? kFeatTex : 0) | (rp.n_alights > 0 ? kFeatArea : 0);
+  return (sc.tex_res > 0 ? kFeatTex : 0) | ((rp.n_alights > 0 || rp.env_nee) ? kFeatArea : 0);
 }
 
 template <bool ANY>
@@ -181,7 +181,10 @@ template <int FMT, bool ANY, bool COUNT, int FEAT>
 __global__ void k_trace_queue(SceneView sc, RenderParams rp, ExtQueue eq, ShadowQueue sq, const uint32_t* count,
                               QueueHits qh, uint8_t* occ, int depth, unsigned long long* visits) {
   constexpr bool TEX = (FEAT & kFeatTex) != 0;
-  if (!(FEAT & kFeatArea)) rp.n_alights = 0;
+  if (!(FEAT & kFeatArea)) {
+    rp.n_alights = 0;
+    rp.env_nee = 0;
+  }
   extern __shared__ uint2 lds[];
   const Stack S = make_stack(lds, depth);
   uint2 spill[kStackTotal];
@@ -209,7 +212,10 @@ __global__ void k_trace_queue_mixed(SceneView sc, RenderParams rp, ExtQueue eq, 
                                     ShadowQueue sq, const uint32_t* count_sh, QueueHits qh, uint8_t* occ, int depth,
                                     int refill, unsigned long long* counter, unsigned long long* visits) {
   constexpr bool TEX = (FEAT & kFeatTex) != 0;
-  if (!(FEAT & kFeatArea)) rp.n_alights = 0;
+  if (!(FEAT & kFeatArea)) {
+    rp.n_alights = 0;
+    rp.env_nee = 0;
+  }
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth);
@@ -274,7 +280,7 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < (int64_t)*count_in;
   bool want_shadow = false, want_next = false;
-  float contrib = 0.0f, beta_next = 0.0f, ndx = 0.0f, ndy = 0.0f, ndz = 0.0f;
+  float contrib = 0.0f, beta_next = 0.0f, ndx = 0.0f, ndy = 0.0f, ndz = 0.0f, pdf_next = 0.0f;
   Shade s{};
   NeeSample ns{false, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   uint32_t pid = 0u, rec = kEmpty, qhv = kEmpty;
@@ -283,7 +289,8 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     const float beta = in.beta[i];
     rec = qh.rec[i];
     if (rec == kEmpty) {
-      rp.slots[pid] += beta * escape_radiance(sc, rp, in.dx[i], in.dy[i], in.dz[i]);  // escaped: sky
+      const float pdf = (b > 0 && rp.env_nee) ? in.pdf[i] : 0.0f;
+      rp.slots[pid] += beta * escape_radiance(sc, rp, in.dx[i], in.dy[i], in.dz[i], pdf);  // escaped
     } else {
       qhv = qh.qh[i];
       const Ray3 r{in.ox[i], in.oy[i], in.oz[i], in.dx[i], in.dy[i], in.dz[i]};
@@ -292,14 +299,14 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
                     tex ? qh.v[i] : 0.0f);
       const bool next = b < rp.depth - 1;
       PathId id{0, 0u, 0u, 0u, 0u};
-      if (next || rp.n_alights > 0) id = path_coords(rp, (int64_t)pid);
-      ns = nee_sample(rp, s, id.pixel, id.sample, id.view, b);
+      if (next || nee_sampled(rp)) id = path_coords(rp, (int64_t)pid);
+      ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, b);
       if (ns.want) {
         want_shadow = true;
         contrib = nee_contrib(beta, s, ns, rp);
       }
       if (next) {
-        bounce_dir(rp, id.pixel, id.sample, id.view, b, s, &ndx, &ndy, &ndz);
+        pdf_next = bounce_dir(rp, id.pixel, id.sample, id.view, b, s, &ndx, &ndy, &ndz);
         beta_next = beta * s.a;
         want_next = true;
       }
@@ -315,7 +322,7 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     sq.contrib[js] = contrib;
     sq.ex_rec[js] = rec;
     sq.ex_qh[js] = qhv;
-    if (rp.n_alights > 0) {
+    if (nee_sampled(rp)) {
       sq.dx[js] = ns.dx;
       sq.dy[js] = ns.dy;
       sq.dz[js] = ns.dz;
@@ -333,6 +340,7 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     out.beta[jn] = beta_next;
     out.ex_rec[jn] = rec;
     out.ex_qh[jn] = qhv;
+    if (rp.env_nee) out.pdf[jn] = pdf_next;
   }
   if (view_done) {  // paths that end here: escaped, or past the last bounce without a shadow ray
     const bool ends = live && !want_next && !want_shadow;
@@ -429,6 +437,7 @@ struct PathLane {
   uint32_t pid;
   int b;
   float beta, radiance, pending, beta_next, ndx, ndy, ndz;
+  float pdf, pdf_next;  // cosine density of the current / next extension ray (0 for camera rays)
   bool shadow, have_next;
 };
 
@@ -439,7 +448,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                                     unsigned long long* counter, unsigned long long* counters,
                                     unsigned long long* view_done, unsigned long long* visits) {
   constexpr bool TEX = (FEAT & kFeatTex) != 0;
-  if (!(FEAT & kFeatArea)) rp.n_alights = 0;
+  if (!(FEAT & kFeatArea)) {
+    rp.n_alights = 0;
+    rp.env_nee = 0;
+  }
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth_lds);
@@ -464,6 +476,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
           const Ray3 r = path_camera_ray(rp, pid, &id);
           P.b = 0;
           P.beta = 1.0f;
+          P.pdf = 0.0f;
           P.radiance = 0.0f;
           P.shadow = false;
           P.have_next = false;
@@ -500,7 +513,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
             bool path_done = false;
             if (!P.shadow) {
               if (L.b_rec == kEmpty) {
-                P.radiance += P.beta * escape_radiance(sc, rp, L.wdx, L.wdy, L.wdz);
+                P.radiance += P.beta * escape_radiance(sc, rp, L.wdx, L.wdy, L.wdz, P.pdf);
                 path_done = true;
               } else {
                 const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
@@ -509,14 +522,14 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                                           TEX ? L.b_u : 0.0f, TEX ? L.b_v : 0.0f);
                 P.have_next = P.b < rp.depth - 1;
                 PathId id{0, 0u, 0u, 0u, 0u};
-                if (P.have_next || rp.n_alights > 0) id = path_coords(rp, (int64_t)P.pid);
+                if (P.have_next || nee_sampled(rp)) id = path_coords(rp, (int64_t)P.pid);
                 if (P.have_next) {
-                  bounce_dir(rp, id.pixel, id.sample, id.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
+                  P.pdf_next = bounce_dir(rp, id.pixel, id.sample, id.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
                   P.beta_next = P.beta * s.a;
                 }
                 L.ex_rec = hrec;
                 L.ex_qh = hqh;
-                const NeeSample ns = nee_sample(rp, s, id.pixel, id.sample, id.view, P.b);
+                const NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, P.b);
                 if (ns.want) {
                   P.pending = nee_contrib(P.beta, s, ns, rp);
                   P.shadow = true;
@@ -525,6 +538,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                   ++n_sh;
                 } else if (P.have_next) {
                   P.beta = P.beta_next;
+                  P.pdf = P.pdf_next;
                   ++P.b;
                   lane_init(L, sc, s.px, s.py, s.pz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
                   ++n_ext;
@@ -538,6 +552,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
               P.shadow = false;
               if (P.have_next) {
                 P.beta = P.beta_next;
+                P.pdf = P.pdf_next;
                 ++P.b;
                 lane_init(L, sc, L.wox, L.woy, L.woz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
                 ++n_ext;
@@ -596,7 +611,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
   VisitCounters vc{0, 0, 0, 0};
   PathId id;
   Ray3 r = path_camera_ray(rp, pid, &id);
-  float beta = 1.0f, radiance = 0.0f;
+  float beta = 1.0f, radiance = 0.0f, pdf = 0.0f;
   uint32_t ex_rec = kEmpty, ex_qh = kEmpty;
   int n = 0, escaped = 0;
   for (int b = 0; b < rp.depth; ++b) {
@@ -607,7 +622,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
       while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
       }
     if (L.b_rec == kEmpty) {
-      radiance += beta * escape_radiance(sc, rp, r.dx, r.dy, r.dz);
+      radiance += beta * escape_radiance(sc, rp, r.dx, r.dy, r.dz, pdf);
       escaped = 1;
       // the escaping ray takes the next record (n < depth here)
       rec_i[6 * n + 0] = -1;
@@ -631,7 +646,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     const uint32_t hqh = L.b_qh;
     const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     int shadow = -1;
-    const NeeSample ns = nee_sample(rp, sh, id.pixel, id.sample, id.view, b);
+    const NeeSample ns = nee_sample(sc, rp, sh, id.pixel, id.sample, id.view, b);
     if (ns.want) {
       const float pending = nee_contrib(beta, sh, ns, rp);
       Lane Ls;
@@ -664,7 +679,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     ++n;
     if (b == rp.depth - 1) break;
     float dx, dy, dz;
-    bounce_dir(rp, id.pixel, id.sample, id.view, b, sh, &dx, &dy, &dz);
+    pdf = bounce_dir(rp, id.pixel, id.sample, id.view, b, sh, &dx, &dy, &dz);
     beta = beta * sh.a;
     r = Ray3{sh.px, sh.py, sh.pz, dx, dy, dz};
     ex_rec = L.b_rec;
@@ -703,7 +718,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
   float betak[kMaxDepth], ck[kMaxDepth], ak[kMaxDepth];
   int K = 0;
   bool escaped = false;
-  float beta = 1.0f;
+  float beta = 1.0f, pdf = 0.0f;
   Lane L;
   VisitCounters vc{0, 0, 0, 0};
   L.ex_rec = kEmpty;
@@ -719,7 +734,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     const uint32_t hrec = L.b_rec, hqh = L.b_qh;
     const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     float c = 0.0f;
-    const NeeSample ns = nee_sample(rp, s, id.pixel, id.sample, id.view, b);
+    const NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, b);
     if (ns.want) {
       L.ex_rec = hrec;
       L.ex_qh = hqh;
@@ -737,13 +752,13 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
     ++K;
     if (b == rp.depth - 1) break;
     float dx, dy, dz;
-    bounce_dir(rp, id.pixel, id.sample, id.view, b, s, &dx, &dy, &dz);
+    pdf = bounce_dir(rp, id.pixel, id.sample, id.view, b, s, &dx, &dy, &dz);
     r = Ray3{s.px, s.py, s.pz, dx, dy, dz};
     beta = beta * s.a;
     L.ex_rec = hrec;
     L.ex_qh = hqh;
   }
-  float V = escaped ? escape_radiance(sc, rp, r.dx, r.dy, r.dz) : 0.0f;
+  float V = escaped ? escape_radiance(sc, rp, r.dx, r.dy, r.dz, pdf) : 0.0f;
   for (int k = K - 1; k >= 0; --k) {
     const float cv = ck[k] + V;
     unsafeAtomicAdd(&grad_albedo[face[k]], g * (betak[k] * cv));

@@ -42,7 +42,18 @@ struct RenderParams {
   float* slots;         // per-path radiance
   const float* alights; // quad area lights, 10 floats each: corner, edge 1, edge 2, radiance
   int32_t n_alights;
+  int32_t env_nee;      // next-event estimation toward the environment map (scene has one)
 };
+
+// Whether next-event estimates sample light directions (area lights or the
+// environment), so shadow rays carry their own direction and tmax.
+__device__ __forceinline__ bool nee_sampled(const RenderParams& rp) { return rp.n_alights > 0 || rp.env_nee != 0; }
+
+// Lights a next-event estimate chooses among: the directional one, the area
+// lights and, when sampled, the environment (the last).
+__device__ __forceinline__ uint32_t n_lights(const RenderParams& rp) {
+  return 1u + (uint32_t)rp.n_alights + (rp.env_nee ? 1u : 0u);
+}
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011): ten rounds of two 32x32->64
 // multiplications with the round keys bumped by the Weyl constants in between.
@@ -179,21 +190,42 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   return s;
 }
 
+constexpr float kPiF = 3.14159265358979323846f;
+
+// Density (per solid angle) with which the environment's next-event estimate
+// draws directions in texel (tx, ty): p_k / Omega_ty, p_k = (T_k - T_{k-1}) / 2^32,
+// Omega_ty = (2 pi / W) (cos(pi ty / H) - cos(pi (ty + 1) / H)).
+__device__ __forceinline__ float env_pdf(const SceneView& sc, int tx, int ty) {
+  const size_t k = (size_t)ty * sc.env_w + tx;
+  const float p = (float)(sc.env_T[k] - (k > 0 ? sc.env_T[k - 1] : 0ull)) * 2.3283064365386963e-10f;
+  const float om = (2.0f * kPiF / (float)sc.env_w) * (cospif((float)ty / (float)sc.env_h) -
+                                                      cospif((float)(ty + 1) / (float)sc.env_h));
+  return p / om;
+}
+
+// Power-heuristic weight of strategy a against b (Veach 1997).
+__device__ __forceinline__ float mis_power(float a, float b) { return a * a / (a * a + b * b); }
+
 // Radiance seen by a ray leaving the scene along d: the constant sky, or the
 // nearest texel of the environment map (Section 4.1 names the scene's textured
 // environment light), an equirectangular map with u = (atan2(d_y, d_x) + pi) /
 // (2 pi) along a row and v = acos(d_z) / pi down the rows (row 0 around +z).
+// pdf_bsdf > 0 marks a ray drawn by a cosine bounce with that density: with
+// next-event estimation toward the map, its radiance is weighted against that
+// strategy by the power heuristic (camera rays pass 0 and keep weight 1).
 __device__ __forceinline__ float escape_radiance(const SceneView& sc, const RenderParams& rp, float dx, float dy,
-                                                 float dz) {
+                                                 float dz, float pdf_bsdf) {
   if (sc.env_w == 0) return rp.L_sky;
   const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
   const float z = fminf(fmaxf(dz * inv, -1.0f), 1.0f);
-  const float u = (atan2f(dy, dx) + 3.14159265358979323846f) / 6.28318530717958647692f;
-  const float v = acosf(z) / 3.14159265358979323846f;
+  const float u = (atan2f(dy, dx) + kPiF) / (2.0f * kPiF);
+  const float v = acosf(z) / kPiF;
   // clamped in float first, so the index stays in range for any direction
   const int tx = (int)fminf(fmaxf(u * (float)sc.env_w, 0.0f), (float)(sc.env_w - 1));
   const int ty = (int)fminf(fmaxf(v * (float)sc.env_h, 0.0f), (float)(sc.env_h - 1));
-  return sc.env[(size_t)ty * sc.env_w + tx];
+  const float L = sc.env[(size_t)ty * sc.env_w + tx];
+  if (!rp.env_nee || !(pdf_bsdf > 0.0f)) return L;
+  return L * mis_power(pdf_bsdf, env_pdf(sc, tx, ty) / (float)n_lights(rp));
 }
 
 // Next-event contribution of a visible light: beta * (a / pi) * E * cos_L.
@@ -220,15 +252,43 @@ struct NeeSample {
 // parallelogram x = c + s e1 + t e2, (s, t) uniform from words 1 and 2, emitting
 // radiance Le from the side e1 x e2 faces: c = nl Le A cos_p cos_l / (pi d^2)
 // for the sampled point at distance d, A = |e1 x e2|.
-__device__ __forceinline__ NeeSample nee_sample(const RenderParams& rp, const Shade& s, uint32_t pixel,
-                                                uint32_t sample, uint32_t view, int b) {
+__device__ __forceinline__ NeeSample nee_sample(const SceneView& sc, const RenderParams& rp, const Shade& s,
+                                                uint32_t pixel, uint32_t sample, uint32_t view, int b) {
   NeeSample r{s.cosl > 0.0f, rp.lx, rp.ly, rp.lz, kInfF, nee_factor(s.cosl, rp)};
-  if (rp.n_alights == 0) return r;
+  if (!nee_sampled(rp)) return r;
   const uint4 w = philox4x32_10(make_uint4(pixel, sample, view, 0x80000000u | (uint32_t)b), rp.keys[0], rp.keys[1]);
-  const uint32_t nl = (uint32_t)rp.n_alights + 1u;
+  const uint32_t nl = n_lights(rp);
   const uint32_t j = (uint32_t)(((uint64_t)(w.x >> 8) * nl) >> 24);
   if (j == 0u) {
     r.c = (float)nl * r.c;
+    return r;
+  }
+  if (rp.env_nee && j == nl - 1u) {
+    // the environment: texel k = the first with w.y < T_k (binary search of the
+    // table, an integer decision), a direction uniform in solid angle within
+    // it from words 2, 3; c = nl L_k cos_p w / (pi pdf), w the power-heuristic
+    // weight against the cosine bounce (density cos_p / pi)
+    const int nt = sc.env_w * sc.env_h;
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((unsigned long long)w.y < sc.env_T[mid]) hi = mid;
+      else lo = mid + 1;
+    }
+    const int ty = lo / sc.env_w, tx = lo - ty * sc.env_w;
+    float sp, cp_;
+    sincospif(2.0f * ((float)tx + u01(w.z)) / (float)sc.env_w - 1.0f, &sp, &cp_);
+    const float z0 = cospif((float)ty / (float)sc.env_h), z1 = cospif((float)(ty + 1) / (float)sc.env_h);
+    const float z = z0 - u01(w.w) * (z0 - z1);
+    const float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+    r.dx = rr * cp_;
+    r.dy = rr * sp;
+    r.dz = z;
+    r.tmax = kInfF;
+    const float cp = s.nx * r.dx + s.ny * r.dy + s.nz * r.dz;
+    r.want = cp > 0.0f;
+    const float pdf = env_pdf(sc, tx, ty);
+    r.c = (float)nl * (sc.env[lo] * cp * mis_power(pdf / (float)nl, cp / kPiF) / (kPiF * pdf));
     return r;
   }
   const float* q = rp.alights + 10 * (j - 1u);
@@ -255,7 +315,7 @@ __device__ __forceinline__ NeeSample nee_sample(const RenderParams& rp, const Sh
 // has no area lights.
 __device__ __forceinline__ float nee_contrib(float beta, const Shade& s, const NeeSample& ns,
                                              const RenderParams& rp) {
-  return rp.n_alights == 0 ? nee_term(beta, s.a, s.cosl, rp) : beta * (s.a * ns.c);
+  return !nee_sampled(rp) ? nee_term(beta, s.a, s.cosl, rp) : beta * (s.a * ns.c);
 }
 
 // Cosine-distributed direction about n from (u1, u2): local
@@ -284,11 +344,13 @@ __device__ __forceinline__ Ray3 path_camera_ray(const RenderParams& rp, int64_t 
   return camera_ray(rp.cams[id->cam], id->pixel, u01(w.x), u01(w.y));
 }
 
-// Bounce direction after hit b of a path (words 2, 3 of counter (pixel, sample, view, b)).
-__device__ __forceinline__ void bounce_dir(const RenderParams& rp, uint32_t pixel, uint32_t sample, uint32_t view,
-                                           int b, const Shade& s, float* dx, float* dy, float* dz) {
+// Bounce direction after hit b of a path (words 2, 3 of counter (pixel, sample,
+// view, b)); returns its density cos / pi.
+__device__ __forceinline__ float bounce_dir(const RenderParams& rp, uint32_t pixel, uint32_t sample, uint32_t view,
+                                            int b, const Shade& s, float* dx, float* dy, float* dz) {
   const uint4 w = philox4x32_10(make_uint4(pixel, sample, view, (uint32_t)b), rp.keys[0], rp.keys[1]);
   cosine_dir(s.nx, s.ny, s.nz, u01(w.z), u01(w.w), dx, dy, dz);
+  return sqrtf(1.0f - u01(w.z)) / kPiF;
 }
 
 }  // namespace rtq

@@ -17,6 +17,8 @@ struct ExtQueue {
   uint32_t* pid;
   float* beta;
   uint32_t *ex_rec, *ex_qh;
+  float* pdf;  // density of the cosine bounce that drew the ray (written when the
+               // environment is sampled by next-event estimation)
 };
 
 // Shadow-ray queue: direction is the light direction.

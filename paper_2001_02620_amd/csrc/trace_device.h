@@ -41,6 +41,8 @@ struct SceneView {
   int32_t tex_res;            // texels per side; 0 shades with `albedo`
   const float* env;           // environment map, env_w x env_h radiance values, or null
   int32_t env_w, env_h;       // 0: escaping rays see the constant sky
+  const unsigned long long* env_T;  // its sampling table: texel k drawn with probability
+                                    // (env_T[k] - env_T[k - 1]) / 2^32
   float pad_rel;              // top-level origin pad per unit of |o|_inf
   float p_world;              // bound on |world coordinate| of the top-level boxes
   uint32_t tlas_root;         // index of the top-level root in `nodes`

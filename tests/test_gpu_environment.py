@@ -1,8 +1,9 @@
-"""Environment map seen by escaping rays on the HIP path: every scheduler and
-node format gives the same image, equal to the oracle's on the pixels it does
-not flag; texel orientation as the oracle's hand-worked cases; a constant map
-is the constant sky bit for bit; the adjoint matches the oracle's gradient
-with the map on."""
+"""Environment map seen by escaping rays on the HIP path, and sampled as a light
+by next-event estimation: every scheduler and node format gives the same
+image, equal to the oracle's on the pixels it does not flag (flagged ones
+replayed path by path); texel orientation as the oracle's hand-worked cases; a
+constant map is the constant sky bit for bit; the adjoint matches the oracle's
+gradient with the map on, sampled or not."""
 import numpy as np
 import pytest
 
@@ -21,12 +22,19 @@ def _env(w, h, seed):
     return np.random.default_rng(seed).uniform(0.05, 1.0, size=(h, w)).astype(np.float32)
 
 
-def test_environment_schedulers_bit_identical_and_match_oracle():
+@pytest.mark.parametrize("nee", [False, True])
+def test_environment_schedulers_bit_identical_and_match_oracle(nee):
+    """With and without next-event estimation toward the map (texels drawn from
+    the 32-bit table, weighted against escaping bounce rays): every scheduler
+    and node format gives the same image, equal to the oracle's where it flags
+    nothing; flagged pixels are replayed and checked path by path."""
     import torch
-    log("case: environment map, multiview")
+    log(f"case: environment map, multiview, next-event estimation {nee}")
     scene, cams = _multi_view_scene()
-    st = sg.RenderSettings(spp=3, depth=5, seed=77, frame=2)
+    st = sg.RenderSettings(spp=3, depth=5, seed=77, frame=2, env_nee=nee)
     env = _env(64, 32, 11)
+    if nee:
+        env[5:8, 20:26] = 30.0  # a small bright region the sampling finds
     S = rtq.Scene(scene)
     S.set_environment(torch.from_numpy(env).cuda())
     imgs = [_render(S, cams, st, **kw) for kw in SCHEDS]
@@ -74,12 +82,13 @@ def test_environment_orientation_and_constant_map_gpu():
         S.set_environment(torch.zeros((2, 16385), device="cuda"))
 
 
-def test_environment_adjoint_vs_oracle():
+@pytest.mark.parametrize("nee", [False, True])
+def test_environment_adjoint_vs_oracle(nee):
     import torch
-    log("case: environment adjoint")
+    log(f"case: environment adjoint, next-event estimation {nee}")
     scene = sg.tiny_scene(31, n_inst=4, n_protos=2, nq=4, spread=1.0)
     cams = [sg.Camera((0.0, -8.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 35.0, 48, 48)]
-    st = sg.RenderSettings(spp=4, depth=3, seed=31)
+    st = sg.RenderSettings(spp=4, depth=3, seed=31, env_nee=nee)
     env = _env(32, 16, 12)
     rng = np.random.default_rng(8)
     alb = scene.albedo.astype(np.float32)
