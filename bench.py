@@ -26,7 +26,8 @@ printed.  Beside it (same JSON line):
                        the headline frame with per-face 4x4 textures, four quad
                        area lights, a 2048x1024 environment map;
   config2              the smaller 1M-instance configuration: frames and
-                       incoherent rays, both paths;
+                       incoherent rays, both paths, and node widths 2, 4 and 8
+                       (quantized persistent, equal hits and images);
   roofline             the timed kernel: algorithmic bytes per launch (visit
                        counts of the same rays) over its launch time from HIP
                        events, against 8 TB/s; the bound named by the committed
@@ -52,6 +53,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # algorithmic bytes per ray of a traversal: ray in, hit out, and per visit
 B_NODE = {1: 128, 2: 64}   # 4-wide node: FP32, 8-bit
+B_NODE_Q8_W = {2: 48, 4: 64, 8: 96}  # quantized node by width
 B_INST = 56                # instance entry: FP32 inverse 3x4, BLAS root, prototype
 B_QUAD = 48                # four FP32 vertices
 B_RAY, B_HIT = 32, 20
@@ -118,6 +120,80 @@ def visit_bytes(v, rays, fmt=2):
     return rays * (B_RAY + B_HIT) + v[0] * B_NODE[fmt] + v[1] * B_INST + v[2] * B_NODE[fmt] + v[3] * B_QUAD
 
 
+def compare_widths(rtq, scene, cams, st, cap, log, steps=5, frames=5):
+    """Node widths 2, 4 and 8 on one workload: one build per width, the
+    quantized persistent kernels.  Each width dumps the bounce >= 1 rays of its
+    own frame 0 (the exclusion keys name its own top-level records); rays,
+    hits and frames must equal the 4-wide build's bit for bit.  Returns per
+    width: nodes, depths, incoherent Mrays/s, ms/frame and visits per ray."""
+    import numpy as np
+    import torch
+    q8p = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+    n_pix = sum(c.w * c.h for c in cams)
+    out, ref = {}, None
+    for w in (4, 8, 2):
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        S = rtq.Scene(scene, node_width=w)
+        info = S.info()
+        build_s = time.time() - t0
+        img = torch.empty(n_pix, device="cuda")
+        d = torch.empty(12 * cap, device="cuda")
+        c = torch.zeros(1, dtype=torch.uint64, device="cuda")
+        st.frame = 0
+        rtq.render(S, cams, st, images=img, dump_rays=d, dump_count=c, **q8p)
+        torch.cuda.synchronize()
+        m = int(min(int(c.cpu().item()), cap))
+        pl = d.view(12, cap)[:, :m]
+        r, e = pl[:8].contiguous(), pl[8:10].view(torch.int32).t().contiguous()
+        h = rtq.trace_closest(S, r, exclude=e, soa_in=True, **q8p)
+        v = torch.zeros((m, 4), dtype=torch.int32, device="cuda")
+        rtq.trace_closest(S, r, exclude=e, soa_in=True, visits=v, **q8p)
+        torch.cuda.synchronize()
+        vis = v.to(torch.float64).sum(0).cpu().numpy() / m
+        del v
+        if ref is None:
+            ref = (img.clone(), r.clone(), h)
+        else:
+            assert torch.equal(ref[0].view(torch.int32), img.view(torch.int32)), f"width {w}: frame differs"
+            assert torch.equal(ref[1].view(torch.int32), r.view(torch.int32)), f"width {w}: bounce rays differ"
+            for k in ("t", "u", "v", "inst", "prim"):
+                assert torch.equal(getattr(ref[2], k).view(torch.int32), getattr(h, k).view(torch.int32)), \
+                    f"width {w}: hits differ ({k})"
+        del h
+        for _ in range(2):
+            rtq.trace_closest(S, r, exclude=e, soa_in=True, **q8p)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(steps):
+            rtq.trace_closest(S, r, exclude=e, soa_in=True, **q8p)
+        torch.cuda.synchronize()
+        inc_ms = (time.perf_counter() - w0) / steps * 1e3
+        for i in range(2):
+            st.frame = 1000 + i
+            rtq.render(S, cams, st, images=img, **q8p)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(frames):
+            st.frame = i
+            rtq.render(S, cams, st, images=img, **q8p)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - w0) / frames * 1e3
+        bn = B_NODE_Q8_W[w]
+        out[w] = {"nodes": info["tlas_nodes"] + info["blas_nodes"], "node_bytes": bn,
+                  "depth": [info["tlas_depth"], info["blas_depth_max"]], "build_s": round(build_s, 1),
+                  "incoherent_mrays_s": round(m / inc_ms / 1e3, 2), "incoherent_ms": round(inc_ms, 3),
+                  "ms_per_frame": round(fms, 3), "visits_per_ray": [round(x, 2) for x in vis],
+                  "algorithmic_bytes_per_ray": round(B_RAY + B_HIT + (vis[0] + vis[2]) * bn + vis[1] * B_INST
+                                                     + vis[3] * B_QUAD, 1)}
+        log(f"node width {w}: {out[w]}")
+        del S, r, e, pl, d, img
+    torch.cuda.empty_cache()
+    best = min(out, key=lambda k: out[k]["incoherent_ms"])
+    return {"widths": {str(k): v for k, v in out.items()}, "fastest_incoherent": best,
+            "fastest_frame": min(out, key=lambda k: out[k]["ms_per_frame"])}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +206,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
     ap.add_argument("--profile", choices=("incoherent", "frame"), default=None,
                     help="only the timed incoherent queries, or only timed frames (for rocprofv3)")
+    ap.add_argument("--widths", action="store_true",
+                    help="only compare node widths 2, 4 and 8 on the configuration-3 workload (one build each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -159,6 +237,10 @@ def main():
     scene, cams, st = sg.config3(scale=args.scale)
     log(f"config 3: {scene.n_quads} unique quads, {scene.n_instances} instances, "
         f"{scene.instanced_quads():.3e} instanced quads ({time.time() - t0:.1f} s)")
+    if args.widths:
+        print(json.dumps({"config3_node_width": compare_widths(rtq, scene, cams, st, args.incoherent_rays, log,
+                                                             steps=args.steps, frames=args.steps)}))
+        return
     t0 = time.time()
     S = rtq.Scene(scene)
     info = S.info()
@@ -374,9 +456,10 @@ def main():
             rays2 = float(cnt2[0].item() + cnt2[1].item()) / 10
             out2[name] = dict(incoherent_mrays_s=round(m2 / inc_ms / 1e3, 2), ms_per_frame=round(fms, 3),
                               frame_mrays_s=round(rays2 / fms / 1e3, 2))
+        del S2, r2, e2, pl2, d2, img2
+        out2["node_width"] = compare_widths(rtq, scene2, cams2, st2, cap, log)
         log(f"config 2: {out2}")
         cfg2 = out2
-        del S2
 
     # ---- CPU baseline: the FP64 oracle tracing a bounded random sample of the
     # same incoherent rays (same exclusions), sized by a pilot to about

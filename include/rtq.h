@@ -61,19 +61,29 @@ const char* rtq_version(void);
 /*
  * The scene builder's bottom-level construction on its own, on the host, over
  * arbitrary boxes (Section 5.2: one BVH per object; here binned SAH, collapsed
- * to 4-wide nodes, emitted as FP32 and as 8-bit quantized nodes).  For
- * inspecting the acceleration structure and for host-side checks; no device is
- * touched.
+ * to `width`-wide nodes, emitted as exact FP32 boxes and as 8-bit quantized
+ * nodes).  For inspecting the acceleration structure and for host-side checks;
+ * no device is touched.
  *   boxes: host, n x 6 FP32 (lo x y z, hi x y z); n >= 1.
  *   leaf_max: primitives per leaf, 1..8.  bins: SAH bins per axis, 4..64.
  *   threads: host threads, 0 = all; the result does not depend on it.
+ *   width: children per node, 2, 4 or 8.
  * Node layouts (little-endian, node 0 is the root):
- *   FP32, 128 B: float lo_x[4], hi_x[4], lo_y[4], hi_y[4], lo_z[4], hi_z[4];
- *                uint32 child[4]; uint32 pad[4].
- *   Q8, 64 B:    float origin[3]; uint32 exps (byte a: int8 exponent of axis a);
- *                uint32 lo_x, hi_x, lo_y, hi_y, lo_z, hi_z (byte c: child c);
- *                uint32 child[4]; uint32 pad[2].  A plane decodes to
- *                fmaf(q, 2^e, origin), which contains the FP32 plane.
+ *   wide, 224 B (every width; slots >= width empty):
+ *                float lo[3][8], hi[3][8] (axis-major); uint32 child[8].
+ *   FP32, 128 B (width 4 only, else NULL): float lo_x[4], hi_x[4], lo_y[4],
+ *                hi_y[4], lo_z[4], hi_z[4]; uint32 child[4]; uint32 pad[4].
+ *   Q8, 64 B (width 4): float origin[3]; uint32 exps (byte a: int8 exponent of
+ *                axis a); uint32 lo_x, hi_x, lo_y, hi_y, lo_z, hi_z (byte c:
+ *                child c); uint32 child[4]; uint32 pad[2].
+ *   Q8, 96 B (width 8): origin and exps as above; uint32 lo_x[2], hi_x[2],
+ *                lo_y[2], hi_y[2], lo_z[2], hi_z[2] (byte c of word j: child
+ *                4 j + c); uint32 child[8].
+ *   Q8, 48 B (width 2): origin and exps; uint32 x, y, z (bytes 0, 1: lower
+ *                planes of children 0, 1; bytes 2, 3: upper planes);
+ *                uint32 child[2]; uint32 pad[3].
+ *   A quantized plane decodes to fmaf(q, 2^e, origin), which contains the
+ *   FP32 plane; an empty slot has lower byte 255 and upper byte 0.
  *   child: 0xFFFFFFFF empty; bit 31 set: leaf of primitives
  *          order[first .. first + count) with first = (c >> 3) & 0x0FFFFFFF and
  *          count = (c & 7) + 1; otherwise the index of an internal node.
@@ -83,9 +93,9 @@ const char* rtq_version(void);
  */
 typedef struct rtq_host_bvh rtq_host_bvh;
 int rtq_host_bvh_build(const float* boxes, int64_t n, int32_t leaf_max, int32_t bins, int32_t threads,
-                       rtq_host_bvh** out);
-int rtq_host_bvh_get(const rtq_host_bvh* bvh, const void** nodes_f32, const void** nodes_q8, int64_t* n_nodes,
-                     const uint32_t** order, int32_t* depth);
+                       int32_t width, rtq_host_bvh** out);
+int rtq_host_bvh_get(const rtq_host_bvh* bvh, const void** nodes_wide, const void** nodes_f32,
+                     const void** nodes_q8, int64_t* n_nodes, const uint32_t** order, int32_t* depth);
 void rtq_host_bvh_destroy(rtq_host_bvh* bvh);
 
 /* ------------------------------------------------------------------ scene */
@@ -109,8 +119,9 @@ typedef struct {
 } rtq_instances;
 
 /* Node formats (bit mask for building, single value for tracing). */
-#define RTQ_NODE_FP32 1 /* 4-wide nodes with FP32 child boxes, 128 B */
-#define RTQ_NODE_Q8 2   /* 4-wide nodes with 8-bit child boxes in an FP32 parent frame, 64 B */
+#define RTQ_NODE_FP32 1 /* 4-wide nodes with FP32 child boxes, 128 B (4-wide scenes only) */
+#define RTQ_NODE_Q8 2   /* nodes with 8-bit child boxes in an FP32 parent frame: 48 B (2-wide),
+                           64 B (4-wide), 96 B (8-wide) */
 
 typedef struct {
   int32_t formats;       /* RTQ_NODE_* mask to build; 0 = both */
@@ -121,6 +132,9 @@ typedef struct {
   int32_t open_pct;      /* top-level entries added by opening instances into subtrees of their
                             bottom-level BVH (partial re-braiding), in percent of the instance
                             count; 0 = default (50), negative = none.  Hits do not depend on it. */
+  int32_t node_width;    /* children per node at both levels: 2, 4 or 8; 0 = 4.  Widths other
+                            than 4 build quantized nodes only (formats 0 or RTQ_NODE_Q8).  Hits
+                            do not depend on it. */
 } rtq_build_opts;
 
 /*
@@ -146,7 +160,7 @@ void rtq_scene_destroy(rtq_scene* scene);
 typedef struct {
   int64_t n_instances, n_prototypes, n_unique_quads, n_instanced_quads;
   int64_t tlas_nodes, blas_nodes;
-  int32_t tlas_depth, blas_depth_max; /* 4-wide node levels */
+  int32_t tlas_depth, blas_depth_max; /* node levels */
   int32_t formats;                    /* RTQ_NODE_* built */
   int64_t device_bytes;               /* all device memory held by the scene (textures included) */
   double build_seconds;               /* wall time of rtq_scene_build */
@@ -154,6 +168,7 @@ typedef struct {
   double build_phase_seconds[4];      /* bottom levels (host); instance inverses and boxes (device) and
                                          bottom-level upload; opening instances (host); top level
                                          (host) and its upload */
+  int32_t node_width;                 /* children per node */
 } rtq_scene_info;
 
 int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);

@@ -45,7 +45,8 @@ class _Insts(ctypes.Structure):
 
 class _BuildOpts(ctypes.Structure):
     _fields_ = [("formats", ctypes.c_int32), ("leaf_max", ctypes.c_int32), ("sah_bins", ctypes.c_int32),
-                ("build_threads", ctypes.c_int32), ("device", ctypes.c_int32), ("open_pct", ctypes.c_int32)]
+                ("build_threads", ctypes.c_int32), ("device", ctypes.c_int32), ("open_pct", ctypes.c_int32),
+                ("node_width", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -54,7 +55,7 @@ class _Info(ctypes.Structure):
                 ("tlas_nodes", ctypes.c_int64), ("blas_nodes", ctypes.c_int64), ("tlas_depth", ctypes.c_int32),
                 ("blas_depth_max", ctypes.c_int32), ("formats", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("n_top_entries", ctypes.c_int64),
-                ("build_phase_seconds", ctypes.c_double * 4)]
+                ("build_phase_seconds", ctypes.c_double * 4), ("node_width", ctypes.c_int32)]
 
 
 class _Rays(ctypes.Structure):
@@ -124,8 +125,9 @@ def load_library():
     L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_closest_noalloc.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_brute.argtypes = [P, P, ctypes.c_int64, P, P]
-    L.rtq_host_bvh_build.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P]
-    L.rtq_host_bvh_get.argtypes = [P, P, P, P, P, P]
+    L.rtq_host_bvh_build.argtypes = [P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, P]
+    L.rtq_host_bvh_get.argtypes = [P, P, P, P, P, P, P]
     L.rtq_host_bvh_destroy.argtypes = [P]
     L.rtq_host_bvh_destroy.restype = None
     L.rtq_render.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
@@ -166,7 +168,7 @@ class Scene:
     """Built acceleration structures of a generator scene (``scenegen.Scene`` arrays)."""
 
     def __init__(self, s, formats: int = 0, leaf_max: int = 0, sah_bins: int = 0, build_threads: int = 0,
-                 device: int = -1, open_pct: int = 0):
+                 device: int = -1, open_pct: int = 0, node_width: int = 0):
         L = load_library()
         _torch()
         self.n_quads = int(s.quads.shape[0])
@@ -189,7 +191,7 @@ class Scene:
         ip = np.ascontiguousarray(s.inst_proto, dtype=np.int32)
         ix = np.ascontiguousarray(s.inst_xform, dtype=np.float32)
         insts = _Insts(ip.shape[0], ip.ctypes.data, ix.ctypes.data)
-        opts = _BuildOpts(formats, leaf_max, sah_bins, build_threads, device, open_pct)
+        opts = _BuildOpts(formats, leaf_max, sah_bins, build_threads, device, open_pct, node_width)
         h = ctypes.c_void_p()
         _check(L.rtq_scene_build(ctypes.cast(protos, ctypes.c_void_p), P, ctypes.byref(insts), ctypes.byref(opts),
                                  ctypes.byref(h)))
@@ -467,32 +469,44 @@ def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None,
 
 
 # ----------------------------------------------------------------------------- host BVH
+NODE_WIDE = np.dtype([("lo", "<f4", (3, 8)), ("hi", "<f4", (3, 8)), ("child", "<u4", 8)])
 NODE_F32 = np.dtype([("lo_x", "<f4", 4), ("hi_x", "<f4", 4), ("lo_y", "<f4", 4), ("hi_y", "<f4", 4),
                      ("lo_z", "<f4", 4), ("hi_z", "<f4", 4), ("child", "<u4", 4), ("pad", "<u4", 4)])
 NODE_Q8 = np.dtype([("origin", "<f4", 3), ("exps", "<u4"), ("lo_x", "<u4"), ("hi_x", "<u4"), ("lo_y", "<u4"),
                     ("hi_y", "<u4"), ("lo_z", "<u4"), ("hi_z", "<u4"), ("child", "<u4", 4), ("pad", "<u4", 2)])
+NODE_Q8W8 = np.dtype([("origin", "<f4", 3), ("exps", "<u4"), ("lo_x", "<u4", 2), ("hi_x", "<u4", 2),
+                      ("lo_y", "<u4", 2), ("hi_y", "<u4", 2), ("lo_z", "<u4", 2), ("hi_z", "<u4", 2),
+                      ("child", "<u4", 8)])
+NODE_Q8W2 = np.dtype([("origin", "<f4", 3), ("exps", "<u4"), ("x", "<u4"), ("y", "<u4"), ("z", "<u4"),
+                      ("child", "<u4", 2), ("pad", "<u4", 3)])
+_Q8_DTYPE = {2: NODE_Q8W2, 4: NODE_Q8, 8: NODE_Q8W8}
 
 
-def host_bvh(boxes, leaf_max: int = 4, bins: int = 32, threads: int = 0) -> dict:
-    """The scene builder's 4-wide BVH over host boxes ([n, 6] lo xyz, hi xyz),
-    built on the host (no device): dict of FP32 nodes, quantized nodes (numpy
-    structured arrays), leaf order and depth."""
+def host_bvh(boxes, leaf_max: int = 4, bins: int = 32, threads: int = 0, width: int = 4) -> dict:
+    """The scene builder's W-wide BVH over host boxes ([n, 6] lo xyz, hi xyz),
+    built on the host (no device): dict of exact FP32 boxes ("wide"), device
+    FP32 nodes ("f32", width 4 only, else None), quantized nodes ("q8") as
+    numpy structured arrays, leaf order, depth and width."""
     L = load_library()
     b = np.ascontiguousarray(boxes, dtype=np.float32).reshape(-1, 6)
     h = ctypes.c_void_p()
-    _check(L.rtq_host_bvh_build(b.ctypes.data, b.shape[0], int(leaf_max), int(bins), int(threads), ctypes.byref(h)))
+    _check(L.rtq_host_bvh_build(b.ctypes.data, b.shape[0], int(leaf_max), int(bins), int(threads), int(width),
+                                ctypes.byref(h)))
     try:
-        pf, pq, po = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        pw, pf, pq, po = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
         nn, depth = ctypes.c_int64(), ctypes.c_int32()
-        _check(L.rtq_host_bvh_get(h, ctypes.byref(pf), ctypes.byref(pq), ctypes.byref(nn), ctypes.byref(po),
-                                  ctypes.byref(depth)))
+        _check(L.rtq_host_bvh_get(h, ctypes.byref(pw), ctypes.byref(pf), ctypes.byref(pq), ctypes.byref(nn),
+                                  ctypes.byref(po), ctypes.byref(depth)))
         n = nn.value
-        f32 = np.frombuffer(ctypes.string_at(pf.value, n * NODE_F32.itemsize), dtype=NODE_F32).copy()
-        q8 = np.frombuffer(ctypes.string_at(pq.value, n * NODE_Q8.itemsize), dtype=NODE_Q8).copy()
+        qd = _Q8_DTYPE[int(width)]
+        wide = np.frombuffer(ctypes.string_at(pw.value, n * NODE_WIDE.itemsize), dtype=NODE_WIDE).copy()
+        f32 = (np.frombuffer(ctypes.string_at(pf.value, n * NODE_F32.itemsize), dtype=NODE_F32).copy()
+               if pf.value else None)
+        q8 = np.frombuffer(ctypes.string_at(pq.value, n * qd.itemsize), dtype=qd).copy()
         order = np.frombuffer(ctypes.string_at(po.value, 4 * b.shape[0]), dtype=np.uint32).copy()
     finally:
         L.rtq_host_bvh_destroy(h)
-    return {"f32": f32, "q8": q8, "order": order, "depth": depth.value}
+    return {"wide": wide, "f32": f32, "q8": q8, "order": order, "depth": depth.value, "width": int(width)}
 
 
 def version() -> str:

@@ -1,4 +1,4 @@
-"""Autotuner for the traversal and scheduling parameters.
+"""Autotuner for the acceleration structure and the traversal parameters.
 
 For a given scene, set of views and render settings, it times candidate launch
 configurations: node format, scheduler, LDS stack depth, resident waves per
@@ -6,7 +6,8 @@ CU, block size and the persistent lane-refill threshold.  Every candidate's
 image must be bit-identical to the FP32 plain-scheduler image, since changing
 these parameters must never change a hit.  The fastest configuration per
 (node format, scheduler) is returned and cached in a JSON file keyed by the
-device, the scene and the render settings.
+device, the scene and the render settings.  `autotune_width` also chooses the
+node width (2, 4 or 8 children per node), which needs one build per width.
 """
 from __future__ import annotations
 
@@ -75,7 +76,9 @@ def autotune_render(S, cams, settings, formats=(RTQ_NODE_Q8, RTQ_NODE_FP32),
     n_pix = sum(c.w * c.h for c in cams)
     img = torch.empty(n_pix, device="cuda")
     frame0 = settings.frame
-    render(S, cams, settings, images=img, node_format=RTQ_NODE_FP32, scheduler=SCHED_PLAIN)
+    # reference: FP32 plain when the scene has FP32 nodes (4-wide), else quantized plain
+    ref_fmt = RTQ_NODE_FP32 if S.info()["formats"] & RTQ_NODE_FP32 else RTQ_NODE_Q8
+    render(S, cams, settings, images=img, node_format=ref_fmt, scheduler=SCHED_PLAIN)
     ref = img.clone()
     lim = torch.cuda.get_device_properties(0).shared_memory_per_block if hasattr(
         torch.cuda.get_device_properties(0), "shared_memory_per_block") else 65536
@@ -154,3 +157,54 @@ def autotune_trace(S, rays, formats=(RTQ_NODE_Q8, RTQ_NODE_FP32), schedulers=(SC
             result[f"{fmt}/{sched}"] = {"opts": best[0], "ms": round(best[1], 3)}
     result["table"] = table
     return result
+
+
+def autotune_width(scene_arrays, cams, settings, widths=(4, 8, 2), schedulers=(SCHED_PERSISTENT,),
+                   grid: Optional[dict] = None, reps: int = 2, build_opts: Optional[dict] = None, rays=None,
+                   log=None) -> dict:
+    """Choose the node width: build the scene (generator arrays) once per width,
+    tune the quantized-node launches of each, and return the fastest width with
+    its launch options.  Every width's frames (and closest hits of `rays`, an
+    [n, 8] FP32 device tensor, when given) must equal the 4-wide FP32 plain
+    reference bit for bit.  The scenes are freed before returning.
+
+    Returns {"best": {"node_width": w, "opts": {...}, "ms": t}, "widths": {w: {...}}}."""
+    import torch
+    from . import Scene, trace_closest
+    build_opts = dict(build_opts or {})
+    grid = grid or QUICK_GRID
+    S4 = Scene(scene_arrays, **build_opts)
+    n_pix = sum(c.w * c.h for c in cams)
+    img = torch.empty(n_pix, device="cuda")
+    render(S4, cams, settings, images=img, node_format=RTQ_NODE_FP32, scheduler=SCHED_PLAIN)
+    ref = img.clone()
+    ref_hits = trace_closest(S4, rays, node_format=RTQ_NODE_FP32, scheduler=SCHED_PLAIN) if rays is not None else None
+    torch.cuda.synchronize()
+    S4.close()
+    per_width = {}
+    best = None
+    for w in widths:
+        S = Scene(scene_arrays, node_width=w, **build_opts)
+        render(S, cams, settings, images=img, node_format=RTQ_NODE_Q8, scheduler=SCHED_PERSISTENT)
+        torch.cuda.synchronize()
+        if not torch.equal(img.view(torch.int32), ref.view(torch.int32)):
+            raise RuntimeError(f"autotune: node width {w} changed the image")
+        if ref_hits is not None:
+            h = trace_closest(S, rays, node_format=RTQ_NODE_Q8, scheduler=SCHED_PERSISTENT)
+            torch.cuda.synchronize()
+            for k in ("t", "u", "v", "inst", "prim"):
+                if not torch.equal(getattr(h, k).view(torch.int32), getattr(ref_hits, k).view(torch.int32)):
+                    raise RuntimeError(f"autotune: node width {w} changed the hits ({k})")
+        r = autotune_render(S, cams, settings, formats=(RTQ_NODE_Q8,), schedulers=schedulers, grid=grid, reps=reps,
+                            cache=None, log=log)
+        r.pop("table", None)
+        info = S.info()
+        top = min(r.values(), key=lambda x: x["ms"])
+        per_width[w] = dict(top, nodes=info["tlas_nodes"] + info["blas_nodes"],
+                            depth=[info["tlas_depth"], info["blas_depth_max"]])
+        if log:
+            log(f"autotune width {w}: {per_width[w]}")
+        if best is None or top["ms"] < best["ms"]:
+            best = dict(node_width=w, opts=top["opts"], ms=top["ms"])
+        S.close()
+    return {"best": best, "widths": per_width}

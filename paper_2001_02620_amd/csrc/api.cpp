@@ -59,7 +59,7 @@ void DeviceBuffers::release() {
 
 SceneView scene_view(const rtq_scene* s, int fmt) {
   SceneView v;
-  v.nodes = reinterpret_cast<const uint4*>(fmt == RTQ_NODE_Q8 ? s->nodes_q8 : s->nodes_f32);
+  v.nodes = reinterpret_cast<const uint4*>(fmt == kCodecF32 ? s->nodes_f32 : s->nodes_q8);
   v.rec_pmax = s->rec_pmax;
   v.p_world = s->p_world;
   v.tlas_root = s->tlas_root;
@@ -85,7 +85,8 @@ int resolve_format(const rtq_scene* s, int32_t req, int* fmt) {
   if (f == 0) f = (s->formats & RTQ_NODE_Q8) ? RTQ_NODE_Q8 : RTQ_NODE_FP32;
   if (f != RTQ_NODE_FP32 && f != RTQ_NODE_Q8) return set_error(RTQ_E_INVALID_ARG, "unknown node format %d", req);
   if (!(s->formats & f)) return set_error(RTQ_E_INVALID_ARG, "node format %d was not built", f);
-  *fmt = f;
+  if (f == RTQ_NODE_FP32) *fmt = kCodecF32;
+  else *fmt = s->width == 8 ? kCodecQ8W8 : (s->width == 2 ? kCodecQ8W2 : kCodecQ8);
   return RTQ_OK;
 }
 
@@ -140,9 +141,14 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     return set_error(RTQ_E_INVALID_ARG, "bad instance arrays");
   rtq_build_opts o{};
   if (opts) o = *opts;
-  const int formats = o.formats ? o.formats : (RTQ_NODE_FP32 | RTQ_NODE_Q8);
+  const int width = o.node_width ? o.node_width : 4;
+  if (width != 2 && width != 4 && width != 8) return set_error(RTQ_E_INVALID_ARG, "node_width %d is not 2, 4 or 8", width);
+  const int formats = o.formats ? o.formats : (width == 4 ? (RTQ_NODE_FP32 | RTQ_NODE_Q8) : RTQ_NODE_Q8);
   if (formats & ~(RTQ_NODE_FP32 | RTQ_NODE_Q8)) return set_error(RTQ_E_INVALID_ARG, "bad formats mask");
+  if ((formats & RTQ_NODE_FP32) && width != 4)
+    return set_error(RTQ_E_INVALID_ARG, "FP32 nodes are 4-wide only (node_width %d)", width);
   BuildParams bp;
+  bp.width = width;
   bp.leaf_max = o.leaf_max ? o.leaf_max : 4;
   bp.bins = o.sah_bins ? o.sah_bins : 32;
   bp.want_q8 = true;  // the quantized nodes are cheap to derive; keep both topologies identical
@@ -182,7 +188,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   if (e != hipSuccess) return hip_error(e, "hipSetDevice");
 
   // ---- bottom level: one BVH per prototype, built on host threads
-  std::vector<Bvh4> blas(n_protos);
+  std::vector<Bvh> blas(n_protos);
   std::vector<int32_t> order_p(n_protos);
   for (int32_t p = 0; p < n_protos; ++p) order_p[p] = p;
   std::sort(order_p.begin(), order_p.end(), [&](int a, int b) { return protos[a].n_quads > protos[b].n_quads; });
@@ -215,7 +221,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     }
     BuildParams pp = bp;
     pp.threads = threads;
-    build_bvh4(boxes.data(), P.n_quads, pp, blas[p]);
+    build_bvh(boxes.data(), P.n_quads, pp, blas[p]);
   };
   {
     std::vector<Aabb> boxes;
@@ -244,6 +250,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   auto t1 = std::chrono::steady_clock::now();
   s->device = dev;
   s->formats = formats;
+  s->width = width;
   s->n_protos = n_protos;
   s->n_inst = N;
   s->n_quads = total_quads;
@@ -259,7 +266,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   uint64_t node_base = 0, quad_base = 0;
   int max_blas_depth = 0;
   for (int32_t p = 0; p < n_protos; ++p) {
-    if (node_base + blas[p].f32.size() >= (uint64_t)kLeafBit) {
+    if (node_base + blas[p].nodes.size() >= (uint64_t)kLeafBit) {
       return set_error(RTQ_E_LIMIT, "bottom-level node count exceeds 2^31");
     }
     if (!relocate(blas[p], (uint32_t)node_base, (uint32_t)quad_base)) {
@@ -274,7 +281,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
       return set_error(RTQ_E_LIMIT, "prototype %d has coordinates beyond 2^60", p);
     }
     max_blas_depth = std::max(max_blas_depth, blas[p].depth);
-    node_base += blas[p].f32.size();
+    node_base += blas[p].nodes.size();
     quad_base += protos[p].n_quads;
   }
   const size_t n_blas_nodes = node_base;
@@ -306,16 +313,17 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     if (e != hipSuccess) return hip_error(e, "hipMemcpy");                        \
   } while (0)
 
-  // bottom levels first; the top level is appended once it is built.  The FP32
-  // nodes stay on the host in any case: opening instances reads their boxes.
-  std::vector<NodeF32> nf;
-  std::vector<NodeQ8> nq;
-  nf.reserve(n_blas_nodes);
-  if (formats & RTQ_NODE_Q8) nq.reserve(n_blas_nodes);
+  // bottom levels first; the top level is appended once it is built.  The host
+  // nodes (exact FP32 boxes) stay until the instances are opened, which reads
+  // their boxes.
+  std::vector<WideNode> nw;
+  std::vector<uint4> nq;
+  nw.reserve(n_blas_nodes);
+  if (formats & RTQ_NODE_Q8) nq.reserve(n_blas_nodes * q8_stride(width));
   for (int32_t p = 0; p < n_protos; ++p) {
-    nf.insert(nf.end(), blas[p].f32.begin(), blas[p].f32.end());
+    nw.insert(nw.end(), blas[p].nodes.begin(), blas[p].nodes.end());
     if (formats & RTQ_NODE_Q8) nq.insert(nq.end(), blas[p].q8.begin(), blas[p].q8.end());
-    blas[p] = Bvh4{};  // release host memory early
+    blas[p] = Bvh{};  // release host memory early
   }
   UPLOAD(s->quads, quads.data(), quads.size() * sizeof(float4));
   UPLOAD(s->quad_prim, quad_prim.data(), quad_prim.size() * sizeof(int32_t));
@@ -408,16 +416,21 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     op.budget = std::min<int64_t>(N * (int64_t)pct / 100, (int64_t)kMaxLeafFirst - N);
     op.threads = nthreads_all;
     entries = open_instances(N, insts->xform, insts->proto, boxes.data(), pad.data(), proto_root, proto_qbase,
-                             proto_nq, nf, op);
+                             proto_nq, nw, op);
   }
   const int64_t E = (int64_t)entries.size();
   s->n_rec = E;
-  if (!(formats & RTQ_NODE_FP32)) nf = std::vector<NodeF32>();
+  std::vector<NodeF32> nf;
+  if (formats & RTQ_NODE_FP32) {
+    nf.resize(nw.size());
+    for (size_t i = 0; i < nw.size(); ++i) nf[i] = pack_f32(nw[i]);
+  }
+  nw = std::vector<WideNode>();
   s->build_phase[2] = since(t1);
   t1 = std::chrono::steady_clock::now();
 
   // ---- top level over the padded entry boxes (one entry per leaf)
-  Bvh4 tlas;
+  Bvh tlas;
   BuildParams tp = bp;
   tp.leaf_max = 1;
   // one box per entry: finer bins pay off at the top level (256 against 64:
@@ -428,32 +441,32 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     std::vector<Aabb> eb(E);
     for (int64_t k = 0; k < E; ++k) eb[k] = entries[k].box;
     boxes = std::vector<Aabb>();
-    build_bvh4(eb.data(), E, tp, tlas);
+    build_bvh(eb.data(), E, tp, tlas);
   } else {
     Aabb none;
     for (int a = 0; a < 3; ++a) none.lo[a] = none.hi[a] = 0.0f;
-    build_bvh4(&none, 1, tp, tlas);  // placeholder root; n_rec = 0 makes every ray miss first
+    build_bvh(&none, 1, tp, tlas);  // placeholder root; n_rec = 0 makes every ray miss first
   }
-  if (n_blas_nodes + tlas.f32.size() >= (uint64_t)kLeafBit)
+  if (n_blas_nodes + tlas.nodes.size() >= (uint64_t)kLeafBit)
     return set_error(RTQ_E_LIMIT, "node count exceeds 2^31");
   if (!relocate(tlas, (uint32_t)n_blas_nodes, 0u))
     return set_error(RTQ_E_LIMIT, "top-level reference overflow");
-  if (3 * (tlas.depth + max_blas_depth) + 8 > kStackTotal)
+  if ((width - 1) * (tlas.depth + max_blas_depth) + 8 > kStackTotal)
     return set_error(RTQ_E_LIMIT, "BVH depth %d + %d exceeds the traversal stack", tlas.depth, max_blas_depth);
   s->p_world = level_pmax(tlas);
   if (!(s->p_world < kMaxPlaneAbs)) return set_error(RTQ_E_LIMIT, "instance boxes reach beyond 2^60");
   s->tlas_root = (uint32_t)n_blas_nodes;
   s->tlas_depth = tlas.depth;
-  s->tlas_nodes = (int64_t)tlas.f32.size();
+  s->tlas_nodes = (int64_t)tlas.nodes.size();
   if (formats & RTQ_NODE_FP32) {
-    nf.insert(nf.end(), tlas.f32.begin(), tlas.f32.end());
+    for (const WideNode& w : tlas.nodes) nf.push_back(pack_f32(w));
     UPLOAD(s->nodes_f32, nf.data(), nf.size() * sizeof(NodeF32));
     nf = std::vector<NodeF32>();
   }
   if (formats & RTQ_NODE_Q8) {
     nq.insert(nq.end(), tlas.q8.begin(), tlas.q8.end());
-    UPLOAD(s->nodes_q8, nq.data(), nq.size() * sizeof(NodeQ8));
-    nq = std::vector<NodeQ8>();
+    UPLOAD(s->nodes_q8, nq.data(), nq.size() * sizeof(uint4));
+    nq = std::vector<uint4>();
   }
   // records in top-level leaf order
   const int64_t En = std::max<int64_t>(E, 1);
@@ -532,6 +545,7 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->tlas_depth = s->tlas_depth;
   info->blas_depth_max = s->blas_depth;
   info->formats = s->formats;
+  info->node_width = s->width;
   info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes + s->env_bytes);
   info->build_seconds = s->build_seconds;
   info->n_top_entries = s->n_rec;
@@ -718,13 +732,14 @@ int rtq_trace_occluded(const rtq_scene* s, const rtq_rays* rays, int64_t n, uint
 }
 
 int rtq_host_bvh_build(const float* boxes, int64_t n, int32_t leaf_max, int32_t bins, int32_t threads,
-                       rtq_host_bvh** out) {
+                       int32_t width, rtq_host_bvh** out) {
   if (!out) return set_error(RTQ_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!boxes || n < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one box");
   if (n > (int64_t)kMaxLeafFirst) return set_error(RTQ_E_LIMIT, "%lld boxes exceed 2^28", (long long)n);
   if (leaf_max < 1 || leaf_max > 8) return set_error(RTQ_E_INVALID_ARG, "leaf_max %d outside [1, 8]", leaf_max);
   if (bins < 4 || bins > 64) return set_error(RTQ_E_INVALID_ARG, "bins %d outside [4, 64]", bins);
+  if (width != 2 && width != 4 && width != 8) return set_error(RTQ_E_INVALID_ARG, "width %d is not 2, 4 or 8", width);
   try {
     std::vector<Aabb> b(n);
     for (int64_t i = 0; i < n; ++i) {
@@ -738,22 +753,28 @@ int rtq_host_bvh_build(const float* boxes, int64_t n, int32_t leaf_max, int32_t 
     BuildParams p;
     p.leaf_max = leaf_max;
     p.bins = bins;
+    p.width = width;
     p.threads = threads > 0 ? threads : (int)std::max(1u, std::thread::hardware_concurrency());
-    rtq_host_bvh* h = new rtq_host_bvh;
-    build_bvh4(b.data(), n, p, h->bvh);
-    *out = h;
+    std::unique_ptr<rtq_host_bvh> h(new rtq_host_bvh);
+    build_bvh(b.data(), n, p, h->bvh);
+    if (width == 4) {
+      h->f32.resize(h->bvh.nodes.size());
+      for (size_t i = 0; i < h->bvh.nodes.size(); ++i) h->f32[i] = pack_f32(h->bvh.nodes[i]);
+    }
+    *out = h.release();
     return RTQ_OK;
   } catch (const std::bad_alloc&) {
     return set_error(RTQ_E_OOM, "host allocation failed");
   }
 }
 
-int rtq_host_bvh_get(const rtq_host_bvh* h, const void** nodes_f32, const void** nodes_q8, int64_t* n_nodes,
-                     const uint32_t** order, int32_t* depth) {
+int rtq_host_bvh_get(const rtq_host_bvh* h, const void** nodes_wide, const void** nodes_f32, const void** nodes_q8,
+                     int64_t* n_nodes, const uint32_t** order, int32_t* depth) {
   if (!h) return set_error(RTQ_E_INVALID_ARG, "NULL bvh");
-  if (nodes_f32) *nodes_f32 = h->bvh.f32.data();
+  if (nodes_wide) *nodes_wide = h->bvh.nodes.data();
+  if (nodes_f32) *nodes_f32 = h->f32.empty() ? nullptr : h->f32.data();
   if (nodes_q8) *nodes_q8 = h->bvh.q8.data();
-  if (n_nodes) *n_nodes = (int64_t)h->bvh.f32.size();
+  if (n_nodes) *n_nodes = (int64_t)h->bvh.nodes.size();
   if (order) *order = h->bvh.order.data();
   if (depth) *depth = h->bvh.depth;
   return RTQ_OK;
@@ -766,7 +787,9 @@ int rtq_trace_brute(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq_hit
   if (rc) return rc;
   if (!hits || (n > 0 && (!hits->t || !hits->u || !hits->v || !hits->inst || !hits->prim)))
     return set_error(RTQ_E_INVALID_ARG, "NULL hit array");
-  const SceneView sv = scene_view(s, (s->formats & RTQ_NODE_FP32) ? RTQ_NODE_FP32 : RTQ_NODE_Q8);
+  int fmt = 0;
+  if ((rc = resolve_format(s, 0, &fmt))) return rc;
+  const SceneView sv = scene_view(s, fmt);
   const HitsSoA h{hits->t, hits->u, hits->v, hits->inst, hits->prim, hits->ref};
   const hipError_t e = launch_trace_brute(sv, soa(rays), n, h, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "brute launch");

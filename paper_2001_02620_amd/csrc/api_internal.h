@@ -34,13 +34,15 @@ int hip_error(hipError_t e, const char* what);
 }  // namespace rtq
 
 struct rtq_host_bvh {
-  rtq::Bvh4 bvh;
+  rtq::Bvh bvh;
+  std::vector<rtq::NodeF32> f32;  // the device FP32 nodes (4-wide trees only)
 };
 
 struct rtq_scene {
   static constexpr int kCounterSlots = 256;
   int device = 0;
   int formats = 0;
+  int width = 4;  // children per node (2, 4 or 8), every level
   int n_cu = 256;
   int max_lds = 65536;  // bytes of LDS one block may use
   int32_t n_protos = 0;

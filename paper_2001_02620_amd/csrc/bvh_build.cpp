@@ -1,6 +1,6 @@
-// Binned SAH construction (after Wald 2007) of a binary BVH, collapse to 4-wide
-// nodes, and 8-bit quantization of child boxes in an FP32 parent frame (the
-// compressed-node idea of Ylitie, Karras, Laine 2017, here with 4 children).
+// Binned SAH construction (after Wald 2007) of a binary BVH, collapse to W-wide
+// nodes (W = 2, 4 or 8), and 8-bit quantization of child boxes in an FP32
+// parent frame (the compressed-node idea of Ylitie, Karras, Laine 2017).
 #include "bvh_build.h"
 
 #include <algorithm>
@@ -340,23 +340,71 @@ struct Builder {
   }
 };
 
-void set_child(NodeF32& n, int k, const Box& b, uint32_t ref) {
-  n.lo_x[k] = b.lo[0];
-  n.hi_x[k] = b.hi[0];
-  n.lo_y[k] = b.lo[1];
-  n.hi_y[k] = b.hi[1];
-  n.lo_z[k] = b.lo[2];
-  n.hi_z[k] = b.hi[2];
+float bit_float(uint32_t u) {
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+void set_child(WideNode& n, int k, const Box& b, uint32_t ref) {
+  for (int a = 0; a < 3; ++a) {
+    n.lo[a][k] = b.lo[a];
+    n.hi[a][k] = b.hi[a];
+  }
   n.child[k] = ref;
 }
 
-void empty_node(NodeF32& n) {
-  for (int k = 0; k < 4; ++k) {
-    n.lo_x[k] = n.lo_y[k] = n.lo_z[k] = kInf;
-    n.hi_x[k] = n.hi_y[k] = n.hi_z[k] = -kInf;
+void empty_node(WideNode& n) {
+  for (int k = 0; k < kMaxWidth; ++k) {
+    for (int a = 0; a < 3; ++a) {
+      n.lo[a][k] = kInf;
+      n.hi[a][k] = -kInf;
+    }
     n.child[k] = kEmpty;
-    n.pad[k] = 0;
   }
+}
+
+// Quantized planes of one axis over the first w children: the frame origin, the
+// exponent and the byte planes (lower rounded down, upper up, each verified by
+// decoding it the kernels' way).  Empty slots get lo = 255, hi = 0.
+void quantize_axis(const WideNode& n, int w, int a, float* org, int* ex, uint32_t* qlo, uint32_t* qhi) {
+  float lo = kInf, hi = -kInf;
+  for (int k = 0; k < w; ++k)
+    if (n.child[k] != kEmpty) {
+      lo = std::min(lo, n.lo[a][k]);
+      hi = std::max(hi, n.hi[a][k]);
+    }
+  if (!(lo <= hi)) lo = hi = 0.0f;  // no children at all
+  *org = lo;
+  const double ext = (double)hi - (double)lo;
+  int e = -126;
+  if (ext > 0.0) e = std::max(-126, (int)std::ceil(std::log2(ext / 255.0)));
+  for (;;) {
+    bool ok = true;
+    for (int k = 0; k < w && ok; ++k) {
+      if (n.child[k] == kEmpty) {
+        qlo[k] = 255u;
+        qhi[k] = 0u;
+        continue;
+      }
+      const double sc = std::ldexp(1.0, e);
+      const double fl = std::floor(((double)n.lo[a][k] - (double)lo) / sc);
+      const double ce = std::ceil(((double)n.hi[a][k] - (double)lo) / sc);
+      int64_t ql = std::max<int64_t>(0, (int64_t)fl);
+      int64_t qh = std::max<int64_t>(0, (int64_t)ce);
+      while (ql > 0 && q8_decode((uint32_t)ql, e, lo) > n.lo[a][k]) --ql;
+      while (qh <= 255 && q8_decode((uint32_t)qh, e, lo) < n.hi[a][k]) ++qh;
+      if (ql > 255 || qh > 255 || q8_decode((uint32_t)ql, e, lo) > n.lo[a][k]) {
+        ok = false;
+        break;
+      }
+      qlo[k] = (uint32_t)ql;
+      qhi[k] = (uint32_t)qh;
+    }
+    if (ok) break;
+    ++e;
+  }
+  *ex = e;
 }
 
 }  // namespace
@@ -365,74 +413,56 @@ float q8_decode(uint32_t q, int e, float origin) {
   return std::fma((float)q, std::ldexp(1.0f, e), origin);
 }
 
-NodeQ8 quantize_node(const NodeF32& n) {
-  NodeQ8 o;
+NodeF32 pack_f32(const WideNode& n) {
+  NodeF32 o;
   std::memset(&o, 0, sizeof(o));
-  const float* LO[3] = {n.lo_x, n.lo_y, n.lo_z};
-  const float* HI[3] = {n.hi_x, n.hi_y, n.hi_z};
-  float org[3];
-  int ex[3];
-  uint32_t qlo[3][4], qhi[3][4];
-  for (int a = 0; a < 3; ++a) {
-    float lo = kInf, hi = -kInf;
-    for (int k = 0; k < 4; ++k)
-      if (n.child[k] != kEmpty) {
-        lo = std::min(lo, LO[a][k]);
-        hi = std::max(hi, HI[a][k]);
-      }
-    if (!(lo <= hi)) lo = hi = 0.0f;  // no children at all
-    org[a] = lo;
-    const double ext = (double)hi - (double)lo;
-    int e = -126;
-    if (ext > 0.0) e = std::max(-126, (int)std::ceil(std::log2(ext / 255.0)));
-    for (;;) {
-      bool ok = true;
-      for (int k = 0; k < 4 && ok; ++k) {
-        if (n.child[k] == kEmpty) {
-          qlo[a][k] = 255u;
-          qhi[a][k] = 0u;
-          continue;
-        }
-        const double s = std::ldexp(1.0, e);
-        double fl = std::floor(((double)LO[a][k] - (double)lo) / s);
-        double ce = std::ceil(((double)HI[a][k] - (double)lo) / s);
-        int64_t ql = std::max<int64_t>(0, (int64_t)fl);
-        int64_t qh = std::max<int64_t>(0, (int64_t)ce);
-        while (ql > 0 && q8_decode((uint32_t)ql, e, lo) > LO[a][k]) --ql;
-        while (qh <= 255 && q8_decode((uint32_t)qh, e, lo) < HI[a][k]) ++qh;
-        if (ql > 255 || qh > 255 || q8_decode((uint32_t)ql, e, lo) > LO[a][k]) {
-          ok = false;
-          break;
-        }
-        qlo[a][k] = (uint32_t)ql;
-        qhi[a][k] = (uint32_t)qh;
-      }
-      if (ok) break;
-      ++e;
-    }
-    ex[a] = e;
+  for (int k = 0; k < 4; ++k) {
+    o.lo_x[k] = n.lo[0][k];
+    o.hi_x[k] = n.hi[0][k];
+    o.lo_y[k] = n.lo[1][k];
+    o.hi_y[k] = n.hi[1][k];
+    o.lo_z[k] = n.lo[2][k];
+    o.hi_z[k] = n.hi[2][k];
+    o.child[k] = n.child[k];
   }
-  o.ox = org[0];
-  o.oy = org[1];
-  o.oz = org[2];
-  o.exps = (uint32_t)(uint8_t)(int8_t)ex[0] | ((uint32_t)(uint8_t)(int8_t)ex[1] << 8) |
-           ((uint32_t)(uint8_t)(int8_t)ex[2] << 16);
-  auto pack = [](const uint32_t q[4]) { return q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24); };
-  o.lo_x = pack(qlo[0]);
-  o.hi_x = pack(qhi[0]);
-  o.lo_y = pack(qlo[1]);
-  o.hi_y = pack(qhi[1]);
-  o.lo_z = pack(qlo[2]);
-  o.hi_z = pack(qhi[2]);
-  for (int k = 0; k < 4; ++k) o.child[k] = n.child[k];
   return o;
 }
 
-void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
-  out.f32.clear();
+void quantize_node(const WideNode& n, int w, uint32_t* words) {
+  float org[3];
+  int ex[3];
+  uint32_t qlo[3][kMaxWidth], qhi[3][kMaxWidth];
+  for (int a = 0; a < 3; ++a) quantize_axis(n, w, a, &org[a], &ex[a], qlo[a], qhi[a]);
+  std::memset(words, 0, 16 * q8_stride(w));
+  std::memcpy(&words[0], &org[0], 4);
+  std::memcpy(&words[1], &org[1], 4);
+  std::memcpy(&words[2], &org[2], 4);
+  words[3] = (uint32_t)(uint8_t)(int8_t)ex[0] | ((uint32_t)(uint8_t)(int8_t)ex[1] << 8) |
+             ((uint32_t)(uint8_t)(int8_t)ex[2] << 16);
+  auto pack4 = [](const uint32_t* q) { return q[0] | (q[1] << 8) | (q[2] << 16) | (q[3] << 24); };
+  for (int a = 0; a < 3; ++a) {
+    if (w == 4) {
+      words[4 + 2 * a] = pack4(qlo[a]);
+      words[5 + 2 * a] = pack4(qhi[a]);
+    } else if (w == 8) {
+      words[4 + 4 * a] = pack4(qlo[a]);
+      words[5 + 4 * a] = pack4(qlo[a] + 4);
+      words[6 + 4 * a] = pack4(qhi[a]);
+      words[7 + 4 * a] = pack4(qhi[a] + 4);
+    } else {
+      words[4 + a] = qlo[a][0] | (qlo[a][1] << 8) | (qhi[a][0] << 16) | (qhi[a][1] << 24);
+    }
+  }
+  for (int k = 0; k < w; ++k) words[q8_child_word(w) + k] = n.child[k];
+}
+
+void build_bvh(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh& out) {
+  const int W = p.width;
+  out.nodes.clear();
   out.q8.clear();
   out.order.clear();
   out.depth = 0;
+  out.width = W;
   Builder bld(boxes, n, p, p.threads);
   bld.run();
   out.order = bld.idx;
@@ -442,28 +472,28 @@ void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
     out.root_box.lo[k] = rb.lo[k];
     out.root_box.hi[k] = rb.hi[k];
   }
-  // collapse: every 4-wide node adopts up to four BVH2 descendants, expanding
+  // collapse: every W-wide node adopts up to W BVH2 descendants, expanding
   // the internal child of largest surface area first
   struct Job {
-    int32_t n2;      // BVH2 node whose subtree this 4-wide node covers
-    uint32_t slot;   // 4-wide node index
+    int32_t n2;      // BVH2 node whose subtree this W-wide node covers
+    uint32_t slot;   // W-wide node index
     int depth;
   };
-  out.f32.emplace_back();
-  empty_node(out.f32[0]);
+  out.nodes.emplace_back();
+  empty_node(out.nodes[0]);
   std::vector<Job> jobs{{0, 0u, 1}};
   while (!jobs.empty()) {
     const Job j = jobs.back();
     jobs.pop_back();
     out.depth = std::max(out.depth, j.depth);
-    int32_t kids[4];
+    int32_t kids[kMaxWidth];
     int nk = 0;
     if (N[j.n2].count > 0) {
       kids[nk++] = j.n2;  // a leaf root: one leaf child
     } else {
       kids[nk++] = N[j.n2].l;
       kids[nk++] = N[j.n2].r;
-      while (nk < 4) {
+      while (nk < W) {
         int best = -1;
         double ba = -1.0;
         for (int k = 0; k < nk; ++k)
@@ -477,7 +507,7 @@ void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
         kids[nk++] = N[c].r;
       }
     }
-    NodeF32 node;
+    WideNode node;
     empty_node(node);
     for (int k = 0; k < nk; ++k) {
       const Node2& c = N[kids[k]];
@@ -485,36 +515,40 @@ void build_bvh4(const Aabb* boxes, int64_t n, const BuildParams& p, Bvh4& out) {
       if (c.count > 0) {
         ref = make_leaf((uint32_t)c.first, (uint32_t)c.count);
       } else {
-        ref = (uint32_t)out.f32.size();
-        out.f32.emplace_back();
+        ref = (uint32_t)out.nodes.size();
+        out.nodes.emplace_back();
         jobs.push_back({kids[k], ref, j.depth + 1});
       }
       set_child(node, k, c.b, ref);
     }
-    out.f32[j.slot] = node;
+    out.nodes[j.slot] = node;
   }
   if (p.want_q8) {
-    out.q8.resize(out.f32.size());
-    const int64_t m = (int64_t)out.f32.size();
+    const int st = q8_stride(W);
+    out.q8.resize(out.nodes.size() * st);
+    const int64_t m = (int64_t)out.nodes.size();
     const int T = m < 65536 ? 1 : std::max(1, p.threads);
     run_threads(T, [&](int t) {
-      for (int64_t i = m * t / T; i < m * (t + 1) / T; ++i) out.q8[i] = quantize_node(out.f32[i]);
+      for (int64_t i = m * t / T; i < m * (t + 1) / T; ++i)
+        quantize_node(out.nodes[i], W, reinterpret_cast<uint32_t*>(&out.q8[i * st]));
     });
   }
 }
 
-float level_pmax(const Bvh4& b) {
+float level_pmax(const Bvh& b) {
   double m = 0.0;
-  for (const NodeF32& n : b.f32)
-    for (int k = 0; k < 4; ++k) {
+  for (const WideNode& n : b.nodes)
+    for (int k = 0; k < b.width; ++k) {
       if (n.child[k] == kEmpty) continue;
-      const float v[6] = {n.lo_x[k], n.hi_x[k], n.lo_y[k], n.hi_y[k], n.lo_z[k], n.hi_z[k]};
-      for (float x : v) m = std::max(m, (double)std::fabs(x));
+      for (int a = 0; a < 3; ++a)
+        m = std::max(m, std::max(std::fabs((double)n.lo[a][k]), std::fabs((double)n.hi[a][k])));
     }
-  for (const NodeQ8& n : b.q8) {
-    const float org[3] = {n.ox, n.oy, n.oz};
+  const size_t st = q8_stride(b.width);
+  for (size_t i = 0; i < b.q8.size(); i += st) {
+    const uint4 h = b.q8[i];
+    const float org[3] = {bit_float(h.x), bit_float(h.y), bit_float(h.z)};
     for (int a = 0; a < 3; ++a) {
-      const int e = (int)(int8_t)((n.exps >> (8 * a)) & 0xFFu);
+      const int e = (int)(int8_t)((h.w >> (8 * a)) & 0xFFu);
       m = std::max(m, std::fabs((double)org[a]));
       m = std::max(m, std::fabs((double)org[a] + 255.0 * std::ldexp(1.0, e)));
     }
@@ -524,7 +558,7 @@ float level_pmax(const Bvh4& b) {
   return (double)f >= m ? f : std::nextafter(f, std::numeric_limits<float>::infinity());
 }
 
-bool relocate(Bvh4& b, uint32_t node_base, uint32_t prim_base) {
+bool relocate(Bvh& b, uint32_t node_base, uint32_t prim_base) {
   auto fix = [&](uint32_t& r) -> bool {
     if (r == kEmpty) return true;
     if (ref_is_leaf(r)) {
@@ -538,12 +572,15 @@ bool relocate(Bvh4& b, uint32_t node_base, uint32_t prim_base) {
     }
     return true;
   };
-  for (auto& nd : b.f32)
-    for (int k = 0; k < 4; ++k)
+  for (auto& nd : b.nodes)
+    for (int k = 0; k < b.width; ++k)
       if (!fix(nd.child[k])) return false;
-  for (auto& nd : b.q8)
-    for (int k = 0; k < 4; ++k)
-      if (!fix(nd.child[k])) return false;
+  const size_t st = q8_stride(b.width);
+  for (size_t i = 0; i < b.q8.size(); i += st) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(&b.q8[i]) + q8_child_word(b.width);
+    for (int k = 0; k < b.width; ++k)
+      if (!fix(w[k])) return false;
+  }
   return true;
 }
 

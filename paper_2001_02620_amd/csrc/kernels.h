@@ -3,10 +3,25 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "rtq_layout.h"
 #include "trace_device.h"
 
 namespace rtq {
+
+// Call f with std::integral_constant<int, CODEC> for the run-time node codec id
+// (kCodecF32, kCodecQ8, kCodecQ8W8, kCodecQ8W2), so a launcher instantiates its
+// kernels once per codec.
+template <class F>
+decltype(auto) with_codec(int fmt, F&& f) {
+  switch (fmt) {
+    case kCodecQ8: return f(std::integral_constant<int, kCodecQ8>{});
+    case kCodecQ8W8: return f(std::integral_constant<int, kCodecQ8W8>{});
+    case kCodecQ8W2: return f(std::integral_constant<int, kCodecQ8W2>{});
+    default: return f(std::integral_constant<int, kCodecF32>{});
+  }
+}
 
 hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint32_t* proto_root,
                                 const uint32_t* face_base, int64_t n, InstRec* out, float* cond, int32_t* status,
@@ -29,7 +44,7 @@ struct HitsSoA {
 };
 
 struct TraceLaunch {
-  int fmt;          // 1 FP32, 2 Q8
+  int fmt;          // node codec: kCodecF32, kCodecQ8, kCodecQ8W8 or kCodecQ8W2
   int persistent;   // 0 plain, 1 persistent with refill
   int stack_depth;  // LDS entries per lane
   int block;        // threads per block

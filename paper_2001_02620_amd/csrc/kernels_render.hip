@@ -869,25 +869,18 @@ hipError_t launch_render_wavefront(const SceneView& sc, const RenderParams& rp, 
   hipLaunchKernelGGL(k_raygen, dim3(gp), dim3(256), 0, s, rp, pb.q[0], pb.counts);
   stage_end(ex.log, 2, ev, s);
   const bool cnt = ex.visits != nullptr;
-  if (tl.persistent) {
-    if (fmt == 2) {
-      if (cnt) wavefront_persistent<2, true>(sc, rp, pb, tl, ex, s);
-      else wavefront_persistent<2, false>(sc, rp, pb, tl, ex, s);
+  with_codec(fmt, [&](auto c) {
+    constexpr int F = decltype(c)::value;
+    if (tl.persistent) {
+      if (cnt) wavefront_persistent<F, true>(sc, rp, pb, tl, ex, s);
+      else wavefront_persistent<F, false>(sc, rp, pb, tl, ex, s);
     } else {
-      if (cnt) wavefront_persistent<1, true>(sc, rp, pb, tl, ex, s);
-      else wavefront_persistent<1, false>(sc, rp, pb, tl, ex, s);
-    }
-  } else {
-    for (int b = 0; b < rp.depth; ++b) {
-      if (fmt == 2) {
-        if (cnt) wavefront_bounce<2, true>(sc, rp, pb, b, tl, ex, s);
-        else wavefront_bounce<2, false>(sc, rp, pb, b, tl, ex, s);
-      } else {
-        if (cnt) wavefront_bounce<1, true>(sc, rp, pb, b, tl, ex, s);
-        else wavefront_bounce<1, false>(sc, rp, pb, b, tl, ex, s);
+      for (int b = 0; b < rp.depth; ++b) {
+        if (cnt) wavefront_bounce<F, true>(sc, rp, pb, b, tl, ex, s);
+        else wavefront_bounce<F, false>(sc, rp, pb, b, tl, ex, s);
       }
     }
-  }
+  });
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
   if (ex.counters)
@@ -921,23 +914,16 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
   stage_end(ex.log, 2, ev, s);
   ev = stage_begin(ex.log, s);
   const bool ts = ex.view_done != nullptr, cnt = ex.visits != nullptr;
-  if (fmt == 2) {
+  with_codec(fmt, [&](auto c) {
+    constexpr int F = decltype(c)::value;
     if (cnt) {
-      if (ts) persistent_launch<2, true, true>(sc, rp, tl, ex, s);
-      else persistent_launch<2, false, true>(sc, rp, tl, ex, s);
+      if (ts) persistent_launch<F, true, true>(sc, rp, tl, ex, s);
+      else persistent_launch<F, false, true>(sc, rp, tl, ex, s);
     } else {
-      if (ts) persistent_launch<2, true, false>(sc, rp, tl, ex, s);
-      else persistent_launch<2, false, false>(sc, rp, tl, ex, s);
+      if (ts) persistent_launch<F, true, false>(sc, rp, tl, ex, s);
+      else persistent_launch<F, false, false>(sc, rp, tl, ex, s);
     }
-  } else {
-    if (cnt) {
-      if (ts) persistent_launch<1, true, true>(sc, rp, tl, ex, s);
-      else persistent_launch<1, false, true>(sc, rp, tl, ex, s);
-    } else {
-      if (ts) persistent_launch<1, true, false>(sc, rp, tl, ex, s);
-      else persistent_launch<1, false, false>(sc, rp, tl, ex, s);
-    }
-  }
+  });
   stage_end(ex.log, 0, ev, s);
   ev = stage_begin(ex.log, s);
   hipLaunchKernelGGL(k_accum, dim3(blocks(n_pixels, 256)), dim3(256), 0, s, rp, image, n_pixels);
@@ -948,10 +934,10 @@ hipError_t launch_render_megakernel(const SceneView& sc, const RenderParams& rp,
 hipError_t launch_path_record(const SceneView& sc, const RenderParams& rp, int fmt, int stack_depth, int64_t pid,
                               int32_t* rec_i, float* rec_f, int32_t* out, hipStream_t s) {
   const size_t lds = (size_t)64 * stack_depth * kStackEntryBytes;
-  if (fmt == 2)
-    hipLaunchKernelGGL((k_path_record<2>), dim3(1), dim3(64), lds, s, sc, rp, pid, stack_depth, rec_i, rec_f, out);
-  else
-    hipLaunchKernelGGL((k_path_record<1>), dim3(1), dim3(64), lds, s, sc, rp, pid, stack_depth, rec_i, rec_f, out);
+  with_codec(fmt, [&](auto c) {
+    hipLaunchKernelGGL((k_path_record<decltype(c)::value>), dim3(1), dim3(64), lds, s, sc, rp, pid, stack_depth,
+                       rec_i, rec_f, out);
+  });
   return hipGetLastError();
 }
 
@@ -964,10 +950,10 @@ hipError_t launch_adjoint(const SceneView& sc, const RenderParams& rp, int fmt, 
                           const float* grad_img, float* grad_albedo, hipStream_t s) {
   const size_t lds = (size_t)block * stack_depth * kStackEntryBytes;
   const unsigned g = blocks(rp.n_paths, block);
-  if (fmt == 2)
-    hipLaunchKernelGGL((k_adjoint<2>), dim3(g), dim3(block), lds, s, sc, rp, grad_img, grad_albedo, stack_depth);
-  else
-    hipLaunchKernelGGL((k_adjoint<1>), dim3(g), dim3(block), lds, s, sc, rp, grad_img, grad_albedo, stack_depth);
+  with_codec(fmt, [&](auto c) {
+    hipLaunchKernelGGL((k_adjoint<decltype(c)::value>), dim3(g), dim3(block), lds, s, sc, rp, grad_img, grad_albedo,
+                       stack_depth);
+  });
   return hipGetLastError();
 }
 

@@ -159,8 +159,7 @@ static hipError_t launch2(const SceneView& sc, const RaysSoA& r, int64_t n, cons
 hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA* hits, uint8_t* occ,
                         uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  return tl.fmt == 2 ? launch2<2>(sc, rays, n, hits, occ, visits, tl, s)
-                     : launch2<1>(sc, rays, n, hits, occ, visits, tl, s);
+  return with_codec(tl.fmt, [&](auto c) { return launch2<decltype(c)::value>(sc, rays, n, hits, occ, visits, tl, s); });
 }
 
 // Claim counters of the allocation-free ray query (rtq_trace_closest_noalloc):

@@ -60,18 +60,16 @@ struct Child {
   float lo[3], hi[3];
 };
 
-int children(const std::vector<NodeF32>& nodes, uint32_t ref, Child out[4]) {
-  const NodeF32& n = nodes[ref];
+int children(const std::vector<WideNode>& nodes, uint32_t ref, Child out[kMaxWidth]) {
+  const WideNode& n = nodes[ref];
   int c = 0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kMaxWidth; ++k) {
     if (n.child[k] == kEmpty) continue;
     out[c].ref = n.child[k];
-    out[c].lo[0] = n.lo_x[k];
-    out[c].lo[1] = n.lo_y[k];
-    out[c].lo[2] = n.lo_z[k];
-    out[c].hi[0] = n.hi_x[k];
-    out[c].hi[1] = n.hi_y[k];
-    out[c].hi[2] = n.hi_z[k];
+    for (int a = 0; a < 3; ++a) {
+      out[c].lo[a] = n.lo[a][k];
+      out[c].hi[a] = n.hi[a][k];
+    }
     ++c;
   }
   return c;
@@ -82,7 +80,7 @@ int children(const std::vector<NodeF32>& nodes, uint32_t ref, Child out[4]) {
 std::vector<TopEntry> open_instances(int64_t n, const float* xform, const int32_t* proto, const Aabb* inst_box,
                                      const double* pad, const std::vector<uint32_t>& proto_root,
                                      const std::vector<int32_t>& proto_qbase, const std::vector<int32_t>& proto_nq,
-                                     const std::vector<NodeF32>& nodes, const OpenParams& params) {
+                                     const std::vector<WideNode>& nodes, const OpenParams& params) {
   std::vector<TopEntry> out((size_t)n);
   for (int64_t i = 0; i < n; ++i) {
     const int32_t p = proto[i];
@@ -95,7 +93,7 @@ std::vector<TopEntry> open_instances(int64_t n, const float* xform, const int32_
   std::vector<uint32_t> q_lo(nodes.size()), q_hi(nodes.size());
   for (size_t j = nodes.size(); j-- > 0;) {
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kMaxWidth; ++k) {
       const uint32_t c = nodes[j].child[k];
       if (c == kEmpty) continue;
       uint32_t a, b;
@@ -141,7 +139,7 @@ std::vector<TopEntry> open_instances(int64_t n, const float* xform, const int32_
     if (ref_is_leaf(e.ref)) return -1.0;
     double m[12];
     load_m(e.inst, m);
-    Child ch[4];
+    Child ch[kMaxWidth];
     const int nc = children(nodes, e.ref, ch);
     const double a = area(box64(e.box));
     double sum = 0.0;
@@ -172,7 +170,7 @@ std::vector<TopEntry> open_instances(int64_t n, const float* xform, const int32_
     const uint32_t ei = heap.top().second;
     heap.pop();
     const TopEntry e = out[ei];
-    Child ch[4];
+    Child ch[kMaxWidth];
     const int nc = children(nodes, e.ref, ch);
     if (extra + nc - 1 > params.budget) break;
     double m[12];

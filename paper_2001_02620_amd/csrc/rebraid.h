@@ -41,8 +41,8 @@ struct OpenParams {
 
 // Entries for n instances.  inst_box[i] is the padded world box of instance i
 // (exact bounds of its transformed vertices plus pad[i]); xform holds the FP32
-// world <- object transforms (row-major 3x4); nodes are the FP32 bottom-level
-// nodes with absolute references; proto_root / proto_qbase / proto_nq give each
+// world <- object transforms (row-major 3x4); nodes are the host bottom-level
+// nodes (exact FP32 boxes) with absolute references; proto_root / proto_qbase / proto_nq give each
 // prototype's root node and quad range.  A subtree's world box is the
 // transformed box of its object-space bounds, padded by pad[i] and clipped to
 // inst_box[i], rounded outward to FP32: it contains every transformed vertex of
@@ -54,6 +54,6 @@ struct OpenParams {
 std::vector<TopEntry> open_instances(int64_t n, const float* xform, const int32_t* proto, const Aabb* inst_box,
                                      const double* pad, const std::vector<uint32_t>& proto_root,
                                      const std::vector<int32_t>& proto_qbase, const std::vector<int32_t>& proto_nq,
-                                     const std::vector<NodeF32>& nodes, const OpenParams& params);
+                                     const std::vector<WideNode>& nodes, const OpenParams& params);
 
 }  // namespace rtq

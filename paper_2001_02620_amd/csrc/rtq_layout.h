@@ -2,10 +2,12 @@
 //
 // Acceleration structure (Section 5.2 of the paper: one BVH per prototype object
 // under a top-level BVH over the instances; quads are the primitives):
-//   * top level (TLAS): 4-wide nodes over instance world boxes; a leaf holds one
+//   * top level (TLAS): W-wide nodes over instance world boxes; a leaf holds one
 //     instance record index.
-//   * bottom level (BLAS): 4-wide nodes per prototype over its quads; a leaf
+//   * bottom level (BLAS): W-wide nodes per prototype over its quads; a leaf
 //     holds 1..8 consecutive quads of the global leaf-ordered quad array.
+// The node width W (2, 4 or 8) is chosen per scene at build; FP32 nodes exist
+// at W = 4 only, quantized nodes at every width.
 // Child references are 32-bit offsets from one 64-bit array base per level (the
 // GPU analogue of the 32-bit addressing from a uniform base that Section 5.5
 // relies on: no object in these scenes needs 64-bit offsets).
@@ -54,6 +56,41 @@ struct alignas(16) NodeQ8 {
 };
 static_assert(sizeof(NodeQ8) == 64, "NodeQ8 is 64 B");
 
+// ---- quantized 8-wide node: 96 B ---------------------------------------------
+// The 4-wide frame and decode with two words per plane set: children 0..3 in
+// the first word of a pair, 4..7 in the second.
+struct alignas(16) NodeQ8W8 {
+  float ox, oy, oz;
+  uint32_t exps;
+  uint32_t lo_x[2], hi_x[2];
+  uint32_t lo_y[2], hi_y[2];
+  uint32_t lo_z[2], hi_z[2];
+  uint32_t child[8];
+};
+static_assert(sizeof(NodeQ8W8) == 96, "NodeQ8W8 is 96 B");
+
+// ---- quantized 2-wide node: 48 B ---------------------------------------------
+// One word per axis: lower planes of children 0, 1 in bytes 0, 1 and upper
+// planes in bytes 2, 3.
+struct alignas(16) NodeQ8W2 {
+  float ox, oy, oz;
+  uint32_t exps;
+  uint32_t x, y, z;
+  uint32_t child[2];
+  uint32_t pad[3];
+};
+static_assert(sizeof(NodeQ8W2) == 48, "NodeQ8W2 is 48 B");
+
+constexpr int kMaxWidth = 8;
+
+// Kernel node codecs: FP32 4-wide, and quantized 4-, 8- and 2-wide.
+constexpr int kCodecF32 = 1, kCodecQ8 = 2, kCodecQ8W8 = 3, kCodecQ8W2 = 4;
+
+// uint4 words per quantized node of width w, and the 32-bit word at which its
+// child references start.
+__host__ __device__ constexpr int q8_stride(int w) { return w == 8 ? 6 : (w == 2 ? 3 : 4); }
+__host__ __device__ constexpr int q8_child_word(int w) { return w == 8 ? 16 : (w == 2 ? 7 : 10); }
+
 // ---- instance record: 64 B ------------------------------------------------------
 // r0..r2: rows of the inverse linear part A^-1 (xyz) and the translation t (w), so
 // that the object-space ray is o' = A^-1 (o - t), d' = A^-1 d (t stays in the
@@ -71,7 +108,9 @@ static_assert(sizeof(InstRec) == 64, "InstRec is 64 B");
 //   (v0.x v0.y v0.z v1.x) (v1.y v1.z v2.x v2.y) (v2.z v3.x v3.y v3.z)
 constexpr int kQuadFloat4 = 3;
 
-// Worst-case traversal stack: every 4-wide level pushes at most 3 entries.
+// Traversal stack per lane: every W-wide level pushes at most W - 1 entries,
+// so a scene needs (W - 1) (top depth + bottom depth) + 8 entries at most; the
+// build rejects deeper trees.
 constexpr int kStackTotal = 192;
 
 // Work counters of one persistent launch: kClaimSlices counters, each on its own

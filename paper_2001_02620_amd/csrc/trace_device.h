@@ -315,7 +315,8 @@ __device__ __forceinline__ uint32_t sign_of(float i) { return __float_as_uint(i)
 // (6 x 16 B plane loads and the child references).  Empty slots have lo = +inf
 // and hi = -inf and miss for every ray.
 template <>
-struct NodeCodec<1> {
+struct NodeCodec<kCodecF32> {
+  static constexpr int kW = 4;
   static constexpr int kStride = 8;  // uint4 per node
   __device__ __forceinline__ static void test(const Lane& L, const uint4* __restrict__ base, uint32_t idx,
                                               float t_lim, float tn[4], uint32_t ch[4]) {
@@ -344,7 +345,8 @@ struct NodeCodec<1> {
 // fused multiply-add per plane.  The near/far byte planes of all four children
 // are selected with one select per axis.
 template <>
-struct NodeCodec<2> {
+struct NodeCodec<kCodecQ8> {
+  static constexpr int kW = 4;
   static constexpr int kStride = 4;
   __device__ __forceinline__ static float ub(uint32_t w, int k) {
     return (float)((w >> (8 * k)) & 0xFFu);
@@ -382,6 +384,96 @@ struct NodeCodec<2> {
   }
 };
 
+// Per-node constants of a quantized node: the exact 2^e / d per axis and the
+// distances of the node origin (near and far constants).
+struct Q8Frame {
+  float bx, by, bz, nax, fax, nay, fay, naz, faz;
+};
+__device__ __forceinline__ Q8Frame q8_frame(const Lane& L, const uint4 q0) {
+  Q8Frame f;
+  const float ox = __uint_as_float(q0.x), oy = __uint_as_float(q0.y), oz = __uint_as_float(q0.z);
+  f.bx = __builtin_amdgcn_ldexpf(L.ix, (int)(int8_t)(q0.w & 0xFFu));
+  f.by = __builtin_amdgcn_ldexpf(L.iy, (int)(int8_t)((q0.w >> 8) & 0xFFu));
+  f.bz = __builtin_amdgcn_ldexpf(L.iz, (int)(int8_t)((q0.w >> 16) & 0xFFu));
+  f.nax = fmaf(ox, L.ix, L.cnx);
+  f.fax = fmaf(ox, L.ix, L.cfx);
+  f.nay = fmaf(oy, L.iy, L.cny);
+  f.fay = fmaf(oy, L.iy, L.cfy);
+  f.naz = fmaf(oz, L.iz, L.cnz);
+  f.faz = fmaf(oz, L.iz, L.cfz);
+  return f;
+}
+// Entry distance of one quantized child with near bytes (qnx, qny, qnz) and far
+// bytes (qfx, qfy, qfz), or kInfF.
+__device__ __forceinline__ float q8_child(const Lane& L, const Q8Frame& f, float qnx, float qfx, float qny, float qfy,
+                                          float qnz, float qfz, float t_lim) {
+  const float n = fmaxf(fmaxf(fmaf(qnx, f.bx, f.nax), fmaf(qny, f.by, f.nay)), fmaxf(fmaf(qnz, f.bz, f.naz), L.tmin));
+  const float t = fminf(fminf(fmaf(qfx, f.bx, f.fax), fmaf(qfy, f.by, f.fay)), fmaf(qfz, f.bz, f.faz));
+  return n <= fminf(t, t_lim) ? n : kInfF;
+}
+
+// Quantized 8-wide nodes: 6 x 16 B loads; per axis the lower and upper byte
+// planes of children 0..3 and 4..7 sit in four words, and the near and far pair
+// is chosen by the direction's sign.
+template <>
+struct NodeCodec<kCodecQ8W8> {
+  static constexpr int kW = 8;
+  static constexpr int kStride = 6;
+  __device__ __forceinline__ static void test(const Lane& L, const uint4* __restrict__ base, uint32_t idx,
+                                              float t_lim, float tn[8], uint32_t ch[8]) {
+    const uint4* p = base + (size_t)idx * kStride;
+    const uint4 q0 = p[0], qx = p[1], qy = p[2], qz = p[3], c0 = p[4], c1 = p[5];
+    const Q8Frame f = q8_frame(L, q0);
+    const bool sx = L.ix >= 0.0f, sy = L.iy >= 0.0f, sz = L.iz >= 0.0f;
+    // (lo[0..3], lo[4..7], hi[0..3], hi[4..7]) per axis
+    const uint32_t nx0 = sx ? qx.x : qx.z, nx1 = sx ? qx.y : qx.w, fx0 = sx ? qx.z : qx.x, fx1 = sx ? qx.w : qx.y;
+    const uint32_t ny0 = sy ? qy.x : qy.z, ny1 = sy ? qy.y : qy.w, fy0 = sy ? qy.z : qy.x, fy1 = sy ? qy.w : qy.y;
+    const uint32_t nz0 = sz ? qz.x : qz.z, nz1 = sz ? qz.y : qz.w, fz0 = sz ? qz.z : qz.x, fz1 = sz ? qz.w : qz.y;
+    ch[0] = c0.x;
+    ch[1] = c0.y;
+    ch[2] = c0.z;
+    ch[3] = c0.w;
+    ch[4] = c1.x;
+    ch[5] = c1.y;
+    ch[6] = c1.z;
+    ch[7] = c1.w;
+    using C = NodeCodec<kCodecQ8>;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      tn[k] = q8_child(L, f, C::ub(nx0, k), C::ub(fx0, k), C::ub(ny0, k), C::ub(fy0, k), C::ub(nz0, k),
+                       C::ub(fz0, k), t_lim);
+      tn[k + 4] = q8_child(L, f, C::ub(nx1, k), C::ub(fx1, k), C::ub(ny1, k), C::ub(fy1, k), C::ub(nz1, k),
+                           C::ub(fz1, k), t_lim);
+    }
+  }
+};
+
+// Quantized 2-wide nodes: 3 x 16 B loads; one word per axis holds the lower
+// planes of both children in bytes 0, 1 and the upper planes in bytes 2, 3.
+template <>
+struct NodeCodec<kCodecQ8W2> {
+  static constexpr int kW = 2;
+  static constexpr int kStride = 3;
+  __device__ __forceinline__ static void test(const Lane& L, const uint4* __restrict__ base, uint32_t idx,
+                                              float t_lim, float tn[2], uint32_t ch[2]) {
+    const uint4* p = base + (size_t)idx * kStride;
+    const uint4 q0 = p[0], q1 = p[1];
+    const uint32_t c1 = p[2].x;
+    const Q8Frame f = q8_frame(L, q0);
+    const bool sx = L.ix >= 0.0f, sy = L.iy >= 0.0f, sz = L.iz >= 0.0f;
+    const uint32_t nx = sx ? q1.x : (q1.x >> 16), fx = sx ? (q1.x >> 16) : q1.x;
+    const uint32_t ny = sy ? q1.y : (q1.y >> 16), fy = sy ? (q1.y >> 16) : q1.y;
+    const uint32_t nz = sz ? q1.z : (q1.z >> 16), fz = sz ? (q1.z >> 16) : q1.z;
+    ch[0] = q1.w;
+    ch[1] = c1;
+    using C = NodeCodec<kCodecQ8>;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      tn[k] = q8_child(L, f, C::ub(nx, k), C::ub(fx, k), C::ub(ny, k), C::ub(fy, k), C::ub(nz, k), C::ub(fz, k),
+                       t_lim);
+  }
+};
+
 __device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32_t& rb) {
   const bool s = tb < ta;
   const float t0 = s ? tb : ta, t1 = s ? ta : tb;
@@ -390,6 +482,31 @@ __device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32
   tb = t1;
   ra = r0;
   rb = r1;
+}
+
+// Sort the children of a node by entry distance (misses, kInfF, go last).
+// Sorting networks: 1 exchange for 2 children, 5 for 4, 19 for 8 (the optimal
+// networks, Knuth TAOCP vol. 3, 5.3.4).
+template <int W>
+__device__ __forceinline__ void sort_children(float* tn, uint32_t* ch);
+template <>
+__device__ __forceinline__ void sort_children<2>(float* tn, uint32_t* ch) {
+  cswap(tn[0], ch[0], tn[1], ch[1]);
+}
+template <>
+__device__ __forceinline__ void sort_children<4>(float* tn, uint32_t* ch) {
+  cswap(tn[0], ch[0], tn[1], ch[1]);
+  cswap(tn[2], ch[2], tn[3], ch[3]);
+  cswap(tn[0], ch[0], tn[2], ch[2]);
+  cswap(tn[1], ch[1], tn[3], ch[3]);
+  cswap(tn[1], ch[1], tn[2], ch[2]);
+}
+template <>
+__device__ __forceinline__ void sort_children<8>(float* tn, uint32_t* ch) {
+  constexpr int net[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                              {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int i = 0; i < 19; ++i) cswap(tn[net[i][0]], ch[net[i][0]], tn[net[i][1]], ch[net[i][1]]);
 }
 
 // Candidate hit (t, record, quad, half) against the best so far, by key
@@ -559,7 +676,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   return true;
 }
 
-// Node step on the lanes with `act` set: test the four children, continue with
+// Node step on the lanes with `act` set: test the W children, continue with
 // the nearest, push the others (farthest first) with their entry distances.
 // Lanes without `act` test the top-level root (any valid node) and keep their
 // state; only the stack stores are predicated.  When no lane of the wave can
@@ -567,51 +684,47 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
 template <int FMT, bool COUNT>
 __device__ __forceinline__ void node_step(bool act, Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
-  float tn[4];
-  uint32_t ch[4];
+  constexpr int W = NodeCodec<FMT>::kW;
+  float tn[W];
+  uint32_t ch[W];
   if (COUNT) {
     vc.tlas += (act && L.inst_sp < 0) ? 1u : 0u;
     vc.blas += (act && L.inst_sp >= 0) ? 1u : 0u;
   }
   NodeCodec<FMT>::test(L, sc.nodes, act ? L.cur : sc.tlas_root, L.t_cull, tn, ch);
-  cswap(tn[0], ch[0], tn[1], ch[1]);
-  cswap(tn[2], ch[2], tn[3], ch[3]);
-  cswap(tn[0], ch[0], tn[2], ch[2]);
-  cswap(tn[1], ch[1], tn[3], ch[3]);
-  cswap(tn[1], ch[1], tn[2], ch[2]);
-  // sorted: the hit children are a prefix; child k goes to slot p_k
-  const bool v1 = act && tn[1] < kInfF, v2 = act && tn[2] < kInfF, v3 = act && tn[3] < kInfF;
+  sort_children<W>(tn, ch);
+  // sorted: the hit children are a prefix; child k (k >= 1) goes to slot p[k],
+  // the farthest to the bottom
+  bool v[W];
+  int pos[W];
   const int sp = L.sp;
-  const int p3 = sp, p2 = sp + (v3 ? 1 : 0), p1 = p2 + (v2 ? 1 : 0);
-  if (!__any(act && sp + 3 > S.depth)) {
-    if (v3) {
-      S.ref[64 * p3] = ch[3];
-      S.tq[64 * p3] = t_down16(tn[3]);
-    }
-    if (v2) {
-      S.ref[64 * p2] = ch[2];
-      S.tq[64 * p2] = t_down16(tn[2]);
-    }
-    if (v1) {
-      S.ref[64 * p1] = ch[1];
-      S.tq[64 * p1] = t_down16(tn[1]);
+#pragma unroll
+  for (int k = 1; k < W; ++k) v[k] = act && tn[k] < kInfF;
+  pos[W - 1] = sp;
+#pragma unroll
+  for (int k = W - 2; k >= 1; --k) pos[k] = pos[k + 1] + (v[k + 1] ? 1 : 0);
+  if (!__any(act && sp + (W - 1) > S.depth)) {
+#pragma unroll
+    for (int k = W - 1; k >= 1; --k) {
+      if (v[k]) {
+        S.ref[64 * pos[k]] = ch[k];
+        S.tq[64 * pos[k]] = t_down16(tn[k]);
+      }
     }
   } else {
-    const bool vk[3] = {v1, v2, v3};
-    const int pk[3] = {p1, p2, p3};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      if (vk[k]) {
-        if (pk[k] < S.depth) {
-          S.ref[64 * pk[k]] = ch[k + 1];
-          S.tq[64 * pk[k]] = t_down16(tn[k + 1]);
+    for (int k = 1; k < W; ++k) {
+      if (v[k]) {
+        if (pos[k] < S.depth) {
+          S.ref[64 * pos[k]] = ch[k];
+          S.tq[64 * pos[k]] = t_down16(tn[k]);
         } else {
-          spill[pk[k] - S.depth] = make_uint2(ch[k + 1], __float_as_uint(tn[k + 1]));
+          spill[pos[k] - S.depth] = make_uint2(ch[k], __float_as_uint(tn[k]));
         }
       }
     }
   }
-  L.sp = p1 + (v1 ? 1 : 0);
+  L.sp = pos[1] + (v[1] ? 1 : 0);
   L.cur = act ? (tn[0] < kInfF ? ch[0] : kEmpty) : L.cur;
 }
 

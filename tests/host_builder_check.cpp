@@ -1,7 +1,8 @@
 // Host-side check of the scene builder, compiled by tests/test_host_sanitizers.py
 // under AddressSanitizer + UndefinedBehaviorSanitizer and under ThreadSanitizer:
-// 4-wide BVH builds over random boxes (duplicates, flat and point boxes, any
-// leaf size, bin count and thread count) must give a permutation as leaf order;
+// 2-, 4- and 8-wide BVH builds over random boxes (duplicates, flat and point
+// boxes, any leaf size, bin count and thread count) must give a permutation as
+// leaf order;
 // instance opening over random prototypes and transforms must stay within its
 // budget, keep every entry's quads inside its prototype and its box inside the
 // instance box, and cover each instance's quads exactly once.
@@ -34,19 +35,24 @@ int main() {
     p.leaf_max = 1 + (int)(g() % 8);
     p.bins = 4 + (int)(g() % 60);
     p.threads = 1 + (int)(g() % 8);
-    Bvh4 out;
-    build_bvh4(b.data(), n, p, out);
+    p.width = 2 << (trial % 3);
+    Bvh out;
+    build_bvh(b.data(), n, p, out);
     std::vector<int> seen(n, 0);
     for (uint32_t o : out.order) seen[o]++;
     for (int64_t i = 0; i < n; ++i)
       if (seen[i] != 1) { std::printf("order not a permutation\n"); return 1; }
-    for (const NodeF32& nd : out.f32) (void)quantize_node(nd);
+    uint32_t words[24];
+    for (const WideNode& nd : out.nodes) quantize_node(nd, p.width, words);
+    if (p.width == 4)
+      for (const WideNode& nd : out.nodes) (void)pack_f32(nd);
     ++checks;
   }
   // instance opening over a few prototypes
   for (int trial = 0; trial < 10; ++trial) {
     const int P = 1 + (int)(g() % 4);
-    std::vector<NodeF32> nodes;
+    std::vector<WideNode> nodes;
+    const int width = 2 << (trial % 3);
     std::vector<uint32_t> root(P);
     std::vector<int32_t> qbase(P), nq(P);
     std::vector<Aabb> pbox(P);
@@ -57,15 +63,16 @@ int main() {
       for (auto& x : b) x = rand_box(g, 5.0f);
       BuildParams bp;
       bp.threads = 2;
-      Bvh4 out;
-      build_bvh4(b.data(), n, bp, out);
+      bp.width = width;
+      Bvh out;
+      build_bvh(b.data(), n, bp, out);
       if (!relocate(out, node_base, quad_base)) { std::printf("relocate failed\n"); return 1; }
       root[pi] = node_base;
       qbase[pi] = (int32_t)quad_base;
       nq[pi] = (int32_t)n;
       pbox[pi] = out.root_box;
-      nodes.insert(nodes.end(), out.f32.begin(), out.f32.end());
-      node_base += (uint32_t)out.f32.size();
+      nodes.insert(nodes.end(), out.nodes.begin(), out.nodes.end());
+      node_base += (uint32_t)out.nodes.size();
       quad_base += (uint32_t)n;
     }
     const int64_t N = 1 + (int64_t)(g() % 3000);

@@ -1,7 +1,7 @@
-"""The scene builder's BVH construction on the host (rtq_host_bvh_*, no GPU):
-trees independent of the thread count, exact FP32 child bounds, leaves that
-partition the primitives, and 8-bit quantized child boxes that contain the FP32
-ones when decoded with the kernels' arithmetic."""
+"""The scene builder's BVH construction on the host (rtq_host_bvh_*, no GPU), at
+node widths 2, 4 and 8: trees independent of the thread count, exact FP32 child
+bounds, leaves that partition the primitives, and 8-bit quantized child boxes
+that contain the FP32 ones when decoded with the kernels' arithmetic."""
 import numpy as np
 import pytest
 
@@ -34,45 +34,60 @@ def _leaf(c):
     return (int(c) >> 3) & 0x0FFFFFFF, (int(c) & 7) + 1
 
 
-@pytest.mark.parametrize("leaf_max,bins", [(1, 64), (4, 32)])
-def test_tree_does_not_depend_on_thread_count(leaf_max, bins):
+@pytest.mark.parametrize("leaf_max,bins,width", [(1, 64, 4), (4, 32, 4), (4, 32, 8), (2, 32, 2)])
+def test_tree_does_not_depend_on_thread_count(leaf_max, bins, width):
     b = _boxes(1, 150_000)
-    ref = rtq.host_bvh(b, leaf_max=leaf_max, bins=bins, threads=1)
+    ref = rtq.host_bvh(b, leaf_max=leaf_max, bins=bins, threads=1, width=width)
     for t in (3, 8):
-        r = rtq.host_bvh(b, leaf_max=leaf_max, bins=bins, threads=t)
+        r = rtq.host_bvh(b, leaf_max=leaf_max, bins=bins, threads=t, width=width)
         assert r["depth"] == ref["depth"]
         assert np.array_equal(r["order"], ref["order"])
-        assert r["f32"].tobytes() == ref["f32"].tobytes(), f"FP32 nodes differ with {t} threads"
+        assert r["wide"].tobytes() == ref["wide"].tobytes(), f"nodes differ with {t} threads"
         assert r["q8"].tobytes() == ref["q8"].tobytes(), f"quantized nodes differ with {t} threads"
 
 
-def _decode(q8, axis, which):
-    """Decoded planes [n, 4] of one axis, lower (which=0) or upper, exactly as the
-    kernels evaluate them: fmaf(q, 2^e, origin), where q 2^e is exact in FP32."""
+def _q8_planes(q8, width, axis, which):
+    """Byte planes [n, width] of one axis, lower (which=0) or upper, in each
+    width's layout."""
+    if width == 4:
+        word = q8[("lo_", "hi_")[which] + "xyz"[axis]]
+        return np.stack([(word >> (8 * c)) & 0xFF for c in range(4)], axis=1)
+    if width == 8:
+        w2 = q8[("lo_", "hi_")[which] + "xyz"[axis]]
+        return np.stack([(w2[:, c // 4] >> (8 * (c % 4))) & 0xFF for c in range(8)], axis=1)
+    word = q8["xyz"[axis]]
+    return np.stack([(word >> (8 * (2 * which + c))) & 0xFF for c in range(2)], axis=1)
+
+
+def _decode(q8, width, axis, which):
+    """Decoded planes [n, width] of one axis exactly as the kernels evaluate them:
+    fmaf(q, 2^e, origin), where q 2^e is exact in FP32."""
     e = ((q8["exps"] >> (8 * axis)) & 0xFF).astype(np.int8).astype(np.int32)
-    word = q8[("lo_", "hi_")[which] + "xyz"[axis]]
-    q = np.stack([(word >> (8 * c)) & 0xFF for c in range(4)], axis=1).astype(np.float32)
+    q = _q8_planes(q8, width, axis, which).astype(np.float32)
     scale = np.ldexp(np.float32(1.0), e).astype(np.float32)[:, None]
     return (q * scale).astype(np.float32) + q8["origin"][:, axis][:, None], q
 
 
-@pytest.mark.parametrize("seed,leaf_max", [(2, 4), (3, 1), (4, 8)])
-def test_bounds_leaves_and_quantized_containment(seed, leaf_max):
+@pytest.mark.parametrize("seed,leaf_max,width", [(2, 4, 4), (3, 1, 4), (4, 8, 4), (5, 4, 8), (6, 1, 8), (7, 4, 2)])
+def test_bounds_leaves_and_quantized_containment(seed, leaf_max, width):
     n = 20_000
     b = _boxes(seed, n)
-    r = rtq.host_bvh(b, leaf_max=leaf_max, bins=32)
-    f32, q8, order = r["f32"], r["q8"], r["order"]
+    r = rtq.host_bvh(b, leaf_max=leaf_max, bins=32, width=width)
+    wide, q8, order = r["wide"], r["q8"], r["order"]
     assert np.array_equal(np.sort(order), np.arange(n, dtype=np.uint32)), "leaf order is not a permutation"
-    m = f32.shape[0]
+    m = wide.shape[0]
+    assert (wide["child"][:, width:] == EMPTY).all(), "slots beyond the width are used"
     lo = np.full((m, 3), np.inf, np.float32)
     hi = np.full((m, 3), -np.inf, np.float32)
     covered = np.zeros(n, np.int32)
+    n_children = 0
     # children follow their parent, so a backward sweep sees every subtree first
     for j in range(m - 1, -1, -1):
-        for k in range(4):
-            c = int(f32["child"][j, k])
+        for k in range(width):
+            c = int(wide["child"][j, k])
             if c == EMPTY:
                 continue
+            n_children += 1
             if c & LEAF:
                 first, count = _leaf(c)
                 assert count <= leaf_max
@@ -82,23 +97,37 @@ def test_bounds_leaves_and_quantized_containment(seed, leaf_max):
             else:
                 assert j < c < m
                 clo, chi = lo[c], hi[c]
-            got_lo = np.array([f32["lo_x"][j, k], f32["lo_y"][j, k], f32["lo_z"][j, k]])
-            got_hi = np.array([f32["hi_x"][j, k], f32["hi_y"][j, k], f32["hi_z"][j, k]])
             # FP32 child boxes are the exact bounds of their subtrees
-            assert np.array_equal(got_lo, clo) and np.array_equal(got_hi, chi), (j, k)
+            assert np.array_equal(wide["lo"][j, :, k], clo) and np.array_equal(wide["hi"][j, :, k], chi), (j, k)
             lo[j] = np.minimum(lo[j], clo)
             hi[j] = np.maximum(hi[j], chi)
     assert (covered == 1).all(), "leaves do not partition the primitives"
-    assert np.array_equal(q8["child"], f32["child"])
-    full = f32["child"] != EMPTY
-    planes = (("lo_x", "hi_x"), ("lo_y", "hi_y"), ("lo_z", "hi_z"))
+    # the greedy collapse fills more than half of every node's slots on
+    # average (measured: 2.0 of 2, 3.07 of 4, 4.2 of 8)
+    assert n_children / m > 0.5 * width, (n_children / m, width)
+    assert np.array_equal(q8["child"], wide["child"][:, :width])
+    if width == 4:
+        f32 = r["f32"]
+        for a, ax in enumerate("xyz"):
+            assert np.array_equal(f32["lo_" + ax], wide["lo"][:, a, :4])
+            assert np.array_equal(f32["hi_" + ax], wide["hi"][:, a, :4])
+        assert np.array_equal(f32["child"], wide["child"][:, :4])
+    else:
+        assert r["f32"] is None
+    full = wide["child"][:, :width] != EMPTY
     for a in range(3):
-        dlo, qlo = _decode(q8, a, 0)
-        dhi, qhi = _decode(q8, a, 1)
-        flo, fhi = f32[planes[a][0]], f32[planes[a][1]]
+        dlo, qlo = _decode(q8, width, a, 0)
+        dhi, qhi = _decode(q8, width, a, 1)
+        flo, fhi = wide["lo"][:, a, :width], wide["hi"][:, a, :width]
         assert (dlo[full] <= flo[full]).all(), f"axis {a}: a decoded lower plane lies above the FP32 plane"
         assert (dhi[full] >= fhi[full]).all(), f"axis {a}: a decoded upper plane lies below the FP32 plane"
         assert (qlo[~full] == 255).all() and (qhi[~full] == 0).all(), "empty slots are not inverted"
+
+
+def test_wider_nodes_make_shallower_trees():
+    b = _boxes(8, 50_000)
+    d = {w: rtq.host_bvh(b, leaf_max=4, bins=32, width=w)["depth"] for w in (2, 4, 8)}
+    assert d[2] > d[4] > d[8], d
 
 
 def test_host_bvh_argument_errors():
@@ -117,3 +146,5 @@ def test_host_bvh_argument_errors():
         rtq.host_bvh(good, leaf_max=9)
     with pytest.raises(rtq.RtqError):
         rtq.host_bvh(good, bins=2)
+    with pytest.raises(rtq.RtqError):
+        rtq.host_bvh(good, width=3)
