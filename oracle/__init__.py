@@ -67,6 +67,9 @@ def lib():
         L.orc_scene_set_albedo.argtypes = [P, P]
         L.orc_scene_set_textures.argtypes = [P, P, i32]
         L.orc_scene_set_environment.argtypes = [P, P, i32, i32]
+        L.orc_scene_set_materials.argtypes = [P, P, i32, P]
+        L.orc_bsdf_eval.argtypes = [P, P, P, i64, P, P]
+        L.orc_bsdf_sample.argtypes = [P, P, P, i64, P, P, P]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
         L.orc_philox.argtypes = [P, P, P]
@@ -77,7 +80,7 @@ def lib():
         L.orc_path.argtypes = [P, P, P, i32, P, P, P, i64, i32, P, P, P, P, P]
         L.orc_flag_breakdown.argtypes = [P, P, P, i32, P, P, P, P, i64, P]
         L.orc_accept.argtypes = [P, i64, P, P, P, i32, i32, P, P, P, P, P, P, P]
-        L.orc_check_path.argtypes = [P, P, P, i32, P, P, P, i32, i64, i32, i32, P, P, i32, ctypes.c_float, P]
+        L.orc_check_path.argtypes = [P, P, P, i32, P, P, P, i32, i64, i32, i32, P, P, i32, P, P]
         L.orc_check_path.restype = i32
         _lib = L
     return _lib
@@ -101,6 +104,32 @@ def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox(_p(c), _p(k), _p(out))
     return out
+
+
+def bsdf_eval(mat, n, wo, wi):
+    """The oracle's BSDF at one frame (tests): mat = (tint r, g, b, roughness,
+    metallic, specular), unit n and wo, directions wi [k, 3].  Returns [k, 4]:
+    (A, B, pdf, P_s) with f mu_i = A + B c for base color c."""
+    m = np.ascontiguousarray(mat, dtype=np.float64)
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    o = np.ascontiguousarray(wo, dtype=np.float64)
+    w = np.ascontiguousarray(np.asarray(wi, dtype=np.float64).reshape(-1, 3))
+    out = np.zeros((w.shape[0], 4))
+    lib().orc_bsdf_eval(_p(m), _p(nn), _p(o), w.shape[0], _p(w), _p(out))
+    return out
+
+
+def bsdf_sample(mat, n, wo, u):
+    """Sampled bounce directions for lobe and direction words u [k, 3] in [0, 1):
+    (directions [k, 3], specular chosen [k], lobe word within rounding [k])."""
+    m = np.ascontiguousarray(mat, dtype=np.float64)
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    o = np.ascontiguousarray(wo, dtype=np.float64)
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1, 3))
+    wi = np.zeros_like(uu)
+    info = np.zeros((uu.shape[0], 2), np.int32)
+    lib().orc_bsdf_sample(_p(m), _p(nn), _p(o), uu.shape[0], _p(uu), _p(wi), _p(info))
+    return wi, info[:, 0].astype(bool), info[:, 1].astype(bool)
 
 
 @dataclass
@@ -133,6 +162,7 @@ class OracleScene:
         k = self._keep
         self.n_quads = int(k["quads"].shape[0])
         self.tex_res = 0
+        self.rgb = False
         self.h = lib().orc_scene_create(_p(k["verts"]), k["verts"].shape[0], _p(k["quads"]), k["quads"].shape[0],
                                         _p(k["vo"]), _p(k["qo"]), k["qo"].shape[0] - 1, _p(k["albedo"]),
                                         _p(k["ip"]), _p(k["x"]), k["ip"].shape[0])
@@ -157,6 +187,22 @@ class OracleScene:
         """Shading parameters that gradients refer to: one albedo per face, or,
         with textures, every texel (face-major, then row v, column u)."""
         return self.n_quads * (self.tex_res * self.tex_res if self.tex_res > 0 else 1)
+
+    def set_materials(self, mats: Optional[np.ndarray], face_mat: Optional[np.ndarray] = None) -> None:
+        """Principled materials: [n_mat, 6] rows (tint r, g, b, roughness,
+        metallic, specular; FP32 values read exactly) and one material index per
+        face; None returns to Lambertian faces.  With materials, images and
+        gradient weights have three channels."""
+        if mats is None:
+            assert lib().orc_scene_set_materials(self.h, None, 0, None) == 0
+            self.rgb = False
+            return
+        m = np.ascontiguousarray(np.asarray(mats, dtype=np.float32).reshape(-1, 6), dtype=np.float64)
+        f = np.ascontiguousarray(face_mat, dtype=np.int32)
+        assert f.shape == (self.n_quads,)
+        assert lib().orc_scene_set_materials(self.h, _p(m), int(m.shape[0]), _p(f)) == 0
+        self._mats = (m, f)
+        self.rgb = True
 
     def set_textures(self, texels: Optional[np.ndarray]) -> None:
         """Per-face textures [n_quads, res, res] (row v, column u; FP32 values read
@@ -243,24 +289,27 @@ class OracleScene:
         return out.reshape(16, 8)
 
     def check_path(self, cams, settings, cam: int, local: int, sample: int, nv: int, vi: np.ndarray,
-                   vf: np.ndarray, escaped: bool, radiance: float):
+                   vf: np.ndarray, escaped: bool, radiance):
         """Check a GPU path record (rtq_render_path: vi 6 int32 and vf 10 float32 per
         recorded ray, the escaping ray last) step by step along its own rays.
         Returns (code, stats): code 0 = valid, else PATH_CODES[code]; stats: failing
         ray, FP64 radiance along the path, vertices, certain answers, vertices
         whose t is ill-conditioned (held to the FP32 bound), shading decisions
         within rounding of a threshold, largest t error in units of
-        2^-24 S / (|d| |cos|)."""
+        2^-24 S / (|d| |cos|), and the FP64 radiance of every channel ("Lc").
+        radiance: the GPU's value (a float, or 3 with materials)."""
         cf, ci, _ = self._cams(cams)
         pi, pu, pd = self._params(settings)
         vi = np.ascontiguousarray(vi, dtype=np.int32)
         vf = np.ascontiguousarray(vf, dtype=np.float32)
-        st = np.zeros(7)
+        st = np.zeros(10)
+        rad = np.zeros(3, np.float32)
+        rad[:] = np.asarray(radiance, dtype=np.float32).ravel()  # a scalar fills all three channels
         code = lib().orc_check_path(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), int(cam), int(local),
-                                    int(sample), int(nv), _p(vi), _p(vf), 1 if escaped else 0, float(radiance),
-                                    _p(st))
+                                    int(sample), int(nv), _p(vi), _p(vf), 1 if escaped else 0, _p(rad), _p(st))
         return int(code), dict(ray=int(st[0]), L=float(st[1]), vertices=int(st[2]), certain=int(st[3]),
-                               t_waived=int(st[4]), ambiguous_shading=int(st[5]), max_t_ulps=float(st[6]))
+                               t_waived=int(st[4]), ambiguous_shading=int(st[5]), max_t_ulps=float(st[6]),
+                               Lc=st[7:10].copy())
 
     @staticmethod
     def _params(settings):
@@ -287,18 +336,19 @@ class OracleScene:
         return np.ascontiguousarray(cf), np.array(ci, dtype=np.int64).reshape(-1, 8), off
 
     def render(self, cams, settings, pixels: Optional[np.ndarray] = None, brute: bool = False):
-        """Returns (image or per-listed-pixel radiance [f64], pixel flags [u8], stats dict)."""
+        """Returns (image or per-listed-pixel radiance [f64]: [n] without materials,
+        [n, 3] with them; pixel flags [u8]; stats dict)."""
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
         n = total if px is None else px.shape[0]
-        img = np.zeros(n)
+        img = np.zeros((n, 3))
         fl = np.zeros(n, np.uint8)
         st = np.zeros(4)
         lib().orc_render(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px),
                          0 if px is None else n, 0 if brute else 1, _p(img), _p(fl), _p(st))
         stats = dict(closest=st[0], shadow=st[1], incoherent=st[2], flagged_pixels=st[3])
-        return img, fl, stats
+        return (img if self.rgb else img[:, 0].copy()), fl, stats
 
     def grad(self, cams, settings, gpix: np.ndarray, pixels: Optional[np.ndarray] = None, brute: bool = False,
              taint: str = "pixel"):
@@ -311,8 +361,7 @@ class OracleScene:
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
         n = total if px is None else px.shape[0]
-        g = np.ascontiguousarray(gpix, dtype=np.float64)
-        assert g.shape == (n,)
+        g = self._gpix(gpix, n)
         out = np.zeros(self.n_params)
         fl = np.zeros(n, np.uint8)
         tmask = np.zeros(self.n_params, np.uint8)
@@ -330,11 +379,24 @@ class OracleScene:
         n = total if px is None else px.shape[0]
         tg = np.ascontiguousarray(tangent, dtype=np.float64)
         assert tg.shape == (self.n_params,)
-        dI = np.zeros(n)
+        dI = np.zeros((n, 3))
         fl = np.zeros(n, np.uint8)
         lib().orc_grad(self.h, _p(cf), _p(ci), len(cams), _p(pi), _p(pu), _p(pd), _p(px), 0 if px is None else n,
                        1, None, 1, _p(tg), None, _p(dI), _p(fl), None, 0)
-        return dI, fl
+        return (dI if self.rgb else dI[:, 0].copy()), fl
+
+    def _gpix(self, gpix, n):
+        """Pixel weights as [n, 3]: [n] weights (no materials) go to channel 0
+        (the three channels are equal there), [n, 3] with materials."""
+        g = np.asarray(gpix, dtype=np.float64)
+        out = np.zeros((n, 3))
+        if self.rgb:
+            assert g.shape == (n, 3)
+            out[:] = g
+        else:
+            assert g.shape == (n,)
+            out[:, 0] = g
+        return np.ascontiguousarray(out)
 
     def path(self, cams, settings, pixel: int, sample: int):
         """The vertices of one path: list of dicts (inst, prim, half, t, albedo,

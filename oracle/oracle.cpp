@@ -1,4 +1,5 @@
-// FP64 CPU oracle for instanced-quad closest-hit tracing and Lambertian path tracing.
+// FP64 CPU oracle for instanced-quad closest-hit tracing and path tracing
+// (Lambertian faces, or principled materials with RGB shading).
 //
 // TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
 // baseline leg of the benchmark may load this library.  It shares no code,
@@ -24,8 +25,11 @@
 //    path loop with next-event estimation toward one directional light and a
 //    constant sky.  Progressive 1 spp frames follow Section 5.4; the per-sample
 //    average over spp is taken in sample order.
+//  * Principled materials (Section 5.4, energy conserving and preserving; the
+//    BSDF is written out where it is defined): RGB path values.
 //  * Gradient of the image with respect to per-face albedo with every path held
-//    fixed: path-replay form (sum over vertices of S_k / a_k) and, independently,
+//    fixed: path-replay form (each vertex's affine estimate and bounce weight,
+//    with the radiance arriving along its bounce) and, independently,
 //    forward-mode dual numbers.
 #include <algorithm>
 #include <atomic>
@@ -67,6 +71,16 @@ enum : uint32_t {
 };
 
 // ---------------------------------------------------------------- scene
+// A principled material (Section 5.4: the scene's materials all use Disney's
+// principled BSDF, made energy conserving and preserving).  Base color
+// c = tint x (the face's albedo or texel), per channel; alpha = roughness^2
+// (GGX); metal in [0, 1]; spec in [0, 1] scales the dielectric Fresnel
+// reflectance (Schlick, F0 = 0.04).
+struct Material {
+  double tint[3];
+  double alpha, metal, spec;
+};
+
 struct Box {
   double lo[3] = {kInf, kInf, kInf};
   double hi[3] = {-kInf, -kInf, -kInf};
@@ -156,6 +170,10 @@ struct Scene {
   // its importance-sampling table: texel k (row-major) is drawn with
   // probability (env_T[k] - env_T[k - 1]) / 2^32 (see env_table)
   std::vector<uint64_t> env_T;
+  // optional principled materials (RGB shading): a table and one entry per face;
+  // without them every face is Lambertian with its scalar albedo
+  std::vector<Material> mats;
+  std::vector<int32_t> face_mat;
   int64_t N = 0;
   std::vector<int32_t> iproto;
   std::vector<double> X;           // 12 per instance: row-major [A | t] (FP32 values)
@@ -755,12 +773,170 @@ Cam make_cam(const double* cf, const int64_t* ci) {
   return c;
 }
 
+// ---------------------------------------------------------------- principled BSDF
+// RGB triple (the three channels shade independently along one path).
+struct C3 {
+  double v[3] = {0.0, 0.0, 0.0};
+};
+inline C3 c3(double x) {
+  C3 r;
+  r.v[0] = r.v[1] = r.v[2] = x;
+  return r;
+}
+inline C3 operator+(C3 a, C3 b) {
+  for (int k = 0; k < 3; ++k) a.v[k] += b.v[k];
+  return a;
+}
+inline C3 operator*(C3 a, C3 b) {
+  for (int k = 0; k < 3; ++k) a.v[k] *= b.v[k];
+  return a;
+}
+inline C3 operator*(double s, C3 a) {
+  for (int k = 0; k < 3; ++k) a.v[k] *= s;
+  return a;
+}
+
+// The BSDF (a reading of Section 5.4; the paper gives no formulas).  At a vertex
+// with unit normal n on the viewer's side and unit direction wo to the viewer,
+// mu_o = n . wo, the cosine-weighted BSDF toward wi (mu_i = n . wi > 0) is
+//   f mu_i = (1 - m) [F_d p_s(wi) + (1 - F_d) c mu_i / pi] + m F_c p_s(wi)
+// with F_d = spec (F0 + (1 - F0)(1 - mu_o)^5), F0 = 0.04, the dielectric
+// Fresnel weight, and F_c = c + (1 - c)(1 - mu_o)^5 the metal's (Schlick, both at
+// the macro-surface angle).  p_s is the density of the specular lobe: a GGX
+// visible normal h is drawn (Heitz 2018; alpha = roughness^2, separable Smith
+// masking), wo is reflected about it, and a reflection below the surface is
+// mirrored above it (w - 2 (n . w) n), so p_s integrates to one over the upper
+// hemisphere: the energy a single-scattering lobe loses below the horizon is
+// returned in closed form.  Hence the albedo of the BSDF at wo is
+// (1 - m)[F_d + (1 - F_d) c] + m F_c: at most one (energy conserving) and exactly
+// one for c = 1 (energy preserving).  With m = spec = 0 it is Lambert's c / pi.
+// The specular lobe is drawn with probability P_s = (1 - m) F_d + m (it does not
+// depend on c, so a path's directions do not depend on the albedo), the cosine
+// lobe otherwise; the weight of a sampled direction is f mu_i / pdf with
+// pdf = P_s p_s + (1 - P_s) mu_i / pi.  f mu_i = A + B c is affine in c.
+struct Shade {
+  V3 n, wo, t1, t2;  // frame: t1, t2 the basis of Duff et al. 2017 about n
+  double mo;         // n . wo
+  double alpha, metal, Fd, k5, Ps;
+  C3 tint;
+};
+
+inline double ggx_D(double a, double nh) {
+  const double a2 = a * a, q = nh * nh * (a2 - 1.0) + 1.0;
+  return a2 / (kPi * q * q);
+}
+inline double smith_G1(double a, double mu) { return 2.0 * mu / (mu + std::sqrt(a * a + (1.0 - a * a) * mu * mu)); }
+
+// basis (t1, t2, n) of Duff et al. 2017; `flip` takes the other sign branch
+void duff_basis(V3 n, bool flip, V3* t1, V3* t2) {
+  double sg = n.z >= 0 ? 1.0 : -1.0;
+  if (flip) sg = -sg;
+  const double aa = -1.0 / (sg + n.z);
+  const double bb = n.x * n.y * aa;
+  *t1 = V3{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
+  *t2 = V3{bb, sg + n.y * n.y * aa, -n.y};
+}
+
+Shade make_shade(const Material& M, V3 n, V3 wo, bool flip) {
+  Shade s;
+  s.n = n;
+  s.wo = wo;
+  duff_basis(n, flip, &s.t1, &s.t2);
+  s.mo = dot(n, wo);
+  const double om = std::max(0.0, 1.0 - s.mo);
+  s.k5 = om * om * om * om * om;
+  s.alpha = M.alpha;
+  s.metal = M.metal;
+  s.Fd = M.spec * (0.04 + 0.96 * s.k5);
+  s.Ps = (1.0 - M.metal) * s.Fd + M.metal;
+  for (int k = 0; k < 3; ++k) s.tint.v[k] = M.tint[k];
+  return s;
+}
+
+// density of the folded specular lobe toward wi (mu_i > 0): each preimage
+// direction (the reflection itself and, when mu_o > mu_i, its mirror below the
+// surface) contributes G1(mu_o) D(h) / (4 mu_o), h the half vector
+double spec_pdf(const Shade& s, V3 wi) {
+  const double mi = dot(s.n, wi);
+  if (!(mi > 0.0) || !(s.mo > 0.0)) return 0.0;
+  const double g = smith_G1(s.alpha, s.mo) / (4.0 * s.mo);
+  const V3 h1 = normalize(s.wo + wi);
+  double p = g * ggx_D(s.alpha, dot(s.n, h1));
+  if (s.mo > mi) {
+    const V3 h2 = normalize(s.wo + (wi - 2.0 * mi * s.n));
+    p += g * ggx_D(s.alpha, dot(s.n, h2));
+  }
+  return p;
+}
+
+// f mu_i = A + B c toward wi; returns false (and zeros) below the surface
+bool eval_AB(const Shade& s, V3 wi, double* A, double* B) {
+  const double mi = dot(s.n, wi);
+  *A = *B = 0.0;
+  if (!(mi > 0.0)) return false;
+  const double ps = s.Ps > 0.0 ? spec_pdf(s, wi) : 0.0;
+  *A = ((1.0 - s.metal) * s.Fd + s.metal * s.k5) * ps;
+  *B = (1.0 - s.metal) * (1.0 - s.Fd) * mi / kPi + s.metal * (1.0 - s.k5) * ps;
+  return true;
+}
+
+double bsdf_pdf(const Shade& s, V3 wi) {
+  const double mi = dot(s.n, wi);
+  if (!(mi > 0.0)) return 0.0;
+  return (s.Ps > 0.0 ? s.Ps * spec_pdf(s, wi) : 0.0) + (1.0 - s.Ps) * mi / kPi;
+}
+
+// A GGX visible normal for wo from (u1, u2) (Heitz 2018, "Sampling the GGX
+// distribution of visible normals"), in the world frame of s.
+V3 sample_vndf(const Shade& s, double u1, double u2) {
+  const double ox = dot(s.wo, s.t1), oy = dot(s.wo, s.t2), oz = s.mo;
+  // stretch to the hemisphere configuration
+  const V3 vh = normalize(V3{s.alpha * ox, s.alpha * oy, oz});
+  const double l2 = vh.x * vh.x + vh.y * vh.y;
+  const V3 T1 = l2 > 0.0 ? (1.0 / std::sqrt(l2)) * V3{-vh.y, vh.x, 0.0} : V3{1.0, 0.0, 0.0};
+  const V3 T2 = cross(vh, T1);
+  const double r = std::sqrt(u1), phi = 2.0 * kPi * u2;
+  const double p1 = r * std::cos(phi);
+  double p2 = r * std::sin(phi);
+  const double sw = 0.5 * (1.0 + vh.z);
+  p2 = (1.0 - sw) * std::sqrt(std::max(0.0, 1.0 - p1 * p1)) + sw * p2;
+  const V3 nh = p1 * T1 + p2 * T2 + std::sqrt(std::max(0.0, 1.0 - p1 * p1 - p2 * p2)) * vh;
+  // unstretch
+  const V3 hl = normalize(V3{s.alpha * nh.x, s.alpha * nh.y, std::max(0.0, nh.z)});
+  return hl.x * s.t1 + hl.y * s.t2 + hl.z * s.n;
+}
+
+// Direction of the bounce from the lobe word u0 and (u1, u2): the specular
+// lobe when u0 < P_s (reflection about a visible normal, mirrored above the
+// surface when below it), else the cosine lobe.  *ambiguous is set when u0 lies
+// within 1e-6 of P_s (FP32 may choose the other lobe).
+V3 sample_bsdf(const Shade& s, double u0, double u1, double u2, bool* spec, bool* ambiguous) {
+  *spec = u0 < s.Ps;
+  if (ambiguous) *ambiguous = s.Ps > 0.0 && std::fabs(u0 - s.Ps) < 1e-6;
+  if (*spec) {
+    const V3 h = sample_vndf(s, u1, u2);
+    V3 wi = 2.0 * dot(s.wo, h) * h - s.wo;
+    const double mi = dot(s.n, wi);
+    if (mi < 0.0) wi = wi - 2.0 * mi * s.n;
+    return wi;
+  }
+  const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
+  return (rr * std::cos(phi)) * s.t1 + (rr * std::sin(phi)) * s.t2 + std::sqrt(1.0 - u1) * s.n;
+}
+
+// The material of a face (the Lambertian default without a table).
+Material face_material(const Scene& S, int64_t face) {
+  if (S.mats.empty()) return Material{{1.0, 1.0, 1.0}, 1.0, 0.0, 0.0};
+  return S.mats[S.face_mat[face]];
+}
+
 // One sampled path, recorded vertex by vertex (for the image and both gradient forms).
 struct Vertex {
   int64_t face;
   int64_t param;  // index of the shading parameter: the face, or its texel when the scene has textures
-  double a;      // albedo at the vertex
-  double c;      // (E / pi) * cos_L * visibility: the NEE factor without beta and albedo
+  double a;      // albedo (texel) at the vertex: the base color is the material's tint times a
+  C3 e, e1;      // next-event estimate at the vertex (visibility included) and its derivative in a
+  C3 w, w1;      // weight f mu / pdf of the bounce leaving the vertex and its derivative in a (0: none)
   int32_t inst, prim, half;  // the hit
   double t;
   uint32_t flags, shadow_flags;
@@ -861,7 +1037,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
   Ray ray{cam.eye, normalize(cam.f + sx * cam.r + sy * cam.u), 0.0, kInf};
   Excl ex;
   double r0 = 0.0;
-  double pdf_bsdf = 0.0;  // density of the cosine sample that produced the current ray (bounce >= 1)
+  double pdf_bsdf = 0.0;  // BSDF density of the sample that produced the current ray (bounce >= 1)
   const bool env_light = P.env_nee && S.env_w > 0;
   const int nl = 1 + P.n_area + (env_light ? 1 : 0);
   for (int b = 0; b < P.depth; ++b) {
@@ -912,7 +1088,22 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       param = ((int64_t)face * R + ty) * R + tx;
       a = S.tex[(size_t)param];
     }
-    Vertex vx{face, param, a, 0.0, -1, -1, -1, 0.0, 0u, 0u, -1};
+    Vertex vx;
+    vx.face = face;
+    vx.param = param;
+    vx.a = a;
+    const Material M = face_material(S, face);
+    const Shade sh = make_shade(M, n, -1.0 * normalize(ray.d), false);
+    // next-event estimate e = X (A + B c) toward the light direction, X the
+    // light's factor (nl, radiance, geometry, density, MIS weight)
+    auto set_nee = [&](V3 wl_dir, double X) {
+      double A, B;
+      eval_AB(sh, wl_dir, &A, &B);
+      for (int ch = 0; ch < 3; ++ch) {
+        vx.e.v[ch] = X * (A + B * sh.tint.v[ch] * a);
+        vx.e1.v[ch] = X * B * sh.tint.v[ch];
+      }
+    };
     const double cl = dot(n, L);
     // next-event estimation (Section 4.1 names the scene's quad-shaped key
     // lights and its environment light): with area lights or a sampled
@@ -947,7 +1138,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
       vx.shadow = o.best.inst >= 0 ? 1 : 0;
       vx.shadow_flags = o.flags;
-      if (o.best.inst < 0) vx.c = nl * (P.E / kPi * cl);
+      if (o.best.inst < 0) set_nee(L, nl * P.E);
     } else if (env_light && j == nl - 1) {
       // the environment: texel k from word 1 (the first k with w1 < T_k), a
       // direction uniform in solid angle within it from words 2, 3; estimate
@@ -976,7 +1167,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
         vx.shadow = o.best.inst >= 0 ? 1 : 0;
         vx.shadow_flags = o.flags;
         const double pdf = env_pdf(S, lo);
-        if (o.best.inst < 0) vx.c = nl * (S.env[lo] * cp * mis_power(pdf / nl, cp / kPi) / (kPi * pdf));
+        if (o.best.inst < 0) set_nee(de, nl * S.env[lo] * mis_power(pdf / nl, bsdf_pdf(sh, de)) / pdf);
       }
     } else if (j > 0) {
       // area light j - 1: the parallelogram c + s e1 + t e2, (s, t) uniform from
@@ -1000,7 +1191,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
         rec.flags |= o.flags & ~(uint32_t)F_T_ILLCOND;
         vx.shadow = o.best.inst >= 0 ? 1 : 0;
         vx.shadow_flags = o.flags;
-        if (o.best.inst < 0) vx.c = nl * (Lq[9] * A * cp * cq / (kPi * d2));
+        if (o.best.inst < 0) set_nee((1.0 / dd) * wi, nl * Lq[9] * A * cq / d2);
       }
     }
     vx.flags |= vshade;
@@ -1014,28 +1205,44 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       rec.flags |= F_SHADE;
       rec.v[rec.nv - 1].flags |= F_SHADE;
     }
-    const double sg = n.z >= 0 ? 1.0 : -1.0;
-    const double aa = -1.0 / (sg + n.z);
-    const double bb = n.x * n.y * aa;
-    const V3 t1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
-    const V3 t2{bb, sg + n.y * n.y * aa, -n.y};
-    const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
-    const V3 dnew = (rr * std::cos(phi)) * t1 + (rr * std::sin(phi)) * t2 + std::sqrt(1.0 - u1) * n;
-    pdf_bsdf = std::sqrt(1.0 - u1) / kPi;
+    // the lobe: word 0 of counter (pixel, sample, view, 2^30 + b), drawn only
+    // when the specular lobe has weight
+    double u0 = 1.0;
+    if (sh.Ps > 0.0) {
+      uint32_t ctr4[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x40000000u | (uint32_t)b};
+      uint32_t wlob[4];
+      philox(ctr4, key, wlob);
+      u0 = unit(wlob[0]);
+    }
+    bool spec = false, amb = false;
+    const V3 dnew = sample_bsdf(sh, u0, u1, u2, &spec, &amb);
+    if (amb) {
+      rec.flags |= F_SHADE;
+      rec.v[rec.nv - 1].flags |= F_SHADE;
+    }
+    double A, B;
+    if (!eval_AB(sh, dnew, &A, &B)) return;  // a direction on the surface (measure zero): the path ends
+    pdf_bsdf = bsdf_pdf(sh, dnew);
+    for (int ch = 0; ch < 3; ++ch) {
+      rec.v[rec.nv - 1].w.v[ch] = (A + B * sh.tint.v[ch] * a) / pdf_bsdf;
+      rec.v[rec.nv - 1].w1.v[ch] = B * sh.tint.v[ch] / pdf_bsdf;
+    }
     ray = Ray{p, dnew, 0.0, kInf};
     ex = here;
     r0 = r1;
   }
 }
 
-// Radiance of a recorded path, in the order the terms arise.
-double path_value(const Params& P, const PathRec& rec) {
-  double L = 0.0, beta = 1.0;
+// Radiance of a recorded path, in the order the terms arise:
+// L = sum_k T_k e_k (+ T_n L_esc), T_0 = 1, T_{k+1} = T_k w_k.
+C3 path_value(const Params& P, const PathRec& rec) {
+  (void)P;
+  C3 L, T = c3(1.0);
   for (int k = 0; k < rec.nv; ++k) {
-    L += beta * rec.v[k].a * rec.v[k].c;
-    beta *= rec.v[k].a;
+    L = L + T * rec.v[k].e;
+    T = T * rec.v[k].w;
   }
-  if (rec.escaped) L += beta * rec.L_esc;
+  if (rec.escaped) L = L + rec.L_esc * T;
   return L;
 }
 
@@ -1057,25 +1264,13 @@ double path_value(const Params& P, const PathRec& rec) {
 struct PathCheck {
   int code = 0;     // 0 valid; otherwise the first failed check (see orc_check_path)
   int vertex = -1;  // the vertex (or ray) where it failed
-  double L = 0.0;   // FP64 radiance along the GPU's decisions
+  double L = 0.0;   // FP64 radiance along the GPU's decisions (channel 0)
+  double Lc[3] = {0.0, 0.0, 0.0};  // all three channels
   int n_vert = 0, n_certain = 0, n_waived = 0, n_ambiguous_shading = 0;  // n_waived: t ill-conditioned
   double max_ulps = 0.0;  // largest t error in units of 2^-24 S / (|d| |cos|)
 };
 
 inline float f32(double x) { return (float)x; }
-
-// Cosine sample about the unit normal n with words (u1, u2), in the basis of
-// Duff et al. 2017; `flip` uses the other branch of the sign choice (n_z ~ 0).
-V3 cosine_sample(V3 n, double u1, double u2, bool flip) {
-  double sg = n.z >= 0 ? 1.0 : -1.0;
-  if (flip) sg = -sg;
-  const double aa = -1.0 / (sg + n.z);
-  const double bb = n.x * n.y * aa;
-  const V3 t1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
-  const V3 t2{bb, sg + n.y * n.y * aa, -n.y};
-  const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
-  return (rr * std::cos(phi)) * t1 + (rr * std::sin(phi)) * t2 + std::sqrt(1.0 - u1) * n;
-}
 
 // Environment texels a direction may read: the exact one, and its neighbours
 // across a texel boundary within rounding (angular distance times sin(theta)
@@ -1118,7 +1313,7 @@ int env_candidates(const Scene& S, V3 d, double out[9], int64_t idx[9]) {
 // when the path escaped, ray nv is the escaping ray (its words are ignored but
 // origin and direction).
 PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, int64_t pix, int32_t sample,
-                     int nv, const int32_t* vi, const float* vf, bool escaped, float radiance, int mode) {
+                     int nv, const int32_t* vi, const float* vf, bool escaped, const float* radiance, int mode) {
   PathCheck R;
   auto fail = [&](int code, int k) {
     if (R.code == 0) {
@@ -1151,9 +1346,9 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     if (norm(r0.d - d) > 1e-5) return fail(1, 0);
   }
   Excl ex;
-  double beta = 1.0;
-  double Lsum = 0.0;
-  double pdf_bsdf = 0.0;  // density of the cosine sample behind the current ray
+  C3 T = c3(1.0);
+  C3 Lsum;
+  double pdf_bsdf = 0.0;  // BSDF density of the sample behind the current ray
   const bool env_light = P.env_nee && S.env_w > 0;
   const int nl = 1 + P.n_area + (env_light ? 1 : 0);
   std::vector<double> esc_vals;
@@ -1260,6 +1455,8 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     } else if (f32(a) != F[1]) {
       return fail(6, k);
     }
+    const Material M = face_material(S, face);
+    const Shade sh = make_shade(M, n, -1.0 * dh, false);
     // next-event estimate
     int j = 0;
     uint32_t wl[4] = {0u, 0u, 0u, 0u};
@@ -1269,15 +1466,15 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       j = (int)(((uint64_t)(wl[0] >> 8) * (uint64_t)nl) >> 24);
     }
     const Excl here{inst, prim, half};
-    double c = 0.0;
     bool want_certain = false, skip_certain = false;
     Ray sr{pg, Lf, 0.0, kInf};
-    double cval = 0.0;
+    V3 ldir = L;     // unit direction of the light sample
+    double X = 0.0;  // the light's factor of the estimate X (A + B c)
     if (j == 0) {
       const double cl = dot(n, L);
       want_certain = cl > 1e-6;
       skip_certain = cl < -1e-6;
-      cval = nl * (P.E / kPi * cl);
+      X = nl * P.E;
     } else if (env_light && j == nl - 1) {
       const int64_t nt = (int64_t)S.env_w * S.env_h;
       int64_t lo = 0, hi = nt - 1;
@@ -1296,7 +1493,8 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       want_certain = cp > 1e-6;
       skip_certain = cp < -1e-6;
       const double pdf = env_pdf(S, lo);
-      cval = nl * (S.env[lo] * cp * mis_power(pdf / nl, cp / kPi) / (kPi * pdf));
+      X = nl * S.env[lo] * mis_power(pdf / nl, bsdf_pdf(sh, de)) / pdf;
+      ldir = de;
       sr = Ray{pg, de, 0.0, kInf};
     } else {
       const double* Lq = P.area + 10 * (j - 1);
@@ -1309,7 +1507,8 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       const double cp = dot(n, wi) / dd, cq = -dot(nlv, wi) / (Ar * dd);
       want_certain = cp > 1e-6 && cq > 1e-6;
       skip_certain = cp < -1e-6 || cq < -1e-6;
-      cval = nl * (Lq[9] * Ar * cp * cq / (kPi * d2));
+      X = nl * Lq[9] * Ar * cq / d2;
+      ldir = (1.0 / dd) * wi;
       sr = Ray{pg, wi, 0.0, 1.0};
     }
     if (!want_certain && !skip_certain) R.n_ambiguous_shading++;
@@ -1318,9 +1517,14 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     if (shadow >= 0) {
       const AcceptSet As = accept_set(S, sr, here, 0.0, mode);
       if (judge_any(As, shadow == 1)) return fail(8, k);
-      if (shadow == 0) c = cval;
+      if (shadow == 0) {
+        double fa, fb;
+        eval_AB(sh, ldir, &fa, &fb);
+        C3 e;
+        for (int ch = 0; ch < 3; ++ch) e.v[ch] = X * (fa + fb * sh.tint.v[ch] * a);
+        Lsum = Lsum + T * e;
+      }
     }
-    Lsum += beta * a * c;
     if (!has_next) break;
     // the next ray: from the FP32 hit point along the cosine sample
     const Ray nr = ray_of(k + 1);
@@ -1328,31 +1532,60 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     uint32_t w2[4];
     uint32_t ctr2[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, (uint32_t)k};
     philox(ctr2, key, w2);
-    const V3 de = cosine_sample(n, unit(w2[2]), unit(w2[3]), false);
-    double err = norm(nr.d - de);
+    double u0 = 1.0;
+    if (sh.Ps > 0.0) {
+      uint32_t ctr4[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x40000000u | (uint32_t)k};
+      uint32_t wlob[4];
+      philox(ctr4, key, wlob);
+      u0 = unit(wlob[0]);
+    }
+    // the sampled direction, for either lobe when the lobe word lies within
+    // rounding of P_s, and for either basis branch when n_z ~ 0
+    bool spec, amb;
+    double err = norm(nr.d - sample_bsdf(sh, u0, unit(w2[2]), unit(w2[3]), &spec, &amb));
+    if (amb) {
+      R.n_ambiguous_shading++;
+      err = std::min(err, norm(nr.d - sample_bsdf(sh, spec ? 1.0 : 0.0, unit(w2[2]), unit(w2[3]), &spec, nullptr)));
+    }
     if (std::fabs(n.z) < 1e-6) {
       R.n_ambiguous_shading++;
-      err = std::min(err, norm(nr.d - cosine_sample(n, unit(w2[2]), unit(w2[3]), true)));
+      const Shade sf = make_shade(M, n, -1.0 * dh, true);
+      err = std::min(err, norm(nr.d - sample_bsdf(sf, u0, unit(w2[2]), unit(w2[3]), &spec, nullptr)));
     }
     if (err > 1e-5) return fail(10, k + 1);
-    pdf_bsdf = std::sqrt(1.0 - unit(w2[2])) / kPi;
-    beta *= a;
+    // the weight of the GPU's direction, in FP64
+    const V3 dn = normalize(nr.d);
+    double fa, fb;
+    if (!eval_AB(sh, dn, &fa, &fb)) return fail(10, k + 1);
+    pdf_bsdf = bsdf_pdf(sh, dn);
+    C3 wgt;
+    for (int ch = 0; ch < 3; ++ch) wgt.v[ch] = (fa + fb * sh.tint.v[ch] * a) / pdf_bsdf;
+    T = T * wgt;
     ex = here;
   }
   // radiance: the FP64 value along these decisions, for each environment
   // texel the escaping ray may read
   if (esc_vals.empty()) esc_vals.push_back(0.0);
-  double best = kInf, Lbest = 0.0;
+  double best = kInf, Lbest = 0.0, scale = 0.0;
+  C3 Lb;
   for (double e : esc_vals) {
-    const double Lv = Lsum + (escaped ? beta * e : 0.0);
-    const double err = std::fabs((double)radiance - Lv);
+    const C3 Lv = escaped ? Lsum + e * T : Lsum;
+    double err = 0.0, mx = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      err = std::max(err, std::fabs((double)radiance[ch] - Lv.v[ch]));
+      mx = std::max(mx, std::fabs(Lv.v[ch]));
+    }
     if (err < best) {
       best = err;
-      Lbest = Lv;
+      Lb = Lv;
+      scale = mx;
     }
   }
-  R.L = Lbest;
-  if (best > 1e-4 * std::fabs(Lbest) + 1e-7) return fail(12, nv);
+  for (int ch = 0; ch < 3; ++ch) R.Lc[ch] = Lb.v[ch];
+  R.L = Lb.v[0];
+  (void)Lbest;
+  // every channel within 1e-4 of the largest one
+  if (best > 1e-4 * scale + 1e-7) return fail(12, nv);
   return R;
 }
 
@@ -1470,6 +1703,58 @@ void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads
 }
 
 void orc_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
+
+// The BSDF at one shading frame, for tests: material m (tint r, g, b,
+// roughness, metallic, specular), unit normal n, unit direction to the viewer
+// wo.  For each of n directions wi (n x 3) writes (A, B, pdf, P_s): f mu_i =
+// A + B c, the sampling density and the specular lobe's probability.
+void orc_bsdf_eval(const double* m, const double* nrm, const double* wo, int64_t n, const double* wi, double* out) {
+  const Material M{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5]};
+  const Shade sh = make_shade(M, V3{nrm[0], nrm[1], nrm[2]}, V3{wo[0], wo[1], wo[2]}, false);
+  for (int64_t i = 0; i < n; ++i) {
+    const V3 w{wi[3 * i], wi[3 * i + 1], wi[3 * i + 2]};
+    eval_AB(sh, w, &out[4 * i], &out[4 * i + 1]);
+    out[4 * i + 2] = bsdf_pdf(sh, w);
+    out[4 * i + 3] = sh.Ps;
+  }
+}
+
+// Sampled bounce directions for (u0, u1, u2) triples (n x 3): writes the
+// direction (n x 3) and, per sample, (specular lobe chosen, lobe word within
+// rounding of P_s).
+void orc_bsdf_sample(const double* m, const double* nrm, const double* wo, int64_t n, const double* u, double* wi,
+                     int32_t* info) {
+  const Material M{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5]};
+  const Shade sh = make_shade(M, V3{nrm[0], nrm[1], nrm[2]}, V3{wo[0], wo[1], wo[2]}, false);
+  for (int64_t i = 0; i < n; ++i) {
+    bool spec, amb;
+    const V3 d = sample_bsdf(sh, u[3 * i], u[3 * i + 1], u[3 * i + 2], &spec, &amb);
+    wi[3 * i] = d.x;
+    wi[3 * i + 1] = d.y;
+    wi[3 * i + 2] = d.z;
+    info[2 * i] = spec ? 1 : 0;
+    info[2 * i + 1] = amb ? 1 : 0;
+  }
+}
+
+// Principled materials (Section 5.4): n_mat entries of (tint r, g, b,
+// roughness, metallic, specular) and one material index per unique quad; n_mat = 0
+// removes them (every face Lambertian again).  Returns -1 on a bad argument.
+int orc_scene_set_materials(void* s, const double* mats, int32_t n_mat, const int32_t* face_mat) {
+  Scene* S = static_cast<Scene*>(s);
+  if (n_mat < 0 || (n_mat > 0 && (!mats || !face_mat))) return -1;
+  S->mats.clear();
+  S->face_mat.clear();
+  if (n_mat == 0) return 0;
+  for (int32_t k = 0; k < n_mat; ++k) {
+    const double* m = mats + 6 * k;
+    S->mats.push_back(Material{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5]});
+  }
+  S->face_mat.assign(face_mat, face_mat + S->albedo.size());
+  for (int32_t f : S->face_mat)
+    if (f < 0 || f >= n_mat) return -1;
+  return 0;
+}
 
 int orc_scene_set_albedo(void* s, const double* albedo) {
   Scene* S = static_cast<Scene*>(s);
@@ -1641,7 +1926,7 @@ void orc_flag_breakdown(void* s, const double* cam_f, const int64_t* cam_i, int3
 // t error in units of 2^-24 S / (|d| |cos|)].
 int32_t orc_check_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
                        const uint64_t* pu, const double* pd, int32_t cam, int64_t local, int32_t sample, int32_t nv,
-                       const int32_t* vi, const float* vf, int32_t escaped, float radiance, double* stats) {
+                       const int32_t* vi, const float* vf, int32_t escaped, const float* radiance, double* stats) {
   const Scene& S = *static_cast<Scene*>(s);
   const Params P = make_params(pi, pu, pd);
   if (cam < 0 || cam >= n_cams) return -1;
@@ -1657,12 +1942,14 @@ int32_t orc_check_path(void* s, const double* cam_f, const int64_t* cam_i, int32
     stats[4] = R.n_waived;
     stats[5] = R.n_ambiguous_shading;
     stats[6] = R.max_ulps;
+    for (int ch = 0; ch < 3; ++ch) stats[7 + ch] = R.Lc[ch];
   }
   return R.code;
 }
 
-// Image (or listed pixels) of n_cams pinhole cameras.  cam_f: n x 10 (eye, look,
-// up, vfov); cam_i: n x 3 (w, h, offset of the view in the packed image).
+// Image (or listed pixels) of n_cams pinhole cameras, 3 channels per pixel
+// (equal without materials).  cam_f: n x 10 (eye, look, up, vfov); cam_i: n x 8
+// (w, h, offset of the view in the packed image, view id, tile).
 // pix: global packed pixel indices, or NULL for every pixel.  stats (may be NULL):
 // [closest rays, shadow rays, incoherent (bounce >= 1) rays, flagged pixels].
 void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
@@ -1684,18 +1971,18 @@ void orc_render(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_ca
     int32_t view;
     int64_t p;
     resolve_pixel(cams, g, &view, &p);
-    double sum = 0.0;
+    C3 sum;
     uint32_t fl = 0;
     for (int32_t smp = 0; smp < P.spp; ++smp) {
       PathRec rec;
       trace_path(S, P, cams[view], (int32_t)cams[view].view_id, p, smp, mode, rec);
-      sum += path_value(P, rec);
+      sum = sum + path_value(P, rec);
       fl |= rec.flags;
       st[4 * tid + 0] += rec.n_closest;
       st[4 * tid + 1] += rec.n_shadow;
       st[4 * tid + 2] += rec.n_incoherent;
     }
-    image[i] = sum / P.spp;
+    for (int ch = 0; ch < 3; ++ch) image[3 * i + ch] = sum.v[ch] / P.spp;
     pflags[i] = (uint8_t)(fl != 0);
     st[4 * tid + 3] += fl != 0;
   });
@@ -1733,11 +2020,15 @@ void orc_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
   *path_flags = rec.flags;
 }
 
-// Gradient of sum_p g_p * I_p with respect to per-face albedo, paths held fixed.
-// mode 0: path replay, dI/da_f = (1/spp) sum_s sum_{k: f_k = f} S_k / a_k with
-//         S_k = sum_{j >= k} D_j + M (contributions from vertex k onward).
-// mode 1: forward-mode dual numbers along `tangent` (per face); writes the
-//         directional derivative of each listed pixel into dI (grad_albedo unused).
+// Gradient of sum_p g_p . I_p (RGB: g_p has 3 weights per pixel) with respect to
+// the per-face albedo (or texel) a, paths held fixed.  Every vertex's estimate
+// e_k and bounce weight w_k are affine in its own a (the base color is the
+// material's tint times a), with derivatives e1_k, w1_k.
+// mode 0: path replay, dI/da_j = (1/spp) sum over vertices k with parameter j
+//         of T_k (e1_k + w1_k R_k), R_k = sum_{i>k} (w_{k+1} .. w_{i-1}) e_i
+//         (+ the escape term) the radiance arriving along the bounce of k.
+// mode 1: forward-mode dual numbers along `tangent` (per parameter); writes the
+//         directional derivative of each listed pixel into dI (3 per pixel).
 void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams, const int32_t* pi,
               const uint64_t* pu, const double* pd, const int64_t* pix, int64_t n_pix, int32_t mode,
               const double* gpix, int32_t grad_mode, const double* tangent, double* grad_albedo, double* dI,
@@ -1762,7 +2053,7 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
     int64_t p;
     resolve_pixel(cams, g, &view, &p);
     uint32_t fl = 0;
-    double dsum = 0.0;
+    C3 dsum;
     std::vector<int64_t> faces;  // every face on the pixel's paths
     for (int32_t smp = 0; smp < P.spp; ++smp) {
       PathRec rec;
@@ -1771,31 +2062,28 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
       if (!taint_per_path || rec.flags)
         for (int k = 0; k < rec.nv; ++k) faces.push_back(rec.v[k].param);
       if (grad_mode == 0) {
-        // D_k = beta_k a_k c_k; S_k = sum_{j>=k} D_j + M.  Accumulate S_k / a_k.
-        std::vector<double> beta(rec.nv + 1, 1.0);
-        for (int k = 0; k < rec.nv; ++k) beta[k + 1] = beta[k] * rec.v[k].a;
-        double tail = rec.escaped ? beta[rec.nv] * rec.L_esc : 0.0;
+        std::vector<C3> T(rec.nv + 1);
+        T[0] = c3(1.0);
+        for (int k = 0; k < rec.nv; ++k) T[k + 1] = T[k] * rec.v[k].w;
+        C3 R = rec.escaped ? c3(rec.L_esc) : C3{};  // radiance arriving at the last vertex along its bounce
         for (int k = rec.nv - 1; k >= 0; --k) {
-          tail += beta[k] * rec.v[k].a * rec.v[k].c;  // now tail = S_k
-          gacc[tid][rec.v[k].param] += gpix[i] * tail / rec.v[k].a / P.spp;
+          const C3 d = T[k] * (rec.v[k].e1 + rec.v[k].w1 * R);
+          double gsum = 0.0;
+          for (int ch = 0; ch < 3; ++ch) gsum += gpix[3 * i + ch] * d.v[ch];
+          gacc[tid][rec.v[k].param] += gsum / P.spp;
+          R = rec.v[k].e + rec.v[k].w * R;
         }
       } else {
         // dual numbers (value, derivative) along the tangent direction
-        double L = 0, dL = 0, beta = 1, dbeta = 0;
+        C3 T = c3(1.0), dT, dL;
         for (int k = 0; k < rec.nv; ++k) {
-          const double a = rec.v[k].a, da = tangent[rec.v[k].param];
-          const double c = rec.v[k].c;
-          L += beta * a * c;
-          dL += (dbeta * a + beta * da) * c;
-          const double nb = beta * a;
-          dbeta = dbeta * a + beta * da;
-          beta = nb;
+          const double da = tangent[rec.v[k].param];
+          dL = dL + dT * rec.v[k].e + da * (T * rec.v[k].e1);
+          dT = dT * rec.v[k].w + da * (T * rec.v[k].w1);
+          T = T * rec.v[k].w;
         }
-        if (rec.escaped) {
-          L += beta * rec.L_esc;
-          dL += dbeta * rec.L_esc;
-        }
-        dsum += dL;
+        if (rec.escaped) dL = dL + rec.L_esc * dT;
+        dsum = dsum + dL;
       }
     }
     // per pixel: a flagged pixel's value may differ on the GPU, and it weights the
@@ -1804,7 +2092,8 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
     // faces on flagged paths.
     if (face_tainted && fl)
       for (int64_t f : faces) taint[tid][f] = 1;
-    if (grad_mode == 1) dI[i] = dsum / P.spp;
+    if (grad_mode == 1)
+      for (int ch = 0; ch < 3; ++ch) dI[3 * i + ch] = dsum.v[ch] / P.spp;
     if (pflags) pflags[i] = (uint8_t)(fl != 0);
   });
   if (grad_mode == 0)
