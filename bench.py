@@ -22,9 +22,11 @@ printed.  Beside it (same JSON line):
                        wavefront vs FP32 plain wavefront, bit-identical images;
   ablation             node format x scheduler frames;
   graph_replay         the headline frame replayed from a captured HIP graph;
-  textured, area_lights, environment
+  textured, area_lights, environment, principled
                        the headline frame with per-face 4x4 textures, four quad
-                       area lights, a 2048x1024 environment map;
+                       area lights, a 2048x1024 environment map, eight
+                       principled materials in three channels;
+  config4_adjoint      forward frame and path-replay backward pass at config 4;
   config2              the smaller 1M-instance configuration: frames and
                        incoherent rays, both paths, and node widths 2, 4 and 8
                        (quantized persistent, equal hits and images);
@@ -77,20 +79,22 @@ def kernel_sources_hash():
 
 
 def committed_counters(name, kernel_key):
-    """Per-launch HBM bytes, VALU issue rate and measured HBM GB/s from a committed
-    rocprofv3 counter summary, or Nones when absent or taken from other sources."""
+    """Per-launch HBM bytes, VALU issue rate, measured HBM GB/s and VALU
+    wave-instructions per launch from a committed rocprofv3 counter summary, or
+    Nones when absent or taken from other sources."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None, None, None
+        return None, None, None, None
     txt = open(path).read()
     m = re.search(r"sources_hash:\s*(\w+)", txt)
     if not m or m.group(1) != kernel_key:
-        return None, None, None
+        return None, None, None, None
 
     def num(key):
         x = re.search(key + r":\s*([0-9.eE+-]+)", txt)
         return float(x.group(1)) if x else None
-    return num("traffic_bytes_per_launch"), num("valu_issue_per_cu_cycle"), num("hbm_gbs")
+    return (num("traffic_bytes_per_launch"), num("valu_issue_per_cu_cycle"), num("hbm_gbs"),
+            num("valu_insts_per_launch"))
 
 
 def roofline(alg_bytes, kern_ms, counters, kernel):
@@ -98,7 +102,7 @@ def roofline(alg_bytes, kern_ms, counters, kernel):
     larger of the measured HBM fraction and the VALU issue fraction (committed
     counters of the same sources), and is reported against its own peak."""
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    tr, valu, hbm = counters
+    tr, valu, hbm, insts = counters
     hbm_frac = None if hbm is None else hbm / HBM_PEAK_GBS
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
@@ -108,9 +112,13 @@ def roofline(alg_bytes, kern_ms, counters, kernel):
         out["valu_issue_frac"] = valu
         out["measured_hbm_frac"] = None if hbm_frac is None else round(hbm_frac, 4)
         if hbm_frac is None or valu > hbm_frac:
-            # issue-bound: VALU lane-operations per second against the issue peak
-            out.update({"bound": "alu", "achieved": round(valu * VALU_PEAK_TOPS, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                        "unit": "T VALU lane-ops/s", "frac": round(valu, 4),
+            # issue-bound: VALU lane-operations per second against the issue peak,
+            # the launch's wave-instructions (counted by rocprofv3) x 64 lanes over
+            # its duration measured here
+            lane_ops = insts * 64 / (kern_ms * 1e-3) / 1e12 if insts else valu * VALU_PEAK_TOPS
+            out.update({"bound": "alu", "achieved": round(lane_ops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                        "unit": "T VALU lane-ops/s", "frac": round(lane_ops / VALU_PEAK_TOPS, 4),
+                        "valu_insts_per_launch": insts,
                         "algorithmic_hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                             "frac": round(achieved / HBM_PEAK_GBS, 4)}})
     return out
@@ -122,11 +130,13 @@ def visit_bytes(v, rays, fmt=2):
 
 def compare_widths(rtq, scene, cams, st, cap, log, steps=5, frames=5):
     """Node widths 2, 4 and 8 on one workload: one build per width, the
-    quantized persistent kernels.  Each width dumps the bounce >= 1 rays of its
-    own frame 0 (the exclusion keys name its own top-level records); rays,
-    hits and frames must equal the 4-wide build's bit for bit.  Returns per
-    width: nodes, depths, incoherent Mrays/s, ms/frame and visits per ray."""
-    import numpy as np
+    quantized persistent kernels.  Frames must equal the 4-wide build's bit for
+    bit, and so must the closest hits of the 4-wide frame's first million
+    bounce rays (traced without exclusions, whose keys name each build's own
+    top-level records).  Each width is timed on the bounce >= 1 rays of its own
+    frame 0 with their exclusions (the same rays in its own queue order).
+    Returns per width: nodes, depths, incoherent Mrays/s, ms/frame and visits
+    per ray."""
     import torch
     q8p = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
     n_pix = sum(c.w * c.h for c in cams)
@@ -146,21 +156,22 @@ def compare_widths(rtq, scene, cams, st, cap, log, steps=5, frames=5):
         m = int(min(int(c.cpu().item()), cap))
         pl = d.view(12, cap)[:, :m]
         r, e = pl[:8].contiguous(), pl[8:10].view(torch.int32).t().contiguous()
-        h = rtq.trace_closest(S, r, exclude=e, soa_in=True, **q8p)
+        if ref is None:
+            probe = r[:, :min(m, 1 << 20)].contiguous()
+            ref = (img.clone(), probe, rtq.trace_closest(S, probe, soa_in=True, **q8p))
+        else:
+            assert torch.equal(ref[0].view(torch.int32), img.view(torch.int32)), f"width {w}: frame differs"
+            h = rtq.trace_closest(S, ref[1], soa_in=True, **q8p)
+            torch.cuda.synchronize()
+            for k in ("t", "u", "v", "inst", "prim"):
+                assert torch.equal(getattr(ref[2], k).view(torch.int32), getattr(h, k).view(torch.int32)), \
+                    f"width {w}: hits differ ({k})"
+            del h
         v = torch.zeros((m, 4), dtype=torch.int32, device="cuda")
         rtq.trace_closest(S, r, exclude=e, soa_in=True, visits=v, **q8p)
         torch.cuda.synchronize()
         vis = v.to(torch.float64).sum(0).cpu().numpy() / m
         del v
-        if ref is None:
-            ref = (img.clone(), r.clone(), h)
-        else:
-            assert torch.equal(ref[0].view(torch.int32), img.view(torch.int32)), f"width {w}: frame differs"
-            assert torch.equal(ref[1].view(torch.int32), r.view(torch.int32)), f"width {w}: bounce rays differ"
-            for k in ("t", "u", "v", "inst", "prim"):
-                assert torch.equal(getattr(ref[2], k).view(torch.int32), getattr(h, k).view(torch.int32)), \
-                    f"width {w}: hits differ ({k})"
-        del h
         for _ in range(2):
             rtq.trace_closest(S, r, exclude=e, soa_in=True, **q8p)
         torch.cuda.synchronize()
@@ -182,15 +193,17 @@ def compare_widths(rtq, scene, cams, st, cap, log, steps=5, frames=5):
         bn = B_NODE_Q8_W[w]
         out[w] = {"nodes": info["tlas_nodes"] + info["blas_nodes"], "node_bytes": bn,
                   "depth": [info["tlas_depth"], info["blas_depth_max"]], "build_s": round(build_s, 1),
-                  "incoherent_mrays_s": round(m / inc_ms / 1e3, 2), "incoherent_ms": round(inc_ms, 3),
-                  "ms_per_frame": round(fms, 3), "visits_per_ray": [round(x, 2) for x in vis],
-                  "algorithmic_bytes_per_ray": round(B_RAY + B_HIT + (vis[0] + vis[2]) * bn + vis[1] * B_INST
-                                                     + vis[3] * B_QUAD, 1)}
+                  "incoherent_rays": m, "incoherent_mrays_s": round(m / inc_ms / 1e3, 2),
+                  "incoherent_ms": round(inc_ms, 3), "ms_per_frame": round(fms, 3),
+                  "visits_per_ray": [round(float(x), 2) for x in vis],
+                  "algorithmic_bytes_per_ray": round(float(B_RAY + B_HIT + (vis[0] + vis[2]) * bn + vis[1] * B_INST
+                                                           + vis[3] * B_QUAD), 1)}
         log(f"node width {w}: {out[w]}")
         del S, r, e, pl, d, img
+    del ref
     torch.cuda.empty_cache()
-    best = min(out, key=lambda k: out[k]["incoherent_ms"])
-    return {"widths": {str(k): v for k, v in out.items()}, "fastest_incoherent": best,
+    return {"widths": {str(k): v for k, v in out.items()},
+            "fastest_incoherent": min(out, key=lambda k: out[k]["incoherent_ms"]),
             "fastest_frame": min(out, key=lambda k: out[k]["ms_per_frame"])}
 
 
@@ -332,14 +345,21 @@ def main():
     assert equal_hits, "incoherent hits differ between the quantized-persistent and FP32-plain kernels"
     hit_frac = float((h_q8.inst >= 0).float().mean().item())
     del h_f32, h_q8
-    inc_visits = {}
+    inc_visits, lane = {}, {}
     for name, fmt in (("q8", rtq.RTQ_NODE_Q8), ("fp32", rtq.RTQ_NODE_FP32)):
         v = torch.zeros((nd, 4), dtype=torch.int32, device="cuda")
+        ls = torch.zeros((nd, 2), dtype=torch.int32, device="cuda")
         rtq.trace_closest(S, rays, exclude=excl, soa_in=True, node_format=fmt, scheduler=rtq.SCHED_PERSISTENT,
-                          visits=v)
+                          visits=v, lane_stats=ls)
         torch.cuda.synchronize()
         inc_visits[name] = v.to(torch.float64).sum(0).cpu().numpy()
-        del v
+        lsum = ls.to(torch.float64).sum(0).cpu().numpy()
+        # a lane does useful work in an iteration when the wave runs its step kind
+        # (one visit); live iterations also include waiting and pop-only ones
+        lane[name] = {"useful_fraction_of_live_iterations": round(float(inc_visits[name].sum() / lsum[0]), 4),
+                      "fp64_edge_reevaluations_per_triangle_test": float(lsum[1] / (2 * inc_visits[name][3])),
+                      "fp64_edge_reevaluations": int(lsum[1])}
+        del v, ls
     log(f"incoherent visits (per ray): q8 {inc_visits['q8'] / nd}")
 
     # ---- the timed steps: the quantized persistent kernel on the incoherent rays
@@ -402,6 +422,20 @@ def main():
     area = variant(lambda: set_lights(lights), lambda: set_lights(()), "area lights", n_lights=4)
     envmap = variant(lambda: S.set_environment(torch.rand((1024, 2048), device="cuda", generator=gen) * 0.5),
                      lambda: S.set_environment(None), "environment", w=2048, h=1024)
+    # principled materials in three channels: 8 random materials over the faces
+    mat_rng = np.random.default_rng(7)
+    mats = np.concatenate([mat_rng.uniform(0.05, 0.95, (8, 3)), mat_rng.uniform(0.1, 1.0, (8, 1)),
+                           mat_rng.uniform(0.0, 1.0, (8, 2))], axis=1).astype(np.float32)
+    face_mat = torch.randint(0, 8, (S.n_quads,), device="cuda", generator=gen, dtype=torch.int64).to(torch.uint8)
+
+    def set_mats():
+        S.set_materials(mats, face_mat)
+        img.resize_(n_pix, 3)
+
+    def unset_mats():
+        S.set_materials(None)
+        img.resize_(n_pix)
+    principled = variant(set_mats, unset_mats, "principled", n_materials=8, channels=3)
 
     # ---- rooflines: the timed kernel and the frame's dominant kernel
     key = kernel_sources_hash()
@@ -460,6 +494,28 @@ def main():
         out2["node_width"] = compare_widths(rtq, scene2, cams2, st2, cap, log)
         log(f"config 2: {out2}")
         cfg2 = out2
+
+    # ---- the adjoint at config 4 (the config-1 scene at 512 x 512, 4 spp, depth
+    # 4): forward frame and one path-replay backward pass, quantized nodes
+    scene4, cams4, st4 = sg.config4()
+    S4 = rtq.Scene(scene4)
+    n4 = sum(c.w * c.h for c in cams4)
+    g4 = torch.full((n4,), 1.0 / n4, device="cuda")
+    adj = {}
+    for name, fn in (("forward", lambda: rtq.render(S4, cams4, st4, **Q8P)),
+                     ("backward", lambda: rtq.render_backward(S4, cams4, st4, g4, **Q8P))):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        adj[name + "_ms"] = round((time.perf_counter() - w0) / 5 * 1e3, 3)
+    adj["paths"] = n4 * st4.spp
+    adj["workload"] = "config4: config-1 scene (1000 instances, 16384 unique quads), 512x512, 4 spp, depth 4"
+    log(f"config 4 adjoint: {adj}")
+    del S4
 
     # ---- CPU baseline: the FP64 oracle tracing a bounded random sample of the
     # same incoherent rays (same exclusions), sized by a pilot to about
@@ -525,7 +581,8 @@ def main():
                        "fp32_plain_mrays_s": round(f32_inc["mrays_s"], 2),
                        "speedup": round(value / f32_inc["mrays_s"], 3),
                        "visits_per_ray_q8": [round(x / nd, 2) for x in inc_visits["q8"]],
-                       "visits_per_ray_fp32": [round(x / nd, 2) for x in inc_visits["fp32"]]},
+                       "visits_per_ray_fp32": [round(x / nd, 2) for x in inc_visits["fp32"]],
+                       "lanes_q8": lane["q8"], "lanes_fp32": lane["fp32"]},
         "frame": {"equal_images": equal_images,
                   "q8_persistent": {"ms_per_frame": round(q8f["wall_ms"], 3), "mrays_s": round(q8f["mrays_s"], 2),
                                     "ms_percentiles": {k: round(v, 3) for k, v in q8f["ev_pct"].items()}},
@@ -540,7 +597,9 @@ def main():
         "textured": textured,
         "area_lights": area,
         "environment": envmap,
+        "principled": principled,
         "config2": cfg2,
+        "config4_adjoint": adj,
         "roofline": roof,
         "roofline_frame": roof_frame,
         "cpu_baseline": cpu,

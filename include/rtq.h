@@ -199,8 +199,7 @@ int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, h
  * the copy on `stream`; renders on other streams are ordered by the caller.
  * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES] or NULL
  * texels with res > 0; RTQ_E_HIP when the allocation or copy fails.
- * rtq_render_backward rejects a textured scene (its gradient is with respect
- * to the per-face albedo).
+ * rtq_render_backward then differentiates with respect to the texels.
  */
 #define RTQ_MAX_TEX_RES 64
 int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t res, hipStream_t stream);
@@ -225,6 +224,43 @@ int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t re
  */
 #define RTQ_MAX_ENV_SIDE 16384
 int rtq_scene_set_environment(rtq_scene* scene, const float* texels_dev, int32_t w, int32_t h, hipStream_t stream);
+
+/*
+ * Principled materials (Section 5.4: every material of the scene uses Disney's
+ * principled BSDF, which the paper made energy conserving and preserving; it
+ * gives no formulas, so this is a reading).  A face's base color is its
+ * material's tint times its albedo (or texel), per channel, and it shades with
+ *   f mu_i = (1 - m)[F_d p_s + (1 - F_d) c mu_i / pi] + m F_c p_s,
+ * F_d = specular (0.04 + 0.96 (1 - mu_o)^5) and F_c = c + (1 - c)(1 - mu_o)^5
+ * (Schlick at the macro-surface angle), p_s the density of the outgoing
+ * direction reflected about a GGX visible normal (alpha = roughness^2, separable
+ * Smith masking, Heitz 2018), a reflection below the surface mirrored above it.
+ * The albedo is (1 - m)[F_d + (1 - F_d) c] + m F_c: one for c = 1, at most one
+ * otherwise; metallic = specular = 0 is Lambert's c / pi.  Bounces draw the
+ * specular lobe with probability (1 - m) F_d + m (word 0 of Philox counter
+ * (pixel, sample, view, 2^30 + bounce)), the cosine lobe otherwise, and weigh
+ * the direction by f mu_i over the mixture's density.  With materials every
+ * path carries three channels: images and image gradients hold 3 floats per
+ * pixel (interleaved RGB) and rtq_render_opts.channels must be 3.  Lights stay
+ * white.
+ *
+ * mats: host memory, n_mat entries (copied); face_mat_dev: device memory, one
+ * material index per unique quad in prototype order (copied into memory the
+ * scene owns).  n_mat = 0 (both may be NULL) removes the materials.  Waits for
+ * all work on the device, then copies synchronously.
+ * Errors: RTQ_E_INVALID_ARG for n_mat outside [0, RTQ_MAX_MATERIALS], NULL
+ * arrays, a tint outside [0, 1], roughness outside [0.05, 1], metallic or
+ * specular outside [0, 1], or a face index >= n_mat; RTQ_E_HIP when the
+ * allocation or copy fails.
+ */
+typedef struct {
+  float tint[3];
+  float roughness, metallic, specular;
+  float pad[2];
+} rtq_material;
+#define RTQ_MAX_MATERIALS 256
+int rtq_scene_set_materials(rtq_scene* scene, const rtq_material* mats, int32_t n_mat, const uint8_t* face_mat_dev,
+                            hipStream_t stream);
 
 /* ------------------------------------------------------------------ tracing */
 /* Rays and hits are structure-of-arrays in device memory, one element per ray. */
@@ -260,6 +296,11 @@ typedef struct {
   int32_t refill;      /* persistent scheduler: refill when this many lanes are idle, 1..64; 0 = 16 */
   uint32_t* visits;    /* optional device n x 4 counters: top nodes, instances entered,
                           bottom nodes, quads tested (slower kernel variant) */
+  uint32_t* lane_stats;/* optional device n x 2 counters (same kernel variant): traversal
+                          iterations of the ray's wave while the ray was not done (its
+                          visits over this is the fraction of its live iterations in
+                          which its lane did useful work), and FP64 re-evaluations of
+                          zero edge values in its leaf tests */
 } rtq_trace_opts;
 
 /*
@@ -408,6 +449,9 @@ typedef struct {
                                 are weighted against each other by the power heuristic.
                                 Unbiased either way; lower variance for small bright
                                 regions of the map. */
+  int32_t channels;          /* floats per image pixel: 0 or 1 without materials, 3 with
+                                them (rtq_scene_set_materials); any other value is an
+                                error, so buffers are sized for the scene's layout */
 } rtq_render_opts;
 
 #define RTQ_MAX_AREA_LIGHTS 64
@@ -416,11 +460,13 @@ typedef struct {
  * Path-trace n_cams pinhole views (Section 5.4: progressive 1 spp frames; here
  * spp samples per call, frames averaged with opts.accumulate) with a
  * Lambertian BSDF (albedo per face, or a texel of the face's texture when the
- * scene has textures), next-event estimation toward one directional light
+ * scene has textures) or, with materials, the principled BSDF in three
+ * channels (rtq_scene_set_materials), next-event estimation toward one directional light
  * (and optional quad area lights, opts.area_lights), and a constant sky (or an
  * environment map, rtq_scene_set_environment).  depth counts closest-hit rays per path including the
  * camera ray.  `images` is a packed FP32 device buffer; view
- * c occupies [img_offset, img_offset + w h), row 0 at the top.  Each pixel is
+ * c occupies pixels [img_offset, img_offset + w h), row 0 at the top, one float
+ * per pixel (three, interleaved RGB, with materials).  Each pixel is
  * the mean over its spp samples, summed in sample order, so every scheduler
  * produces bit-identical images.  cams: host memory.  Scratch memory is
  * allocated on first use and kept in the scene handle.
@@ -457,8 +503,10 @@ int rtq_render_timing(rtq_scene* scene, float* ms, int32_t* launches);
  * vertex, origin xyz and direction xyz of the ray that found the vertex);
  * *escaped = 1 if the path left the scene, and then record *n_vert holds the
  * escaping ray (ids -1, t = +inf, its origin and direction); *radiance = the
- * path's total.
- * vert_i: host, 6 depth int32; vert_f: host, 10 depth floats.  Synchronises
+ * path's total (radiance[0..2], the three channels, with materials; then the
+ * radiance after each vertex is the red channel).
+ * vert_i: host, 6 depth int32; vert_f: host, 10 depth floats; radiance: host,
+ * 1 float (3 with materials).  Synchronises
  * `stream`.  Errors: INVALID_ARG (view, pixel or sample out of range, NULL
  * outputs), as rtq_render otherwise.
  */
@@ -472,9 +520,13 @@ int rtq_render_path(const rtq_scene* scene, const rtq_camera* cams, int32_t n_ca
  * Adjoint of rtq_render with respect to per-face albedo, paths held fixed:
  * grad_albedo[f] += sum over pixels p of grad_images[p] * dI_p / d albedo[f].
  * Each path is replayed from its RNG counters (same hits as the forward pass).
- * grad_albedo: device, n_unique_quads floats, zeroed by the caller, accumulated
- * with atomics (summation order is not fixed).  Errors: RTQ_E_INVALID_ARG on a
- * scene with textures (rtq_scene_set_textures), as rtq_render otherwise.
+ * With textures the gradient is per texel (the parameter a hit reads):
+ * grad_albedo then holds n_unique_quads * res * res floats in the texture's
+ * layout (rtq_scene_set_textures).  With materials, grad_images holds 3 floats per pixel (as the image) and each
+ * vertex's estimate and bounce weight, affine in its albedo, are differentiated
+ * per channel.
+ * grad_albedo: device, n_unique_quads floats (times res^2 with textures), zeroed by the caller, accumulated
+ * with atomics (summation order is not fixed).  Errors: as rtq_render.
  */
 int rtq_render_backward(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp,
                         int32_t depth, const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,

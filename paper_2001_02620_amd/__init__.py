@@ -69,7 +69,7 @@ class _Hits(ctypes.Structure):
 class _TraceOpts(ctypes.Structure):
     _fields_ = [("node_format", ctypes.c_int32), ("scheduler", ctypes.c_int32), ("stack_depth", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("refill", ctypes.c_int32),
-                ("visits", ctypes.c_void_p)]
+                ("visits", ctypes.c_void_p), ("lane_stats", ctypes.c_void_p)]
 
 
 class _Camera(ctypes.Structure):
@@ -87,7 +87,13 @@ class _RenderOpts(ctypes.Structure):
                 ("view_done", ctypes.c_void_p), ("start_tick", ctypes.c_void_p), ("visits", ctypes.c_void_p),
                 ("dump_rays", ctypes.c_void_p), ("dump_cap", ctypes.c_int64), ("dump_count", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("graph", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("n_area_lights", ctypes.c_int32), ("area_lights", ctypes.c_void_p), ("env_nee", ctypes.c_int32)]
+                ("n_area_lights", ctypes.c_int32), ("area_lights", ctypes.c_void_p), ("env_nee", ctypes.c_int32),
+                ("channels", ctypes.c_int32)]
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("tint", ctypes.c_float * 3), ("roughness", ctypes.c_float), ("metallic", ctypes.c_float),
+                ("specular", ctypes.c_float), ("pad", ctypes.c_float * 2)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -97,7 +103,7 @@ EXPORTS = ["rtq_last_error", "rtq_version", "rtq_scene_build", "rtq_scene_destro
            "rtq_scene_set_albedo", "rtq_trace_closest", "rtq_trace_occluded", "rtq_trace_brute", "rtq_render",
            "rtq_render_backward", "rtq_render_timing", "rtq_render_path", "rtq_host_bvh_build", "rtq_host_bvh_get",
            "rtq_host_bvh_destroy", "rtq_scene_set_textures", "rtq_scene_set_environment",
-           "rtq_trace_closest_noalloc"]
+           "rtq_trace_closest_noalloc", "rtq_scene_set_materials"]
 
 
 def load_library():
@@ -121,6 +127,7 @@ def load_library():
     L.rtq_scene_set_albedo.argtypes = [P, P, ctypes.c_int64, P]
     L.rtq_scene_set_textures.argtypes = [P, P, ctypes.c_int32, P]
     L.rtq_scene_set_environment.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P]
+    L.rtq_scene_set_materials.argtypes = [P, P, ctypes.c_int32, P, P]
     L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_occluded.argtypes = [P, P, ctypes.c_int64, P, P, P]
     L.rtq_trace_closest_noalloc.argtypes = [P, P, ctypes.c_int64, P, P, P]
@@ -196,6 +203,8 @@ class Scene:
         _check(L.rtq_scene_build(ctypes.cast(protos, ctypes.c_void_p), P, ctypes.byref(insts), ctypes.byref(opts),
                                  ctypes.byref(h)))
         self._h = h
+        self.rgb = False
+        self.tex_res = 0
 
     @property
     def handle(self):
@@ -223,12 +232,38 @@ class Scene:
         if texels is None:
             _check(load_library().rtq_scene_set_textures(self.handle, None, 0, _stream()))
             self._tex_keep = None
+            self.tex_res = 0
             return
         assert texels.is_cuda and texels.dim() == 3 and texels.shape[0] == self.n_quads
         assert texels.shape[1] == texels.shape[2]
         t = texels.contiguous().float()
         _check(load_library().rtq_scene_set_textures(self.handle, t.data_ptr(), int(t.shape[1]), _stream()))
         self._tex_keep = t
+        self.tex_res = int(t.shape[1])
+
+    def set_materials(self, mats, face_mat=None) -> None:
+        """Principled materials: rows (tint r, g, b, roughness, metallic,
+        specular) and one material index per unique face (uint8, device tensor
+        or host array); None removes them.  With materials, images and image
+        gradients have three channels per pixel (interleaved RGB)."""
+        L = load_library()
+        if mats is None:
+            _check(L.rtq_scene_set_materials(self.handle, None, 0, None, _stream()))
+            self.rgb = False
+            return
+        torch = _torch()
+        m = np.asarray(mats, dtype=np.float32).reshape(-1, 6)
+        arr = (_Material * m.shape[0])()
+        for k, row in enumerate(m):
+            arr[k].tint[:] = [float(x) for x in row[:3]]
+            arr[k].roughness, arr[k].metallic, arr[k].specular = (float(x) for x in row[3:6])
+        fm = face_mat if isinstance(face_mat, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(face_mat, dtype=np.uint8))
+        fm = fm.to(device="cuda", dtype=torch.uint8).contiguous()
+        assert fm.numel() == self.n_quads
+        _check(L.rtq_scene_set_materials(self.handle, ctypes.cast(arr, ctypes.c_void_p), m.shape[0], fm.data_ptr(),
+                                         _stream()))
+        self.rgb = True
 
     def set_environment(self, texels) -> None:
         """Environment map seen by escaping rays: a device tensor [h, w] (row 0
@@ -287,8 +322,9 @@ def _rays_struct(rays, exclude=None, soa_in=False):
 
 
 def _trace_opts(node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, block=0, waves_per_cu=0, refill=0,
-                visits=None):
-    return _TraceOpts(node_format, scheduler, stack_depth, block, waves_per_cu, refill, _ptr(visits))
+                visits=None, lane_stats=None):
+    return _TraceOpts(node_format, scheduler, stack_depth, block, waves_per_cu, refill, _ptr(visits),
+                      _ptr(lane_stats))
 
 
 def trace_closest(scene: Scene, rays, exclude=None, want_ref: bool = False, soa_in: bool = False, **opts) -> Hits:
@@ -393,14 +429,22 @@ def render_opts(settings, node_format=0, scheduler=SCHED_PLAIN, stack_depth=0, b
     return o
 
 
+def _channels(scene) -> int:
+    return 3 if getattr(scene, "rgb", False) else 1
+
+
 def render(scene: Scene, cams, settings, images=None, **opts):
-    """Packed FP32 image of all views (view c at its offset, row 0 at the top)."""
+    """Packed FP32 image of all views (view c at its offset, row 0 at the top);
+    [pixels, 3] (RGB) for a scene with materials."""
     torch = _torch()
     arr, total = camera_structs(cams)
+    ch = _channels(scene)
     if images is None:
-        images = torch.empty(total, device="cuda", dtype=torch.float32)
-    assert images.is_cuda and images.dtype == torch.float32 and images.numel() >= total and images.is_contiguous()
+        images = torch.empty((total, 3) if ch == 3 else total, device="cuda", dtype=torch.float32)
+    assert images.is_cuda and images.dtype == torch.float32 and images.numel() >= ch * total
+    assert images.is_contiguous()
     o = render_opts(settings, **opts)
+    o.channels = ch
     _check(load_library().rtq_render(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
                                      settings.depth, ctypes.byref(o), images.data_ptr(), _stream()))
     return images
@@ -423,45 +467,52 @@ def render_path(scene: Scene, cams, settings, view: int, pixel: int, sample: int
     direction of the ray that found it)."""
     arr, _ = camera_structs(cams)
     o = render_opts(settings, **opts)
+    o.channels = _channels(scene)
     d = settings.depth
     vi = (ctypes.c_int32 * (6 * d))()
     vf = (ctypes.c_float * (10 * d))()
-    nv, esc, rad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    nv, esc, rad = ctypes.c_int32(), ctypes.c_int32(), (ctypes.c_float * 3)()
     _check(load_library().rtq_render_path(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
                                           d, ctypes.byref(o), view, pixel, sample, ctypes.cast(vi, ctypes.c_void_p),
                                           ctypes.cast(vf, ctypes.c_void_p), ctypes.byref(nv), ctypes.byref(esc),
-                                          ctypes.byref(rad), _stream()))
+                                          ctypes.cast(rad, ctypes.c_void_p), _stream()))
     verts = [dict(inst=vi[6 * k], prim=vi[6 * k + 1], half=vi[6 * k + 2], shadow=vi[6 * k + 3], face=vi[6 * k + 4],
                   t=vf[10 * k], albedo=vf[10 * k + 1], cosl=vf[10 * k + 2], radiance=vf[10 * k + 3],
                   origin=tuple(vf[10 * k + 4:10 * k + 7]), direction=tuple(vf[10 * k + 7:10 * k + 10]))
              for k in range(nv.value)]
-    return verts, bool(esc.value), float(rad.value)
+    return verts, bool(esc.value), (tuple(rad) if o.channels == 3 else float(rad[0]))
 
 
 def render_path_raw(scene: Scene, cams, settings, view: int, pixel: int, sample: int, **opts):
     """One path traced alone, as recorded by the library: (n_vert, vi [depth, 6]
-    int32, vf [depth, 10] float32, escaped, radiance); when the path escaped, row
-    n_vert holds the escaping ray."""
+    int32, vf [depth, 10] float32, escaped, radiance: a float32, or 3 for a scene
+    with materials); when the path escaped, row n_vert holds the escaping ray."""
     arr, _ = camera_structs(cams)
     o = render_opts(settings, **opts)
+    o.channels = _channels(scene)
     d = settings.depth
     vi = np.zeros((d, 6), np.int32)
     vf = np.zeros((d, 10), np.float32)
-    nv, esc, rad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    nv, esc = ctypes.c_int32(), ctypes.c_int32()
+    rad = np.zeros(3, np.float32)
     _check(load_library().rtq_render_path(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams), settings.spp,
                                           d, ctypes.byref(o), view, pixel, sample, vi.ctypes.data, vf.ctypes.data,
-                                          ctypes.byref(nv), ctypes.byref(esc), ctypes.byref(rad), _stream()))
-    return nv.value, vi, vf, bool(esc.value), np.float32(rad.value)
+                                          ctypes.byref(nv), ctypes.byref(esc), rad.ctypes.data, _stream()))
+    return nv.value, vi, vf, bool(esc.value), (rad if o.channels == 3 else np.float32(rad[0]))
 
 
 def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None, **opts):
     torch = _torch()
     arr, total = camera_structs(cams)
     g = grad_images.contiguous().float()
-    assert g.numel() == total and g.is_cuda
+    ch = _channels(scene)
+    assert g.numel() == ch * total and g.is_cuda
     if grad_albedo is None:
-        grad_albedo = torch.zeros(scene.n_quads, device=g.device, dtype=torch.float32)
+        # one entry per shading parameter: per face, or per texel with textures
+        n_par = scene.n_quads * max(1, getattr(scene, "tex_res", 0)) ** 2
+        grad_albedo = torch.zeros(n_par, device=g.device, dtype=torch.float32)
     o = render_opts(settings, **opts)
+    o.channels = ch
     _check(load_library().rtq_render_backward(scene.handle, ctypes.cast(arr, ctypes.c_void_p), len(cams),
                                               settings.spp, settings.depth, ctypes.byref(o), g.data_ptr(),
                                               grad_albedo.data_ptr(), _stream()))

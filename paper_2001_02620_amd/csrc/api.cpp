@@ -19,6 +19,7 @@
 #include "bvh_build.h"
 #include "kernels.h"
 #include "rebraid.h"
+#include "render_device.h"
 
 using namespace rtq;
 
@@ -531,6 +532,8 @@ void rtq_scene_destroy(rtq_scene* s) {
   if (s->tex) (void)hipFree(s->tex);
   if (s->env) (void)hipFree(s->env);
   if (s->env_T) (void)hipFree(s->env_T);
+  if (s->mats) (void)hipFree(s->mats);
+  if (s->face_mat) (void)hipFree(s->face_mat);
   delete s;
 }
 
@@ -546,7 +549,7 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->blas_depth_max = s->blas_depth;
   info->formats = s->formats;
   info->node_width = s->width;
-  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes + s->env_bytes);
+  info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes + s->env_bytes + s->mat_bytes);
   info->build_seconds = s->build_seconds;
   info->n_top_entries = s->n_rec;
   for (int k = 0; k < 4; ++k) info->build_phase_seconds[k] = s->build_phase[k];
@@ -560,6 +563,66 @@ int rtq_scene_set_albedo(rtq_scene* s, const float* albedo_dev, int64_t n, hipSt
                      (long long)s->n_quads);
   const hipError_t e = hipMemcpyAsync(s->albedo, albedo_dev, n * sizeof(float), hipMemcpyDeviceToDevice, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "hipMemcpyAsync");
+}
+
+int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_mat, const uint8_t* face_mat_dev,
+                            hipStream_t stream) {
+  if (!s) return set_error(RTQ_E_INVALID_ARG, "NULL scene");
+  if (n_mat < 0 || n_mat > RTQ_MAX_MATERIALS)
+    return set_error(RTQ_E_INVALID_ARG, "%d materials outside [0, %d]", n_mat, RTQ_MAX_MATERIALS);
+  if (n_mat > 0 && (!mats || !face_mat_dev)) return set_error(RTQ_E_INVALID_ARG, "NULL materials or face indices");
+  std::vector<MatDev> md(n_mat);
+  auto in01 = [](float x) { return x >= 0.0f && x <= 1.0f; };
+  for (int32_t k = 0; k < n_mat; ++k) {
+    const rtq_material& m = mats[k];
+    if (!in01(m.tint[0]) || !in01(m.tint[1]) || !in01(m.tint[2]) || !(m.roughness >= 0.05f && m.roughness <= 1.0f) ||
+        !in01(m.metallic) || !in01(m.specular))
+      return set_error(RTQ_E_INVALID_ARG, "material %d: parameter outside its range", k);
+    md[k].tint[0] = m.tint[0];
+    md[k].tint[1] = m.tint[1];
+    md[k].tint[2] = m.tint[2];
+    md[k].alpha = m.roughness * m.roughness;
+    md[k].metal = m.metallic;
+    md[k].spec = m.specular;
+    md[k].pad[0] = md[k].pad[1] = 0.0f;
+  }
+  hipError_t e = hipSetDevice(s->device);
+  if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+  // renders already queued may still read the old materials
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
+  (void)stream;
+  std::vector<uint8_t> fm;
+  if (n_mat > 0) {
+    fm.resize(s->n_quads);
+    e = hipMemcpy(fm.data(), face_mat_dev, s->n_quads, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_error(e, "hipMemcpy");
+    for (int64_t f = 0; f < s->n_quads; ++f)
+      if (fm[f] >= n_mat) return set_error(RTQ_E_INVALID_ARG, "face %lld: material %d >= %d", (long long)f, fm[f], n_mat);
+  }
+  if (s->mats) (void)hipFree(s->mats);
+  if (s->face_mat) (void)hipFree(s->face_mat);
+  s->mats = nullptr;
+  s->face_mat = nullptr;
+  s->n_mat = 0;
+  s->mat_bytes = 0;
+  if (n_mat == 0) return RTQ_OK;
+  void* dm = nullptr;
+  void* df = nullptr;
+  e = hipMalloc(&dm, n_mat * sizeof(MatDev));
+  if (e == hipSuccess) e = hipMalloc(&df, (size_t)s->n_quads);
+  if (e == hipSuccess) e = hipMemcpy(dm, md.data(), n_mat * sizeof(MatDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(df, fm.data(), (size_t)s->n_quads, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (dm) (void)hipFree(dm);
+    if (df) (void)hipFree(df);
+    return hip_error(e, "material upload");
+  }
+  s->mats = dm;
+  s->face_mat = static_cast<uint8_t*>(df);
+  s->n_mat = n_mat;
+  s->mat_bytes = n_mat * sizeof(MatDev) + (size_t)s->n_quads;
+  return RTQ_OK;
 }
 
 int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, hipStream_t stream) {
@@ -687,7 +750,7 @@ static int trace_common(const rtq_scene* s, const rtq_rays* rays, int64_t n, rtq
   const SceneView sv = scene_view(s, fmt);
   HitsSoA h{};
   if (hits) h = HitsSoA{hits->t, hits->u, hits->v, hits->inst, hits->prim, hits->ref};
-  const hipError_t e = launch_trace(sv, soa(rays), n, hits ? &h : nullptr, occ, o.visits, tl, stream);
+  const hipError_t e = launch_trace(sv, soa(rays), n, hits ? &h : nullptr, occ, o.visits, o.lane_stats, tl, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "trace launch");
 }
 
@@ -721,7 +784,7 @@ int rtq_trace_closest_noalloc(const rtq_scene* s, const rtq_rays* rays, int64_t 
   if (n == 0) return RTQ_OK;
   const SceneView sv = scene_view(s, fmt);
   const HitsSoA h{hits->t, hits->u, hits->v, hits->inst, hits->prim, hits->ref};
-  e = launch_trace(sv, soa(rays), n, &h, nullptr, o.visits, tl, stream);
+  e = launch_trace(sv, soa(rays), n, &h, nullptr, o.visits, o.lane_stats, tl, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "trace launch");
 }
 

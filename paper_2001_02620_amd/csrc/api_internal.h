@@ -72,6 +72,10 @@ struct rtq_scene {
   int32_t env_w = 0, env_h = 0;
   size_t env_bytes = 0;
   unsigned long long* env_T = nullptr;  // its sampling table (own allocation)
+  void* mats = nullptr;        // principled materials (rtq::MatDev, own allocation), or null
+  uint8_t* face_mat = nullptr; // material of each unique face (own allocation)
+  int32_t n_mat = 0;
+  size_t mat_bytes = 0;
   unsigned long long* counters = nullptr;  // ring of persistent-kernel work counters
   mutable std::atomic<uint32_t> counter_next{0};
   rtq::DeviceBuffers bufs;

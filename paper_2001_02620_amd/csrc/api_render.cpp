@@ -32,6 +32,7 @@ struct RenderScratch {
   DeviceBuffers bufs;
   int64_t paths_cap = 0;
   bool plain = false;
+  bool rgb = false;  // three radiance slots per path and RGB queue channels
   int32_t cams_cap = 0;
   CamDev* cams = nullptr;
   float* slots = nullptr;
@@ -118,15 +119,16 @@ RenderScratch* scratch_of(rtq_scene* s) {
 
 // Grow the scene's render scratch to hold n_paths paths (and the plain
 // scheduler's queues when asked).  Existing contents are not preserved.
-int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
+int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain, bool rgb) {
   RenderScratch* r = scratch_of(s);
-  if (r->paths_cap >= n_paths && r->cams_cap >= n_cams && (r->plain || !plain)) return RTQ_OK;
+  if (r->paths_cap >= n_paths && r->cams_cap >= n_cams && (r->plain || !plain) && (r->rgb || !rgb)) return RTQ_OK;
   (void)hipDeviceSynchronize();
   r->clear_graphs();  // their launches point into the buffers released here
   r->bufs.release();
   const int64_t P = std::max<int64_t>(std::max(n_paths, r->paths_cap), 64);
   const int32_t C = std::max(std::max(n_cams, r->cams_cap), 64);
   const bool want_plain = plain || r->plain;
+  const bool want_rgb = rgb || r->rgb;
   hipError_t e;
   auto A = [&](size_t bytes) { return r->bufs.alloc(bytes, &e); };
 #define RALLOC(dst, bytes)                                              \
@@ -137,11 +139,12 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
       r->paths_cap = 0;                                                 \
       r->cams_cap = 0;                                                  \
       r->plain = false;                                                 \
+      r->rgb = false;                                                   \
       return hip_error(e, "render scratch allocation");                 \
     }                                                                   \
   } while (0)
   RALLOC(r->cams, C * sizeof(CamDev));
-  RALLOC(r->slots, P * sizeof(float));
+  RALLOC(r->slots, (want_rgb ? 3 : 1) * P * sizeof(float));
   RALLOC(r->keys, 64);
   RALLOC(r->alights, RTQ_MAX_AREA_LIGHTS * 10 * sizeof(float));
   if (want_plain) {
@@ -158,6 +161,12 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
       RALLOC(q.ex_rec, P * 4);
       RALLOC(q.ex_qh, P * 4);
       RALLOC(q.pdf, P * 4);
+      if (want_rgb) {
+        RALLOC(q.beta_g, P * 4);
+        RALLOC(q.beta_b, P * 4);
+      } else {
+        q.beta_g = q.beta_b = nullptr;
+      }
     }
     ShadowQueue& sq = r->pb.sq;
     RALLOC(sq.ox, P * 4);
@@ -171,6 +180,12 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
     RALLOC(sq.dy, P * 4);
     RALLOC(sq.dz, P * 4);
     RALLOC(sq.tmax, P * 4);
+    if (want_rgb) {
+      RALLOC(sq.contrib_g, P * 4);
+      RALLOC(sq.contrib_b, P * 4);
+    } else {
+      sq.contrib_g = sq.contrib_b = nullptr;
+    }
     RALLOC(r->pb.hits.t, P * 4);
     RALLOC(r->pb.hits.rec, P * 4);
     RALLOC(r->pb.hits.qh, P * 4);
@@ -184,6 +199,7 @@ int ensure_scratch(rtq_scene* s, int64_t n_paths, int32_t n_cams, bool plain) {
   r->paths_cap = P;
   r->cams_cap = C;
   r->plain = want_plain;
+  r->rgb = want_rgb;
   s->scratch.total = r->bufs.total;
   return RTQ_OK;
 }
@@ -225,6 +241,10 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   if (opts->n_area_lights < 0 || opts->n_area_lights > RTQ_MAX_AREA_LIGHTS)
     return set_error(RTQ_E_INVALID_ARG, "%d area lights outside [0, %d]", opts->n_area_lights, RTQ_MAX_AREA_LIGHTS);
   if (opts->n_area_lights > 0 && !opts->area_lights) return set_error(RTQ_E_INVALID_ARG, "NULL area lights");
+  const bool rgb = s->mats != nullptr;
+  if (rgb ? opts->channels != 3 : (opts->channels != 0 && opts->channels != 1))
+    return set_error(RTQ_E_INVALID_ARG, "channels %d: the scene %s", opts->channels,
+                     rgb ? "has materials, so images have 3 channels" : "has no materials, so images have 1 channel");
   for (int32_t k = 0; k < 10 * opts->n_area_lights; ++k)
     if (!std::isfinite(opts->area_lights[k])) return set_error(RTQ_E_INVALID_ARG, "non-finite area light %d", k / 10);
   std::vector<CamDev> cd(n_cams);
@@ -299,7 +319,7 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
     return set_error(RTQ_E_LIMIT, "%lld paths per call exceed 2^31 - 1", (long long)path_base);
   {
     std::lock_guard<std::mutex> lock(s->scratch_mu);
-    rc = ensure_scratch(s, path_base, n_cams, plain_buffers);
+    rc = ensure_scratch(s, path_base, n_cams, plain_buffers, rgb);
     if (rc) return rc;
   }
   RenderScratch* sc = scratch_of(s);
@@ -331,6 +351,9 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
   rp.alights = sc->alights;
   rp.n_alights = opts->n_area_lights;
   rp.env_nee = (opts->env_nee && s->env_w > 0) ? 1 : 0;
+  rp.mats = static_cast<const MatDev*>(s->mats);
+  rp.face_mat = s->face_mat;
+  rp.E = opts->E;
   out->n_pixels = n_pixels;
   return RTQ_OK;
 }
@@ -359,8 +382,8 @@ int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prep
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
                 (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights,
                 (const void*)sv.env, (int)sv.env_w, (int)sv.env_h);
-  std::snprintf(key + std::strlen(key), sizeof(key) - std::strlen(key), "|%d %p", (int)rp.env_nee,
-                (const void*)sv.env_T);
+  std::snprintf(key + std::strlen(key), sizeof(key) - std::strlen(key), "|%d %p|%p %p %a", (int)rp.env_nee,
+                (const void*)sv.env_T, (const void*)rp.mats, (const void*)rp.face_mat, rp.E);
   // the accumulation grid and its bound bake in the packed image size, and the
   // camera layout decides which image pixels a replay writes
   const std::string k = std::string(key) + "|" + std::to_string((long long)p.n_pixels) + "|" + p.layout;
@@ -530,7 +553,7 @@ int rtq_render_path(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, 
   hipError_t e;
   DeviceBuffers tmp;
   int32_t* d_i = reinterpret_cast<int32_t*>(tmp.alloc(6 * kMaxDepth * sizeof(int32_t) + 64, &e));
-  float* d_f = reinterpret_cast<float*>(tmp.alloc((10 * kMaxDepth + 1) * sizeof(float), &e));
+  float* d_f = reinterpret_cast<float*>(tmp.alloc((10 * kMaxDepth + 3) * sizeof(float), &e));
   int32_t* d_o = reinterpret_cast<int32_t*>(tmp.alloc(64, &e));
   if (!d_i || !d_f || !d_o) {
     tmp.release();
@@ -539,7 +562,7 @@ int rtq_render_path(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, 
   const SceneView sv = scene_view(s, p.fmt);
   e = launch_path_record(sv, p.rp, p.fmt, p.tl.stack_depth, pid, d_i, d_f, d_o, stream);
   int32_t ho[2] = {0, 0};
-  float hf[10 * kMaxDepth + 1];
+  float hf[10 * kMaxDepth + 3];
   if (e == hipSuccess) e = hipMemcpyAsync(vert_i, d_i, 6 * depth * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(hf, d_f, sizeof(hf), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ho, d_o, sizeof(ho), hipMemcpyDeviceToHost, stream);
@@ -549,7 +572,11 @@ int rtq_render_path(const rtq_scene* s, const rtq_camera* cams, int32_t n_cams, 
   for (int k = 0; k < 10 * depth; ++k) vert_f[k] = hf[k];
   *n_vert = ho[0];
   *escaped = ho[1];
-  *radiance = hf[10 * kMaxDepth];
+  radiance[0] = hf[10 * kMaxDepth];
+  if (s->mats) {
+    radiance[1] = hf[10 * kMaxDepth + 1];
+    radiance[2] = hf[10 * kMaxDepth + 2];
+  }
   return RTQ_OK;
 }
 
@@ -557,8 +584,6 @@ int rtq_render_backward(const rtq_scene* s, const rtq_camera* cams, int32_t n_ca
                         const rtq_render_opts* opts, const float* grad_images, float* grad_albedo,
                         hipStream_t stream) {
   if (!grad_images || !grad_albedo) return set_error(RTQ_E_INVALID_ARG, "NULL gradient buffer");
-  if (s && s->tex_res > 0)
-    return set_error(RTQ_E_INVALID_ARG, "the adjoint is with respect to per-face albedo; the scene has textures");
   Prepared p;
   int rc = prepare(s, cams, n_cams, spp, depth, opts, false, stream, &p);
   if (rc) return rc;

@@ -54,7 +54,7 @@ struct TraceLaunch {
 };
 
 hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA* hits, uint8_t* occ,
-                        uint32_t* visits, const TraceLaunch& tl, hipStream_t s);
+                        uint32_t* visits, uint32_t* lane_stats, const TraceLaunch& tl, hipStream_t s);
 // Device address of the allocation-free query's claim counters (kClaimWords
 // words, a static device array) on `device`; looked up once per device.
 hipError_t noalloc_counters(int device, unsigned long long** out);

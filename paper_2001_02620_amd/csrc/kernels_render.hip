@@ -121,6 +121,12 @@ __global__ void k_raygen(RenderParams rp, ExtQueue q, uint32_t* counts) {
   q.ex_rec[pid] = kEmpty;
   q.ex_qh[pid] = kEmpty;
   rp.slots[pid] = 0.0f;
+  if (rgb_mode(rp)) {
+    q.beta_g[pid] = 1.0f;
+    q.beta_b[pid] = 1.0f;
+    rp.slots[rp.n_paths + pid] = 0.0f;
+    rp.slots[2 * rp.n_paths + pid] = 0.0f;
+  }
 }
 
 // Load queue entry i into a lane: an extension ray (closest hit) or a shadow
@@ -281,16 +287,49 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
   const bool live = i < (int64_t)*count_in;
   bool want_shadow = false, want_next = false;
   float contrib = 0.0f, beta_next = 0.0f, ndx = 0.0f, ndy = 0.0f, ndz = 0.0f, pdf_next = 0.0f;
+  float contrib3[3] = {0.0f, 0.0f, 0.0f}, beta3[3] = {0.0f, 0.0f, 0.0f};  // RGB: contribution, next throughput
   Shade s{};
-  NeeSample ns{false, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  NeeSample ns{false, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   uint32_t pid = 0u, rec = kEmpty, qhv = kEmpty;
+  const bool rgb = rgb_mode(rp);
   if (live) {
     pid = in.pid[i];
     const float beta = in.beta[i];
     rec = qh.rec[i];
     if (rec == kEmpty) {
       const float pdf = (b > 0 && rp.env_nee) ? in.pdf[i] : 0.0f;
-      rp.slots[pid] += beta * escape_radiance(sc, rp, in.dx[i], in.dy[i], in.dz[i], pdf);  // escaped
+      const float Le = escape_radiance(sc, rp, in.dx[i], in.dy[i], in.dz[i], pdf);
+      rp.slots[pid] += beta * Le;  // escaped
+      if (rgb) {
+        rp.slots[rp.n_paths + pid] += in.beta_g[i] * Le;
+        rp.slots[2 * rp.n_paths + pid] += in.beta_b[i] * Le;
+      }
+    } else if (rgb) {
+      qhv = qh.qh[i];
+      const Ray3 r{in.ox[i], in.oy[i], in.oz[i], in.dx[i], in.dy[i], in.dz[i]};
+      const bool tex = sc.tex_res > 0;
+      s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31, tex ? qh.u[i] : 0.0f,
+                    tex ? qh.v[i] : 0.0f);
+      float c[3];
+      const PShade ps = principled_vertex(rp, s, r, c);
+      const float bt[3] = {beta, in.beta_g[i], in.beta_b[i]};
+      const bool next = b < rp.depth - 1;
+      const PathId id = path_coords(rp, (int64_t)pid);
+      ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, b);
+      if (ns.want) {
+        float e[3], e1[3];
+        pnee_estimate(ps, c, ns, e, e1);
+        want_shadow = true;
+        for (int k = 0; k < 3; ++k) contrib3[k] = bt[k] * e[k];
+        contrib = contrib3[0];
+      }
+      if (next) {
+        float w[3], w1[3];
+        pdf_next = pbsdf_bounce(rp, ps, c, id.pixel, id.sample, id.view, b, &ndx, &ndy, &ndz, w, w1);
+        for (int k = 0; k < 3; ++k) beta3[k] = bt[k] * w[k];
+        beta_next = beta3[0];
+        want_next = pdf_next > 0.0f;
+      }
     } else {
       qhv = qh.qh[i];
       const Ray3 r{in.ox[i], in.oy[i], in.oz[i], in.dx[i], in.dy[i], in.dz[i]};
@@ -320,6 +359,10 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     sq.oz[js] = s.pz;
     sq.pid[js] = pid;
     sq.contrib[js] = contrib;
+    if (rgb) {
+      sq.contrib_g[js] = contrib3[1];
+      sq.contrib_b[js] = contrib3[2];
+    }
     sq.ex_rec[js] = rec;
     sq.ex_qh[js] = qhv;
     if (nee_sampled(rp)) {
@@ -338,6 +381,10 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
     out.dz[jn] = ndz;
     out.pid[jn] = pid;
     out.beta[jn] = beta_next;
+    if (rgb) {
+      out.beta_g[jn] = beta3[1];
+      out.beta_b[jn] = beta3[2];
+    }
     out.ex_rec[jn] = rec;
     out.ex_qh[jn] = qhv;
     if (rp.env_nee) out.pdf[jn] = pdf_next;
@@ -373,7 +420,14 @@ __global__ void k_shadow_resolve(RenderParams rp, ShadowQueue sq, const uint32_t
                                  unsigned long long* view_done) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < (int64_t)*count;
-  if (live && !occ[i]) rp.slots[sq.pid[i]] += sq.contrib[i];
+  if (live && !occ[i]) {
+    const uint32_t pid = sq.pid[i];
+    rp.slots[pid] += sq.contrib[i];
+    if (rgb_mode(rp)) {
+      rp.slots[rp.n_paths + pid] += sq.contrib_g[i];
+      rp.slots[2 * rp.n_paths + pid] += sq.contrib_b[i];
+    }
+  }
   if (view_done && b == rp.depth - 1) {
     wave_stamp_views(live, live ? path_coords(rp, (int64_t)sq.pid[i]).cam : 0, view_done);
   }
@@ -394,12 +448,17 @@ __global__ void k_accum(RenderParams rp, float* image, int64_t n_pixels) {
   const int64_t pixel = g - c.img_offset;
   // before the first view, or in a gap between views: not part of any image
   if (pixel < 0 || pixel >= wh) return;
-  float sum = 0.0f;
-  for (int s = 0; s < rp.spp; ++s) sum += rp.slots[c.path_base + s * wh + pixel];
-  const float m = sum / (float)rp.spp;
   // progressive refinement: keys[2] frames are already averaged in the image
   const uint32_t k = rp.keys[2];
-  image[g] = k == 0u ? m : image[g] + (m - image[g]) / (float)(k + 1u);
+  const int nch = rgb_mode(rp) ? 3 : 1;
+  for (int ch = 0; ch < nch; ++ch) {
+    const float* sl = rp.slots + ch * rp.n_paths;
+    float sum = 0.0f;
+    for (int s = 0; s < rp.spp; ++s) sum += sl[c.path_base + s * wh + pixel];
+    const float m = sum / (float)rp.spp;
+    const int64_t o = nch * g + ch;  // RGB images interleave the channels per pixel
+    image[o] = k == 0u ? m : image[o] + (m - image[o]) / (float)(k + 1u);
+  }
 }
 
 // counters[0..3] += closest, shadow, incoherent (bounce >= 1), paths
@@ -437,7 +496,9 @@ struct PathLane {
   uint32_t pid;
   int b;
   float beta, radiance, pending, beta_next, ndx, ndy, ndz;
-  float pdf, pdf_next;  // cosine density of the current / next extension ray (0 for camera rays)
+  float pdf, pdf_next;  // BSDF density of the current / next extension ray (0 for camera rays)
+  // green and blue channels of beta, radiance, pending and beta_next (RGB shading)
+  float beta_g, beta_b, rad_g, rad_b, pend_g, pend_b, bn_g, bn_b;
   bool shadow, have_next;
 };
 
@@ -478,6 +539,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
           P.beta = 1.0f;
           P.pdf = 0.0f;
           P.radiance = 0.0f;
+          P.beta_g = P.beta_b = 1.0f;
+          P.rad_g = P.rad_b = 0.0f;
           P.shadow = false;
           P.have_next = false;
           L.ex_rec = kEmpty;
@@ -513,7 +576,12 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
             bool path_done = false;
             if (!P.shadow) {
               if (L.b_rec == kEmpty) {
-                P.radiance += P.beta * escape_radiance(sc, rp, L.wdx, L.wdy, L.wdz, P.pdf);
+                const float Le = escape_radiance(sc, rp, L.wdx, L.wdy, L.wdz, P.pdf);
+                P.radiance += P.beta * Le;
+                if (rgb_mode(rp)) {
+                  P.rad_g += P.beta_g * Le;
+                  P.rad_b += P.beta_b * Le;
+                }
                 path_done = true;
               } else {
                 const Ray3 r{L.wox, L.woy, L.woz, L.wdx, L.wdy, L.wdz};
@@ -522,22 +590,45 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                                           TEX ? L.b_u : 0.0f, TEX ? L.b_v : 0.0f);
                 P.have_next = P.b < rp.depth - 1;
                 PathId id{0, 0u, 0u, 0u, 0u};
-                if (P.have_next || nee_sampled(rp)) id = path_coords(rp, (int64_t)P.pid);
-                if (P.have_next) {
-                  P.pdf_next = bounce_dir(rp, id.pixel, id.sample, id.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
-                  P.beta_next = P.beta * s.a;
+                if (P.have_next || nee_sampled(rp) || rgb_mode(rp)) id = path_coords(rp, (int64_t)P.pid);
+                const NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, P.b);
+                if (rgb_mode(rp)) {
+                  float c[3];
+                  const PShade ps = principled_vertex(rp, s, r, c);
+                  if (P.have_next) {
+                    float w[3], w1[3];
+                    P.pdf_next = pbsdf_bounce(rp, ps, c, id.pixel, id.sample, id.view, P.b, &P.ndx, &P.ndy,
+                                              &P.ndz, w, w1);
+                    P.have_next = P.pdf_next > 0.0f;
+                    P.beta_next = P.beta * w[0];
+                    P.bn_g = P.beta_g * w[1];
+                    P.bn_b = P.beta_b * w[2];
+                  }
+                  if (ns.want) {
+                    float e[3], e1[3];
+                    pnee_estimate(ps, c, ns, e, e1);
+                    P.pending = P.beta * e[0];
+                    P.pend_g = P.beta_g * e[1];
+                    P.pend_b = P.beta_b * e[2];
+                  }
+                } else {
+                  if (P.have_next) {
+                    P.pdf_next = bounce_dir(rp, id.pixel, id.sample, id.view, P.b, s, &P.ndx, &P.ndy, &P.ndz);
+                    P.beta_next = P.beta * s.a;
+                  }
+                  if (ns.want) P.pending = nee_contrib(P.beta, s, ns, rp);
                 }
                 L.ex_rec = hrec;
                 L.ex_qh = hqh;
-                const NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, P.b);
                 if (ns.want) {
-                  P.pending = nee_contrib(P.beta, s, ns, rp);
                   P.shadow = true;
                   lane_init(L, sc, s.px, s.py, s.pz, ns.dx, ns.dy, ns.dz, 0.0f, ns.tmax);
                   L.any = true;
                   ++n_sh;
                 } else if (P.have_next) {
                   P.beta = P.beta_next;
+                  P.beta_g = P.bn_g;
+                  P.beta_b = P.bn_b;
                   P.pdf = P.pdf_next;
                   ++P.b;
                   lane_init(L, sc, s.px, s.py, s.pz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
@@ -548,10 +639,18 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                 }
               }
             } else {
-              if (L.b_rec == kEmpty) P.radiance += P.pending;
+              if (L.b_rec == kEmpty) {
+                P.radiance += P.pending;
+                if (rgb_mode(rp)) {
+                  P.rad_g += P.pend_g;
+                  P.rad_b += P.pend_b;
+                }
+              }
               P.shadow = false;
               if (P.have_next) {
                 P.beta = P.beta_next;
+                P.beta_g = P.bn_g;
+                P.beta_b = P.bn_b;
                 P.pdf = P.pdf_next;
                 ++P.b;
                 lane_init(L, sc, L.wox, L.woy, L.woz, P.ndx, P.ndy, P.ndz, 0.0f, kInfF);
@@ -563,6 +662,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
             }
             if (path_done) {
               rp.slots[P.pid] = P.radiance;
+              if (rgb_mode(rp)) {
+                rp.slots[rp.n_paths + P.pid] = P.rad_g;
+                rp.slots[2 * rp.n_paths + P.pid] = P.rad_b;
+              }
               ++n_paths;
               if (TS) atomicMax(&view_done[path_coords(rp, (int64_t)P.pid).cam], (unsigned long long)wall_clock64());
               has = false;
@@ -600,7 +703,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
 // radiance after the vertex, origin xyz and direction xyz of the ray that found
 // it); a path that escapes records its escaping ray after its last vertex (ids
 // -1, t = +inf).  out[0] = vertices, out[1] = 1 if the path escaped, and
-// rec_f[10 kMaxDepth] holds the final radiance.
+// rec_f[10 kMaxDepth ..] holds the final radiance (three channels with
+// principled shading; rec_f[10 k + 3] then holds the red channel).
 template <int FMT>
 __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int depth_lds, int32_t* rec_i,
                               float* rec_f, int32_t* out) {
@@ -612,6 +716,8 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
   PathId id;
   Ray3 r = path_camera_ray(rp, pid, &id);
   float beta = 1.0f, radiance = 0.0f, pdf = 0.0f;
+  float beta3[3] = {1.0f, 1.0f, 1.0f}, rad3[3] = {0.0f, 0.0f, 0.0f};  // RGB shading
+  const bool rgb = rgb_mode(rp);
   uint32_t ex_rec = kEmpty, ex_qh = kEmpty;
   int n = 0, escaped = 0;
   for (int b = 0; b < rp.depth; ++b) {
@@ -622,7 +728,10 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
       while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
       }
     if (L.b_rec == kEmpty) {
-      radiance += beta * escape_radiance(sc, rp, r.dx, r.dy, r.dz, pdf);
+      const float Le = escape_radiance(sc, rp, r.dx, r.dy, r.dz, pdf);
+      radiance += beta * Le;
+      for (int k = 0; k < 3; ++k) rad3[k] += beta3[k] * Le;
+      if (rgb) radiance = rad3[0];
       escaped = 1;
       // the escaping ray takes the next record (n < depth here)
       rec_i[6 * n + 0] = -1;
@@ -647,8 +756,17 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     const Shade sh = shade_hit(sc, rp, r, L.t_best, L.b_rec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     int shadow = -1;
     const NeeSample ns = nee_sample(sc, rp, sh, id.pixel, id.sample, id.view, b);
+    float c3[3] = {0.0f, 0.0f, 0.0f};
+    PShade ps{};
+    if (rgb) ps = principled_vertex(rp, sh, r, c3);
     if (ns.want) {
-      const float pending = nee_contrib(beta, sh, ns, rp);
+      float pend3[3] = {0.0f, 0.0f, 0.0f};
+      if (rgb) {
+        float e[3], e1[3];
+        pnee_estimate(ps, c3, ns, e, e1);
+        for (int k = 0; k < 3; ++k) pend3[k] = beta3[k] * e[k];
+      }
+      const float pending = rgb ? pend3[0] : nee_contrib(beta, sh, ns, rp);
       Lane Ls;
       Ls.ex_rec = L.b_rec;
       Ls.ex_qh = hqh;
@@ -658,7 +776,10 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
         }
       }
       shadow = Ls.b_rec != kEmpty ? 1 : 0;
-      if (shadow == 0) radiance += pending;
+      if (shadow == 0) {
+        radiance += pending;
+        for (int k = 0; k < 3; ++k) rad3[k] += pend3[k];
+      }
     }
     rec_i[6 * n + 0] = (int32_t)sc.inst[L.b_rec].inst_id;
     rec_i[6 * n + 1] = sc.quad_prim[hqh & 0x7FFFFFFFu];
@@ -679,15 +800,25 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     ++n;
     if (b == rp.depth - 1) break;
     float dx, dy, dz;
-    pdf = bounce_dir(rp, id.pixel, id.sample, id.view, b, sh, &dx, &dy, &dz);
-    beta = beta * sh.a;
+    if (rgb) {
+      float w[3], w1[3];
+      pdf = pbsdf_bounce(rp, ps, c3, id.pixel, id.sample, id.view, b, &dx, &dy, &dz, w, w1);
+      if (!(pdf > 0.0f)) break;  // a direction on the surface: the path ends
+      for (int k = 0; k < 3; ++k) beta3[k] *= w[k];
+      beta = beta3[0];
+    } else {
+      pdf = bounce_dir(rp, id.pixel, id.sample, id.view, b, sh, &dx, &dy, &dz);
+      beta = beta * sh.a;
+    }
     r = Ray3{sh.px, sh.py, sh.pz, dx, dy, dz};
     ex_rec = L.b_rec;
     ex_qh = hqh;
   }
   out[0] = n;
   out[1] = escaped;
-  rec_f[10 * kMaxDepth] = radiance;
+  rec_f[10 * kMaxDepth] = rgb ? rad3[0] : radiance;
+  rec_f[10 * kMaxDepth + 1] = rgb ? rad3[1] : radiance;
+  rec_f[10 * kMaxDepth + 2] = rgb ? rad3[2] : radiance;
 }
 
 __global__ void k_start_tick(unsigned long long* t) {
@@ -695,6 +826,84 @@ __global__ void k_start_tick(unsigned long long* t) {
 }
 
 // ---------------------------------------------------------------- adjoint
+// Principled (RGB) form of the adjoint: every vertex's next-event estimate e_k
+// and bounce weight w_k are affine in its face's albedo (the base color is the
+// material's tint times the albedo, and the sampled directions do not depend on
+// it), with derivatives e1_k and w1_k.  With T_k the throughput before vertex k
+// and R_k the radiance arriving at k along its bounce (R = e_{k+1} + w_{k+1}
+// R_{k+1}, the escape's radiance after the last vertex), the derivative of the
+// path value is T_k (e1_k + w1_k R_k), weighted per channel by the pixel's
+// gradient.  Called by k_adjoint for scenes with materials.
+template <int FMT>
+__device__ __forceinline__ void adjoint_rgb(const SceneView& sc, const RenderParams& rp, const float* grad_img,
+                                            float* grad_albedo, const Stack& S, uint2* spill, int64_t pid) {
+  PathId id;
+  Ray3 r = path_camera_ray(rp, pid, &id);
+  const int64_t px = rp.cams[id.cam].img_offset + id.local;
+  const float g[3] = {grad_img[3 * px] / (float)rp.spp, grad_img[3 * px + 1] / (float)rp.spp,
+                      grad_img[3 * px + 2] / (float)rp.spp};
+  if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) return;
+  uint32_t face[kMaxDepth];
+  float T[kMaxDepth][3], e[kMaxDepth][3], e1[kMaxDepth][3], w[kMaxDepth][3], w1[kMaxDepth][3];
+  int K = 0;
+  bool escaped = false;
+  float beta[3] = {1.0f, 1.0f, 1.0f}, pdf = 0.0f;
+  Lane L;
+  VisitCounters vc{0, 0, 0, 0};
+  L.ex_rec = kEmpty;
+  L.ex_qh = kEmpty;
+  for (int b = 0; b < rp.depth; ++b) {
+    if (lane_init(L, sc, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, 0.0f, kInfF))
+      while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+      }
+    if (L.b_rec == kEmpty) {
+      escaped = true;
+      break;
+    }
+    const uint32_t hrec = L.b_rec, hqh = L.b_qh;
+    const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
+    float c[3];
+    const PShade ps = principled_vertex(rp, s, r, c);
+    NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, b);
+    if (ns.want) {
+      L.ex_rec = hrec;
+      L.ex_qh = hqh;
+      if (lane_init(L, sc, s.px, s.py, s.pz, ns.dx, ns.dy, ns.dz, 0.0f, ns.tmax)) {
+        L.any = true;
+        while (!lane_step<FMT, false>(L, sc, S, spill, vc)) {
+        }
+      }
+      ns.want = L.b_rec == kEmpty;  // the estimate counts only when the light is visible
+    }
+    pnee_estimate(ps, c, ns, e[K], e1[K]);
+    face[K] = s.param;
+    for (int k = 0; k < 3; ++k) {
+      T[K][k] = beta[k];
+      w[K][k] = 0.0f;
+      w1[K][k] = 0.0f;
+    }
+    ++K;
+    if (b == rp.depth - 1) break;
+    float dx, dy, dz;
+    pdf = pbsdf_bounce(rp, ps, c, id.pixel, id.sample, id.view, b, &dx, &dy, &dz, w[K - 1], w1[K - 1]);
+    if (!(pdf > 0.0f)) break;
+    for (int k = 0; k < 3; ++k) beta[k] *= w[K - 1][k];
+    r = Ray3{s.px, s.py, s.pz, dx, dy, dz};
+    L.ex_rec = hrec;
+    L.ex_qh = hqh;
+  }
+  const float Le = escaped ? escape_radiance(sc, rp, r.dx, r.dy, r.dz, pdf) : 0.0f;
+  float R[3] = {Le, Le, Le};
+  for (int k = K - 1; k >= 0; --k) {
+    float d = 0.0f;
+    for (int ch = 0; ch < 3; ++ch) {
+      d += g[ch] * (T[k][ch] * (e1[k][ch] + w1[k][ch] * R[ch]));
+      R[ch] = e[k][ch] + w[k][ch] * R[ch];
+    }
+    unsafeAtomicAdd(&grad_albedo[face[k]], d);
+  }
+}
+
 // One lane per path: replay the path from its RNG counters with the same device
 // functions (identical hits), keep per vertex the face, beta_k and the NEE factor
 // c_k = (E / pi) cos_L V_k, then walk back: with V_K the sky (or environment)
@@ -709,6 +918,10 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
   uint2 spill[kStackTotal];
   const int64_t pid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pid >= rp.n_paths) return;
+  if (rgb_mode(rp)) {
+    adjoint_rgb<FMT>(sc, rp, grad_img, grad_albedo, S, spill, pid);
+    return;
+  }
   PathId id;
   Ray3 r = path_camera_ray(rp, pid, &id);
   // id.local < tw * th: the index stays inside the camera's image rectangle
@@ -745,7 +958,7 @@ __global__ void k_adjoint(SceneView sc, RenderParams rp, const float* grad_img, 
       }
       if (L.b_rec == kEmpty) c = ns.c;
     }
-    face[K] = s.face;
+    face[K] = s.param;  // taken at shading, before the shadow ray reuses the lane's (u, v)
     betak[K] = beta;
     ck[K] = c;
     ak[K] = s.a;

@@ -40,16 +40,17 @@ __device__ __forceinline__ bool load_ray(Lane& L, const SceneView& sc, const Ray
 }
 
 template <bool COUNT>
-__device__ __forceinline__ void store_visits(uint32_t* visits, int64_t i, const VisitCounters& vc) {
+__device__ __forceinline__ void store_visits(uint32_t* visits, uint32_t* lane_stats, int64_t i,
+                                             const VisitCounters& vc) {
   if (COUNT) {
-    uint4* v = reinterpret_cast<uint4*>(visits);
-    v[i] = make_uint4(vc.tlas, vc.inst, vc.blas, vc.quads);
+    if (visits) reinterpret_cast<uint4*>(visits)[i] = make_uint4(vc.tlas, vc.inst, vc.blas, vc.quads);
+    if (lane_stats) reinterpret_cast<uint2*>(lane_stats)[i] = make_uint2(vc.iters, vc.fp64);
   }
 }
 
 template <int FMT, bool ANY, bool COUNT>
 __global__ void k_trace_plain(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hits, uint8_t* occ, uint32_t* visits,
-                              int depth) {
+                              uint32_t* lane_stats, int depth) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth);
@@ -62,12 +63,13 @@ __global__ void k_trace_plain(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
     while (!lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
     }
   store_result<ANY>(L, sc, i, hits, occ);
-  store_visits<COUNT>(visits, i, vc);
+  store_visits<COUNT>(visits, lane_stats, i, vc);
 }
 
 template <int FMT, bool ANY, bool COUNT>
 __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hits, uint8_t* occ,
-                                   uint32_t* visits, int depth, int refill, unsigned long long* counter) {
+                                   uint32_t* visits, uint32_t* lane_stats, int depth, int refill,
+                                   unsigned long long* counter) {
   extern __shared__ uint2 lds[];
   const int lane = threadIdx.x & 63;
   const Stack S = make_stack(lds, depth);
@@ -90,7 +92,7 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
           has = true;
         } else {
           store_result<ANY>(L, sc, idx, hits, occ);
-          store_visits<COUNT>(visits, idx, vc);
+          store_visits<COUNT>(visits, lane_stats, idx, vc);
         }
       }
     }
@@ -102,7 +104,7 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
       for (;;) {
         if (lane_step<FMT, COUNT>(L, sc, S, spill, vc)) {
           store_result<ANY>(L, sc, idx, hits, occ);
-          store_visits<COUNT>(visits, idx, vc);
+          store_visits<COUNT>(visits, lane_stats, idx, vc);
           has = false;
           break;
         }
@@ -129,37 +131,40 @@ __global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hit
 
 template <int FMT, bool ANY, bool COUNT>
 static hipError_t launch3(const SceneView& sc, const RaysSoA& r, int64_t n, const HitsSoA& h, uint8_t* occ,
-                          uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
+                          uint32_t* visits, uint32_t* lane_stats, const TraceLaunch& tl, hipStream_t s) {
   const size_t lds = (size_t)tl.block * tl.stack_depth * kStackEntryBytes;
   if (tl.persistent) {
     hipError_t e = launch_zero_u64(tl.counter, kClaimWords, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_trace_persistent<FMT, ANY, COUNT>), dim3(tl.grid), dim3(tl.block), lds, s, sc, r, n, h,
-                       occ, visits, tl.stack_depth, tl.refill, tl.counter);
+                       occ, visits, lane_stats, tl.stack_depth, tl.refill, tl.counter);
   } else {
     const unsigned g = (unsigned)((n + tl.block - 1) / tl.block);
     hipLaunchKernelGGL((k_trace_plain<FMT, ANY, COUNT>), dim3(g), dim3(tl.block), lds, s, sc, r, n, h, occ, visits,
-                       tl.stack_depth);
+                       lane_stats, tl.stack_depth);
   }
   return hipGetLastError();
 }
 
 template <int FMT>
 static hipError_t launch2(const SceneView& sc, const RaysSoA& r, int64_t n, const HitsSoA* h, uint8_t* occ,
-                          uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
+                          uint32_t* visits, uint32_t* lane_stats, const TraceLaunch& tl, hipStream_t s) {
   const HitsSoA hh = h ? *h : HitsSoA{};
+  const bool cnt = visits || lane_stats;
   if (occ) {
-    return visits ? launch3<FMT, true, true>(sc, r, n, hh, occ, visits, tl, s)
-                  : launch3<FMT, true, false>(sc, r, n, hh, occ, visits, tl, s);
+    return cnt ? launch3<FMT, true, true>(sc, r, n, hh, occ, visits, lane_stats, tl, s)
+               : launch3<FMT, true, false>(sc, r, n, hh, occ, visits, lane_stats, tl, s);
   }
-  return visits ? launch3<FMT, false, true>(sc, r, n, hh, occ, visits, tl, s)
-                : launch3<FMT, false, false>(sc, r, n, hh, occ, visits, tl, s);
+  return cnt ? launch3<FMT, false, true>(sc, r, n, hh, occ, visits, lane_stats, tl, s)
+             : launch3<FMT, false, false>(sc, r, n, hh, occ, visits, lane_stats, tl, s);
 }
 
 hipError_t launch_trace(const SceneView& sc, const RaysSoA& rays, int64_t n, const HitsSoA* hits, uint8_t* occ,
-                        uint32_t* visits, const TraceLaunch& tl, hipStream_t s) {
+                        uint32_t* visits, uint32_t* lane_stats, const TraceLaunch& tl, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  return with_codec(tl.fmt, [&](auto c) { return launch2<decltype(c)::value>(sc, rays, n, hits, occ, visits, tl, s); });
+  return with_codec(tl.fmt, [&](auto c) {
+    return launch2<decltype(c)::value>(sc, rays, n, hits, occ, visits, lane_stats, tl, s);
+  });
 }
 
 // Claim counters of the allocation-free ray query (rtq_trace_closest_noalloc):

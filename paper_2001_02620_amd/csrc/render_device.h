@@ -1,6 +1,7 @@
-// Device-side pieces of the Lambertian path tracer shared by every scheduler:
+// Device-side pieces of the path tracer shared by every scheduler:
 // counter-based random numbers, pinhole camera rays, hit shading with next-event
-// estimation toward a directional light, and cosine-distributed bounces.
+// estimation, and bounces: cosine-distributed for Lambertian faces, drawn from
+// the principled BSDF (RGB) when the scene has materials.
 //
 // Every scheduler calls exactly these functions in the same order per path, so
 // the per-path radiance is bit-identical whichever kernel runs the path.
@@ -28,6 +29,16 @@ struct CamDev {
   int64_t path_base;   // first path id of the rectangle; paths are sample-major: base + s * tw * th + local pixel
 };
 
+// A principled material (Section 5.4: the scene's materials use Disney's
+// principled BSDF, made energy conserving and preserving): base color
+// c = tint x (the face's albedo or texel), alpha = roughness^2 (GGX), metallic,
+// and specular, which scales the dielectric Fresnel reflectance.
+struct MatDev {
+  float tint[3];
+  float alpha, metal, spec;
+  float pad[2];
+};
+
 struct RenderParams {
   const CamDev* cams;
   int32_t n_cams;
@@ -43,7 +54,14 @@ struct RenderParams {
   const float* alights; // quad area lights, 10 floats each: corner, edge 1, edge 2, radiance
   int32_t n_alights;
   int32_t env_nee;      // next-event estimation toward the environment map (scene has one)
+  const MatDev* mats;   // principled materials, or null: Lambertian faces, one channel
+  const uint8_t* face_mat;  // material of each unique face
+  float E;              // irradiance of the directional light
 };
+
+// Whether paths shade with the principled BSDF in three channels; radiance
+// slots are then channel-major: slot of channel k of path p at k n_paths + p.
+__device__ __forceinline__ bool rgb_mode(const RenderParams& rp) { return rp.mats != nullptr; }
 
 // Whether next-event estimates sample light directions (area lights or the
 // environment), so shadow rays carry their own direction and tmax.
@@ -128,18 +146,19 @@ struct Shade {
   float a;           // albedo
   float cosl;        // n . light
   uint32_t face;     // unique face index (albedo index)
+  uint32_t param;    // the shading parameter read: the face, or its texel (f res + ty) res + tx
 };
 
-// Texture value of face `face` at (u, v) (Section 5.3: looked up by face id and
+// Texel index of face `face` at (u, v) (Section 5.3: looked up by face id and
 // the hit's coordinates on the face): the nearest of tex_res x tex_res texels
 // over the face's unit square.  Clamping in float first keeps the index in
 // range for any u, v (NaN included: fmaxf returns the other operand).
-__device__ __forceinline__ float face_texel(const SceneView& sc, uint32_t face, float u, float v) {
+__device__ __forceinline__ uint32_t face_texel(const SceneView& sc, uint32_t face, float u, float v) {
   const int R = sc.tex_res;
   const float hi = (float)(R - 1);
   const int tx = (int)fminf(fmaxf(u * (float)R, 0.0f), hi);
   const int ty = (int)fminf(fmaxf(v * (float)R, 0.0f), hi);
-  return sc.tex[((size_t)face * R + ty) * R + tx];
+  return (face * (uint32_t)R + (uint32_t)ty) * (uint32_t)R + (uint32_t)tx;
 }
 
 // Geometric normal of the hit half in object space, mapped to world space by
@@ -185,7 +204,8 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   s.ny = ny;
   s.nz = nz;
   s.face = ir.face_base + (uint32_t)sc.quad_prim[quad];
-  s.a = sc.tex_res > 0 ? face_texel(sc, s.face, u, v) : sc.albedo[s.face];
+  s.param = sc.tex_res > 0 ? face_texel(sc, s.face, u, v) : s.face;
+  s.a = sc.tex_res > 0 ? sc.tex[s.param] : sc.albedo[s.face];
   s.cosl = nx * rp.lx + ny * rp.ly + nz * rp.lz;
   return s;
 }
@@ -242,6 +262,10 @@ struct NeeSample {
   float dx, dy, dz;    // its direction (toward the directional light, or to the sampled point)
   float tmax;          // +inf, or 1 for an area-light sample (the ray ends at the point)
   float c;
+  // for principled shading: the estimate is X (A + B c) toward the unit
+  // direction (ux, uy, uz), times the power-heuristic weight against the BSDF
+  // density when pdf_light > 0 (the environment)
+  float X, ux, uy, uz, pdf_light;
 };
 
 // Next-event estimate at hit s of path (pixel, sample, view), bounce b.
@@ -254,13 +278,14 @@ struct NeeSample {
 // for the sampled point at distance d, A = |e1 x e2|.
 __device__ __forceinline__ NeeSample nee_sample(const SceneView& sc, const RenderParams& rp, const Shade& s,
                                                 uint32_t pixel, uint32_t sample, uint32_t view, int b) {
-  NeeSample r{s.cosl > 0.0f, rp.lx, rp.ly, rp.lz, kInfF, nee_factor(s.cosl, rp)};
+  NeeSample r{s.cosl > 0.0f, rp.lx, rp.ly, rp.lz, kInfF, nee_factor(s.cosl, rp), rp.E, rp.lx, rp.ly, rp.lz, 0.0f};
   if (!nee_sampled(rp)) return r;
   const uint4 w = philox4x32_10(make_uint4(pixel, sample, view, 0x80000000u | (uint32_t)b), rp.keys[0], rp.keys[1]);
   const uint32_t nl = n_lights(rp);
   const uint32_t j = (uint32_t)(((uint64_t)(w.x >> 8) * nl) >> 24);
   if (j == 0u) {
     r.c = (float)nl * r.c;
+    r.X = (float)nl * rp.E;
     return r;
   }
   if (rp.env_nee && j == nl - 1u) {
@@ -289,6 +314,11 @@ __device__ __forceinline__ NeeSample nee_sample(const SceneView& sc, const Rende
     r.want = cp > 0.0f;
     const float pdf = env_pdf(sc, tx, ty);
     r.c = (float)nl * (sc.env[lo] * cp * mis_power(pdf / (float)nl, cp / kPiF) / (kPiF * pdf));
+    r.X = (float)nl * sc.env[lo] / pdf;
+    r.ux = r.dx;
+    r.uy = r.dy;
+    r.uz = r.dz;
+    r.pdf_light = pdf / (float)nl;
     return r;
   }
   const float* q = rp.alights + 10 * (j - 1u);
@@ -308,6 +338,10 @@ __device__ __forceinline__ NeeSample nee_sample(const SceneView& sc, const Rende
   r.dz = wz;
   r.tmax = 1.0f;
   r.c = (float)nl * (q[9] * A * cp * cq / (3.14159265358979323846f * d2));
+  r.X = (float)nl * (q[9] * A * cq / d2);
+  r.ux = wx * inv_d;
+  r.uy = wy * inv_d;
+  r.uz = wz * inv_d;
   return r;
 }
 
@@ -335,6 +369,230 @@ __device__ __forceinline__ void cosine_dir(float nx, float ny, float nz, float u
   *dx = lx * t1x + ly * t2x + lz * nx;
   *dy = lx * t1y + ly * t2y + lz * ny;
   *dz = lx * t1z + ly * t2z + lz * nz;
+}
+
+// ---------------------------------------------------------------- principled BSDF
+// At a vertex with unit normal n (the viewer's side) and unit direction wo to
+// the viewer, mu_o = n . wo, the cosine-weighted BSDF toward wi (mu_i = n . wi > 0)
+// is f mu_i = (1 - m)[F_d p_s + (1 - F_d) c mu_i / pi] + m F_c p_s = A + B c, with
+// the dielectric Fresnel weight F_d = spec (0.04 + 0.96 (1 - mu_o)^5) and the
+// metal's F_c = c + (1 - c)(1 - mu_o)^5 (Schlick at the macro-surface angle).
+// p_s is the density of the specular lobe: wo reflected about a GGX visible
+// normal (Heitz 2018), a reflection below the surface mirrored above it, so p_s
+// integrates to one and the albedo is (1 - m)[F_d + (1 - F_d) c] + m F_c: one
+// for a white base (energy preserving), below one otherwise (conserving).  The
+// specular lobe is drawn with probability P_s = (1 - m) F_d + m, independent of
+// c; the density of a direction is P_s p_s + (1 - P_s) mu_i / pi.
+struct PShade {
+  float nx, ny, nz;           // normal
+  float ox, oy, oz;           // unit direction to the viewer
+  float t1x, t1y, t1z, t2x, t2y, t2z;  // basis of Duff et al. 2017 about n
+  float mo, alpha, metal, Fd, k5, Ps;
+  float tint[3];
+};
+
+__device__ __forceinline__ PShade make_pshade(const MatDev& m, const Shade& s, const Ray3& r) {
+  PShade p;
+  p.nx = s.nx;
+  p.ny = s.ny;
+  p.nz = s.nz;
+  const float inv = 1.0f / sqrtf(r.dx * r.dx + r.dy * r.dy + r.dz * r.dz);
+  p.ox = -r.dx * inv;
+  p.oy = -r.dy * inv;
+  p.oz = -r.dz * inv;
+  const float sg = s.nz >= 0.0f ? 1.0f : -1.0f;
+  const float a = -1.0f / (sg + s.nz);
+  const float b = s.nx * s.ny * a;
+  p.t1x = 1.0f + sg * s.nx * s.nx * a;
+  p.t1y = sg * b;
+  p.t1z = -sg * s.nx;
+  p.t2x = b;
+  p.t2y = sg + s.ny * s.ny * a;
+  p.t2z = -s.ny;
+  p.mo = p.nx * p.ox + p.ny * p.oy + p.nz * p.oz;
+  const float om = fmaxf(0.0f, 1.0f - p.mo);
+  const float om2 = om * om;
+  p.k5 = om2 * om2 * om;
+  p.alpha = m.alpha;
+  p.metal = m.metal;
+  p.Fd = m.spec * (0.04f + 0.96f * p.k5);
+  p.Ps = (1.0f - m.metal) * p.Fd + m.metal;
+  p.tint[0] = m.tint[0];
+  p.tint[1] = m.tint[1];
+  p.tint[2] = m.tint[2];
+  return p;
+}
+
+// GGX distribution with the cosine c = n . h and s2 = |n x h|^2 (the form
+// 1 - c^2 (1 - alpha^2) = s2 + c^2 alpha^2 keeps its precision near the peak)
+__device__ __forceinline__ float ggx_D(float alpha, float c, float s2) {
+  const float a2 = alpha * alpha;
+  const float q = s2 + c * c * a2;
+  return a2 / (kPiF * q * q);
+}
+__device__ __forceinline__ float smith_G1(float alpha, float mu) {
+  return 2.0f * mu / (mu + sqrtf(alpha * alpha + (1.0f - alpha * alpha) * mu * mu));
+}
+// D of the half vector of unit directions a and b about n
+__device__ __forceinline__ float ggx_D_half(const PShade& p, float ax, float ay, float az, float bx, float by,
+                                            float bz) {
+  float hx = ax + bx, hy = ay + by, hz = az + bz;
+  const float inv = 1.0f / sqrtf(hx * hx + hy * hy + hz * hz);
+  hx *= inv;
+  hy *= inv;
+  hz *= inv;
+  const float c = p.nx * hx + p.ny * hy + p.nz * hz;
+  const float cx = p.ny * hz - p.nz * hy, cy = p.nz * hx - p.nx * hz, cz = p.nx * hy - p.ny * hx;
+  return ggx_D(p.alpha, c, cx * cx + cy * cy + cz * cz);
+}
+
+// density of the mirrored specular lobe toward unit wi
+__device__ __forceinline__ float spec_pdf(const PShade& p, float wx, float wy, float wz) {
+  const float mi = p.nx * wx + p.ny * wy + p.nz * wz;
+  if (!(mi > 0.0f) || !(p.mo > 0.0f)) return 0.0f;
+  const float g = smith_G1(p.alpha, p.mo) / (4.0f * p.mo);
+  float pdf = g * ggx_D_half(p, p.ox, p.oy, p.oz, wx, wy, wz);
+  if (p.mo > mi) {
+    const float mx = wx - 2.0f * mi * p.nx, my = wy - 2.0f * mi * p.ny, mz = wz - 2.0f * mi * p.nz;
+    pdf += g * ggx_D_half(p, p.ox, p.oy, p.oz, mx, my, mz);
+  }
+  return pdf;
+}
+
+// f mu_i = A + B c toward unit wi (zero below the surface) and the density of
+// drawing wi
+__device__ __forceinline__ void pbsdf_eval(const PShade& p, float wx, float wy, float wz, float* A, float* B,
+                                           float* pdf) {
+  const float mi = p.nx * wx + p.ny * wy + p.nz * wz;
+  if (!(mi > 0.0f)) {
+    *A = *B = *pdf = 0.0f;
+    return;
+  }
+  const float ps = p.Ps > 0.0f ? spec_pdf(p, wx, wy, wz) : 0.0f;
+  *A = ((1.0f - p.metal) * p.Fd + p.metal * p.k5) * ps;
+  *B = (1.0f - p.metal) * (1.0f - p.Fd) * mi / kPiF + p.metal * (1.0f - p.k5) * ps;
+  *pdf = (p.Ps > 0.0f ? p.Ps * ps : 0.0f) + (1.0f - p.Ps) * mi / kPiF;
+}
+
+// Bounce direction from the lobe word u0 and (u1, u2): a GGX visible normal
+// (Heitz 2018: stretch wo by alpha, sample the projected half disk, unstretch)
+// and the reflection about it, mirrored above the surface, when u0 < P_s; the
+// cosine lobe otherwise.
+__device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1, float u2, float* dx, float* dy,
+                                             float* dz) {
+  float sn, cs;
+  sincospif(2.0f * u2, &sn, &cs);
+  if (!(u0 < p.Ps)) {
+    const float rr = sqrtf(u1);
+    const float lx = rr * cs, ly = rr * sn, lz = sqrtf(1.0f - u1);
+    *dx = lx * p.t1x + ly * p.t2x + lz * p.nx;
+    *dy = lx * p.t1y + ly * p.t2y + lz * p.ny;
+    *dz = lx * p.t1z + ly * p.t2z + lz * p.nz;
+    return;
+  }
+  const float olx = p.ox * p.t1x + p.oy * p.t1y + p.oz * p.t1z;
+  const float oly = p.ox * p.t2x + p.oy * p.t2y + p.oz * p.t2z;
+  float vx = p.alpha * olx, vy = p.alpha * oly, vz = p.mo;
+  const float iv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+  vx *= iv;
+  vy *= iv;
+  vz *= iv;
+  const float l2 = vx * vx + vy * vy;
+  float T1x = 1.0f, T1y = 0.0f;
+  if (l2 > 0.0f) {
+    const float il = 1.0f / sqrtf(l2);
+    T1x = -vy * il;
+    T1y = vx * il;
+  }
+  // T2 = v x T1 (T1 has no z component)
+  const float T2x = -vz * T1y, T2y = vz * T1x, T2z = vx * T1y - vy * T1x;
+  // a point of the unit disk, (p1, r sin phi), its second coordinate warped to
+  // p2 = (1 - s) q + s r sin phi with q = sqrt(1 - p1^2), and its height
+  // sqrt(1 - p1^2 - p2^2).  Near the rim, 1 - p1^2 - p2^2 cancels; written as
+  // (q - p2)(q + p2) with q - p2 = s (q - r sin phi) and
+  // q^2 - (r sin phi)^2 = 1 - u1 exactly, it keeps full precision.
+  const float rr = sqrtf(u1);
+  const float p1 = rr * cs, rs = rr * sn;
+  const float sw = 0.5f * (1.0f + vz);
+  const float q = sqrtf((1.0f - u1) + u1 * (sn * sn));
+  const float p2 = (1.0f - sw) * q + sw * rs;
+  const float qm = rs > 0.0f ? (1.0f - u1) / (q + rs) : q - rs;  // q - r sin phi
+  const float pz = sqrtf(fmaxf(0.0f, sw * qm * (q + p2)));
+  const float nhx = p1 * T1x + p2 * T2x + pz * vx;
+  const float nhy = p1 * T1y + p2 * T2y + pz * vy;
+  const float nhz = p2 * T2z + pz * vz;
+  float hx = p.alpha * nhx, hy = p.alpha * nhy, hz = fmaxf(0.0f, nhz);
+  const float ih = 1.0f / sqrtf(hx * hx + hy * hy + hz * hz);
+  hx *= ih;
+  hy *= ih;
+  hz *= ih;
+  const float wx_h = hx * p.t1x + hy * p.t2x + hz * p.nx;
+  const float wy_h = hx * p.t1y + hy * p.t2y + hz * p.ny;
+  const float wz_h = hx * p.t1z + hy * p.t2z + hz * p.nz;
+  const float oh = p.ox * wx_h + p.oy * wy_h + p.oz * wz_h;
+  float rx = 2.0f * oh * wx_h - p.ox, ry = 2.0f * oh * wy_h - p.oy, rz = 2.0f * oh * wz_h - p.oz;
+  const float mi = p.nx * rx + p.ny * ry + p.nz * rz;
+  if (mi < 0.0f) {
+    rx -= 2.0f * mi * p.nx;
+    ry -= 2.0f * mi * p.ny;
+    rz -= 2.0f * mi * p.nz;
+  }
+  *dx = rx;
+  *dy = ry;
+  *dz = rz;
+}
+
+// The principled vertex of hit s reached by ray r: its frame, and base color
+// tint x s.a per channel in c.
+__device__ __forceinline__ PShade principled_vertex(const RenderParams& rp, const Shade& s, const Ray3& r,
+                                                    float c[3]) {
+  const PShade p = make_pshade(rp.mats[rp.face_mat[s.face]], s, r);
+  c[0] = p.tint[0] * s.a;
+  c[1] = p.tint[1] * s.a;
+  c[2] = p.tint[2] * s.a;
+  return p;
+}
+
+// Principled next-event estimate per channel (zero when no shadow ray is
+// traced): X (A + B c_k) toward the sampled light direction, with the power
+// heuristic against the BSDF density for the environment; e1 receives its
+// derivative in the face's albedo.
+__device__ __forceinline__ void pnee_estimate(const PShade& p, const float c[3], const NeeSample& ns, float e[3],
+                                              float e1[3]) {
+  float A, B, pdf;
+  pbsdf_eval(p, ns.ux, ns.uy, ns.uz, &A, &B, &pdf);
+  float X = ns.X;
+  if (ns.pdf_light > 0.0f) X *= mis_power(ns.pdf_light, pdf);
+  for (int k = 0; k < 3; ++k) {
+    e[k] = ns.want ? X * (A + B * c[k]) : 0.0f;
+    e1[k] = ns.want ? X * (B * p.tint[k]) : 0.0f;
+  }
+}
+
+// Principled bounce after hit b: the lobe word (word 0 of counter (pixel,
+// sample, view, 2^30 + b), drawn only when the specular lobe has weight), the
+// direction from words 2, 3 of counter (pixel, sample, view, b), its weight
+// w_k = (A + B c_k) / pdf per channel and derivative w1_k = B tint_k / pdf.
+// Returns the density (0: the direction lies on the surface and the path ends).
+__device__ __forceinline__ float pbsdf_bounce(const RenderParams& rp, const PShade& p, const float c[3],
+                                              uint32_t pixel, uint32_t sample, uint32_t view, int b, float* dx,
+                                              float* dy, float* dz, float w[3], float w1[3]) {
+  const uint4 wd = philox4x32_10(make_uint4(pixel, sample, view, (uint32_t)b), rp.keys[0], rp.keys[1]);
+  float u0 = 1.0f;
+  if (p.Ps > 0.0f) {
+    const uint4 wl = philox4x32_10(make_uint4(pixel, sample, view, 0x40000000u | (uint32_t)b), rp.keys[0],
+                                   rp.keys[1]);
+    u0 = u01(wl.x);
+  }
+  pbsdf_sample(p, u0, u01(wd.z), u01(wd.w), dx, dy, dz);
+  const float inv = 1.0f / sqrtf(*dx * *dx + *dy * *dy + *dz * *dz);
+  float A, B, pdf;
+  pbsdf_eval(p, *dx * inv, *dy * inv, *dz * inv, &A, &B, &pdf);
+  for (int k = 0; k < 3; ++k) {
+    w[k] = pdf > 0.0f ? (A + B * c[k]) / pdf : 0.0f;
+    w1[k] = pdf > 0.0f ? B * p.tint[k] / pdf : 0.0f;
+  }
+  return pdf;
 }
 
 // Camera ray of path `pid` (jitter from words 0, 1 of the bounce-0 counter).

@@ -17,8 +17,9 @@ struct ExtQueue {
   uint32_t* pid;
   float* beta;
   uint32_t *ex_rec, *ex_qh;
-  float* pdf;  // density of the cosine bounce that drew the ray (written when the
+  float* pdf;  // density of the bounce that drew the ray (written when the
                // environment is sampled by next-event estimation)
+  float *beta_g, *beta_b;  // green and blue throughput (RGB shading; beta holds red)
 };
 
 // Shadow-ray queue: direction is the light direction.
@@ -28,6 +29,7 @@ struct ShadowQueue {
   float* contrib;
   uint32_t *ex_rec, *ex_qh;
   float *dx, *dy, *dz, *tmax;  // written only for a scene with area lights
+  float *contrib_g, *contrib_b;  // green and blue contributions (RGB shading; contrib holds red)
 };
 
 // Closest hits of an extension queue (internal form).

@@ -210,6 +210,7 @@ __device__ __forceinline__ float edge(const Sv& P, const Sv& Q) { return Q.X * P
 
 struct TriResult {
   bool hit;
+  bool f64;  // the edge values were re-evaluated in FP64
   float t, U, V, W, det;
 };
 
@@ -230,10 +231,12 @@ __device__ __forceinline__ TriResult tri_finish(float U, float V, float W, const
                                                 float tmin, float tmax) {
   TriResult r;
   r.hit = false;
+  r.f64 = false;
   const bool neg = (U < 0.0f) || (V < 0.0f) || (W < 0.0f);
   const bool pos = (U > 0.0f) || (V > 0.0f) || (W > 0.0f);
   if (neg && pos) return r;
   if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    r.f64 = true;
     const double u = edge64(B, C), v = edge64(C, A), w = edge64(A, B);
     const bool n64 = (u < 0.0) || (v < 0.0) || (w < 0.0);
     const bool p64 = (u > 0.0) || (v > 0.0) || (w > 0.0);
@@ -526,7 +529,9 @@ __device__ __forceinline__ bool better(const Lane& L, const SceneView& sc, float
 // lanes evaluate the same instructions on quad q (any valid index) and keep their
 // state.  Every update is a select, so no lane state is written under divergent
 // control flow.  Returns true on the lanes where an any-hit query found its hit.
-__device__ __forceinline__ bool quad_test(Lane& L, const SceneView& sc, bool act, uint32_t q) {
+// *n64 (when given) counts this lane's FP64 edge re-evaluations.
+__device__ __forceinline__ bool quad_test(Lane& L, const SceneView& sc, bool act, uint32_t q,
+                                          uint32_t* n64 = nullptr) {
   const int kx = L.kz == 2 ? 0 : L.kz + 1;
   const int ky = kx == 2 ? 0 : kx + 1;
   const float4 f0 = sc.quads[3 * (size_t)q + 0];
@@ -546,6 +551,7 @@ __device__ __forceinline__ bool quad_test(Lane& L, const SceneView& sc, bool act
   const float t_lim = L.any ? L.tmax : L.t_best;
   const TriResult ra = tri_finish(e13, e30, e01, s0, s1, s3, L.tmin, t_lim);
   const TriResult rb = tri_finish(e31, e12, e23, s2, s3, s1, L.tmin, t_lim);
+  if (n64) *n64 += (act && ra.f64 ? 1u : 0u) + (act && rb.f64 ? 1u : 0u);
   const bool exq = L.rec == L.ex_rec;
   const bool oka = act && ra.hit && !(exq && L.ex_qh == q);
   const bool okb = act && rb.hit && !(exq && L.ex_qh == (q | 0x80000000u));
@@ -585,6 +591,8 @@ __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_
 
 struct VisitCounters {
   uint32_t tlas, inst, blas, quads;
+  uint32_t iters = 0;  // traversal iterations of its wave while the ray was not done
+  uint32_t fp64 = 0;   // FP64 re-evaluations of zero edge values in its leaf tests
 };
 
 // ---- work claiming of the persistent kernels ------------------------------------
@@ -764,7 +772,7 @@ template <bool COUNT>
 __device__ __forceinline__ void quad_step(bool act, Lane& L, const SceneView& sc, VisitCounters& vc) {
   if (COUNT) vc.quads += act ? 1u : 0u;
   const uint32_t first = leaf_first(L.cur), count = leaf_count(L.cur);
-  const bool answered = quad_test(L, sc, act, act ? first : 0u);
+  const bool answered = quad_test(L, sc, act, act ? first : 0u, COUNT ? &vc.fp64 : nullptr);
   const uint32_t rest = count > 1u ? make_leaf(first + 1u, count - 1u) : kEmpty;
   L.cur = act ? (answered ? kEmpty : rest) : L.cur;
   L.done = L.done || answered;
@@ -848,6 +856,7 @@ template <int FMT, bool COUNT>
 __device__ __forceinline__ bool lane_step(Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
   const int kind = step_kind(L);
+  if (COUNT) vc.iters += kind != 0 ? 1u : 0u;
   run_step<FMT, COUNT>(vote_kind(kind), kind, L, sc, S, spill, vc);
   pop_step(L, sc, S, spill);
   return L.done;

@@ -145,29 +145,33 @@ def replay_check_pixels(rtq, osc, S, cams, st, pixels, img, **kw):
     FP64 radiance to 1e-4).  The pixel must equal the mean of its recorded
     paths' radiance bit for bit (FP32 sum in sample order over spp, as the
     accumulation forms it) and the mean of the oracle's replay values to 1e-4.
-    Returns counts (paths, vertices, certain answers, vertices whose t is
-    ill-conditioned and held to the FP32 bound, shading decisions near a
+    img: [n] floats, or [n, 3] (RGB) for a scene with materials, compared per
+    channel.  Returns counts (paths, vertices, certain answers, vertices whose t
+    is ill-conditioned and held to the FP32 bound, shading decisions near a
     threshold) and the largest t error in units of 2^-24 S / (|d| |cos|)."""
     offs = np.cumsum([0] + [c.n_pixels() if hasattr(c, "n_pixels") else c.w * c.h for c in cams])
     tot = dict(paths=0, vertices=0, certain=0, t_waived=0, ambiguous_shading=0, max_t_ulps=0.0)
+    rgb = np.ndim(img) == 2
+    nch = 3 if rgb else 1
     for g in np.asarray(pixels):
         view = int(np.searchsorted(offs, g, side="right") - 1)
         p = int(g - offs[view])
-        acc = np.float32(0.0)
-        ref = 0.0
+        acc = np.zeros(nch, np.float32)
+        ref = np.zeros(nch)
         for s_ in range(st.spp):
             nv, vi, vf, esc, rad = rtq.render_path_raw(S, cams, st, view, p, s_, **kw)
             code, info = osc.check_path(cams, st, view, p, s_, nv, vi, vf, esc, rad)
             assert code == 0, (f"pixel {g} sample {s_}: {oracle.PATH_CODES.get(code)} at ray {info['ray']}",
                                nv, vi[:nv + 1].tolist(), vf[:nv + 1].tolist(), esc, rad, info)
-            acc = np.float32(acc + rad)
-            ref += info["L"]
+            acc = (acc + np.asarray(rad, np.float32).reshape(nch)).astype(np.float32)
+            ref += info["Lc"] if rgb else info["L"]
             tot["paths"] += 1
             for k in ("vertices", "certain", "t_waived", "ambiguous_shading"):
                 tot[k] += info[k]
             tot["max_t_ulps"] = max(tot["max_t_ulps"], info["max_t_ulps"])
-        mean = np.float32(acc / np.float32(st.spp))
-        assert mean.view(np.uint32) == np.float32(img[g]).view(np.uint32), (g, mean, img[g])
+        mean = (acc / np.float32(st.spp)).astype(np.float32)
+        gv = np.asarray(img[g], np.float32).reshape(nch)
+        assert (mean.view(np.uint32) == gv.view(np.uint32)).all(), (g, mean, gv)
         ref /= st.spp
-        assert abs(float(img[g]) - ref) <= 1e-4 * abs(ref) + 1e-7, (g, img[g], ref)
+        assert (np.abs(gv - ref) <= 1e-4 * np.abs(ref).max() + 1e-7).all(), (g, gv, ref)
     return tot

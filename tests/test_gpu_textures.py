@@ -103,10 +103,44 @@ def test_textured_path_records_and_errors():
             exact += 1
     assert checked > 10 and exact > 10
     grad = torch.ones(sum(c.w * c.h for c in cams), device="cuda")
-    with pytest.raises(rtq.RtqError):
-        rtq.render_backward(S, cams, st, grad)
+    assert rtq.render_backward(S, cams, st, grad).numel() == scene.albedo.shape[0] * 16  # one entry per texel
     with pytest.raises(rtq.RtqError):
         S.set_textures(torch.zeros((scene.albedo.shape[0], 65, 65), device="cuda"))
     S.set_textures(None)
     rtq.render_backward(S, cams, st, grad)
     torch.cuda.synchronize()
+
+
+def test_texel_adjoint_vs_oracle():
+    """The adjoint of a textured scene is per texel: the GPU kernel takes each
+    vertex's texel index at shading (before the shadow ray reuses the lane's
+    (u, v)) and matches the oracle's pinned per-texel path-replay gradient,
+    with flagged paths carrying zero pixel weight on both sides."""
+    import torch
+    log("case: per-texel adjoint")
+    scene = sg.tiny_scene(31, n_inst=4, n_protos=2, nq=4, spread=1.0)
+    cams = [sg.Camera((0.0, -8.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 35.0, 64, 64)]
+    st = sg.RenderSettings(spp=2, depth=4, seed=31)
+    R = 4
+    tex = _texels(scene.albedo.shape[0], R, 5)
+    S = rtq.Scene(scene)
+    S.set_textures(torch.from_numpy(tex).cuda())
+    o = oracle.OracleScene(scene)
+    o.set_textures(tex)
+    ref, fl, _ = o.render(cams, st)
+    gp = np.random.default_rng(3).normal(size=ref.shape)
+    gp[fl != 0] = 0.0
+    g_ref, _, taint = o.grad(cams, st, gp, taint="path")
+    g = rtq.render_backward(S, cams, st, torch.from_numpy(gp.astype(np.float32)).cuda(),
+                            node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    assert g.shape == g_ref.shape == (scene.albedo.shape[0] * R * R,)
+    keep = taint == 0
+    scale = np.abs(g_ref[keep]).max()
+    err = np.abs(g[keep] - g_ref[keep])
+    log(f"  texels {keep.sum()} of {keep.size}, {int((g_ref[keep] != 0).sum())} with a gradient, max |grad| "
+        f"{scale:.4g}, max error {err.max():.3g}")
+    assert scale > 0 and (err <= 2e-4 * scale + 1e-4 * np.abs(g_ref[keep])).all(), err.max()
+    # texels no path reads get exactly zero on both sides
+    assert (g[keep & (g_ref == 0)] == 0).all()
