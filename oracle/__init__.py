@@ -62,13 +62,15 @@ def lib():
         i64 = ctypes.c_int64
         i32 = ctypes.c_int32
         L.orc_scene_create.restype = P
-        L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64]
+        L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64, P, P]
         L.orc_scene_destroy.argtypes = [P]
         L.orc_scene_set_albedo.argtypes = [P, P]
         L.orc_scene_set_textures.argtypes = [P, P, i32]
         L.orc_scene_set_environment.argtypes = [P, P, i32, i32]
         L.orc_scene_set_materials.argtypes = [P, P, i32, P]
         L.orc_bsdf_eval.argtypes = [P, P, P, i64, P, P]
+        L.orc_scene_capsules.argtypes = [P, P]
+        L.orc_scene_capsules.restype = i64
         L.orc_bsdf_sample.argtypes = [P, P, P, i64, P, P, P]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_get_threads.restype = ctypes.c_int
@@ -159,13 +161,19 @@ class OracleScene:
             ip=np.ascontiguousarray(scene.inst_proto, dtype=np.int32),
             x=np.ascontiguousarray(scene.inst_xform, dtype=np.float32),
         )
+        curves = getattr(scene, "curves", None)
+        if curves is not None:
+            self._keep["curves"] = np.ascontiguousarray(curves, dtype=np.float32)
+            self._keep["co"] = np.ascontiguousarray(scene.proto_curve_off, dtype=np.int64)
         k = self._keep
-        self.n_quads = int(k["quads"].shape[0])
+        # shading faces: every quad and every curve (in prototype order)
+        self.n_quads = int(k["albedo"].shape[0])
         self.tex_res = 0
         self.rgb = False
         self.h = lib().orc_scene_create(_p(k["verts"]), k["verts"].shape[0], _p(k["quads"]), k["quads"].shape[0],
                                         _p(k["vo"]), _p(k["qo"]), k["qo"].shape[0] - 1, _p(k["albedo"]),
-                                        _p(k["ip"]), _p(k["x"]), k["ip"].shape[0])
+                                        _p(k["ip"]), _p(k["x"]), k["ip"].shape[0], _p(k.get("curves")),
+                                        _p(k.get("co")))
         if not self.h:
             raise ValueError("oracle: singular instance transform")
 
@@ -203,6 +211,13 @@ class OracleScene:
         assert lib().orc_scene_set_materials(self.h, _p(m), int(m.shape[0]), _p(f)) == 0
         self._mats = (m, f)
         self.rgb = True
+
+    def capsules(self) -> np.ndarray:
+        """The capsules the curves are tessellated into: [n, 7] (a, b, radius)."""
+        n = int(lib().orc_scene_capsules(self.h, None))
+        out = np.zeros((n, 7))
+        lib().orc_scene_capsules(self.h, _p(out))
+        return out
 
     def set_textures(self, texels: Optional[np.ndarray]) -> None:
         """Per-face textures [n_quads, res, res] (row v, column u; FP32 values read

@@ -155,12 +155,25 @@ struct Bvh {
   }
 };
 
+// One capsule of a tessellated curve (object space): the points within r of
+// the segment [a, b].
+struct Cap {
+  V3 a, b;
+  double r;
+};
+
 struct Scene {
   int32_t P = 0;
   std::vector<V3> verts;           // object space, exact copies of the FP32 input
   std::vector<int32_t> quads;      // 4 per quad, local vertex index
   std::vector<int64_t> vo, qo;     // per-prototype offsets
-  std::vector<double> albedo;      // per unique quad
+  // curve prototypes (Section 5.2 "Curves"): pkind 1, their curves tessellated
+  // into capsules (kCapsPerCurve per curve, prototype order) at co[p] .. co[p + 1]
+  std::vector<int32_t> pkind;      // 0 quads, 1 curves
+  std::vector<int64_t> co;         // per-prototype capsule offsets
+  std::vector<Cap> caps;
+  std::vector<int64_t> fo;         // per-prototype face offsets: a face is a quad or a curve
+  std::vector<double> albedo;      // per unique face
   // optional per-face textures: res x res values per unique quad, row v, column u
   std::vector<double> tex;
   int32_t tex_res = 0;
@@ -336,6 +349,102 @@ double point_tri_dist(V3 p, V3 a, V3 b, V3 c) {
   return norm(p - (a + v * ab + w * ac));
 }
 
+// ---------------------------------------------------------------- curves
+// Section 5.2 renders the scene's curves (cubic Bezier, round) with Embree's
+// curve primitives.  Reading: a curve with control points P0..P3 and radii
+// r0..r3 is the chain of kCapsPerCurve capsules between its points at
+// parameters j / kCapsPerCurve, each point the FP32 rounding of the Bezier
+// evaluated in FP64 by de Casteljau's construction, each capsule's radius the
+// FP32 rounding of the mean of the radii at its ends.  A capsule is hit from
+// outside only (a ray starting inside it does not hit it).
+constexpr int kCapsPerCurve = 8;
+
+inline double lerp(double a, double b, double s) { return a + s * (b - a); }
+// de Casteljau evaluation of a cubic Bezier component
+double bez(double c0, double c1, double c2, double c3, double s) {
+  const double a = lerp(c0, c1, s), b = lerp(c1, c2, s), c = lerp(c2, c3, s);
+  const double d = lerp(a, b, s), e = lerp(b, c, s);
+  return lerp(d, e, s);
+}
+
+// Capsules of one curve: cp holds 4 control points (x, y, z, r), FP32 values.
+void tessellate_curve(const float* cp, Cap out[kCapsPerCurve]) {
+  V3 X[kCapsPerCurve + 1];
+  double R[kCapsPerCurve + 1];
+  for (int j = 0; j <= kCapsPerCurve; ++j) {
+    const double s = (double)j / kCapsPerCurve;
+    double v[4];
+    for (int c = 0; c < 4; ++c) v[c] = (double)(float)bez(cp[c], cp[4 + c], cp[8 + c], cp[12 + c], s);
+    X[j] = V3{v[0], v[1], v[2]};
+    R[j] = v[3];
+  }
+  for (int j = 0; j < kCapsPerCurve; ++j) out[j] = Cap{X[j], X[j + 1], (double)(float)(0.5 * (R[j] + R[j + 1]))};
+}
+
+// Distance from point p to the segment [a, b].
+double point_seg_dist(V3 p, V3 a, V3 b) {
+  const V3 ab = b - a;
+  const double e = dot(ab, ab);
+  const double u = e > 0.0 ? std::min(1.0, std::max(0.0, dot(p - a, ab) / e)) : 0.0;
+  return norm(p - (a + u * ab));
+}
+
+// Entry of ray (o, d) (object space, d not normalised) into capsule c: the
+// smallest t >= 0 at which the ray reaches the capsule's surface from outside.
+// A ray outside the infinite cylinder around the axis enters it at the smaller
+// root of the cylinder's quadratic; there it is on the capsule's body if the
+// axial coordinate lies within the segment, else it can only enter through the
+// end sphere on that side.  A ray starting inside the infinite cylinder but
+// beyond an end can only enter through that end's sphere.  Returns +inf when
+// the ray misses the capsule or starts inside it; *n receives the outward
+// normal (not normalised) and *y01 the axis parameter in [0, 1] of the hit.
+double cap_entry(V3 o, V3 d, const Cap& c, V3* n, double* y01) {
+  if (point_seg_dist(o, c.a, c.b) < c.r) return kInf;
+  const V3 ba = c.b - c.a, oa = o - c.a;
+  const double bb = dot(ba, ba), bd = dot(ba, d), bo = dot(ba, oa), dd = dot(d, d);
+  const double rr = c.r * c.r;
+  auto sphere = [&](V3 ctr, double y) {
+    const V3 oc = o - ctr;
+    const double b2 = dot(oc, d), c2 = dot(oc, oc) - rr;
+    const double disc = b2 * b2 - dd * c2;
+    if (disc < 0.0 || b2 >= 0.0) return kInf;  // missed, or moving away from it
+    const double t = (-b2 - std::sqrt(disc)) / dd;
+    *n = (o + t * d) - ctr;
+    *y01 = y;
+    return t;
+  };
+  if (bb <= 0.0) return sphere(c.a, 0.0);
+  const double A = bb * dd - bd * bd;
+  const double C = bb * dot(oa, oa) - bo * bo - rr * bb;
+  if (A <= 1e-30 * bb * dd || C < 0.0) {
+    // parallel to the axis, or inside the infinite cylinder beyond an end
+    V3 na;
+    double ya;
+    const double ta = sphere(c.a, 0.0);
+    na = *n;
+    ya = *y01;
+    const double tb = sphere(c.b, 1.0);
+    if (ta <= tb) {
+      *n = na;
+      *y01 = ya;
+      return ta;
+    }
+    return tb;
+  }
+  const double B = bb * dot(oa, d) - bo * bd;
+  const double disc = B * B - A * C;
+  if (disc < 0.0) return kInf;  // misses the infinite cylinder, hence the capsule
+  const double t = (-B - std::sqrt(disc)) / A;
+  if (t < 0.0) return kInf;  // both roots behind the origin
+  const double y = bo + t * bd;
+  if (y >= 0.0 && y <= bb) {
+    *n = (o + t * d) - (c.a + (y / bb) * ba);
+    *y01 = y / bb;
+    return t;
+  }
+  return y < 0.0 ? sphere(c.a, 0.0) : sphere(c.b, 1.0);
+}
+
 // ---------------------------------------------------------------- traversal
 inline bool slab(const Ray& r, const Box& b, double pad, double t_hi) {
   double tn = r.tmin, tf = t_hi;
@@ -354,15 +463,20 @@ inline bool slab(const Ray& r, const Box& b, double pad, double t_hi) {
   return tn <= tf;
 }
 
-// Visit every (instance, quad) whose inflated boxes intersect the ray over
-// [tmin, t_hi]; t_hi may shrink as the callback finds hits.  g_world is an
-// extra world-space inflation (graze distance).  mode 0 visits all quads.
+// Visit every (instance, quad) -- (instance, capsule) for a curve prototype --
+// whose inflated boxes intersect the ray over [tmin, t_hi]; t_hi may shrink as
+// the callback finds hits.  g_world is an extra world-space inflation (graze
+// distance).  mode 0 visits all primitives.  The callback gets the global quad
+// or capsule index.
 template <class Fn>
 void visit(const Scene& S, const Ray& r, int mode, double g_world, double& t_hi, Fn&& fn) {
   if (mode == 0) {
     for (int64_t i = 0; i < S.N; ++i) {
       const int32_t p = S.iproto[i];
-      for (int64_t q = S.qo[p]; q < S.qo[p + 1]; ++q) fn(i, q);
+      if (S.pkind[p])
+        for (int64_t c = S.co[p]; c < S.co[p + 1]; ++c) fn(i, c);
+      else
+        for (int64_t q = S.qo[p]; q < S.qo[p + 1]; ++q) fn(i, q);
     }
     return;
   }
@@ -400,10 +514,37 @@ void visit(const Scene& S, const Ray& r, int mode, double g_world, double& t_hi,
           st2.push_back(pn.right);
           continue;
         }
-        for (int32_t m = pn.start; m < pn.start + pn.count; ++m) fn(inst, S.qo[p] + pb.items[m]);
+        const int64_t base = S.pkind[p] ? S.co[p] : S.qo[p];
+        for (int32_t m = pn.start; m < pn.start + pn.count; ++m) fn(inst, base + pb.items[m]);
       }
     }
   }
+}
+
+// The ray in the object space of instance inst (same parameter t).
+inline Ray obj_ray(const Scene& S, int64_t inst, const Ray& r) {
+  const double* Y = &S.Xi[12 * inst];
+  return Ray{xform_point(Y, r.o), xform_vec(Y, r.d), r.tmin, r.tmax};
+}
+// World coordinates' extent of capsule c of instance inst, seen from o.
+double cap_extent(const Scene& S, int64_t inst, const Cap& c, V3 o) {
+  const double* X = &S.X[12 * inst];
+  const V3 a = xform_point(X, c.a), b = xform_point(X, c.b);
+  return std::max(std::max(maxabs(a - o), maxabs(b - o)), std::max(maxabs(a), maxabs(b)));
+}
+// World normal (not normalised) of an object-space normal of instance inst: A^-T n.
+inline V3 normal_to_world(const Scene& S, int64_t inst, V3 n) {
+  const double* Y = &S.Xi[12 * inst];
+  return {Y[0] * n.x + Y[4] * n.y + Y[8] * n.z, Y[1] * n.x + Y[5] * n.y + Y[9] * n.z,
+          Y[2] * n.x + Y[6] * n.y + Y[10] * n.z};
+}
+// Outward normal (not normalised) of capsule c at object point p: p minus its
+// closest point on the axis segment.
+inline V3 cap_normal(const Cap& c, V3 p) {
+  const V3 ab = c.b - c.a;
+  const double e = dot(ab, ab);
+  const double u = e > 0.0 ? std::min(1.0, std::max(0.0, dot(p - c.a, ab) / e)) : 0.0;
+  return p - (c.a + u * ab);
 }
 
 struct TraceOut {
@@ -424,6 +565,22 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   double t_hi = r.tmax;
   Key best;
   visit(S, r, mode, 0.0, t_hi, [&](int64_t inst, int64_t qg) {
+    const int32_t pr0 = S.iproto[inst];
+    if (S.pkind[pr0]) {
+      // capsule qg: entry in object space, key (t, inst, prim, half 0)
+      const int32_t prim = (int32_t)(qg - S.co[pr0]);
+      if ((int32_t)inst == ex.inst && prim == ex.prim && ex.half == 0) return;
+      const Ray ro = obj_ray(S, inst, r);
+      V3 n;
+      double y = 0.0;
+      const double t = cap_entry(ro.o, ro.d, S.caps[qg], &n, &y);
+      if (t < kInf && t > r.tmin && t <= t_hi) {
+        const Key k{t, (int32_t)inst, prim, 0, ((prim % kCapsPerCurve) + y) / kCapsPerCurve, 0.0};
+        if (key_less(k, best)) best = k;
+      }
+      if (best.t < t_hi) t_hi = best.t;
+      return;
+    }
     V3 w[4];
     quad_world(S, inst, qg, w);
     TriHit h[2];
@@ -454,13 +611,22 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   // pass 2: flags
   double t_end = std::isfinite(r.tmax) ? r.tmax + 1e-5 * r.tmax + 1e-6 * Sv / dn : kInf, win = 0;
   if (hit) {
-    V3 w[4];
-    quad_world(S, best.inst, S.qo[S.iproto[best.inst]] + best.prim, w);
-    S_best = std::max(Sv, extent(w));
+    V3 n;
+    const int32_t bp = S.iproto[best.inst];
+    if (S.pkind[bp]) {
+      const Cap& c = S.caps[S.co[bp] + best.prim];
+      S_best = std::max(Sv, cap_extent(S, best.inst, c, r.o));
+      const Ray ro = obj_ray(S, best.inst, r);
+      n = normal_to_world(S, best.inst, cap_normal(c, ro.o + best.t * ro.d));
+    } else {
+      V3 w[4];
+      quad_world(S, best.inst, S.qo[bp] + best.prim, w);
+      S_best = std::max(Sv, extent(w));
+      n = best.half == 0 ? cross(w[1] - w[0], w[3] - w[0]) : cross(w[3] - w[2], w[1] - w[2]);
+    }
     win = 1e-5 * best.t + 1e-6 * S_best / dn;
     t_end = best.t + win;
     if (best.t * dn < 1e-6 * S_best + r0) out.flags |= F_NEAR_ORIGIN;
-    const V3 n = best.half == 0 ? cross(w[1] - w[0], w[3] - w[0]) : cross(w[3] - w[2], w[1] - w[2]);
     out.cos_abs = std::fabs(dot(n, r.d)) / (norm(n) * dn);
     if (16.0 * std::ldexp(1.0, -24) * S_best > 1e-5 * best.t * dn * out.cos_abs) out.flags |= F_T_ILLCOND;
   }
@@ -470,6 +636,39 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   const V3 o0 = r.o + r.tmin * r.d;
   double t_lim = t_end;
   visit(S, r, mode, g_cull, t_lim, [&](int64_t inst, int64_t qg) {
+    const int32_t pr0 = S.iproto[inst];
+    if (S.pkind[pr0]) {
+      // capsule: near origin, near tie and graze (the ray passing within the
+      // graze distance of the capsule's surface), in object space with the
+      // world distance scaled by |A^-1|
+      const int32_t prim = (int32_t)(qg - S.co[pr0]);
+      if ((int32_t)inst == ex.inst && prim == ex.prim && ex.half == 0) return;
+      const Cap& c = S.caps[qg];
+      const double Sq = std::max(Sv, cap_extent(S, inst, c, r.o));
+      const double g = (1e-6 * Sq + r0) * S.ainv_frob[inst];
+      const Ray ro = obj_ray(S, inst, r);
+      const V3 oo0 = ro.o + r.tmin * ro.d;
+      if (std::fabs(point_seg_dist(oo0, c.a, c.b) - c.r) < g) out.flags |= F_NEAR_ORIGIN;
+      V3 n;
+      double y;
+      const double t = cap_entry(ro.o, ro.d, c, &n, &y);
+      const bool same = hit && inst == best.inst && prim == best.prim;
+      if (t < kInf && t > r.tmin && t <= t_end && !same) {
+        out.flags |= F_NEAR_TIE;
+        bool dup = false;
+        for (int cc = 0; cc < out.ncand; ++cc)
+          if (out.cand[2 * cc] == (int32_t)inst && out.cand[2 * cc + 1] == prim) dup = true;
+        if (!dup && out.ncand < 4) {
+          out.cand[2 * out.ncand] = (int32_t)inst;
+          out.cand[2 * out.ncand + 1] = prim;
+          out.ncand++;
+        }
+      }
+      V3 q;
+      const double dist = seg_dist(ro.o, ro.d, r.tmin, t_end, c.a, c.b, &q);
+      if (std::fabs(dist - c.r) < g) out.flags |= F_GRAZE;
+      return;
+    }
     V3 w[4];
     quad_world(S, inst, qg, w);
     const int32_t prim = (int32_t)(qg - S.qo[S.iproto[inst]]);
@@ -611,6 +810,48 @@ TriClass classify_tri(const Ray& r, double dn, double Sv, V3 w0, V3 w1, V3 w2, c
   return c;
 }
 
+// Capsule c of instance inst against ray r (world) -- the same classes as a
+// triangle: rounding can move the ray across the capsule's silhouette (the
+// ray passes within the graze distance of its surface), its start point may
+// lie within that distance of the surface, or the hit may lie next to tmax.
+// Distances are taken in object space, the world graze distance scaled by
+// |A^-1|.
+TriClass classify_cap(const Scene& S, int64_t inst, const Cap& c, const Ray& r, double dn, double Sv, double r0) {
+  TriClass k;
+  const double Sq = std::max(Sv, cap_extent(S, inst, c, r.o));
+  k.S = Sq;
+  const double thr = (1e-6 * Sq + r0) * S.ainv_frob[inst];
+  const Ray ro = obj_ray(S, inst, r);
+  const V3 o0 = ro.o + r.tmin * ro.d;
+  const bool near_org = std::fabs(point_seg_dist(o0, c.a, c.b) - c.r) < thr;
+  const double lg = line_seg_dist(ro.o, ro.d, c.a, c.b);
+  const bool graze = std::fabs(lg - c.r) < thr;
+  V3 n;
+  double y;
+  double t = cap_entry(ro.o, ro.d, c, &n, &y);
+  const bool inside = t < kInf;
+  double cosv = 0.0;
+  if (inside) {
+    cosv = std::fabs(dot(n, ro.d)) / (norm(n) * norm(ro.d));
+  } else {
+    // no exact hit: the parameter of the ray's closest approach to the axis
+    const V3 ab = c.b - c.a, w0 = ro.o - c.a;
+    const double a = dot(ro.d, ro.d), b = dot(ro.d, ab), e = dot(ab, ab);
+    const double dd = dot(ro.d, w0), ee = dot(ab, w0);
+    const double den = a * e - b * b;
+    t = den > 1e-300 * a * e ? (b * ee - e * dd) / den : -dd / a;
+    if (near_org && !(t > r.tmin)) t = r.tmin;
+  }
+  k.t = t;
+  const bool in_iv = t > r.tmin && t <= r.tmax;
+  const bool near_tmax = std::isfinite(r.tmax) && std::fabs(t - r.tmax) <= 1e-5 * r.tmax + 1e-6 * Sq / dn;
+  k.illcond = !(cosv > 0.0) || 16.0 * std::ldexp(1.0, -24) * Sq > 1e-5 * std::fabs(t) * dn * cosv;
+  k.tulp = cosv > 0.0 ? std::ldexp(1.0, -24) * Sq / (dn * cosv) : kInf;
+  k.certain = inside && in_iv && !graze && !near_org && !near_tmax;
+  k.possible = (inside || graze || near_org) && (in_iv || near_org || near_tmax);
+  return k;
+}
+
 AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, int mode) {
   AcceptSet A;
   const double dn = norm(r.d);
@@ -620,6 +861,13 @@ AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, in
   }
   const double Sv = std::max(1.0, maxabs(r.o));
   auto each_tri = [&](int64_t inst, int64_t qg, auto&& fn) {
+    const int32_t pr0 = S.iproto[inst];
+    if (S.pkind[pr0]) {
+      const int32_t prim = (int32_t)(qg - S.co[pr0]);
+      if ((int32_t)inst == ex.inst && prim == ex.prim && ex.half == 0) return;
+      fn((int32_t)inst, prim, 0, classify_cap(S, inst, S.caps[qg], r, dn, Sv, r0));
+      return;
+    }
     V3 w[4];
     quad_world(S, inst, qg, w);
     const int32_t prim = (int32_t)(qg - S.qo[S.iproto[inst]]);
@@ -1057,9 +1305,17 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     }
     V3 wq[4];
     const int32_t pr = S.iproto[h.best.inst];
-    const int64_t face = S.qo[pr] + h.best.prim;
-    quad_world(S, h.best.inst, face, wq);
-    V3 n = h.best.half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
+    const bool is_cap = S.pkind[pr] != 0;
+    const int64_t face = S.fo[pr] + (is_cap ? h.best.prim / kCapsPerCurve : h.best.prim);
+    V3 n;
+    if (is_cap) {
+      // the capsule's outward normal at the hit, mapped by A^-T
+      const Ray ro = obj_ray(S, h.best.inst, ray);
+      n = normal_to_world(S, h.best.inst, cap_normal(S.caps[S.co[pr] + h.best.prim], ro.o + h.best.t * ro.d));
+    } else {
+      quad_world(S, h.best.inst, S.qo[pr] + h.best.prim, wq);
+      n = h.best.half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
+    }
     n = normalize(n);
     const double nd = dot(n, ray.d);
     uint32_t vshade = 0;  // shading decisions of this vertex within rounding of a threshold
@@ -1380,7 +1636,9 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     const int32_t inst = I[0], prim = I[1], half = I[2], shadow = I[3];
     if (inst < 0 || inst >= S.N || prim < 0 || half < 0 || half > 1) return fail(2, k);
     const int32_t pr = S.iproto[inst];
-    if (prim >= S.qo[pr + 1] - S.qo[pr]) return fail(2, k);
+    const bool is_cap = S.pkind[pr] != 0;
+    if (prim >= (is_cap ? S.co[pr + 1] - S.co[pr] : S.qo[pr + 1] - S.qo[pr]) || (is_cap && half != 0))
+      return fail(2, k);
     int info = 0;
     double ulps = 0.0;
     const int jc = judge_closest(A, inst, prim, half, (double)F[0], &info, &ulps);
@@ -1390,11 +1648,18 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     R.n_vert++;
     if (info & 1) R.n_certain++;
     if (info & 2) R.n_waived++;
-    const int64_t face = S.qo[pr] + prim;
+    const int64_t face = S.fo[pr] + (is_cap ? prim / kCapsPerCurve : prim);
     if (I[4] != (int32_t)face) return fail(5, k);
     V3 wq[4];
-    quad_world(S, inst, face, wq);
-    V3 n = half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
+    V3 n;
+    if (is_cap) {
+      // the capsule's outward normal at the GPU's t along the recorded ray
+      const Ray ro = obj_ray(S, inst, ray);
+      n = normal_to_world(S, inst, cap_normal(S.caps[S.co[pr] + prim], ro.o + (double)F[0] * ro.d));
+    } else {
+      quad_world(S, inst, S.qo[pr] + prim, wq);
+      n = half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
+    }
     n = normalize(n);
     const V3 dh = normalize(ray.d);
     const double nd = dot(n, dh);
@@ -1640,9 +1905,13 @@ int orc_get_threads() { return threads(); }
 
 void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox(ctr, key, out); }
 
+// A prototype holds quads or, when proto_curve_off gives it curves, only
+// curves: 16 floats each (4 control points x, y, z, radius), tessellated into
+// capsules here.  albedo: one per face (quad or curve) in prototype order.
 void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads, int64_t n_quads,
                        const int64_t* proto_vert_off, const int64_t* proto_quad_off, int32_t n_protos,
-                       const float* albedo, const int32_t* inst_proto, const float* inst_xform, int64_t n_inst) {
+                       const float* albedo, const int32_t* inst_proto, const float* inst_xform, int64_t n_inst,
+                       const float* curves, const int64_t* proto_curve_off) {
   Scene* S = new Scene;
   S->P = n_protos;
   S->verts.resize(n_verts);
@@ -1650,8 +1919,25 @@ void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads
   S->quads.assign(quads, quads + 4 * n_quads);
   S->vo.assign(proto_vert_off, proto_vert_off + n_protos + 1);
   S->qo.assign(proto_quad_off, proto_quad_off + n_protos + 1);
-  S->albedo.resize(n_quads);
-  for (int64_t i = 0; i < n_quads; ++i) S->albedo[i] = albedo ? (double)albedo[i] : 0.5;
+  S->pkind.assign(n_protos, 0);
+  S->co.assign(n_protos + 1, 0);
+  S->fo.assign(n_protos + 1, 0);
+  for (int32_t p = 0; p < n_protos; ++p) {
+    const int64_t nc = proto_curve_off ? proto_curve_off[p + 1] - proto_curve_off[p] : 0;
+    if (nc > 0) {
+      S->pkind[p] = 1;
+      for (int64_t k = proto_curve_off[p]; k < proto_curve_off[p + 1]; ++k) {
+        Cap cc[kCapsPerCurve];
+        tessellate_curve(curves + 16 * k, cc);
+        for (int j = 0; j < kCapsPerCurve; ++j) S->caps.push_back(cc[j]);
+      }
+    }
+    S->co[p + 1] = (int64_t)S->caps.size();
+    S->fo[p + 1] = S->fo[p] + (nc > 0 ? nc : S->qo[p + 1] - S->qo[p]);
+  }
+  const int64_t n_faces = S->fo[n_protos];
+  S->albedo.resize(n_faces);
+  for (int64_t i = 0; i < n_faces; ++i) S->albedo[i] = albedo ? (double)albedo[i] : 0.5;
   S->N = n_inst;
   S->iproto.assign(inst_proto, inst_proto + n_inst);
   S->X.resize(12 * n_inst);
@@ -1672,8 +1958,25 @@ void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads
   S->proto_box.resize(n_protos);
   S->proto_bvh.resize(n_protos);
   parallel_for(n_protos, threads(), [&](int64_t p, int) {
-    std::vector<Box> qb(S->qo[p + 1] - S->qo[p]);
     Box all;
+    if (S->pkind[p]) {
+      // capsule boxes: the segment's box grown by the radius
+      std::vector<Box> cb(S->co[p + 1] - S->co[p]);
+      for (int64_t c = S->co[p]; c < S->co[p + 1]; ++c) {
+        const Cap& k = S->caps[c];
+        Box b;
+        b.grow(k.a - V3{k.r, k.r, k.r});
+        b.grow(k.a + V3{k.r, k.r, k.r});
+        b.grow(k.b - V3{k.r, k.r, k.r});
+        b.grow(k.b + V3{k.r, k.r, k.r});
+        cb[c - S->co[p]] = b;
+        all.grow(b);
+      }
+      S->proto_box[p] = all;
+      S->proto_bvh[p].build(cb);
+      return;
+    }
+    std::vector<Box> qb(S->qo[p + 1] - S->qo[p]);
     for (int64_t q = S->qo[p]; q < S->qo[p + 1]; ++q) {
       Box b;
       for (int k = 0; k < 4; ++k) b.grow(S->verts[S->vo[p] + S->quads[4 * q + k]]);
@@ -1737,6 +2040,19 @@ void orc_bsdf_sample(const double* m, const double* nrm, const double* wo, int64
   }
 }
 
+// The capsules of every curve prototype, for tests: 7 doubles each (a, b,
+// radius), prototype order.  Returns their count.
+int64_t orc_scene_capsules(void* s, double* out) {
+  const Scene& S = *static_cast<Scene*>(s);
+  if (out)
+    for (size_t k = 0; k < S.caps.size(); ++k) {
+      const Cap& c = S.caps[k];
+      const double v[7] = {c.a.x, c.a.y, c.a.z, c.b.x, c.b.y, c.b.z, c.r};
+      for (int j = 0; j < 7; ++j) out[7 * k + j] = v[j];
+    }
+  return (int64_t)S.caps.size();
+}
+
 // Principled materials (Section 5.4): n_mat entries of (tint r, g, b,
 // roughness, metallic, specular) and one material index per unique quad; n_mat = 0
 // removes them (every face Lambertian again).  Returns -1 on a bad argument.
@@ -1768,6 +2084,9 @@ int orc_scene_set_albedo(void* s, const double* albedo) {
 int orc_scene_set_textures(void* s, const double* texels, int32_t res) {
   Scene* S = static_cast<Scene*>(s);
   if (res < 0 || (res > 0 && !texels)) return -1;
+  if (res > 0)
+    for (int32_t k : S->pkind)
+      if (k) return -1;  // textures are per quad face: a scene with curves has none
   S->tex_res = res;
   S->tex.clear();
   if (res > 0) S->tex.assign(texels, texels + S->albedo.size() * (size_t)res * (size_t)res);

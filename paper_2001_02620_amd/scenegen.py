@@ -39,9 +39,13 @@ class Scene:
     quads: np.ndarray          # int32 [Q, 4], indices local to the prototype
     proto_vert_off: np.ndarray  # int64 [P + 1]
     proto_quad_off: np.ndarray  # int64 [P + 1]
-    albedo: np.ndarray         # float32 [Q]
+    albedo: np.ndarray         # float32 [F]: one per face (quad, or curve) in prototype order
     inst_proto: np.ndarray     # int32 [N]
     inst_xform: np.ndarray     # float32 [N, 12]
+    # curves (a prototype holds quads or curves): 4 control points (x, y, z,
+    # radius) per cubic Bezier curve, and per-prototype offsets
+    curves: Optional[np.ndarray] = None           # float32 [C, 16]
+    proto_curve_off: Optional[np.ndarray] = None  # int64 [P + 1]
 
     @property
     def n_protos(self) -> int:
@@ -55,6 +59,21 @@ class Scene:
     def n_instances(self) -> int:
         return int(self.inst_proto.shape[0])
 
+    @property
+    def n_curves(self) -> int:
+        return 0 if self.curves is None else int(self.curves.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        """Shading faces: every quad and every curve."""
+        return self.n_quads + self.n_curves
+
+    def proto_face_off(self) -> np.ndarray:
+        """First face of each prototype (its quads, or its curves)."""
+        nq = np.diff(self.proto_quad_off)
+        nc = np.diff(self.proto_curve_off) if self.proto_curve_off is not None else np.zeros_like(nq)
+        return np.concatenate([[0], np.cumsum(nq + nc)]).astype(np.int64)
+
     def instanced_quads(self) -> int:
         counts = np.diff(self.proto_quad_off)
         return int(counts[self.inst_proto].sum())
@@ -63,7 +82,13 @@ class Scene:
         P = self.n_protos
         assert self.verts.dtype == np.float32 and self.verts.ndim == 2 and self.verts.shape[1] == 3
         assert self.quads.dtype == np.int32 and self.quads.shape[1] == 4
-        assert self.albedo.dtype == np.float32 and self.albedo.shape[0] == self.quads.shape[0]
+        assert self.albedo.dtype == np.float32 and self.albedo.shape[0] == self.n_faces
+        if self.curves is not None:
+            assert self.curves.dtype == np.float32 and self.curves.ndim == 2 and self.curves.shape[1] == 16
+            assert self.proto_curve_off[-1] == self.curves.shape[0]
+            nq, nc = np.diff(self.proto_quad_off), np.diff(self.proto_curve_off)
+            assert ((nq > 0) != (nc > 0)).all(), "a prototype holds quads or curves"
+            assert (self.curves[:, 3::4] >= 0).all()
         assert self.proto_vert_off[-1] == self.verts.shape[0]
         assert self.proto_quad_off[-1] == self.quads.shape[0]
         assert self.inst_proto.dtype == np.int32 and self.inst_xform.dtype == np.float32
@@ -426,6 +451,57 @@ def tiny_scene(seed: int, n_inst: int = 4, n_protos: int = 2, nq: int = 4, sprea
     s = rng.uniform(0.5, 2.0, size=n_inst)
     t = rng.uniform(-spread, spread, size=(n_inst, 3))
     return _concat(protos, rng, inst_proto, compose_xforms(R, s, t))
+
+
+def blade_curves(rng: np.random.Generator, n: int, height: float, radius: float, spread: float) -> np.ndarray:
+    """n grass-blade curves rooted on a disk of the given spread: cubic Beziers
+    rising to `height` with a random lean, radius tapering from `radius` at the
+    root to a tenth of it at the tip: float32 [n, 16]."""
+    c = np.zeros((n, 16), np.float64)
+    root = np.c_[rng.uniform(-spread, spread, (n, 2)), np.zeros(n)]
+    lean = rng.normal(size=(n, 2)) * 0.35 * height
+    for k in range(4):
+        f = k / 3.0
+        c[:, 4 * k + 0] = root[:, 0] + lean[:, 0] * f * f
+        c[:, 4 * k + 1] = root[:, 1] + lean[:, 1] * f * f
+        c[:, 4 * k + 2] = height * f * rng.uniform(0.8, 1.2, n)
+        c[:, 4 * k + 3] = radius * (1.0 - 0.9 * f)
+    return c.astype(np.float32)
+
+
+def curve_scene(seed: int, n_inst: int = 6, n_curves: int = 24, spread: float = 2.5, with_ground: bool = True) -> Scene:
+    """Tufts of curves (Section 5.2: the scene's curves) instanced over a small
+    quad ground: prototype 0 the ground grid (when asked), the others curve
+    tufts, each tuft instance rotated about z and scaled uniformly."""
+    rng = np.random.default_rng(seed)
+    protos_q = [grid_proto(rng, 6, 6, spread + 1.0, spread + 1.0, 0.05)] if with_ground else []
+    tufts = [blade_curves(rng, n_curves, rng.uniform(0.6, 1.2), rng.uniform(0.02, 0.05), 0.4) for _ in range(2)]
+    verts = [v for v, _ in protos_q]
+    quads = [q for _, q in protos_q]
+    vo = np.cumsum([0] + [v.shape[0] for v in verts] + [0] * len(tufts)).astype(np.int64)
+    qo = np.cumsum([0] + [q.shape[0] for q in quads] + [0] * len(tufts)).astype(np.int64)
+    co = np.cumsum([0] * (len(protos_q) + 1) + [t.shape[0] for t in tufts]).astype(np.int64)
+    P = len(protos_q) + len(tufts)
+    n_faces = int(qo[-1] + co[-1])
+    albedo = rng.uniform(0.2, 0.8, n_faces).astype(np.float32)
+    inst_proto = list(range(len(protos_q))) + list(rng.integers(len(protos_q), P, n_inst))
+    xf = []
+    for k, p in enumerate(inst_proto):
+        if p < len(protos_q):
+            xf.append([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0])
+            continue
+        a = rng.uniform(0, 2 * math.pi)
+        sc = rng.uniform(0.7, 1.4)
+        tx, ty = rng.uniform(-spread, spread, 2)
+        ca, sa = math.cos(a) * sc, math.sin(a) * sc
+        xf.append([ca, -sa, 0, tx, sa, ca, 0, ty, 0, 0, sc, 0])
+    s = Scene(verts=np.concatenate(verts).astype(np.float32) if verts else np.zeros((0, 3), np.float32),
+              quads=np.concatenate(quads).astype(np.int32) if quads else np.zeros((0, 4), np.int32),
+              proto_vert_off=vo, proto_quad_off=qo, albedo=albedo,
+              inst_proto=np.asarray(inst_proto, np.int32), inst_xform=np.asarray(xf, np.float32),
+              curves=np.concatenate(tufts).astype(np.float32), proto_curve_off=co)
+    s.validate()
+    return s
 
 
 def identity_xform(n: int = 1) -> np.ndarray:

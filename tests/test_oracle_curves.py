@@ -1,0 +1,238 @@
+"""Pins of the oracle's curves (Section 5.2 "Curves": cubic Bezier curves with
+a radius, rendered as chains of capsules) against closed forms, brute force
+and invariants."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2001_02620_amd import scenegen as sg
+
+K = 8  # capsules per curve
+
+
+def _curve_scene(curves, xforms=None, albedo=0.5):
+    """Curve prototype(s) only: one prototype holding `curves` [n, 16]."""
+    curves = np.asarray(curves, np.float32).reshape(-1, 16)
+    if xforms is None:
+        xforms = sg.identity_xform(1)
+    xforms = np.asarray(xforms, np.float32).reshape(-1, 12)
+    s = sg.Scene(verts=np.zeros((0, 3), np.float32), quads=np.zeros((0, 4), np.int32),
+                 proto_vert_off=np.array([0, 0], np.int64), proto_quad_off=np.array([0, 0], np.int64),
+                 albedo=np.full(curves.shape[0], albedo, np.float32),
+                 inst_proto=np.zeros(xforms.shape[0], np.int32), inst_xform=xforms, curves=curves,
+                 proto_curve_off=np.array([0, curves.shape[0]], np.int64))
+    s.validate()
+    return s
+
+
+def _straight(x0=-2.0, x1=2.0, r=0.25, y=0.0, z=0.0):
+    """A straight curve along x with evenly spaced control points and a
+    constant radius (the Bezier is then linear in its parameter)."""
+    xs = np.linspace(x0, x1, 4)
+    return [v for x in xs for v in (x, y, z, r)]
+
+
+def _rays(o, d):
+    o = np.atleast_2d(np.asarray(o, np.float64))
+    d = np.atleast_2d(np.asarray(d, np.float64))
+    r = np.zeros((o.shape[0], 8), np.float64)
+    r[:, 0:3] = o
+    r[:, 3:6] = d
+    r[:, 7] = np.inf
+    return r
+
+
+def test_tessellation_points_lie_on_the_bezier():
+    """Capsule ends are the Bezier's points at j / 8 (rounded to FP32): for a
+    straight curve with evenly spaced control points they are evenly spaced on
+    the line; for the standard cubic approximation of a quarter circle (handle
+    length 0.5523 R) they lie within its known radial error (2.7e-4 R) of the
+    circle; the curve's ends are the end control points exactly."""
+    o = oracle.OracleScene(_curve_scene(_straight()))
+    c = o.capsules()
+    assert c.shape == (K, 7)
+    xs = np.concatenate([c[:, 0], c[-1:, 3]])
+    np.testing.assert_allclose(xs, np.linspace(-2, 2, K + 1), atol=1e-6)
+    assert (c[:, 6] == np.float32(0.25)).all()
+    R, h = 3.0, 0.5523 * 3.0
+    arc = [R, 0, 0, 0.1, R, h, 0, 0.1, h, R, 0, 0.1, 0, R, 0, 0.1]
+    c = oracle.OracleScene(_curve_scene(arc)).capsules()
+    pts = np.concatenate([c[:, 0:3], c[-1:, 3:6]])
+    rad = np.linalg.norm(pts[:, :2], axis=1)
+    assert (np.abs(rad - R) < 2.8e-4 * R + 1e-6).all(), rad - R
+    assert tuple(pts[0]) == (R, 0, 0) and tuple(pts[-1]) == (0, R, 0)
+    # radii: the FP32 mean of the radius at the ends; a tapered curve decreases
+    taper = [0, 0, 0, 0.4, 1, 0, 0, 0.3, 2, 0, 0, 0.2, 3, 0, 0, 0.1]
+    cr = oracle.OracleScene(_curve_scene(taper)).capsules()[:, 6]
+    # radii 0.4 .. 0.1 at evenly spaced control points: r(s) = 0.4 - 0.3 s, so
+    # the first capsule's radius is the mean of r(0) and r(1/8), 0.38125
+    assert (np.diff(cr) < 0).all() and abs(cr[0] - 0.38125) < 1e-7
+
+
+def test_capsule_closed_forms():
+    """Straight curve of radius r along x: a ray toward the axis at offset h
+    meets the body at t = D - sqrt(r^2 - h^2); a ray along the axis meets the
+    end sphere at D - r; a ray passing at h > r misses; a ray starting inside
+    the capsule does not hit it (capsules are entered from outside only), also
+    when it runs along the axis toward the last capsule's end sphere."""
+    r = 0.25
+    o = oracle.OracleScene(_curve_scene(_straight(r=r)))
+    hs = np.array([0.0, 0.1, 0.2, 0.249])
+    rays = _rays([[0.3, h, 5.0] for h in hs], [[0, 0, -1.0]] * len(hs))
+    out = o.trace(rays)
+    expect = 5.0 - np.sqrt(r * r - hs ** 2)
+    np.testing.assert_allclose(out.t, expect, rtol=1e-12)
+    assert (out.inst == 0).all() and (out.half == 0).all()
+    # the hit capsule is the one covering x = 0.3 (each spans 0.5 along x)
+    assert (out.prim == int((0.3 + 2.0) / 0.5)).all()
+    end = o.trace(_rays([[-6.0, 0.05, 0.0]], [[1.0, 0, 0]]))
+    np.testing.assert_allclose(end.t, [-2.0 - math.sqrt(r * r - 0.05 ** 2) + 6.0], rtol=1e-12)
+    assert end.prim[0] == 0
+    miss = o.trace(_rays([[0.3, 0.26, 5.0], [0.3, 0.0, 0.1]], [[0, 0, -1.0], [0, 0, 1.0]]))
+    assert (miss.inst == -1).all() and np.isinf(miss.t).all()
+    # a ray along +z from the axis point at x = 0.3: inside capsule 4 and
+    # nowhere else near it
+    inside = o.trace(_rays([[0.3, 0.0, 0.0], [1.7, 0.0, 0.0], [1.7, 0.1, 0.0]],
+                           [[0, 0, 1.0], [1.0, 0, 0], [1.0, 0.0, 0.0]]))
+    assert (inside.inst == -1).all()
+
+
+def test_curve_bvh_equals_brute_force_and_instances():
+    """Over a tuft scene with ground, the BVH traversal equals brute force bit
+    for bit (flags included); an instanced straight curve's hits equal the
+    prototype's hits under the FP64 inverse transform."""
+    scene = sg.curve_scene(3)
+    o = oracle.OracleScene(scene)
+    rng = np.random.default_rng(5)
+    rays = sg.random_rays(rng, 4000, [-3, -3, 0.05], [3, 3, 1.5], [-3, -3, 0.0], [3, 3, 1.2])
+    a, b = o.trace(rays), o.trace(rays, brute=True)
+    for f in ("t", "inst", "prim", "half", "flags"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    cap_hits = (a.inst >= 1).sum()
+    assert cap_hits > 200, cap_hits
+    # instance invariance: rotation about z by 30 degrees, scale 1.5, translation
+    c, s_ = math.cos(math.pi / 6) * 1.5, math.sin(math.pi / 6) * 1.5
+    X = np.array([[c, -s_, 0, 1.0, s_, c, 0, -2.0, 0, 0, 1.5, 0.5]], np.float32)
+    o1 = oracle.OracleScene(_curve_scene(_straight(), xforms=X))
+    o0 = oracle.OracleScene(_curve_scene(_straight()))
+    A = X.reshape(3, 4).astype(np.float64)
+    Ainv = np.linalg.inv(A[:, :3])
+    rw = sg.random_rays(rng, 2000, [-4, -5, -2], [6, 2, 3], [-1, -4, 0], [3, 0, 1])
+    ro = rw.astype(np.float64).copy()
+    ro[:, 0:3] = (rw[:, 0:3].astype(np.float64) - A[:, 3]) @ Ainv.T
+    ro[:, 3:6] = rw[:, 3:6].astype(np.float64) @ Ainv.T
+    hw, h0 = o1.trace(rw), o0.trace(ro)
+    assert np.array_equal(hw.inst, h0.inst) and (hw.inst >= 0).sum() > 100
+    m = hw.inst >= 0
+    np.testing.assert_allclose(hw.t[m], h0.t[m], rtol=1e-12)
+
+
+def test_curve_flags():
+    """A ray passing the capsule's surface within the graze distance is
+    flagged GRAZE; a ray through the middle of the body is not flagged; a ray
+    starting on the surface is flagged NEAR_ORIGIN."""
+    r = 0.25
+    o = oracle.OracleScene(_curve_scene(_straight(r=r)))
+    rays = _rays([[0.3, r * (1 + 1e-9), 5.0], [0.3, r * (1 - 1e-9), 5.0], [0.3, 0.0, 5.0],
+                  [0.3, 0.0, r]], [[0, 0, -1.0], [0, 0, -1.0], [0, 0, -1.0], [0, 1.0, 1.0]])
+    out = o.trace(rays)
+    assert out.flags[0] & oracle.F_GRAZE and out.flags[1] & oracle.F_GRAZE
+    assert out.flags[2] == 0 and out.inst[2] == 0
+    assert out.flags[3] & oracle.F_NEAR_ORIGIN
+    # the acceptance check: the grazing ray may hit or miss, the central ray must hit
+    code, info = o.accept(rays[:3].astype(np.float32), np.array([-1, 0, -1]), np.array([-1, 4, -1]),
+                          np.array([np.inf, out.t[1], np.inf], np.float32))
+    assert code[0] == 0 and code[1] == 0 and code[2] == 2
+
+
+def test_curve_sky_closed_form():
+    """A curve floating under the constant sky, no sun, depth 2: a convex
+    capsule never sees itself, so every camera sample that hits a capsule
+    carries a L_sky and every other one L_sky; a pixel of two samples is one
+    of L_sky, (1 + a) L_sky / 2 and a L_sky."""
+    a = float(np.float32(0.6))
+    o = oracle.OracleScene(_curve_scene(_straight(r=0.3), albedo=a))
+    cams = [sg.Camera((0.0, -6.0, 1.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 40.0, 32, 24)]
+    st = sg.RenderSettings(spp=2, depth=2, seed=3)
+    st.E = 0.0
+    img, _, _ = o.render(cams, st)
+    L = st.L_sky
+    k = np.rint((L - img) / ((1.0 - a) * L / 2)).astype(int)  # samples on a capsule
+    assert set(np.unique(k)) <= {0, 1, 2} and (k == 2).sum() > 50 and (k == 1).sum() > 0
+    np.testing.assert_allclose(img, ((2 - k) * L + k * a * L) / 2, rtol=1e-12)
+
+
+def test_curve_gradient_forms_agree():
+    """Curves are faces of their own (one albedo per curve): PRB = dual
+    numbers = central differences on a tuft scene with ground."""
+    scene = sg.curve_scene(4, n_inst=4, n_curves=12)
+    o = oracle.OracleScene(scene)
+    cams = [sg.Camera((0.0, -6.0, 1.5), (0.0, 0.0, 0.4), (0.0, 0.0, 1.0), 45.0, 24, 24)]
+    st = sg.RenderSettings(spp=2, depth=3, seed=5)
+    rng = np.random.default_rng(2)
+    alb = scene.albedo.astype(np.float64)
+    o.set_albedo(alb + rng.uniform(-0.1, 0.1, alb.shape))
+    T, _, _ = o.render(cams, st)
+    o.set_albedo(alb)
+    I, _, _ = o.render(cams, st)
+    gp = 2 * (I - T) / I.size
+    g, _, _ = o.grad(cams, st, gp)
+    nq = scene.n_quads
+    assert np.abs(g[nq:]).max() > 0, "no curve face has a gradient"
+    e = rng.normal(size=alb.shape)
+    dI, _ = o.tangent(cams, st, e)
+    assert abs((g * e).sum() - (gp * dI).sum()) <= 1e-10 * abs((gp * dI).sum())
+
+    def loss(x):
+        o.set_albedo(x)
+        Ix, _, _ = o.render(cams, st)
+        return ((Ix - T) ** 2).sum() / I.size
+
+    h = 1e-5
+    f = nq + int(np.argmax(np.abs(g[nq:])))
+    ef = np.zeros_like(alb)
+    ef[f] = 1.0
+    fd = (loss(alb + h * ef) - loss(alb - h * ef)) / (2 * h)
+    assert abs(fd - g[f]) <= 1e-6 * abs(g[f])
+
+
+def test_curve_scene_rejects_textures():
+    o = oracle.OracleScene(sg.curve_scene(1))
+    with pytest.raises(AssertionError):
+        o.set_textures(np.zeros((o.n_quads, 2, 2), np.float32))
+
+
+@pytest.mark.parametrize("turned", [False, True])
+def test_curve_sun_shading_closed_form(turned):
+    """A straight curve along x seen from high above, the sun overhead: a
+    sample on the capsule carries a L_sky + a E cos / pi with cos the z part of
+    the outward normal, so cos lies in (0, 1] and its mean over the footprint is
+    the area-weighted mean of sqrt(1 - (y / r)^2) over the body (pi / 4) and of
+    n_z over the two end half-disks (2 / 3).  Turned: the same curve built
+    along y and placed by a quarter turn about x and one about y, so the world
+    normal depends on the instance transform."""
+    a, r, L = float(np.float32(0.5)), 0.3, 0.25
+    if turned:
+        # object y -> world x: a quarter turn about x (y -> z), then about y (z -> x)
+        proto = [v for y in np.linspace(-2, 2, 4) for v in (0.0, y, 0.0, r)]
+        Rx = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], np.float64)
+        Ry = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], np.float64)
+        M = Ry @ Rx
+        assert np.allclose(M @ [0, 1, 0], [1, 0, 0])
+        X = np.concatenate([M, np.zeros((3, 1))], axis=1).reshape(1, 12)
+        o = oracle.OracleScene(_curve_scene(proto, xforms=X, albedo=a))
+    else:
+        o = oracle.OracleScene(_curve_scene(_straight(r=r), albedo=a))
+    # far away with a narrow field, so the camera rays are nearly parallel
+    cams = [sg.Camera((0.0, 0.0, 200.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 1.5, 128, 128)]
+    st = sg.RenderSettings(spp=1, depth=2, seed=9, light_dir=(0.0, 0.0, 1.0), E=math.pi, L_sky=L)
+    img, fl, _ = o.render(cams, st)
+    hit = np.abs(img - L) > 1e-9
+    cos = (img[hit] - a * L) / a
+    assert hit.sum() > 1000 and (cos > 0).all() and (cos <= 1 + 1e-12).all()
+    body, disks = 4.0 * 2 * r, math.pi * r * r
+    expect = (body * math.pi / 4 + disks * 2 / 3) / (body + disks)
+    # 1600 samples: the mean's standard error is about 0.003
+    assert abs(cos.mean() - expect) < 0.009, (cos.mean(), expect)
