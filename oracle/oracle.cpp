@@ -664,9 +664,16 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
           out.ncand++;
         }
       }
+      // graze: the ray's closest approach to the axis (over t >= tmin, not cut
+      // at t_end: the hit point itself lies on the surface) within g of the
+      // radius, where the capsule could be entered no later than t_end (the
+      // entry lies within the half-chord sqrt(2 r g + g^2) of that approach)
       V3 q;
-      const double dist = seg_dist(ro.o, ro.d, r.tmin, t_end, c.a, c.b, &q);
-      if (std::fabs(dist - c.r) < g) out.flags |= F_GRAZE;
+      const double dist = seg_dist(ro.o, ro.d, r.tmin, kInf, c.a, c.b, &q);
+      const double ddo = dot(ro.d, ro.d);
+      const double s_q = dot(q - ro.o, ro.d) / ddo;
+      const double half = std::sqrt(2.0 * c.r * g + g * g) / std::sqrt(ddo);
+      if (std::fabs(dist - c.r) < g && s_q - half <= t_end) out.flags |= F_GRAZE;
       return;
     }
     V3 w[4];

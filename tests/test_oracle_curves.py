@@ -131,8 +131,8 @@ def test_curve_bvh_equals_brute_force_and_instances():
 
 def test_curve_flags():
     """A ray passing the capsule's surface within the graze distance is
-    flagged GRAZE; a ray through the middle of the body is not flagged; a ray
-    starting on the surface is flagged NEAR_ORIGIN."""
+    flagged GRAZE; rays through the body, head-on or at a shallow angle, are
+    not flagged; a ray starting on the surface is flagged NEAR_ORIGIN."""
     r = 0.25
     o = oracle.OracleScene(_curve_scene(_straight(r=r)))
     rays = _rays([[0.3, r * (1 + 1e-9), 5.0], [0.3, r * (1 - 1e-9), 5.0], [0.3, 0.0, 5.0],
@@ -141,6 +141,11 @@ def test_curve_flags():
     assert out.flags[0] & oracle.F_GRAZE and out.flags[1] & oracle.F_GRAZE
     assert out.flags[2] == 0 and out.inst[2] == 0
     assert out.flags[3] & oracle.F_NEAR_ORIGIN
+    # a ray nearly parallel to the axis enters the body at a shallow angle
+    # (cos 0.02) and passes far from the surface afterwards: not a graze
+    shallow = o.trace(_rays([[-1.3, 0.0, r + 0.01]], [[1.0, 0.0, -0.02]]))
+    assert shallow.inst[0] == 0 and shallow.prim[0] == 2 and (shallow.flags[0] & oracle.ID_FLAGS) == 0
+    np.testing.assert_allclose(shallow.t, [0.5], rtol=1e-12)
     # the acceptance check: the grazing ray may hit or miss, the central ray must hit
     code, info = o.accept(rays[:3].astype(np.float32), np.array([-1, 0, -1]), np.array([-1, 4, -1]),
                           np.array([np.inf, out.t[1], np.inf], np.float32))
