@@ -547,6 +547,24 @@ inline V3 cap_normal(const Cap& c, V3 p) {
   return p - (c.a + u * ab);
 }
 
+// Uncertainty (radians) of a capsule's normal at the hit at parameter t along
+// world ray r, as an FP32 renderer forms it: the normal follows the hit point,
+// whose object-space coordinates carry rounding of about 2^-24 times the hit
+// point's offset from the instance origin mapped by the inverse transform, the
+// object-space hit point and the capsule's ends; 16 such units, plus a shift
+// `t_shift` (world units) of the hit along the ray, over the radius.  One
+// radian (no information) for a capsule of radius 0.
+double cap_normal_uncertainty(const Scene& S, int64_t inst, const Cap& c, const Ray& r, double t, double t_shift) {
+  if (!(c.r > 0.0)) return 1.0;
+  const double* X = &S.X[12 * inst];
+  const V3 tA{X[3], X[7], X[11]};
+  const Ray ro = obj_ray(S, inst, r);
+  const V3 ho = ro.o + t * ro.d;
+  const V3 pw = r.o + t * r.d;
+  const double e = 16.0 * std::ldexp(1.0, -24) * (norm(pw - tA) * S.ainv_frob[inst] + norm(ho) + norm(c.a) + norm(c.b));
+  return std::min(1.0, (e + t_shift * S.ainv_frob[inst]) / c.r);
+}
+
 struct TraceOut {
   Key best;
   uint32_t flags = 0;
@@ -1327,6 +1345,9 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     const double nd = dot(n, ray.d);
     uint32_t vshade = 0;  // shading decisions of this vertex within rounding of a threshold
     if (std::fabs(nd) < 1e-3) vshade |= F_SHADE;
+    if (is_cap && cap_normal_uncertainty(S, h.best.inst, S.caps[S.co[pr] + h.best.prim], ray, h.best.t,
+                                         16.0 * std::ldexp(1.0, -24) * h.S / std::max(h.cos_abs, 1e-3)) > 1e-6)
+      vshade |= F_SHADE;
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
     double a = S.albedo[face];
@@ -1611,6 +1632,12 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
   Excl ex;
   C3 T = c3(1.0);
   C3 Lsum;
+  // error budget of the radiance from capsule normals known only to their FP32
+  // uncertainty: absolute per channel (Bsum), and the relative uncertainty of
+  // the path weight T so far (rho)
+  C3 Bsum;
+  double rho = 0.0;
+  bool unbounded = false;  // a capsule normal's uncertainty reaches a weight's support: no bound
   double pdf_bsdf = 0.0;  // BSDF density of the sample behind the current ray
   const bool env_light = P.env_nee && S.env_w > 0;
   const int nl = 1 + P.n_area + (env_light ? 1 : 0);
@@ -1690,6 +1717,10 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       }
     }
     n = side * n;
+    // a capsule's normal follows the hit point: the GPU's is known to within
+    // dn_unc of the exact normal at its t
+    const double dn_unc = is_cap ? cap_normal_uncertainty(S, inst, S.caps[S.co[pr] + prim], ray, (double)F[0], 0.0)
+                                 : 0.0;
     // shading value: the face's albedo, or a texel at the hit's (u, v)
     double a = S.albedo[face];
     if (S.tex_res > 0) {
@@ -1729,6 +1760,13 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     }
     const Material M = face_material(S, face);
     const Shade sh = make_shade(M, n, -1.0 * dh, false);
+    // the shade with the normal turned by dn_unc about tangent axis q & 1, in
+    // direction q & 2 (q = 0..3): the spread of every value that depends on
+    // the normal over these four bounds its change to first order
+    auto turned_shade = [&](int q) {
+      const V3 tq = (q & 1) ? sh.t2 : sh.t1;
+      return make_shade(M, normalize(n + (((q & 2) ? -1.0 : 1.0) * dn_unc) * tq), -1.0 * dh, false);
+    };
     // next-event estimate
     int j = 0;
     uint32_t wl[4] = {0u, 0u, 0u, 0u};
@@ -1742,10 +1780,12 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     Ray sr{pg, Lf, 0.0, kInf};
     V3 ldir = L;     // unit direction of the light sample
     double X = 0.0;  // the light's factor of the estimate X (A + B c)
+    double env_L = 0.0, env_p = 0.0;  // an environment sample's radiance and density (its X depends on the BSDF)
+    const double cth = 1e-6 + dn_unc;  // cosine thresholds of the light tests
     if (j == 0) {
       const double cl = dot(n, L);
-      want_certain = cl > 1e-6;
-      skip_certain = cl < -1e-6;
+      want_certain = cl > cth;
+      skip_certain = cl < -cth;
       X = nl * P.E;
     } else if (env_light && j == nl - 1) {
       const int64_t nt = (int64_t)S.env_w * S.env_h;
@@ -1762,10 +1802,12 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       const double sr_ = std::sqrt(std::max(0.0, 1.0 - z * z));
       const V3 de{sr_ * std::cos(phi), sr_ * std::sin(phi), z};
       const double cp = dot(n, de);
-      want_certain = cp > 1e-6;
-      skip_certain = cp < -1e-6;
+      want_certain = cp > cth;
+      skip_certain = cp < -cth;
       const double pdf = env_pdf(S, lo);
       X = nl * S.env[lo] * mis_power(pdf / nl, bsdf_pdf(sh, de)) / pdf;
+      env_L = S.env[lo];
+      env_p = pdf;
       ldir = de;
       sr = Ray{pg, de, 0.0, kInf};
     } else {
@@ -1777,8 +1819,8 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       const V3 nlv = cross(e1, e2);
       const double Ar = norm(nlv);
       const double cp = dot(n, wi) / dd, cq = -dot(nlv, wi) / (Ar * dd);
-      want_certain = cp > 1e-6 && cq > 1e-6;
-      skip_certain = cp < -1e-6 || cq < -1e-6;
+      want_certain = cp > cth && cq > 1e-6;
+      skip_certain = cp < -cth || cq < -1e-6;
       X = nl * Lq[9] * Ar * cq / d2;
       ldir = (1.0 / dd) * wi;
       sr = Ray{pg, wi, 0.0, 1.0};
@@ -1795,6 +1837,17 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
         C3 e;
         for (int ch = 0; ch < 3; ++ch) e.v[ch] = X * (fa + fb * sh.tint.v[ch] * a);
         Lsum = Lsum + T * e;
+        for (int ch = 0; ch < 3; ++ch) Bsum.v[ch] += std::fabs(T.v[ch] * e.v[ch]) * rho;
+        if (dn_unc > 0.0) {
+          for (int q = 0; q < 4; ++q) {
+            const Shade sq = turned_shade(q);
+            const double Xq = env_p > 0.0 ? nl * env_L * mis_power(env_p / nl, bsdf_pdf(sq, ldir)) / env_p : X;
+            double qa, qb;
+            eval_AB(sq, ldir, &qa, &qb);
+            for (int ch = 0; ch < 3; ++ch)
+              Bsum.v[ch] += 0.5 * std::fabs(T.v[ch]) * std::fabs(Xq * (qa + qb * sq.tint.v[ch] * a) - e.v[ch]);
+          }
+        }
       }
     }
     if (!has_next) break;
@@ -1815,6 +1868,12 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     // rounding of P_s, and for either basis branch when n_z ~ 0
     bool spec, amb;
     double err = norm(nr.d - sample_bsdf(sh, u0, unit(w2[2]), unit(w2[3]), &spec, &amb));
+    if (dn_unc > 0.0 && sh.Ps > 0.0) {
+      // the lobe choice u0 < P_s is ambiguous within P_s's spread as well
+      double dps = 0.0;
+      for (int q = 0; q < 4; ++q) dps = std::max(dps, std::fabs(turned_shade(q).Ps - sh.Ps));
+      amb = amb || std::fabs(u0 - sh.Ps) < 1e-6 + 2.0 * dps;
+    }
     if (amb) {
       R.n_ambiguous_shading++;
       err = std::min(err, norm(nr.d - sample_bsdf(sh, spec ? 1.0 : 0.0, unit(w2[2]), unit(w2[3]), &spec, nullptr)));
@@ -1824,14 +1883,42 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
       const Shade sf = make_shade(M, n, -1.0 * dh, true);
       err = std::min(err, norm(nr.d - sample_bsdf(sf, u0, unit(w2[2]), unit(w2[3]), &spec, nullptr)));
     }
-    if (err > 1e-5) return fail(10, k + 1);
+    // a direction sampled about a normal turned by dn_unc turns by up to about
+    // twice that (the specular lobe reflects about the microfacet normal)
+    if (err > 1e-5 + 4.0 * dn_unc) return fail(10, k + 1);
     // the weight of the GPU's direction, in FP64
     const V3 dn = normalize(nr.d);
     double fa, fb;
-    if (!eval_AB(sh, dn, &fa, &fb)) return fail(10, k + 1);
+    if (!eval_AB(sh, dn, &fa, &fb)) {
+      // below the surface for the exact normal: acceptable only within the
+      // normal's uncertainty, and the rest of the path then carries no bound
+      if (!(dn_unc > 0.0) || dot(n, dn) < -2.0 * dn_unc) return fail(10, k + 1);
+      unbounded = true;
+    }
     pdf_bsdf = bsdf_pdf(sh, dn);
     C3 wgt;
-    for (int ch = 0; ch < 3; ++ch) wgt.v[ch] = (fa + fb * sh.tint.v[ch] * a) / pdf_bsdf;
+    for (int ch = 0; ch < 3; ++ch) wgt.v[ch] = pdf_bsdf > 0.0 ? (fa + fb * sh.tint.v[ch] * a) / pdf_bsdf : 0.0;
+    if (dn_unc > 0.0 && !unbounded) {
+      // relative spread of the weight and of the density (the environment's
+      // MIS weight at an escape reads it) over the turned normals
+      double dr = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const Shade sq = turned_shade(q);
+        double qa, qb;
+        const double pq = bsdf_pdf(sq, dn);
+        if (!eval_AB(sq, dn, &qa, &qb) || !(pq > 0.0) || !(pdf_bsdf > 0.0)) {
+          dr = kInf;
+          break;
+        }
+        dr = std::max(dr, std::fabs(pq / pdf_bsdf - 1.0));
+        for (int ch = 0; ch < 3; ++ch) {
+          const double wq = (qa + qb * sq.tint.v[ch] * a) / pq;
+          if (wgt.v[ch] != 0.0) dr = std::max(dr, std::fabs(wq / wgt.v[ch] - 1.0));
+        }
+      }
+      if (std::isfinite(dr)) rho += 2.0 * dr;
+      else unbounded = true;
+    }
     T = T * wgt;
     ex = here;
   }
@@ -1840,15 +1927,18 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
   if (esc_vals.empty()) esc_vals.push_back(0.0);
   double best = kInf, Lbest = 0.0, scale = 0.0;
   C3 Lb;
+  double budget = 0.0;  // of the chosen value, from uncertain capsule normals
   for (double e : esc_vals) {
     const C3 Lv = escaped ? Lsum + e * T : Lsum;
-    double err = 0.0, mx = 0.0;
+    double err = 0.0, mx = 0.0, bud = 0.0;
     for (int ch = 0; ch < 3; ++ch) {
       err = std::max(err, std::fabs((double)radiance[ch] - Lv.v[ch]));
       mx = std::max(mx, std::fabs(Lv.v[ch]));
+      bud = std::max(bud, Bsum.v[ch] + (escaped ? std::fabs(e * T.v[ch]) * rho : 0.0));
     }
-    if (err < best) {
+    if (err - bud < best - budget || best == kInf) {
       best = err;
+      budget = bud;
       Lb = Lv;
       scale = mx;
     }
@@ -1856,8 +1946,8 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
   for (int ch = 0; ch < 3; ++ch) R.Lc[ch] = Lb.v[ch];
   R.L = Lb.v[0];
   (void)Lbest;
-  // every channel within 1e-4 of the largest one
-  if (best > 1e-4 * scale + 1e-7) return fail(12, nv);
+  // every channel within 1e-4 of the largest one (plus the budget of capsule normals)
+  if (!unbounded && !(best <= 1e-4 * scale + 1e-7 + budget)) return fail(12, nv);
   return R;
 }
 

@@ -241,3 +241,138 @@ def test_curve_sun_shading_closed_form(turned):
     expect = (body * math.pi / 4 + disks * 2 / 3) / (body + disks)
     # 1600 samples: the mean's standard error is about 0.003
     assert abs(cos.mean() - expect) < 0.009, (cos.mean(), expect)
+
+
+def _u01(w):
+    return float(int(w) >> 8) * 2.0 ** -24
+
+
+def _curve_model_path(o, scene, caps, cam, st, pix, sample, turn=0.0, rng=None):
+    """A path over a scene with curves built the way an FP32 renderer builds
+    it: rays traced by the oracle's closest hit (the previous primitive
+    excluded), hit points o + t d rounded to FP32 per operation, a capsule's
+    normal formed from the hit point relative to the instance origin through
+    the FP32-rounded inverse transform, a quad's from its vertices, the next
+    direction the cosine sample about the normal (rounded to FP32).  turn > 0
+    turns every capsule normal by that angle about a random tangent first.
+    Returns the record in rtq_render_path's layout."""
+    f32 = np.float32
+    key = (st.seed & 0xFFFFFFFF, (st.seed >> 32) ^ st.frame)
+    eye = np.array(cam.eye, np.float64)
+    fw = np.array(cam.look, np.float64) - eye
+    fw /= np.linalg.norm(fw)
+    rt = np.cross(fw, cam.up)
+    rt /= np.linalg.norm(rt)
+    up = np.cross(rt, fw)
+    th = math.tan(math.radians(cam.vfov_deg) / 2)
+    w = oracle.philox([pix, sample, 0, 0], key)
+    x, y = pix % cam.w, pix // cam.w
+    sx = (2 * (x + _u01(w[0])) / cam.w - 1) * th * cam.w / cam.h
+    sy = (1 - 2 * (y + _u01(w[1])) / cam.h) * th
+    d = fw + sx * rt + sy * up
+    d /= np.linalg.norm(d)
+    ray_o, ray_d = eye.astype(f32), d.astype(f32)
+    L = np.array(st.light_dir)
+    fo = scene.proto_face_off()
+    curve_proto = np.diff(scene.proto_curve_off) > 0
+    vi, vf = [], []
+    excl = None
+    beta, rad = 1.0, 0.0
+    for b in range(st.depth):
+        r = np.zeros((1, 8), np.float32)
+        r[0, 0:3], r[0, 3:6], r[0, 7] = ray_o, ray_d, np.inf
+        hh = o.trace(r, excl=None if excl is None else np.array([excl], np.int32))
+        rec_f = [np.inf, 0, 0, 0, *ray_o, *ray_d]
+        if hh.inst[0] < 0:
+            rad += beta * st.L_sky
+            vi.append([-1, -1, -1, -1, -1, 0])
+            vf.append(rec_f)
+            return len(vi) - 1, np.array(vi), np.array(vf, np.float32), True, f32(rad)
+        inst, prim, half = int(hh.inst[0]), int(hh.prim[0]), int(hh.half[0])
+        p_ = scene.inst_proto[inst]
+        X = scene.inst_xform[inst].astype(np.float64).reshape(3, 4)
+        t32 = f32(hh.t[0])
+        if curve_proto[p_]:
+            c = caps[8 * scene.proto_curve_off[p_] + prim]
+            Ai = np.linalg.inv(X[:, :3]).astype(np.float32).astype(np.float64)
+            h = (ray_o.astype(np.float64) - X[:, 3].astype(np.float32)) + float(t32) * ray_d.astype(np.float64)
+            ho = Ai @ h
+            ba = c[3:6] - c[0:3]
+            s_ = np.clip((ho - c[0:3]) @ ba / (ba @ ba), 0, 1)
+            no = (ho - (c[0:3] + s_ * ba)).astype(np.float32).astype(np.float64)
+            n = Ai.T @ no
+            face = int(fo[p_] + prim // 8)
+        else:
+            q = scene.quads[scene.proto_quad_off[p_] + prim] + scene.proto_vert_off[p_]
+            V = scene.verts[q].astype(np.float64) @ X[:, :3].T + X[:, 3]
+            n = np.cross(V[1] - V[0], V[3] - V[0]) if half == 0 else np.cross(V[3] - V[2], V[1] - V[2])
+            face = int(fo[p_] + prim)
+        n /= np.linalg.norm(n)
+        if n @ ray_d.astype(np.float64) > 0:
+            n = -n
+        if turn > 0 and curve_proto[p_]:
+            tv = np.cross(n, rng.normal(size=3))
+            tv /= np.linalg.norm(tv)
+            n = math.cos(turn) * n + math.sin(turn) * tv
+        p = np.array([f32(f32(ray_o[k]) + f32(t32 * ray_d[k])) for k in range(3)], np.float32)
+        alb = float(scene.albedo[face])
+        cl = float(n @ L)
+        shadow = -1
+        key3 = (inst, prim, half)
+        if cl > 0:
+            rs = np.zeros((1, 8), np.float32)
+            rs[0, 0:3], rs[0, 3:6], rs[0, 7] = p, np.array(L, np.float32), np.inf
+            occ = o.trace(rs, excl=np.array([key3], np.int32), any_hit=True)
+            shadow = 1 if occ.inst[0] >= 0 else 0
+            if shadow == 0:
+                rad += beta * alb * (st.E / math.pi) * cl
+        vi.append([inst, prim, half, shadow, face, 0])
+        rec_f[0], rec_f[1], rec_f[2], rec_f[3] = t32, alb, cl, rad
+        vf.append(rec_f)
+        if b == st.depth - 1:
+            break
+        w2 = oracle.philox([pix, sample, 0, b], key)
+        u1, u2 = _u01(w2[2]), _u01(w2[3])
+        sg_ = 1.0 if n[2] >= 0 else -1.0
+        aa = -1.0 / (sg_ + n[2])
+        bb = n[0] * n[1] * aa
+        t1 = np.array([1 + sg_ * n[0] ** 2 * aa, sg_ * bb, -sg_ * n[0]])
+        t2 = np.array([bb, sg_ + n[1] ** 2 * aa, -n[1]])
+        dn = (math.sqrt(u1) * math.cos(2 * math.pi * u2)) * t1 + (math.sqrt(u1) * math.sin(2 * math.pi * u2)) * t2 \
+            + math.sqrt(1 - u1) * n
+        ray_o, ray_d = p, dn.astype(np.float32)
+        beta *= alb
+        excl = key3
+    return len(vi), np.array(vi), np.array(vf, np.float32), False, f32(rad)
+
+
+def test_path_check_on_curves():
+    """The replay check accepts paths over curves whose capsule normals carry
+    an FP32 renderer's rounding (through the FP32 inverse transform), and
+    rejects paths whose capsule normals are turned by 0.05 rad, and a wrong
+    radiance."""
+    scene = sg.curve_scene(4, n_inst=8, n_curves=24)
+    o = oracle.OracleScene(scene)
+    caps = o.capsules()
+    cams = [sg.Camera((0.0, -5.5, 1.4), (0.0, 0.0, 0.4), (0.0, 0.0, 1.0), 45.0, 48, 40)]
+    st = sg.RenderSettings(spp=1, depth=3, seed=17, frame=1)
+    cam = cams[0]
+    rng = np.random.default_rng(3)
+    curve_proto = np.diff(scene.proto_curve_off) > 0
+    n_ok = n_cap = n_turn = n_rad = 0
+    for pix in rng.choice(cam.w * cam.h, 400, replace=False):
+        nv, vi, vf, esc, rad = _curve_model_path(o, scene, caps, cam, st, int(pix), 0)
+        code, stats = o.check_path(cams, st, 0, int(pix), 0, nv, vi, vf, esc, rad)
+        assert code == 0, (pix, oracle.PATH_CODES.get(code), stats, vi, vf)
+        n_ok += 1
+        on_cap = [k for k in range(nv) if curve_proto[scene.inst_proto[vi[k, 0]]]]
+        if not on_cap or on_cap[0] == nv - 1:
+            continue
+        n_cap += 1
+        nv2, vi2, vf2, esc2, rad2 = _curve_model_path(o, scene, caps, cam, st, int(pix), 0, turn=0.05,
+                                                      rng=np.random.default_rng(int(pix)))
+        c = o.check_path(cams, st, 0, int(pix), 0, nv2, vi2, vf2, esc2, rad2)[0]
+        n_turn += c != 0
+        n_rad += o.check_path(cams, st, 0, int(pix), 0, nv, vi, vf, esc, np.float32(rad * 1.01 + 1e-3))[0] == 12
+    assert n_ok == 400 and n_cap > 30, n_cap
+    assert n_turn == n_cap and n_rad == n_cap, (n_turn, n_rad, n_cap)
