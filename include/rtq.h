@@ -26,6 +26,15 @@
  *    triangles A = (v0, v1, v3) and B = (v2, v3, v1), both sides visible.  The hit
  *    parameterisation is v0 -> (u, v) = (0, 0), v1 -> (1, 0), v2 -> (1, 1),
  *    v3 -> (0, 1).
+ *  - A curve (Section 5.2: the scene's curves, rendered as chains of
+ *    primitives) is a cubic Bezier of four control points (x, y, z, radius).  It
+ *    is traced as 8 capsules: capsule j joins the curve's points at parameters
+ *    j/8 and (j+1)/8 (each the FP32 rounding of the exact Bezier point) with the
+ *    FP32 rounding of the mean of the two points' radii.  A capsule is a
+ *    cylinder with a hemisphere on each end, hit from outside only (a ray that
+ *    starts inside a capsule does not hit it).  Capsule j of curve c of a
+ *    prototype is its primitive 8 c + j; the hit's u is the curve parameter
+ *    (j + y) / 8, y in [0, 1] the position along the capsule's axis, and v = 0.
  *  - An instance transform is a row-major 3x4 FP32 matrix [A | t] mapping object
  *    to world space, w = A v + t.
  *  - A hit is accepted when tmin < t <= tmax; among accepted hits the one with
@@ -101,13 +110,18 @@ void rtq_host_bvh_destroy(rtq_host_bvh* bvh);
 /* ------------------------------------------------------------------ scene */
 typedef struct rtq_scene rtq_scene;
 
-/* One prototype quad mesh (host memory). */
+/* One prototype (host memory): a quad mesh, or a set of curves.  Its faces
+ * (the units that carry an albedo, a material or a gradient) are its quads, or
+ * its curves. */
 typedef struct {
-  const float* verts;   /* n_verts x 3 FP32, object space */
+  const float* verts;   /* n_verts x 3 FP32, object space (quad meshes) */
   const int32_t* quads; /* n_quads x 4 vertex indices into verts (CCW) */
   int32_t n_verts;
-  int32_t n_quads;      /* >= 1 */
-  const float* albedo;  /* n_quads per-face albedo, or NULL for 0.5 */
+  int32_t n_quads;      /* >= 1 for a quad mesh, 0 for curves */
+  const float* albedo;  /* one per face (n_quads, or n_curves), or NULL for 0.5 */
+  const float* curves;  /* n_curves x 16 FP32: 4 control points (x, y, z, radius), radius >= 0;
+                           NULL for a quad mesh */
+  int32_t n_curves;     /* >= 1 for curves (then n_quads = 0 and verts, quads may be NULL), else 0 */
 } rtq_prototype;
 
 /* Object-level instances (host memory): instance i draws prototype proto[i]
@@ -139,16 +153,18 @@ typedef struct {
 
 /*
  * Build the acceleration structures of a scene (Section 5.2: per-object BVHs
- * under a top-level BVH over instances, quads as primitives).
+ * under a top-level BVH over instances, quads and curves' capsules as
+ * primitives).
  *   protos[0..n_protos), insts: host memory, read during the call only.
  *   opts: may be NULL for defaults.
  *   *out: receives a handle owning all device memory of the scene.
  * Instance inverses and world boxes are computed on the device in FP64; the
  * BVHs are built on the host (binned SAH) and uploaded.  The call
  * synchronizes the device it builds on.
- * Errors: INVALID_ARG (NULL pointer, n_quads < 1, vertex index out of range,
- * non-finite vertex or transform, proto index out of range), SINGULAR_XFORM,
- * LIMIT (more than 2^28 unique quads or instances, 2^31 nodes, or BVHs deeper
+ * Errors: INVALID_ARG (NULL pointer, a prototype with neither or both of quads
+ * and curves, vertex index out of range, non-finite vertex, control point or
+ * transform, negative radius, proto index out of range), SINGULAR_XFORM, LIMIT
+ * (more than 2^28 unique primitives or instances, 2^31 nodes, or BVHs deeper
  * than the traversal stack allows), OOM, HIP.
  */
 int rtq_scene_build(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
@@ -169,13 +185,15 @@ typedef struct {
                                          bottom-level upload; opening instances (host); top level
                                          (host) and its upload */
   int32_t node_width;                 /* children per node */
+  int64_t n_unique_curves, n_unique_capsules;
+  int64_t n_faces;                    /* unique faces: quads and curves */
 } rtq_scene_info;
 
 int rtq_scene_get_info(const rtq_scene* scene, rtq_scene_info* info);
 
 /*
- * Replace the per-face albedo (device memory, n = total unique quads, in
- * prototype order) without rebuilding.  Enqueued on `stream` (a device copy).
+ * Replace the per-face albedo (device memory, n = total unique faces -- quads
+ * and curves --, in prototype order) without rebuilding.  Enqueued on `stream` (a device copy).
  * Not part of the paper's system (its colours come from Ptex textures, Section
  * 5.3): this library's addition for gradient-driven loops over the albedo
  * (rtq_render_backward).
@@ -197,8 +215,9 @@ int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, h
  * rtq_scene_destroy), the caller keeps its buffer.  res = 0 (texels_dev may be
  * NULL) removes the textures.  Waits for all work on the device, then enqueues
  * the copy on `stream`; renders on other streams are ordered by the caller.
- * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES] or NULL
- * texels with res > 0; RTQ_E_HIP when the allocation or copy fails.
+ * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES], NULL texels
+ * with res > 0, or res > 0 in a scene with curves (they have no (u, v)
+ * square); RTQ_E_HIP when the allocation or copy fails.
  * rtq_render_backward then differentiates with respect to the texels.
  */
 #define RTQ_MAX_TEX_RES 64
@@ -245,8 +264,8 @@ int rtq_scene_set_environment(rtq_scene* scene, const float* texels_dev, int32_t
  * white.
  *
  * mats: host memory, n_mat entries (copied); face_mat_dev: device memory, one
- * material index per unique quad in prototype order (copied into memory the
- * scene owns).  n_mat = 0 (both may be NULL) removes the materials.  Waits for
+ * material index per unique face (quad or curve) in prototype order (copied
+ * into memory the scene owns).  n_mat = 0 (both may be NULL) removes the materials.  Waits for
  * all work on the device, then copies synchronously.
  * Errors: RTQ_E_INVALID_ARG for n_mat outside [0, RTQ_MAX_MATERIALS], NULL
  * arrays, a tint outside [0, 1], roughness outside [0.05, 1], metallic or
@@ -276,7 +295,7 @@ typedef struct {
 
 typedef struct {
   float *t, *u, *v;      /* miss: t = +inf, u = v = 0 */
-  int32_t *inst, *prim;  /* miss: -1, -1; prim is the quad index within its prototype */
+  int32_t *inst, *prim;  /* miss: -1, -1; prim is the quad (or capsule) index within its prototype */
   uint32_t* ref;         /* optional (NULL: not written), 2 words per ray: an opaque reference of the
                             hit triangle (top-level entry; leaf-ordered quad, and the half in bit 31)
                             valid for this scene, for rtq_rays.exclude of rays that leave it; a miss
@@ -342,8 +361,8 @@ int rtq_trace_occluded(const rtq_scene* scene, const rtq_rays* rays, int64_t n, 
                        const rtq_trace_opts* opts, hipStream_t stream);
 
 /*
- * Reference traversal for tests: every instance and every quad of its
- * prototype is tested with the same leaf code as rtq_trace_closest (no
+ * Reference traversal for tests: every instance and every quad (or capsule) of
+ * its prototype is tested with the same leaf code as rtq_trace_closest (no
  * acceleration structure).  Meant for tiny scenes only.
  */
 int rtq_trace_brute(const rtq_scene* scene, const rtq_rays* rays, int64_t n, rtq_hits* hits, hipStream_t stream);
@@ -460,7 +479,7 @@ typedef struct {
  * Path-trace n_cams pinhole views (Section 5.4: progressive 1 spp frames; here
  * spp samples per call, frames averaged with opts.accumulate) with a
  * Lambertian BSDF (albedo per face, or a texel of the face's texture when the
- * scene has textures) or, with materials, the principled BSDF in three
+ * scene has textures; a curve's normal is the capsule's) or, with materials, the principled BSDF in three
  * channels (rtq_scene_set_materials), next-event estimation toward one directional light
  * (and optional quad area lights, opts.area_lights), and a constant sky (or an
  * environment map, rtq_scene_set_environment).  depth counts closest-hit rays per path including the
@@ -525,7 +544,7 @@ int rtq_render_path(const rtq_scene* scene, const rtq_camera* cams, int32_t n_ca
  * layout (rtq_scene_set_textures).  With materials, grad_images holds 3 floats per pixel (as the image) and each
  * vertex's estimate and bounce weight, affine in its albedo, are differentiated
  * per channel.
- * grad_albedo: device, n_unique_quads floats (times res^2 with textures), zeroed by the caller, accumulated
+ * grad_albedo: device, n_faces floats (n_unique_quads times res^2 with textures), zeroed by the caller, accumulated
  * with atomics (summation order is not fixed).  Errors: as rtq_render.
  */
 int rtq_render_backward(const rtq_scene* scene, const rtq_camera* cams, int32_t n_cams, int32_t spp,

@@ -36,7 +36,8 @@ class RtqError(RuntimeError):
 # ----------------------------------------------------------------------------- C structs
 class _Proto(ctypes.Structure):
     _fields_ = [("verts", ctypes.c_void_p), ("quads", ctypes.c_void_p), ("n_verts", ctypes.c_int32),
-                ("n_quads", ctypes.c_int32), ("albedo", ctypes.c_void_p)]
+                ("n_quads", ctypes.c_int32), ("albedo", ctypes.c_void_p), ("curves", ctypes.c_void_p),
+                ("n_curves", ctypes.c_int32)]
 
 
 class _Insts(ctypes.Structure):
@@ -55,7 +56,8 @@ class _Info(ctypes.Structure):
                 ("tlas_nodes", ctypes.c_int64), ("blas_nodes", ctypes.c_int64), ("tlas_depth", ctypes.c_int32),
                 ("blas_depth_max", ctypes.c_int32), ("formats", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("n_top_entries", ctypes.c_int64),
-                ("build_phase_seconds", ctypes.c_double * 4), ("node_width", ctypes.c_int32)]
+                ("build_phase_seconds", ctypes.c_double * 4), ("node_width", ctypes.c_int32),
+                ("n_unique_curves", ctypes.c_int64), ("n_unique_capsules", ctypes.c_int64), ("n_faces", ctypes.c_int64)]
 
 
 class _Rays(ctypes.Structure):
@@ -179,22 +181,33 @@ class Scene:
         L = load_library()
         _torch()
         self.n_quads = int(s.quads.shape[0])
+        curves = getattr(s, "curves", None)
+        self.n_curves = 0 if curves is None else int(curves.shape[0])
+        self.n_faces = self.n_quads + self.n_curves  # shading faces: quads, then curves, in prototype order
         verts = np.ascontiguousarray(s.verts, dtype=np.float32)
         quads = np.ascontiguousarray(s.quads, dtype=np.int32)
         albedo = np.ascontiguousarray(s.albedo, dtype=np.float32)
+        assert albedo.shape[0] == self.n_faces
+        cv = np.ascontiguousarray(curves if curves is not None else np.zeros((0, 16)), dtype=np.float32)
+        co = s.proto_curve_off if curves is not None else np.zeros(s.n_protos + 1, np.int64)
         P = s.n_protos
         protos = (_Proto * P)()
         vb = verts.ctypes.data
         qb = quads.ctypes.data
         ab = albedo.ctypes.data
+        f0 = 0
         for p in range(P):
             v0, v1 = int(s.proto_vert_off[p]), int(s.proto_vert_off[p + 1])
             q0, q1 = int(s.proto_quad_off[p]), int(s.proto_quad_off[p + 1])
+            c0, c1 = int(co[p]), int(co[p + 1])
             protos[p].verts = vb + 12 * v0
             protos[p].quads = qb + 16 * q0
             protos[p].n_verts = v1 - v0
             protos[p].n_quads = q1 - q0
-            protos[p].albedo = ab + 4 * q0
+            protos[p].albedo = ab + 4 * f0
+            protos[p].curves = cv.ctypes.data + 64 * c0 if c1 > c0 else None
+            protos[p].n_curves = c1 - c0
+            f0 += (q1 - q0) + (c1 - c0)
         ip = np.ascontiguousarray(s.inst_proto, dtype=np.int32)
         ix = np.ascontiguousarray(s.inst_xform, dtype=np.float32)
         insts = _Insts(ip.shape[0], ip.ctypes.data, ix.ctypes.data)
@@ -220,7 +233,7 @@ class Scene:
         return out
 
     def set_albedo(self, albedo) -> None:
-        assert albedo.dtype.is_floating_point and albedo.numel() == self.n_quads and albedo.is_cuda
+        assert albedo.dtype.is_floating_point and albedo.numel() == self.n_faces and albedo.is_cuda
         a = albedo.contiguous().float()
         _check(load_library().rtq_scene_set_albedo(self.handle, a.data_ptr(), a.numel(), _stream()))
         self._albedo_keep = a
@@ -260,7 +273,7 @@ class Scene:
         fm = face_mat if isinstance(face_mat, torch.Tensor) else torch.from_numpy(
             np.ascontiguousarray(face_mat, dtype=np.uint8))
         fm = fm.to(device="cuda", dtype=torch.uint8).contiguous()
-        assert fm.numel() == self.n_quads
+        assert fm.numel() == self.n_faces
         _check(L.rtq_scene_set_materials(self.handle, ctypes.cast(arr, ctypes.c_void_p), m.shape[0], fm.data_ptr(),
                                          _stream()))
         self.rgb = True
@@ -509,7 +522,7 @@ def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None,
     assert g.numel() == ch * total and g.is_cuda
     if grad_albedo is None:
         # one entry per shading parameter: per face, or per texel with textures
-        n_par = scene.n_quads * max(1, getattr(scene, "tex_res", 0)) ** 2
+        n_par = scene.n_faces * max(1, getattr(scene, "tex_res", 0)) ** 2
         grad_albedo = torch.zeros(n_par, device=g.device, dtype=torch.float32)
     o = render_opts(settings, **opts)
     o.channels = ch

@@ -60,7 +60,7 @@ void DeviceBuffers::release() {
 
 SceneView scene_view(const rtq_scene* s, int fmt) {
   SceneView v;
-  v.nodes = reinterpret_cast<const uint4*>(fmt == kCodecF32 ? s->nodes_f32 : s->nodes_q8);
+  v.nodes = reinterpret_cast<const uint4*>((fmt & kCodecMask) == kCodecF32 ? s->nodes_f32 : s->nodes_q8);
   v.rec_pmax = s->rec_pmax;
   v.p_world = s->p_world;
   v.tlas_root = s->tlas_root;
@@ -88,6 +88,7 @@ int resolve_format(const rtq_scene* s, int32_t req, int* fmt) {
   if (!(s->formats & f)) return set_error(RTQ_E_INVALID_ARG, "node format %d was not built", f);
   if (f == RTQ_NODE_FP32) *fmt = kCodecF32;
   else *fmt = s->width == 8 ? kCodecQ8W8 : (s->width == 2 ? kCodecQ8W2 : kCodecQ8);
+  if (s->n_curves > 0) *fmt |= kCodecCurves;
   return RTQ_OK;
 }
 
@@ -129,6 +130,61 @@ const char* rtq_version(void) { return "rtq 0.1 (gfx950)"; }
 // count, when the caller leaves rtq_build_opts.open_pct at 0.
 constexpr int32_t kDefaultOpenPct = 50;
 
+// One capsule of a curve: axis from a to b, radius r (FP32 values).
+struct Capsule {
+  float a[3], b[3], r;
+};
+
+// Curve -> kCapsPerCurve capsules (Section 5.2: curves rendered as chains of
+// primitives).  The Bezier point at s = j / 8 is evaluated by de Casteljau's
+// construction in FP64, which is exact here: every control value is an FP32
+// number and s a dyadic fraction of 3 bits, so each of the three rounds of
+// interpolation adds at most 3 bits to the operands' 24 (plus their exponent
+// spread), well inside FP64's 53.  The exact point is then rounded once to FP32.
+// A capsule's radius is the FP32 rounding of the mean of its end radii (exact
+// in FP64 for the same reason).
+static void tessellate_curve(const float* cp, Capsule* out) {
+  double X[kCapsPerCurve + 1][4];
+  for (int j = 0; j <= kCapsPerCurve; ++j) {
+    const double s = (double)j / kCapsPerCurve;
+    for (int c = 0; c < 4; ++c) {
+      double v[4] = {cp[c], cp[4 + c], cp[8 + c], cp[12 + c]};
+      for (int level = 3; level > 0; --level)
+        for (int k = 0; k < level; ++k) v[k] = v[k] + s * (v[k + 1] - v[k]);
+      X[j][c] = (double)(float)v[0];
+    }
+  }
+  for (int j = 0; j < kCapsPerCurve; ++j) {
+    Capsule& c = out[j];
+    for (int k = 0; k < 3; ++k) {
+      c.a[k] = (float)X[j][k];
+      c.b[k] = (float)X[j + 1][k];
+    }
+    c.r = (float)(0.5 * (X[j][3] + X[j + 1][3]));
+  }
+}
+
+// Box of a capsule for the bottom-level build: the axis's box grown by r and by
+// a margin of 2^-18 (max |coordinate| + r) for the FP32 capsule test, whose
+// hits may lie that far outside the exact surface (the traversal must not cull
+// a box whose capsule the same test would report hit), rounded outward.
+static Aabb capsule_box(const Capsule& c) {
+  double m = c.r;
+  for (int k = 0; k < 3; ++k) m = std::max(m, std::max(std::fabs((double)c.a[k]), std::fabs((double)c.b[k])));
+  const double g = (double)c.r + std::ldexp(m + (double)c.r, -18);
+  Aabb b;
+  for (int k = 0; k < 3; ++k) {
+    const double lo = std::min((double)c.a[k], (double)c.b[k]) - g;
+    const double hi = std::max((double)c.a[k], (double)c.b[k]) + g;
+    float l = (float)lo, h = (float)hi;
+    if ((double)l > lo) l = std::nextafter(l, -std::numeric_limits<float>::infinity());
+    if ((double)h < hi) h = std::nextafter(h, std::numeric_limits<float>::infinity());
+    b.lo[k] = l;
+    b.hi[k] = h;
+  }
+  return b;
+}
+
 static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_instances* insts,
                       const rtq_build_opts* opts, rtq_scene** out) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -158,21 +214,42 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   const int64_t N = insts->n;
   if (N > (int64_t)kMaxLeafFirst) return set_error(RTQ_E_LIMIT, "%lld instances exceed 2^28", (long long)N);
 
-  // ---- validate prototypes
-  int64_t total_quads = 0;
+  // ---- validate prototypes: a quad mesh, or curves
+  int64_t total_quads = 0, total_curves = 0, total_prims = 0, total_faces = 0;
+  std::vector<int32_t> n_prim(n_protos);
   for (int32_t p = 0; p < n_protos; ++p) {
     const rtq_prototype& P = protos[p];
-    if (!P.verts || !P.quads || P.n_quads < 1 || P.n_verts < 1)
-      return set_error(RTQ_E_INVALID_ARG, "prototype %d: empty or NULL arrays", p);
-    for (int64_t i = 0; i < 3 * (int64_t)P.n_verts; ++i)
-      if (!std::isfinite(P.verts[i])) return set_error(RTQ_E_INVALID_ARG, "prototype %d: non-finite vertex", p);
-    for (int64_t i = 0; i < 4 * (int64_t)P.n_quads; ++i)
-      if (P.quads[i] < 0 || P.quads[i] >= P.n_verts)
-        return set_error(RTQ_E_INVALID_ARG, "prototype %d: quad index %d out of range", p, P.quads[i]);
-    total_quads += P.n_quads;
+    if (P.n_curves < 0 || P.n_quads < 0) return set_error(RTQ_E_INVALID_ARG, "prototype %d: negative count", p);
+    if ((P.n_quads > 0) == (P.n_curves > 0))
+      return set_error(RTQ_E_INVALID_ARG, "prototype %d: needs quads or curves (one kind)", p);
+    if (P.n_curves > 0) {
+      if (!P.curves) return set_error(RTQ_E_INVALID_ARG, "prototype %d: NULL curves", p);
+      if ((int64_t)P.n_curves * kCapsPerCurve > (int64_t)kMaxLeafFirst)
+        return set_error(RTQ_E_LIMIT, "prototype %d: %d curves exceed 2^28 capsules", p, P.n_curves);
+      for (int64_t i = 0; i < 16 * (int64_t)P.n_curves; ++i) {
+        if (!std::isfinite(P.curves[i]))
+          return set_error(RTQ_E_INVALID_ARG, "prototype %d: non-finite control point", p);
+        if (i % 4 == 3 && P.curves[i] < 0.0f) return set_error(RTQ_E_INVALID_ARG, "prototype %d: negative radius", p);
+      }
+      n_prim[p] = P.n_curves * kCapsPerCurve;
+      total_curves += P.n_curves;
+      total_faces += P.n_curves;
+    } else {
+      if (!P.verts || !P.quads || P.n_verts < 1)
+        return set_error(RTQ_E_INVALID_ARG, "prototype %d: empty or NULL arrays", p);
+      for (int64_t i = 0; i < 3 * (int64_t)P.n_verts; ++i)
+        if (!std::isfinite(P.verts[i])) return set_error(RTQ_E_INVALID_ARG, "prototype %d: non-finite vertex", p);
+      for (int64_t i = 0; i < 4 * (int64_t)P.n_quads; ++i)
+        if (P.quads[i] < 0 || P.quads[i] >= P.n_verts)
+          return set_error(RTQ_E_INVALID_ARG, "prototype %d: quad index %d out of range", p, P.quads[i]);
+      n_prim[p] = P.n_quads;
+      total_quads += P.n_quads;
+      total_faces += P.n_quads;
+    }
+    total_prims += n_prim[p];
+    if (total_prims > (int64_t)kMaxLeafFirst)
+      return set_error(RTQ_E_LIMIT, "more than 2^28 unique primitives (quads and capsules)");
   }
-  if (total_quads > (int64_t)kMaxLeafFirst)
-    return set_error(RTQ_E_LIMIT, "%lld unique quads exceed 2^28", (long long)total_quads);
   for (int64_t i = 0; i < N; ++i)
     if (insts->proto[i] < 0 || insts->proto[i] >= n_protos)
       return set_error(RTQ_E_INVALID_ARG, "instance %lld: prototype %d out of range", (long long)i, insts->proto[i]);
@@ -192,19 +269,28 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   std::vector<Bvh> blas(n_protos);
   std::vector<int32_t> order_p(n_protos);
   for (int32_t p = 0; p < n_protos; ++p) order_p[p] = p;
-  std::sort(order_p.begin(), order_p.end(), [&](int a, int b) { return protos[a].n_quads > protos[b].n_quads; });
+  std::sort(order_p.begin(), order_p.end(), [&](int a, int b) { return n_prim[a] > n_prim[b]; });
   const int nthreads_all =
       o.build_threads > 0 ? o.build_threads : (int)std::max(1u, std::thread::hardware_concurrency());
   // prototypes of kBigProto quads or more are built one at a time on every
   // thread (they come first in order_p); the rest concurrently, one per thread
   constexpr int32_t kBigProto = 1 << 18;
   int32_t n_big = 0;
-  while (n_big < n_protos && protos[order_p[n_big]].n_quads >= kBigProto) ++n_big;
+  while (n_big < n_protos && n_prim[order_p[n_big]] >= kBigProto) ++n_big;
   const int nthreads = std::min(nthreads_all, std::max(1, n_protos - n_big));
   std::atomic<int32_t> next{n_big};
+  // capsules of every curve prototype (empty for quad meshes), in curve order
+  std::vector<std::vector<Capsule>> caps(n_protos);
+  for (int32_t p = 0; p < n_protos; ++p) {
+    if (protos[p].n_curves == 0) continue;
+    caps[p].resize((size_t)n_prim[p]);
+    for (int32_t c = 0; c < protos[p].n_curves; ++c)
+      tessellate_curve(protos[p].curves + 16 * (int64_t)c, &caps[p][(size_t)c * kCapsPerCurve]);
+  }
   auto build_proto = [&](int32_t p, int threads, std::vector<Aabb>& boxes) {
     const rtq_prototype& P = protos[p];
-    boxes.resize(P.n_quads);
+    boxes.resize(n_prim[p]);
+    for (int32_t k = 0; k < (int32_t)caps[p].size(); ++k) boxes[k] = capsule_box(caps[p][k]);
     for (int32_t q = 0; q < P.n_quads; ++q) {
       Aabb b;
       for (int a = 0; a < 3; ++a) {
@@ -222,7 +308,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     }
     BuildParams pp = bp;
     pp.threads = threads;
-    build_bvh(boxes.data(), P.n_quads, pp, blas[p]);
+    build_bvh(boxes.data(), n_prim[p], pp, blas[p]);
   };
   {
     std::vector<Aabb> boxes;
@@ -255,16 +341,19 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   s->n_protos = n_protos;
   s->n_inst = N;
   s->n_quads = total_quads;
+  s->n_curves = total_curves;
+  s->n_caps = total_prims - total_quads;
+  s->n_faces = total_faces;
   (void)hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (s->n_cu <= 0) s->n_cu = 256;
   (void)hipDeviceGetAttribute(&s->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (s->max_lds <= 0) s->max_lds = 65536;
 
   // ---- concatenate the bottom levels with absolute references
-  std::vector<uint32_t> proto_root(n_protos), face_base(n_protos);
+  std::vector<uint32_t> proto_root(n_protos), face_base(n_protos), proto_flags(n_protos);
   std::vector<int32_t> proto_qbase(n_protos), proto_nq(n_protos);
   std::vector<float> proto_pmax(n_protos);
-  uint64_t node_base = 0, quad_base = 0;
+  uint64_t node_base = 0, quad_base = 0, fbase = 0;
   int max_blas_depth = 0;
   for (int32_t p = 0; p < n_protos; ++p) {
     if (node_base + blas[p].nodes.size() >= (uint64_t)kLeafBit) {
@@ -274,24 +363,48 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
       return set_error(RTQ_E_LIMIT, "reference overflow while relocating prototype %d", p);
     }
     proto_root[p] = (uint32_t)node_base;
-    face_base[p] = (uint32_t)quad_base;  // original-order face offset equals the leaf-order quad offset
+    face_base[p] = (uint32_t)fbase;  // faces: quads, or curves, in prototype order
+    proto_flags[p] = protos[p].n_curves > 0 ? kProtoCurve : 0u;
     proto_qbase[p] = (int32_t)quad_base;
-    proto_nq[p] = protos[p].n_quads;
+    proto_nq[p] = n_prim[p];
     proto_pmax[p] = level_pmax(blas[p]);
     if (!(proto_pmax[p] < kMaxPlaneAbs)) {
       return set_error(RTQ_E_LIMIT, "prototype %d has coordinates beyond 2^60", p);
     }
     max_blas_depth = std::max(max_blas_depth, blas[p].depth);
     node_base += blas[p].nodes.size();
-    quad_base += protos[p].n_quads;
+    quad_base += n_prim[p];
+    fbase += protos[p].n_curves > 0 ? protos[p].n_curves : protos[p].n_quads;
   }
   const size_t n_blas_nodes = node_base;
-  std::vector<float4> quads(3 * (size_t)total_quads);
-  std::vector<int32_t> quad_prim(total_quads);
-  std::vector<float> albedo(total_quads);
+  std::vector<float4> quads(3 * (size_t)total_prims);
+  std::vector<int32_t> quad_prim(total_prims);
+  std::vector<float> albedo(total_faces);
+  // world boxes of curve instances bound the corners of their capsules' boxes
+  std::vector<float> cap_corners;
+  std::vector<int64_t> corner_off(n_protos + 1, 0);
+  for (int32_t p = 0; p < n_protos; ++p) corner_off[p + 1] = corner_off[p] + 8 * (int64_t)caps[p].size();
+  cap_corners.resize(3 * (size_t)corner_off[n_protos]);
   for (int32_t p = 0; p < n_protos; ++p) {
     const rtq_prototype& P = protos[p];
     const size_t qb = proto_qbase[p];
+    for (int32_t j = 0; j < (int32_t)caps[p].size(); ++j) {
+      const uint32_t k = blas[p].order[j];
+      const Capsule& c = caps[p][k];
+      quads[3 * (qb + j) + 0] = make_float4(c.a[0], c.a[1], c.a[2], c.r);
+      quads[3 * (qb + j) + 1] = make_float4(c.b[0], c.b[1], c.b[2], 0.0f);
+      quads[3 * (qb + j) + 2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      quad_prim[qb + j] = (int32_t)k;
+      const Aabb bx = capsule_box(c);
+      float* out = &cap_corners[3 * (size_t)(corner_off[p] + 8 * (int64_t)k)];
+      for (int m = 0; m < 8; ++m) {
+        out[3 * m + 0] = (m & 1) ? bx.hi[0] : bx.lo[0];
+        out[3 * m + 1] = (m & 2) ? bx.hi[1] : bx.lo[1];
+        out[3 * m + 2] = (m & 4) ? bx.hi[2] : bx.lo[2];
+      }
+    }
+    for (int32_t c = 0; c < P.n_curves; ++c) albedo[face_base[p] + c] = P.albedo ? P.albedo[c] : 0.5f;
+    caps[p] = std::vector<Capsule>();
     for (int32_t j = 0; j < P.n_quads; ++j) {
       const uint32_t q = blas[p].order[j];
       const int32_t* iq = P.quads + 4 * (int64_t)q;
@@ -303,7 +416,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
       quads[3 * (qb + j) + 2] = make_float4(f[8], f[9], f[10], f[11]);
       quad_prim[qb + j] = (int32_t)q;
     }
-    for (int32_t q = 0; q < P.n_quads; ++q) albedo[qb + q] = P.albedo ? P.albedo[q] : 0.5f;
+    for (int32_t q = 0; q < P.n_quads; ++q) albedo[face_base[p] + q] = P.albedo ? P.albedo[q] : 0.5f;
   }
 
 #define UPLOAD(dst, src, bytes)                                                   \
@@ -358,8 +471,13 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   TALLOC(d_proto, Nn * sizeof(int32_t));
   TALLOC(d_root, n_protos * sizeof(uint32_t));
   TALLOC(d_face, n_protos * sizeof(uint32_t));
+  uint32_t* d_pflags = nullptr;
+  TALLOC(d_pflags, n_protos * sizeof(uint32_t));
+  // points whose transformed bounds give an instance's world box: the mesh's
+  // vertices, or the corners of the capsules' boxes
   std::vector<int64_t> vert_off(n_protos + 1, 0);
-  for (int32_t p = 0; p < n_protos; ++p) vert_off[p + 1] = vert_off[p] + protos[p].n_verts;
+  for (int32_t p = 0; p < n_protos; ++p)
+    vert_off[p + 1] = vert_off[p] + (protos[p].n_curves > 0 ? corner_off[p + 1] - corner_off[p] : protos[p].n_verts);
   TALLOC(d_verts, std::max<int64_t>(3 * vert_off[n_protos], 1) * sizeof(float));
   TALLOC(d_voff, (n_protos + 1) * sizeof(int64_t));
   TALLOC(d_cond, Nn * sizeof(float));
@@ -372,13 +490,18 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   }
   TCHECK(hipMemcpy(d_root, proto_root.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
   TCHECK(hipMemcpy(d_face, face_base.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
-  for (int32_t p = 0; p < n_protos; ++p)
-    if (protos[p].n_verts > 0)
-      TCHECK(hipMemcpy(d_verts + 3 * vert_off[p], protos[p].verts, 3 * (size_t)protos[p].n_verts * sizeof(float),
-                       hipMemcpyHostToDevice),
-             "hipMemcpy");
+  TCHECK(hipMemcpy(d_pflags, proto_flags.data(), n_protos * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+  for (int32_t p = 0; p < n_protos; ++p) {
+    const int64_t nv = vert_off[p + 1] - vert_off[p];
+    if (nv == 0) continue;
+    const float* src = protos[p].n_curves > 0 ? &cap_corners[3 * (size_t)corner_off[p]] : protos[p].verts;
+    TCHECK(hipMemcpy(d_verts + 3 * vert_off[p], src, 3 * (size_t)nv * sizeof(float), hipMemcpyHostToDevice),
+           "hipMemcpy");
+  }
+  cap_corners = std::vector<float>();
   TCHECK(hipMemcpy(d_voff, vert_off.data(), (n_protos + 1) * sizeof(int64_t), hipMemcpyHostToDevice), "hipMemcpy");
-  TCHECK(launch_invert_affine(d_x, d_proto, d_root, d_face, N, d_rec, d_cond, d_status, 0), "invert kernel");
+  TCHECK(launch_invert_affine(d_x, d_proto, d_root, d_face, d_pflags, N, d_rec, d_cond, d_status, 0),
+         "invert kernel");
   TCHECK(launch_instance_aabb(d_x, d_proto, d_verts, d_voff, d_cond, N, d_box, 0), "aabb kernel");
   std::vector<int32_t> status(N);
   std::vector<float> cond(N);
@@ -502,7 +625,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   if (!s->counters) return hip_error(e, "hipMalloc");
   TCHECK(hipDeviceSynchronize(), "hipDeviceSynchronize");
   tmp.release();
-  for (int64_t i = 0; i < N; ++i) s->n_instanced_quads += protos[insts->proto[i]].n_quads;
+  for (int64_t i = 0; i < N; ++i) s->n_instanced_quads += protos[insts->proto[i]].n_quads;  // quads only
   s->build_phase[3] = since(t1);
   s->build_seconds = since(t0);
   *out = holder.release();
@@ -549,6 +672,9 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
   info->blas_depth_max = s->blas_depth;
   info->formats = s->formats;
   info->node_width = s->width;
+  info->n_unique_curves = s->n_curves;
+  info->n_unique_capsules = s->n_caps;
+  info->n_faces = s->n_faces;
   info->device_bytes = (int64_t)(s->bufs.total + s->scratch.total + s->tex_bytes + s->env_bytes + s->mat_bytes);
   info->build_seconds = s->build_seconds;
   info->n_top_entries = s->n_rec;
@@ -558,9 +684,9 @@ int rtq_scene_get_info(const rtq_scene* s, rtq_scene_info* info) {
 
 int rtq_scene_set_albedo(rtq_scene* s, const float* albedo_dev, int64_t n, hipStream_t stream) {
   if (!s || !albedo_dev) return set_error(RTQ_E_INVALID_ARG, "NULL argument");
-  if (n != s->n_quads)
+  if (n != s->n_faces)
     return set_error(RTQ_E_INVALID_ARG, "albedo has %lld entries, scene has %lld faces", (long long)n,
-                     (long long)s->n_quads);
+                     (long long)s->n_faces);
   const hipError_t e = hipMemcpyAsync(s->albedo, albedo_dev, n * sizeof(float), hipMemcpyDeviceToDevice, stream);
   return e == hipSuccess ? RTQ_OK : hip_error(e, "hipMemcpyAsync");
 }
@@ -594,10 +720,10 @@ int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_ma
   (void)stream;
   std::vector<uint8_t> fm;
   if (n_mat > 0) {
-    fm.resize(s->n_quads);
-    e = hipMemcpy(fm.data(), face_mat_dev, s->n_quads, hipMemcpyDeviceToHost);
+    fm.resize(s->n_faces);
+    e = hipMemcpy(fm.data(), face_mat_dev, s->n_faces, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_error(e, "hipMemcpy");
-    for (int64_t f = 0; f < s->n_quads; ++f)
+    for (int64_t f = 0; f < s->n_faces; ++f)
       if (fm[f] >= n_mat) return set_error(RTQ_E_INVALID_ARG, "face %lld: material %d >= %d", (long long)f, fm[f], n_mat);
   }
   if (s->mats) (void)hipFree(s->mats);
@@ -610,9 +736,9 @@ int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_ma
   void* dm = nullptr;
   void* df = nullptr;
   e = hipMalloc(&dm, n_mat * sizeof(MatDev));
-  if (e == hipSuccess) e = hipMalloc(&df, (size_t)s->n_quads);
+  if (e == hipSuccess) e = hipMalloc(&df, (size_t)s->n_faces);
   if (e == hipSuccess) e = hipMemcpy(dm, md.data(), n_mat * sizeof(MatDev), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(df, fm.data(), (size_t)s->n_quads, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(df, fm.data(), (size_t)s->n_faces, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (dm) (void)hipFree(dm);
     if (df) (void)hipFree(df);
@@ -621,7 +747,7 @@ int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_ma
   s->mats = dm;
   s->face_mat = static_cast<uint8_t*>(df);
   s->n_mat = n_mat;
-  s->mat_bytes = n_mat * sizeof(MatDev) + (size_t)s->n_quads;
+  s->mat_bytes = n_mat * sizeof(MatDev) + (size_t)s->n_faces;
   return RTQ_OK;
 }
 
@@ -630,6 +756,8 @@ int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, h
   if (res < 0 || res > RTQ_MAX_TEX_RES)
     return set_error(RTQ_E_INVALID_ARG, "texture resolution %d outside [0, %d]", res, RTQ_MAX_TEX_RES);
   if (res > 0 && !texels_dev) return set_error(RTQ_E_INVALID_ARG, "NULL texels");
+  if (res > 0 && s->n_curves > 0)
+    return set_error(RTQ_E_INVALID_ARG, "textures need (u, v) squares: the scene has curves");
   hipError_t e = hipSetDevice(s->device);
   if (e != hipSuccess) return hip_error(e, "hipSetDevice");
   // renders already queued may still read the old texels

@@ -47,6 +47,8 @@ struct rtq_scene {
   int max_lds = 65536;  // bytes of LDS one block may use
   int32_t n_protos = 0;
   int64_t n_inst = 0, n_quads = 0, n_instanced_quads = 0;
+  int64_t n_curves = 0, n_caps = 0;  // unique curves and their capsules
+  int64_t n_faces = 0;               // unique faces: quads and curves
   int64_t n_rec = 0;  // top-level entries (instances, opened ones counted per subtree)
   int64_t tlas_nodes = 0, blas_nodes = 0;
   int tlas_depth = 0, blas_depth = 0;
@@ -59,8 +61,8 @@ struct rtq_scene {
   void* nodes_f32 = nullptr;  // [bottom levels | top level], FP32 nodes
   void* nodes_q8 = nullptr;   // same topology, quantized nodes
   float* rec_pmax = nullptr;  // per instance record: bound on |object coordinate| of its prototype's planes
-  float4* quads = nullptr;
-  int32_t* quad_prim = nullptr;
+  float4* quads = nullptr;      // leaf-ordered primitives: quads and capsules, 3 float4 each
+  int32_t* quad_prim = nullptr; // leaf order -> primitive index within its prototype
   rtq::InstRec* inst = nullptr;
   uint32_t* rec_qfirst = nullptr;  // per record: quad range of the subtree it enters
   uint32_t* rec_nq = nullptr;

@@ -11,21 +11,26 @@
 namespace rtq {
 
 // Call f with std::integral_constant<int, CODEC> for the run-time node codec id
-// (kCodecF32, kCodecQ8, kCodecQ8W8, kCodecQ8W2), so a launcher instantiates its
-// kernels once per codec.
+// (kCodecF32, kCodecQ8, kCodecQ8W8, kCodecQ8W2, each with or without
+// kCodecCurves), so a launcher instantiates its kernels once per codec.
 template <class F>
 decltype(auto) with_codec(int fmt, F&& f) {
+  constexpr int C = kCodecCurves;
   switch (fmt) {
     case kCodecQ8: return f(std::integral_constant<int, kCodecQ8>{});
     case kCodecQ8W8: return f(std::integral_constant<int, kCodecQ8W8>{});
     case kCodecQ8W2: return f(std::integral_constant<int, kCodecQ8W2>{});
+    case kCodecF32 | C: return f(std::integral_constant<int, kCodecF32 | C>{});
+    case kCodecQ8 | C: return f(std::integral_constant<int, kCodecQ8 | C>{});
+    case kCodecQ8W8 | C: return f(std::integral_constant<int, kCodecQ8W8 | C>{});
+    case kCodecQ8W2 | C: return f(std::integral_constant<int, kCodecQ8W2 | C>{});
     default: return f(std::integral_constant<int, kCodecF32>{});
   }
 }
 
 hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint32_t* proto_root,
-                                const uint32_t* face_base, int64_t n, InstRec* out, float* cond, int32_t* status,
-                                hipStream_t s);
+                                const uint32_t* face_base, const uint32_t* proto_flags, int64_t n, InstRec* out,
+                                float* cond, int32_t* status, hipStream_t s);
 hipError_t launch_instance_aabb(const float* X, const int32_t* proto, const float* verts, const int64_t* vert_off,
                                 const float* cond, int64_t n, float* box, hipStream_t s);
 // out[k] = in[order[k]] with its bottom-level entry reference replaced by root[k].
@@ -44,7 +49,7 @@ struct HitsSoA {
 };
 
 struct TraceLaunch {
-  int fmt;          // node codec: kCodecF32, kCodecQ8, kCodecQ8W8 or kCodecQ8W2
+  int fmt;          // node codec: kCodecF32, kCodecQ8, kCodecQ8W8 or kCodecQ8W2, | kCodecCurves
   int persistent;   // 0 plain, 1 persistent with refill
   int stack_depth;  // LDS entries per lane
   int block;        // threads per block

@@ -16,7 +16,7 @@ namespace rtq {
 // non-finite.
 __global__ void k_invert_affine_fp64(const float* __restrict__ X, const int32_t* __restrict__ proto,
                                      const uint32_t* __restrict__ proto_root, const uint32_t* __restrict__ face_base,
-                                     int64_t n, InstRec* __restrict__ out, float* __restrict__ cond,
+                                     const uint32_t* __restrict__ proto_flags, int64_t n, InstRec* __restrict__ out, float* __restrict__ cond,
                                      int32_t* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -53,7 +53,7 @@ __global__ void k_invert_affine_fp64(const float* __restrict__ X, const int32_t*
   rec.blas_root = proto_root[p];
   rec.inst_id = (uint32_t)i;
   rec.face_base = face_base[p];
-  rec.proto = (uint32_t)p;
+  rec.proto = (uint32_t)p | proto_flags[p];
   out[i] = rec;
   cond[i] = ok ? (float)(sqrt(fa) * sqrt(fi)) : 0.0f;
   status[i] = ok ? 0 : 1;
@@ -142,11 +142,11 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_invert_affine(const float* X, const int32_t* proto, const uint32_t* proto_root,
-                                const uint32_t* face_base, int64_t n, InstRec* out, float* cond, int32_t* status,
-                                hipStream_t s) {
+                                const uint32_t* face_base, const uint32_t* proto_flags, int64_t n, InstRec* out,
+                                float* cond, int32_t* status, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_invert_affine_fp64, dim3(grid_for(n, 256)), dim3(256), 0, s, X, proto, proto_root, face_base,
-                     n, out, cond, status);
+                     proto_flags, n, out, cond, status);
   return hipGetLastError();
 }
 

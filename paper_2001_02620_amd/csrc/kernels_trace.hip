@@ -21,11 +21,14 @@ __device__ __forceinline__ void store_result(const Lane& L, const SceneView& sc,
     occ[i] = hit ? 1 : 0;
     return;
   }
+  const int32_t prim = hit ? sc.quad_prim[L.b_qh & 0x7FFFFFFFu] : -1;
+  // a capsule hit carries its axis position y: u is the curve parameter (j + y) / 8
+  const bool cap = hit && (sc.inst[L.b_rec].proto & kProtoCurve) != 0u;
   h.t[i] = hit ? L.t_best : kInfF;
-  h.u[i] = hit ? L.b_u : 0.0f;
+  h.u[i] = hit ? (cap ? ((float)(prim % kCapsPerCurve) + L.b_u) * (1.0f / kCapsPerCurve) : L.b_u) : 0.0f;
   h.v[i] = hit ? L.b_v : 0.0f;
   h.inst[i] = hit ? (int32_t)sc.inst[L.b_rec].inst_id : -1;
-  h.prim[i] = hit ? sc.quad_prim[L.b_qh & 0x7FFFFFFFu] : -1;
+  h.prim[i] = prim;
   if (h.ref) reinterpret_cast<uint2*>(h.ref)[i] = hit ? make_uint2(L.b_rec, L.b_qh) : make_uint2(kEmpty, kEmpty);
 }
 
@@ -114,7 +117,7 @@ __global__ void k_trace_persistent(SceneView sc, RaysSoA rays, int64_t n, HitsSo
   }
 }
 
-// Reference: every instance, every quad, the same leaf code.
+// Reference: every instance, every quad or capsule, the same leaf code.
 __global__ void k_trace_brute(SceneView sc, RaysSoA rays, int64_t n, HitsSoA hits) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;

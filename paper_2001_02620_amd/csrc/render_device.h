@@ -161,29 +161,58 @@ __device__ __forceinline__ uint32_t face_texel(const SceneView& sc, uint32_t fac
   return (face * (uint32_t)R + (uint32_t)ty) * (uint32_t)R + (uint32_t)tx;
 }
 
-// Geometric normal of the hit half in object space, mapped to world space by
-// A^-T (columns of the stored inverse rows), normalised and turned to face the
-// incoming ray; hit point p = o + t d; albedo of the unique prototype face, or
-// its texel at the hit's (u, v) when the scene has textures.
+// Geometric normal of the hit in object space -- the hit half's for a quad; for
+// a capsule the hit point minus its closest point on the axis -- mapped to world
+// space by A^-T (columns of the stored inverse rows), normalised and turned to
+// face the incoming ray; hit point p = o + t d; albedo of the unique prototype
+// face (a quad, or the capsule's curve), or its texel at the hit's (u, v) when
+// the scene has textures.
 __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderParams& rp, const Ray3& r, float t,
                                            uint32_t rec, uint32_t quad, uint32_t half, float u, float v) {
   const float4 f0 = sc.quads[3 * (size_t)quad + 0];
   const float4 f1 = sc.quads[3 * (size_t)quad + 1];
   const float4 f2 = sc.quads[3 * (size_t)quad + 2];
-  // v0 = f0.xyz, v1 = (f0.w, f1.x, f1.y), v2 = (f1.z, f1.w, f2.x), v3 = (f2.y, f2.z, f2.w)
-  float ax, ay, az, bx, by, bz;
-  if (half == 0u) {  // (v1 - v0) x (v3 - v0)
-    ax = f0.w - f0.x; ay = f1.x - f0.y; az = f1.y - f0.z;
-    bx = f2.y - f0.x; by = f2.z - f0.y; bz = f2.w - f0.z;
-  } else {           // (v3 - v2) x (v1 - v2)
-    ax = f2.y - f1.z; ay = f2.z - f1.w; az = f2.w - f2.x;
-    bx = f0.w - f1.z; by = f1.x - f1.w; bz = f1.y - f2.x;
-  }
-  const float onx = ay * bz - az * by, ony = az * bx - ax * bz, onz = ax * by - ay * bx;
   const InstRec& ir = sc.inst[rec];
   const float4 r0 = *reinterpret_cast<const float4*>(ir.r0);
   const float4 r1 = *reinterpret_cast<const float4*>(ir.r1);
   const float4 r2 = *reinterpret_cast<const float4*>(ir.r2);
+  const bool cap = (ir.proto & kProtoCurve) != 0u;
+  float onx, ony, onz;
+  if (cap) {
+    // capsule (a, r) = f0, b = f1.xyz.  Its normal follows the hit point, so the
+    // point is formed in FP64 from the FP32 ray and t (exact products, one
+    // rounding per sum) relative to the instance origin, where it is small,
+    // before the stored inverse rows map it to object space: the normal then
+    // carries the rounding of those rows and of the capsule (about 2^-24 of the
+    // object coordinates over the radius), not that of the ray's length
+    const double hx = ((double)r.ox - (double)r0.w) + (double)t * (double)r.dx;
+    const double hy = ((double)r.oy - (double)r1.w) + (double)t * (double)r.dy;
+    const double hz = ((double)r.oz - (double)r2.w) + (double)t * (double)r.dz;
+    const double px = (double)r0.x * hx + (double)r0.y * hy + (double)r0.z * hz;
+    const double py = (double)r1.x * hx + (double)r1.y * hy + (double)r1.z * hz;
+    const double pz = (double)r2.x * hx + (double)r2.y * hy + (double)r2.z * hz;
+    const double bax = (double)f1.x - (double)f0.x, bay = (double)f1.y - (double)f0.y,
+                 baz = (double)f1.z - (double)f0.z;
+    const double wx = px - (double)f0.x, wy = py - (double)f0.y, wz = pz - (double)f0.z;
+    const double bb = bax * bax + bay * bay + baz * baz;
+    const double sa = bb > 0.0 ? fmin(fmax((wx * bax + wy * bay + wz * baz) / bb, 0.0), 1.0) : 0.0;
+    onx = (float)(wx - sa * bax);
+    ony = (float)(wy - sa * bay);
+    onz = (float)(wz - sa * baz);
+  } else {
+    // v0 = f0.xyz, v1 = (f0.w, f1.x, f1.y), v2 = (f1.z, f1.w, f2.x), v3 = (f2.y, f2.z, f2.w)
+    float ax, ay, az, bx, by, bz;
+    if (half == 0u) {  // (v1 - v0) x (v3 - v0)
+      ax = f0.w - f0.x; ay = f1.x - f0.y; az = f1.y - f0.z;
+      bx = f2.y - f0.x; by = f2.z - f0.y; bz = f2.w - f0.z;
+    } else {           // (v3 - v2) x (v1 - v2)
+      ax = f2.y - f1.z; ay = f2.z - f1.w; az = f2.w - f2.x;
+      bx = f0.w - f1.z; by = f1.x - f1.w; bz = f1.y - f2.x;
+    }
+    onx = ay * bz - az * by;
+    ony = az * bx - ax * bz;
+    onz = ax * by - ay * bx;
+  }
   float nx = r0.x * onx + r1.x * ony + r2.x * onz;
   float ny = r0.y * onx + r1.y * ony + r2.y * onz;
   float nz = r0.z * onx + r1.z * ony + r2.z * onz;
@@ -203,7 +232,8 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   s.nx = nx;
   s.ny = ny;
   s.nz = nz;
-  s.face = ir.face_base + (uint32_t)sc.quad_prim[quad];
+  const uint32_t prim = (uint32_t)sc.quad_prim[quad];
+  s.face = ir.face_base + (cap ? prim / (uint32_t)kCapsPerCurve : prim);
   s.param = sc.tex_res > 0 ? face_texel(sc, s.face, u, v) : s.face;
   s.a = sc.tex_res > 0 ? sc.tex[s.param] : sc.albedo[s.face];
   s.cosl = nx * rp.lx + ny * rp.ly + nz * rp.lz;

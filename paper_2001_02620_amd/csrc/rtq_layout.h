@@ -4,8 +4,9 @@
 // under a top-level BVH over the instances; quads are the primitives):
 //   * top level (TLAS): W-wide nodes over instance world boxes; a leaf holds one
 //     instance record index.
-//   * bottom level (BLAS): W-wide nodes per prototype over its quads; a leaf
-//     holds 1..8 consecutive quads of the global leaf-ordered quad array.
+//   * bottom level (BLAS): W-wide nodes per prototype over its primitives (its
+//     quads, or the capsules its curves are traced as); a leaf holds 1..8
+//     consecutive primitives of the global leaf-ordered primitive array.
 // The node width W (2, 4 or 8) is chosen per scene at build; FP32 nodes exist
 // at W = 4 only, quantized nodes at every width.
 // Child references are 32-bit offsets from one 64-bit array base per level (the
@@ -85,6 +86,11 @@ constexpr int kMaxWidth = 8;
 
 // Kernel node codecs: FP32 4-wide, and quantized 4-, 8- and 2-wide.
 constexpr int kCodecF32 = 1, kCodecQ8 = 2, kCodecQ8W8 = 3, kCodecQ8W2 = 4;
+// Flag added to the codec of a scene with curves: its kernels carry the capsule
+// test beside the quad test, while scenes of quads alone run kernels without it
+// (fewer registers, more waves per SIMD).
+constexpr int kCodecCurves = 16;
+constexpr int kCodecMask = 15;
 
 // uint4 words per quantized node of width w, and the 32-bit word at which its
 // child references start.
@@ -100,13 +106,20 @@ struct alignas(16) InstRec {
   uint32_t blas_root;  // absolute index of the prototype's root node
   uint32_t inst_id;    // caller's instance index
   uint32_t face_base;  // first unique face of the prototype (albedo index base)
-  uint32_t proto;      // prototype index
+  uint32_t proto;      // prototype index, kProtoCurve set for a prototype of curves
 };
 static_assert(sizeof(InstRec) == 64, "InstRec is 64 B");
 
-// Quads are stored in leaf order as 3 x float4:
+// Primitives are stored in leaf order as 3 x float4.  A quad:
 //   (v0.x v0.y v0.z v1.x) (v1.y v1.z v2.x v2.y) (v2.z v3.x v3.y v3.z)
+// A capsule (axis from a to b, radius r):
+//   (a.x a.y a.z r) (b.x b.y b.z 0) (0 0 0 0)
 constexpr int kQuadFloat4 = 3;
+
+// Curves (Section 5.2): a cubic Bezier traced as kCapsPerCurve capsules; the
+// capsules of curve c of a prototype are its primitives kCapsPerCurve c + j.
+constexpr int kCapsPerCurve = 8;
+constexpr uint32_t kProtoCurve = 0x80000000u;  // InstRec::proto flag: the prototype holds curves
 
 // Traversal stack per lane: every W-wide level pushes at most W - 1 entries,
 // so a scene needs (W - 1) (top depth + bottom depth) + 8 entries at most; the

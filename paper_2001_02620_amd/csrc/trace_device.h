@@ -95,6 +95,7 @@ struct Lane {
   float lox, loy, loz;
   float Sx, Sy, Sz;
   int kz;            // dominant axis of the object-space direction
+  bool curve;        // the current instance's prototype holds curves (capsule leaves)
   // traversal
   uint32_t cur;      // reference to process next, kEmpty = pop
   int sp;            // stack size
@@ -153,6 +154,7 @@ __device__ __forceinline__ void enter_instance(Lane& L, const SceneView& sc, uin
   const float4 b = *reinterpret_cast<const float4*>(sc.inst[r].r1);
   const float4 c = *reinterpret_cast<const float4*>(sc.inst[r].r2);
   const uint32_t root = sc.inst[r].blas_root;
+  const uint32_t proto = sc.inst[r].proto;
   const float pmax = sc.rec_pmax[r];
   const float px = L.wox - a.w, py = L.woy - b.w, pz = L.woz - c.w;
   const float ox = fmaf(a.x, px, fmaf(a.y, py, a.z * pz));
@@ -180,6 +182,7 @@ __device__ __forceinline__ void enter_instance(Lane& L, const SceneView& sc, uin
   L.Sx = pick3(dx, dy, dz, kx) * L.Sz;
   L.Sy = pick3(dx, dy, dz, ky) * L.Sz;
   L.rec = r;
+  L.curve = (proto & kProtoCurve) != 0u;
   *blas_root = root;
 }
 
@@ -581,11 +584,166 @@ __device__ __forceinline__ bool quad_test(Lane& L, const SceneView& sc, bool act
   return false;
 }
 
-// Test quads [first, first + count) of the current instance on every lane.
+// ---- capsule test -----------------------------------------------------------------
+// Curves (Section 5.2) are traced as chains of capsules: a capsule is the set of
+// points within r of the segment [a, b], entered from outside only.  The test
+// runs in object space in FP32:
+//   * the direction is recomputed from the instance record with the expressions
+//     of enter_instance (bit-identical to the lane's leaf-test frame) and scaled
+//     by a power of two so that |d|_inf lies in [0.5, 1) (exact; the squares
+//     below stay in range for any ray);
+//   * a ray starting inside the capsule misses it;
+//   * the quadratics are solved from the ray's point of closest approach to the
+//     axis midpoint, so their coefficients are formed next to the capsule, and
+//     their roots are taken in the cancellation-free form
+//     q = -(b + sign(b) sqrt(b^2 - a c)), roots q / a and c / q;
+//   * the cylinder around the axis, |(b - a) x (p - a)|^2 = r^2 |b - a|^2, is
+//     written with cross products (Lagrange's identity), which keeps its
+//     leading coefficient exact in sign for a ray nearly parallel to the axis.
+// A ray outside the infinite cylinder enters it at the smaller root; there it is
+// on the capsule's body when the axial coordinate lies within the segment, else
+// it can only enter through the end sphere on that side.  A ray starting inside
+// the infinite cylinder (beyond an end) or parallel to the axis can only enter
+// through an end sphere, the nearer one.
+struct CapResult {
+  float t;  // entry parameter in the world ray's units, kInfF for none at t >= 0
+  float y;  // position of the entry along the axis, 0 at a and 1 at b
+};
+
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+  return fmaf(ax, bx, fmaf(ay, by, az * bz));
+}
+
+// Smaller root s of |p + s d - c|^2 = r^2 (dd = d.d), or kInfF when the line
+// misses the sphere.
+__device__ __forceinline__ float sphere_root(float px, float py, float pz, float cx, float cy, float cz, float rr,
+                                             float dx, float dy, float dz, float dd) {
+  const float ox = px - cx, oy = py - cy, oz = pz - cz;
+  const float b = dot3(ox, oy, oz, dx, dy, dz);
+  const float c = dot3(ox, oy, oz, ox, oy, oz) - rr;
+  const float disc = b * b - dd * c;
+  if (!(disc >= 0.0f)) return kInfF;
+  const float q = -(b + copysignf(sqrtf(disc), b));
+  return fminf(q / dd, c / q);  // q = 0 only for a line touching the sphere at p: q / dd = 0
+}
+
+// Capsule q under instance record `rec` (both valid indices on every lane).
+__device__ __forceinline__ CapResult cap_hit(const Lane& L, const SceneView& sc, uint32_t rec, uint32_t q) {
+  CapResult res{kInfF, 0.0f};
+  const float4 c0 = sc.quads[3 * (size_t)q + 0];
+  const float4 c1 = sc.quads[3 * (size_t)q + 1];
+  const float4 ra = *reinterpret_cast<const float4*>(sc.inst[rec].r0);
+  const float4 rb = *reinterpret_cast<const float4*>(sc.inst[rec].r1);
+  const float4 rc = *reinterpret_cast<const float4*>(sc.inst[rec].r2);
+  float dx = fmaf(ra.x, L.wdx, fmaf(ra.y, L.wdy, ra.z * L.wdz));
+  float dy = fmaf(rb.x, L.wdx, fmaf(rb.y, L.wdy, rb.z * L.wdz));
+  float dz = fmaf(rc.x, L.wdx, fmaf(rc.y, L.wdy, rc.z * L.wdz));
+  const float dm = fmaxf(fabsf(dx), fmaxf(fabsf(dy), fabsf(dz)));
+  if (!(dm > 0.0f) || !(dm < kInfF)) return res;
+  const int e = __builtin_amdgcn_frexp_expf(dm);
+  dx = __builtin_amdgcn_ldexpf(dx, -e);
+  dy = __builtin_amdgcn_ldexpf(dy, -e);
+  dz = __builtin_amdgcn_ldexpf(dz, -e);
+  const float ax = c0.x, ay = c0.y, az = c0.z, r = c0.w, rr = r * r;
+  const float bax = c1.x - ax, bay = c1.y - ay, baz = c1.z - az;
+  const float bb = dot3(bax, bay, baz, bax, bay, baz);
+  // the origin inside the capsule: no entry
+  const float wx = L.lox - ax, wy = L.loy - ay, wz = L.loz - az;
+  const float s0 = bb > 0.0f ? fminf(fmaxf(dot3(wx, wy, wz, bax, bay, baz) / bb, 0.0f), 1.0f) : 0.0f;
+  const float ex = fmaf(-s0, bax, wx), ey = fmaf(-s0, bay, wy), ez = fmaf(-s0, baz, wz);
+  if (dot3(ex, ey, ez, ex, ey, ez) < rr) return res;
+  // closest approach of the axis midpoint
+  const float dd = dot3(dx, dy, dz, dx, dy, dz);
+  const float mx = fmaf(0.5f, bax, ax), my = fmaf(0.5f, bay, ay), mz = fmaf(0.5f, baz, az);
+  const float t0 = dot3(mx - L.lox, my - L.loy, mz - L.loz, dx, dy, dz) / dd;
+  const float px = fmaf(t0, dx, L.lox), py = fmaf(t0, dy, L.loy), pz = fmaf(t0, dz, L.loz);
+  // which end spheres to test: 1 = a, 2 = b, 3 = both (the nearer wins)
+  int ends = 0;
+  float s = kInfF, y = 0.0f;
+  const float gx = bay * wz - baz * wy, gy = baz * wx - bax * wz, gz = bax * wy - bay * wx;  // ba x (o - a)
+  const float ux = bay * dz - baz * dy, uy = baz * dx - bax * dz, uz = bax * dy - bay * dx;  // ba x d
+  const float A = dot3(ux, uy, uz, ux, uy, uz);
+  if (dot3(gx, gy, gz, gx, gy, gz) - rr * bb < 0.0f || !(A > 0.0f)) {
+    ends = 3;
+  } else {
+    const float pax = px - ax, pay = py - ay, paz = pz - az;
+    const float vx = bay * paz - baz * pay, vy = baz * pax - bax * paz, vz = bax * pay - bay * pax;  // ba x (p - a)
+    const float B = dot3(vx, vy, vz, ux, uy, uz);
+    const float C = dot3(vx, vy, vz, vx, vy, vz) - rr * bb;
+    const float disc = B * B - A * C;
+    if (disc >= 0.0f) {
+      const float qq = -(B + copysignf(sqrtf(disc), B));
+      const float sc_ = fminf(qq / A, C / qq);
+      if (t0 + sc_ >= 0.0f) {
+        const float ya = fmaf(sc_, dot3(bax, bay, baz, dx, dy, dz), dot3(bax, bay, baz, pax, pay, paz));
+        if (ya >= 0.0f && ya <= bb) {
+          s = sc_;
+          y = ya / bb;
+        } else {
+          ends = ya < 0.0f ? 1 : 2;
+        }
+      }
+    }
+  }
+  if (ends & 1) {
+    const float sa = sphere_root(px, py, pz, ax, ay, az, rr, dx, dy, dz, dd);
+    if (t0 + sa > 0.0f) s = sa;
+  }
+  if (ends & 2) {
+    const float sb = sphere_root(px, py, pz, c1.x, c1.y, c1.z, rr, dx, dy, dz, dd);
+    if (t0 + sb > 0.0f && !(sb >= s)) {
+      s = sb;
+      y = 1.0f;
+    }
+  }
+  const float t = t0 + s;
+  res.t = t < kInfF ? __builtin_amdgcn_ldexpf(t, -e) : kInfF;
+  res.y = y;
+  return res;
+}
+
+// Test capsule q of the current instance on the lanes with `act` set (the
+// others evaluate the same instructions on record 0 -- a lane that has not
+// entered an instance yet holds no record -- and keep their state); updates as
+// quad_test.  No entry is t = +inf, which must not pass t <= t_best when
+// t_best = tmax = +inf.  The hit's u holds its axis position y (the curve
+// parameter is formed from it when the hit is stored), v = 0.
+__device__ __forceinline__ bool cap_test(Lane& L, const SceneView& sc, bool act, uint32_t q) {
+  const CapResult c = cap_hit(L, sc, act ? L.rec : 0u, q);
+  const float t_lim = L.any ? L.tmax : L.t_best;
+  const bool ok = act && c.t < kInfF && c.t > L.tmin && c.t <= t_lim && !(L.rec == L.ex_rec && L.ex_qh == q);
+  if (L.any) {
+    L.t_best = ok ? c.t : L.t_best;
+    L.b_rec = ok ? L.rec : L.b_rec;
+    L.b_qh = ok ? q : L.b_qh;
+    return ok;
+  }
+  const bool u = ok && better(L, sc, c.t, q, 0u);
+  L.t_best = u ? c.t : L.t_best;
+  L.b_rec = u ? L.rec : L.b_rec;
+  L.b_qh = u ? q : L.b_qh;
+  L.b_u = u ? c.y : L.b_u;
+  L.b_v = u ? 0.0f : L.b_v;
+  L.t_cull = L.t_best * kSlack;
+  return false;
+}
+
+// Primitive test of the current instance: a quad, or a capsule when the
+// instance's prototype holds curves.  The two tests run only when a lane of the
+// wave needs them (wave-uniform branches).
+__device__ __forceinline__ bool prim_test(Lane& L, const SceneView& sc, bool act, uint32_t q,
+                                          uint32_t* n64 = nullptr) {
+  bool answered = false;
+  if (__any(act && !L.curve)) answered = quad_test(L, sc, act && !L.curve, q, n64);
+  if (__any(act && L.curve)) answered = cap_test(L, sc, act && L.curve, q) || answered;
+  return answered;
+}
+
+// Test primitives [first, first + count) of the current instance on every lane.
 // Returns true if an any-hit query found a hit.
 __device__ __forceinline__ bool leaf_quads(Lane& L, const SceneView& sc, uint32_t first, uint32_t count) {
   for (uint32_t q = first; q < first + count; ++q)
-    if (quad_test(L, sc, true, q)) return true;
+    if (prim_test(L, sc, true, q)) return true;
   return false;
 }
 
@@ -660,6 +818,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   L.sp = 0;
   L.inst_sp = -1;
   L.rec = kEmpty;
+  L.curve = false;
   L.cur = sc.tlas_root;
   L.any = false;
   L.done = false;
@@ -692,14 +851,14 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
 template <int FMT, bool COUNT>
 __device__ __forceinline__ void node_step(bool act, Lane& L, const SceneView& sc, const Stack& S, uint2* spill,
                                           VisitCounters& vc) {
-  constexpr int W = NodeCodec<FMT>::kW;
+  constexpr int W = NodeCodec<FMT & kCodecMask>::kW;
   float tn[W];
   uint32_t ch[W];
   if (COUNT) {
     vc.tlas += (act && L.inst_sp < 0) ? 1u : 0u;
     vc.blas += (act && L.inst_sp >= 0) ? 1u : 0u;
   }
-  NodeCodec<FMT>::test(L, sc.nodes, act ? L.cur : sc.tlas_root, L.t_cull, tn, ch);
+  NodeCodec<FMT & kCodecMask>::test(L, sc.nodes, act ? L.cur : sc.tlas_root, L.t_cull, tn, ch);
   sort_children<W>(tn, ch);
   // sorted: the hit children are a prefix; child k (k >= 1) goes to slot p[k],
   // the farthest to the bottom
@@ -761,6 +920,7 @@ __device__ __forceinline__ void inst_step(bool act, Lane& L, const SceneView& sc
   L.Sy = act ? N.Sy : L.Sy;
   L.Sz = act ? N.Sz : L.Sz;
   L.kz = act ? N.kz : L.kz;
+  L.curve = act ? N.curve : L.curve;
   L.rec = act ? N.rec : L.rec;
   L.inst_sp = act ? L.sp : L.inst_sp;
   L.cur = act ? root : L.cur;
@@ -768,11 +928,15 @@ __device__ __forceinline__ void inst_step(bool act, Lane& L, const SceneView& sc
 
 // Quad step on the lanes with `act` set: test the first quad of the current
 // bottom-level leaf and keep the rest of the leaf as the current reference.
-template <bool COUNT>
+template <int FMT, bool COUNT>
 __device__ __forceinline__ void quad_step(bool act, Lane& L, const SceneView& sc, VisitCounters& vc) {
   if (COUNT) vc.quads += act ? 1u : 0u;
   const uint32_t first = leaf_first(L.cur), count = leaf_count(L.cur);
-  const bool answered = quad_test(L, sc, act, act ? first : 0u, COUNT ? &vc.fp64 : nullptr);
+  const uint32_t q = act ? first : 0u;
+  uint32_t* n64 = COUNT ? &vc.fp64 : nullptr;
+  bool answered;
+  if constexpr ((FMT & kCodecCurves) != 0) answered = prim_test(L, sc, act, q, n64);
+  else answered = quad_test(L, sc, act, q, n64);
   const uint32_t rest = count > 1u ? make_leaf(first + 1u, count - 1u) : kEmpty;
   L.cur = act ? (answered ? kEmpty : rest) : L.cur;
   L.done = L.done || answered;
@@ -832,7 +996,7 @@ __device__ __forceinline__ void run_step(int chosen, int kind, Lane& L, const Sc
                                          uint2* spill, VisitCounters& vc) {
   if (chosen == 2) inst_step<COUNT>(kind == 2, L, sc, vc);
   if (chosen == 1) node_step<FMT, COUNT>(kind == 1, L, sc, S, spill, vc);
-  if (chosen == 3) quad_step<COUNT>(kind == 3, L, sc, vc);
+  if (chosen == 3) quad_step<FMT, COUNT>(kind == 3, L, sc, vc);
 }
 
 // Wave-uniform choice among the step kinds the participating lanes need: the

@@ -54,7 +54,8 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
       (instance, primitive); t within 1e-5 relative unless t is ill-conditioned;
       u, v within uv_factor * 2^-24 * S / (shortest world edge * |cos|), the FP32
       position error carried into the quad's parameterisation, with S the
-      oracle's position scale of the answer;
+      oracle's position scale of the answer (a capsule hit: u, the curve
+      parameter, within that error over 8 axis lengths, and v = 0);
     * flagged rays: the GPU's answer (hit or miss) is one an FP32 traversal may
       give (the oracle's acceptance check over every triangle near the ray),
       with its t within tolerance unless ill-conditioned -- every flagged ray is
@@ -79,6 +80,30 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
     assert (rel <= 1e-5).all(), f"t relative error {rel.max()} > 1e-5"
     miss = ok & (o.inst < 0)
     assert np.isinf(g["t"][miss]).all() and (g["u"][miss] == 0).all() and (g["v"][miss] == 0).all()
+    osc = ora_scene if ora_scene is not None else oracle.OracleScene(scene)
+    # hits on the capsules of curves (Section 5.2) carry u = curve parameter, v = 0
+    caph = np.zeros_like(hit)
+    if getattr(scene, "curves", None) is not None:
+        curve_proto = np.diff(scene.proto_curve_off) > 0
+        caph = hit & curve_proto[scene.inst_proto[np.maximum(o.inst, 0)]]
+        hit = hit & ~caph
+    if caph.any():
+        caps = osc.capsules()
+        pi = scene.inst_proto[o.inst[caph]]
+        c = caps[8 * scene.proto_curve_off[pi] + o.prim[caph]]
+        X = scene.inst_xform[o.inst[caph]].astype(np.float64).reshape(-1, 3, 4)
+        a = np.einsum("nij,nj->ni", X[:, :, :3], c[:, 0:3]) + X[:, :, 3]
+        b = np.einsum("nij,nj->ni", X[:, :, :3], c[:, 3:6]) + X[:, :, 3]
+        r = rays[caph].astype(np.float64)
+        P = r[:, 0:3] + o.t[caph][:, None] * r[:, 3:6]
+        ba = b - a
+        Lc = np.linalg.norm(ba, axis=1)
+        s_ = np.clip(((P - a) * ba).sum(1) / np.maximum(Lc * Lc, 1e-300), 0, 1)
+        nrm = P - (a + s_[:, None] * ba)
+        cos = np.abs((nrm * r[:, 3:6]).sum(1)) / (np.linalg.norm(nrm, axis=1) * np.linalg.norm(r[:, 3:6], axis=1))
+        tol = uv_factor * 2.0 ** -24 * o.scale[caph] / (8 * np.maximum(Lc, 1e-30) * np.maximum(cos, 1e-3)) + 2.0 ** -21
+        du = np.abs(g["u"][caph] - o.u[caph])
+        assert (du <= tol).all() and (g["v"][caph] == 0).all(), f"capsule u error {du.max()}"
     if hit.any():
         W = world_quads(scene, o.inst[hit], o.prim[hit])
         r = rays[hit].astype(np.float64)
@@ -95,7 +120,6 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
     # every ray (flagged ones included): the GPU's answer must be acceptable for
     # the FP32 ray; its t error is measured in units of 2^-24 S / (|d| |cos|)
     fl = np.nonzero(flagged)[0]
-    osc = ora_scene if ora_scene is not None else oracle.OracleScene(scene)
     code, info, ulps = osc.accept(rays, gi, gp, g["t"], excl=excl, want_ulps=True)
     bad = code != 0
     if bad.any():
