@@ -27,6 +27,9 @@ printed.  Beside it (same JSON line):
                        area lights, a 2048x1024 environment map, eight
                        principled materials in three channels;
   config4_adjoint      forward frame and path-replay backward pass at config 4;
+  curves               a grass field of 100k tufts of cubic Bezier curves (51M
+                       instanced capsules) over a quad ground: frames of both
+                       paths (bit-identical) and its bounce rays' closest hits;
   config2              the smaller 1M-instance configuration: frames and
                        incoherent rays, both paths, and node widths 2, 4 and 8
                        (quantized persistent, equal hits and images);
@@ -207,6 +210,95 @@ def compare_widths(rtq, scene, cams, st, cap, log, steps=5, frames=5):
             "fastest_frame": min(out, key=lambda k: out[k]["ms_per_frame"])}
 
 
+def curve_field(rtq, sg, args, log):
+    """Curves (Section 5.2: the scene's curves): a grass field of tuft
+    instances -- cubic Beziers traced as chains of capsules -- over a ground
+    grid, one 1280x720 view at 4 spp, depth 4.  FP32-plain and
+    quantized-persistent frames must be bit-identical; then timed frames, and
+    the closest-hit rate of the frame's bounce rays (with the primitive each
+    leaves excluded)."""
+    import numpy as np
+    import torch
+    t0 = time.time()
+    scene = sg.curve_scene(11, n_inst=args.curve_instances, n_curves=64, spread=40.0)
+    S = rtq.Scene(scene)
+    build_s = time.time() - t0
+    info = S.info()
+    cams = [sg.Camera((0.0, -46.0, 4.0), (0.0, 0.0, 0.3), (0.0, 0.0, 1.0), 50.0, 1280, 720)]
+    st = sg.RenderSettings(spp=4, depth=4, seed=7)
+    n_pix = 1280 * 720
+    img = torch.empty(n_pix, device="cuda")
+    Q8P = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
+    F32 = dict(node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PLAIN)
+    log(f"curves: {scene.n_instances} instances, {info['n_unique_curves']} unique curves "
+        f"({info['n_unique_capsules']} capsules), {build_s:.1f} s to generate and build")
+
+    def timed(kw, steps, warmup):
+        for i in range(warmup):
+            st.frame = 100 + i
+            rtq.render(S, cams, st, images=img, **kw)
+        cnt = torch.zeros(4, dtype=torch.uint64, device="cuda")
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(steps):
+            st.frame = i
+            rtq.render(S, cams, st, images=img, counters=cnt, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        c = cnt.cpu().numpy().astype(np.float64)
+        return dict(ms_per_frame=round(1e3 * wall / steps, 3), mrays_s=round((c[0] + c[1]) / wall / 1e6, 2),
+                    rays_per_frame=(c[0] + c[1]) / steps)
+
+    if args.profile == "curves":
+        log(f"profile run (curve frames): {timed(Q8P, args.steps, args.warmup)}")
+        return None
+    st.frame = 0
+    rtq.render(S, cams, st, images=img, **F32)
+    ref = img.clone()
+    rtq.render(S, cams, st, images=img, **Q8P)
+    torch.cuda.synchronize()
+    equal = bool(torch.equal(ref.view(torch.int32), img.view(torch.int32)))
+    assert equal, "curve frames differ between the quantized-persistent and FP32-plain paths"
+    q8 = timed(Q8P, max(3, args.steps // 2), 2)
+    f32 = timed(F32, 3, 1)
+    # bounce rays of frame 0, traced alone
+    cap = 8_000_000
+    dump = torch.empty(12 * cap, device="cuda")
+    dcount = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    st.frame = 0
+    rtq.render(S, cams, st, images=img, dump_rays=dump, dump_count=dcount, **F32)
+    torch.cuda.synchronize()
+    nd = int(min(int(dcount.cpu().item()), cap))
+    planes = dump.view(12, cap)[:, :nd]
+    rays = planes[:8].contiguous()
+    excl = planes[8:10].view(torch.int32).t().contiguous()
+    h = rtq.trace_closest(S, rays, exclude=excl, soa_in=True, **Q8P)
+    torch.cuda.synchronize()
+    on_cap = (np.diff(scene.proto_curve_off) > 0)[scene.inst_proto[np.maximum(h.inst.cpu().numpy(), 0)]]
+    hit = h.inst.cpu().numpy() >= 0
+    for _ in range(2):
+        rtq.trace_closest(S, rays, exclude=excl, soa_in=True, **Q8P)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    w0 = time.perf_counter()
+    for _ in range(steps):
+        rtq.trace_closest(S, rays, exclude=excl, soa_in=True, **Q8P)
+    torch.cuda.synchronize()
+    inc = nd * steps / (time.perf_counter() - w0) / 1e6
+    out = {"workload": f"grass field: {scene.n_instances - 1} tufts of 64 curves (2 prototypes, rotated and "
+                       f"scaled) over a 6x6 quad ground, {info['n_unique_capsules']} unique capsules, "
+                       f"{8 * 64 * (scene.n_instances - 1):.3e} instanced capsules; 1280x720, 4 spp, depth 4",
+           "equal_images": equal, "q8_persistent": q8, "fp32_plain": f32,
+           "speedup": round(f32["ms_per_frame"] / q8["ms_per_frame"], 3),
+           "incoherent": {"rays": nd, "q8_persistent_mrays_s": round(inc, 2),
+                          "hit_fraction": round(float(hit.mean()), 4),
+                          "capsule_hit_fraction": round(float((hit & on_cap).mean()), 4)},
+           "build_s": round(info["build_seconds"], 2), "device_gib": round(info["device_bytes"] / 2**30, 3)}
+    log(f"curves: {out}")
+    S.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +309,9 @@ def main():
     ap.add_argument("--no-config2", action="store_true")
     ap.add_argument("--incoherent-rays", type=int, default=16_000_000)
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
-    ap.add_argument("--profile", choices=("incoherent", "frame"), default=None,
+    ap.add_argument("--curve-instances", type=int, default=100_000, help="tufts of the curve field")
+    ap.add_argument("--no-curves", action="store_true")
+    ap.add_argument("--profile", choices=("incoherent", "frame", "curves"), default=None,
                     help="only the timed incoherent queries, or only timed frames (for rocprofv3)")
     ap.add_argument("--widths", action="store_true",
                     help="only compare node widths 2, 4 and 8 on the configuration-3 workload (one build each)")
@@ -245,6 +339,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         log("copied 5 x 1 GiB")
+        return
+    if args.profile == "curves":
+        curve_field(rtq, sg, args, log)
         return
     t0 = time.time()
     scene, cams, st = sg.config3(scale=args.scale)
@@ -516,6 +613,7 @@ def main():
     adj["workload"] = "config4: config-1 scene (1000 instances, 16384 unique quads), 512x512, 4 spp, depth 4"
     log(f"config 4 adjoint: {adj}")
     del S4
+    curves = None if args.no_curves else curve_field(rtq, sg, args, log)
 
     # ---- CPU baseline: the FP64 oracle tracing a bounded random sample of the
     # same incoherent rays (same exclusions), sized by a pilot to about
@@ -600,6 +698,7 @@ def main():
         "principled": principled,
         "config2": cfg2,
         "config4_adjoint": adj,
+        "curves": curves,
         "roofline": roof,
         "roofline_frame": roof_frame,
         "cpu_baseline": cpu,
