@@ -62,7 +62,7 @@ def lib():
         i64 = ctypes.c_int64
         i32 = ctypes.c_int32
         L.orc_scene_create.restype = P
-        L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64, P, P]
+        L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64, P, P, P]
         L.orc_scene_destroy.argtypes = [P]
         L.orc_scene_set_albedo.argtypes = [P, P]
         L.orc_scene_set_textures.argtypes = [P, P, i32]
@@ -165,6 +165,9 @@ class OracleScene:
         if curves is not None:
             self._keep["curves"] = np.ascontiguousarray(curves, dtype=np.float32)
             self._keep["co"] = np.ascontiguousarray(scene.proto_curve_off, dtype=np.int64)
+            flat = getattr(scene, "proto_curve_flat", None)
+            if flat is not None:
+                self._keep["flat"] = np.ascontiguousarray(flat, dtype=np.int32)
         k = self._keep
         # shading faces: every quad and every curve (in prototype order)
         self.n_quads = int(k["albedo"].shape[0])
@@ -173,7 +176,7 @@ class OracleScene:
         self.h = lib().orc_scene_create(_p(k["verts"]), k["verts"].shape[0], _p(k["quads"]), k["quads"].shape[0],
                                         _p(k["vo"]), _p(k["qo"]), k["qo"].shape[0] - 1, _p(k["albedo"]),
                                         _p(k["ip"]), _p(k["x"]), k["ip"].shape[0], _p(k.get("curves")),
-                                        _p(k.get("co")))
+                                        _p(k.get("co")), _p(k.get("flat")))
         if not self.h:
             raise ValueError("oracle: singular instance transform")
 
@@ -213,9 +216,10 @@ class OracleScene:
         self.rgb = True
 
     def capsules(self) -> np.ndarray:
-        """The capsules the curves are tessellated into: [n, 7] (a, b, radius)."""
+        """The segments the curves are tessellated into: [n, 8] (a, b, radius at
+        a, radius at b; equal for the capsules of round curves)."""
         n = int(lib().orc_scene_capsules(self.h, None))
-        out = np.zeros((n, 7))
+        out = np.zeros((n, 8))
         lib().orc_scene_capsules(self.h, _p(out))
         return out
 

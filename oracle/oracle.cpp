@@ -155,11 +155,12 @@ struct Bvh {
   }
 };
 
-// One capsule of a tessellated curve (object space): the points within r of
-// the segment [a, b].
+// One segment of a tessellated curve (object space).  Round curves: a capsule,
+// the points within r of the segment [a, b] (rb = r).  Flat ribbons: the
+// segment with radius r at a and rb at b, varying linearly.
 struct Cap {
   V3 a, b;
-  double r;
+  double r, rb;
 };
 
 struct Scene {
@@ -167,9 +168,10 @@ struct Scene {
   std::vector<V3> verts;           // object space, exact copies of the FP32 input
   std::vector<int32_t> quads;      // 4 per quad, local vertex index
   std::vector<int64_t> vo, qo;     // per-prototype offsets
-  // curve prototypes (Section 5.2 "Curves"): pkind 1, their curves tessellated
-  // into capsules (kCapsPerCurve per curve, prototype order) at co[p] .. co[p + 1]
-  std::vector<int32_t> pkind;      // 0 quads, 1 curves
+  // curve prototypes (Section 5.2 "Curves"): pkind 1 round, 2 flat ribbons,
+  // their curves tessellated into segments (kCapsPerCurve per curve, prototype
+  // order) at co[p] .. co[p + 1]
+  std::vector<int32_t> pkind;      // 0 quads, 1 round curves, 2 flat ribbons
   std::vector<int64_t> co;         // per-prototype capsule offsets
   std::vector<Cap> caps;
   std::vector<int64_t> fo;         // per-prototype face offsets: a face is a quad or a curve
@@ -367,8 +369,9 @@ double bez(double c0, double c1, double c2, double c3, double s) {
   return lerp(d, e, s);
 }
 
-// Capsules of one curve: cp holds 4 control points (x, y, z, r), FP32 values.
-void tessellate_curve(const float* cp, Cap out[kCapsPerCurve]) {
+// Segments of one curve: cp holds 4 control points (x, y, z, r), FP32 values.
+// Round: capsules of the mean radius; flat: the radii at both ends.
+void tessellate_curve(const float* cp, Cap out[kCapsPerCurve], bool flat) {
   V3 X[kCapsPerCurve + 1];
   double R[kCapsPerCurve + 1];
   for (int j = 0; j <= kCapsPerCurve; ++j) {
@@ -378,7 +381,43 @@ void tessellate_curve(const float* cp, Cap out[kCapsPerCurve]) {
     X[j] = V3{v[0], v[1], v[2]};
     R[j] = v[3];
   }
-  for (int j = 0; j < kCapsPerCurve; ++j) out[j] = Cap{X[j], X[j + 1], (double)(float)(0.5 * (R[j] + R[j + 1]))};
+  for (int j = 0; j < kCapsPerCurve; ++j) {
+    const double rm = (double)(float)(0.5 * (R[j] + R[j + 1]));
+    out[j] = flat ? Cap{X[j], X[j + 1], R[j], R[j + 1]} : Cap{X[j], X[j + 1], rm, rm};
+  }
+}
+
+// Flat ribbons (Section 5.2 names flat ribbon curves for grass and palm
+// fronds).  Reading: a ray-facing ribbon.  Segment c, seen along the ray
+// (o, d), is the strip of points within r(u) = r + u (rb - r) of the segment's
+// projection onto the plane orthogonal to the ray; the ray meets it when its
+// line passes within r(u) of the projected segment's point u closest to it,
+// at the depth of that segment point along the ray.  Returns t (+inf when the
+// line passes farther), *u_out the segment parameter and *margin the
+// distance minus r(u).
+// ribbon_eval returns the depth whether or not the line passes within r(u).
+double ribbon_eval(V3 o, V3 d, const Cap& c, double* u_out, double* margin) {
+  const double dd = dot(d, d);
+  const V3 A = c.a - o, B = c.b - o;
+  const V3 Ap = A - (dot(A, d) / dd) * d, Bp = B - (dot(B, d) / dd) * d;
+  const V3 E = Bp - Ap;
+  const double ee = dot(E, E);
+  const double u = ee > 0.0 ? std::min(1.0, std::max(0.0, -dot(Ap, E) / ee)) : 0.0;
+  *margin = norm(Ap + u * E) - (c.r + u * (c.rb - c.r));
+  *u_out = u;
+  return dot(A + u * (B - A), d) / dd;
+}
+double ribbon_hit(V3 o, V3 d, const Cap& c, double* u_out) {
+  double m;
+  const double t = ribbon_eval(o, d, c, u_out, &m);
+  return m > 0.0 ? kInf : t;
+}
+// The ribbon's normal there (not normalised): the reverse ray direction
+// without its component along the segment, so the ribbon faces the ray.
+inline V3 ribbon_normal(const Cap& c, V3 d) {
+  const V3 T = c.b - c.a;
+  const double tt = dot(T, T);
+  return tt > 0.0 ? -1.0 * (d - (dot(d, T) / tt) * T) : -1.0 * d;
 }
 
 // Distance from point p to the segment [a, b].
@@ -565,6 +604,15 @@ double cap_normal_uncertainty(const Scene& S, int64_t inst, const Cap& c, const 
   return std::min(1.0, (e + t_shift * S.ainv_frob[inst]) / c.r);
 }
 
+// A ray leaving a curve segment does not hit that segment; a ray leaving a flat
+// ribbon does not hit any segment of that curve in that instance.  Reading: a
+// ray-facing ribbon turns toward every ray, so the neighbouring segments of the
+// curve a ray starts on would face it and be met next to its origin.
+inline bool curve_excluded(const Scene& S, int32_t pr, int32_t inst, int32_t prim, const Excl& ex) {
+  if (inst != ex.inst || ex.half != 0) return false;
+  return S.pkind[pr] == 2 ? prim / kCapsPerCurve == ex.prim / kCapsPerCurve : prim == ex.prim;
+}
+
 struct TraceOut {
   Key best;
   uint32_t flags = 0;
@@ -585,13 +633,13 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   visit(S, r, mode, 0.0, t_hi, [&](int64_t inst, int64_t qg) {
     const int32_t pr0 = S.iproto[inst];
     if (S.pkind[pr0]) {
-      // capsule qg: entry in object space, key (t, inst, prim, half 0)
+      // capsule or ribbon segment qg: in object space, key (t, inst, prim, half 0)
       const int32_t prim = (int32_t)(qg - S.co[pr0]);
-      if ((int32_t)inst == ex.inst && prim == ex.prim && ex.half == 0) return;
+      if (curve_excluded(S, pr0, (int32_t)inst, prim, ex)) return;
       const Ray ro = obj_ray(S, inst, r);
       V3 n;
       double y = 0.0;
-      const double t = cap_entry(ro.o, ro.d, S.caps[qg], &n, &y);
+      const double t = S.pkind[pr0] == 2 ? ribbon_hit(ro.o, ro.d, S.caps[qg], &y) : cap_entry(ro.o, ro.d, S.caps[qg], &n, &y);
       if (t < kInf && t > r.tmin && t <= t_hi) {
         const Key k{t, (int32_t)inst, prim, 0, ((prim % kCapsPerCurve) + y) / kCapsPerCurve, 0.0};
         if (key_less(k, best)) best = k;
@@ -635,7 +683,7 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
       const Cap& c = S.caps[S.co[bp] + best.prim];
       S_best = std::max(Sv, cap_extent(S, best.inst, c, r.o));
       const Ray ro = obj_ray(S, best.inst, r);
-      n = normal_to_world(S, best.inst, cap_normal(c, ro.o + best.t * ro.d));
+      n = normal_to_world(S, best.inst, S.pkind[bp] == 2 ? ribbon_normal(c, ro.d) : cap_normal(c, ro.o + best.t * ro.d));
     } else {
       V3 w[4];
       quad_world(S, best.inst, S.qo[bp] + best.prim, w);
@@ -655,12 +703,41 @@ TraceOut trace_one(const Scene& S, const Ray& r, const Excl& ex, double r0, int 
   double t_lim = t_end;
   visit(S, r, mode, g_cull, t_lim, [&](int64_t inst, int64_t qg) {
     const int32_t pr0 = S.iproto[inst];
+    if (S.pkind[pr0] == 2) {
+      // ribbon: near tie; graze when the line passes within the graze distance
+      // of the strip's edge at a depth up to t_end; near origin when that
+      // depth lies within it of tmin (object space, as for capsules)
+      const int32_t prim = (int32_t)(qg - S.co[pr0]);
+      if (curve_excluded(S, pr0, (int32_t)inst, prim, ex)) return;
+      const Cap& c = S.caps[qg];
+      const double Sq = std::max(Sv, cap_extent(S, inst, c, r.o));
+      const double g = (1e-6 * Sq + r0) * S.ainv_frob[inst];
+      const Ray ro = obj_ray(S, inst, r);
+      double u, m;
+      const double t = ribbon_eval(ro.o, ro.d, c, &u, &m);
+      const double dlen = norm(ro.d);
+      if (m < g && std::fabs(t - r.tmin) * dlen < g) out.flags |= F_NEAR_ORIGIN;
+      const bool same = hit && inst == best.inst && prim == best.prim;
+      if (m <= 0.0 && t > r.tmin && t <= t_end && !same) {
+        out.flags |= F_NEAR_TIE;
+        bool dup = false;
+        for (int cc = 0; cc < out.ncand; ++cc)
+          if (out.cand[2 * cc] == (int32_t)inst && out.cand[2 * cc + 1] == prim) dup = true;
+        if (!dup && out.ncand < 4) {
+          out.cand[2 * out.ncand] = (int32_t)inst;
+          out.cand[2 * out.ncand + 1] = prim;
+          out.ncand++;
+        }
+      }
+      if (std::fabs(m) < g && t > r.tmin - g / dlen && t <= t_end) out.flags |= F_GRAZE;
+      return;
+    }
     if (S.pkind[pr0]) {
       // capsule: near origin, near tie and graze (the ray passing within the
       // graze distance of the capsule's surface), in object space with the
       // world distance scaled by |A^-1|
       const int32_t prim = (int32_t)(qg - S.co[pr0]);
-      if ((int32_t)inst == ex.inst && prim == ex.prim && ex.half == 0) return;
+      if (curve_excluded(S, pr0, (int32_t)inst, prim, ex)) return;
       const Cap& c = S.caps[qg];
       const double Sq = std::max(Sv, cap_extent(S, inst, c, r.o));
       const double g = (1e-6 * Sq + r0) * S.ainv_frob[inst];
@@ -841,6 +918,36 @@ TriClass classify_tri(const Ray& r, double dn, double Sv, V3 w0, V3 w1, V3 w2, c
 // lie within that distance of the surface, or the hit may lie next to tmax.
 // Distances are taken in object space, the world graze distance scaled by
 // |A^-1|.
+// Ribbon segment c of instance inst against ray r: rounding can move the line
+// across the strip's edge (graze), or the depth across tmin (near origin) or
+// tmax.  t is ill-conditioned where the ray runs nearly along the segment
+// (the closest point then moves fast along it): the sine of that angle plays
+// the part of a triangle's |cos|.
+TriClass classify_ribbon(const Scene& S, int64_t inst, const Cap& c, const Ray& r, double dn, double Sv, double r0) {
+  TriClass k;
+  const double Sq = std::max(Sv, cap_extent(S, inst, c, r.o));
+  k.S = Sq;
+  const double thr = (1e-6 * Sq + r0) * S.ainv_frob[inst];
+  const Ray ro = obj_ray(S, inst, r);
+  double u, m;
+  const double t = ribbon_eval(ro.o, ro.d, c, &u, &m);
+  const double dlen = norm(ro.d);
+  const bool hit = m <= 0.0;
+  const bool graze = std::fabs(m) < thr;
+  const bool near_org = m < thr && std::fabs(t - r.tmin) * dlen < thr;
+  const V3 T = c.b - c.a;
+  const double tl = norm(T);
+  const double cosv = tl > 0.0 ? norm(cross(T, ro.d)) / (tl * dlen) : 1.0;
+  k.t = t;
+  const bool in_iv = t > r.tmin && t <= r.tmax;
+  const bool near_tmax = std::isfinite(r.tmax) && std::fabs(t - r.tmax) <= 1e-5 * r.tmax + 1e-6 * Sq / dn;
+  k.illcond = !(cosv > 0.0) || 16.0 * std::ldexp(1.0, -24) * Sq > 1e-5 * std::fabs(t) * dn * cosv;
+  k.tulp = cosv > 0.0 ? std::ldexp(1.0, -24) * Sq / (dn * cosv) : kInf;
+  k.certain = hit && in_iv && !graze && !near_org && !near_tmax;
+  k.possible = (hit || graze) && (in_iv || near_org || near_tmax);
+  return k;
+}
+
 TriClass classify_cap(const Scene& S, int64_t inst, const Cap& c, const Ray& r, double dn, double Sv, double r0) {
   TriClass k;
   const double Sq = std::max(Sv, cap_extent(S, inst, c, r.o));
@@ -889,8 +996,10 @@ AcceptSet accept_set(const Scene& S, const Ray& r, const Excl& ex, double r0, in
     const int32_t pr0 = S.iproto[inst];
     if (S.pkind[pr0]) {
       const int32_t prim = (int32_t)(qg - S.co[pr0]);
-      if ((int32_t)inst == ex.inst && prim == ex.prim && ex.half == 0) return;
-      fn((int32_t)inst, prim, 0, classify_cap(S, inst, S.caps[qg], r, dn, Sv, r0));
+      if (curve_excluded(S, pr0, (int32_t)inst, prim, ex)) return;
+      fn((int32_t)inst, prim, 0,
+         S.pkind[pr0] == 2 ? classify_ribbon(S, inst, S.caps[qg], r, dn, Sv, r0)
+                           : classify_cap(S, inst, S.caps[qg], r, dn, Sv, r0));
       return;
     }
     V3 w[4];
@@ -1336,7 +1445,8 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (is_cap) {
       // the capsule's outward normal at the hit, mapped by A^-T
       const Ray ro = obj_ray(S, h.best.inst, ray);
-      n = normal_to_world(S, h.best.inst, cap_normal(S.caps[S.co[pr] + h.best.prim], ro.o + h.best.t * ro.d));
+      const Cap& hc = S.caps[S.co[pr] + h.best.prim];
+      n = normal_to_world(S, h.best.inst, S.pkind[pr] == 2 ? ribbon_normal(hc, ro.d) : cap_normal(hc, ro.o + h.best.t * ro.d));
     } else {
       quad_world(S, h.best.inst, S.qo[pr] + h.best.prim, wq);
       n = h.best.half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
@@ -1345,7 +1455,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     const double nd = dot(n, ray.d);
     uint32_t vshade = 0;  // shading decisions of this vertex within rounding of a threshold
     if (std::fabs(nd) < 1e-3) vshade |= F_SHADE;
-    if (is_cap && cap_normal_uncertainty(S, h.best.inst, S.caps[S.co[pr] + h.best.prim], ray, h.best.t,
+    if (is_cap && S.pkind[pr] == 1 && cap_normal_uncertainty(S, h.best.inst, S.caps[S.co[pr] + h.best.prim], ray, h.best.t,
                                          16.0 * std::ldexp(1.0, -24) * h.S / std::max(h.cos_abs, 1e-3)) > 1e-6)
       vshade |= F_SHADE;
     if (nd > 0) n = -1.0 * n;
@@ -1689,7 +1799,8 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     if (is_cap) {
       // the capsule's outward normal at the GPU's t along the recorded ray
       const Ray ro = obj_ray(S, inst, ray);
-      n = normal_to_world(S, inst, cap_normal(S.caps[S.co[pr] + prim], ro.o + (double)F[0] * ro.d));
+      const Cap& hc = S.caps[S.co[pr] + prim];
+      n = normal_to_world(S, inst, S.pkind[pr] == 2 ? ribbon_normal(hc, ro.d) : cap_normal(hc, ro.o + (double)F[0] * ro.d));
     } else {
       quad_world(S, inst, S.qo[pr] + prim, wq);
       n = half == 0 ? cross(wq[1] - wq[0], wq[3] - wq[0]) : cross(wq[3] - wq[2], wq[1] - wq[2]);
@@ -1719,8 +1830,9 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     n = side * n;
     // a capsule's normal follows the hit point: the GPU's is known to within
     // dn_unc of the exact normal at its t
-    const double dn_unc = is_cap ? cap_normal_uncertainty(S, inst, S.caps[S.co[pr] + prim], ray, (double)F[0], 0.0)
-                                 : 0.0;
+    const double dn_unc = is_cap && S.pkind[pr] == 1
+                              ? cap_normal_uncertainty(S, inst, S.caps[S.co[pr] + prim], ray, (double)F[0], 0.0)
+                              : 0.0;
     // shading value: the face's albedo, or a texel at the hit's (u, v)
     double a = S.albedo[face];
     if (S.tex_res > 0) {
@@ -2008,7 +2120,7 @@ void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philo
 void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads, int64_t n_quads,
                        const int64_t* proto_vert_off, const int64_t* proto_quad_off, int32_t n_protos,
                        const float* albedo, const int32_t* inst_proto, const float* inst_xform, int64_t n_inst,
-                       const float* curves, const int64_t* proto_curve_off) {
+                       const float* curves, const int64_t* proto_curve_off, const int32_t* proto_curve_flat) {
   Scene* S = new Scene;
   S->P = n_protos;
   S->verts.resize(n_verts);
@@ -2022,10 +2134,11 @@ void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads
   for (int32_t p = 0; p < n_protos; ++p) {
     const int64_t nc = proto_curve_off ? proto_curve_off[p + 1] - proto_curve_off[p] : 0;
     if (nc > 0) {
-      S->pkind[p] = 1;
+      const bool flat = proto_curve_flat && proto_curve_flat[p] != 0;
+      S->pkind[p] = flat ? 2 : 1;
       for (int64_t k = proto_curve_off[p]; k < proto_curve_off[p + 1]; ++k) {
         Cap cc[kCapsPerCurve];
-        tessellate_curve(curves + 16 * k, cc);
+        tessellate_curve(curves + 16 * k, cc, flat);
         for (int j = 0; j < kCapsPerCurve; ++j) S->caps.push_back(cc[j]);
       }
     }
@@ -2061,11 +2174,12 @@ void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads
       std::vector<Box> cb(S->co[p + 1] - S->co[p]);
       for (int64_t c = S->co[p]; c < S->co[p + 1]; ++c) {
         const Cap& k = S->caps[c];
+        const double rr = std::max(k.r, k.rb);
         Box b;
-        b.grow(k.a - V3{k.r, k.r, k.r});
-        b.grow(k.a + V3{k.r, k.r, k.r});
-        b.grow(k.b - V3{k.r, k.r, k.r});
-        b.grow(k.b + V3{k.r, k.r, k.r});
+        b.grow(k.a - V3{rr, rr, rr});
+        b.grow(k.a + V3{rr, rr, rr});
+        b.grow(k.b - V3{rr, rr, rr});
+        b.grow(k.b + V3{rr, rr, rr});
         cb[c - S->co[p]] = b;
         all.grow(b);
       }
@@ -2137,15 +2251,16 @@ void orc_bsdf_sample(const double* m, const double* nrm, const double* wo, int64
   }
 }
 
-// The capsules of every curve prototype, for tests: 7 doubles each (a, b,
-// radius), prototype order.  Returns their count.
+// The segments of every curve prototype, for tests: 8 doubles each (a, b,
+// radius at a, radius at b; equal for round capsules), prototype order.
+// Returns their count.
 int64_t orc_scene_capsules(void* s, double* out) {
   const Scene& S = *static_cast<Scene*>(s);
   if (out)
     for (size_t k = 0; k < S.caps.size(); ++k) {
       const Cap& c = S.caps[k];
-      const double v[7] = {c.a.x, c.a.y, c.a.z, c.b.x, c.b.y, c.b.z, c.r};
-      for (int j = 0; j < 7; ++j) out[7 * k + j] = v[j];
+      const double v[8] = {c.a.x, c.a.y, c.a.z, c.b.x, c.b.y, c.b.z, c.r, c.rb};
+      for (int j = 0; j < 8; ++j) out[8 * k + j] = v[j];
     }
   return (int64_t)S.caps.size();
 }

@@ -46,6 +46,8 @@ class Scene:
     # radius) per cubic Bezier curve, and per-prototype offsets
     curves: Optional[np.ndarray] = None           # float32 [C, 16]
     proto_curve_off: Optional[np.ndarray] = None  # int64 [P + 1]
+    # per prototype of curves: 0 round curves, 1 flat (ray-facing) ribbons
+    proto_curve_flat: Optional[np.ndarray] = None  # int32 [P]
 
     @property
     def n_protos(self) -> int:
@@ -89,6 +91,8 @@ class Scene:
             nq, nc = np.diff(self.proto_quad_off), np.diff(self.proto_curve_off)
             assert ((nq > 0) != (nc > 0)).all(), "a prototype holds quads or curves"
             assert (self.curves[:, 3::4] >= 0).all()
+            if self.proto_curve_flat is not None:
+                assert self.proto_curve_flat.shape == (P,) and ((self.proto_curve_flat == 0) | (nc > 0)).all()
         assert self.proto_vert_off[-1] == self.verts.shape[0]
         assert self.proto_quad_off[-1] == self.quads.shape[0]
         assert self.inst_proto.dtype == np.int32 and self.inst_xform.dtype == np.float32
@@ -469,10 +473,12 @@ def blade_curves(rng: np.random.Generator, n: int, height: float, radius: float,
     return c.astype(np.float32)
 
 
-def curve_scene(seed: int, n_inst: int = 6, n_curves: int = 24, spread: float = 2.5, with_ground: bool = True) -> Scene:
+def curve_scene(seed: int, n_inst: int = 6, n_curves: int = 24, spread: float = 2.5, with_ground: bool = True,
+                flat: Tuple[bool, bool] = (False, False)) -> Scene:
     """Tufts of curves (Section 5.2: the scene's curves) instanced over a small
     quad ground: prototype 0 the ground grid (when asked), the others curve
-    tufts, each tuft instance rotated about z and scaled uniformly."""
+    tufts, each tuft instance rotated about z and scaled uniformly; `flat`
+    makes the first or second tuft flat ribbons instead of round curves."""
     rng = np.random.default_rng(seed)
     protos_q = [grid_proto(rng, 6, 6, spread + 1.0, spread + 1.0, 0.05)] if with_ground else []
     tufts = [blade_curves(rng, n_curves, rng.uniform(0.6, 1.2), rng.uniform(0.02, 0.05), 0.4) for _ in range(2)]
@@ -499,7 +505,8 @@ def curve_scene(seed: int, n_inst: int = 6, n_curves: int = 24, spread: float = 
               quads=np.concatenate(quads).astype(np.int32) if quads else np.zeros((0, 4), np.int32),
               proto_vert_off=vo, proto_quad_off=qo, albedo=albedo,
               inst_proto=np.asarray(inst_proto, np.int32), inst_xform=np.asarray(xf, np.float32),
-              curves=np.concatenate(tufts).astype(np.float32), proto_curve_off=co)
+              curves=np.concatenate(tufts).astype(np.float32), proto_curve_off=co,
+              proto_curve_flat=np.array([0] * len(protos_q) + [int(f) for f in flat], np.int32))
     s.validate()
     return s
 

@@ -12,8 +12,9 @@ from paper_2001_02620_amd import scenegen as sg
 K = 8  # capsules per curve
 
 
-def _curve_scene(curves, xforms=None, albedo=0.5):
-    """Curve prototype(s) only: one prototype holding `curves` [n, 16]."""
+def _curve_scene(curves, xforms=None, albedo=0.5, flat=False):
+    """Curve prototype(s) only: one prototype holding `curves` [n, 16], round
+    capsule chains or (flat) ray-facing ribbons."""
     curves = np.asarray(curves, np.float32).reshape(-1, 16)
     if xforms is None:
         xforms = sg.identity_xform(1)
@@ -22,7 +23,8 @@ def _curve_scene(curves, xforms=None, albedo=0.5):
                  proto_vert_off=np.array([0, 0], np.int64), proto_quad_off=np.array([0, 0], np.int64),
                  albedo=np.full(curves.shape[0], albedo, np.float32),
                  inst_proto=np.zeros(xforms.shape[0], np.int32), inst_xform=xforms, curves=curves,
-                 proto_curve_off=np.array([0, curves.shape[0]], np.int64))
+                 proto_curve_off=np.array([0, curves.shape[0]], np.int64),
+                 proto_curve_flat=np.array([1 if flat else 0], np.int32))
     s.validate()
     return s
 
@@ -52,7 +54,7 @@ def test_tessellation_points_lie_on_the_bezier():
     circle; the curve's ends are the end control points exactly."""
     o = oracle.OracleScene(_curve_scene(_straight()))
     c = o.capsules()
-    assert c.shape == (K, 7)
+    assert c.shape == (K, 8)
     xs = np.concatenate([c[:, 0], c[-1:, 3]])
     np.testing.assert_allclose(xs, np.linspace(-2, 2, K + 1), atol=1e-6)
     assert (c[:, 6] == np.float32(0.25)).all()
@@ -99,11 +101,13 @@ def test_capsule_closed_forms():
     assert (inside.inst == -1).all()
 
 
-def test_curve_bvh_equals_brute_force_and_instances():
-    """Over a tuft scene with ground, the BVH traversal equals brute force bit
-    for bit (flags included); an instanced straight curve's hits equal the
-    prototype's hits under the FP64 inverse transform."""
-    scene = sg.curve_scene(3)
+@pytest.mark.parametrize("flat", [False, True])
+def test_curve_bvh_equals_brute_force_and_instances(flat):
+    """Over a tuft scene with ground (one tuft prototype of flat ribbons when
+    asked), the BVH traversal equals brute force bit for bit (flags
+    included); an instanced straight curve's hits equal the prototype's hits
+    under the FP64 inverse transform."""
+    scene = sg.curve_scene(3, flat=(False, flat))
     o = oracle.OracleScene(scene)
     rng = np.random.default_rng(5)
     rays = sg.random_rays(rng, 4000, [-3, -3, 0.05], [3, 3, 1.5], [-3, -3, 0.0], [3, 3, 1.2])
@@ -115,8 +119,8 @@ def test_curve_bvh_equals_brute_force_and_instances():
     # instance invariance: rotation about z by 30 degrees, scale 1.5, translation
     c, s_ = math.cos(math.pi / 6) * 1.5, math.sin(math.pi / 6) * 1.5
     X = np.array([[c, -s_, 0, 1.0, s_, c, 0, -2.0, 0, 0, 1.5, 0.5]], np.float32)
-    o1 = oracle.OracleScene(_curve_scene(_straight(), xforms=X))
-    o0 = oracle.OracleScene(_curve_scene(_straight()))
+    o1 = oracle.OracleScene(_curve_scene(_straight(), xforms=X, flat=flat))
+    o0 = oracle.OracleScene(_curve_scene(_straight(), flat=flat))
     A = X.reshape(3, 4).astype(np.float64)
     Ainv = np.linalg.inv(A[:, :3])
     rw = sg.random_rays(rng, 2000, [-4, -5, -2], [6, 2, 3], [-1, -4, 0], [3, 0, 1])
@@ -169,10 +173,11 @@ def test_curve_sky_closed_form():
     np.testing.assert_allclose(img, ((2 - k) * L + k * a * L) / 2, rtol=1e-12)
 
 
-def test_curve_gradient_forms_agree():
+@pytest.mark.parametrize("flat", [False, True])
+def test_curve_gradient_forms_agree(flat):
     """Curves are faces of their own (one albedo per curve): PRB = dual
     numbers = central differences on a tuft scene with ground."""
-    scene = sg.curve_scene(4, n_inst=4, n_curves=12)
+    scene = sg.curve_scene(4, n_inst=4, n_curves=12, flat=(flat, False))
     o = oracle.OracleScene(scene)
     cams = [sg.Camera((0.0, -6.0, 1.5), (0.0, 0.0, 0.4), (0.0, 0.0, 1.0), 45.0, 24, 24)]
     st = sg.RenderSettings(spp=2, depth=3, seed=5)
@@ -275,6 +280,8 @@ def _curve_model_path(o, scene, caps, cam, st, pix, sample, turn=0.0, rng=None):
     L = np.array(st.light_dir)
     fo = scene.proto_face_off()
     curve_proto = np.diff(scene.proto_curve_off) > 0
+    flat_proto = (scene.proto_curve_flat if scene.proto_curve_flat is not None
+                  else np.zeros(scene.n_protos, np.int32)) != 0
     vi, vf = [], []
     excl = None
     beta, rad = 1.0, 0.0
@@ -292,7 +299,17 @@ def _curve_model_path(o, scene, caps, cam, st, pix, sample, turn=0.0, rng=None):
         p_ = scene.inst_proto[inst]
         X = scene.inst_xform[inst].astype(np.float64).reshape(3, 4)
         t32 = f32(hh.t[0])
-        if curve_proto[p_]:
+        if curve_proto[p_] and flat_proto[p_]:
+            # a ribbon faces the ray: the reverse object-space direction without
+            # its part along the segment
+            c = caps[8 * scene.proto_curve_off[p_] + prim]
+            Ai = np.linalg.inv(X[:, :3]).astype(np.float32).astype(np.float64)
+            do = Ai @ ray_d.astype(np.float64)
+            T = c[3:6] - c[0:3]
+            no = -(do - (do @ T) / (T @ T) * T)
+            n = Ai.T @ no.astype(np.float32).astype(np.float64)
+            face = int(fo[p_] + prim // 8)
+        elif curve_proto[p_]:
             c = caps[8 * scene.proto_curve_off[p_] + prim]
             Ai = np.linalg.inv(X[:, :3]).astype(np.float32).astype(np.float64)
             h = (ray_o.astype(np.float64) - X[:, 3].astype(np.float32)) + float(t32) * ray_d.astype(np.float64)
@@ -346,12 +363,13 @@ def _curve_model_path(o, scene, caps, cam, st, pix, sample, turn=0.0, rng=None):
     return len(vi), np.array(vi), np.array(vf, np.float32), False, f32(rad)
 
 
-def test_path_check_on_curves():
-    """The replay check accepts paths over curves whose capsule normals carry
-    an FP32 renderer's rounding (through the FP32 inverse transform), and
-    rejects paths whose capsule normals are turned by 0.05 rad, and a wrong
-    radiance."""
-    scene = sg.curve_scene(4, n_inst=8, n_curves=24)
+@pytest.mark.parametrize("flat", [False, True])
+def test_path_check_on_curves(flat):
+    """The replay check accepts paths over curves whose normals carry an FP32
+    renderer's rounding (through the FP32 inverse transform), and rejects
+    paths whose curve normals are turned by 0.05 rad, and a wrong radiance;
+    with flat ribbons (one tuft prototype) as well."""
+    scene = sg.curve_scene(4, n_inst=8, n_curves=24, flat=(flat, flat))
     o = oracle.OracleScene(scene)
     caps = o.capsules()
     cams = [sg.Camera((0.0, -5.5, 1.4), (0.0, 0.0, 0.4), (0.0, 0.0, 1.0), 45.0, 48, 40)]
@@ -376,3 +394,89 @@ def test_path_check_on_curves():
         n_rad += o.check_path(cams, st, 0, int(pix), 0, nv, vi, vf, esc, np.float32(rad * 1.01 + 1e-3))[0] == 12
     assert n_ok == 400 and n_cap > 30, n_cap
     assert n_turn == n_cap and n_rad == n_cap, (n_turn, n_rad, n_cap)
+
+
+def test_ribbon_closed_forms():
+    """A flat ribbon faces the ray: a ray toward a straight ribbon of radius r
+    along x meets it at the depth of the axis point closest to the ray's line
+    whenever the line passes within r of the axis (t = D for a ray straight
+    down from height D at any offset h < r; t = 5 for a ray crossing the axis
+    5 units away at 53 degrees), and misses beyond r; a ray along the axis
+    meets the first segment at its start; a tapered ribbon's half-width at a
+    segment end is that end's radius."""
+    r = 0.25
+    o = oracle.OracleScene(_curve_scene(_straight(r=r), flat=True))
+    c = o.capsules()
+    assert (c[:, 6] == np.float32(r)).all() and (c[:, 7] == np.float32(r)).all()
+    hs = np.array([0.0, 0.1, 0.2, 0.249, -0.249])
+    out = o.trace(_rays([[0.3, h, 5.0] for h in hs], [[0, 0, -1.0]] * len(hs)))
+    np.testing.assert_allclose(out.t, 5.0, rtol=1e-12)
+    assert (out.prim == 4).all()
+    obl = o.trace(_rays([[0.3, -3.0, 4.0], [0.3, -3.2, 4.0]], [[0, 0.6, -0.8], [0, 0.6, -0.8]]))
+    np.testing.assert_allclose(obl.t[0], 5.0, rtol=1e-12)
+    # shifted 0.2 in y: the line passes the axis at distance 0.2 * 0.8 = 0.16 < r,
+    # closest to the axis point x = 0.3; depth (3.2 * 0.6 + 4 * 0.8) = 5.12
+    np.testing.assert_allclose(obl.t[1], 5.12, rtol=1e-12)
+    miss = o.trace(_rays([[0.3, 0.26, 5.0], [0.3, -0.26, 5.0]], [[0, 0, -1.0], [0, 0, -1.0]]))
+    assert (miss.inst == -1).all()
+    along = o.trace(_rays([[-6.0, 0.05, 0.0]], [[1.0, 0, 0]]))
+    assert along.prim[0] == 0
+    np.testing.assert_allclose(along.t, [4.0], rtol=1e-12)
+    taper = [0, 0, 0, 0.4, 1, 0, 0, 0.3, 2, 0, 0, 0.2, 3, 0, 0, 0.1]
+    ot = oracle.OracleScene(_curve_scene(taper, flat=True))
+    ct = ot.capsules()
+    assert (ct[:-1, 7] == ct[1:, 6]).all() and ct[4, 6] == np.float32(0.25)
+    # at x = 1.5 (the start of segment 4) the half-width is 0.25
+    near = ot.trace(_rays([[1.5, 0.25 * (1 - 1e-6), 5.0], [1.5, 0.25 * (1 + 1e-6), 5.0]], [[0, 0, -1.0]] * 2))
+    assert near.inst[0] == 0 and near.inst[1] == -1
+
+
+@pytest.mark.parametrize("turned", [False, True])
+def test_ribbon_sun_shading_closed_form(turned):
+    """A flat ribbon faces the ray: seen from far away at 45 degrees along its
+    axis, its normal is the reverse ray direction without the part along the
+    axis, i.e. straight up up to the ray's sideways tilt beta (the ribbon's
+    half-width 0.3 at distance 200, over the 45-degree ray's vertical part:
+    |beta| < 2.3e-3).  With the sun at angle alpha from the zenith across the
+    axis, a camera sample on it carries a L_sky + a E cos(alpha - beta) / pi:
+    within a sin(alpha) 2.3e-3 of a L_sky + a E cos(alpha) / pi, and cos(alpha) on
+    average over the symmetric footprint.  (The reverse ray direction itself
+    would give cos(alpha) / sqrt(2).)"""
+    a, r, L, alpha = float(np.float32(0.5)), 0.3, 0.25, 0.6
+    if turned:
+        proto = [v for y in np.linspace(-2, 2, 4) for v in (0.0, y, 0.0, r)]
+        Rx = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], np.float64)
+        Ry = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], np.float64)
+        X = np.concatenate([Ry @ Rx, np.zeros((3, 1))], axis=1).reshape(1, 12)
+        o = oracle.OracleScene(_curve_scene(proto, xforms=X, albedo=a, flat=True))
+    else:
+        o = oracle.OracleScene(_curve_scene(_straight(r=r), albedo=a, flat=True))
+    D = 200.0 / math.sqrt(2.0)
+    cams = [sg.Camera((-D, 0.0, D), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 1.5, 96, 96)]
+    st = sg.RenderSettings(spp=1, depth=2, seed=9, light_dir=(0.0, math.sin(alpha), math.cos(alpha)), E=math.pi,
+                           L_sky=L)
+    img, fl, _ = o.render(cams, st)
+    hit = np.abs(img - L) > 1e-9
+    assert hit.sum() > 300
+    cosv = (img[hit] - a * L) / a
+    assert (np.abs(cosv - math.cos(alpha)) <= math.sin(alpha) * 2.3e-3).all(), np.abs(cosv - math.cos(alpha)).max()
+    assert abs(cosv.mean() - math.cos(alpha)) < 1e-4, cosv.mean() - math.cos(alpha)
+
+
+def test_ribbon_flags():
+    """A ray passing a flat ribbon's edge within the graze distance is flagged
+    GRAZE and either answer is acceptable; a ray through the middle of a
+    segment is not flagged and must hit.  (Segments 0.5 long with radius 0.2,
+    rays at x = 0.25, the middle of segment 4: the neighbouring segments' ends
+    lie 0.25 away, beyond their radius.  Where the round ends of neighbouring
+    segments overlap a segment seen face-on, both lie at the same depth: a
+    tie.)"""
+    r = 0.2
+    o = oracle.OracleScene(_curve_scene(_straight(r=r), flat=True))
+    rays = _rays([[0.25, r * (1 + 1e-9), 5.0], [0.25, r * (1 - 1e-9), 5.0], [0.25, 0.0, 5.0]], [[0, 0, -1.0]] * 3)
+    out = o.trace(rays)
+    assert out.flags[0] & oracle.F_GRAZE and out.flags[1] & oracle.F_GRAZE
+    assert (out.flags[2] & oracle.ID_FLAGS) == 0 and out.inst[2] == 0
+    code, info = o.accept(rays.astype(np.float32), np.array([-1, 0, -1]), np.array([-1, 4, -1]),
+                          np.array([np.inf, out.t[1], np.inf], np.float32))
+    assert code[0] == 0 and code[1] == 0 and code[2] == 2
