@@ -35,6 +35,15 @@
  *    starts inside a capsule does not hit it).  Capsule j of curve c of a
  *    prototype is its primitive 8 c + j; the hit's u is the curve parameter
  *    (j + y) / 8, y in [0, 1] the position along the capsule's axis, and v = 0.
+ *    A prototype may instead hold flat (ray-facing) ribbons: the same 8
+ *    segments with radius varying linearly from one point's radius to the
+ *    next, each seen along the ray as the strip of points within that radius
+ *    of its projection; a ray meets it when its line passes within the radius
+ *    of the projected segment's closest point, at the depth of that segment
+ *    point (u then holds that point's curve parameter).  A ray that excludes
+ *    a ribbon segment (rtq_rays.exclude) ignores every segment of that curve
+ *    in that instance: a ribbon turns toward every ray, so the neighbours of
+ *    the segment a ray leaves would face it next to its origin.
  *  - An instance transform is a row-major 3x4 FP32 matrix [A | t] mapping object
  *    to world space, w = A v + t.
  *  - A hit is accepted when tmin < t <= tmax; among accepted hits the one with
@@ -122,6 +131,7 @@ typedef struct {
   const float* curves;  /* n_curves x 16 FP32: 4 control points (x, y, z, radius), radius >= 0;
                            NULL for a quad mesh */
   int32_t n_curves;     /* >= 1 for curves (then n_quads = 0 and verts, quads may be NULL), else 0 */
+  int32_t curves_flat;  /* nonzero: the curves are flat ray-facing ribbons; 0: round */
 } rtq_prototype;
 
 /* Object-level instances (host memory): instance i draws prototype proto[i]

@@ -37,7 +37,7 @@ class RtqError(RuntimeError):
 class _Proto(ctypes.Structure):
     _fields_ = [("verts", ctypes.c_void_p), ("quads", ctypes.c_void_p), ("n_verts", ctypes.c_int32),
                 ("n_quads", ctypes.c_int32), ("albedo", ctypes.c_void_p), ("curves", ctypes.c_void_p),
-                ("n_curves", ctypes.c_int32)]
+                ("n_curves", ctypes.c_int32), ("curves_flat", ctypes.c_int32)]
 
 
 class _Insts(ctypes.Structure):
@@ -190,6 +190,7 @@ class Scene:
         assert albedo.shape[0] == self.n_faces
         cv = np.ascontiguousarray(curves if curves is not None else np.zeros((0, 16)), dtype=np.float32)
         co = s.proto_curve_off if curves is not None else np.zeros(s.n_protos + 1, np.int64)
+        flat = getattr(s, "proto_curve_flat", None)
         P = s.n_protos
         protos = (_Proto * P)()
         vb = verts.ctypes.data
@@ -207,6 +208,7 @@ class Scene:
             protos[p].albedo = ab + 4 * f0
             protos[p].curves = cv.ctypes.data + 64 * c0 if c1 > c0 else None
             protos[p].n_curves = c1 - c0
+            protos[p].curves_flat = int(flat[p]) if flat is not None else 0
             f0 += (q1 - q0) + (c1 - c0)
         ip = np.ascontiguousarray(s.inst_proto, dtype=np.int32)
         ix = np.ascontiguousarray(s.inst_xform, dtype=np.float32)

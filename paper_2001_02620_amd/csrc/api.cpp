@@ -130,9 +130,10 @@ const char* rtq_version(void) { return "rtq 0.1 (gfx950)"; }
 // count, when the caller leaves rtq_build_opts.open_pct at 0.
 constexpr int32_t kDefaultOpenPct = 50;
 
-// One capsule of a curve: axis from a to b, radius r (FP32 values).
+// One segment of a curve: axis from a to b, radius r at a and rb at b (equal
+// for the capsules of round curves; FP32 values).
 struct Capsule {
-  float a[3], b[3], r;
+  float a[3], b[3], r, rb;
 };
 
 // Curve -> kCapsPerCurve capsules (Section 5.2: curves rendered as chains of
@@ -142,8 +143,8 @@ struct Capsule {
 // interpolation adds at most 3 bits to the operands' 24 (plus their exponent
 // spread), well inside FP64's 53.  The exact point is then rounded once to FP32.
 // A capsule's radius is the FP32 rounding of the mean of its end radii (exact
-// in FP64 for the same reason).
-static void tessellate_curve(const float* cp, Capsule* out) {
+// in FP64 for the same reason); a ribbon segment keeps both end radii.
+static void tessellate_curve(const float* cp, Capsule* out, bool flat) {
   double X[kCapsPerCurve + 1][4];
   for (int j = 0; j <= kCapsPerCurve; ++j) {
     const double s = (double)j / kCapsPerCurve;
@@ -160,7 +161,12 @@ static void tessellate_curve(const float* cp, Capsule* out) {
       c.a[k] = (float)X[j][k];
       c.b[k] = (float)X[j + 1][k];
     }
-    c.r = (float)(0.5 * (X[j][3] + X[j + 1][3]));
+    if (flat) {
+      c.r = (float)X[j][3];
+      c.rb = (float)X[j + 1][3];
+    } else {
+      c.r = c.rb = (float)(0.5 * (X[j][3] + X[j + 1][3]));
+    }
   }
 }
 
@@ -169,9 +175,10 @@ static void tessellate_curve(const float* cp, Capsule* out) {
 // hits may lie that far outside the exact surface (the traversal must not cull
 // a box whose capsule the same test would report hit), rounded outward.
 static Aabb capsule_box(const Capsule& c) {
-  double m = c.r;
+  const double rr = std::max((double)c.r, (double)c.rb);
+  double m = rr;
   for (int k = 0; k < 3; ++k) m = std::max(m, std::max(std::fabs((double)c.a[k]), std::fabs((double)c.b[k])));
-  const double g = (double)c.r + std::ldexp(m + (double)c.r, -18);
+  const double g = rr + std::ldexp(m + rr, -18);
   Aabb b;
   for (int k = 0; k < 3; ++k) {
     const double lo = std::min((double)c.a[k], (double)c.b[k]) - g;
@@ -194,6 +201,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   if (!out) return set_error(RTQ_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!protos || n_protos < 1) return set_error(RTQ_E_INVALID_ARG, "need at least one prototype");
+  if (n_protos >= (1 << 30)) return set_error(RTQ_E_LIMIT, "%d prototypes exceed 2^30", n_protos);
   if (!insts || insts->n < 0 || (insts->n > 0 && (!insts->proto || !insts->xform)))
     return set_error(RTQ_E_INVALID_ARG, "bad instance arrays");
   rtq_build_opts o{};
@@ -285,7 +293,8 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     if (protos[p].n_curves == 0) continue;
     caps[p].resize((size_t)n_prim[p]);
     for (int32_t c = 0; c < protos[p].n_curves; ++c)
-      tessellate_curve(protos[p].curves + 16 * (int64_t)c, &caps[p][(size_t)c * kCapsPerCurve]);
+      tessellate_curve(protos[p].curves + 16 * (int64_t)c, &caps[p][(size_t)c * kCapsPerCurve],
+                       protos[p].curves_flat != 0);
   }
   auto build_proto = [&](int32_t p, int threads, std::vector<Aabb>& boxes) {
     const rtq_prototype& P = protos[p];
@@ -364,7 +373,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     }
     proto_root[p] = (uint32_t)node_base;
     face_base[p] = (uint32_t)fbase;  // faces: quads, or curves, in prototype order
-    proto_flags[p] = protos[p].n_curves > 0 ? kProtoCurve : 0u;
+    proto_flags[p] = protos[p].n_curves > 0 ? (kProtoCurve | (protos[p].curves_flat ? kProtoFlat : 0u)) : 0u;
     proto_qbase[p] = (int32_t)quad_base;
     proto_nq[p] = n_prim[p];
     proto_pmax[p] = level_pmax(blas[p]);
@@ -392,7 +401,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
       const uint32_t k = blas[p].order[j];
       const Capsule& c = caps[p][k];
       quads[3 * (qb + j) + 0] = make_float4(c.a[0], c.a[1], c.a[2], c.r);
-      quads[3 * (qb + j) + 1] = make_float4(c.b[0], c.b[1], c.b[2], 0.0f);
+      quads[3 * (qb + j) + 1] = make_float4(c.b[0], c.b[1], c.b[2], c.rb);
       quads[3 * (qb + j) + 2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       quad_prim[qb + j] = (int32_t)k;
       const Aabb bx = capsule_box(c);

@@ -162,7 +162,8 @@ __device__ __forceinline__ uint32_t face_texel(const SceneView& sc, uint32_t fac
 }
 
 // Geometric normal of the hit in object space -- the hit half's for a quad; for
-// a capsule the hit point minus its closest point on the axis -- mapped to world
+// a capsule the hit point minus its closest point on the axis; for a ribbon the
+// reverse ray direction without its part along the segment -- mapped to world
 // space by A^-T (columns of the stored inverse rows), normalised and turned to
 // face the incoming ray; hit point p = o + t d; albedo of the unique prototype
 // face (a quad, or the capsule's curve), or its texel at the hit's (u, v) when
@@ -178,7 +179,19 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   const float4 r2 = *reinterpret_cast<const float4*>(ir.r2);
   const bool cap = (ir.proto & kProtoCurve) != 0u;
   float onx, ony, onz;
-  if (cap) {
+  if ((ir.proto & kProtoFlat) != 0u) {
+    // ribbon segment (a, b) = (f0, f1): it faces the ray, so its normal is the
+    // reverse object-space direction without its part along the segment
+    const float dx = fmaf(r0.x, r.dx, fmaf(r0.y, r.dy, r0.z * r.dz));
+    const float dy = fmaf(r1.x, r.dx, fmaf(r1.y, r.dy, r1.z * r.dz));
+    const float dz = fmaf(r2.x, r.dx, fmaf(r2.y, r.dy, r2.z * r.dz));
+    const float tx = f1.x - f0.x, ty = f1.y - f0.y, tz = f1.z - f0.z;
+    const float tt = fmaf(tx, tx, fmaf(ty, ty, tz * tz));
+    const float k = tt > 0.0f ? fmaf(dx, tx, fmaf(dy, ty, dz * tz)) / tt : 0.0f;
+    onx = fmaf(k, tx, -dx);
+    ony = fmaf(k, ty, -dy);
+    onz = fmaf(k, tz, -dz);
+  } else if (cap) {
     // capsule (a, r) = f0, b = f1.xyz.  Its normal follows the hit point, so the
     // point is formed in FP64 from the FP32 ray and t (exact products, one
     // rounding per sum) relative to the instance origin, where it is small,

@@ -112,14 +112,16 @@ static_assert(sizeof(InstRec) == 64, "InstRec is 64 B");
 
 // Primitives are stored in leaf order as 3 x float4.  A quad:
 //   (v0.x v0.y v0.z v1.x) (v1.y v1.z v2.x v2.y) (v2.z v3.x v3.y v3.z)
-// A capsule (axis from a to b, radius r):
-//   (a.x a.y a.z r) (b.x b.y b.z 0) (0 0 0 0)
+// A curve segment (a capsule of radius r = rb, or a ribbon of radius r at a
+// and rb at b):
+//   (a.x a.y a.z r) (b.x b.y b.z rb) (0 0 0 0)
 constexpr int kQuadFloat4 = 3;
 
 // Curves (Section 5.2): a cubic Bezier traced as kCapsPerCurve capsules; the
 // capsules of curve c of a prototype are its primitives kCapsPerCurve c + j.
 constexpr int kCapsPerCurve = 8;
 constexpr uint32_t kProtoCurve = 0x80000000u;  // InstRec::proto flag: the prototype holds curves
+constexpr uint32_t kProtoFlat = 0x40000000u;   // ... and they are flat ribbons (set with kProtoCurve)
 
 // Traversal stack per lane: every W-wide level pushes at most W - 1 entries,
 // so a scene needs (W - 1) (top depth + bottom depth) + 8 entries at most; the

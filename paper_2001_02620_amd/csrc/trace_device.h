@@ -96,6 +96,7 @@ struct Lane {
   float Sx, Sy, Sz;
   int kz;            // dominant axis of the object-space direction
   bool curve;        // the current instance's prototype holds curves (capsule leaves)
+  bool flat;         // ... flat ribbons (ribbon leaves)
   // traversal
   uint32_t cur;      // reference to process next, kEmpty = pop
   int sp;            // stack size
@@ -183,6 +184,7 @@ __device__ __forceinline__ void enter_instance(Lane& L, const SceneView& sc, uin
   L.Sy = pick3(dx, dy, dz, ky) * L.Sz;
   L.rec = r;
   L.curve = (proto & kProtoCurve) != 0u;
+  L.flat = (proto & kProtoFlat) != 0u;
   *blas_root = root;
 }
 
@@ -728,14 +730,94 @@ __device__ __forceinline__ bool cap_test(Lane& L, const SceneView& sc, bool act,
   return false;
 }
 
-// Primitive test of the current instance: a quad, or a capsule when the
-// instance's prototype holds curves.  The two tests run only when a lane of the
-// wave needs them (wave-uniform branches).
+// Flat ribbon segment q under record `rec` (Section 5.2 names flat ribbon
+// curves): (a, ra) = c0, (b, rb) = c1, radius ra + u (rb - ra).  Seen along the
+// ray it is the strip of points within that radius of its projection onto
+// the plane orthogonal to the ray; the ray meets it when its line passes
+// within the radius of the projected segment's point u closest to it, at the
+// depth of that segment point.  In object space in FP32, the direction scaled
+// by a power of two as in cap_hit, the origin moved to the ray's closest
+// approach to the segment midpoint so every vector below is formed next to the
+// segment.  y returns u.
+__device__ __forceinline__ CapResult ribbon_hit(const Lane& L, const SceneView& sc, uint32_t rec, uint32_t q) {
+  CapResult res{kInfF, 0.0f};
+  const float4 c0 = sc.quads[3 * (size_t)q + 0];
+  const float4 c1 = sc.quads[3 * (size_t)q + 1];
+  const float4 ra = *reinterpret_cast<const float4*>(sc.inst[rec].r0);
+  const float4 rb = *reinterpret_cast<const float4*>(sc.inst[rec].r1);
+  const float4 rc = *reinterpret_cast<const float4*>(sc.inst[rec].r2);
+  float dx = fmaf(ra.x, L.wdx, fmaf(ra.y, L.wdy, ra.z * L.wdz));
+  float dy = fmaf(rb.x, L.wdx, fmaf(rb.y, L.wdy, rb.z * L.wdz));
+  float dz = fmaf(rc.x, L.wdx, fmaf(rc.y, L.wdy, rc.z * L.wdz));
+  const float dm = fmaxf(fabsf(dx), fmaxf(fabsf(dy), fabsf(dz)));
+  if (!(dm > 0.0f) || !(dm < kInfF)) return res;
+  const int e = __builtin_amdgcn_frexp_expf(dm);
+  dx = __builtin_amdgcn_ldexpf(dx, -e);
+  dy = __builtin_amdgcn_ldexpf(dy, -e);
+  dz = __builtin_amdgcn_ldexpf(dz, -e);
+  const float dd = dot3(dx, dy, dz, dx, dy, dz);
+  const float bax = c1.x - c0.x, bay = c1.y - c0.y, baz = c1.z - c0.z;
+  const float mx = fmaf(0.5f, bax, c0.x), my = fmaf(0.5f, bay, c0.y), mz = fmaf(0.5f, baz, c0.z);
+  const float t0 = dot3(mx - L.lox, my - L.loy, mz - L.loz, dx, dy, dz) / dd;
+  const float px = fmaf(t0, dx, L.lox), py = fmaf(t0, dy, L.loy), pz = fmaf(t0, dz, L.loz);
+  const float Ax = c0.x - px, Ay = c0.y - py, Az = c0.z - pz;
+  const float Bx = c1.x - px, By = c1.y - py, Bz = c1.z - pz;
+  const float ka = dot3(Ax, Ay, Az, dx, dy, dz) / dd, kb = dot3(Bx, By, Bz, dx, dy, dz) / dd;
+  const float apx = fmaf(-ka, dx, Ax), apy = fmaf(-ka, dy, Ay), apz = fmaf(-ka, dz, Az);
+  const float ex = fmaf(-kb, dx, Bx) - apx, ey = fmaf(-kb, dy, By) - apy, ez = fmaf(-kb, dz, Bz) - apz;
+  const float ee = dot3(ex, ey, ez, ex, ey, ez);
+  const float u = ee > 0.0f ? fminf(fmaxf(-dot3(apx, apy, apz, ex, ey, ez) / ee, 0.0f), 1.0f) : 0.0f;
+  const float qx = fmaf(u, ex, apx), qy = fmaf(u, ey, apy), qz = fmaf(u, ez, apz);
+  const float r = fmaf(u, c1.w - c0.w, c0.w);
+  if (!(dot3(qx, qy, qz, qx, qy, qz) <= r * r)) return res;
+  const float t = t0 + fmaf(u, kb - ka, ka);
+  res.t = t < kInfF ? __builtin_amdgcn_ldexpf(t, -e) : kInfF;
+  res.y = u;
+  return res;
+}
+
+// Test ribbon segment q of the current instance on the lanes with `act` set;
+// updates as cap_test.  A ray that excludes a segment of a ribbon ignores every
+// segment of that curve in that instance (a ribbon turns toward every ray, so
+// the neighbours of the segment a ray leaves would face it next to its
+// origin): compared by instance id and curve (primitive / 8), looked up only
+// for a hit of a ray that has an exclusion.
+__device__ __forceinline__ bool ribbon_test(Lane& L, const SceneView& sc, bool act, uint32_t q) {
+  const CapResult c = ribbon_hit(L, sc, act ? L.rec : 0u, q);
+  const float t_lim = L.any ? L.tmax : L.t_best;
+  bool ok = act && c.t < kInfF && c.t > L.tmin && c.t <= t_lim;
+  if (ok && L.ex_rec != kEmpty) {
+    const bool same_curve =
+        sc.inst[L.rec].inst_id == sc.inst[L.ex_rec].inst_id &&
+        (uint32_t)sc.quad_prim[q] / (uint32_t)kCapsPerCurve ==
+            (uint32_t)sc.quad_prim[L.ex_qh & 0x7FFFFFFFu] / (uint32_t)kCapsPerCurve;
+    ok = !same_curve;
+  }
+  if (L.any) {
+    L.t_best = ok ? c.t : L.t_best;
+    L.b_rec = ok ? L.rec : L.b_rec;
+    L.b_qh = ok ? q : L.b_qh;
+    return ok;
+  }
+  const bool upd = ok && better(L, sc, c.t, q, 0u);
+  L.t_best = upd ? c.t : L.t_best;
+  L.b_rec = upd ? L.rec : L.b_rec;
+  L.b_qh = upd ? q : L.b_qh;
+  L.b_u = upd ? c.y : L.b_u;
+  L.b_v = upd ? 0.0f : L.b_v;
+  L.t_cull = L.t_best * kSlack;
+  return false;
+}
+
+// Primitive test of the current instance: a quad, a capsule or a ribbon
+// segment, by the instance's prototype.  Each test runs only when a lane of the
+// wave needs it (wave-uniform branches).
 __device__ __forceinline__ bool prim_test(Lane& L, const SceneView& sc, bool act, uint32_t q,
                                           uint32_t* n64 = nullptr) {
   bool answered = false;
   if (__any(act && !L.curve)) answered = quad_test(L, sc, act && !L.curve, q, n64);
-  if (__any(act && L.curve)) answered = cap_test(L, sc, act && L.curve, q) || answered;
+  if (__any(act && L.curve && !L.flat)) answered = cap_test(L, sc, act && L.curve && !L.flat, q) || answered;
+  if (__any(act && L.flat)) answered = ribbon_test(L, sc, act && L.flat, q) || answered;
   return answered;
 }
 
@@ -819,6 +901,7 @@ __device__ __forceinline__ bool lane_init(Lane& L, const SceneView& sc, float ox
   L.inst_sp = -1;
   L.rec = kEmpty;
   L.curve = false;
+  L.flat = false;
   L.cur = sc.tlas_root;
   L.any = false;
   L.done = false;
@@ -921,6 +1004,7 @@ __device__ __forceinline__ void inst_step(bool act, Lane& L, const SceneView& sc
   L.Sz = act ? N.Sz : L.Sz;
   L.kz = act ? N.kz : L.kz;
   L.curve = act ? N.curve : L.curve;
+  L.flat = act ? N.flat : L.flat;
   L.rec = act ? N.rec : L.rec;
   L.inst_sp = act ? L.sp : L.inst_sp;
   L.cur = act ? root : L.cur;

@@ -101,6 +101,14 @@ def compare_with_oracle(scene, rays, g, o, uv_factor=64.0, excl=None, ora_scene=
         s_ = np.clip(((P - a) * ba).sum(1) / np.maximum(Lc * Lc, 1e-300), 0, 1)
         nrm = P - (a + s_[:, None] * ba)
         cos = np.abs((nrm * r[:, 3:6]).sum(1)) / (np.linalg.norm(nrm, axis=1) * np.linalg.norm(r[:, 3:6], axis=1))
+        flat = getattr(scene, "proto_curve_flat", None)
+        if flat is not None:
+            # a ribbon's u follows the projected segment: the sine of the angle
+            # between the ray and the segment takes the part of |cos|
+            fl_ = flat[pi] != 0
+            sin = np.linalg.norm(np.cross(ba, r[:, 3:6]), axis=1) / (np.maximum(Lc, 1e-300) *
+                                                                     np.linalg.norm(r[:, 3:6], axis=1))
+            cos = np.where(fl_, sin, cos)
         tol = uv_factor * 2.0 ** -24 * o.scale[caph] / (8 * np.maximum(Lc, 1e-30) * np.maximum(cos, 1e-3)) + 2.0 ** -21
         du = np.abs(g["u"][caph] - o.u[caph])
         assert (du <= tol).all() and (g["v"][caph] == 0).all(), f"capsule u error {du.max()}"

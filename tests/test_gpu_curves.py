@@ -65,8 +65,8 @@ def capsule_rays(scene, osc, rng, n):
     return rays
 
 
-def _curve_case(seed=3):
-    scene = sg.curve_scene(seed, n_inst=8, n_curves=24)
+def _curve_case(seed=3, flat=(False, False)):
+    scene = sg.curve_scene(seed, n_inst=8, n_curves=24, flat=flat)
     osc = oracle.OracleScene(scene)
     rng = np.random.default_rng(seed + 100)
     rays = np.concatenate([capsule_rays(scene, osc, rng, 30000),
@@ -74,10 +74,12 @@ def _curve_case(seed=3):
     return scene, osc, rays
 
 
-@pytest.mark.parametrize("width", [4, 2, 8])
-def test_curve_hits_bvh_brute_and_oracle(width):
-    log(f"case: curves, closest hits and occlusion, width {width}")
-    scene, osc, rays = _curve_case()
+@pytest.mark.parametrize("width,flat", [(4, False), (2, False), (8, False), (4, True), (2, True)])
+def test_curve_hits_bvh_brute_and_oracle(width, flat):
+    """Round capsule chains, or one tuft prototype of each kind (flat: the
+    second tuft is ribbons)."""
+    log(f"case: curves, closest hits and occlusion, width {width}, flat ribbons {flat}")
+    scene, osc, rays = _curve_case(flat=(False, flat))
     R = to_dev(rays)
     fmts = 0 if width == 4 else rtq.RTQ_NODE_Q8
     S = rtq.Scene(scene, node_width=width, formats=fmts)
@@ -102,13 +104,14 @@ def test_curve_hits_bvh_brute_and_oracle(width):
     S.close()
 
 
-def test_curve_secondary_rays_with_exclusion():
-    """Bounce rays leaving capsule (and ground) hits exclude the primitive they
-    leave: variants equal brute force, and the oracle, given the same
-    exclusions, accepts every answer."""
+@pytest.mark.parametrize("flat", [False, True])
+def test_curve_secondary_rays_with_exclusion(flat):
+    """Bounce rays leaving capsule, ribbon (and ground) hits exclude the
+    primitive they leave (a ribbon: its whole curve): variants equal brute
+    force, and the oracle, given the same exclusions, accepts every answer."""
     import torch
-    log("case: curves, secondary rays with exclusion")
-    scene, osc, rays = _curve_case(5)
+    log(f"case: curves, secondary rays with exclusion, flat ribbons {flat}")
+    scene, osc, rays = _curve_case(5, flat=(flat, flat))
     S = rtq.Scene(scene)
     h0 = rtq.trace_closest(S, to_dev(rays), want_ref=True, node_format=rtq.RTQ_NODE_Q8,
                            scheduler=rtq.SCHED_PERSISTENT)
@@ -137,19 +140,20 @@ def test_curve_secondary_rays_with_exclusion():
     S.close()
 
 
-def _frame_setup(seed=4):
-    scene = sg.curve_scene(seed, n_inst=8, n_curves=24)
+def _frame_setup(seed=4, flat=(False, False)):
+    scene = sg.curve_scene(seed, n_inst=8, n_curves=24, flat=flat)
     cams = [sg.Camera((0.0, -5.5, 1.4), (0.0, 0.0, 0.4), (0.0, 0.0, 1.0), 45.0, 48, 40),
             sg.Camera((3.0, 3.0, 2.0), (0.0, 0.0, 0.3), (0.0, 0.0, 1.0), 50.0, 40, 32)]
     st = sg.RenderSettings(spp=2, depth=4, seed=17, frame=1)
     return scene, cams, st
 
 
-@pytest.mark.parametrize("mode", ["lambert", "principled+lights"])
-def test_curve_frames_schedulers_and_oracle(mode):
+@pytest.mark.parametrize("mode,flat", [("lambert", False), ("principled+lights", False), ("lambert", True),
+                                       ("principled+lights", True)])
+def test_curve_frames_schedulers_and_oracle(mode, flat):
     import torch
-    log(f"case: curve frames, {mode}")
-    scene, cams, st = _frame_setup()
+    log(f"case: curve frames, {mode}, flat ribbons {flat}")
+    scene, cams, st = _frame_setup(flat=(flat, flat))
     S = rtq.Scene(scene)
     osc = oracle.OracleScene(scene)
     if mode != "lambert":
@@ -191,7 +195,7 @@ def test_curve_frames_schedulers_and_oracle(mode):
 
 def test_curve_frames_equal_across_widths():
     log("case: curve frames, node widths")
-    scene, cams, st = _frame_setup(6)
+    scene, cams, st = _frame_setup(6, flat=(False, True))
     S4 = rtq.Scene(scene)
     ref = _np(rtq.render(S4, cams, st, node_format=rtq.RTQ_NODE_FP32, scheduler=rtq.SCHED_PLAIN))
     S4.close()
@@ -214,7 +218,7 @@ def test_curve_adjoint():
     uncertainty -- set to zero: the faces no flagged path reaches agree."""
     import torch
     log("case: curve adjoint")
-    scene, cams, st = _frame_setup(7)
+    scene, cams, st = _frame_setup(7, flat=(True, False))
     st.depth = 3
     S = rtq.Scene(scene)
     kw = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)
@@ -304,3 +308,33 @@ def test_curve_argument_errors():
                       inst_xform=scene.inst_xform, curves=c, proto_curve_off=scene.proto_curve_off)
         with pytest.raises(rtq.RtqError):
             rtq.Scene(s2)
+
+
+def test_ribbon_sun_closed_form_gpu():
+    """A flat ribbon seen from far away at 45 degrees along its axis faces up
+    to within the ray's sideways tilt (|beta| < 2.3e-3): with the sun at
+    alpha = 0.6 from the zenith across the axis, every camera sample on it
+    carries a L_sky + a E cos(alpha - beta) / pi (the reverse ray direction
+    as the normal would give cos(alpha) / sqrt(2))."""
+    log("case: ribbon closed form on the GPU")
+    a, r, L, alpha = float(np.float32(0.5)), 0.3, 0.25, 0.6
+    curve = [v for x in np.linspace(-2, 2, 4) for v in (x, 0.0, 0.0, r)]
+    scene = sg.Scene(verts=np.zeros((0, 3), np.float32), quads=np.zeros((0, 4), np.int32),
+                     proto_vert_off=np.array([0, 0], np.int64), proto_quad_off=np.array([0, 0], np.int64),
+                     albedo=np.array([a], np.float32), inst_proto=np.zeros(1, np.int32),
+                     inst_xform=sg.identity_xform(1), curves=np.array([curve], np.float32),
+                     proto_curve_off=np.array([0, 1], np.int64), proto_curve_flat=np.array([1], np.int32))
+    scene.validate()
+    S = rtq.Scene(scene)
+    D = 200.0 / math.sqrt(2.0)
+    cams = [sg.Camera((-D, 0.0, D), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 1.5, 96, 96)]
+    st = sg.RenderSettings(spp=1, depth=2, seed=9, light_dir=(0.0, math.sin(alpha), math.cos(alpha)), E=math.pi,
+                           L_sky=L)
+    img = _np(rtq.render(S, cams, st)).astype(np.float64)
+    hit = np.abs(img - L) > 1e-6
+    cosv = (img[hit] - a * L) / a
+    log(f"  {hit.sum()} samples on the ribbon, cos spread {cosv.min():.6f} .. {cosv.max():.6f} "
+        f"(cos(alpha) {math.cos(alpha):.6f})")
+    assert hit.sum() > 300
+    assert (np.abs(cosv - math.cos(alpha)) <= math.sin(alpha) * 2.3e-3 + 2e-6).all()
+    S.close()
