@@ -28,7 +28,8 @@ printed.  Beside it (same JSON line):
                        principled materials in three channels;
   config4_adjoint      forward frame and path-replay backward pass at config 4;
   curves               a grass field of 100k tufts of cubic Bezier curves (51M
-                       instanced capsules) over a quad ground: frames of both
+                       instanced segments) over a quad ground, round (capsule
+                       chains) and flat (ray-facing ribbons): frames of both
                        paths (bit-identical) and its bounce rays' closest hits;
   config2              the smaller 1M-instance configuration: frames and
                        incoherent rays, both paths, and node widths 2, 4 and 8
@@ -210,7 +211,7 @@ def compare_widths(rtq, scene, cams, st, cap, log, steps=5, frames=5):
             "fastest_frame": min(out, key=lambda k: out[k]["ms_per_frame"])}
 
 
-def curve_field(rtq, sg, args, log):
+def curve_field(rtq, sg, args, log, flat=False):
     """Curves (Section 5.2: the scene's curves): a grass field of tuft
     instances -- cubic Beziers traced as chains of capsules -- over a ground
     grid, one 1280x720 view at 4 spp, depth 4.  FP32-plain and
@@ -220,7 +221,7 @@ def curve_field(rtq, sg, args, log):
     import numpy as np
     import torch
     t0 = time.time()
-    scene = sg.curve_scene(11, n_inst=args.curve_instances, n_curves=64, spread=40.0)
+    scene = sg.curve_scene(11, n_inst=args.curve_instances, n_curves=64, spread=40.0, flat=(flat, flat))
     S = rtq.Scene(scene)
     build_s = time.time() - t0
     info = S.info()
@@ -249,8 +250,8 @@ def curve_field(rtq, sg, args, log):
         return dict(ms_per_frame=round(1e3 * wall / steps, 3), mrays_s=round((c[0] + c[1]) / wall / 1e6, 2),
                     rays_per_frame=(c[0] + c[1]) / steps)
 
-    if args.profile == "curves":
-        log(f"profile run (curve frames): {timed(Q8P, args.steps, args.warmup)}")
+    if args.profile in ("curves", "ribbons"):
+        log(f"profile run ({args.profile} frames): {timed(Q8P, args.steps, args.warmup)}")
         return None
     st.frame = 0
     rtq.render(S, cams, st, images=img, **F32)
@@ -285,9 +286,10 @@ def curve_field(rtq, sg, args, log):
         rtq.trace_closest(S, rays, exclude=excl, soa_in=True, **Q8P)
     torch.cuda.synchronize()
     inc = nd * steps / (time.perf_counter() - w0) / 1e6
-    out = {"workload": f"grass field: {scene.n_instances - 1} tufts of 64 curves (2 prototypes, rotated and "
-                       f"scaled) over a 6x6 quad ground, {info['n_unique_capsules']} unique capsules, "
-                       f"{8 * 64 * (scene.n_instances - 1):.3e} instanced capsules; 1280x720, 4 spp, depth 4",
+    kind = "flat ribbons" if flat else "round curves (capsule chains)"
+    out = {"workload": f"grass field of {kind}: {scene.n_instances - 1} tufts of 64 curves (2 prototypes, rotated and "
+                       f"scaled) over a 6x6 quad ground, {info['n_unique_capsules']} unique segments, "
+                       f"{8 * 64 * (scene.n_instances - 1):.3e} instanced segments; 1280x720, 4 spp, depth 4",
            "equal_images": equal, "q8_persistent": q8, "fp32_plain": f32,
            "speedup": round(f32["ms_per_frame"] / q8["ms_per_frame"], 3),
            "incoherent": {"rays": nd, "q8_persistent_mrays_s": round(inc, 2),
@@ -311,7 +313,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
     ap.add_argument("--curve-instances", type=int, default=100_000, help="tufts of the curve field")
     ap.add_argument("--no-curves", action="store_true")
-    ap.add_argument("--profile", choices=("incoherent", "frame", "curves"), default=None,
+    ap.add_argument("--profile", choices=("incoherent", "frame", "curves", "ribbons"), default=None,
                     help="only the timed incoherent queries, or only timed frames (for rocprofv3)")
     ap.add_argument("--widths", action="store_true",
                     help="only compare node widths 2, 4 and 8 on the configuration-3 workload (one build each)")
@@ -340,8 +342,8 @@ def main():
         torch.cuda.synchronize()
         log("copied 5 x 1 GiB")
         return
-    if args.profile == "curves":
-        curve_field(rtq, sg, args, log)
+    if args.profile in ("curves", "ribbons"):
+        curve_field(rtq, sg, args, log, flat=args.profile == "ribbons")
         return
     t0 = time.time()
     scene, cams, st = sg.config3(scale=args.scale)
@@ -613,7 +615,8 @@ def main():
     adj["workload"] = "config4: config-1 scene (1000 instances, 16384 unique quads), 512x512, 4 spp, depth 4"
     log(f"config 4 adjoint: {adj}")
     del S4
-    curves = None if args.no_curves else curve_field(rtq, sg, args, log)
+    curves = None if args.no_curves else {"round": curve_field(rtq, sg, args, log),
+                                          "flat": curve_field(rtq, sg, args, log, flat=True)}
 
     # ---- CPU baseline: the FP64 oracle tracing a bounded random sample of the
     # same incoherent rays (same exclusions), sized by a pilot to about
