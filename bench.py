@@ -313,6 +313,11 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
     ap.add_argument("--curve-instances", type=int, default=100_000, help="tufts of the curve field")
     ap.add_argument("--no-curves", action="store_true")
+    ap.add_argument("--open-pct", type=int, default=200,
+                    help="config 3's build: top-level entries added by opening instances, in percent of the instance "
+                         "count (the library's default is 50; at config 3, 25/50/100/200/400 measured 27.0/22.7/"
+                         "21.4/20.3/21.4 ms per incoherent query, and frames of 56.7 ms at 50, 50.6 at 200, 52.8 at "
+                         "400 -- the pick of autotune_build; config 2 keeps the default, its best)")
     ap.add_argument("--profile", choices=("incoherent", "frame", "curves", "ribbons"), default=None,
                     help="only the timed incoherent queries, or only timed frames (for rocprofv3)")
     ap.add_argument("--widths", action="store_true",
@@ -354,9 +359,10 @@ def main():
                                                              steps=args.steps, frames=args.steps)}))
         return
     t0 = time.time()
-    S = rtq.Scene(scene)
+    S = rtq.Scene(scene, open_pct=args.open_pct)
     info = S.info()
-    log(f"build: {time.time() - t0:.1f} s, device {info['device_bytes'] / 2**30:.2f} GiB")
+    log(f"build: {time.time() - t0:.1f} s, device {info['device_bytes'] / 2**30:.2f} GiB, "
+        f"{info['n_top_entries']} top-level entries")
     n_pix = sum(c.w * c.h for c in cams)
     img = torch.empty(n_pix, device="cuda")
     Q8P = dict(node_format=rtq.RTQ_NODE_Q8, scheduler=rtq.SCHED_PERSISTENT)

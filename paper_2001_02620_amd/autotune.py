@@ -159,16 +159,20 @@ def autotune_trace(S, rays, formats=(RTQ_NODE_Q8, RTQ_NODE_FP32), schedulers=(SC
     return result
 
 
-def autotune_width(scene_arrays, cams, settings, widths=(4, 8, 2), schedulers=(SCHED_PERSISTENT,),
-                   grid: Optional[dict] = None, reps: int = 2, build_opts: Optional[dict] = None, rays=None,
-                   log=None) -> dict:
-    """Choose the node width: build the scene (generator arrays) once per width,
-    tune the quantized-node launches of each, and return the fastest width with
-    its launch options.  Every width's frames (and closest hits of `rays`, an
-    [n, 8] FP32 device tensor, when given) must equal the 4-wide FP32 plain
-    reference bit for bit.  The scenes are freed before returning.
+def autotune_build(scene_arrays, cams, settings, widths=(4, 8, 2), open_pcts=(0,),
+                   schedulers=(SCHED_PERSISTENT,), grid: Optional[dict] = None, reps: int = 2,
+                   build_opts: Optional[dict] = None, rays=None, log=None) -> dict:
+    """Choose the build: the node width and how many top-level entries
+    opening instances adds (rtq_build_opts.open_pct; 0 is the library's
+    default).  The scene (generator arrays) is built once per (width, opening)
+    pair, the quantized-node launches of each are tuned, and the fastest pair
+    is returned with its launch options.  Every build's frames (and closest
+    hits of `rays`, an [n, 8] FP32 device tensor, when given) must equal the
+    4-wide FP32 plain reference bit for bit.  The scenes are freed before
+    returning.
 
-    Returns {"best": {"node_width": w, "opts": {...}, "ms": t}, "widths": {w: {...}}}."""
+    Returns {"best": {"node_width": w, "open_pct": p, "opts": {...}, "ms": t},
+    "builds": {(w, p): {...}}}."""
     import torch
     from . import Scene, trace_closest
     build_opts = dict(build_opts or {})
@@ -181,30 +185,45 @@ def autotune_width(scene_arrays, cams, settings, widths=(4, 8, 2), schedulers=(S
     ref_hits = trace_closest(S4, rays, node_format=RTQ_NODE_FP32, scheduler=SCHED_PLAIN) if rays is not None else None
     torch.cuda.synchronize()
     S4.close()
-    per_width = {}
+    builds = {}
     best = None
     for w in widths:
-        S = Scene(scene_arrays, node_width=w, **build_opts)
-        render(S, cams, settings, images=img, node_format=RTQ_NODE_Q8, scheduler=SCHED_PERSISTENT)
-        torch.cuda.synchronize()
-        if not torch.equal(img.view(torch.int32), ref.view(torch.int32)):
-            raise RuntimeError(f"autotune: node width {w} changed the image")
-        if ref_hits is not None:
-            h = trace_closest(S, rays, node_format=RTQ_NODE_Q8, scheduler=SCHED_PERSISTENT)
+        for pct in open_pcts:
+            S = Scene(scene_arrays, **dict(build_opts, node_width=w, open_pct=pct))
+            render(S, cams, settings, images=img, node_format=RTQ_NODE_Q8, scheduler=SCHED_PERSISTENT)
             torch.cuda.synchronize()
-            for k in ("t", "u", "v", "inst", "prim"):
-                if not torch.equal(getattr(h, k).view(torch.int32), getattr(ref_hits, k).view(torch.int32)):
-                    raise RuntimeError(f"autotune: node width {w} changed the hits ({k})")
-        r = autotune_render(S, cams, settings, formats=(RTQ_NODE_Q8,), schedulers=schedulers, grid=grid, reps=reps,
-                            cache=None, log=log)
-        r.pop("table", None)
-        info = S.info()
-        top = min(r.values(), key=lambda x: x["ms"])
-        per_width[w] = dict(top, nodes=info["tlas_nodes"] + info["blas_nodes"],
-                            depth=[info["tlas_depth"], info["blas_depth_max"]])
-        if log:
-            log(f"autotune width {w}: {per_width[w]}")
-        if best is None or top["ms"] < best["ms"]:
-            best = dict(node_width=w, opts=top["opts"], ms=top["ms"])
-        S.close()
-    return {"best": best, "widths": per_width}
+            if not torch.equal(img.view(torch.int32), ref.view(torch.int32)):
+                raise RuntimeError(f"autotune: node width {w}, opening {pct} changed the image")
+            if ref_hits is not None:
+                h = trace_closest(S, rays, node_format=RTQ_NODE_Q8, scheduler=SCHED_PERSISTENT)
+                torch.cuda.synchronize()
+                for k in ("t", "u", "v", "inst", "prim"):
+                    if not torch.equal(getattr(h, k).view(torch.int32), getattr(ref_hits, k).view(torch.int32)):
+                        raise RuntimeError(f"autotune: node width {w}, opening {pct} changed the hits ({k})")
+            r = autotune_render(S, cams, settings, formats=(RTQ_NODE_Q8,), schedulers=schedulers, grid=grid,
+                                reps=reps, cache=None, log=log)
+            r.pop("table", None)
+            info = S.info()
+            top = min(r.values(), key=lambda x: x["ms"])
+            builds[(w, pct)] = dict(top, nodes=info["tlas_nodes"] + info["blas_nodes"],
+                                    depth=[info["tlas_depth"], info["blas_depth_max"]],
+                                    top_entries=info["n_top_entries"])
+            if log:
+                log(f"autotune width {w}, opening {pct}: {builds[(w, pct)]}")
+            if best is None or top["ms"] < best["ms"]:
+                best = dict(node_width=w, open_pct=pct, opts=top["opts"], ms=top["ms"])
+            S.close()
+    return {"best": best, "builds": builds}
+
+
+def autotune_width(scene_arrays, cams, settings, widths=(4, 8, 2), schedulers=(SCHED_PERSISTENT,),
+                   grid: Optional[dict] = None, reps: int = 2, build_opts: Optional[dict] = None, rays=None,
+                   log=None) -> dict:
+    """autotune_build over node widths at the default opening.
+
+    Returns {"best": {"node_width": w, "opts": {...}, "ms": t}, "widths": {w: {...}}}."""
+    opening = (build_opts or {}).get("open_pct", 0)
+    r = autotune_build(scene_arrays, cams, settings, widths=widths, open_pcts=(opening,), schedulers=schedulers,
+                       grid=grid, reps=reps, build_opts={k: v for k, v in (build_opts or {}).items()
+                                                         if k != "open_pct"}, rays=rays, log=log)
+    return {"best": r["best"], "widths": {w: v for (w, _), v in r["builds"].items()}}

@@ -157,3 +157,18 @@ def test_autotuner_chooses_a_width_at_equal_frames():
     assert set(res["widths"]) == {2, 4, 8}
     assert res["best"]["ms"] == min(v["ms"] for v in res["widths"].values())
     torch.cuda.synchronize()
+
+
+def test_autotuner_chooses_the_opening():
+    """autotune_build also tries top-level openings (none, the default, twice
+    the instance count), keeps the frames bit-identical and returns the
+    fastest pair."""
+    from paper_2001_02620_amd.autotune import autotune_build
+    log("case: build autotuner (opening), config 1")
+    scene, cams, st = sg.config1()
+    grid = {rtq.SCHED_PERSISTENT: dict(stack_depth=[16], waves_per_cu=[24], block=[256], refill=[16])}
+    res = autotune_build(scene, cams, st, widths=(4,), open_pcts=(-1, 0, 200), grid=grid, reps=1, log=log)
+    assert set(res["builds"]) == {(4, -1), (4, 0), (4, 200)}
+    ent = {p: v["top_entries"] for (_, p), v in res["builds"].items()}
+    assert ent[-1] == scene.n_instances and ent[-1] < ent[0] < ent[200]
+    assert res["best"]["ms"] == min(v["ms"] for v in res["builds"].values())
