@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="scene scale (1.0 = the full configuration)")
     ap.add_argument("--curve-instances", type=int, default=100_000, help="tufts of the curve field")
     ap.add_argument("--no-curves", action="store_true")
+    ap.add_argument("--open-area-pct", type=int, default=0,
+                    help="config 3's build: area limit of opened subtrees in percent (0: the library's 150)")
     ap.add_argument("--open-pct", type=int, default=200,
                     help="config 3's build: top-level entries added by opening instances, in percent of the instance "
                          "count (the library's default is 50; at config 3, 25/50/100/200/400 measured 27.0/22.7/"
@@ -359,7 +361,7 @@ def main():
                                                              steps=args.steps, frames=args.steps)}))
         return
     t0 = time.time()
-    S = rtq.Scene(scene, open_pct=args.open_pct)
+    S = rtq.Scene(scene, open_pct=args.open_pct, open_area_pct=args.open_area_pct)
     info = S.info()
     log(f"build: {time.time() - t0:.1f} s, device {info['device_bytes'] / 2**30:.2f} GiB, "
         f"{info['n_top_entries']} top-level entries")

@@ -159,6 +159,9 @@ typedef struct {
   int32_t node_width;    /* children per node at both levels: 2, 4 or 8; 0 = 4.  Widths other
                             than 4 build quantized nodes only (formats 0 or RTQ_NODE_Q8).  Hits
                             do not depend on it. */
+  int32_t open_area_pct; /* an instance subtree is opened only if its children's world boxes
+                            cover at most this percentage of its own box's surface area,
+                            100..1000; 0 = 150.  Hits do not depend on it. */
 } rtq_build_opts;
 
 /*

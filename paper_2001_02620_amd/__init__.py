@@ -47,7 +47,7 @@ class _Insts(ctypes.Structure):
 class _BuildOpts(ctypes.Structure):
     _fields_ = [("formats", ctypes.c_int32), ("leaf_max", ctypes.c_int32), ("sah_bins", ctypes.c_int32),
                 ("build_threads", ctypes.c_int32), ("device", ctypes.c_int32), ("open_pct", ctypes.c_int32),
-                ("node_width", ctypes.c_int32)]
+                ("node_width", ctypes.c_int32), ("open_area_pct", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -177,7 +177,7 @@ class Scene:
     """Built acceleration structures of a generator scene (``scenegen.Scene`` arrays)."""
 
     def __init__(self, s, formats: int = 0, leaf_max: int = 0, sah_bins: int = 0, build_threads: int = 0,
-                 device: int = -1, open_pct: int = 0, node_width: int = 0):
+                 device: int = -1, open_pct: int = 0, node_width: int = 0, open_area_pct: int = 0):
         L = load_library()
         _torch()
         self.n_quads = int(s.quads.shape[0])
@@ -213,7 +213,7 @@ class Scene:
         ip = np.ascontiguousarray(s.inst_proto, dtype=np.int32)
         ix = np.ascontiguousarray(s.inst_xform, dtype=np.float32)
         insts = _Insts(ip.shape[0], ip.ctypes.data, ix.ctypes.data)
-        opts = _BuildOpts(formats, leaf_max, sah_bins, build_threads, device, open_pct, node_width)
+        opts = _BuildOpts(formats, leaf_max, sah_bins, build_threads, device, open_pct, node_width, open_area_pct)
         h = ctypes.c_void_p()
         _check(L.rtq_scene_build(ctypes.cast(protos, ctypes.c_void_p), P, ctypes.byref(insts), ctypes.byref(opts),
                                  ctypes.byref(h)))

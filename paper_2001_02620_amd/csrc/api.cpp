@@ -219,6 +219,8 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
   bp.want_q8 = true;  // the quantized nodes are cheap to derive; keep both topologies identical
   if (bp.leaf_max < 1 || bp.leaf_max > 8) return set_error(RTQ_E_INVALID_ARG, "leaf_max %d outside [1, 8]", bp.leaf_max);
   if (bp.bins < 4 || bp.bins > 64) return set_error(RTQ_E_INVALID_ARG, "sah_bins %d outside [4, 64]", bp.bins);
+  if (o.open_area_pct != 0 && (o.open_area_pct < 100 || o.open_area_pct > 1000))
+    return set_error(RTQ_E_INVALID_ARG, "open_area_pct %d outside [100, 1000]", o.open_area_pct);
   const int64_t N = insts->n;
   if (N > (int64_t)kMaxLeafFirst) return set_error(RTQ_E_LIMIT, "%lld instances exceed 2^28", (long long)N);
 
@@ -546,6 +548,7 @@ static int build_impl(const rtq_prototype* protos, int32_t n_protos, const rtq_i
     }
     OpenParams op;
     const int32_t pct = o.open_pct == 0 ? kDefaultOpenPct : std::max(o.open_pct, 0);
+    if (o.open_area_pct) op.max_ratio = o.open_area_pct / 100.0;
     op.budget = std::min<int64_t>(N * (int64_t)pct / 100, (int64_t)kMaxLeafFirst - N);
     op.threads = nthreads_all;
     entries = open_instances(N, insts->xform, insts->proto, boxes.data(), pad.data(), proto_root, proto_qbase,
