@@ -108,11 +108,22 @@ def philox(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
     return out
 
 
+def _mat8(mat) -> np.ndarray:
+    """Material rows of 8 parameters (tint r, g, b, roughness, metallic,
+    specular, clearcoat, clearcoat roughness); rows of 6 have no clearcoat."""
+    m = np.asarray(mat, dtype=np.float64)
+    if m.shape[-1] == 6:
+        m = np.concatenate([m, np.zeros(m.shape[:-1] + (2,))], axis=-1)
+    assert m.shape[-1] == 8, m.shape
+    return np.ascontiguousarray(m)
+
+
 def bsdf_eval(mat, n, wo, wi):
     """The oracle's BSDF at one frame (tests): mat = (tint r, g, b, roughness,
-    metallic, specular), unit n and wo, directions wi [k, 3].  Returns [k, 4]:
-    (A, B, pdf, P_s) with f mu_i = A + B c for base color c."""
-    m = np.ascontiguousarray(mat, dtype=np.float64)
+    metallic, specular[, clearcoat, clearcoat roughness]), unit n and wo,
+    directions wi [k, 3].  Returns [k, 4]: (A, B, pdf, Pn) with f mu_i = A + B c
+    for base color c, Pn the probability of a specular or coat lobe."""
+    m = _mat8(mat)
     nn = np.ascontiguousarray(n, dtype=np.float64)
     o = np.ascontiguousarray(wo, dtype=np.float64)
     w = np.ascontiguousarray(np.asarray(wi, dtype=np.float64).reshape(-1, 3))
@@ -123,15 +134,16 @@ def bsdf_eval(mat, n, wo, wi):
 
 def bsdf_sample(mat, n, wo, u):
     """Sampled bounce directions for lobe and direction words u [k, 3] in [0, 1):
-    (directions [k, 3], specular chosen [k], lobe word within rounding [k])."""
-    m = np.ascontiguousarray(mat, dtype=np.float64)
+    (directions [k, 3], lobe [k] (0 cosine, 1 specular, 2 coat), lobe word
+    within rounding of a threshold [k])."""
+    m = _mat8(mat)
     nn = np.ascontiguousarray(n, dtype=np.float64)
     o = np.ascontiguousarray(wo, dtype=np.float64)
     uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1, 3))
     wi = np.zeros_like(uu)
     info = np.zeros((uu.shape[0], 2), np.int32)
     lib().orc_bsdf_sample(_p(m), _p(nn), _p(o), uu.shape[0], _p(uu), _p(wi), _p(info))
-    return wi, info[:, 0].astype(bool), info[:, 1].astype(bool)
+    return wi, info[:, 0].copy(), info[:, 1].astype(bool)
 
 
 @dataclass
@@ -200,15 +212,17 @@ class OracleScene:
         return self.n_quads * (self.tex_res * self.tex_res if self.tex_res > 0 else 1)
 
     def set_materials(self, mats: Optional[np.ndarray], face_mat: Optional[np.ndarray] = None) -> None:
-        """Principled materials: [n_mat, 6] rows (tint r, g, b, roughness,
-        metallic, specular; FP32 values read exactly) and one material index per
+        """Principled materials: [n_mat, 6] or [n_mat, 8] rows (tint r, g, b,
+        roughness, metallic, specular[, clearcoat, clearcoat roughness]; FP32
+        values read exactly; 6 columns: no clearcoat) and one material index per
         face; None returns to Lambertian faces.  With materials, images and
         gradient weights have three channels."""
         if mats is None:
             assert lib().orc_scene_set_materials(self.h, None, 0, None) == 0
             self.rgb = False
             return
-        m = np.ascontiguousarray(np.asarray(mats, dtype=np.float32).reshape(-1, 6), dtype=np.float64)
+        m32 = np.asarray(mats, dtype=np.float32)
+        m = _mat8(m32.reshape(-1, m32.shape[-1]).astype(np.float64))
         f = np.ascontiguousarray(face_mat, dtype=np.int32)
         assert f.shape == (self.n_quads,)
         assert lib().orc_scene_set_materials(self.h, _p(m), int(m.shape[0]), _p(f)) == 0

@@ -79,6 +79,7 @@ enum : uint32_t {
 struct Material {
   double tint[3];
   double alpha, metal, spec;
+  double coat = 0.0, calpha = 0.0;  // clearcoat weight and the coat's GGX alpha
 };
 
 struct Box {
@@ -1196,10 +1197,21 @@ inline C3 operator*(double s, C3 a) {
 // depend on c, so a path's directions do not depend on the albedo), the cosine
 // lobe otherwise; the weight of a sampled direction is f mu_i / pdf with
 // pdf = P_s p_s + (1 - P_s) mu_i / pi.  f mu_i = A + B c is affine in c.
+//
+// A clearcoat of weight k (the principled model's coat layer) lies over that
+// base: a second mirrored visible-normal lobe p_k of its own roughness with the
+// Fresnel weight F_k = k (F0 + (1 - F0)(1 - mu_o)^5), and the base below it
+// receives what the coat does not reflect:
+//   f mu_i = F_k p_k(wi) + (1 - F_k) [base f mu_i],
+// so the albedo is F_k + (1 - F_k) [base albedo]: still at most one, and one
+// for c = 1.  The coat lobe is drawn with probability F_k, the base's lobes
+// with the rest; the density is F_k p_k + (1 - F_k) [base density].  k = 0 is
+// the base alone.
 struct Shade {
   V3 n, wo, t1, t2;  // frame: t1, t2 the basis of Duff et al. 2017 about n
   double mo;         // n . wo
   double alpha, metal, Fd, k5, Ps;
+  double calpha, Fk, Pn;  // the coat's alpha and weight F_k; Pn = F_k + (1 - F_k) P_s, a non-diffuse lobe's probability
   C3 tint;
 };
 
@@ -1231,6 +1243,9 @@ Shade make_shade(const Material& M, V3 n, V3 wo, bool flip) {
   s.metal = M.metal;
   s.Fd = M.spec * (0.04 + 0.96 * s.k5);
   s.Ps = (1.0 - M.metal) * s.Fd + M.metal;
+  s.calpha = M.calpha;
+  s.Fk = M.coat * (0.04 + 0.96 * s.k5);
+  s.Pn = s.Fk + (1.0 - s.Fk) * s.Ps;
   for (int k = 0; k < 3; ++k) s.tint.v[k] = M.tint[k];
   return s;
 }
@@ -1238,15 +1253,15 @@ Shade make_shade(const Material& M, V3 n, V3 wo, bool flip) {
 // density of the folded specular lobe toward wi (mu_i > 0): each preimage
 // direction (the reflection itself and, when mu_o > mu_i, its mirror below the
 // surface) contributes G1(mu_o) D(h) / (4 mu_o), h the half vector
-double spec_pdf(const Shade& s, V3 wi) {
+double spec_pdf(const Shade& s, double alpha, V3 wi) {
   const double mi = dot(s.n, wi);
   if (!(mi > 0.0) || !(s.mo > 0.0)) return 0.0;
-  const double g = smith_G1(s.alpha, s.mo) / (4.0 * s.mo);
+  const double g = smith_G1(alpha, s.mo) / (4.0 * s.mo);
   const V3 h1 = normalize(s.wo + wi);
-  double p = g * ggx_D(s.alpha, dot(s.n, h1));
+  double p = g * ggx_D(alpha, dot(s.n, h1));
   if (s.mo > mi) {
     const V3 h2 = normalize(s.wo + (wi - 2.0 * mi * s.n));
-    p += g * ggx_D(s.alpha, dot(s.n, h2));
+    p += g * ggx_D(alpha, dot(s.n, h2));
   }
   return p;
 }
@@ -1256,24 +1271,29 @@ bool eval_AB(const Shade& s, V3 wi, double* A, double* B) {
   const double mi = dot(s.n, wi);
   *A = *B = 0.0;
   if (!(mi > 0.0)) return false;
-  const double ps = s.Ps > 0.0 ? spec_pdf(s, wi) : 0.0;
+  const double ps = s.Ps > 0.0 ? spec_pdf(s, s.alpha, wi) : 0.0;
   *A = ((1.0 - s.metal) * s.Fd + s.metal * s.k5) * ps;
   *B = (1.0 - s.metal) * (1.0 - s.Fd) * mi / kPi + s.metal * (1.0 - s.k5) * ps;
+  if (s.Fk > 0.0) {
+    *A = s.Fk * spec_pdf(s, s.calpha, wi) + (1.0 - s.Fk) * *A;
+    *B = (1.0 - s.Fk) * *B;
+  }
   return true;
 }
 
 double bsdf_pdf(const Shade& s, V3 wi) {
   const double mi = dot(s.n, wi);
   if (!(mi > 0.0)) return 0.0;
-  return (s.Ps > 0.0 ? s.Ps * spec_pdf(s, wi) : 0.0) + (1.0 - s.Ps) * mi / kPi;
+  const double base = (s.Ps > 0.0 ? s.Ps * spec_pdf(s, s.alpha, wi) : 0.0) + (1.0 - s.Ps) * mi / kPi;
+  return s.Fk > 0.0 ? s.Fk * spec_pdf(s, s.calpha, wi) + (1.0 - s.Fk) * base : base;
 }
 
 // A GGX visible normal for wo from (u1, u2) (Heitz 2018, "Sampling the GGX
 // distribution of visible normals"), in the world frame of s.
-V3 sample_vndf(const Shade& s, double u1, double u2) {
+V3 sample_vndf(const Shade& s, double alpha, double u1, double u2) {
   const double ox = dot(s.wo, s.t1), oy = dot(s.wo, s.t2), oz = s.mo;
   // stretch to the hemisphere configuration
-  const V3 vh = normalize(V3{s.alpha * ox, s.alpha * oy, oz});
+  const V3 vh = normalize(V3{alpha * ox, alpha * oy, oz});
   const double l2 = vh.x * vh.x + vh.y * vh.y;
   const V3 T1 = l2 > 0.0 ? (1.0 / std::sqrt(l2)) * V3{-vh.y, vh.x, 0.0} : V3{1.0, 0.0, 0.0};
   const V3 T2 = cross(vh, T1);
@@ -1284,19 +1304,24 @@ V3 sample_vndf(const Shade& s, double u1, double u2) {
   p2 = (1.0 - sw) * std::sqrt(std::max(0.0, 1.0 - p1 * p1)) + sw * p2;
   const V3 nh = p1 * T1 + p2 * T2 + std::sqrt(std::max(0.0, 1.0 - p1 * p1 - p2 * p2)) * vh;
   // unstretch
-  const V3 hl = normalize(V3{s.alpha * nh.x, s.alpha * nh.y, std::max(0.0, nh.z)});
+  const V3 hl = normalize(V3{alpha * nh.x, alpha * nh.y, std::max(0.0, nh.z)});
   return hl.x * s.t1 + hl.y * s.t2 + hl.z * s.n;
 }
 
-// Direction of the bounce from the lobe word u0 and (u1, u2): the specular
-// lobe when u0 < P_s (reflection about a visible normal, mirrored above the
-// surface when below it), else the cosine lobe.  *ambiguous is set when u0 lies
-// within 1e-6 of P_s (FP32 may choose the other lobe).
-V3 sample_bsdf(const Shade& s, double u0, double u1, double u2, bool* spec, bool* ambiguous) {
-  *spec = u0 < s.Ps;
-  if (ambiguous) *ambiguous = s.Ps > 0.0 && std::fabs(u0 - s.Ps) < 1e-6;
-  if (*spec) {
-    const V3 h = sample_vndf(s, u1, u2);
+// Lobes of the mixture: 0 the cosine lobe, 1 the base's specular lobe, 2 the coat.
+enum { kLobeDiffuse = 0, kLobeSpec = 1, kLobeCoat = 2 };
+
+// Direction of the bounce from the lobe word u0 and (u1, u2): the coat when
+// u0 < F_k, the specular lobe when F_k <= u0 < Pn (each a reflection about a
+// visible normal of its roughness, mirrored above the surface when below it),
+// else the cosine lobe.  *ambiguous is set when u0 lies within 1e-6 of a
+// threshold (FP32 may choose the neighbouring lobe).
+V3 sample_bsdf(const Shade& s, double u0, double u1, double u2, int* lobe, bool* ambiguous) {
+  *lobe = u0 < s.Fk ? kLobeCoat : (u0 < s.Pn ? kLobeSpec : kLobeDiffuse);
+  if (ambiguous)
+    *ambiguous = (s.Fk > 0.0 && std::fabs(u0 - s.Fk) < 1e-6) || (s.Pn > 0.0 && std::fabs(u0 - s.Pn) < 1e-6);
+  if (*lobe != kLobeDiffuse) {
+    const V3 h = sample_vndf(s, *lobe == kLobeCoat ? s.calpha : s.alpha, u1, u2);
     V3 wi = 2.0 * dot(s.wo, h) * h - s.wo;
     const double mi = dot(s.n, wi);
     if (mi < 0.0) wi = wi - 2.0 * mi * s.n;
@@ -1304,6 +1329,13 @@ V3 sample_bsdf(const Shade& s, double u0, double u1, double u2, bool* spec, bool
   }
   const double rr = std::sqrt(u1), phi = 2.0 * kPi * u2;
   return (rr * std::cos(phi)) * s.t1 + (rr * std::sin(phi)) * s.t2 + std::sqrt(1.0 - u1) * s.n;
+}
+
+// A lobe word inside lobe l's interval, or -1 when l has probability 0.
+double lobe_word(const Shade& s, int l) {
+  if (l == kLobeCoat) return s.Fk > 0.0 ? 0.0 : -1.0;
+  if (l == kLobeSpec) return s.Pn > s.Fk ? 0.5 * (s.Fk + s.Pn) : -1.0;
+  return s.Pn < 1.0 ? 1.0 : -1.0;
 }
 
 // The material of a face (the Lambertian default without a table).
@@ -1600,16 +1632,17 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       rec.v[rec.nv - 1].flags |= F_SHADE;
     }
     // the lobe: word 0 of counter (pixel, sample, view, 2^30 + b), drawn only
-    // when the specular lobe has weight
+    // when a specular or coat lobe has weight
     double u0 = 1.0;
-    if (sh.Ps > 0.0) {
+    if (sh.Pn > 0.0) {
       uint32_t ctr4[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x40000000u | (uint32_t)b};
       uint32_t wlob[4];
       philox(ctr4, key, wlob);
       u0 = unit(wlob[0]);
     }
-    bool spec = false, amb = false;
-    const V3 dnew = sample_bsdf(sh, u0, u1, u2, &spec, &amb);
+    int lobe = 0;
+    bool amb = false;
+    const V3 dnew = sample_bsdf(sh, u0, u1, u2, &lobe, &amb);
     if (amb) {
       rec.flags |= F_SHADE;
       rec.v[rec.nv - 1].flags |= F_SHADE;
@@ -1970,30 +2003,41 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     uint32_t ctr2[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, (uint32_t)k};
     philox(ctr2, key, w2);
     double u0 = 1.0;
-    if (sh.Ps > 0.0) {
+    if (sh.Pn > 0.0) {
       uint32_t ctr4[4] = {(uint32_t)pix, (uint32_t)sample, (uint32_t)view, 0x40000000u | (uint32_t)k};
       uint32_t wlob[4];
       philox(ctr4, key, wlob);
       u0 = unit(wlob[0]);
     }
-    // the sampled direction, for either lobe when the lobe word lies within
-    // rounding of P_s, and for either basis branch when n_z ~ 0
-    bool spec, amb;
-    double err = norm(nr.d - sample_bsdf(sh, u0, unit(w2[2]), unit(w2[3]), &spec, &amb));
-    if (dn_unc > 0.0 && sh.Ps > 0.0) {
-      // the lobe choice u0 < P_s is ambiguous within P_s's spread as well
-      double dps = 0.0;
-      for (int q = 0; q < 4; ++q) dps = std::max(dps, std::fabs(turned_shade(q).Ps - sh.Ps));
-      amb = amb || std::fabs(u0 - sh.Ps) < 1e-6 + 2.0 * dps;
+    // the sampled direction, for every lobe when the lobe word lies within
+    // rounding of a threshold, and for either basis branch when n_z ~ 0
+    int lobe;
+    bool amb;
+    double err = norm(nr.d - sample_bsdf(sh, u0, unit(w2[2]), unit(w2[3]), &lobe, &amb));
+    if (dn_unc > 0.0 && sh.Pn > 0.0) {
+      // the lobe thresholds F_k and Pn are uncertain within their spread as well
+      double dfk = 0.0, dpn = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const Shade sq = turned_shade(q);
+        dfk = std::max(dfk, std::fabs(sq.Fk - sh.Fk));
+        dpn = std::max(dpn, std::fabs(sq.Pn - sh.Pn));
+      }
+      amb = amb || (sh.Fk > 0.0 && std::fabs(u0 - sh.Fk) < 1e-6 + 2.0 * dfk) ||
+            std::fabs(u0 - sh.Pn) < 1e-6 + 2.0 * dpn;
     }
     if (amb) {
       R.n_ambiguous_shading++;
-      err = std::min(err, norm(nr.d - sample_bsdf(sh, spec ? 1.0 : 0.0, unit(w2[2]), unit(w2[3]), &spec, nullptr)));
+      for (int l = 0; l < 3; ++l) {
+        const double ul = lobe_word(sh, l);
+        int ll;
+        if (l != lobe && ul >= 0.0)
+          err = std::min(err, norm(nr.d - sample_bsdf(sh, ul, unit(w2[2]), unit(w2[3]), &ll, nullptr)));
+      }
     }
     if (std::fabs(n.z) < 1e-6) {
       R.n_ambiguous_shading++;
       const Shade sf = make_shade(M, n, -1.0 * dh, true);
-      err = std::min(err, norm(nr.d - sample_bsdf(sf, u0, unit(w2[2]), unit(w2[3]), &spec, nullptr)));
+      err = std::min(err, norm(nr.d - sample_bsdf(sf, u0, unit(w2[2]), unit(w2[3]), &lobe, nullptr)));
     }
     // a direction sampled about a normal turned by dn_unc turns by up to about
     // twice that (the specular lobe reflects about the microfacet normal)
@@ -2103,6 +2147,10 @@ void resolve_pixel(const std::vector<Cam>& cams, int64_t g, int32_t* cam, int64_
   *cam = -1;
   *pix = -1;
 }
+
+// A material from its 8 parameters (tint r, g, b, roughness, metallic,
+// specular, clearcoat, clearcoat roughness).
+Material material_of(const double* m) { return Material{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5], m[6], m[7] * m[7]}; }
 
 }  // namespace
 
@@ -2218,35 +2266,36 @@ void* orc_scene_create(const float* verts, int64_t n_verts, const int32_t* quads
 
 void orc_scene_destroy(void* s) { delete static_cast<Scene*>(s); }
 
-// The BSDF at one shading frame, for tests: material m (tint r, g, b,
-// roughness, metallic, specular), unit normal n, unit direction to the viewer
-// wo.  For each of n directions wi (n x 3) writes (A, B, pdf, P_s): f mu_i =
-// A + B c, the sampling density and the specular lobe's probability.
+// The BSDF at one shading frame, for tests: material m (8 parameters), unit
+// normal n, unit direction to the viewer wo.  For each of n directions wi
+// (n x 3) writes (A, B, pdf, Pn): f mu_i = A + B c, the sampling density and the
+// probability of a specular or coat lobe.
 void orc_bsdf_eval(const double* m, const double* nrm, const double* wo, int64_t n, const double* wi, double* out) {
-  const Material M{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5]};
+  const Material M = material_of(m);
   const Shade sh = make_shade(M, V3{nrm[0], nrm[1], nrm[2]}, V3{wo[0], wo[1], wo[2]}, false);
   for (int64_t i = 0; i < n; ++i) {
     const V3 w{wi[3 * i], wi[3 * i + 1], wi[3 * i + 2]};
     eval_AB(sh, w, &out[4 * i], &out[4 * i + 1]);
     out[4 * i + 2] = bsdf_pdf(sh, w);
-    out[4 * i + 3] = sh.Ps;
+    out[4 * i + 3] = sh.Pn;
   }
 }
 
 // Sampled bounce directions for (u0, u1, u2) triples (n x 3): writes the
-// direction (n x 3) and, per sample, (specular lobe chosen, lobe word within
-// rounding of P_s).
+// direction (n x 3) and, per sample, (lobe: 0 cosine, 1 specular, 2 coat; lobe
+// word within rounding of a threshold).
 void orc_bsdf_sample(const double* m, const double* nrm, const double* wo, int64_t n, const double* u, double* wi,
                      int32_t* info) {
-  const Material M{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5]};
+  const Material M = material_of(m);
   const Shade sh = make_shade(M, V3{nrm[0], nrm[1], nrm[2]}, V3{wo[0], wo[1], wo[2]}, false);
   for (int64_t i = 0; i < n; ++i) {
-    bool spec, amb;
-    const V3 d = sample_bsdf(sh, u[3 * i], u[3 * i + 1], u[3 * i + 2], &spec, &amb);
+    int lobe;
+    bool amb;
+    const V3 d = sample_bsdf(sh, u[3 * i], u[3 * i + 1], u[3 * i + 2], &lobe, &amb);
     wi[3 * i] = d.x;
     wi[3 * i + 1] = d.y;
     wi[3 * i + 2] = d.z;
-    info[2 * i] = spec ? 1 : 0;
+    info[2 * i] = lobe;
     info[2 * i + 1] = amb ? 1 : 0;
   }
 }
@@ -2274,10 +2323,7 @@ int orc_scene_set_materials(void* s, const double* mats, int32_t n_mat, const in
   S->mats.clear();
   S->face_mat.clear();
   if (n_mat == 0) return 0;
-  for (int32_t k = 0; k < n_mat; ++k) {
-    const double* m = mats + 6 * k;
-    S->mats.push_back(Material{{m[0], m[1], m[2]}, m[3] * m[3], m[4], m[5]});
-  }
+  for (int32_t k = 0; k < n_mat; ++k) S->mats.push_back(material_of(mats + 8 * k));
   S->face_mat.assign(face_mat, face_mat + S->albedo.size());
   for (int32_t f : S->face_mat)
     if (f < 0 || f >= n_mat) return -1;
