@@ -268,10 +268,16 @@ int rtq_scene_set_environment(rtq_scene* scene, const float* texels_dev, int32_t
  * direction reflected about a GGX visible normal (alpha = roughness^2, separable
  * Smith masking, Heitz 2018), a reflection below the surface mirrored above it.
  * The albedo is (1 - m)[F_d + (1 - F_d) c] + m F_c: one for c = 1, at most one
- * otherwise; metallic = specular = 0 is Lambert's c / pi.  Bounces draw the
- * specular lobe with probability (1 - m) F_d + m (word 0 of Philox counter
- * (pixel, sample, view, 2^30 + bounce)), the cosine lobe otherwise, and weigh
- * the direction by f mu_i over the mixture's density.  With materials every
+ * otherwise; metallic = specular = 0 is Lambert's c / pi.  A clearcoat of weight
+ * k (the principled model's coat layer) lies over that base: a second such lobe
+ * p_k of its own roughness with the Fresnel weight F_k = k (0.04 + 0.96
+ * (1 - mu_o)^5), the base keeping the rest,
+ *   f mu_i = F_k p_k + (1 - F_k) [base f mu_i],
+ * albedo F_k + (1 - F_k) [base albedo]; clearcoat = 0 is the base alone.  Bounces
+ * draw, from word 0 u of Philox counter (pixel, sample, view, 2^30 + bounce),
+ * the coat when u < F_k, the base's specular lobe when u < F_k + (1 - F_k) P_s
+ * with P_s = (1 - m) F_d + m, the cosine lobe otherwise, and weigh the
+ * direction by f mu_i over the mixture's density.  With materials every
  * path carries three channels: images and image gradients hold 3 floats per
  * pixel (interleaved RGB) and rtq_render_opts.channels must be 3.  Lights stay
  * white.
@@ -281,14 +287,15 @@ int rtq_scene_set_environment(rtq_scene* scene, const float* texels_dev, int32_t
  * into memory the scene owns).  n_mat = 0 (both may be NULL) removes the materials.  Waits for
  * all work on the device, then copies synchronously.
  * Errors: RTQ_E_INVALID_ARG for n_mat outside [0, RTQ_MAX_MATERIALS], NULL
- * arrays, a tint outside [0, 1], roughness outside [0.05, 1], metallic or
- * specular outside [0, 1], or a face index >= n_mat; RTQ_E_HIP when the
- * allocation or copy fails.
+ * arrays, a tint outside [0, 1], roughness outside [0.05, 1], metallic,
+ * specular or clearcoat outside [0, 1], a clearcoat roughness outside
+ * [0.05, 1] where clearcoat > 0 (it is ignored where clearcoat = 0), or a face
+ * index >= n_mat; RTQ_E_HIP when the allocation or copy fails.
  */
 typedef struct {
   float tint[3];
   float roughness, metallic, specular;
-  float pad[2];
+  float clearcoat, clearcoat_roughness;
 } rtq_material;
 #define RTQ_MAX_MATERIALS 256
 int rtq_scene_set_materials(rtq_scene* scene, const rtq_material* mats, int32_t n_mat, const uint8_t* face_mat_dev,

@@ -95,7 +95,7 @@ class _RenderOpts(ctypes.Structure):
 
 class _Material(ctypes.Structure):
     _fields_ = [("tint", ctypes.c_float * 3), ("roughness", ctypes.c_float), ("metallic", ctypes.c_float),
-                ("specular", ctypes.c_float), ("pad", ctypes.c_float * 2)]
+                ("specular", ctypes.c_float), ("clearcoat", ctypes.c_float), ("clearcoat_roughness", ctypes.c_float)]
 
 
 # ----------------------------------------------------------------------------- loading
@@ -258,20 +258,26 @@ class Scene:
 
     def set_materials(self, mats, face_mat=None) -> None:
         """Principled materials: rows (tint r, g, b, roughness, metallic,
-        specular) and one material index per unique face (uint8, device tensor
-        or host array); None removes them.  With materials, images and image
-        gradients have three channels per pixel (interleaved RGB)."""
+        specular[, clearcoat, clearcoat roughness]; rows of 6 have no coat) and
+        one material index per unique face (uint8, device tensor or host
+        array); None removes them.  With materials, images and image gradients
+        have three channels per pixel (interleaved RGB)."""
         L = load_library()
         if mats is None:
             _check(L.rtq_scene_set_materials(self.handle, None, 0, None, _stream()))
             self.rgb = False
             return
         torch = _torch()
-        m = np.asarray(mats, dtype=np.float32).reshape(-1, 6)
+        m = np.asarray(mats, dtype=np.float32)
+        m = m.reshape(-1, m.shape[-1])
+        if m.shape[1] not in (6, 8):
+            raise ValueError(f"material rows have 6 or 8 parameters, not {m.shape[1]}")
         arr = (_Material * m.shape[0])()
         for k, row in enumerate(m):
             arr[k].tint[:] = [float(x) for x in row[:3]]
             arr[k].roughness, arr[k].metallic, arr[k].specular = (float(x) for x in row[3:6])
+            if m.shape[1] == 8:
+                arr[k].clearcoat, arr[k].clearcoat_roughness = float(row[6]), float(row[7])
         fm = face_mat if isinstance(face_mat, torch.Tensor) else torch.from_numpy(
             np.ascontiguousarray(face_mat, dtype=np.uint8))
         fm = fm.to(device="cuda", dtype=torch.uint8).contiguous()

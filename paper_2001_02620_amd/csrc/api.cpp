@@ -714,7 +714,8 @@ int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_ma
   for (int32_t k = 0; k < n_mat; ++k) {
     const rtq_material& m = mats[k];
     if (!in01(m.tint[0]) || !in01(m.tint[1]) || !in01(m.tint[2]) || !(m.roughness >= 0.05f && m.roughness <= 1.0f) ||
-        !in01(m.metallic) || !in01(m.specular))
+        !in01(m.metallic) || !in01(m.specular) || !in01(m.clearcoat) ||
+        (m.clearcoat > 0.0f && !(m.clearcoat_roughness >= 0.05f && m.clearcoat_roughness <= 1.0f)))
       return set_error(RTQ_E_INVALID_ARG, "material %d: parameter outside its range", k);
     md[k].tint[0] = m.tint[0];
     md[k].tint[1] = m.tint[1];
@@ -722,7 +723,8 @@ int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_ma
     md[k].alpha = m.roughness * m.roughness;
     md[k].metal = m.metallic;
     md[k].spec = m.specular;
-    md[k].pad[0] = md[k].pad[1] = 0.0f;
+    md[k].coat = m.clearcoat;
+    md[k].calpha = m.clearcoat > 0.0f ? m.clearcoat_roughness * m.clearcoat_roughness : 0.0f;
   }
   hipError_t e = hipSetDevice(s->device);
   if (e != hipSuccess) return hip_error(e, "hipSetDevice");

@@ -32,11 +32,12 @@ struct CamDev {
 // A principled material (Section 5.4: the scene's materials use Disney's
 // principled BSDF, made energy conserving and preserving): base color
 // c = tint x (the face's albedo or texel), alpha = roughness^2 (GGX), metallic,
-// and specular, which scales the dielectric Fresnel reflectance.
+// and specular, which scales the dielectric Fresnel reflectance; a clearcoat of
+// weight coat and GGX alpha calpha over that base.
 struct MatDev {
   float tint[3];
   float alpha, metal, spec;
-  float pad[2];
+  float coat, calpha;
 };
 
 struct RenderParams {
@@ -426,11 +427,17 @@ __device__ __forceinline__ void cosine_dir(float nx, float ny, float nz, float u
 // for a white base (energy preserving), below one otherwise (conserving).  The
 // specular lobe is drawn with probability P_s = (1 - m) F_d + m, independent of
 // c; the density of a direction is P_s p_s + (1 - P_s) mu_i / pi.
+// A clearcoat of weight k adds a second such lobe p_k with the coat's roughness
+// and Fresnel weight F_k = k (0.04 + 0.96 (1 - mu_o)^5) over the base, which
+// keeps the rest: f mu_i = F_k p_k + (1 - F_k) [base], albedo F_k + (1 - F_k)
+// [base albedo].  The coat is drawn with probability F_k, the base's lobes with
+// the rest; k = 0 is the base alone, bit for bit.
 struct PShade {
   float nx, ny, nz;           // normal
   float ox, oy, oz;           // unit direction to the viewer
   float t1x, t1y, t1z, t2x, t2y, t2z;  // basis of Duff et al. 2017 about n
   float mo, alpha, metal, Fd, k5, Ps;
+  float calpha, Fk, Pn;       // the coat's alpha and weight; Pn = F_k + (1 - F_k) P_s
   float tint[3];
 };
 
@@ -460,6 +467,9 @@ __device__ __forceinline__ PShade make_pshade(const MatDev& m, const Shade& s, c
   p.metal = m.metal;
   p.Fd = m.spec * (0.04f + 0.96f * p.k5);
   p.Ps = (1.0f - m.metal) * p.Fd + m.metal;
+  p.calpha = m.calpha;
+  p.Fk = m.coat * (0.04f + 0.96f * p.k5);
+  p.Pn = p.Fk + (1.0f - p.Fk) * p.Ps;
   p.tint[0] = m.tint[0];
   p.tint[1] = m.tint[1];
   p.tint[2] = m.tint[2];
@@ -477,8 +487,8 @@ __device__ __forceinline__ float smith_G1(float alpha, float mu) {
   return 2.0f * mu / (mu + sqrtf(alpha * alpha + (1.0f - alpha * alpha) * mu * mu));
 }
 // D of the half vector of unit directions a and b about n
-__device__ __forceinline__ float ggx_D_half(const PShade& p, float ax, float ay, float az, float bx, float by,
-                                            float bz) {
+__device__ __forceinline__ float ggx_D_half(const PShade& p, float alpha, float ax, float ay, float az, float bx,
+                                            float by, float bz) {
   float hx = ax + bx, hy = ay + by, hz = az + bz;
   const float inv = 1.0f / sqrtf(hx * hx + hy * hy + hz * hz);
   hx *= inv;
@@ -486,18 +496,18 @@ __device__ __forceinline__ float ggx_D_half(const PShade& p, float ax, float ay,
   hz *= inv;
   const float c = p.nx * hx + p.ny * hy + p.nz * hz;
   const float cx = p.ny * hz - p.nz * hy, cy = p.nz * hx - p.nx * hz, cz = p.nx * hy - p.ny * hx;
-  return ggx_D(p.alpha, c, cx * cx + cy * cy + cz * cz);
+  return ggx_D(alpha, c, cx * cx + cy * cy + cz * cz);
 }
 
-// density of the mirrored specular lobe toward unit wi
-__device__ __forceinline__ float spec_pdf(const PShade& p, float wx, float wy, float wz) {
+// density of a mirrored visible-normal lobe of GGX alpha toward unit wi
+__device__ __forceinline__ float spec_pdf(const PShade& p, float alpha, float wx, float wy, float wz) {
   const float mi = p.nx * wx + p.ny * wy + p.nz * wz;
   if (!(mi > 0.0f) || !(p.mo > 0.0f)) return 0.0f;
-  const float g = smith_G1(p.alpha, p.mo) / (4.0f * p.mo);
-  float pdf = g * ggx_D_half(p, p.ox, p.oy, p.oz, wx, wy, wz);
+  const float g = smith_G1(alpha, p.mo) / (4.0f * p.mo);
+  float pdf = g * ggx_D_half(p, alpha, p.ox, p.oy, p.oz, wx, wy, wz);
   if (p.mo > mi) {
     const float mx = wx - 2.0f * mi * p.nx, my = wy - 2.0f * mi * p.ny, mz = wz - 2.0f * mi * p.nz;
-    pdf += g * ggx_D_half(p, p.ox, p.oy, p.oz, mx, my, mz);
+    pdf += g * ggx_D_half(p, alpha, p.ox, p.oy, p.oz, mx, my, mz);
   }
   return pdf;
 }
@@ -511,21 +521,28 @@ __device__ __forceinline__ void pbsdf_eval(const PShade& p, float wx, float wy, 
     *A = *B = *pdf = 0.0f;
     return;
   }
-  const float ps = p.Ps > 0.0f ? spec_pdf(p, wx, wy, wz) : 0.0f;
+  const float ps = p.Ps > 0.0f ? spec_pdf(p, p.alpha, wx, wy, wz) : 0.0f;
   *A = ((1.0f - p.metal) * p.Fd + p.metal * p.k5) * ps;
   *B = (1.0f - p.metal) * (1.0f - p.Fd) * mi / kPiF + p.metal * (1.0f - p.k5) * ps;
   *pdf = (p.Ps > 0.0f ? p.Ps * ps : 0.0f) + (1.0f - p.Ps) * mi / kPiF;
+  if (p.Fk > 0.0f) {
+    const float pk = spec_pdf(p, p.calpha, wx, wy, wz);
+    *A = p.Fk * pk + (1.0f - p.Fk) * *A;
+    *B = (1.0f - p.Fk) * *B;
+    *pdf = p.Fk * pk + (1.0f - p.Fk) * *pdf;
+  }
 }
 
 // Bounce direction from the lobe word u0 and (u1, u2): a GGX visible normal
 // (Heitz 2018: stretch wo by alpha, sample the projected half disk, unstretch)
-// and the reflection about it, mirrored above the surface, when u0 < P_s; the
-// cosine lobe otherwise.
+// and the reflection about it, mirrored above the surface, when u0 < Pn -- of
+// the coat's alpha when u0 < F_k, else of the base's; the cosine lobe
+// otherwise.
 __device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1, float u2, float* dx, float* dy,
                                              float* dz) {
   float sn, cs;
   sincospif(2.0f * u2, &sn, &cs);
-  if (!(u0 < p.Ps)) {
+  if (!(u0 < p.Pn)) {
     const float rr = sqrtf(u1);
     const float lx = rr * cs, ly = rr * sn, lz = sqrtf(1.0f - u1);
     *dx = lx * p.t1x + ly * p.t2x + lz * p.nx;
@@ -533,9 +550,10 @@ __device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1
     *dz = lx * p.t1z + ly * p.t2z + lz * p.nz;
     return;
   }
+  const float alpha = u0 < p.Fk ? p.calpha : p.alpha;
   const float olx = p.ox * p.t1x + p.oy * p.t1y + p.oz * p.t1z;
   const float oly = p.ox * p.t2x + p.oy * p.t2y + p.oz * p.t2z;
-  float vx = p.alpha * olx, vy = p.alpha * oly, vz = p.mo;
+  float vx = alpha * olx, vy = alpha * oly, vz = p.mo;
   const float iv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
   vx *= iv;
   vy *= iv;
@@ -564,7 +582,7 @@ __device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1
   const float nhx = p1 * T1x + p2 * T2x + pz * vx;
   const float nhy = p1 * T1y + p2 * T2y + pz * vy;
   const float nhz = p2 * T2z + pz * vz;
-  float hx = p.alpha * nhx, hy = p.alpha * nhy, hz = fmaxf(0.0f, nhz);
+  float hx = alpha * nhx, hy = alpha * nhy, hz = fmaxf(0.0f, nhz);
   const float ih = 1.0f / sqrtf(hx * hx + hy * hy + hz * hz);
   hx *= ih;
   hy *= ih;
@@ -613,7 +631,7 @@ __device__ __forceinline__ void pnee_estimate(const PShade& p, const float c[3],
 }
 
 // Principled bounce after hit b: the lobe word (word 0 of counter (pixel,
-// sample, view, 2^30 + b), drawn only when the specular lobe has weight), the
+// sample, view, 2^30 + b), drawn only when a specular or coat lobe has weight), the
 // direction from words 2, 3 of counter (pixel, sample, view, b), its weight
 // w_k = (A + B c_k) / pdf per channel and derivative w1_k = B tint_k / pdf.
 // Returns the density (0: the direction lies on the surface and the path ends).
@@ -622,7 +640,7 @@ __device__ __forceinline__ float pbsdf_bounce(const RenderParams& rp, const PSha
                                               float* dy, float* dz, float w[3], float w1[3]) {
   const uint4 wd = philox4x32_10(make_uint4(pixel, sample, view, (uint32_t)b), rp.keys[0], rp.keys[1]);
   float u0 = 1.0f;
-  if (p.Ps > 0.0f) {
+  if (p.Pn > 0.0f) {
     const uint4 wl = philox4x32_10(make_uint4(pixel, sample, view, 0x40000000u | (uint32_t)b), rp.keys[0],
                                    rp.keys[1]);
     u0 = u01(wl.x);
