@@ -529,10 +529,13 @@ def main():
     area = variant(lambda: set_lights(lights), lambda: set_lights(()), "area lights", n_lights=4)
     envmap = variant(lambda: S.set_environment(torch.rand((1024, 2048), device="cuda", generator=gen) * 0.5),
                      lambda: S.set_environment(None), "environment", w=2048, h=1024)
-    # principled materials in three channels: 8 random materials over the faces
+    # principled materials in three channels: 8 random materials over the faces,
+    # the last four under a clearcoat
     mat_rng = np.random.default_rng(7)
     mats = np.concatenate([mat_rng.uniform(0.05, 0.95, (8, 3)), mat_rng.uniform(0.1, 1.0, (8, 1)),
-                           mat_rng.uniform(0.0, 1.0, (8, 2))], axis=1).astype(np.float32)
+                           mat_rng.uniform(0.0, 1.0, (8, 2))], axis=1)
+    coats = np.stack([np.r_[np.zeros(4), mat_rng.uniform(0.3, 1.0, 4)], mat_rng.uniform(0.1, 0.6, 8)], axis=1)
+    mats = np.concatenate([mats, coats], axis=1).astype(np.float32)
     face_mat = torch.randint(0, 8, (S.n_quads,), device="cuda", generator=gen, dtype=torch.int64).to(torch.uint8)
 
     def set_mats():
@@ -542,7 +545,7 @@ def main():
     def unset_mats():
         S.set_materials(None)
         img.resize_(n_pix)
-    principled = variant(set_mats, unset_mats, "principled", n_materials=8, channels=3)
+    principled = variant(set_mats, unset_mats, "principled", n_materials=8, coated=4, channels=3)
 
     # ---- rooflines: the timed kernel and the frame's dominant kernel
     key = kernel_sources_hash()
