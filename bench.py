@@ -83,22 +83,23 @@ def kernel_sources_hash():
 
 
 def committed_counters(name, kernel_key):
-    """Per-launch HBM bytes, VALU issue rate, measured HBM GB/s and VALU
-    wave-instructions per launch from a committed rocprofv3 counter summary, or
-    Nones when absent or taken from other sources."""
+    """Per-launch HBM bytes, VALU issue rate, measured HBM GB/s, VALU
+    wave-instructions per launch and enabled lanes per VALU instruction from a
+    committed rocprofv3 counter summary, or Nones when absent or taken from
+    other sources."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None, None, None, None
+        return None, None, None, None, None
     txt = open(path).read()
     m = re.search(r"sources_hash:\s*(\w+)", txt)
     if not m or m.group(1) != kernel_key:
-        return None, None, None, None
+        return None, None, None, None, None
 
     def num(key):
         x = re.search(key + r":\s*([0-9.eE+-]+)", txt)
         return float(x.group(1)) if x else None
     return (num("traffic_bytes_per_launch"), num("valu_issue_per_cu_cycle"), num("hbm_gbs"),
-            num("valu_insts_per_launch"))
+            num("valu_insts_per_launch"), num("valu_active_lanes_per_inst"))
 
 
 def roofline(alg_bytes, kern_ms, counters, kernel):
@@ -106,7 +107,7 @@ def roofline(alg_bytes, kern_ms, counters, kernel):
     larger of the measured HBM fraction and the VALU issue fraction (committed
     counters of the same sources), and is reported against its own peak."""
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    tr, valu, hbm, insts = counters
+    tr, valu, hbm, insts, lanes = counters
     hbm_frac = None if hbm is None else hbm / HBM_PEAK_GBS
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
@@ -122,7 +123,7 @@ def roofline(alg_bytes, kern_ms, counters, kernel):
             lane_ops = insts * 64 / (kern_ms * 1e-3) / 1e12 if insts else valu * VALU_PEAK_TOPS
             out.update({"bound": "alu", "achieved": round(lane_ops, 2), "peak": round(VALU_PEAK_TOPS, 2),
                         "unit": "T VALU lane-ops/s", "frac": round(lane_ops / VALU_PEAK_TOPS, 4),
-                        "valu_insts_per_launch": insts,
+                        "valu_insts_per_launch": insts, "valu_active_lanes_per_inst": lanes,
                         "algorithmic_hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                             "frac": round(achieved / HBM_PEAK_GBS, 4)}})
     return out
