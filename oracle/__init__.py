@@ -65,7 +65,7 @@ def lib():
         L.orc_scene_create.argtypes = [P, i64, P, i64, P, P, i32, P, P, P, i64, P, P, P]
         L.orc_scene_destroy.argtypes = [P]
         L.orc_scene_set_albedo.argtypes = [P, P]
-        L.orc_scene_set_textures.argtypes = [P, P, i32]
+        L.orc_scene_set_textures.argtypes = [P, P, i32, i32]
         L.orc_scene_set_environment.argtypes = [P, P, i32, i32]
         L.orc_scene_set_materials.argtypes = [P, P, i32, P]
         L.orc_bsdf_eval.argtypes = [P, P, P, i64, P, P]
@@ -184,6 +184,7 @@ class OracleScene:
         # shading faces: every quad and every curve (in prototype order)
         self.n_quads = int(k["albedo"].shape[0])
         self.tex_res = 0
+        self.tex_ch = 1
         self.rgb = False
         self.h = lib().orc_scene_create(_p(k["verts"]), k["verts"].shape[0], _p(k["quads"]), k["quads"].shape[0],
                                         _p(k["vo"]), _p(k["qo"]), k["qo"].shape[0] - 1, _p(k["albedo"]),
@@ -208,8 +209,9 @@ class OracleScene:
     @property
     def n_params(self) -> int:
         """Shading parameters that gradients refer to: one albedo per face, or,
-        with textures, every texel (face-major, then row v, column u)."""
-        return self.n_quads * (self.tex_res * self.tex_res if self.tex_res > 0 else 1)
+        with textures, every texel (face-major, then row v, column u), and with
+        RGB texels every channel of every texel (channel fastest)."""
+        return self.n_quads * (self.tex_res * self.tex_res * self.tex_ch if self.tex_res > 0 else 1)
 
     def set_materials(self, mats: Optional[np.ndarray], face_mat: Optional[np.ndarray] = None) -> None:
         """Principled materials: [n_mat, 6] or [n_mat, 8] rows (tint r, g, b,
@@ -239,17 +241,22 @@ class OracleScene:
 
     def set_textures(self, texels: Optional[np.ndarray]) -> None:
         """Per-face textures [n_quads, res, res] (row v, column u; FP32 values read
-        exactly), or None to shade with the per-face albedo again.  With
-        textures the gradient functions refer to the texels."""
+        exactly) or [n_quads, res, res, 3] (RGB base colors, for scenes with
+        materials), or None to shade with the per-face albedo again.  With
+        textures the gradient functions refer to the texels (and channels)."""
         if texels is None:
-            assert lib().orc_scene_set_textures(self.h, None, 0) == 0
+            assert lib().orc_scene_set_textures(self.h, None, 0, 1) == 0
             self.tex_res = 0
+            self.tex_ch = 1
             return
         t = np.ascontiguousarray(np.asarray(texels, dtype=np.float32), dtype=np.float64)
-        assert t.ndim == 3 and t.shape[0] == self.n_quads and t.shape[1] == t.shape[2] >= 1
-        assert lib().orc_scene_set_textures(self.h, _p(t), int(t.shape[1])) == 0
+        ch = 3 if t.ndim == 4 else 1
+        assert t.ndim in (3, 4) and t.shape[0] == self.n_quads and t.shape[1] == t.shape[2] >= 1
+        assert ch == 1 or t.shape[3] == 3
+        assert lib().orc_scene_set_textures(self.h, _p(t), int(t.shape[1]), ch) == 0
         self._tex = t
         self.tex_res = int(t.shape[1])
+        self.tex_ch = ch
 
     def set_environment(self, texels: Optional[np.ndarray]) -> None:
         """Environment map [h, w] (row 0 around +z; FP32 values read exactly)
@@ -371,6 +378,8 @@ class OracleScene:
     def render(self, cams, settings, pixels: Optional[np.ndarray] = None, brute: bool = False):
         """Returns (image or per-listed-pixel radiance [f64]: [n] without materials,
         [n, 3] with them; pixel flags [u8]; stats dict)."""
+        if self.tex_res > 0 and self.tex_ch == 3 and not self.rgb:
+            raise ValueError("RGB textures shade a scene with materials")
         cf, ci, total = self._cams(cams)
         pi, pu, pd = self._params(settings)
         px = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)

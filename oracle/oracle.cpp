@@ -180,6 +180,7 @@ struct Scene {
   // optional per-face textures: res x res values per unique quad, row v, column u
   std::vector<double> tex;
   int32_t tex_res = 0;
+  int32_t tex_ch = 1;  // texel channels: 1 (a scalar albedo) or 3 (an RGB base color)
   // optional environment map: env_w x env_h radiance values, equirectangular
   std::vector<double> env;
   int32_t env_w = 0, env_h = 0;
@@ -1348,7 +1349,8 @@ Material face_material(const Scene& S, int64_t face) {
 struct Vertex {
   int64_t face;
   int64_t param;  // index of the shading parameter: the face, or its texel when the scene has textures
-  double a;      // albedo (texel) at the vertex: the base color is the material's tint times a
+  double a;      // albedo (texel; an RGB texel's first channel) at the vertex
+  C3 a3;         // per channel: the base color is the material's tint times a3
   C3 e, e1;      // next-event estimate at the vertex (visibility included) and its derivative in a
   C3 w, w1;      // weight f mu / pdf of the bounce leaving the vertex and its derivative in a (0: none)
   int32_t inst, prim, half;  // the hit
@@ -1493,6 +1495,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (nd > 0) n = -1.0 * n;
     const V3 p = ray.o + h.best.t * ray.d;
     double a = S.albedo[face];
+    C3 a3 = c3(a);
     int64_t param = face;
     uint32_t tex_flag = 0;
     if (S.tex_res > 0) {
@@ -1512,12 +1515,14 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       const int tx = std::min(std::max((int)std::floor(gu), 0), R - 1);
       const int ty = std::min(std::max((int)std::floor(gv), 0), R - 1);
       param = ((int64_t)face * R + ty) * R + tx;
-      a = S.tex[(size_t)param];
+      for (int ch = 0; ch < 3; ++ch) a3.v[ch] = S.tex[(size_t)param * S.tex_ch + (S.tex_ch == 3 ? ch : 0)];
+      a = a3.v[0];
     }
     Vertex vx;
     vx.face = face;
     vx.param = param;
     vx.a = a;
+    vx.a3 = a3;
     const Material M = face_material(S, face);
     const Shade sh = make_shade(M, n, -1.0 * normalize(ray.d), false);
     // next-event estimate e = X (A + B c) toward the light direction, X the
@@ -1526,7 +1531,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
       double A, B;
       eval_AB(sh, wl_dir, &A, &B);
       for (int ch = 0; ch < 3; ++ch) {
-        vx.e.v[ch] = X * (A + B * sh.tint.v[ch] * a);
+        vx.e.v[ch] = X * (A + B * sh.tint.v[ch] * a3.v[ch]);
         vx.e1.v[ch] = X * B * sh.tint.v[ch];
       }
     };
@@ -1651,7 +1656,7 @@ void trace_path(const Scene& S, const Params& P, const Cam& cam, int32_t view, i
     if (!eval_AB(sh, dnew, &A, &B)) return;  // a direction on the surface (measure zero): the path ends
     pdf_bsdf = bsdf_pdf(sh, dnew);
     for (int ch = 0; ch < 3; ++ch) {
-      rec.v[rec.nv - 1].w.v[ch] = (A + B * sh.tint.v[ch] * a) / pdf_bsdf;
+      rec.v[rec.nv - 1].w.v[ch] = (A + B * sh.tint.v[ch] * a3.v[ch]) / pdf_bsdf;
       rec.v[rec.nv - 1].w1.v[ch] = B * sh.tint.v[ch] / pdf_bsdf;
     }
     ray = Ray{p, dnew, 0.0, kInf};
@@ -1866,8 +1871,10 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     const double dn_unc = is_cap && S.pkind[pr] == 1
                               ? cap_normal_uncertainty(S, inst, S.caps[S.co[pr] + prim], ray, (double)F[0], 0.0)
                               : 0.0;
-    // shading value: the face's albedo, or a texel at the hit's (u, v)
+    // shading value: the face's albedo, or a texel at the hit's (u, v) (the
+    // recorded value is an RGB texel's first channel)
     double a = S.albedo[face];
+    C3 a3 = c3(a);
     if (S.tex_res > 0) {
       // barycentric (u, v) of the plane point along the recorded ray
       const V3 w0 = half == 0 ? wq[0] : wq[2], w1 = half == 0 ? wq[1] : wq[3], w2 = half == 0 ? wq[3] : wq[1];
@@ -1893,8 +1900,10 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
           // a neighbour is acceptable only across an edge within rounding
           if (dx != 0 && std::fabs(u * Rr - (dx > 0 ? tx + 1 : tx)) * lu / Rr >= tol) continue;
           if (dy != 0 && std::fabs(v * Rr - (dy > 0 ? ty + 1 : ty)) * lv / Rr >= tol) continue;
-          const double val = S.tex[((size_t)face * Rr + y2) * Rr + x2];
+          const size_t ti = ((size_t)face * Rr + y2) * Rr + x2;
+          const double val = S.tex[ti * S.tex_ch];
           if (f32(val) == F[1]) {
+            for (int ch = 0; ch < 3; ++ch) a3.v[ch] = S.tex[ti * S.tex_ch + (S.tex_ch == 3 ? ch : 0)];
             a = val;
             found = true;
           }
@@ -1980,7 +1989,7 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
         double fa, fb;
         eval_AB(sh, ldir, &fa, &fb);
         C3 e;
-        for (int ch = 0; ch < 3; ++ch) e.v[ch] = X * (fa + fb * sh.tint.v[ch] * a);
+        for (int ch = 0; ch < 3; ++ch) e.v[ch] = X * (fa + fb * sh.tint.v[ch] * a3.v[ch]);
         Lsum = Lsum + T * e;
         for (int ch = 0; ch < 3; ++ch) Bsum.v[ch] += std::fabs(T.v[ch] * e.v[ch]) * rho;
         if (dn_unc > 0.0) {
@@ -1990,7 +1999,7 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
             double qa, qb;
             eval_AB(sq, ldir, &qa, &qb);
             for (int ch = 0; ch < 3; ++ch)
-              Bsum.v[ch] += 0.5 * std::fabs(T.v[ch]) * std::fabs(Xq * (qa + qb * sq.tint.v[ch] * a) - e.v[ch]);
+              Bsum.v[ch] += 0.5 * std::fabs(T.v[ch]) * std::fabs(Xq * (qa + qb * sq.tint.v[ch] * a3.v[ch]) - e.v[ch]);
           }
         }
       }
@@ -2053,7 +2062,7 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
     }
     pdf_bsdf = bsdf_pdf(sh, dn);
     C3 wgt;
-    for (int ch = 0; ch < 3; ++ch) wgt.v[ch] = pdf_bsdf > 0.0 ? (fa + fb * sh.tint.v[ch] * a) / pdf_bsdf : 0.0;
+    for (int ch = 0; ch < 3; ++ch) wgt.v[ch] = pdf_bsdf > 0.0 ? (fa + fb * sh.tint.v[ch] * a3.v[ch]) / pdf_bsdf : 0.0;
     if (dn_unc > 0.0 && !unbounded) {
       // relative spread of the weight and of the density (the environment's
       // MIS weight at an escape reads it) over the turned normals
@@ -2068,7 +2077,7 @@ PathCheck check_path(const Scene& S, const Params& P, const Cam& cam, int32_t vi
         }
         dr = std::max(dr, std::fabs(pq / pdf_bsdf - 1.0));
         for (int ch = 0; ch < 3; ++ch) {
-          const double wq = (qa + qb * sq.tint.v[ch] * a) / pq;
+          const double wq = (qa + qb * sq.tint.v[ch] * a3.v[ch]) / pq;
           if (wgt.v[ch] != 0.0) dr = std::max(dr, std::fabs(wq / wgt.v[ch] - 1.0));
         }
       }
@@ -2337,17 +2346,19 @@ int orc_scene_set_albedo(void* s, const double* albedo) {
 }
 
 // Per-face textures (Section 5.3: a Ptex lookup at the hit's face and (u, v)),
-// here synthetic: res x res values per unique quad in face order, row v, column
-// u; res = 0 removes them.
-int orc_scene_set_textures(void* s, const double* texels, int32_t res) {
+// here synthetic: res x res texels per unique quad in face order, row v, column
+// u, each of `channels` values (1: an albedo; 3: an RGB base color, channel
+// fastest); res = 0 removes them.
+int orc_scene_set_textures(void* s, const double* texels, int32_t res, int32_t channels) {
   Scene* S = static_cast<Scene*>(s);
-  if (res < 0 || (res > 0 && !texels)) return -1;
+  if (res < 0 || (res > 0 && !texels) || (channels != 1 && channels != 3)) return -1;
   if (res > 0)
     for (int32_t k : S->pkind)
       if (k) return -1;  // textures are per quad face: a scene with curves has none
   S->tex_res = res;
+  S->tex_ch = channels;
   S->tex.clear();
-  if (res > 0) S->tex.assign(texels, texels + S->albedo.size() * (size_t)res * (size_t)res);
+  if (res > 0) S->tex.assign(texels, texels + S->albedo.size() * (size_t)res * (size_t)res * (size_t)channels);
   return 0;
 }
 
@@ -2600,7 +2611,9 @@ void orc_path(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
 // Gradient of sum_p g_p . I_p (RGB: g_p has 3 weights per pixel) with respect to
 // the per-face albedo (or texel) a, paths held fixed.  Every vertex's estimate
 // e_k and bounce weight w_k are affine in its own a (the base color is the
-// material's tint times a), with derivatives e1_k, w1_k.
+// material's tint times a), with derivatives e1_k, w1_k.  With RGB texels each
+// channel of a texel is a parameter of its own (index 3 texel + channel), and
+// channel c of a vertex's estimate and weight depends on channel c alone.
 // mode 0: path replay, dI/da_j = (1/spp) sum over vertices k with parameter j
 //         of T_k (e1_k + w1_k R_k), R_k = sum_{i>k} (w_{k+1} .. w_{i-1}) e_i
 //         (+ the escape term) the radiance arriving along the bounce of k.
@@ -2620,8 +2633,9 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
   }
   const int64_t n = pix ? n_pix : total;
   const int nt = threads();
-  // shading parameters: per-face albedo, or every texel of every face
-  const int64_t Q = (int64_t)S.albedo.size() * (S.tex_res > 0 ? (int64_t)S.tex_res * S.tex_res : 1);
+  // shading parameters: per-face albedo, or every texel (channel) of every face
+  const int nch = S.tex_res > 0 ? S.tex_ch : 1;
+  const int64_t Q = (int64_t)S.albedo.size() * (S.tex_res > 0 ? (int64_t)S.tex_res * S.tex_res : 1) * nch;
   std::vector<std::vector<double>> gacc(grad_mode == 0 ? nt : 0, std::vector<double>(grad_mode == 0 ? Q : 0, 0.0));
   std::vector<std::vector<uint8_t>> taint(face_tainted ? nt : 0, std::vector<uint8_t>(face_tainted ? Q : 0, 0));
   parallel_for(n, nt, [&](int64_t i, int tid) {
@@ -2645,16 +2659,21 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
         C3 R = rec.escaped ? c3(rec.L_esc) : C3{};  // radiance arriving at the last vertex along its bounce
         for (int k = rec.nv - 1; k >= 0; --k) {
           const C3 d = T[k] * (rec.v[k].e1 + rec.v[k].w1 * R);
-          double gsum = 0.0;
-          for (int ch = 0; ch < 3; ++ch) gsum += gpix[3 * i + ch] * d.v[ch];
-          gacc[tid][rec.v[k].param] += gsum / P.spp;
+          if (nch == 3) {
+            for (int ch = 0; ch < 3; ++ch) gacc[tid][3 * rec.v[k].param + ch] += gpix[3 * i + ch] * d.v[ch] / P.spp;
+          } else {
+            double gsum = 0.0;
+            for (int ch = 0; ch < 3; ++ch) gsum += gpix[3 * i + ch] * d.v[ch];
+            gacc[tid][rec.v[k].param] += gsum / P.spp;
+          }
           R = rec.v[k].e + rec.v[k].w * R;
         }
       } else {
         // dual numbers (value, derivative) along the tangent direction
         C3 T = c3(1.0), dT, dL;
         for (int k = 0; k < rec.nv; ++k) {
-          const double da = tangent[rec.v[k].param];
+          const int64_t q = rec.v[k].param;
+          const C3 da = nch == 3 ? C3{{tangent[3 * q], tangent[3 * q + 1], tangent[3 * q + 2]}} : c3(tangent[q]);
           dL = dL + dT * rec.v[k].e + da * (T * rec.v[k].e1);
           dT = dT * rec.v[k].w + da * (T * rec.v[k].w1);
           T = T * rec.v[k].w;
@@ -2668,7 +2687,8 @@ void orc_grad(void* s, const double* cam_f, const int64_t* cam_i, int32_t n_cams
     // tainted.  Per path (when both sides use the same pixel weights): only the
     // faces on flagged paths.
     if (face_tainted && fl)
-      for (int64_t f : faces) taint[tid][f] = 1;
+      for (int64_t f : faces)
+        for (int ch = 0; ch < nch; ++ch) taint[tid][nch * f + ch] = 1;
     if (grad_mode == 1)
       for (int ch = 0; ch < 3; ++ch) dI[3 * i + ch] = dsum.v[ch] / P.spp;
     if (pflags) pflags[i] = (uint8_t)(fl != 0);
