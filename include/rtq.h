@@ -216,25 +216,33 @@ int rtq_scene_set_albedo(rtq_scene* scene, const float* albedo_dev, int64_t n, h
 /*
  * Per-face textures (Section 5.3: the diffuse colour of nearly every face comes
  * from a Ptex texture, looked up by face id and the hit's coordinates on the
- * face).  Here each unique quad carries res x res values, read at the nearest
+ * face).  Here each unique quad carries res x res texels, read at the nearest
  * texel of the hit's (u, v) (v0 -> (0, 0), v1 -> (1, 0), v2 -> (1, 1),
- * v3 -> (0, 1)), and that value replaces the face's albedo in shading, in every
- * scheduler and node format.  No filtering, no mip levels, no borders shared
+ * v3 -> (0, 1)), in every scheduler and node format.  A texel of one channel
+ * replaces the face's albedo in shading; a texel of three (an RGB colour, for
+ * scenes with materials) gives channel k of the base colour as the material's
+ * tint_k times texel channel k.  No filtering, no mip levels, no borders shared
  * with adjacent faces.
  *
- * texels_dev: device memory, n_unique_quads * res * res floats, face-major in
- * prototype order, then row v, then column u: texel (tx, ty) of face f at
- * [(f * res + ty) * res + tx]; it is copied into memory the scene owns (freed by
- * rtq_scene_destroy), the caller keeps its buffer.  res = 0 (texels_dev may be
- * NULL) removes the textures.  Waits for all work on the device, then enqueues
- * the copy on `stream`; renders on other streams are ordered by the caller.
- * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES], NULL texels
- * with res > 0, or res > 0 in a scene with curves (they have no (u, v)
- * square); RTQ_E_HIP when the allocation or copy fails.
- * rtq_render_backward then differentiates with respect to the texels.
+ * texels_dev: device memory, n_unique_quads * res * res * channels floats,
+ * face-major in prototype order, then row v, then column u, channel fastest:
+ * channel k of texel (tx, ty) of face f at [((f * res + ty) * res + tx) *
+ * channels + k]; it is copied into memory the scene owns (freed by
+ * rtq_scene_destroy), the caller keeps its buffer.  channels: 1 or 3.  res = 0
+ * (texels_dev may be NULL) removes the textures.  Waits for all work on the
+ * device, then enqueues the copy on `stream`; renders on other streams are
+ * ordered by the caller.
+ * Errors: RTQ_E_INVALID_ARG for res outside [0, RTQ_MAX_TEX_RES], channels
+ * other than 1 or 3, NULL texels with res > 0, or res > 0 in a scene with
+ * curves (they have no (u, v) square); RTQ_E_HIP when the allocation or copy
+ * fails.  A render of a scene with RGB texels and no materials fails with
+ * RTQ_E_INVALID_ARG.
+ * rtq_render_backward then differentiates with respect to the texels (every
+ * channel of an RGB texel separately, at index texel * 3 + channel).
  */
 #define RTQ_MAX_TEX_RES 64
-int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t res, hipStream_t stream);
+int rtq_scene_set_textures(rtq_scene* scene, const float* texels_dev, int32_t res, int32_t channels,
+                           hipStream_t stream);
 
 /*
  * Environment map (Section 4.1: the scene has a textured environment light):

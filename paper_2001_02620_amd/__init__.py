@@ -127,7 +127,7 @@ def load_library():
     L.rtq_scene_destroy.argtypes = [P]
     L.rtq_scene_get_info.argtypes = [P, P]
     L.rtq_scene_set_albedo.argtypes = [P, P, ctypes.c_int64, P]
-    L.rtq_scene_set_textures.argtypes = [P, P, ctypes.c_int32, P]
+    L.rtq_scene_set_textures.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P]
     L.rtq_scene_set_environment.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, P]
     L.rtq_scene_set_materials.argtypes = [P, P, ctypes.c_int32, P, P]
     L.rtq_trace_closest.argtypes = [P, P, ctypes.c_int64, P, P, P]
@@ -220,6 +220,7 @@ class Scene:
         self._h = h
         self.rgb = False
         self.tex_res = 0
+        self.tex_ch = 1
 
     @property
     def handle(self):
@@ -243,18 +244,22 @@ class Scene:
     def set_textures(self, texels) -> None:
         """Per-face textures: a device tensor [n_quads, res, res] (row v, column u),
         read at the nearest texel of each hit's (u, v) in place of the face's
-        albedo; None removes them."""
+        albedo, or [n_quads, res, res, 3]: RGB texels, each channel scaling the
+        material's tint (scenes with materials); None removes them."""
         if texels is None:
-            _check(load_library().rtq_scene_set_textures(self.handle, None, 0, _stream()))
+            _check(load_library().rtq_scene_set_textures(self.handle, None, 0, 1, _stream()))
             self._tex_keep = None
             self.tex_res = 0
+            self.tex_ch = 1
             return
-        assert texels.is_cuda and texels.dim() == 3 and texels.shape[0] == self.n_quads
-        assert texels.shape[1] == texels.shape[2]
+        assert texels.is_cuda and texels.dim() in (3, 4) and texels.shape[0] == self.n_quads
+        assert texels.shape[1] == texels.shape[2] and (texels.dim() == 3 or texels.shape[3] == 3)
+        ch = 3 if texels.dim() == 4 else 1
         t = texels.contiguous().float()
-        _check(load_library().rtq_scene_set_textures(self.handle, t.data_ptr(), int(t.shape[1]), _stream()))
+        _check(load_library().rtq_scene_set_textures(self.handle, t.data_ptr(), int(t.shape[1]), ch, _stream()))
         self._tex_keep = t
         self.tex_res = int(t.shape[1])
+        self.tex_ch = ch
 
     def set_materials(self, mats, face_mat=None) -> None:
         """Principled materials: rows (tint r, g, b, roughness, metallic,
@@ -529,8 +534,11 @@ def render_backward(scene: Scene, cams, settings, grad_images, grad_albedo=None,
     ch = _channels(scene)
     assert g.numel() == ch * total and g.is_cuda
     if grad_albedo is None:
-        # one entry per shading parameter: per face, or per texel with textures
+        # one entry per shading parameter: per face, or per texel (and channel
+        # of an RGB texel) with textures
         n_par = scene.n_faces * max(1, getattr(scene, "tex_res", 0)) ** 2
+        if getattr(scene, "tex_res", 0) > 0:
+            n_par *= getattr(scene, "tex_ch", 1)
         grad_albedo = torch.zeros(n_par, device=g.device, dtype=torch.float32)
     o = render_opts(settings, **opts)
     o.channels = ch

@@ -72,6 +72,7 @@ SceneView scene_view(const rtq_scene* s, int fmt) {
   v.albedo = s->albedo;
   v.tex = s->tex;
   v.tex_res = s->tex_res;
+  v.tex_ch = s->tex_ch;
   v.env = s->env;
   v.env_w = s->env_w;
   v.env_h = s->env_h;
@@ -765,10 +766,12 @@ int rtq_scene_set_materials(rtq_scene* s, const rtq_material* mats, int32_t n_ma
   return RTQ_OK;
 }
 
-int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, hipStream_t stream) {
+int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, int32_t channels,
+                           hipStream_t stream) {
   if (!s) return set_error(RTQ_E_INVALID_ARG, "NULL scene");
   if (res < 0 || res > RTQ_MAX_TEX_RES)
     return set_error(RTQ_E_INVALID_ARG, "texture resolution %d outside [0, %d]", res, RTQ_MAX_TEX_RES);
+  if (channels != 1 && channels != 3) return set_error(RTQ_E_INVALID_ARG, "%d texel channels (1 or 3)", channels);
   if (res > 0 && !texels_dev) return set_error(RTQ_E_INVALID_ARG, "NULL texels");
   if (res > 0 && s->n_curves > 0)
     return set_error(RTQ_E_INVALID_ARG, "textures need (u, v) squares: the scene has curves");
@@ -777,11 +780,12 @@ int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, h
   // renders already queued may still read the old texels
   e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
-  const size_t bytes = (size_t)s->n_quads * (size_t)res * (size_t)res * sizeof(float);
+  const size_t bytes = (size_t)s->n_quads * (size_t)res * (size_t)res * (size_t)channels * sizeof(float);
   if (res == 0 || bytes != s->tex_bytes) {
     if (s->tex) (void)hipFree(s->tex);
     s->tex = nullptr;
     s->tex_res = 0;
+    s->tex_ch = 1;
     s->tex_bytes = 0;
     if (res == 0) return RTQ_OK;
     e = hipMalloc(reinterpret_cast<void**>(&s->tex), bytes);
@@ -794,6 +798,7 @@ int rtq_scene_set_textures(rtq_scene* s, const float* texels_dev, int32_t res, h
   e = hipMemcpyAsync(s->tex, texels_dev, bytes, hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync");
   s->tex_res = res;
+  s->tex_ch = channels;
   return RTQ_OK;
 }
 

@@ -69,6 +69,7 @@ struct rtq_scene {
   float* albedo = nullptr;
   float* tex = nullptr;  // per-face textures (own allocation, rtq_scene_set_textures)
   int32_t tex_res = 0;
+  int32_t tex_ch = 1;  // channels per texel: 1 or 3
   size_t tex_bytes = 0;
   float* env = nullptr;  // environment map (own allocation, rtq_scene_set_environment)
   int32_t env_w = 0, env_h = 0;

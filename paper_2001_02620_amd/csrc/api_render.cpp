@@ -242,6 +242,8 @@ int prepare(const rtq_scene* cs, const rtq_camera* cams, int32_t n_cams, int32_t
     return set_error(RTQ_E_INVALID_ARG, "%d area lights outside [0, %d]", opts->n_area_lights, RTQ_MAX_AREA_LIGHTS);
   if (opts->n_area_lights > 0 && !opts->area_lights) return set_error(RTQ_E_INVALID_ARG, "NULL area lights");
   const bool rgb = s->mats != nullptr;
+  if (s->tex_res > 0 && s->tex_ch == 3 && !rgb)
+    return set_error(RTQ_E_INVALID_ARG, "RGB texels shade with materials: the scene has none");
   if (rgb ? opts->channels != 3 : (opts->channels != 0 && opts->channels != 1))
     return set_error(RTQ_E_INVALID_ARG, "channels %d: the scene %s", opts->channels,
                      rgb ? "has materials, so images have 3 channels" : "has no materials, so images have 1 channel");
@@ -380,7 +382,7 @@ int render_graph(rtq_scene* s, RenderScratch* r, const SceneView& sv, const Prep
                 (long long)rp.depth, (long long)rp.n_paths, rp.lx, rp.ly, rp.lz, rp.e_over_pi, rp.L_sky,
                 (const void*)rp.cams, (const void*)rp.slots, (const void*)images, (void*)ex.counters,
                 (void*)ex.visits, (void*)ex.dump, (long long)ex.dump_cap, (void*)ex.dump_count, (void*)ex.view_done,
-                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)sv.tex_res, (int)rp.n_alights,
+                (void*)ex.start_tick, (void*)sv.nodes, (const void*)sv.tex, (int)(sv.tex_res * 4 + sv.tex_ch), (int)rp.n_alights,
                 (const void*)sv.env, (int)sv.env_w, (int)sv.env_h);
   std::snprintf(key + std::strlen(key), sizeof(key) - std::strlen(key), "|%d %p|%p %p %a", (int)rp.env_nee,
                 (const void*)sv.env_T, (const void*)rp.mats, (const void*)rp.face_mat, rp.E);

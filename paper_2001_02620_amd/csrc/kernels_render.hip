@@ -311,7 +311,7 @@ __global__ void k_shade(SceneView sc, RenderParams rp, int b, ExtQueue in, const
       s = shade_hit(sc, rp, r, qh.t[i], rec, qhv & 0x7FFFFFFFu, qhv >> 31, tex ? qh.u[i] : 0.0f,
                     tex ? qh.v[i] : 0.0f);
       float c[3];
-      const PShade ps = principled_vertex(rp, s, r, c);
+      const PShade ps = principled_vertex(sc, rp, s, r, c);
       const float bt[3] = {beta, in.beta_g[i], in.beta_b[i]};
       const bool next = b < rp.depth - 1;
       const PathId id = path_coords(rp, (int64_t)pid);
@@ -594,7 +594,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(4))) void k_render_persistent(Scen
                 const NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, P.b);
                 if (rgb_mode(rp)) {
                   float c[3];
-                  const PShade ps = principled_vertex(rp, s, r, c);
+                  const PShade ps = principled_vertex(sc, rp, s, r, c);
                   if (P.have_next) {
                     float w[3], w1[3];
                     P.pdf_next = pbsdf_bounce(rp, ps, c, id.pixel, id.sample, id.view, P.b, &P.ndx, &P.ndy,
@@ -758,7 +758,7 @@ __global__ void k_path_record(SceneView sc, RenderParams rp, int64_t pid, int de
     const NeeSample ns = nee_sample(sc, rp, sh, id.pixel, id.sample, id.view, b);
     float c3[3] = {0.0f, 0.0f, 0.0f};
     PShade ps{};
-    if (rgb) ps = principled_vertex(rp, sh, r, c3);
+    if (rgb) ps = principled_vertex(sc, rp, sh, r, c3);
     if (ns.want) {
       float pend3[3] = {0.0f, 0.0f, 0.0f};
       if (rgb) {
@@ -863,7 +863,7 @@ __device__ __forceinline__ void adjoint_rgb(const SceneView& sc, const RenderPar
     const uint32_t hrec = L.b_rec, hqh = L.b_qh;
     const Shade s = shade_hit(sc, rp, r, L.t_best, hrec, hqh & 0x7FFFFFFFu, hqh >> 31, L.b_u, L.b_v);
     float c[3];
-    const PShade ps = principled_vertex(rp, s, r, c);
+    const PShade ps = principled_vertex(sc, rp, s, r, c);
     NeeSample ns = nee_sample(sc, rp, s, id.pixel, id.sample, id.view, b);
     if (ns.want) {
       L.ex_rec = hrec;
@@ -894,13 +894,17 @@ __device__ __forceinline__ void adjoint_rgb(const SceneView& sc, const RenderPar
   }
   const float Le = escaped ? escape_radiance(sc, rp, r.dx, r.dy, r.dz, pdf) : 0.0f;
   float R[3] = {Le, Le, Le};
+  // per channel with RGB texels (parameter 3 texel + channel), summed otherwise
+  const bool rgb_tex = sc.tex_res > 0 && sc.tex_ch == 3;
   for (int k = K - 1; k >= 0; --k) {
     float d = 0.0f;
     for (int ch = 0; ch < 3; ++ch) {
-      d += g[ch] * (T[k][ch] * (e1[k][ch] + w1[k][ch] * R[ch]));
+      const float dch = g[ch] * (T[k][ch] * (e1[k][ch] + w1[k][ch] * R[ch]));
+      if (rgb_tex) unsafeAtomicAdd(&grad_albedo[3 * (size_t)face[k] + ch], dch);
+      d += dch;
       R[ch] = e[k][ch] + w[k][ch] * R[ch];
     }
-    unsafeAtomicAdd(&grad_albedo[face[k]], d);
+    if (!rgb_tex) unsafeAtomicAdd(&grad_albedo[face[k]], d);
   }
 }
 

@@ -249,7 +249,8 @@ __device__ __forceinline__ Shade shade_hit(const SceneView& sc, const RenderPara
   const uint32_t prim = (uint32_t)sc.quad_prim[quad];
   s.face = ir.face_base + (cap ? prim / (uint32_t)kCapsPerCurve : prim);
   s.param = sc.tex_res > 0 ? face_texel(sc, s.face, u, v) : s.face;
-  s.a = sc.tex_res > 0 ? sc.tex[s.param] : sc.albedo[s.face];
+  // (an RGB texel's first channel; principled_vertex reads the other two)
+  s.a = sc.tex_res > 0 ? sc.tex[(size_t)s.param * sc.tex_ch] : sc.albedo[s.face];
   s.cosl = nx * rp.lx + ny * rp.ly + nz * rp.lz;
   return s;
 }
@@ -554,7 +555,8 @@ __device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1
   const float olx = p.ox * p.t1x + p.oy * p.t1y + p.oz * p.t1z;
   const float oly = p.ox * p.t2x + p.oy * p.t2y + p.oz * p.t2z;
   float vx = alpha * olx, vy = alpha * oly, vz = p.mo;
-  const float iv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+  const float vlen = sqrtf(vx * vx + vy * vy + vz * vz);
+  const float iv = 1.0f / vlen;
   vx *= iv;
   vy *= iv;
   vz *= iv;
@@ -570,15 +572,20 @@ __device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1
   // a point of the unit disk, (p1, r sin phi), its second coordinate warped to
   // p2 = (1 - s) q + s r sin phi with q = sqrt(1 - p1^2), and its height
   // sqrt(1 - p1^2 - p2^2).  Near the rim, 1 - p1^2 - p2^2 cancels; written as
-  // (q - p2)(q + p2) with q - p2 = s (q - r sin phi) and
-  // q^2 - (r sin phi)^2 = 1 - u1 exactly, it keeps full precision.
+  // (q - p2)(q + p2) with q - p2 = s (q - r sin phi), q + p2 = 2 (1 - s) q +
+  // s (q + r sin phi), and (q - r sin phi)(q + r sin phi) = 1 - u1 exactly, each
+  // factor is formed without cancellation: the one of q -+ r sin phi whose terms
+  // cancel as (1 - u1) over the other, and 1 - s = (1 - v_z) / 2 with
+  // 1 - v_z = alpha^2 (1 - mu_o^2) / (|v| (|v| + mu_o)) from the unnormalised v.
   const float rr = sqrtf(u1);
   const float p1 = rr * cs, rs = rr * sn;
-  const float sw = 0.5f * (1.0f + vz);
+  const float osw = 0.5f * ((alpha * alpha * (olx * olx + oly * oly)) / (vlen * (vlen + p.mo)));  // 1 - s
+  const float sw = 1.0f - osw;
   const float q = sqrtf((1.0f - u1) + u1 * (sn * sn));
-  const float p2 = (1.0f - sw) * q + sw * rs;
+  const float p2 = osw * q + sw * rs;
   const float qm = rs > 0.0f ? (1.0f - u1) / (q + rs) : q - rs;  // q - r sin phi
-  const float pz = sqrtf(fmaxf(0.0f, sw * qm * (q + p2)));
+  const float qp = rs < 0.0f ? (1.0f - u1) / (q - rs) : q + rs;  // q + r sin phi
+  const float pz = sqrtf(fmaxf(0.0f, sw * qm * (2.0f * osw * q + sw * qp)));
   const float nhx = p1 * T1x + p2 * T2x + pz * vx;
   const float nhy = p1 * T1y + p2 * T2y + pz * vy;
   const float nhz = p2 * T2z + pz * vz;
@@ -604,13 +611,14 @@ __device__ __forceinline__ void pbsdf_sample(const PShade& p, float u0, float u1
 }
 
 // The principled vertex of hit s reached by ray r: its frame, and base color
-// tint x s.a per channel in c.
-__device__ __forceinline__ PShade principled_vertex(const RenderParams& rp, const Shade& s, const Ray3& r,
-                                                    float c[3]) {
+// per channel in c: tint x s.a, or tint_k x channel k of an RGB texel.
+__device__ __forceinline__ PShade principled_vertex(const SceneView& sc, const RenderParams& rp, const Shade& s,
+                                                    const Ray3& r, float c[3]) {
   const PShade p = make_pshade(rp.mats[rp.face_mat[s.face]], s, r);
+  const bool rgb_tex = sc.tex_res > 0 && sc.tex_ch == 3;
   c[0] = p.tint[0] * s.a;
-  c[1] = p.tint[1] * s.a;
-  c[2] = p.tint[2] * s.a;
+  c[1] = p.tint[1] * (rgb_tex ? sc.tex[3 * (size_t)s.param + 1] : s.a);
+  c[2] = p.tint[2] * (rgb_tex ? sc.tex[3 * (size_t)s.param + 2] : s.a);
   return p;
 }
 

@@ -39,6 +39,7 @@ struct SceneView {
   const float* albedo;        // per unique face (prototype order)
   const float* tex;           // per unique face: tex_res x tex_res texels (row v, column u), or null
   int32_t tex_res;            // texels per side; 0 shades with `albedo`
+  int32_t tex_ch;             // channels per texel (fastest): 1, or 3 for RGB base colours
   const float* env;           // environment map, env_w x env_h radiance values, or null
   int32_t env_w, env_h;       // 0: escaping rays see the constant sky
   const unsigned long long* env_T;  // its sampling table: texel k drawn with probability

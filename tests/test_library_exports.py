@@ -39,6 +39,6 @@ def test_null_arguments_are_rejected_on_the_host():
     """Argument checks that run before any device call (no GPU needed)."""
     import paper_2001_02620_amd as rtq
     L = rtq.load_library()
-    assert L.rtq_scene_set_textures(None, None, 4, None) == -1
+    assert L.rtq_scene_set_textures(None, None, 4, 1, None) == -1
     assert b"NULL" in L.rtq_last_error()
     assert L.rtq_scene_set_albedo(None, None, 0, None) == -1
