@@ -548,6 +548,17 @@ def main():
         img.resize_(n_pix)
     principled = variant(set_mats, unset_mats, "principled", n_materials=8, coated=4, channels=3)
 
+    # the same materials over RGB per-face textures (4 x 4 texels of 3 channels)
+    def set_rgb_tex():
+        set_mats()
+        S.set_textures(torch.rand((S.n_quads, 4, 4, 3), device="cuda", generator=gen) * 0.9 + 0.05)
+
+    def unset_rgb_tex():
+        S.set_textures(None)
+        unset_mats()
+    rgb_textured = variant(set_rgb_tex, unset_rgb_tex, "principled, RGB textures", n_materials=8, tex_res=4,
+                           channels=3)
+
     # ---- rooflines: the timed kernel and the frame's dominant kernel
     key = kernel_sources_hash()
     inc_bytes = visit_bytes(inc_visits["q8"], nd)
@@ -711,6 +722,7 @@ def main():
         "area_lights": area,
         "environment": envmap,
         "principled": principled,
+        "principled_rgb_textures": rgb_textured,
         "config2": cfg2,
         "config4_adjoint": adj,
         "curves": curves,
